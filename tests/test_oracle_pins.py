@@ -1,0 +1,497 @@
+"""Pins for the FP64 CPU oracle (no GPU).
+
+Each test ties an oracle function to something other than the oracle's own
+formula: finite differences of the dual, long-double brute force, closed
+forms, dense linear algebra (SciPy), brute-force / LP optimal transport, the
+paper's lemmas (eigenvalue bounds, Armijo equivalence, Newton-residual
+structure) and the worked 4x4 example of App. C (tests/golden/appC_4x4.json).
+Rectangular shapes (n != m) are used wherever a transposition could hide.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+from scipy.optimize import linprog
+
+import oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def instance(n, m, seed, beta=5.0, spread=1.0):
+    rng = np.random.default_rng(seed)
+    C = rng.uniform(0.0, 1.0, size=(n, m))
+    r = rng.dirichlet(np.ones(n)) + 1e-3
+    r /= r.sum()
+    c = rng.dirichlet(np.ones(m)) + 1e-3
+    c /= c.sum()
+    u = np.log(r) + spread * rng.standard_normal(n)
+    v = np.log(c) + spread * rng.standard_normal(m)
+    return C, r, c, u, v, beta
+
+
+def fixed_cols(C, beta, u, c):
+    """v with c(P) = c (the column fix of Alg. 4 L1), from the oracle's
+    column LSE."""
+    lc = O.log_col_marginal(C, beta, u, np.zeros(C.shape[1]))
+    return np.log(c) - lc
+
+
+def dense_hessian(C, beta, u, v, rho):
+    n, m = C.shape
+    H = np.zeros((n + m, n + m))
+    for k in range(n + m):
+        e = np.zeros(n + m)
+        e[k] = 1.0
+        hx, hy = O.hvp(C, beta, u, v, rho, e[:n], e[n:])
+        H[:n, k] = hx
+        H[n:, k] = hy
+    return H
+
+
+def dense_fr(C, beta, u, v, rP, c, rho):
+    n = C.shape[0]
+    F = np.zeros((n, n))
+    for k in range(n):
+        e = np.zeros(n)
+        e[k] = 1.0
+        F[:, k] = O.fr_apply(C, beta, u, v, rP, c, rho, e)
+    return F
+
+
+# ------------------------------------------------------------ plan level
+
+def test_marginals_match_longdouble_bruteforce():
+    C, r, c, u, v, beta = instance(7, 11, 1, beta=40.0, spread=3.0)
+    ld = np.longdouble
+    X = u.astype(ld)[:, None] + v.astype(ld)[None, :] - ld(beta) * C.astype(ld)
+    P = np.exp(X)
+    lr = O.log_row_marginal(C, beta, u, v)
+    lc = O.log_col_marginal(C, beta, u, v)
+    np.testing.assert_allclose(lr, np.log(P.sum(1)).astype(np.float64), rtol=0, atol=2e-13)
+    np.testing.assert_allclose(lc, np.log(P.sum(0)).astype(np.float64), rtol=0, atol=2e-13)
+    assert abs(O.mass(C, beta, u, v) - float(P.sum())) <= 1e-13 * float(P.sum())
+
+
+def test_mass_identity_rows_equal_cols():
+    C, r, c, u, v, beta = instance(9, 4, 2, beta=20.0)
+    lr = O.log_row_marginal(C, beta, u, v)
+    lc = O.log_col_marginal(C, beta, u, v)
+    mass = O.mass(C, beta, u, v)
+    assert abs(np.exp(lr).sum() - mass) <= 1e-14 * mass
+    assert abs(np.exp(lc).sum() - mass) <= 1e-13 * mass
+
+
+def test_gradient_is_finite_difference_of_dual():
+    # grad_u g = r(P) - r, grad_v g = c(P) - c  (eq. opt:sinkhorn-dual)
+    C, r, c, u, v, beta = instance(5, 8, 3, beta=10.0)
+    g = lambda uu, vv: O.dual(C, beta, uu, vv, r, c)
+    h = 1e-5
+    gu = np.exp(O.log_row_marginal(C, beta, u, v)) - r
+    gv = np.exp(O.log_col_marginal(C, beta, u, v)) - c
+    for i in range(5):
+        e = np.zeros(5); e[i] = h
+        fd = (g(u + e, v) - g(u - e, v)) / (2 * h)
+        assert abs(fd - gu[i]) < 1e-8
+    for j in range(8):
+        e = np.zeros(8); e[j] = h
+        fd = (g(u, v + e) - g(u, v - e)) / (2 * h)
+        assert abs(fd - gv[j]) < 1e-8
+
+
+def test_dual_two_by_two_closed_form():
+    # Uniform 2x2 marginals: P11 = k / (2 (1 + k)), k = exp(-beta Delta / 2),
+    # Delta = C11 + C22 - C12 - C21 (optimality P11 P22 / (P12 P21) = e^{-beta Delta}).
+    C = np.array([[0.0, 0.7], [0.4, 0.1]])
+    r = np.array([0.5, 0.5]); c = np.array([0.5, 0.5])
+    gamma = 0.1
+    u, v, st = O.solve(C, r, c, gamma_init=1.0, gamma_final=gamma, tol=1e-13)
+    assert st["status"] == 0
+    beta = 1.0 / gamma
+    P11 = np.exp(u[0] + v[0] - beta * C[0, 0])
+    delta = C[0, 0] + C[1, 1] - C[0, 1] - C[1, 0]
+    k = np.exp(-beta * delta / 2)
+    assert abs(P11 - k / (2 * (1 + k))) < 1e-12
+
+
+# ------------------------------------------------------------ Hessian
+
+def test_hvp_is_finite_difference_of_gradient():
+    C, r, c, u, v, beta = instance(6, 9, 4, beta=8.0)
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(6); y = rng.standard_normal(9)
+    h = 1e-6
+    lrp = O.log_row_marginal(C, beta, u + h * x, v + h * y)
+    lrm = O.log_row_marginal(C, beta, u - h * x, v - h * y)
+    lcp = O.log_col_marginal(C, beta, u + h * x, v + h * y)
+    lcm = O.log_col_marginal(C, beta, u - h * x, v - h * y)
+    Hx, Hy = O.hvp(C, beta, u, v, 1.0, x, y)
+    np.testing.assert_allclose((np.exp(lrp) - np.exp(lrm)) / (2 * h), Hx, rtol=0, atol=1e-8)
+    np.testing.assert_allclose((np.exp(lcp) - np.exp(lcm)) / (2 * h), Hy, rtol=0, atol=1e-8)
+
+
+def test_hvp_null_vector_symmetry_and_discount():
+    C, r, c, u, v, beta = instance(5, 7, 5, beta=12.0)
+    # H (1, -1) = 0 (footnote of eq. hessian) -- only for a square block
+    # structure in the sense of equal scalar shift; holds for any n, m.
+    Hx, Hy = O.hvp(C, beta, u, v, 1.0, np.ones(5), -np.ones(7))
+    assert np.abs(Hx).max() < 1e-15 and np.abs(Hy).max() < 1e-15
+    H = dense_hessian(C, beta, u, v, 1.0)
+    np.testing.assert_allclose(H, H.T, rtol=0, atol=1e-16)
+    assert np.linalg.eigvalsh(H).min() > -1e-15                  # PSD
+    # eq. discounted-hessian: off-diagonal blocks scale with sqrt(rho)
+    H0 = dense_hessian(C, beta, u, v, 0.0)
+    Hr = dense_hessian(C, beta, u, v, 0.36)
+    np.testing.assert_allclose(Hr - H0, 0.6 * (H - H0), rtol=0, atol=1e-16)
+    # Gerschgorin bound of Sec. 3.1 for the discounted Hessian
+    rP = np.diag(H)[:5]; cP = np.diag(H)[5:]
+    lam = np.linalg.eigvalsh(Hr).min()
+    assert lam >= (1 - 0.6) * min(rP.min(), cP.min()) - 1e-15
+
+
+# ------------------------------------------------------------ reduced operator
+
+def test_fr_is_schur_complement_of_discounted_hessian():
+    # eq. inverse-discounted-hessian: the u-block of H(rho)^-1 is F_r(rho)^-1,
+    # i.e. F_r(rho) = H_uu - H_uv H_vv^-1 H_vu, with c(P) = c.
+    C, r, c, u, v, beta = instance(6, 5, 6, beta=9.0)
+    v = fixed_cols(C, beta, u, c)
+    rP = np.exp(O.log_row_marginal(C, beta, u, v))
+    for rho in (0.0, 0.3, 0.9, 1.0):
+        H = dense_hessian(C, beta, u, v, rho)
+        S = H[:6, :6] - H[:6, 6:] @ np.linalg.solve(H[6:, 6:], H[6:, :6])
+        F = dense_fr(C, beta, u, v, rP, c, rho)
+        np.testing.assert_allclose(F, S, rtol=0, atol=1e-14)
+
+
+def test_fr_eigenvalue_bounds_and_preconditioner_spectrum():
+    # lemma "frprops" and lemma "condo"
+    C, r, c, u, v, beta = instance(8, 6, 7, beta=6.0)
+    v = fixed_cols(C, beta, u, c)
+    rP = np.exp(O.log_row_marginal(C, beta, u, v))
+    s = O.row_square_sum(C, beta, u, v, c)
+    for rho in (0.2, 0.75, 0.99):
+        F = dense_fr(C, beta, u, v, rP, c, rho)
+        np.testing.assert_allclose(F, F.T, rtol=0, atol=1e-16)
+        lam = np.linalg.eigvalsh(F)
+        assert lam.min() >= (1 - rho) * rP.min() * (1 - 1e-12)
+        assert lam.max() <= (1 + rho) * rP.max() * (1 + 1e-12)
+        # diag F_r(rho) = r(P) - rho s  (M_ii = r(P)_i (1 - rho mu_i))
+        np.testing.assert_allclose(np.diag(F), rP - rho * s, rtol=1e-13, atol=0)
+        mu = s / rP
+        Mi = 1.0 / np.sqrt(np.diag(F))
+        lamp = np.linalg.eigvalsh(Mi[:, None] * F * Mi[None, :])
+        rad = rho * (1 - mu.min()) / (1 - rho * mu.min())
+        assert lamp.min() >= 1 - rad - 1e-12 and lamp.max() <= 1 + rad + 1e-12
+
+
+def test_bellman_form_of_discounted_newton_direction():
+    # eq. bellman2: with c(P) = c, d_u = (r / r(P) - 1) + rho P_rc d_u
+    C, r, c, u, v, beta = instance(7, 7, 8, beta=7.0)
+    v = fixed_cols(C, beta, u, c)
+    lr = O.log_row_marginal(C, beta, u, v)
+    rP = np.exp(lr)
+    rho = 0.8
+    F = dense_fr(C, beta, u, v, rP, c, rho)
+    d = np.linalg.solve(F, -(rP - r))
+    F1 = dense_fr(C, beta, u, v, rP, c, 1.0)
+    Prc = np.eye(7) - F1 / rP[:, None]                 # F_r(1) = D(r(P)) (I - P_rc)
+    np.testing.assert_allclose(Prc.sum(1), 1.0, atol=1e-13)   # row-stochastic
+    np.testing.assert_allclose(rP @ Prc, rP, atol=1e-15)      # stationary r(P)
+    np.testing.assert_allclose(rP[:, None] * Prc, (rP[:, None] * Prc).T, atol=1e-16)  # reversible
+    np.testing.assert_allclose(d, (r / rP - 1) + rho * Prc @ d, atol=1e-12)
+
+
+def test_pcg_matches_dense_cholesky():
+    C, r, c, u, v, beta = instance(10, 13, 9, beta=15.0)
+    v = fixed_cols(C, beta, u, c)
+    rP = np.exp(O.log_row_marginal(C, beta, u, v))
+    s = O.row_square_sum(C, beta, u, v, c)
+    rng = np.random.default_rng(1)
+    b = rng.standard_normal(10) * 1e-3
+    for rho in (0.5, 0.9375, 0.999):
+        F = dense_fr(C, beta, u, v, rP, c, rho)
+        ref = sla.cho_solve(sla.cho_factor(F), b)
+        d, it, st = O.pcg(C, beta, u, v, rP, c, s, rho, b, 1e-14 * np.abs(b).sum(), 500)
+        assert st == 0
+        np.testing.assert_allclose(d, ref, rtol=1e-9, atol=1e-12 * np.abs(ref).max())
+        assert np.abs(F @ d - b).sum() <= 1e-13 * np.abs(b).sum() * 10
+    d, it, st = O.pcg(C, beta, u, v, rP, c, s, 0.0, b, 1e-14 * np.abs(b).sum(), 500)
+    assert it == 1 and st == 0
+    np.testing.assert_allclose(d, b / rP, rtol=1e-15)
+
+
+def test_pcg_first_step_uses_jacobi_preconditioner():
+    # Diagonally preconditioned CG (Alg. 2 with M = D(diag F_r(rho)), lemma
+    # "condo"): from d = 0 the first iterate is alpha z0 with z0 = M^-1 b,
+    # alpha = <b, z0> / <z0, F z0>, the diagonal taken from the dense matrix.
+    C, r, c, u, v, beta = instance(9, 7, 19, beta=12.0)
+    v = fixed_cols(C, beta, u, c)
+    rP = np.exp(O.log_row_marginal(C, beta, u, v))
+    s = O.row_square_sum(C, beta, u, v, c)
+    b = np.random.default_rng(2).standard_normal(9)
+    for rho in (0.75, 0.99):
+        F = dense_fr(C, beta, u, v, rP, c, rho)
+        z0 = b / np.diag(F)
+        d1 = (b @ z0) / (z0 @ F @ z0) * z0
+        d, it, st = O.pcg(C, beta, u, v, rP, c, s, rho, b, 0.0, 1)
+        assert it == 1
+        np.testing.assert_allclose(d, d1, rtol=1e-12)
+
+
+# ------------------------------------------------------------ NewtonSolve
+
+def test_newton_solve_forcing_residual_structure_and_rho_sequence():
+    C, r, c, u, v, beta = instance(9, 12, 10, beta=20.0, spread=0.3)
+    v = fixed_cols(C, beta, u, c)
+    lr = O.log_row_marginal(C, beta, u, v)
+    rP = np.exp(lr)
+    grad = rP - r
+    eta = 0.05
+    R = O.newton_solve(C, beta, u, v, r, c, lr, eta, rho0=0.0)
+    assert R.status == 0 and R.forcing_miss == 0
+    # rho runs 0, 3/4, 15/16, ...: the returned value is 1 - 4^-levels
+    assert R.rho == 1.0 - 4.0 ** (-R.levels)
+    # Newton residual of the full system (proof of theorem "resid"):
+    # e = H [d_u; d_v] + grad g = [F_r(1) d_u + grad_u g; 0] when d_v = -P_c d_u
+    Hx, Hy = O.hvp(C, beta, u, v, 1.0, R.du, R.dv)
+    gv = np.exp(O.log_col_marginal(C, beta, u, v)) - c
+    eu = Hx + grad
+    ev = Hy + gv
+    assert np.abs(ev).sum() <= 1e-12 * np.abs(eu).sum() + 1e-16
+    assert np.abs(eu).sum() <= eta * np.abs(grad).sum()
+    # tiny eta -> the undiscounted Newton direction: compare the gauge-invariant
+    # change of log P (d_u,i + d_v,j) with a dense least-squares solve
+    R2 = O.newton_solve(C, beta, u, v, r, c, lr, 1e-9, rho0=0.0)
+    H = dense_hessian(C, beta, u, v, 1.0)
+    sol = np.linalg.lstsq(H, -np.concatenate([grad, gv]), rcond=1e-13)[0]
+    dP_ref = sol[:9, None] + sol[None, 9:]
+    dP = R2.du[:, None] + R2.dv[None, :]
+    np.testing.assert_allclose(dP, dP_ref, rtol=0, atol=1e-6 * np.abs(dP_ref).max())
+
+
+def test_newton_solve_warm_discount_starts_at_rho0():
+    C, r, c, u, v, beta = instance(8, 8, 11, beta=30.0, spread=0.3)
+    v = fixed_cols(C, beta, u, c)
+    lr = O.log_row_marginal(C, beta, u, v)
+    R0 = O.newton_solve(C, beta, u, v, r, c, lr, 0.01, rho0=0.0)
+    rho0 = max(0.0, 1 - 4 * (1 - R0.rho))          # App. B
+    R1 = O.newton_solve(C, beta, u, v, r, c, lr, 0.01, rho0=rho0)
+    # annealing resumes from the second-last level of the previous call
+    assert R1.levels <= 2 and R1.rho >= rho0
+    assert 1.0 - R1.rho == pytest.approx((1 - rho0) * 4.0 ** (-R1.levels), rel=1e-12)
+
+
+# ------------------------------------------------------------ line search
+
+def test_line_search_is_armijo_on_the_dual():
+    # lemma "suffdecr": the mass test of Alg. 4 L10 is Armijo with c1 = 0.01
+    C, r, c, u, v, beta = instance(7, 9, 12, beta=25.0, spread=1.0)
+    v = fixed_cols(C, beta, u, c)
+    lr = O.log_row_marginal(C, beta, u, v)
+    grad = np.exp(lr) - r
+    R = O.newton_solve(C, beta, u, v, r, c, lr, 0.5, rho0=0.0)
+    g0 = O.dual(C, beta, u, v, r, c)
+    slope = grad @ R.du                       # <grad g, d>, the v-part vanishes
+    for scale in (1.0, 40.0):
+        du, dv = scale * R.du, scale * R.dv
+        alpha, lca, bt, st = O.line_search(C, beta, u, v, grad, du, dv)
+        assert st == 0
+        g1 = O.dual(C, beta, u + alpha * du, v + alpha * dv, r, c)
+        assert g1 <= g0 + 0.01 * alpha * scale * slope + 1e-15
+        np.testing.assert_allclose(lca, O.log_col_marginal(C, beta, u + alpha * du, v + alpha * dv),
+                                   atol=1e-14)
+        if bt > 0:
+            a2 = 2 * alpha
+            g2 = O.dual(C, beta, u + a2 * du, v + a2 * dv, r, c)
+            assert g2 > g0 + 0.01 * a2 * scale * slope
+    assert scale == 40.0 and bt > 0
+
+
+# ------------------------------------------------------------ ChiSinkhorn / TNP
+
+def test_chi_sinkhorn_exit_condition_keeps_columns_fixed():
+    C, r, c, u, v, beta = instance(10, 6, 13, beta=10.0, spread=1.0)
+    v = fixed_cols(C, beta, u, c)
+    lr = O.log_row_marginal(C, beta, u, v)
+    u2, v2, lr2, it, st = O.chi_sinkhorn(C, beta, u, v, r, c, lr, 1e-4)
+    assert st == 0 and it >= 1
+    rP = np.exp(O.log_row_marginal(C, beta, u2, v2))
+    np.testing.assert_allclose(np.exp(lr2), rP, rtol=1e-14)
+    assert ((r - rP) ** 2 / rP).sum() <= 1e-4
+    np.testing.assert_allclose(np.exp(O.log_col_marginal(C, beta, u2, v2)), c, rtol=1e-13)
+
+
+def test_tnp_reaches_tolerance_and_dual_decreases():
+    C, r, c, u, v, beta = instance(12, 10, 14, beta=60.0, spread=0.5)
+    eps = 1e-9
+    g_start = O.dual(C, beta, u, fixed_cols(C, beta, u, c), r, c)
+    u2, v2, dmin, rho, st, status = O.tnp(C, beta, u, v, r, c, eps)
+    assert status == 0 and st["newton_steps"] >= 1
+    rP = np.exp(O.log_row_marginal(C, beta, u2, v2))
+    cP = np.exp(O.log_col_marginal(C, beta, u2, v2))
+    assert np.abs(rP - r).sum() <= 1e-14          # L18 matches the rows exactly
+    assert np.abs(cP - c).sum() <= eps * 1.001     # columns moved by < ||r - r(P)||_1
+    assert O.dual(C, beta, u2, v2, r, c) <= g_start
+
+
+def test_tnp_steps_monotone_dual_and_superlinear_tail():
+    # Manual Alg. 4 loop from the oracle's pieces: g never increases across
+    # accepted steps (Armijo) and the marginal error falls superlinearly
+    # near the solution (theorem "algthreeimprov").
+    C, r, c, u, v, beta = instance(15, 15, 15, beta=40.0, spread=0.2)
+    eps = 1e-12
+    v = fixed_cols(C, beta, u, c)
+    lr = O.log_row_marginal(C, beta, u, v)
+    gs, errs = [O.dual(C, beta, u, v, r, c)], [np.abs(np.exp(lr) - r).sum()]
+    rho0 = 0.0
+    for _ in range(30):
+        if errs[-1] <= eps:
+            break
+        u, v, lr, _, _ = O.chi_sinkhorn(C, beta, u, v, r, c, lr, eps ** 0.4)
+        grad = np.exp(lr) - r
+        gk = np.abs(grad).sum()
+        eta = max(gk, 0.8 * eps / gk)
+        R = O.newton_solve(C, beta, u, v, r, c, lr, eta, rho0)
+        rho0 = max(0.0, 1 - 4 * (1 - R.rho))
+        alpha, lca, _, _ = O.line_search(C, beta, u, v, grad, R.du, R.dv)
+        u = u + alpha * R.du
+        v = v + alpha * R.dv + np.log(c) - lca
+        lr = O.log_row_marginal(C, beta, u, v)
+        gs.append(O.dual(C, beta, u, v, r, c))
+        errs.append(np.abs(np.exp(lr) - r).sum())
+    assert errs[-1] <= eps
+    assert all(b <= a + 1e-15 for a, b in zip(gs, gs[1:]))
+    tail = [e for e in errs if 1e-11 < e < 1e-4]
+    ratios = [b / a for a, b in zip(tail, tail[1:])]
+    assert ratios and max(ratios) < 0.2
+
+
+# ------------------------------------------------------------ end to end
+
+def _plan(C, beta, u, v):
+    return np.exp(u[:, None] + v[None, :] - beta * C)
+
+
+def test_solve_separable_cost_gives_independent_coupling():
+    # C_ij = a_i + b_j: P* = r c^T for every temperature (the separable part
+    # is absorbed by the potentials).
+    rng = np.random.default_rng(3)
+    a = rng.uniform(0, 0.5, 9); b = rng.uniform(0, 0.5, 6)
+    C = a[:, None] + b[None, :]
+    r = rng.dirichlet(np.ones(9)); c = rng.dirichlet(np.ones(6))
+    u, v, st = O.solve(C, r, c, gamma_init=0.1, gamma_final=1e-3, tol=1e-12)
+    assert st["status"] == 0
+    P = _plan(C, 1e3, u, v)
+    np.testing.assert_allclose(P, r[:, None] * c[None, :], rtol=0, atol=1e-12)
+    assert st["cost"] == pytest.approx(r @ C @ c, rel=1e-10)
+
+
+def test_solve_approaches_bruteforce_assignment():
+    # Uniform marginals, n = 6: OT* = min over permutations (Birkhoff). The
+    # rounded plan is feasible and within 2 gamma_f min(H(r), H(c)) of OT*
+    # (the guarantee quoted after Alg. 1).
+    rng = np.random.default_rng(5)
+    n = 6
+    X = rng.uniform(size=(n, 2)); Y = rng.uniform(size=(n, 2))
+    C = ((X[:, None] - Y[None]) ** 2).sum(-1)
+    C /= C.max()
+    r = np.full(n, 1.0 / n); c = np.full(n, 1.0 / n)
+    ot = min(sum(C[i, s[i]] for i in range(n)) / n for s in itertools.permutations(range(n)))
+    prev_gap = None
+    for gamma in (1e-1, 1e-2, 1e-3):
+        u, v, st = O.solve(C, r, c, gamma_init=0.5, gamma_final=gamma, tol=1e-10)
+        assert st["status"] == 0
+        P = O.round_plan(C, 1 / gamma, u, v, r, c)
+        np.testing.assert_allclose(P.sum(1), r, atol=1e-15)
+        np.testing.assert_allclose(P.sum(0), c, atol=1e-15)
+        gap = (P * C).sum() - ot
+        assert -1e-12 <= gap <= 2 * gamma * np.log(n) + 1e-12
+        if prev_gap is not None:
+            assert gap <= prev_gap + 1e-12
+        prev_gap = gap
+    assert prev_gap < 1e-6
+
+
+def test_solve_matches_linear_program_rectangular():
+    rng = np.random.default_rng(6)
+    n, m = 8, 5
+    C = rng.uniform(size=(n, m))
+    r = rng.dirichlet(np.ones(n)); c = rng.dirichlet(np.ones(m))
+    A = np.zeros((n + m, n * m))
+    for i in range(n):
+        A[i, i * m:(i + 1) * m] = 1
+    for j in range(m):
+        A[n + j, j::m] = 1
+    lp = linprog(C.reshape(-1), A_eq=A, b_eq=np.concatenate([r, c]), bounds=(0, None),
+                 method="highs")
+    gamma = 1e-3
+    u, v, st = O.solve(C, r, c, gamma_init=0.1, gamma_final=gamma, tol=1e-10)
+    assert st["status"] == 0 and st["err_r"] + st["err_c"] <= 1e-10
+    P = O.round_plan(C, 1 / gamma, u, v, r, c)
+    H = lambda x: -(x * np.log(x)).sum()
+    gap = (P * C).sum() - lp.fun
+    assert -1e-9 <= gap <= 2 * gamma * min(H(r), H(c)) + 1e-9
+
+
+def test_solve_strong_duality_and_tolerance():
+    # At a feasible P(u, v): <P, C> - gamma H(P) = -gamma g(u, v) with the
+    # KL-to-uniform primal of App. A.2 (value gamma(<u, r> + <v, c>)).
+    C, r, c, _, _, _ = instance(10, 14, 16)
+    gamma = 1e-2
+    u, v, st = O.solve(C, r, c, gamma_init=0.1, gamma_final=gamma, tol=1e-11)
+    assert st["status"] == 0
+    assert st["err_r"] + st["err_c"] <= 1e-11
+    ld = np.longdouble
+    X = u.astype(ld)[:, None] + v.astype(ld)[None, :] - ld(1 / gamma) * C.astype(ld)
+    P = np.exp(X)
+    primal = float((P * C.astype(ld)).sum() + ld(gamma) * (P * X).sum())
+    assert primal == pytest.approx(-gamma * st["dual_value"], rel=1e-9)
+    assert st["cost"] == pytest.approx(float((P * C.astype(ld)).sum()), rel=1e-12)
+
+
+def test_round_is_feasible_and_close():
+    C, r, c, u, v, beta = instance(6, 9, 17, beta=5.0, spread=0.5)
+    P0 = _plan(C, beta, u, v)
+    P = O.round_plan(C, beta, u, v, r, c)
+    assert (P >= 0).all()
+    np.testing.assert_allclose(P.sum(1), r, atol=1e-15)
+    np.testing.assert_allclose(P.sum(0), c, atol=1e-15)
+    bound = 2 * (np.abs(P0.sum(1) - r).sum() + np.abs(P0.sum(0) - c).sum())
+    assert np.abs(P - P0).sum() <= bound + 1e-15
+
+
+def test_appendix_c_worked_example():
+    # App. C: P_rc close to the block matrix Q mixes at rate 0.5 along
+    # r(P) - r when r has the right mass in each block, despite lambda_2 ~ 1.
+    g = json.load(open(os.path.join(GOLDEN, "appC_4x4.json")))
+    Q = np.array(g["Q"])
+    np.testing.assert_allclose(np.sort(np.linalg.eigvalsh(Q))[::-1], g["eigenvalues"], atol=1e-15)
+    # A 4x4 plan with uniform marginals and P_rc ~ Q: blocks [[a, b], [b, a]],
+    # a^2 + b^2 = 3/4, 2ab = 1/4, tiny coupling delta between the blocks.
+    delta = 1e-10
+    a = (1 + np.sqrt(0.5)) / 2 - delta
+    b = (1 - np.sqrt(0.5)) / 2 - delta
+    B = np.array([[a, b], [b, a]])
+    P = np.full((4, 4), delta)
+    P[:2, :2] = B; P[2:, 2:] = B
+    P /= 4.0
+    beta = 30.0
+    C = -np.log(P) / beta                      # u = v = 0 reproduces P
+    assert C.min() >= 0 and C.max() <= 1
+    u = np.zeros(4); v = np.zeros(4)
+    rP = np.exp(O.log_row_marginal(C, beta, u, v))
+    cP = np.exp(O.log_col_marginal(C, beta, u, v))
+    np.testing.assert_allclose(rP, g["r_P"], atol=1e-15)
+    F1 = dense_fr(C, beta, u, v, rP, cP, 1.0)
+    Prc = np.eye(4) - F1 / rP[:, None]
+    np.testing.assert_allclose(Prc, Q, atol=1e-8)
+    rt = np.array(g["r"])
+    chi = np.sqrt(((rt - rP) ** 2 / rP).sum())
+    w = rP - rt
+    for ell in range(1, 6):
+        w = w @ Prc
+        assert np.abs(w).sum() == pytest.approx(g["decay_per_step"] ** ell * chi, rel=1e-6)
