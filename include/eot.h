@@ -1,0 +1,208 @@
+/*
+ * eot.h -- C ABI of the MI355X (gfx950) truncated-Newton entropic-OT library.
+ *
+ * The method is the one of Kemertas, Farahmand & Jepson, "A Truncated Newton
+ * Method for Optimal Transport" (ICLR 2025): MDOT temperature annealing
+ * (Alg. 1) around TruncatedNewtonProject (Alg. 4), whose Newton direction
+ * comes from NewtonSolve (Alg. 2), a diagonally preconditioned conjugate-
+ * gradient solve of the discounted reduced Newton system (Sec. 3.1).
+ *
+ * Problem statement (Sec. 2.1): cost C (n x m, entries in [0, 1], eq.
+ * opt:original-OT-problem), marginals r (n) and c (m) on the simplex, and a
+ * temperature gamma > 0. NOTE: the paper's "gamma" is the inverse
+ * temperature; here `gamma` is the temperature itself (beta = 1/gamma is the
+ * paper's gamma). Potentials at this interface are in cost units:
+ *
+ *     P_ij = exp((f_i + g_j - C_ij) / gamma)          (eq. lagrangian-closed-form)
+ *
+ * i.e. f = u / beta, g = v / beta with the paper's log-unit (u, v).
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are DEVICE pointers owned by the caller (e.g. PyTorch
+ *    tensors); the library never allocates or frees them. Struct pointers
+ *    marked "host" point to host memory.
+ *  - Scratch memory comes from the caller-provided `ws` (device, 256-byte
+ *    aligned) of at least the size eot_workspace_size() reports; the library
+ *    calls no hipMalloc.
+ *  - `stream` is a hipStream_t (NULL = the default stream). eot_marginals
+ *    and eot_hvp are asynchronous on it; eot_newton_cg and eot_solve make
+ *    host-side decisions and return after their work on `stream` finished.
+ *  - Errors are returned as eot_status; nothing throws across the ABI. On
+ *    an error the contents of output arrays are unspecified, except
+ *    EOT_ERR_NOT_CONVERGED, which leaves the last iterate in the outputs.
+ *  - Vectors are FP64. Dense costs are row-major with leading dimension
+ *    ldc >= m (elements).
+ *  - Calls on different streams with different workspaces are independent;
+ *    the library keeps no global mutable state.
+ */
+#ifndef EOT_H
+#define EOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EOT_OK = 0,
+    EOT_ERR_INVALID_ARG = 1,   /* null pointer, n or m < 1, gamma <= 0 or not finite, bad option */
+    EOT_ERR_BAD_MARGINALS = 2, /* an entry <= 0 or not finite, or |sum - 1| > 1e-9              */
+    EOT_ERR_NONFINITE = 3,     /* a NaN / Inf appeared and the range fallback failed            */
+    EOT_ERR_NOT_CONVERGED = 4, /* an iteration cap was hit; outputs hold the last iterate       */
+    EOT_ERR_WORKSPACE = 5,     /* ws NULL or smaller than eot_workspace_size() / misaligned     */
+    EOT_ERR_UNSUPPORTED = 6,   /* e.g. mixed precision on an FP64 dense cost                    */
+    EOT_ERR_HIP = 7            /* a HIP runtime call failed                                     */
+} eot_status;
+
+typedef enum {
+    EOT_PREC_FP64 = 0,  /* every operation in FP64 (exp included)                          */
+    EOT_PREC_MIXED = 1  /* plan entries, exp and cost in FP32 (exponent assembled exactly
+                           from FP64 potentials), all sums, CG inner products, residual
+                           norms, potentials and the line search in FP64                   */
+} eot_precision;
+
+typedef enum {
+    EOT_COST_DENSE_F32 = 0,       /* C: float[n * ldc]                                       */
+    EOT_COST_DENSE_F64 = 1,       /* C: double[n * ldc]                                      */
+    EOT_COST_SQEUCLID_POINTS = 2  /* C_ij = |x_i - y_j|^2 / scale, recomputed on the fly
+                                     from X: float[n * d], Y: float[m * d] (Sec. 4.2: the
+                                     O(n)-memory variant)                                    */
+} eot_cost_kind;
+
+typedef struct {
+    int32_t kind;      /* eot_cost_kind                                            */
+    int32_t d;         /* point dimension (points only), 1..16                      */
+    int64_t n;         /* rows    (length of r, f)                                  */
+    int64_t m;         /* columns (length of c, g)                                  */
+    int64_t ldc;       /* dense: leading dimension in elements, >= m                */
+    const void* C;     /* dense: device pointer                                     */
+    const float* X;    /* points: device, n x d row-major                           */
+    const float* Y;    /* points: device, m x d row-major                           */
+    double scale;      /* points: normaliser (> 0), e.g. max_ij |x_i - y_j|^2        */
+} eot_cost;
+
+typedef enum {
+    EOT_OP_MARGINALS = 0,
+    EOT_OP_HVP = 1,
+    EOT_OP_NEWTON_CG = 2,
+    EOT_OP_SOLVE = 3
+} eot_op;
+
+/* Scratch bytes that `op` needs for `cost` in precision `prec`.
+ * Returns EOT_ERR_INVALID_ARG for a malformed cost. */
+eot_status eot_workspace_size(int32_t op, const eot_cost* cost, int32_t prec, size_t* bytes);
+
+/* Row and column marginals of the plan (Sec. 2 Notation, LSE_r / LSE_c):
+ *   log_rP[i] = log sum_j P_ij,  log_cP[j] = log sum_i P_ij,
+ *   mass[0]   = sum_ij P_ij                       (device scalar),
+ *   s[i]      = sum_j P_ij^2 / c[j]   with c = c_for_s (the diagonal term of
+ *               the CG preconditioner diag F_r(rho) = r(P) - rho s, lemma
+ *               "condo" in App. A).
+ * One streaming pass over C computes all requested outputs.
+ * row_shift (nullable): an estimate of log r(P) used only to keep the
+ * exponentials in range (any value within ~80 of the truth works in mixed
+ * precision, ~700 in FP64); NULL makes the library compute the exact row
+ * maximum first (one extra pass).
+ * log_rP, log_cP, mass, s are nullable (skip); s needs c_for_s.
+ * f: n, g: m, log_rP/s: n, log_cP: m. */
+eot_status eot_marginals(const eot_cost* cost, double gamma, const double* f, const double* g,
+                         const double* row_shift, double* log_rP, double* log_cP, double* mass,
+                         const double* c_for_s, double* s, int32_t prec,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* Discounted Hessian-vector product of the dual g(u, v) (eqs. hessian and
+ * discounted-hessian), in the paper's log units, at P(f, g):
+ *   Hx = r(P) * x + sqrt(rho) * P y,    Hy = sqrt(rho) * P^T x + c(P) * y.
+ * rho in [0, 1]; rho = 1 is the undiscounted Hessian. One pass over C serves
+ * both the row (P y, r(P)) and the column (P^T x, c(P)) reductions.
+ * x, Hx: n; y, Hy: m. row_shift as for eot_marginals. */
+eot_status eot_hvp(const eot_cost* cost, double gamma, const double* f, const double* g,
+                   const double* row_shift, double rho, const double* x, const double* y,
+                   double* Hx, double* Hy, int32_t prec, void* ws, size_t ws_bytes,
+                   void* stream);
+
+typedef struct {
+    double rho_out;     /* discount at exit (Alg. 2 L4 after the last solve)          */
+    int32_t cg_iters;   /* CG iterations over all discount levels                     */
+    int32_t levels;     /* discount levels solved                                     */
+    int32_t forcing_miss; /* 1 if the forcing test was unmet at the discount cap      */
+    int32_t status;
+    int64_t passes;     /* streaming passes over C                                    */
+    double forcing_ratio; /* ||F_r(1) d + grad_u g||_1 / ||grad g||_1 at exit         */
+} eot_newton_stats;
+
+/* NewtonSolve (Alg. 2) with the warm discount of App. B: diagonally
+ * preconditioned CG on F_r(rho) d = -grad_u g from d = 0, stopped at
+ * ||F_r(rho) d + grad_u g||_1 <= (eta/4) ||grad g||_1, rho annealed
+ * rho <- 1 - (1 - rho)/4 from rho0 until ||F_r(1) d + grad_u g||_1 <=
+ * eta ||grad g||_1, then d_v = -P_c d_u (Alg. 4 L7). Here
+ * F_r(rho) = D(r(P)) - rho P D(c)^-1 P^T (eq. matrix-definitions).
+ * Precondition (as in Alg. 4): the columns are fixed, c(P) = c.
+ * r: n, c: m (targets); outputs dir_f: n, dir_g: m in cost units
+ * (gamma * d_u, gamma * d_v). The discount is capped at 1 - 2^-30; if the
+ * forcing test is still unmet there (nearly decomposable P_rc) or a CG solve
+ * hits max_cg, the last converged CG direction is returned and
+ * stats->forcing_miss = 1. stats: host pointer, nullable. */
+eot_status eot_newton_cg(const eot_cost* cost, double gamma, const double* f, const double* g,
+                         const double* r, const double* c, double eta, double rho0,
+                         int32_t max_cg, int32_t max_levels, double* dir_f, double* dir_g,
+                         eot_newton_stats* stats, int32_t prec, void* ws, size_t ws_bytes,
+                         void* stream);
+
+typedef struct {
+    double gamma_init;      /* initial temperature (1/beta_i); default 1/32            */
+    double gamma_final;     /* final temperature (1/beta_f)                            */
+    double tol;             /* target L1 marginal error vs the given r, c; 1e-6        */
+    double p;               /* eps_d = min(H(r), H(c)) / beta^p (Alg. 1 L4); 1.5       */
+    double q1;              /* initial decay factor q^(1); 2                           */
+    double w_r;             /* row smoothing weight (Sec. 3.4), w_c = 1/2 - w_r; 0.45  */
+    int32_t adaptive_q;     /* AdjustSchedule (Sec. 3.3) on; 1                         */
+    int32_t adaptive_rho0;  /* warm discount of App. B on; 1                           */
+    int32_t max_cg;         /* 1000 */
+    int32_t max_levels;     /* 30   */
+    int32_t max_backtrack;  /* 60   */
+    int32_t max_newton;     /* 200  */
+    int32_t max_sinkhorn;   /* 10000 */
+    int32_t max_mdot;       /* 500  */
+    int32_t precision;      /* eot_precision                                           */
+    int32_t verify_fp64;    /* mixed: check (and if needed finish) the last projection
+                               with FP64 passes so the reported error is exact; 1     */
+} eot_solve_opts;
+
+typedef struct {
+    int32_t status;
+    int32_t mdot_steps, newton_steps, cg_iters, backtracks, sinkhorn_iters, levels;
+    int32_t forcing_misses, range_retries;
+    int64_t passes_newton, passes_linesearch, passes_sinkhorn, passes_projection, passes_other;
+    double final_gamma;
+    double err_r, err_c;    /* L1 marginal errors vs the unsmoothed r, c, FP64 pass     */
+    double cost;            /* <P, C> at the output potentials, FP64                    */
+    double dual_value;      /* W = gamma (<u, r> + <v, c> - sum P + 1), cost units      */
+    double rho_last, delta_min_last;
+    double seconds;         /* host wall-clock of the call                              */
+} eot_solve_stats;
+
+void eot_solve_opts_default(eot_solve_opts* opts);
+
+/* MDOT (Alg. 1) with AdjustSchedule (Sec. 3.3), asymmetric smoothing
+ * (Sec. 3.4) and TruncatedNewtonProject (Alg. 4) as the Bregman projection;
+ * returns the potentials at gamma_final in cost units (f: n, g: m). The
+ * plan at the output is exp((f_i + g_j - C_ij)/gamma_final); rounding onto
+ * U(r, c) (Alg. 1 L13) is not applied. r: n, c: m on the simplex.
+ * opts, stats: host pointers (stats nullable). */
+eot_status eot_solve(const eot_cost* cost, const double* r, const double* c,
+                     const eot_solve_opts* opts, double* f, double* g,
+                     eot_solve_stats* stats, void* ws, size_t ws_bytes, void* stream);
+
+/* Static text for a status code. */
+const char* eot_status_string(int32_t status);
+
+/* Library version string, e.g. "0.1.0 gfx950". */
+const char* eot_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EOT_H */

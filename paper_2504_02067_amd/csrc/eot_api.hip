@@ -1,0 +1,792 @@
+// C ABI and host drivers of the truncated-Newton entropic-OT library.
+//
+// The drivers take the steps of the paper's algorithms in order -- MDOT
+// (Alg. 1), TruncatedNewtonProject (Alg. 4), ChiSinkhorn (Alg. 3),
+// NewtonSolve (Alg. 2) with diagonally preconditioned CG -- and run every
+// O(nm) primitive as a streaming pass on the device (eot_kernels.hip). The
+// host only makes the scalar decisions (CG stop, forcing test, Armijo,
+// ChiSinkhorn and projection loop tests, schedule updates), reading a few
+// FP64 scalars back after the kernels that produce them.
+//
+// Everything is in the paper's log units inside (u = f / gamma, beta =
+// 1 / gamma); the ABI speaks cost units (see include/eot.h).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "eot_internal.h"
+
+using namespace eot;
+
+namespace {
+
+// Discount cap of NewtonSolve: 1 - 2^-30 (kappa(F_r) <= 2 / (1 - rho) ~ 2e9).
+constexpr double kRhoMax = 1.0 - 9.313225746154785e-10;
+
+constexpr size_t kAlign = 256;
+
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0;
+    size_t off = 0;
+    bool dry = true;
+    template <typename T>
+    T* take(size_t count)
+    {
+        off = (off + kAlign - 1) / kAlign * kAlign;
+        T* p = dry ? nullptr : reinterpret_cast<T*>(base + off);
+        off += std::max<size_t>(count, 1) * sizeof(T);
+        return p;
+    }
+};
+
+#define HIPCHK(x)                                          \
+    do {                                                   \
+        hipError_t e_ = (x);                               \
+        if (e_ != hipSuccess) return EOT_ERR_HIP;          \
+    } while (0)
+
+#define EOTCHK(x)                                          \
+    do {                                                   \
+        eot_status s_ = (x);                               \
+        if (s_ != EOT_OK) return s_;                       \
+    } while (0)
+
+struct Scratch {
+    double* row_part = nullptr;  // 2 x tiles_m x n
+    double* col_part = nullptr;  // 2 x tiles_n x m
+    double* red = nullptr;       // 2 x kMaxRedBlocks
+    double* red2 = nullptr;      // 2 x kMaxRedBlocks
+    double* scal = nullptr;      // 64 device scalars
+    int32_t* flags = nullptr;    // 16 flags
+    CgScalars* cg = nullptr;
+};
+
+struct NewtonVecs {
+    double *rP, *grad, *b, *d, *e1, *dtry, *res, *z, *p, *q, *t, *M, *pcptd_try, *pcptd;  // n
+    double *w, *wc, *ptd_try, *ptd;                                                         // m
+};
+
+struct SolveVecs {
+    double *u, *lr, *s, *rt, *lrt, *du, *u_prev, *ua, *sh, *sh2;   // n
+    double *v, *ct, *lct, *inv_ct, *dv, *v_prev, *va, *colsum, *lca; // m
+};
+
+struct Ctx {
+    eot_cost cost{};
+    int64_t n = 0, m = 0;
+    int tiles_m = 0, tiles_n = 0;
+    hipStream_t s = nullptr;
+    Scratch sc;
+    double* tmp_n[4] = {nullptr, nullptr, nullptr, nullptr};
+    double* tmp_m[4] = {nullptr, nullptr, nullptr, nullptr};
+    NewtonVecs nv{};
+    SolveVecs sv{};
+    int64_t passes = 0;
+    int32_t range_retries = 0;
+};
+
+void carve(Arena& ar, Ctx& x, int op)
+{
+    const int64_t n = x.n, m = x.m;
+    x.sc.row_part = ar.take<double>((size_t)2 * x.tiles_m * n);
+    x.sc.col_part = ar.take<double>((size_t)2 * x.tiles_n * m);
+    x.sc.red = ar.take<double>(2 * kMaxRedBlocks);
+    x.sc.red2 = ar.take<double>(2 * kMaxRedBlocks);
+    x.sc.scal = ar.take<double>(64);
+    x.sc.flags = ar.take<int32_t>(16);
+    x.sc.cg = ar.take<CgScalars>(1);
+    for (int k = 0; k < 4; ++k) x.tmp_n[k] = ar.take<double>(n);
+    for (int k = 0; k < 4; ++k) x.tmp_m[k] = ar.take<double>(m);
+    if (op == EOT_OP_NEWTON_CG || op == EOT_OP_SOLVE) {
+        NewtonVecs& v = x.nv;
+        double** nvec[] = {&v.rP, &v.grad, &v.b, &v.d, &v.e1, &v.dtry, &v.res, &v.z,
+                           &v.p, &v.q, &v.t, &v.M, &v.pcptd_try, &v.pcptd};
+        for (double** p : nvec) *p = ar.take<double>(n);
+        double** mvec[] = {&v.w, &v.wc, &v.ptd_try, &v.ptd};
+        for (double** p : mvec) *p = ar.take<double>(m);
+    }
+    if (op == EOT_OP_SOLVE) {
+        SolveVecs& v = x.sv;
+        double** nvec[] = {&v.u, &v.lr, &v.s, &v.rt, &v.lrt, &v.du, &v.u_prev, &v.ua, &v.sh, &v.sh2};
+        for (double** p : nvec) *p = ar.take<double>(n);
+        double** mvec[] = {&v.v, &v.ct, &v.lct, &v.inv_ct, &v.dv, &v.v_prev, &v.va, &v.colsum, &v.lca};
+        for (double** p : mvec) *p = ar.take<double>(m);
+    }
+}
+
+eot_status check_cost(const eot_cost* c)
+{
+    if (!c) return EOT_ERR_INVALID_ARG;
+    if (c->n < 1 || c->m < 1) return EOT_ERR_INVALID_ARG;
+    if (c->kind == EOT_COST_DENSE_F32 || c->kind == EOT_COST_DENSE_F64) {
+        if (!c->C || c->ldc < c->m) return EOT_ERR_INVALID_ARG;
+        return EOT_OK;
+    }
+    if (c->kind == EOT_COST_SQEUCLID_POINTS) return EOT_ERR_UNSUPPORTED;
+    return EOT_ERR_INVALID_ARG;
+}
+
+eot_status setup(Ctx& x, const eot_cost* cost, int op, int prec, void* ws, size_t ws_bytes,
+                 void* stream)
+{
+    EOTCHK(check_cost(cost));
+    if (prec != EOT_PREC_FP64 && prec != EOT_PREC_MIXED) return EOT_ERR_INVALID_ARG;
+    if (prec == EOT_PREC_MIXED && cost->kind == EOT_COST_DENSE_F64) return EOT_ERR_UNSUPPORTED;
+    x.cost = *cost;
+    x.n = cost->n;
+    x.m = cost->m;
+    x.tiles_m = (int)tiles_m_of(x.m);
+    x.tiles_n = (int)tiles_n_of(x.n);
+    x.s = static_cast<hipStream_t>(stream);
+    Arena dry;
+    carve(dry, x, op);
+    if (!ws || ws_bytes < dry.off || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0)
+        return EOT_ERR_WORKSPACE;
+    Arena ar;
+    ar.base = static_cast<char*>(ws);
+    ar.cap = ws_bytes;
+    ar.dry = false;
+    carve(ar, x, op);
+    HIPCHK(hipMemsetAsync(x.sc.flags, 0, 16 * sizeof(int32_t), x.s));
+    return EOT_OK;
+}
+
+PassArgs make_args(const Ctx& x, const double* u, const double* a, const double* v, double beta)
+{
+    PassArgs A{};
+    A.kind = x.cost.kind;
+    A.C = x.cost.C;
+    A.n = x.n;
+    A.m = x.m;
+    A.ldc = x.cost.ldc;
+    A.vec_ok = (x.cost.ldc % 4 == 0) && (reinterpret_cast<uintptr_t>(x.cost.C) % 16 == 0);
+    A.u = u;
+    A.a = a;
+    A.v = v;
+    A.beta = beta;
+    A.row_part = x.sc.row_part;
+    A.col_part = x.sc.col_part;
+    A.tiles_m = x.tiles_m;
+    A.tiles_n = x.tiles_n;
+    return A;
+}
+
+// Read `k` device doubles back to the host (waits for the stream).
+eot_status fetch(Ctx& x, const double* d, double* h, int k)
+{
+    HIPCHK(hipMemcpyAsync(h, d, sizeof(double) * k, hipMemcpyDeviceToHost, x.s));
+    HIPCHK(hipStreamSynchronize(x.s));
+    return EOT_OK;
+}
+
+eot_status fetch_flags(Ctx& x, int32_t* h)
+{
+    HIPCHK(hipMemcpyAsync(h, x.sc.flags, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, x.s));
+    HIPCHK(hipStreamSynchronize(x.s));
+    return EOT_OK;
+}
+
+eot_status clear_flags(Ctx& x)
+{
+    HIPCHK(hipMemsetAsync(x.sc.flags, 0, 16 * sizeof(int32_t), x.s));
+    return EOT_OK;
+}
+
+// Device reduction -> host scalar.
+eot_status reduce_host(Ctx& x, int op, const double* a, const double* b, int64_t k, double* out)
+{
+    int nb = 0;
+    HIPCHK(launch_reduce(op, a, b, k, x.sc.red, &nb, x.s));
+    HIPCHK(launch_finish_sum(x.sc.red, nb, x.sc.scal, x.s));
+    return fetch(x, x.sc.scal, out, 1);
+}
+
+// Row shift = exact row maxima (one FP64 pass).
+eot_status row_max(Ctx& x, const double* u, const double* v, double beta, double* out)
+{
+    PassArgs A = make_args(x, u, nullptr, v, beta);
+    HIPCHK(launch_rowmax(A, x.sc.row_part, out, x.s));
+    x.passes += 1;
+    return EOT_OK;
+}
+
+// log r(P) (and s_i = sum_j P_ij^2 / c_j when inv_c) at (u, v), shift a.
+eot_status row_pass(Ctx& x, int prec, const double* u, const double* a, const double* v,
+                    double beta, const double* inv_c, double* log_rP, double* s_out)
+{
+    PassArgs A = make_args(x, u, a, v, beta);
+    A.yw1 = inv_c;
+    const int nr = inv_c ? 2 : 1;
+    HIPCHK(launch_pass(A, prec, nr, 0, R2_SQUARE, x.s));
+    HIPCHK(launch_log_row_from_sums(x.sc.row_part, x.tiles_m, x.n, a, log_rP, x.sc.flags, x.s));
+    if (inv_c && s_out)
+        HIPCHK(launch_merge_rows(x.sc.row_part, x.tiles_m, x.n, 2, a, nullptr, s_out, 1, x.s));
+    x.passes += 1;
+    return EOT_OK;
+}
+
+// Column sums sum_i P_ij xw_i (xw nullable = 1) at (u, v), shift a.
+eot_status col_pass(Ctx& x, int prec, const double* u, const double* a, const double* v,
+                    double beta, const double* xw, double* colsum)
+{
+    PassArgs A = make_args(x, u, a, v, beta);
+    A.xw0 = xw;
+    HIPCHK(launch_pass(A, prec, 0, 1, R2_WEIGHT, x.s));
+    HIPCHK(launch_merge_cols(x.sc.col_part, x.tiles_n, x.m, 1, colsum, nullptr, x.s));
+    x.passes += 1;
+    return EOT_OK;
+}
+
+// Row sums sum_j P_ij yw_j at (u, v), shift a -> out (with exp(a) applied).
+eot_status rowsum_pass(Ctx& x, int prec, const double* u, const double* a, const double* v,
+                       double beta, const double* yw, double* out)
+{
+    PassArgs A = make_args(x, u, a, v, beta);
+    A.yw0 = yw;
+    HIPCHK(launch_pass(A, prec, 1, 0, R2_WEIGHT, x.s));
+    HIPCHK(launch_merge_rows(x.sc.row_part, x.tiles_m, x.n, 1, a, out, nullptr, 0, x.s));
+    x.passes += 1;
+    return EOT_OK;
+}
+
+// ---------------------------------------------------------------- NewtonSolve
+struct NewtonResult {
+    double rho = 0.0;
+    int32_t cg_iters = 0, levels = 0, miss = 0;
+    int64_t passes = 0;
+    double forcing_ratio = 0.0;
+};
+
+// Alg. 2 at (u, v) with c(P) = c: lr = log r(P) (also the row shift), s_i =
+// sum_j P_ij^2 / c_j. Writes d_u to du and d_v = -(P^T d_u) / c to dv.
+eot_status newton_solve(Ctx& x, int prec, const double* u, const double* v, double beta,
+                        const double* lr, const double* s, const double* r, const double* c,
+                        double eta, double rho0, int max_cg, int max_levels, double* du,
+                        double* dv, NewtonResult* out)
+{
+    NewtonVecs& V = x.nv;
+    const int64_t n = x.n, m = x.m;
+    const int64_t p0 = x.passes;
+    HIPCHK(launch_newton_init(lr, r, V.rP, V.grad, V.b, V.d, n, x.s));
+    double gnorm = 0.0;
+    EOTCHK(reduce_host(x, RED_L1, V.grad, nullptr, n, &gnorm));
+    // F_r(1) d for the rho = 0 direction: two explicit passes
+    EOTCHK(col_pass(x, prec, u, lr, v, beta, V.d, V.ptd));
+    HIPCHK(launch_div(V.ptd, c, V.wc, 1.0, m, x.s));
+    EOTCHK(rowsum_pass(x, prec, u, lr, v, beta, V.wc, V.pcptd));
+    HIPCHK(launch_forcing_resid(V.rP, V.d, V.pcptd, V.grad, V.e1, n, x.s));
+    double e1 = 0.0;
+    EOTCHK(reduce_host(x, RED_L1, V.e1, nullptr, n, &e1));
+
+    double rho = rho0;
+    int32_t lev = 0, cgk = 0, miss = 0;
+    for (;;) {
+        if (e1 <= eta * gnorm) break;
+        if (lev >= max_levels || rho > kRhoMax) { miss = 1; break; }
+        if (rho == 0.0) {
+            // F_r(0) = D(r(P)): the CG solution is -grad / r(P), the current d.
+            cgk += 1;
+            rho = 0.75;
+            ++lev;
+            continue;
+        }
+        const double tol = 0.25 * eta * gnorm;
+        HIPCHK(launch_cg_init(V.b, V.rP, s, rho, V.dtry, V.res, V.z, V.p, V.M, V.ptd_try,
+                              V.pcptd_try, n, m, x.sc.red, x.sc.cg, x.s));
+        CgScalars h{};
+        EOTCHK(fetch(x, reinterpret_cast<const double*>(x.sc.cg), reinterpret_cast<double*>(&h),
+                     sizeof(CgScalars) / sizeof(double)));
+        bool conv = h.res_l1 <= tol;
+        int k = 0;
+        bool broke = false;
+        while (!conv && k < max_cg) {
+            // pass A: w = P^T p ; pass B: t = P (w / c) ; q = r(P) p - rho t
+            EOTCHK(col_pass(x, prec, u, lr, v, beta, V.p, V.w));
+            HIPCHK(launch_div(V.w, c, V.wc, 1.0, m, x.s));
+            {
+                PassArgs A = make_args(x, u, lr, v, beta);
+                A.yw0 = V.wc;
+                HIPCHK(launch_pass(A, prec, 1, 0, R2_WEIGHT, x.s));
+                x.passes += 1;
+            }
+            int nb_pq = 0, nb = 0;
+            HIPCHK(launch_cg_rowstep(x.sc.row_part, x.tiles_m, n, lr, V.rP, V.p, rho, V.t, V.q,
+                                     x.sc.red2, &nb_pq, x.s));
+            HIPCHK(launch_cg_update(x.sc.red2, nb_pq, V.dtry, V.res, V.z, V.p, V.q, V.M, V.t,
+                                    V.pcptd_try, V.w, V.ptd_try, n, m, x.sc.red, &nb, x.sc.cg,
+                                    x.s));
+            HIPCHK(launch_cg_direction(x.sc.red, nb, V.z, V.p, n, x.sc.cg, x.s));
+            EOTCHK(fetch(x, reinterpret_cast<const double*>(x.sc.cg),
+                         reinterpret_cast<double*>(&h), sizeof(CgScalars) / sizeof(double)));
+            ++k;
+            if (!std::isfinite(h.alpha) || !(h.pq > 0.0)) { broke = true; break; }
+            conv = h.res_l1 <= tol;
+        }
+        cgk += k;
+        if (!conv || broke) { miss = 1; break; }
+        std::swap(V.d, V.dtry);
+        std::swap(V.ptd, V.ptd_try);
+        std::swap(V.pcptd, V.pcptd_try);
+        HIPCHK(launch_forcing_resid(V.rP, V.d, V.pcptd, V.grad, V.e1, n, x.s));
+        EOTCHK(reduce_host(x, RED_L1, V.e1, nullptr, n, &e1));
+        rho = 1.0 - (1.0 - rho) / 4.0;
+        ++lev;
+    }
+    HIPCHK(launch_copy(V.d, du, n, x.s));
+    HIPCHK(launch_div(V.ptd, c, dv, -1.0, m, x.s));
+    out->rho = rho;
+    out->cg_iters = cgk;
+    out->levels = lev;
+    out->miss = miss;
+    out->passes = x.passes - p0;
+    out->forcing_ratio = gnorm > 0.0 ? e1 / gnorm : 0.0;
+    return EOT_OK;
+}
+
+// ---------------------------------------------------------------- projection
+struct SolveState {
+    const eot_solve_opts* o;
+    eot_solve_stats* st;
+};
+
+// Column fix (v <- v + log c~ - log c(P)) followed by the row refresh
+// (log r(P), s), with a fallback to FP64 passes from exact row maxima when
+// the FP32 range guard fires.
+eot_status fix_and_refresh(Ctx& x, int prec, double beta, const double* shift_guess,
+                           SolveState& ss)
+{
+    SolveVecs& S = x.sv;
+    EOTCHK(clear_flags(x));
+    EOTCHK(col_pass(x, prec, S.u, shift_guess, S.v, beta, nullptr, S.colsum));
+    HIPCHK(launch_fix_cols(S.v, S.lct, S.colsum, x.m, x.sc.flags, x.s));
+    EOTCHK(row_pass(x, prec, S.u, shift_guess, S.v, beta, S.inv_ct, S.lr, S.s));
+    int32_t fl[2] = {0, 0};
+    EOTCHK(fetch_flags(x, fl));
+    if (fl[0] == 0 && fl[1] == 0) return EOT_OK;
+    ss.st->range_retries += 1;
+    EOTCHK(clear_flags(x));
+    EOTCHK(row_max(x, S.u, S.v, beta, S.sh2));
+    EOTCHK(col_pass(x, EOT_PREC_FP64, S.u, S.sh2, S.v, beta, nullptr, S.colsum));
+    HIPCHK(launch_fix_cols(S.v, S.lct, S.colsum, x.m, x.sc.flags, x.s));
+    EOTCHK(row_max(x, S.u, S.v, beta, S.sh2));
+    EOTCHK(row_pass(x, EOT_PREC_FP64, S.u, S.sh2, S.v, beta, S.inv_ct, S.lr, S.s));
+    EOTCHK(fetch_flags(x, fl));
+    if (fl[0] || fl[1]) return EOT_ERR_NONFINITE;
+    return EOT_OK;
+}
+
+// Row refresh only (Alg. 4 L16), same fallback.
+eot_status refresh(Ctx& x, int prec, double beta, const double* shift_guess, SolveState& ss)
+{
+    SolveVecs& S = x.sv;
+    EOTCHK(clear_flags(x));
+    EOTCHK(row_pass(x, prec, S.u, shift_guess, S.v, beta, S.inv_ct, S.lr, S.s));
+    int32_t fl[2] = {0, 0};
+    EOTCHK(fetch_flags(x, fl));
+    if (fl[0] == 0) return EOT_OK;
+    ss.st->range_retries += 1;
+    EOTCHK(clear_flags(x));
+    EOTCHK(row_max(x, S.u, S.v, beta, S.sh2));
+    EOTCHK(row_pass(x, EOT_PREC_FP64, S.u, S.sh2, S.v, beta, S.inv_ct, S.lr, S.s));
+    EOTCHK(fetch_flags(x, fl));
+    return fl[0] ? EOT_ERR_NONFINITE : EOT_OK;
+}
+
+// TruncatedNewtonProject (Alg. 4) on the smoothed marginals held in S.rt,
+// S.ct (logs S.lrt, S.lct; S.inv_ct = 1 / ct).
+eot_status tnp(Ctx& x, int prec, double beta, double eps, double* rho0, double* delta_min,
+               SolveState& ss)
+{
+    SolveVecs& S = x.sv;
+    const eot_solve_opts* o = ss.o;
+    eot_solve_stats* st = ss.st;
+    const int64_t n = x.n, m = x.m;
+    int64_t p0 = x.passes;
+    // L1-L2 from exact row maxima (the potentials were extrapolated).
+    EOTCHK(row_max(x, S.u, S.v, beta, S.sh));
+    EOTCHK(fix_and_refresh(x, prec, beta, S.sh, ss));
+    st->passes_projection += x.passes - p0;
+    double dmin = INFINITY;
+    int32_t k = 0;
+    eot_status status = EOT_OK;
+    for (;;) {
+        double gn = 0.0;
+        EOTCHK(reduce_host(x, RED_L1_DIFF_EXP, S.rt, S.lr, n, &gn));
+        if (!std::isfinite(gn)) return EOT_ERR_NONFINITE;
+        if (gn <= eps) break;                                              // L3
+        if (k >= o->max_newton) { status = EOT_ERR_NOT_CONVERGED; break; }
+        // L4: ChiSinkhorn(eps^(2/5))
+        const double eps_chi = std::pow(eps, 0.4);
+        for (int it = 0;; ++it) {
+            double chi2 = 0.0;
+            EOTCHK(reduce_host(x, RED_CHI2, S.rt, S.lr, n, &chi2));
+            if (!(chi2 > eps_chi)) break;
+            if (it >= o->max_sinkhorn) return EOT_ERR_NOT_CONVERGED;
+            p0 = x.passes;
+            HIPCHK(launch_add_logdiff(S.u, S.lrt, S.lr, n, x.s));           // u += log r - log r(P)
+            EOTCHK(fix_and_refresh(x, prec, beta, S.lrt, ss));
+            st->passes_sinkhorn += x.passes - p0;
+            st->sinkhorn_iters += 1;
+        }
+        HIPCHK(launch_newton_init(S.lr, S.rt, x.nv.rP, x.nv.grad, x.nv.b, x.nv.d, n, x.s));
+        double gk = 0.0;
+        EOTCHK(reduce_host(x, RED_L1, x.nv.grad, nullptr, n, &gk));
+        const double eta = std::max(gk, 0.8 * eps / gk);                  // L5
+        NewtonResult nr;                                                   // L6-L7
+        p0 = x.passes;
+        EOTCHK(newton_solve(x, prec, S.u, S.v, beta, S.lr, S.s, S.rt, S.ct, eta, *rho0,
+                            o->max_cg, o->max_levels, S.du, S.dv, &nr));
+        st->passes_newton += x.passes - p0;
+        st->cg_iters += nr.cg_iters;
+        st->levels += nr.levels;
+        st->forcing_misses += nr.miss;
+        st->rho_last = nr.rho;
+        *rho0 = o->adaptive_rho0 ? std::max(0.0, 1.0 - 4.0 * (1.0 - nr.rho)) : 0.0;
+        // L8-L13: backtracking line search on the mass, FP64 passes.
+        double slope = 0.0;
+        EOTCHK(reduce_host(x, RED_DOT, x.nv.grad, S.du, n, &slope));
+        slope = -slope;
+        double alpha = 1.0;
+        int32_t bt = 0;
+        p0 = x.passes;
+        for (;;) {
+            HIPCHK(launch_shifted(S.u, alpha, S.du, S.ua, n, x.s));
+            HIPCHK(launch_shifted(S.v, alpha, S.dv, S.va, m, x.s));
+            HIPCHK(launch_shifted(S.lr, alpha, S.du, S.sh, n, x.s));
+            EOTCHK(col_pass(x, EOT_PREC_FP64, S.ua, S.sh, S.va, beta, nullptr, S.colsum));
+            double mass = 0.0;
+            EOTCHK(reduce_host(x, RED_SUM, S.colsum, nullptr, m, &mass));
+            if (std::isfinite(mass) && mass - 1.0 <= 0.99 * alpha * slope) break;
+            if (bt >= o->max_backtrack) { status = EOT_ERR_NOT_CONVERGED; break; }
+            alpha *= 0.5;
+            ++bt;
+        }
+        st->passes_linesearch += x.passes - p0;
+        st->backtracks += bt;
+        if (status != EOT_OK) break;
+        // L14-L15: u <- u + alpha d_u ; v <- v + alpha d_v + log c - log c(P(alpha))
+        HIPCHK(launch_copy(S.ua, S.u, n, x.s));
+        EOTCHK(clear_flags(x));
+        HIPCHK(launch_log_ratio_fix(S.v, S.va, S.lct, S.colsum, m, x.sc.flags, x.s));
+        // L16
+        p0 = x.passes;
+        EOTCHK(refresh(x, prec, beta, S.sh, ss));
+        st->passes_projection += x.passes - p0;
+        st->newton_steps += 1;
+        double gk1 = 0.0;
+        EOTCHK(reduce_host(x, RED_L1_DIFF_EXP, S.rt, S.lr, n, &gk1));
+        const double dk = (gk - gk1) / ((1.0 - eta) * gk);
+        dmin = std::min(dmin, dk);
+        ++k;
+    }
+    HIPCHK(launch_add_logdiff(S.u, S.lrt, S.lr, n, x.s));                 // L18
+    *delta_min = dmin;
+    return status;
+}
+
+// FP64 report at the output potentials against the unsmoothed marginals.
+eot_status report(Ctx& x, double beta, const double* r, const double* c, eot_solve_stats* st)
+{
+    SolveVecs& S = x.sv;
+    EOTCHK(row_max(x, S.u, S.v, beta, S.sh));
+    PassArgs A = make_args(x, S.u, S.sh, S.v, beta);
+    HIPCHK(launch_pass(A, EOT_PREC_FP64, 2, 1, R2_COST, x.s));
+    x.passes += 1;
+    HIPCHK(launch_merge_rows(x.sc.row_part, x.tiles_m, x.n, 2, S.sh, x.tmp_n[0], x.tmp_n[1], 0, x.s));
+    HIPCHK(launch_merge_cols(x.sc.col_part, x.tiles_n, x.m, 1, x.tmp_m[0], nullptr, x.s));
+    HIPCHK(launch_log(x.tmp_n[0], x.tmp_n[2], x.n, x.s));
+    HIPCHK(launch_log(x.tmp_m[0], x.tmp_m[2], x.m, x.s));
+    double er = 0, ec = 0, cost = 0, mass = 0, ur = 0, vc = 0;
+    EOTCHK(reduce_host(x, RED_L1_DIFF_EXP, r, x.tmp_n[2], x.n, &er));
+    EOTCHK(reduce_host(x, RED_L1_DIFF_EXP, c, x.tmp_m[2], x.m, &ec));
+    EOTCHK(reduce_host(x, RED_SUM, x.tmp_n[1], nullptr, x.n, &cost));
+    EOTCHK(reduce_host(x, RED_SUM, x.tmp_n[0], nullptr, x.n, &mass));
+    EOTCHK(reduce_host(x, RED_DOT, S.u, r, x.n, &ur));
+    EOTCHK(reduce_host(x, RED_DOT, S.v, c, x.m, &vc));
+    st->err_r = er;
+    st->err_c = ec;
+    st->cost = cost;
+    st->dual_value = (ur + vc - mass + 1.0) / beta;
+    return EOT_OK;
+}
+
+eot_status check_marginal(Ctx& x, const double* p, int64_t k)
+{
+    double bad = 0.0, sum = 0.0;
+    EOTCHK(reduce_host(x, RED_BAD, p, nullptr, k, &bad));
+    EOTCHK(reduce_host(x, RED_SUM, p, nullptr, k, &sum));
+    if (bad != 0.0 || !(std::fabs(sum - 1.0) <= 1e-9)) return EOT_ERR_BAD_MARGINALS;
+    return EOT_OK;
+}
+
+eot_status solve_impl(Ctx& x, const double* r, const double* c, const eot_solve_opts* o,
+                      double* f_out, double* g_out, eot_solve_stats* st)
+{
+    SolveVecs& S = x.sv;
+    const int64_t n = x.n, m = x.m;
+    const int prec = o->precision;
+    EOTCHK(check_marginal(x, r, n));
+    EOTCHK(check_marginal(x, c, m));
+    double hr = 0.0, hc = 0.0;
+    EOTCHK(reduce_host(x, RED_ENTROPY, r, nullptr, n, &hr));
+    EOTCHK(reduce_host(x, RED_ENTROPY, c, nullptr, m, &hc));
+    const double hmin = std::min(hr, hc);
+    const double beta_f = 1.0 / o->gamma_final;
+    const double beta_i = 1.0 / o->gamma_init;
+    const double w_c = 0.5 - o->w_r;
+    double beta_prev = 0.0;
+    double beta = std::min(beta_i, beta_f);
+    double q = o->q1;
+    double rho0 = 0.0;
+    SolveState ss{o, st};
+    eot_status status = EOT_OK;
+    bool done = false;
+    int32_t t = 1;
+    while (!done) {
+        if (t > o->max_mdot) { status = EOT_ERR_NOT_CONVERGED; break; }
+        done = (beta == beta_f);                                           // L3
+        double eps_d = hmin / std::pow(beta, o->p);                        // L4
+        if (done && eps_d > 0.5 * o->tol) eps_d = 0.5 * o->tol;
+        HIPCHK(launch_smooth(r, o->w_r * eps_d, 1.0 / (double)n, S.rt, S.lrt, n, x.s));   // L5
+        HIPCHK(launch_smooth(c, w_c * eps_d, 1.0 / (double)m, S.ct, S.lct, m, x.s));
+        HIPCHK(launch_recip(S.ct, S.inv_ct, m, x.s));
+        if (t == 1) {                                                      // L6
+            HIPCHK(launch_copy(S.lrt, S.u, n, x.s));
+            HIPCHK(launch_copy(S.lrt, S.u_prev, n, x.s));
+            HIPCHK(launch_copy(S.lct, S.v, m, x.s));
+            HIPCHK(launch_copy(S.lct, S.v_prev, m, x.s));
+        }
+        double dmin = INFINITY;                                            // L7
+        status = tnp(x, prec, beta, 0.5 * eps_d, &rho0, &dmin, ss);
+        if (status == EOT_OK && done && prec == EOT_PREC_MIXED && o->verify_fp64) {
+            double dmin64 = INFINITY;
+            status = tnp(x, EOT_PREC_FP64, beta, 0.5 * eps_d, &rho0, &dmin64, ss);
+        }
+        st->delta_min_last = dmin;
+        st->mdot_steps = t;
+        st->final_gamma = 1.0 / beta;
+        if (status != EOT_OK || done) break;
+        if (o->adaptive_q) {                                               // L8
+            if (dmin > 0.95) q = std::min(2.0, q * q);
+            else if (dmin < 0.8) q = std::sqrt(q);
+        }
+        const double beta_next = std::min(q * beta, beta_f);               // L9
+        const double ratio = (beta_next - beta) / (beta - beta_prev);      // L10
+        HIPCHK(launch_extrapolate(S.u, S.u_prev, ratio, n, x.s));
+        HIPCHK(launch_extrapolate(S.v, S.v_prev, ratio, m, x.s));
+        beta_prev = beta;
+        beta = beta_next;
+        ++t;
+    }
+    if (status == EOT_OK || status == EOT_ERR_NOT_CONVERGED) {
+        eot_status rs = report(x, beta, r, c, st);
+        if (rs != EOT_OK) return rs;
+        HIPCHK(launch_scale(S.u, 1.0 / beta, f_out, n, x.s));
+        HIPCHK(launch_scale(S.v, 1.0 / beta, g_out, m, x.s));
+        HIPCHK(hipStreamSynchronize(x.s));
+    }
+    return status;
+}
+
+bool bad_gamma(double gamma) { return !(gamma > 0.0) || !std::isfinite(gamma); }
+
+}  // namespace
+
+extern "C" {
+
+eot_status eot_workspace_size(int32_t op, const eot_cost* cost, int32_t prec, size_t* bytes)
+{
+    if (!bytes) return EOT_ERR_INVALID_ARG;
+    eot_status cs = check_cost(cost);
+    if (cs != EOT_OK) return cs;
+    if (op < EOT_OP_MARGINALS || op > EOT_OP_SOLVE) return EOT_ERR_INVALID_ARG;
+    (void)prec;
+    Ctx x;
+    x.n = cost->n;
+    x.m = cost->m;
+    x.tiles_m = (int)tiles_m_of(x.m);
+    x.tiles_n = (int)tiles_n_of(x.n);
+    Arena dry;
+    carve(dry, x, op);
+    *bytes = dry.off + kAlign;
+    return EOT_OK;
+}
+
+eot_status eot_marginals(const eot_cost* cost, double gamma, const double* f, const double* g,
+                         const double* row_shift, double* log_rP, double* log_cP, double* mass,
+                         const double* c_for_s, double* s, int32_t prec, void* ws,
+                         size_t ws_bytes, void* stream)
+{
+    if (!f || !g || bad_gamma(gamma)) return EOT_ERR_INVALID_ARG;
+    if (s && !c_for_s) return EOT_ERR_INVALID_ARG;
+    if (!log_rP && !log_cP && !mass && !s) return EOT_ERR_INVALID_ARG;
+    Ctx x;
+    EOTCHK(setup(x, cost, EOT_OP_MARGINALS, prec, ws, ws_bytes, stream));
+    const double beta = 1.0 / gamma;
+    double* u = x.tmp_n[0];
+    double* a = x.tmp_n[1];
+    double* lr = log_rP ? log_rP : x.tmp_n[2];
+    double* v = x.tmp_m[0];
+    HIPCHK(launch_divs(f, gamma, u, x.n, x.s));
+    HIPCHK(launch_divs(g, gamma, v, x.m, x.s));
+    if (row_shift) HIPCHK(launch_copy(row_shift, a, x.n, x.s));
+    else EOTCHK(row_max(x, u, v, beta, a));
+    const bool rows = log_rP || mass || s;
+    const int nr = rows ? (s ? 2 : 1) : 0;
+    const int nc = log_cP ? 1 : 0;
+    if (s) HIPCHK(launch_recip(c_for_s, x.tmp_m[1], x.m, x.s));
+    PassArgs A = make_args(x, u, a, v, beta);
+    A.yw1 = s ? x.tmp_m[1] : nullptr;
+    HIPCHK(launch_pass(A, prec, nr, nc, R2_SQUARE, x.s));
+    if (rows) {
+        HIPCHK(launch_log_row_from_sums(x.sc.row_part, x.tiles_m, x.n, a, lr, x.sc.flags, x.s));
+        if (s) HIPCHK(launch_merge_rows(x.sc.row_part, x.tiles_m, x.n, 2, a, nullptr, s, 1, x.s));
+        if (mass) {
+            int nb = 0;
+            HIPCHK(launch_reduce(RED_SUM_EXP, nullptr, lr, x.n, x.sc.red, &nb, x.s));
+            HIPCHK(launch_finish_sum(x.sc.red, nb, mass, x.s));
+        }
+    }
+    if (log_cP) {
+        HIPCHK(launch_merge_cols(x.sc.col_part, x.tiles_n, x.m, 1, x.tmp_m[2], nullptr, x.s));
+        HIPCHK(launch_log(x.tmp_m[2], log_cP, x.m, x.s));
+    }
+    return EOT_OK;
+}
+
+eot_status eot_hvp(const eot_cost* cost, double gamma, const double* f, const double* g,
+                   const double* row_shift, double rho, const double* xv, const double* yv,
+                   double* Hx, double* Hy, int32_t prec, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!f || !g || !xv || !yv || !Hx || !Hy || bad_gamma(gamma)) return EOT_ERR_INVALID_ARG;
+    if (!(rho >= 0.0 && rho <= 1.0)) return EOT_ERR_INVALID_ARG;
+    Ctx x;
+    EOTCHK(setup(x, cost, EOT_OP_HVP, prec, ws, ws_bytes, stream));
+    const double beta = 1.0 / gamma;
+    double* u = x.tmp_n[0];
+    double* a = x.tmp_n[1];
+    double* v = x.tmp_m[0];
+    HIPCHK(launch_divs(f, gamma, u, x.n, x.s));
+    HIPCHK(launch_divs(g, gamma, v, x.m, x.s));
+    if (row_shift) HIPCHK(launch_copy(row_shift, a, x.n, x.s));
+    else EOTCHK(row_max(x, u, v, beta, a));
+    PassArgs A = make_args(x, u, a, v, beta);
+    A.yw1 = yv;
+    A.xw1 = xv;
+    HIPCHK(launch_pass(A, prec, 2, 2, R2_WEIGHT, x.s));
+    HIPCHK(launch_hvp_finish(x.sc.row_part, x.tiles_m, x.sc.col_part, x.tiles_n, x.n, x.m, a, xv,
+                             yv, std::sqrt(rho), Hx, Hy, x.s));
+    return EOT_OK;
+}
+
+eot_status eot_newton_cg(const eot_cost* cost, double gamma, const double* f, const double* g,
+                         const double* r, const double* c, double eta, double rho0,
+                         int32_t max_cg, int32_t max_levels, double* dir_f, double* dir_g,
+                         eot_newton_stats* stats, int32_t prec, void* ws, size_t ws_bytes,
+                         void* stream)
+{
+    if (!f || !g || !r || !c || !dir_f || !dir_g || bad_gamma(gamma)) return EOT_ERR_INVALID_ARG;
+    if (!(eta > 0.0) || !(rho0 >= 0.0 && rho0 < 1.0) || max_cg < 1 || max_levels < 0)
+        return EOT_ERR_INVALID_ARG;
+    Ctx x;
+    EOTCHK(setup(x, cost, EOT_OP_NEWTON_CG, prec, ws, ws_bytes, stream));
+    const double beta = 1.0 / gamma;
+    double* u = x.tmp_n[0];
+    double* lr = x.tmp_n[1];
+    double* s = x.tmp_n[2];
+    double* a = x.tmp_n[3];
+    double* v = x.tmp_m[0];
+    double* inv_c = x.tmp_m[1];
+    HIPCHK(launch_divs(f, gamma, u, x.n, x.s));
+    HIPCHK(launch_divs(g, gamma, v, x.m, x.s));
+    HIPCHK(launch_recip(c, inv_c, x.m, x.s));
+    EOTCHK(row_max(x, u, v, beta, a));
+    EOTCHK(row_pass(x, prec, u, a, v, beta, inv_c, lr, s));
+    NewtonResult nr;
+    double* du = a;                 // the row maxima are not needed past the row pass
+    double* dv = x.tmp_m[2];
+    EOTCHK(newton_solve(x, prec, u, v, beta, lr, s, r, c, eta, rho0, max_cg, max_levels, du, dv,
+                        &nr));
+    HIPCHK(launch_scale(du, gamma, dir_f, x.n, x.s));
+    HIPCHK(launch_scale(dv, gamma, dir_g, x.m, x.s));
+    HIPCHK(hipStreamSynchronize(x.s));
+    if (stats) {
+        stats->rho_out = nr.rho;
+        stats->cg_iters = nr.cg_iters;
+        stats->levels = nr.levels;
+        stats->forcing_miss = nr.miss;
+        stats->status = EOT_OK;
+        stats->passes = x.passes;
+        stats->forcing_ratio = nr.forcing_ratio;
+    }
+    return EOT_OK;
+}
+
+void eot_solve_opts_default(eot_solve_opts* o)
+{
+    if (!o) return;
+    o->gamma_init = 1.0 / 32.0;
+    o->gamma_final = 1e-3;
+    o->tol = 1e-6;
+    o->p = 1.5;
+    o->q1 = 2.0;
+    o->w_r = 0.45;
+    o->adaptive_q = 1;
+    o->adaptive_rho0 = 1;
+    o->max_cg = 1000;
+    o->max_levels = 30;
+    o->max_backtrack = 60;
+    o->max_newton = 200;
+    o->max_sinkhorn = 10000;
+    o->max_mdot = 500;
+    o->precision = EOT_PREC_FP64;
+    o->verify_fp64 = 1;
+}
+
+eot_status eot_solve(const eot_cost* cost, const double* r, const double* c,
+                     const eot_solve_opts* opts, double* f, double* g, eot_solve_stats* stats,
+                     void* ws, size_t ws_bytes, void* stream)
+{
+    if (!r || !c || !opts || !f || !g) return EOT_ERR_INVALID_ARG;
+    const eot_solve_opts& o = *opts;
+    if (bad_gamma(o.gamma_init) || bad_gamma(o.gamma_final) || !(o.tol > 0.0) ||
+        !(o.p >= 1.0) || !(o.q1 > 1.0) || !(o.w_r > 0.0 && o.w_r < 0.5) || o.max_cg < 1 ||
+        o.max_levels < 0 || o.max_backtrack < 0 || o.max_newton < 0 || o.max_sinkhorn < 0 ||
+        o.max_mdot < 1)
+        return EOT_ERR_INVALID_ARG;
+    const auto t0 = std::chrono::steady_clock::now();
+    Ctx x;
+    EOTCHK(setup(x, cost, EOT_OP_SOLVE, o.precision, ws, ws_bytes, stream));
+    eot_solve_stats st{};
+    eot_status status = solve_impl(x, r, c, &o, f, g, &st);
+    st.passes_other = x.passes - st.passes_newton - st.passes_linesearch - st.passes_sinkhorn -
+                      st.passes_projection;
+    st.status = status;
+    st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = st;
+    return status;
+}
+
+const char* eot_status_string(int32_t status)
+{
+    switch (status) {
+        case EOT_OK: return "ok";
+        case EOT_ERR_INVALID_ARG: return "invalid argument";
+        case EOT_ERR_BAD_MARGINALS: return "marginals must be positive, finite and sum to 1";
+        case EOT_ERR_NONFINITE: return "non-finite values that the range fallback could not repair";
+        case EOT_ERR_NOT_CONVERGED: return "iteration cap reached; outputs hold the last iterate";
+        case EOT_ERR_WORKSPACE: return "workspace missing, too small or not 256-byte aligned";
+        case EOT_ERR_UNSUPPORTED: return "unsupported cost kind / precision combination";
+        case EOT_ERR_HIP: return "HIP runtime error";
+        default: return "unknown status";
+    }
+}
+
+const char* eot_version(void) { return "0.1.0 gfx950"; }
+
+}  // extern "C"

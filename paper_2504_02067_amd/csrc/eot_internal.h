@@ -1,0 +1,131 @@
+// Internal interface between the ABI/driver (eot_api.hip) and the device
+// kernels (eot_kernels.hip). Not installed; not part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "eot.h"
+
+namespace eot {
+
+// Tile geometry of the streaming pass (see eot_kernels.hip).
+constexpr int kPassThreads = 256;        // 4 wave64 per workgroup
+constexpr int kVec = 4;                  // consecutive columns per thread per row
+constexpr int kChunks = 2;               // column chunks of 1024 per tile
+constexpr int kTileCols = kPassThreads * kVec * kChunks;   // 2048
+constexpr int kTileRows = 128;           // rows per tile (column partials per band)
+constexpr int kSubRows = 8;              // rows in flight per thread
+constexpr int kVecThreads = 256;         // O(n) vector kernels
+constexpr int kMaxRedBlocks = 1024;      // partial sums per reduction
+
+// Weighting of the second row accumulator.
+enum RowMode2 : int { R2_WEIGHT = 0, R2_SQUARE = 1, R2_COST = 2 };
+
+struct PassArgs {
+    int32_t kind;          // eot_cost_kind
+    const void* C;
+    int64_t n, m, ldc;
+    int32_t vec_ok;        // 16-byte aligned rows: vector loads allowed
+    const double* u;       // log-unit row potentials
+    const double* a;       // row shifts (~log r(P))
+    const double* v;       // log-unit column potentials
+    double beta;           // inverse temperature
+    const double* xw0;     // per-row weights of column sum 0 (nullable = 1)
+    const double* xw1;     // per-row weights of column sum 1 (nullable = 1)
+    const double* yw0;     // per-column weights of row sum 0 (nullable = 1)
+    const double* yw1;     // per-column weights of row sum 1 (nullable = 1)
+    double* row_part;      // [nr][tiles_m][n]
+    double* col_part;      // [nc][tiles_n][m]
+    int32_t tiles_m, tiles_n;
+};
+
+inline int64_t tiles_m_of(int64_t m) { return (m + kTileCols - 1) / kTileCols; }
+inline int64_t tiles_n_of(int64_t n) { return (n + kTileRows - 1) / kTileRows; }
+
+// One streaming pass: nr row sums (0..2), nc column sums (0..2).
+hipError_t launch_pass(const PassArgs& a, int prec, int nr, int nc, int mode2, hipStream_t s);
+// Exact row maxima of u_i + v_j - beta C_ij (robust shift): out[n].
+hipError_t launch_rowmax(const PassArgs& a, double* part, double* out, hipStream_t s);
+
+// ---- merges / epilogues (all FP64) ----------------------------------------
+// out_k[i] = exp(a_i) * sum_t part[k][t][i]   (nr row sums)
+// out1 carries exp(2 a_i) instead when sq1 (sums of squared plan entries)
+hipError_t launch_merge_rows(const double* part, int tiles, int64_t n, int nr,
+                             const double* a, double* out0, double* out1, int sq1, hipStream_t s);
+// out_k[j] = sum_t part[k][t][j]
+hipError_t launch_merge_cols(const double* part, int tiles, int64_t m, int nc,
+                             double* out0, double* out1, hipStream_t s);
+
+// ---- vector kernels ---------------------------------------------------------
+hipError_t launch_scale(const double* x, double alpha, double* y, int64_t k, hipStream_t s);
+hipError_t launch_divs(const double* x, double d, double* y, int64_t k, hipStream_t s);
+// v = va + log_ct - log colsum (columns whose sum is 0 / not finite keep va, flags[1] = 1)
+hipError_t launch_log_ratio_fix(double* v, const double* va, const double* log_ct,
+                                const double* colsum, int64_t m, int32_t* flags, hipStream_t s);
+hipError_t launch_hvp_finish(const double* row_part, int tiles_m, const double* col_part,
+                             int tiles_n, int64_t n, int64_t m, const double* a, const double* x,
+                             const double* y, double srho, double* Hx, double* Hy, hipStream_t s);
+hipError_t launch_log_row_from_sums(const double* part, int tiles, int64_t n, const double* a,
+                                    double* log_rP, int32_t* flags, hipStream_t s);
+// Block partial sums of an elementwise expression: writes nb partials to red.
+enum VecRed : int {
+    RED_L1_DIFF_EXP = 0,   // |x_i - exp(y_i)|
+    RED_CHI2 = 1,          // (x_i - exp(y_i))^2 / exp(y_i)
+    RED_DOT = 2,           // x_i * y_i
+    RED_SUM_EXP = 3,       // exp(y_i)
+    RED_SUM = 4,           // x_i
+    RED_ENTROPY = 5,       // -x_i log x_i
+    RED_L1 = 6,            // |x_i|
+    RED_BAD = 7            // 1 if x_i is not finite and positive
+};
+hipError_t launch_reduce(int op, const double* x, const double* y, int64_t k, double* red,
+                         int* nb_out, hipStream_t s);
+// Host-visible scalar: sum of nb partials written to dst[0] (device).
+hipError_t launch_finish_sum(const double* red, int nb, double* dst, hipStream_t s);
+
+// Elementwise updates used by the drivers.
+hipError_t launch_axpy(double alpha, const double* x, double* y, int64_t k, hipStream_t s);
+hipError_t launch_fix_cols(double* v, const double* log_ct, const double* colsum, int64_t m,
+                           int32_t* flags, hipStream_t s);            // v += log ct - log colsum
+hipError_t launch_add_logdiff(double* x, const double* la, const double* lb, int64_t k,
+                              hipStream_t s);                        // x += la - lb
+hipError_t launch_log(const double* x, double* y, int64_t k, hipStream_t s);
+hipError_t launch_exp(const double* x, double* y, int64_t k, hipStream_t s);
+hipError_t launch_recip(const double* x, double* y, int64_t k, hipStream_t s);
+hipError_t launch_smooth(const double* x, double w, double k_inv, double* out, double* log_out,
+                         int64_t k, hipStream_t s);
+hipError_t launch_extrapolate(double* z, double* z_prev, double ratio, int64_t k, hipStream_t s);
+hipError_t launch_shifted(const double* base, double alpha, const double* d, double* out,
+                          int64_t k, hipStream_t s);                 // out = base + alpha d
+hipError_t launch_newton_init(const double* log_rP, const double* r, double* rP, double* grad,
+                              double* b, double* d, int64_t n, hipStream_t s);
+hipError_t launch_forcing_resid(const double* rP, const double* d, const double* pcptd,
+                                const double* grad, double* e, int64_t n, hipStream_t s);
+hipError_t launch_div(const double* x, const double* y, double* out, double sign, int64_t k,
+                      hipStream_t s);                                // out = sign * x / y
+hipError_t launch_copy(const double* x, double* y, int64_t k, hipStream_t s);
+hipError_t launch_fill(double* x, double val, int64_t k, hipStream_t s);
+
+// CG building blocks (state lives in device scalars `sc`).
+struct CgScalars {
+    double rz, pq, alpha, beta, res_l1, rz_new;
+};
+hipError_t launch_cg_init(const double* b, const double* rP, const double* s, double rho,
+                          double* d, double* res, double* z, double* p, double* M, double* ptd,
+                          double* pcptd, int64_t n, int64_t m, double* red, CgScalars* sc,
+                          hipStream_t st);
+// after pass A (column sums of P p): w = raw column sums, wc = w / c
+hipError_t launch_cg_colstep(const double* part, int tiles, int64_t m, const double* c,
+                             double* w, double* wc, hipStream_t st);
+// after pass B (row sums of P wc): t = row sums, q = rP p - rho t; partial <p, q>
+hipError_t launch_cg_rowstep(const double* part, int tiles, int64_t n, const double* a,
+                             const double* rP, const double* p, double rho, double* t,
+                             double* q, double* red, int* nb, hipStream_t st);
+hipError_t launch_cg_update(const double* red_pq, int nb_pq, double* d, double* res, double* z,
+                            const double* p, const double* q, const double* M, const double* t,
+                            double* pcptd, const double* w, double* ptd, int64_t n, int64_t m,
+                            double* red, int* nb, CgScalars* sc, hipStream_t st);
+hipError_t launch_cg_direction(const double* red, int nb, const double* z, double* p,
+                               int64_t n, CgScalars* sc, hipStream_t st);
+
+}  // namespace eot

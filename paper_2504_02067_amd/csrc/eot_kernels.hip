@@ -1,0 +1,995 @@
+// Device kernels of the truncated-Newton entropic-OT library for gfx950.
+//
+// The hot path is the streaming pass over the implicit plan
+//     P_ij = exp(u_i + v_j - beta C_ij)            (eq. lagrangian-closed-form)
+// that serves every O(nm) primitive of the method: the LSE_r / LSE_c
+// marginals (Sec. 2 Notation; Alg. 3 L3-L4, Alg. 4 L1, L2, L9, L16), the two
+// halves of the reduced Newton operator F_r(rho) p = r(P) p - rho P (P^T p / c)
+// (eq. matrix-definitions) inside CG, the discounted Hessian-vector product
+// (eq. discounted-hessian) and the preconditioner diagonal sum_j P_ij^2 / c_j
+// (lemma "condo").
+//
+// Design (gfx950):
+//  * A workgroup of 256 threads (4 wave64) owns a tile of kTileRows x
+//    kTileCols entries. Each thread owns 4 consecutive columns in each of 2
+//    column chunks, so every row of the tile is read as 16-byte, fully
+//    coalesced loads; kSubRows rows are loaded before any is used, keeping
+//    8 x 16 bytes per thread in flight.
+//  * One read of C feeds both directions: column sums accumulate in
+//    registers across the whole row band (written once per band), row sums
+//    accumulate per thread over its 8 columns and are reduced across the
+//    workgroup through LDS every kSubRows rows (a transposed reduction: 16-32
+//    threads per row, then a shuffle inside the wave).
+//  * No atomics: per-tile partial sums are merged in a fixed order by small
+//    epilogue kernels, so results are bit-reproducible.
+//  * Mixed precision: the exponent is assembled in FP32 without losing the
+//    FP64 potentials. In base 2, U_i = log2(e)(u_i - a_i) and V_j = log2(e) v_j
+//    are split per tile into a hi part on a grid 2^-g (g chosen from the
+//    tile's largest |U|, |V|) and an FP32 lo part, and log2(e) beta into
+//    Bh + Bl, so that Uh + Vh is exact in FP32 and
+//        x = fma(-Bh, C, Uh + Vh) + fma(-Bl, C, Vl)
+//    carries one rounding of a number close to log2(P_ij / r(P)_i). 2^Ul and
+//    exp(a_i) become an FP64 per-row factor. exp2 is v_exp_f32; every sum is
+//    accumulated in FP64.
+//  * FP64 mode evaluates x = fma(-beta, C, (u_i - a_i) + v_j) and exp in FP64.
+// The row shift a_i (about log r(P)_i) only keeps exponentials in range.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "eot_internal.h"
+
+namespace eot {
+
+namespace {
+
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr int kWaves = kPassThreads / 64;
+
+__device__ __forceinline__ double wave_max(double x)
+{
+    for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
+    return x;
+}
+
+__device__ __forceinline__ double wave_sum(double x)
+{
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+template <typename TC>
+__device__ __forceinline__ void load_row_vec(const TC* __restrict__ row, int64_t jb, int64_t m,
+                                             bool vec_ok, float (&out)[kVec]);
+
+template <>
+__device__ __forceinline__ void load_row_vec<float>(const float* __restrict__ row, int64_t jb,
+                                                    int64_t m, bool vec_ok, float (&out)[kVec])
+{
+    if (vec_ok && jb + kVec <= m) {
+        const float4 x = *reinterpret_cast<const float4*>(row + jb);
+        out[0] = x.x; out[1] = x.y; out[2] = x.z; out[3] = x.w;
+    } else {
+#pragma unroll
+        for (int q = 0; q < kVec; ++q) out[q] = (jb + q < m) ? row[jb + q] : 0.0f;
+    }
+}
+
+template <typename TC>
+__device__ __forceinline__ void load_row_vec_d(const TC* __restrict__ row, int64_t jb, int64_t m,
+                                               bool vec_ok, double (&out)[kVec]);
+
+template <>
+__device__ __forceinline__ void load_row_vec_d<float>(const float* __restrict__ row, int64_t jb,
+                                                      int64_t m, bool vec_ok, double (&out)[kVec])
+{
+    if (vec_ok && jb + kVec <= m) {
+        const float4 x = *reinterpret_cast<const float4*>(row + jb);
+        out[0] = x.x; out[1] = x.y; out[2] = x.z; out[3] = x.w;
+    } else {
+#pragma unroll
+        for (int q = 0; q < kVec; ++q) out[q] = (jb + q < m) ? (double)row[jb + q] : 0.0;
+    }
+}
+
+template <>
+__device__ __forceinline__ void load_row_vec_d<double>(const double* __restrict__ row, int64_t jb,
+                                                       int64_t m, bool vec_ok, double (&out)[kVec])
+{
+    if (vec_ok && jb + kVec <= m) {
+        const double2 x0 = *reinterpret_cast<const double2*>(row + jb);
+        const double2 x1 = *reinterpret_cast<const double2*>(row + jb + 2);
+        out[0] = x0.x; out[1] = x0.y; out[2] = x1.x; out[3] = x1.y;
+    } else {
+#pragma unroll
+        for (int q = 0; q < kVec; ++q) out[q] = (jb + q < m) ? row[jb + q] : 0.0;
+    }
+}
+
+// Transposed LDS reduction of NR x kSubRows per-thread row partials; writes
+// one partial per row of the sub-band to row_part.
+template <int NR, int MODE2>
+__device__ __forceinline__ void reduce_rows(double (&racc)[NR > 0 ? NR : 1][kSubRows],
+                                            double* s_red, const double* s_rf, int sb,
+                                            int64_t i0, int64_t n, const PassArgs& A)
+{
+    constexpr int G = NR * kSubRows;
+    constexpr int TPG = kPassThreads / G;          // threads per row group (16 or 32)
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+#pragma unroll
+        for (int rr = 0; rr < kSubRows; ++rr) s_red[(k * kSubRows + rr) * kPassThreads + tid] = racc[k][rr];
+    __syncthreads();
+    const int grp = tid / TPG, sub = tid % TPG;
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < kPassThreads / TPG; ++t) acc += s_red[grp * kPassThreads + sub + t * TPG];
+    for (int off = TPG / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, TPG);
+    if (sub == 0) {
+        const int k = grp / kSubRows, rr = grp % kSubRows;
+        const int64_t i = i0 + sb + rr;
+        if (i < n) {
+            double fac = s_rf[sb + rr];
+            if (k == 1 && MODE2 == R2_SQUARE) fac *= fac;
+            A.row_part[((int64_t)k * A.tiles_m + blockIdx.x) * n + i] = acc * fac;
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- mixed pass
+template <int NR, int NC, int MODE2>
+__global__ __launch_bounds__(kPassThreads) void k_pass_mixed(PassArgs A)
+{
+    constexpr int RB = kTileRows, RS = kSubRows, NCH = kChunks, V = kVec, T = kPassThreads;
+    __shared__ float s_uh[RB];
+    __shared__ double s_rf[RB];
+    __shared__ double s_xw[2][RB];
+    __shared__ double s_red[NR > 0 ? NR * RS * T : 1];
+    __shared__ double s_wmax[kWaves];
+
+    const int tid = threadIdx.x;
+    const int64_t n = A.n, m = A.m;
+    const int64_t i0 = (int64_t)blockIdx.y * RB;
+    const int64_t j0 = (int64_t)blockIdx.x * kTileCols;
+    const float* __restrict__ C = static_cast<const float*>(A.C);
+    const bool vec_ok = A.vec_ok != 0;
+
+    // Tile-local bound on |U|, |V| to pick the hi/lo grid.
+    double Vd[NCH][V];
+    double mx = 0.0;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+            const int64_t j = j0 + (int64_t)ch * T * V + tid * V + q;
+            Vd[ch][q] = (j < m) ? kLog2e * A.v[j] : 0.0;
+            mx = fmax(mx, fabs(Vd[ch][q]));
+        }
+    const int64_t irow = i0 + tid;
+    const bool rvalid = tid < RB && irow < n;
+    double Ud = 0.0, arow = 0.0;
+    if (rvalid) {
+        arow = A.a[irow];
+        Ud = kLog2e * (A.u[irow] - arow);
+        mx = fmax(mx, fabs(Ud));
+    }
+    mx = wave_max(mx);
+    if ((tid & 63) == 0) s_wmax[tid >> 6] = mx;
+    __syncthreads();
+    mx = s_wmax[0];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) mx = fmax(mx, s_wmax[w]);
+    if (!(mx < 4.0e6)) mx = 4.0e6;          // non-finite input: results flagged later
+    int e2;
+    frexp(2.0 * mx + 2.0, &e2);              // 2 mx + 2 < 2^e2
+    const int g = 23 - e2;                   // |Uh + Vh| < 2^(23-g) on a 2^-g grid: exact
+    const double sc = ldexp(1.0, g), isc = ldexp(1.0, -g);
+
+    float vh[NCH][V], vl[NCH][V];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+            const int64_t j = j0 + (int64_t)ch * T * V + tid * V + q;
+            const double h = rint(Vd[ch][q] * sc) * isc;
+            vh[ch][q] = (j < m) ? (float)h : -INFINITY;
+            vl[ch][q] = (j < m) ? (float)(Vd[ch][q] - h) : 0.0f;
+        }
+    if (tid < RB) {
+        if (rvalid) {
+            const double h = rint(Ud * sc) * isc;
+            const double lo = Ud - h;
+            const double rf = exp2(lo);
+            const double R = exp(arow) * rf;
+            s_uh[tid] = (float)h;
+            s_rf[tid] = rf;
+            s_xw[0][tid] = R * (A.xw0 ? A.xw0[irow] : 1.0);
+            s_xw[1][tid] = R * (A.xw1 ? A.xw1[irow] : 1.0);
+        } else {
+            s_uh[tid] = -INFINITY;
+            s_rf[tid] = 0.0;
+            s_xw[0][tid] = 0.0;
+            s_xw[1][tid] = 0.0;
+        }
+    }
+    const double Bd = kLog2e * A.beta;
+    const float Bh = (float)Bd;
+    const float Bl = (float)(Bd - (double)Bh);
+
+    double ywr[NR > 0 ? NR : 1][NCH][V];
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                const int64_t j = j0 + (int64_t)ch * T * V + tid * V + q;
+                const double* yw = k == 0 ? A.yw0 : A.yw1;
+                ywr[k][ch][q] = (j < m) ? (yw ? yw[j] : 1.0) : 0.0;
+            }
+    double cacc[NC > 0 ? NC : 1][NCH][V];
+#pragma unroll
+    for (int k = 0; k < (NC > 0 ? NC : 1); ++k)
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+            for (int q = 0; q < V; ++q) cacc[k][ch][q] = 0.0;
+    __syncthreads();
+
+    for (int sb = 0; sb < RB; sb += RS) {
+        if (i0 + sb >= n) break;
+        double racc[NR > 0 ? NR : 1][RS];
+#pragma unroll
+        for (int k = 0; k < (NR > 0 ? NR : 1); ++k)
+#pragma unroll
+            for (int rr = 0; rr < RS; ++rr) racc[k][rr] = 0.0;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            const int64_t jb = j0 + (int64_t)ch * T * V + tid * V;
+            float cv[RS][V];
+#pragma unroll
+            for (int rr = 0; rr < RS; ++rr) {
+                int64_t i = i0 + sb + rr;
+                i = i < n ? i : n - 1;
+                load_row_vec<float>(C + i * A.ldc, jb, m, vec_ok, cv[rr]);
+            }
+#pragma unroll
+            for (int rr = 0; rr < RS; ++rr) {
+                const float uh = s_uh[sb + rr];
+                const double xw0 = s_xw[0][sb + rr];
+                const double xw1 = s_xw[1][sb + rr];
+#pragma unroll
+                for (int q = 0; q < V; ++q) {
+                    const float c = cv[rr][q];
+                    const float t = fmaf(-Bh, c, uh + vh[ch][q]);
+                    const float w = fmaf(-Bl, c, vl[ch][q]);
+                    const float e = __builtin_amdgcn_exp2f(t + w);
+                    const double e64 = (double)e;
+                    if constexpr (NR >= 1) racc[0][rr] = fma(e64, ywr[0][ch][q], racc[0][rr]);
+                    if constexpr (NR >= 2) {
+                        double term = e64;
+                        if constexpr (MODE2 == R2_SQUARE) term = e64 * e64;
+                        if constexpr (MODE2 == R2_COST) term = e64 * (double)c;
+                        racc[NR - 1][rr] = fma(term, ywr[NR - 1][ch][q], racc[NR - 1][rr]);
+                    }
+                    if constexpr (NC >= 1) cacc[0][ch][q] = fma(e64, xw0, cacc[0][ch][q]);
+                    if constexpr (NC >= 2) cacc[NC - 1][ch][q] = fma(e64, xw1, cacc[NC - 1][ch][q]);
+                }
+            }
+        }
+        if constexpr (NR > 0) reduce_rows<NR, MODE2>(racc, s_red, s_rf, sb, i0, n, A);
+    }
+    if constexpr (NC > 0) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+                for (int q = 0; q < V; ++q) {
+                    const int64_t j = j0 + (int64_t)ch * T * V + tid * V + q;
+                    if (j < m) A.col_part[((int64_t)k * A.tiles_n + blockIdx.y) * m + j] = cacc[k][ch][q];
+                }
+    }
+}
+
+// ---------------------------------------------------------------- FP64 pass
+template <typename TC, int NR, int NC, int MODE2>
+__global__ __launch_bounds__(kPassThreads) void k_pass_f64(PassArgs A)
+{
+    constexpr int RB = kTileRows, RS = kSubRows, NCH = kChunks, V = kVec, T = kPassThreads;
+    __shared__ double s_A[RB];
+    __shared__ double s_rf[RB];
+    __shared__ double s_xw[2][RB];
+    __shared__ double s_red[NR > 0 ? NR * RS * T : 1];
+
+    const int tid = threadIdx.x;
+    const int64_t n = A.n, m = A.m;
+    const int64_t i0 = (int64_t)blockIdx.y * RB;
+    const int64_t j0 = (int64_t)blockIdx.x * kTileCols;
+    const TC* __restrict__ C = static_cast<const TC*>(A.C);
+    const bool vec_ok = A.vec_ok != 0;
+    const double beta = A.beta;
+
+    if (tid < RB) {
+        const int64_t i = i0 + tid;
+        if (i < n) {
+            const double a = A.a[i];
+            const double R = exp(a);
+            s_A[tid] = A.u[i] - a;
+            s_rf[tid] = 1.0;
+            s_xw[0][tid] = R * (A.xw0 ? A.xw0[i] : 1.0);
+            s_xw[1][tid] = R * (A.xw1 ? A.xw1[i] : 1.0);
+        } else {
+            s_A[tid] = -INFINITY;
+            s_rf[tid] = 0.0;
+            s_xw[0][tid] = 0.0;
+            s_xw[1][tid] = 0.0;
+        }
+    }
+    double vc[NCH][V];
+    double ywr[NR > 0 ? NR : 1][NCH][V];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+            const int64_t j = j0 + (int64_t)ch * T * V + tid * V + q;
+            vc[ch][q] = (j < m) ? A.v[j] : -INFINITY;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                const double* yw = k == 0 ? A.yw0 : A.yw1;
+                ywr[k][ch][q] = (j < m) ? (yw ? yw[j] : 1.0) : 0.0;
+            }
+        }
+    double cacc[NC > 0 ? NC : 1][NCH][V];
+#pragma unroll
+    for (int k = 0; k < (NC > 0 ? NC : 1); ++k)
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+            for (int q = 0; q < V; ++q) cacc[k][ch][q] = 0.0;
+    __syncthreads();
+
+    for (int sb = 0; sb < RB; sb += RS) {
+        if (i0 + sb >= n) break;
+        double racc[NR > 0 ? NR : 1][RS];
+#pragma unroll
+        for (int k = 0; k < (NR > 0 ? NR : 1); ++k)
+#pragma unroll
+            for (int rr = 0; rr < RS; ++rr) racc[k][rr] = 0.0;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            const int64_t jb = j0 + (int64_t)ch * T * V + tid * V;
+            double cv[RS][V];
+#pragma unroll
+            for (int rr = 0; rr < RS; ++rr) {
+                int64_t i = i0 + sb + rr;
+                i = i < n ? i : n - 1;
+                load_row_vec_d<TC>(C + i * A.ldc, jb, m, vec_ok, cv[rr]);
+            }
+#pragma unroll
+            for (int rr = 0; rr < RS; ++rr) {
+                const double ar = s_A[sb + rr];
+                const double xw0 = s_xw[0][sb + rr];
+                const double xw1 = s_xw[1][sb + rr];
+#pragma unroll
+                for (int q = 0; q < V; ++q) {
+                    const double c = cv[rr][q];
+                    const double e = exp(fma(-beta, c, ar + vc[ch][q]));
+                    if constexpr (NR >= 1) racc[0][rr] = fma(e, ywr[0][ch][q], racc[0][rr]);
+                    if constexpr (NR >= 2) {
+                        double term = e;
+                        if constexpr (MODE2 == R2_SQUARE) term = e * e;
+                        if constexpr (MODE2 == R2_COST) term = e * c;
+                        racc[NR - 1][rr] = fma(term, ywr[NR - 1][ch][q], racc[NR - 1][rr]);
+                    }
+                    if constexpr (NC >= 1) cacc[0][ch][q] = fma(e, xw0, cacc[0][ch][q]);
+                    if constexpr (NC >= 2) cacc[NC - 1][ch][q] = fma(e, xw1, cacc[NC - 1][ch][q]);
+                }
+            }
+        }
+        if constexpr (NR > 0) reduce_rows<NR, MODE2>(racc, s_red, s_rf, sb, i0, n, A);
+    }
+    if constexpr (NC > 0) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+                for (int q = 0; q < V; ++q) {
+                    const int64_t j = j0 + (int64_t)ch * T * V + tid * V + q;
+                    if (j < m) A.col_part[((int64_t)k * A.tiles_n + blockIdx.y) * m + j] = cacc[k][ch][q];
+                }
+    }
+}
+
+// Exact row maxima of u_i + v_j - beta C_ij, FP64; one partial per column tile.
+template <typename TC>
+__global__ __launch_bounds__(kPassThreads) void k_rowmax(PassArgs A, double* part)
+{
+    constexpr int NCH = kChunks, V = kVec, T = kPassThreads;
+    __shared__ double s_w[kWaves];
+    const int tid = threadIdx.x;
+    const int64_t n = A.n, m = A.m;
+    const int64_t i0 = (int64_t)blockIdx.y * kTileRows;
+    const int64_t j0 = (int64_t)blockIdx.x * kTileCols;
+    const TC* __restrict__ C = static_cast<const TC*>(A.C);
+    for (int rr = 0; rr < kTileRows; ++rr) {
+        const int64_t i = i0 + rr;
+        if (i >= n) break;
+        double mx = -INFINITY;
+        const double ui = A.u[i];
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            const int64_t jb = j0 + (int64_t)ch * T * V + tid * V;
+            double cv[V];
+            load_row_vec_d<TC>(C + i * A.ldc, jb, m, A.vec_ok != 0, cv);
+#pragma unroll
+            for (int q = 0; q < V; ++q)
+                if (jb + q < m) mx = fmax(mx, fma(-A.beta, cv[q], ui + A.v[jb + q]));
+        }
+        mx = wave_max(mx);
+        if ((tid & 63) == 0) s_w[tid >> 6] = mx;
+        __syncthreads();
+        if (tid == 0) {
+            double r = s_w[0];
+            for (int w = 1; w < kWaves; ++w) r = fmax(r, s_w[w]);
+            part[(int64_t)blockIdx.x * n + i] = r;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_merge_max(const double* part, int tiles, int64_t n, double* out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double r = part[i];
+    for (int t = 1; t < tiles; ++t) r = fmax(r, part[(int64_t)t * n + i]);
+    out[i] = r;
+}
+
+// ---------------------------------------------------------------- merges
+__global__ void k_merge_rows(const double* part, int tiles, int64_t n, int nr, const double* a,
+                             double* out0, double* out1, int sq1)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double ea = a ? exp(a[i]) : 1.0;
+    const double ea1 = sq1 ? ea * ea : ea;
+    double s0 = 0.0;
+    for (int t = 0; t < tiles; ++t) s0 += part[(int64_t)t * n + i];
+    if (out0) out0[i] = ea * s0;
+    if (nr > 1 && out1) {
+        double s1 = 0.0;
+        for (int t = 0; t < tiles; ++t) s1 += part[((int64_t)tiles + t) * n + i];
+        out1[i] = ea1 * s1;
+    }
+}
+
+__global__ void k_merge_cols(const double* part, int tiles, int64_t m, int nc, double* out0,
+                             double* out1)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    double s0 = 0.0;
+    for (int t = 0; t < tiles; ++t) s0 += part[(int64_t)t * m + j];
+    if (out0) out0[j] = s0;
+    if (nc > 1 && out1) {
+        double s1 = 0.0;
+        for (int t = 0; t < tiles; ++t) s1 += part[((int64_t)tiles + t) * m + j];
+        out1[j] = s1;
+    }
+}
+
+// log r(P)_i = a_i + log sum_t part[t][i]; flags[0] set when the shifted sum
+// left the range where FP32 terms are exact (mixed) or is not finite.
+__global__ void k_log_row(const double* part, int tiles, int64_t n, const double* a,
+                          double* log_rP, int32_t* flags)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int t = 0; t < tiles; ++t) s += part[(int64_t)t * n + i];
+    if (!(s > 5.421010862427522e-20 && s < 1.8446744073709552e19)) flags[0] = 1;   // 2^-64, 2^64
+    log_rP[i] = a[i] + log(s);
+}
+
+// ---------------------------------------------------------------- reductions
+template <int OP>
+__device__ __forceinline__ double red_term(const double* x, const double* y, int64_t i)
+{
+    if (OP == RED_L1_DIFF_EXP) return fabs(x[i] - exp(y[i]));
+    if (OP == RED_CHI2) { const double e = exp(y[i]); const double d = x[i] - e; return d * d / e; }
+    if (OP == RED_DOT) return x[i] * y[i];
+    if (OP == RED_SUM_EXP) return exp(y[i]);
+    if (OP == RED_SUM) return x[i];
+    if (OP == RED_ENTROPY) return x[i] > 0.0 ? -x[i] * log(x[i]) : 0.0;
+    if (OP == RED_BAD) return (x[i] > 0.0 && x[i] < INFINITY) ? 0.0 : 1.0;
+    return fabs(x[i]);
+}
+
+__device__ __forceinline__ double block_sum(double v, double* s_w)
+{
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) s_w[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    for (int k = 0; k < nw; ++k) r += s_w[k];
+    __syncthreads();
+    return r;
+}
+
+template <int OP>
+__global__ void k_reduce(const double* x, const double* y, int64_t k, double* red)
+{
+    __shared__ double s_w[kVecThreads / 64];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
+         i += (int64_t)gridDim.x * blockDim.x)
+        acc += red_term<OP>(x, y, i);
+    acc = block_sum(acc, s_w);
+    if (threadIdx.x == 0) red[blockIdx.x] = acc;
+}
+
+__device__ __forceinline__ double sum_partials(const double* red, int nb, double* s_w)
+{
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += red[b];
+    return block_sum(acc, s_w);
+}
+
+__global__ void k_finish_sum(const double* red, int nb, double* dst)
+{
+    __shared__ double s_w[kVecThreads / 64];
+    const double s = sum_partials(red, nb, s_w);
+    if (threadIdx.x == 0) dst[0] = s;
+}
+
+// ---------------------------------------------------------------- elementwise
+#define EW_LOOP(k) for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (k); \
+                        i += (int64_t)gridDim.x * blockDim.x)
+
+__global__ void k_scale(const double* x, double alpha, double* y, int64_t k) { EW_LOOP(k) y[i] = alpha * x[i]; }
+__global__ void k_divs(const double* x, double d, double* y, int64_t k) { EW_LOOP(k) y[i] = x[i] / d; }
+__global__ void k_log_ratio_fix(double* v, const double* va, const double* log_ct, const double* colsum,
+                                int64_t m, int32_t* flags)
+{
+    EW_LOOP(m) {
+        const double s = colsum[i];
+        if (s > 0.0 && s < INFINITY) v[i] = va[i] + log_ct[i] - log(s);
+        else { v[i] = va[i]; flags[1] = 1; }
+    }
+}
+// Hx = r(P) x + sqrt(rho) P y, from the (2, 2) pass: row sums 0 = sum e, 1 = sum e y.
+__global__ void k_hvp_rows(const double* part, int tiles, int64_t n, const double* a,
+                           const double* x, double srho, double* Hx)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s0 = 0.0, s1 = 0.0;
+    for (int t = 0; t < tiles; ++t) {
+        s0 += part[(int64_t)t * n + i];
+        s1 += part[((int64_t)tiles + t) * n + i];
+    }
+    const double ea = exp(a[i]);
+    Hx[i] = (ea * s0) * x[i] + srho * (ea * s1);
+}
+// Hy = sqrt(rho) P^T x + c(P) y, column sums 0 = sum P, 1 = sum P x.
+__global__ void k_hvp_cols(const double* part, int tiles, int64_t m, const double* y, double srho,
+                           double* Hy)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    double s0 = 0.0, s1 = 0.0;
+    for (int t = 0; t < tiles; ++t) {
+        s0 += part[(int64_t)t * m + j];
+        s1 += part[((int64_t)tiles + t) * m + j];
+    }
+    Hy[j] = srho * s1 + s0 * y[j];
+}
+__global__ void k_axpy(double alpha, const double* x, double* y, int64_t k) { EW_LOOP(k) y[i] += alpha * x[i]; }
+__global__ void k_log(const double* x, double* y, int64_t k) { EW_LOOP(k) y[i] = log(x[i]); }
+__global__ void k_exp(const double* x, double* y, int64_t k) { EW_LOOP(k) y[i] = exp(x[i]); }
+__global__ void k_recip(const double* x, double* y, int64_t k) { EW_LOOP(k) y[i] = 1.0 / x[i]; }
+__global__ void k_copy(const double* x, double* y, int64_t k) { EW_LOOP(k) y[i] = x[i]; }
+__global__ void k_fill(double* x, double val, int64_t k) { EW_LOOP(k) x[i] = val; }
+__global__ void k_add_logdiff(double* x, const double* la, const double* lb, int64_t k)
+{
+    EW_LOOP(k) x[i] += la[i] - lb[i];
+}
+__global__ void k_fix_cols(double* v, const double* log_ct, const double* colsum, int64_t m,
+                           int32_t* flags)
+{
+    EW_LOOP(m) {
+        const double s = colsum[i];
+        if (s > 0.0 && s < INFINITY) v[i] += log_ct[i] - log(s);
+        else flags[1] = 1;
+    }
+}
+__global__ void k_smooth(const double* x, double w, double k_inv, double* out, double* log_out,
+                         int64_t k)
+{
+    EW_LOOP(k) {
+        const double y = (1.0 - w) * x[i] + w * k_inv;
+        out[i] = y;
+        log_out[i] = log(y);
+    }
+}
+__global__ void k_extrapolate(double* z, double* z_prev, double ratio, int64_t k)
+{
+    EW_LOOP(k) {
+        const double zn = z[i] + ratio * (z[i] - z_prev[i]);
+        z_prev[i] = z[i];
+        z[i] = zn;
+    }
+}
+__global__ void k_shifted(const double* base, double alpha, const double* d, double* out, int64_t k)
+{
+    EW_LOOP(k) out[i] = base[i] + alpha * d[i];
+}
+__global__ void k_newton_init(const double* log_rP, const double* r, double* rP, double* grad,
+                              double* b, double* d, int64_t n)
+{
+    EW_LOOP(n) {
+        const double e = exp(log_rP[i]);
+        const double gr = e - r[i];
+        rP[i] = e;
+        grad[i] = gr;
+        b[i] = -gr;
+        d[i] = -gr / e;
+    }
+}
+__global__ void k_forcing_resid(const double* rP, const double* d, const double* pcptd,
+                                const double* grad, double* e, int64_t n)
+{
+    EW_LOOP(n) e[i] = rP[i] * d[i] - pcptd[i] + grad[i];
+}
+__global__ void k_div(const double* x, const double* y, double* out, double sign, int64_t k)
+{
+    EW_LOOP(k) out[i] = sign * x[i] / y[i];
+}
+
+// ---------------------------------------------------------------- CG
+__global__ void k_cg_init(const double* b, const double* rP, const double* s, double rho,
+                          double* d, double* res, double* z, double* p, double* M, double* ptd,
+                          double* pcptd, int64_t n, int64_t m, double* red)
+{
+    __shared__ double s_w[kVecThreads / 64];
+    double rz = 0.0, l1 = 0.0;
+    const int64_t k = n > m ? n : m;
+    EW_LOOP(k) {
+        if (i < n) {
+            const double lo = (1.0 - rho) * rP[i];
+            double mi = rP[i] - rho * s[i];
+            mi = mi > lo ? mi : lo;
+            const double bi = b[i];
+            const double zi = bi / mi;
+            M[i] = mi;
+            d[i] = 0.0;
+            res[i] = bi;
+            z[i] = zi;
+            p[i] = zi;
+            pcptd[i] = 0.0;
+            rz += bi * zi;
+            l1 += fabs(bi);
+        }
+        if (i < m) ptd[i] = 0.0;
+    }
+    rz = block_sum(rz, s_w);
+    l1 = block_sum(l1, s_w);
+    if (threadIdx.x == 0) {
+        red[blockIdx.x] = rz;
+        red[gridDim.x + blockIdx.x] = l1;
+    }
+}
+
+__global__ void k_cg_init_finish(const double* red, int nb, CgScalars* sc)
+{
+    __shared__ double s_w[kVecThreads / 64];
+    const double rz = sum_partials(red, nb, s_w);
+    const double l1 = sum_partials(red + nb, nb, s_w);
+    if (threadIdx.x == 0) {
+        sc->rz = rz;
+        sc->rz_new = rz;
+        sc->res_l1 = l1;
+        sc->alpha = 0.0;
+        sc->beta = 0.0;
+        sc->pq = 0.0;
+    }
+}
+
+__global__ void k_cg_colstep(const double* part, int tiles, int64_t m, const double* c, double* w,
+                             double* wc)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    double s = 0.0;
+    for (int t = 0; t < tiles; ++t) s += part[(int64_t)t * m + j];
+    w[j] = s;
+    wc[j] = s / c[j];
+}
+
+__global__ void k_cg_rowstep(const double* part, int tiles, int64_t n, const double* a,
+                             const double* rP, const double* p, double rho, double* t, double* q,
+                             double* red)
+{
+    __shared__ double s_w[kVecThreads / 64];
+    double pq = 0.0;
+    EW_LOOP(n) {
+        double s = 0.0;
+        for (int tt = 0; tt < tiles; ++tt) s += part[(int64_t)tt * n + i];
+        const double ti = exp(a[i]) * s;
+        const double qi = rP[i] * p[i] - rho * ti;
+        t[i] = ti;
+        q[i] = qi;
+        pq += p[i] * qi;
+    }
+    pq = block_sum(pq, s_w);
+    if (threadIdx.x == 0) red[blockIdx.x] = pq;
+}
+
+// alpha = rz / <p, q>; d += alpha p; res -= alpha q; z = res / M; recurrences
+// for P D(c)^-1 P^T d (n) and P^T d (m); partials of <res, z> and ||res||_1.
+__global__ void k_cg_update(const double* red_pq, int nb_pq, double* d, double* res, double* z,
+                            const double* p, const double* q, const double* M, const double* t,
+                            double* pcptd, const double* w, double* ptd, int64_t n, int64_t m,
+                            double* red, CgScalars* sc)
+{
+    __shared__ double s_w[kVecThreads / 64];
+    const double pq = sum_partials(red_pq, nb_pq, s_w);
+    const double alpha = sc->rz / pq;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->pq = pq;
+        sc->alpha = alpha;
+    }
+    double rz = 0.0, l1 = 0.0;
+    const int64_t k = n > m ? n : m;
+    EW_LOOP(k) {
+        if (i < n) {
+            d[i] += alpha * p[i];
+            const double ri = res[i] - alpha * q[i];
+            res[i] = ri;
+            const double zi = ri / M[i];
+            z[i] = zi;
+            pcptd[i] += alpha * t[i];
+            rz += ri * zi;
+            l1 += fabs(ri);
+        }
+        if (i < m) ptd[i] += alpha * w[i];
+    }
+    rz = block_sum(rz, s_w);
+    l1 = block_sum(l1, s_w);
+    if (threadIdx.x == 0) {
+        red[blockIdx.x] = rz;
+        red[gridDim.x + blockIdx.x] = l1;
+    }
+}
+
+// beta = rz_new / rz; p = z + beta p. rz itself is replaced by the single
+// thread of the tail kernel below, after every block has read it.
+__global__ void k_cg_direction(const double* red, int nb, const double* z, double* p, int64_t n,
+                               CgScalars* sc)
+{
+    __shared__ double s_w[kVecThreads / 64];
+    const double rz_new = sum_partials(red, nb, s_w);
+    const double beta = rz_new / sc->rz;
+    EW_LOOP(n) p[i] = z[i] + beta * p[i];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->rz_new = rz_new;
+        sc->beta = beta;
+    }
+}
+
+__global__ void k_cg_tail(const double* red, int nb, CgScalars* sc)
+{
+    __shared__ double s_w[kVecThreads / 64];
+    const double l1 = sum_partials(red + nb, nb, s_w);
+    if (threadIdx.x == 0) {
+        sc->res_l1 = l1;
+        sc->rz = sc->rz_new;
+    }
+}
+
+inline int vec_blocks(int64_t k)
+{
+    int64_t b = (k + kVecThreads - 1) / kVecThreads;
+    if (b < 1) b = 1;
+    if (b > kMaxRedBlocks) b = kMaxRedBlocks;
+    return (int)b;
+}
+
+inline int map_blocks(int64_t k)
+{
+    int64_t b = (k + kVecThreads - 1) / kVecThreads;
+    return (int)(b < 1 ? 1 : b);
+}
+
+template <typename TC, int NR, int NC, int MODE2>
+hipError_t launch_pass_t(const PassArgs& a, int prec, hipStream_t s)
+{
+    dim3 grid((unsigned)a.tiles_m, (unsigned)a.tiles_n);
+    if (prec == EOT_PREC_MIXED) {
+        if constexpr (sizeof(TC) == 4) {
+            hipLaunchKernelGGL((k_pass_mixed<NR, NC, MODE2>), grid, dim3(kPassThreads), 0, s, a);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else {
+        hipLaunchKernelGGL((k_pass_f64<TC, NR, NC, MODE2>), grid, dim3(kPassThreads), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+template <typename TC>
+hipError_t dispatch_pass(const PassArgs& a, int prec, int nr, int nc, int mode2, hipStream_t s)
+{
+    // Instantiated combinations (nr, nc, mode2):
+    if (nr == 1 && nc == 1) return launch_pass_t<TC, 1, 1, R2_WEIGHT>(a, prec, s);
+    if (nr == 2 && nc == 1 && mode2 == R2_SQUARE) return launch_pass_t<TC, 2, 1, R2_SQUARE>(a, prec, s);
+    if (nr == 2 && nc == 2 && mode2 == R2_WEIGHT) return launch_pass_t<TC, 2, 2, R2_WEIGHT>(a, prec, s);
+    if (nr == 2 && nc == 1 && mode2 == R2_COST) return launch_pass_t<TC, 2, 1, R2_COST>(a, prec, s);
+    if (nr == 2 && nc == 0 && mode2 == R2_SQUARE) return launch_pass_t<TC, 2, 0, R2_SQUARE>(a, prec, s);
+    if (nr == 2 && nc == 0 && mode2 == R2_COST) return launch_pass_t<TC, 2, 0, R2_COST>(a, prec, s);
+    if (nr == 1 && nc == 0) return launch_pass_t<TC, 1, 0, R2_WEIGHT>(a, prec, s);
+    if (nr == 0 && nc == 1) return launch_pass_t<TC, 0, 1, R2_WEIGHT>(a, prec, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_pass(const PassArgs& a, int prec, int nr, int nc, int mode2, hipStream_t s)
+{
+    if (a.kind == EOT_COST_DENSE_F32) return dispatch_pass<float>(a, prec, nr, nc, mode2, s);
+    if (a.kind == EOT_COST_DENSE_F64) return dispatch_pass<double>(a, prec, nr, nc, mode2, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_rowmax(const PassArgs& a, double* part, double* out, hipStream_t s)
+{
+    dim3 grid((unsigned)a.tiles_m, (unsigned)a.tiles_n);
+    if (a.kind == EOT_COST_DENSE_F32)
+        hipLaunchKernelGGL(k_rowmax<float>, grid, dim3(kPassThreads), 0, s, a, part);
+    else if (a.kind == EOT_COST_DENSE_F64)
+        hipLaunchKernelGGL(k_rowmax<double>, grid, dim3(kPassThreads), 0, s, a, part);
+    else
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_merge_max, dim3(map_blocks(a.n)), dim3(kVecThreads), 0, s, part,
+                       a.tiles_m, a.n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_rows(const double* part, int tiles, int64_t n, int nr, const double* a,
+                             double* out0, double* out1, int sq1, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_merge_rows, dim3(map_blocks(n)), dim3(kVecThreads), 0, s, part, tiles, n,
+                       nr, a, out0, out1, sq1);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_cols(const double* part, int tiles, int64_t m, int nc, double* out0,
+                             double* out1, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_merge_cols, dim3(map_blocks(m)), dim3(kVecThreads), 0, s, part, tiles, m,
+                       nc, out0, out1);
+    return hipGetLastError();
+}
+
+hipError_t launch_log_row_from_sums(const double* part, int tiles, int64_t n, const double* a,
+                                    double* log_rP, int32_t* flags, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_log_row, dim3(map_blocks(n)), dim3(kVecThreads), 0, s, part, tiles, n, a,
+                       log_rP, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(int op, const double* x, const double* y, int64_t k, double* red,
+                         int* nb_out, hipStream_t s)
+{
+    const int nb = vec_blocks(k);
+    *nb_out = nb;
+    dim3 g(nb), b(kVecThreads);
+    switch (op) {
+        case RED_L1_DIFF_EXP: hipLaunchKernelGGL(k_reduce<RED_L1_DIFF_EXP>, g, b, 0, s, x, y, k, red); break;
+        case RED_CHI2: hipLaunchKernelGGL(k_reduce<RED_CHI2>, g, b, 0, s, x, y, k, red); break;
+        case RED_DOT: hipLaunchKernelGGL(k_reduce<RED_DOT>, g, b, 0, s, x, y, k, red); break;
+        case RED_SUM_EXP: hipLaunchKernelGGL(k_reduce<RED_SUM_EXP>, g, b, 0, s, x, y, k, red); break;
+        case RED_SUM: hipLaunchKernelGGL(k_reduce<RED_SUM>, g, b, 0, s, x, y, k, red); break;
+        case RED_ENTROPY: hipLaunchKernelGGL(k_reduce<RED_ENTROPY>, g, b, 0, s, x, y, k, red); break;
+        case RED_L1: hipLaunchKernelGGL(k_reduce<RED_L1>, g, b, 0, s, x, y, k, red); break;
+        case RED_BAD: hipLaunchKernelGGL(k_reduce<RED_BAD>, g, b, 0, s, x, y, k, red); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_sum(const double* red, int nb, double* dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finish_sum, dim3(1), dim3(kVecThreads), 0, s, red, nb, dst);
+    return hipGetLastError();
+}
+
+#define EW_LAUNCH(kern, k, ...)                                                                  \
+    do {                                                                                         \
+        hipLaunchKernelGGL(kern, dim3(vec_blocks(k)), dim3(kVecThreads), 0, s, __VA_ARGS__);   \
+        return hipGetLastError();                                                                \
+    } while (0)
+
+hipError_t launch_scale(const double* x, double alpha, double* y, int64_t k, hipStream_t s) { EW_LAUNCH(k_scale, k, x, alpha, y, k); }
+hipError_t launch_divs(const double* x, double d, double* y, int64_t k, hipStream_t s) { EW_LAUNCH(k_divs, k, x, d, y, k); }
+hipError_t launch_log_ratio_fix(double* v, const double* va, const double* log_ct, const double* colsum, int64_t m, int32_t* flags, hipStream_t s) { EW_LAUNCH(k_log_ratio_fix, m, v, va, log_ct, colsum, m, flags); }
+hipError_t launch_hvp_finish(const double* row_part, int tiles_m, const double* col_part, int tiles_n,
+                             int64_t n, int64_t m, const double* a, const double* x, const double* y,
+                             double srho, double* Hx, double* Hy, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_hvp_rows, dim3(map_blocks(n)), dim3(kVecThreads), 0, s, row_part, tiles_m, n, a, x, srho, Hx);
+    hipLaunchKernelGGL(k_hvp_cols, dim3(map_blocks(m)), dim3(kVecThreads), 0, s, col_part, tiles_n, m, y, srho, Hy);
+    return hipGetLastError();
+}
+hipError_t launch_axpy(double alpha, const double* x, double* y, int64_t k, hipStream_t s) { EW_LAUNCH(k_axpy, k, alpha, x, y, k); }
+hipError_t launch_log(const double* x, double* y, int64_t k, hipStream_t s) { EW_LAUNCH(k_log, k, x, y, k); }
+hipError_t launch_exp(const double* x, double* y, int64_t k, hipStream_t s) { EW_LAUNCH(k_exp, k, x, y, k); }
+hipError_t launch_recip(const double* x, double* y, int64_t k, hipStream_t s) { EW_LAUNCH(k_recip, k, x, y, k); }
+hipError_t launch_copy(const double* x, double* y, int64_t k, hipStream_t s) { EW_LAUNCH(k_copy, k, x, y, k); }
+hipError_t launch_fill(double* x, double val, int64_t k, hipStream_t s) { EW_LAUNCH(k_fill, k, x, val, k); }
+hipError_t launch_add_logdiff(double* x, const double* la, const double* lb, int64_t k, hipStream_t s) { EW_LAUNCH(k_add_logdiff, k, x, la, lb, k); }
+hipError_t launch_fix_cols(double* v, const double* log_ct, const double* colsum, int64_t m, int32_t* flags, hipStream_t s) { EW_LAUNCH(k_fix_cols, m, v, log_ct, colsum, m, flags); }
+hipError_t launch_smooth(const double* x, double w, double k_inv, double* out, double* log_out, int64_t k, hipStream_t s) { EW_LAUNCH(k_smooth, k, x, w, k_inv, out, log_out, k); }
+hipError_t launch_extrapolate(double* z, double* z_prev, double ratio, int64_t k, hipStream_t s) { EW_LAUNCH(k_extrapolate, k, z, z_prev, ratio, k); }
+hipError_t launch_shifted(const double* base, double alpha, const double* d, double* out, int64_t k, hipStream_t s) { EW_LAUNCH(k_shifted, k, base, alpha, d, out, k); }
+hipError_t launch_newton_init(const double* log_rP, const double* r, double* rP, double* grad, double* b, double* d, int64_t n, hipStream_t s) { EW_LAUNCH(k_newton_init, n, log_rP, r, rP, grad, b, d, n); }
+hipError_t launch_forcing_resid(const double* rP, const double* d, const double* pcptd, const double* grad, double* e, int64_t n, hipStream_t s) { EW_LAUNCH(k_forcing_resid, n, rP, d, pcptd, grad, e, n); }
+hipError_t launch_div(const double* x, const double* y, double* out, double sign, int64_t k, hipStream_t s) { EW_LAUNCH(k_div, k, x, y, out, sign, k); }
+
+hipError_t launch_cg_init(const double* b, const double* rP, const double* s_, double rho, double* d,
+                          double* res, double* z, double* p, double* M, double* ptd, double* pcptd,
+                          int64_t n, int64_t m, double* red, CgScalars* sc, hipStream_t s)
+{
+    const int nb = vec_blocks(n > m ? n : m);
+    hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(kVecThreads), 0, s, b, rP, s_, rho, d, res, z, p,
+                       M, ptd, pcptd, n, m, red);
+    hipLaunchKernelGGL(k_cg_init_finish, dim3(1), dim3(kVecThreads), 0, s, red, nb, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_colstep(const double* part, int tiles, int64_t m, const double* c, double* w,
+                             double* wc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cg_colstep, dim3(map_blocks(m)), dim3(kVecThreads), 0, s, part, tiles, m,
+                       c, w, wc);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_rowstep(const double* part, int tiles, int64_t n, const double* a,
+                             const double* rP, const double* p, double rho, double* t, double* q,
+                             double* red, int* nb, hipStream_t s)
+{
+    *nb = vec_blocks(n);
+    hipLaunchKernelGGL(k_cg_rowstep, dim3(*nb), dim3(kVecThreads), 0, s, part, tiles, n, a, rP, p,
+                       rho, t, q, red);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update(const double* red_pq, int nb_pq, double* d, double* res, double* z,
+                            const double* p, const double* q, const double* M, const double* t,
+                            double* pcptd, const double* w, double* ptd, int64_t n, int64_t m,
+                            double* red, int* nb, CgScalars* sc, hipStream_t s)
+{
+    *nb = vec_blocks(n > m ? n : m);
+    hipLaunchKernelGGL(k_cg_update, dim3(*nb), dim3(kVecThreads), 0, s, red_pq, nb_pq, d, res, z,
+                       p, q, M, t, pcptd, w, ptd, n, m, red, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_direction(const double* red, int nb, const double* z, double* p, int64_t n,
+                               CgScalars* sc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cg_direction, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, red, nb, z, p,
+                       n, sc);
+    hipLaunchKernelGGL(k_cg_tail, dim3(1), dim3(kVecThreads), 0, s, red, nb, sc);
+    return hipGetLastError();
+}
+
+}  // namespace eot

@@ -1,0 +1,279 @@
+"""Thin ctypes binding of libeot.so (include/eot.h) with the same names.
+
+Arguments are torch tensors on the GPU; this module only checks shapes and
+dtypes, allocates the workspace with torch, and forwards raw device
+pointers and the current HIP stream. Every computation happens in the HIP
+library; if it is not built, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libeot.so")
+
+EOT_OK = 0
+EOT_ERR_INVALID_ARG = 1
+EOT_ERR_BAD_MARGINALS = 2
+EOT_ERR_NONFINITE = 3
+EOT_ERR_NOT_CONVERGED = 4
+EOT_ERR_WORKSPACE = 5
+EOT_ERR_UNSUPPORTED = 6
+EOT_ERR_HIP = 7
+
+EOT_PREC_FP64 = 0
+EOT_PREC_MIXED = 1
+EOT_COST_DENSE_F32 = 0
+EOT_COST_DENSE_F64 = 1
+EOT_COST_SQEUCLID_POINTS = 2
+EOT_OP_MARGINALS = 0
+EOT_OP_HVP = 1
+EOT_OP_NEWTON_CG = 2
+EOT_OP_SOLVE = 3
+
+_c_i32, _c_i64, _c_f64, _c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+
+
+class eot_cost(ctypes.Structure):
+    _fields_ = [("kind", _c_i32), ("d", _c_i32), ("n", _c_i64), ("m", _c_i64), ("ldc", _c_i64),
+                ("C", _c_vp), ("X", _c_vp), ("Y", _c_vp), ("scale", _c_f64)]
+
+
+class eot_newton_stats(ctypes.Structure):
+    _fields_ = [("rho_out", _c_f64), ("cg_iters", _c_i32), ("levels", _c_i32),
+                ("forcing_miss", _c_i32), ("status", _c_i32), ("passes", _c_i64),
+                ("forcing_ratio", _c_f64)]
+
+
+class eot_solve_opts(ctypes.Structure):
+    _fields_ = [("gamma_init", _c_f64), ("gamma_final", _c_f64), ("tol", _c_f64), ("p", _c_f64),
+                ("q1", _c_f64), ("w_r", _c_f64), ("adaptive_q", _c_i32),
+                ("adaptive_rho0", _c_i32), ("max_cg", _c_i32), ("max_levels", _c_i32),
+                ("max_backtrack", _c_i32), ("max_newton", _c_i32), ("max_sinkhorn", _c_i32),
+                ("max_mdot", _c_i32), ("precision", _c_i32), ("verify_fp64", _c_i32)]
+
+
+class eot_solve_stats(ctypes.Structure):
+    _fields_ = [("status", _c_i32), ("mdot_steps", _c_i32), ("newton_steps", _c_i32),
+                ("cg_iters", _c_i32), ("backtracks", _c_i32), ("sinkhorn_iters", _c_i32),
+                ("levels", _c_i32), ("forcing_misses", _c_i32), ("range_retries", _c_i32),
+                ("passes_newton", _c_i64), ("passes_linesearch", _c_i64),
+                ("passes_sinkhorn", _c_i64), ("passes_projection", _c_i64),
+                ("passes_other", _c_i64), ("final_gamma", _c_f64), ("err_r", _c_f64),
+                ("err_c", _c_f64), ("cost", _c_f64), ("dual_value", _c_f64),
+                ("rho_last", _c_f64), ("delta_min_last", _c_f64), ("seconds", _c_f64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# Every entry point declared in include/eot.h, with its ctypes signature.
+SIGNATURES = {
+    "eot_workspace_size": (_c_i32, [_c_i32, ctypes.POINTER(eot_cost), _c_i32,
+                                    ctypes.POINTER(ctypes.c_size_t)]),
+    "eot_marginals": (_c_i32, [ctypes.POINTER(eot_cost), _c_f64, _c_vp, _c_vp, _c_vp, _c_vp,
+                               _c_vp, _c_vp, _c_vp, _c_vp, _c_i32, _c_vp, ctypes.c_size_t,
+                               _c_vp]),
+    "eot_hvp": (_c_i32, [ctypes.POINTER(eot_cost), _c_f64, _c_vp, _c_vp, _c_vp, _c_f64, _c_vp,
+                         _c_vp, _c_vp, _c_vp, _c_i32, _c_vp, ctypes.c_size_t, _c_vp]),
+    "eot_newton_cg": (_c_i32, [ctypes.POINTER(eot_cost), _c_f64, _c_vp, _c_vp, _c_vp, _c_vp,
+                               _c_f64, _c_f64, _c_i32, _c_i32, _c_vp, _c_vp,
+                               ctypes.POINTER(eot_newton_stats), _c_i32, _c_vp,
+                               ctypes.c_size_t, _c_vp]),
+    "eot_solve_opts_default": (None, [ctypes.POINTER(eot_solve_opts)]),
+    "eot_solve": (_c_i32, [ctypes.POINTER(eot_cost), _c_vp, _c_vp,
+                           ctypes.POINTER(eot_solve_opts), _c_vp, _c_vp,
+                           ctypes.POINTER(eot_solve_stats), _c_vp, ctypes.c_size_t, _c_vp]),
+    "eot_status_string": (ctypes.c_char_p, [_c_i32]),
+    "eot_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+class EotError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} (status {status})")
+
+
+def lib() -> ctypes.CDLL:
+    """Load libeot.so (built in-tree); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2504_02067_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().eot_status_string(int(status)).decode()
+
+
+def version() -> str:
+    return lib().eot_version().decode()
+
+
+def _check(status: int, where: str, allow=(EOT_OK,)):
+    if status not in allow:
+        raise EotError(status, where)
+    return status
+
+
+def _vec(t: Optional[torch.Tensor], k: int, name: str, optional: bool = False):
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name} is required")
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == k):
+        raise ValueError(f"{name}: need a contiguous float64 GPU tensor of {k} elements")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_cost(C: torch.Tensor) -> eot_cost:
+    """Dense cost descriptor for a 2-D float32 / float64 GPU tensor (row stride
+    >= columns, unit column stride)."""
+    if not C.is_cuda or C.dim() != 2 or C.stride(1) != 1 or C.stride(0) < C.shape[1]:
+        raise ValueError("C: need a 2-D GPU tensor with unit column stride")
+    if C.dtype == torch.float32:
+        kind = EOT_COST_DENSE_F32
+    elif C.dtype == torch.float64:
+        kind = EOT_COST_DENSE_F64
+    else:
+        raise ValueError("C must be float32 or float64")
+    return eot_cost(kind=kind, d=0, n=C.shape[0], m=C.shape[1], ldc=C.stride(0),
+                    C=ctypes.c_void_p(C.data_ptr()), X=None, Y=None, scale=0.0)
+
+
+def _prec(precision) -> int:
+    if precision in ("fp64", EOT_PREC_FP64):
+        return EOT_PREC_FP64
+    if precision in ("mixed", EOT_PREC_MIXED):
+        return EOT_PREC_MIXED
+    raise ValueError(precision)
+
+
+def workspace(op: int, cost: eot_cost, prec: int, device) -> torch.Tensor:
+    nbytes = ctypes.c_size_t(0)
+    _check(lib().eot_workspace_size(op, ctypes.byref(cost), prec, ctypes.byref(nbytes)),
+           "eot_workspace_size")
+    buf = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + int(nbytes.value)]
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def eot_marginals(C, gamma, f, g, row_shift=None, c_for_s=None, precision="fp64",
+                  want=("log_rP", "log_cP", "mass")):
+    """log r(P), log c(P), sum P and (with c_for_s) s_i = sum_j P_ij^2 / c_j."""
+    cost = make_cost(C)
+    n, m = cost.n, cost.m
+    dev = C.device
+    prec = _prec(precision)
+    out = {}
+    lr = torch.empty(n, dtype=torch.float64, device=dev) if "log_rP" in want else None
+    lc = torch.empty(m, dtype=torch.float64, device=dev) if "log_cP" in want else None
+    ms = torch.empty(1, dtype=torch.float64, device=dev) if "mass" in want else None
+    s = torch.empty(n, dtype=torch.float64, device=dev) if c_for_s is not None else None
+    ws = workspace(EOT_OP_MARGINALS, cost, prec, dev)
+    st = lib().eot_marginals(ctypes.byref(cost), float(gamma), _vec(f, n, "f"), _vec(g, m, "g"),
+                             _vec(row_shift, n, "row_shift", True),
+                             _vec(lr, n, "log_rP", True), _vec(lc, m, "log_cP", True),
+                             _vec(ms, 1, "mass", True), _vec(c_for_s, m, "c_for_s", True),
+                             _vec(s, n, "s", True), prec, ctypes.c_void_p(ws.data_ptr()),
+                             ws.numel(), _stream(dev))
+    _check(st, "eot_marginals")
+    out.update(log_rP=lr, log_cP=lc, mass=ms, s=s)
+    return out
+
+
+def eot_hvp(C, gamma, f, g, rho, x, y, row_shift=None, precision="fp64"):
+    """(Hx, Hy) = discounted Hessian of the dual times (x, y), log units."""
+    cost = make_cost(C)
+    n, m = cost.n, cost.m
+    dev = C.device
+    prec = _prec(precision)
+    Hx = torch.empty(n, dtype=torch.float64, device=dev)
+    Hy = torch.empty(m, dtype=torch.float64, device=dev)
+    ws = workspace(EOT_OP_HVP, cost, prec, dev)
+    st = lib().eot_hvp(ctypes.byref(cost), float(gamma), _vec(f, n, "f"), _vec(g, m, "g"),
+                       _vec(row_shift, n, "row_shift", True), float(rho), _vec(x, n, "x"),
+                       _vec(y, m, "y"), _vec(Hx, n, "Hx"), _vec(Hy, m, "Hy"), prec,
+                       ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev))
+    _check(st, "eot_hvp")
+    return Hx, Hy
+
+
+@dataclass
+class NewtonOut:
+    dir_f: torch.Tensor
+    dir_g: torch.Tensor
+    rho_out: float
+    cg_iters: int
+    levels: int
+    forcing_miss: int
+    passes: int
+    forcing_ratio: float
+
+
+def eot_newton_cg(C, gamma, f, g, r, c, eta, rho0=0.0, max_cg=1000, max_levels=30,
+                  precision="fp64"):
+    """NewtonSolve (Alg. 2) at (f, g) with c(P) = c; direction in cost units."""
+    cost = make_cost(C)
+    n, m = cost.n, cost.m
+    dev = C.device
+    prec = _prec(precision)
+    df = torch.empty(n, dtype=torch.float64, device=dev)
+    dg = torch.empty(m, dtype=torch.float64, device=dev)
+    stats = eot_newton_stats()
+    ws = workspace(EOT_OP_NEWTON_CG, cost, prec, dev)
+    st = lib().eot_newton_cg(ctypes.byref(cost), float(gamma), _vec(f, n, "f"), _vec(g, m, "g"),
+                             _vec(r, n, "r"), _vec(c, m, "c"), float(eta), float(rho0),
+                             int(max_cg), int(max_levels), _vec(df, n, "dir_f"),
+                             _vec(dg, m, "dir_g"), ctypes.byref(stats), prec,
+                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev))
+    _check(st, "eot_newton_cg")
+    return NewtonOut(df, dg, stats.rho_out, stats.cg_iters, stats.levels, stats.forcing_miss,
+                     stats.passes, stats.forcing_ratio)
+
+
+def default_solve_opts(**kw) -> eot_solve_opts:
+    o = eot_solve_opts()
+    lib().eot_solve_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "precision":
+            v = _prec(v)
+        setattr(o, k, v)
+    return o
+
+
+def eot_solve(C, r, c, opts: Optional[eot_solve_opts] = None, allow_not_converged=False, **kw):
+    """MDOT + TruncatedNewtonProject; returns (f, g, stats dict)."""
+    cost = make_cost(C)
+    n, m = cost.n, cost.m
+    dev = C.device
+    o = opts if opts is not None else default_solve_opts(**kw)
+    f = torch.empty(n, dtype=torch.float64, device=dev)
+    g = torch.empty(m, dtype=torch.float64, device=dev)
+    stats = eot_solve_stats()
+    ws = workspace(EOT_OP_SOLVE, cost, o.precision, dev)
+    st = lib().eot_solve(ctypes.byref(cost), _vec(r, n, "r"), _vec(c, m, "c"), ctypes.byref(o),
+                         _vec(f, n, "f"), _vec(g, m, "g"), ctypes.byref(stats),
+                         ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev))
+    allow = (EOT_OK, EOT_ERR_NOT_CONVERGED) if allow_not_converged else (EOT_OK,)
+    _check(st, "eot_solve", allow)
+    return f, g, stats.as_dict()

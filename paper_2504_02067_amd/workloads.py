@@ -230,3 +230,23 @@ def random_potentials(rng: np.random.Generator, n: int, m: int, gamma: float,
     f = spread * gamma * rng.standard_normal(n)
     g = spread * gamma * rng.standard_normal(m)
     return f, g
+
+
+def grid_cost_device(side: int, kind: str = "sqeuclid", device="cuda", block: int = 2048):
+    """:func:`grid_cost` built directly in device memory as float32 (same
+    integer distances and the same single float32 division by the max), in
+    row blocks so no n x n integer temporary is materialised."""
+    import torch
+    n = side * side
+    idx = torch.arange(n, device=device)
+    py, px = idx // side, idx % side
+    dmax = 2 * (side - 1) ** 2 if kind == "sqeuclid" else 2 * (side - 1)
+    out = torch.empty((n, n), dtype=torch.float32, device=device)
+    for i0 in range(0, n, block):
+        i1 = min(n, i0 + block)
+        dy = (py[i0:i1, None] - py[None, :]).abs()
+        dx = (px[i0:i1, None] - px[None, :]).abs()
+        d = dy * dy + dx * dx if kind == "sqeuclid" else dy + dx
+        out[i0:i1] = d.to(torch.float32) / torch.tensor(float(dmax), dtype=torch.float32,
+                                                       device=device)
+    return out

@@ -1,0 +1,130 @@
+"""CPU checks of the C ABI library: it loads, exports every entry point that
+include/eot.h declares, and its host-only logic (workspace sizing, argument
+validation, status strings, option defaults) behaves as documented. No
+kernel is launched."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "eot.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(eot_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2504_02067_amd import eot
+    if not os.path.exists(eot.LIB_PATH):
+        pytest.fail("libeot.so not built (run __graft_entry__.build())")
+    return eot.lib()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("eot_marginals", "eot_hvp", "eot_newton_cg", "eot_solve", "eot_workspace_size",
+              "eot_status_string", "eot_version", "eot_solve_opts_default"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    from paper_2504_02067_amd import eot
+    for name in _declared():
+        assert hasattr(L, name), name
+        assert name in eot.SIGNATURES, f"binding lacks {name}"
+
+
+def test_status_strings_and_version(L):
+    from paper_2504_02067_amd import eot
+    assert eot.version().endswith("gfx950")
+    seen = set()
+    for s in range(8):
+        txt = eot.status_string(s)
+        assert txt and txt != "unknown status"
+        seen.add(txt)
+    assert len(seen) == 8
+    assert eot.status_string(99) == "unknown status"
+
+
+def test_workspace_size_scales_and_validates(L):
+    from paper_2504_02067_amd import eot
+    sz = ctypes.c_size_t(0)
+
+    def ws(op, n, m, kind=0):
+        c = eot.eot_cost(kind=kind, d=0, n=n, m=m, ldc=m, C=ctypes.c_void_p(4096), X=None,
+                         Y=None, scale=0.0)
+        st = L.eot_workspace_size(op, ctypes.byref(c), 0, ctypes.byref(sz))
+        return st, sz.value
+
+    st, small = ws(eot.EOT_OP_SOLVE, 64, 64)
+    assert st == eot.EOT_OK and small > 0
+    st, big = ws(eot.EOT_OP_SOLVE, 16384, 16384)
+    assert st == eot.EOT_OK and big > 100 * small
+    for op in range(4):
+        assert ws(op, 1, 1)[0] == eot.EOT_OK
+    assert ws(eot.EOT_OP_SOLVE, 0, 5)[0] == eot.EOT_ERR_INVALID_ARG
+    assert ws(7, 5, 5)[0] == eot.EOT_ERR_INVALID_ARG
+    assert ws(0, 5, 5, kind=9)[0] == eot.EOT_ERR_INVALID_ARG
+    assert L.eot_workspace_size(0, None, 0, ctypes.byref(sz)) == eot.EOT_ERR_INVALID_ARG
+
+
+def test_argument_validation_happens_before_any_device_work(L):
+    from paper_2504_02067_amd import eot
+    c = eot.eot_cost(kind=0, d=0, n=8, m=8, ldc=8, C=ctypes.c_void_p(4096), X=None, Y=None,
+                     scale=0.0)
+    p = ctypes.c_void_p(4096)
+    # bad temperature, null potentials, null outputs
+    assert L.eot_marginals(ctypes.byref(c), -1.0, p, p, None, p, None, None, None, None, 0,
+                           p, 1 << 20, None) == eot.EOT_ERR_INVALID_ARG
+    assert L.eot_marginals(ctypes.byref(c), float("nan"), p, p, None, p, None, None, None, None,
+                           0, p, 1 << 20, None) == eot.EOT_ERR_INVALID_ARG
+    assert L.eot_marginals(ctypes.byref(c), 1.0, None, p, None, p, None, None, None, None, 0,
+                           p, 1 << 20, None) == eot.EOT_ERR_INVALID_ARG
+    assert L.eot_marginals(ctypes.byref(c), 1.0, p, p, None, None, None, None, None, None, 0,
+                           p, 1 << 20, None) == eot.EOT_ERR_INVALID_ARG
+    # s requested without c_for_s
+    assert L.eot_marginals(ctypes.byref(c), 1.0, p, p, None, p, None, None, None, p, 0,
+                           p, 1 << 20, None) == eot.EOT_ERR_INVALID_ARG
+    # rho outside [0, 1]
+    assert L.eot_hvp(ctypes.byref(c), 1.0, p, p, None, 1.5, p, p, p, p, 0, p, 1 << 20,
+                     None) == eot.EOT_ERR_INVALID_ARG
+    # mixed precision on an FP64 dense cost is not supported
+    c64 = eot.eot_cost(kind=1, d=0, n=8, m=8, ldc=8, C=ctypes.c_void_p(4096), X=None, Y=None,
+                       scale=0.0)
+    assert L.eot_marginals(ctypes.byref(c64), 1.0, p, p, None, p, None, None, None, None, 1,
+                           p, 1 << 20, None) == eot.EOT_ERR_UNSUPPORTED
+    # workspace too small / misaligned
+    assert L.eot_marginals(ctypes.byref(c), 1.0, p, p, None, p, None, None, None, None, 0,
+                           p, 16, None) == eot.EOT_ERR_WORKSPACE
+    assert L.eot_marginals(ctypes.byref(c), 1.0, p, p, None, p, None, None, None, None, 0,
+                           ctypes.c_void_p(4100), 1 << 20, None) == eot.EOT_ERR_WORKSPACE
+    # ldc < m
+    bad = eot.eot_cost(kind=0, d=0, n=8, m=8, ldc=4, C=p, X=None, Y=None, scale=0.0)
+    assert L.eot_marginals(ctypes.byref(bad), 1.0, p, p, None, p, None, None, None, None, 0,
+                           p, 1 << 20, None) == eot.EOT_ERR_INVALID_ARG
+    # solve options
+    o = eot.eot_solve_opts()
+    L.eot_solve_opts_default(ctypes.byref(o))
+    assert (o.p, o.q1, o.w_r, o.adaptive_q, o.adaptive_rho0) == (1.5, 2.0, 0.45, 1, 1)
+    assert o.max_backtrack == 60 and o.verify_fp64 == 1
+    o.w_r = 0.6
+    st = eot.eot_solve_stats()
+    assert L.eot_solve(ctypes.byref(c), p, p, ctypes.byref(o), p, p, ctypes.byref(st), p,
+                       1 << 20, None) == eot.EOT_ERR_INVALID_ARG
+    o.w_r = 0.45
+    o.gamma_final = 0.0
+    assert L.eot_solve(ctypes.byref(c), p, p, ctypes.byref(o), p, p, ctypes.byref(st), p,
+                       1 << 20, None) == eot.EOT_ERR_INVALID_ARG
+
+
+def test_binding_rejects_cpu_tensors():
+    import torch
+    from paper_2504_02067_amd import eot
+    with pytest.raises(ValueError):
+        eot.make_cost(torch.zeros(4, 4))
