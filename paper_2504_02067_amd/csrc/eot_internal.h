@@ -13,7 +13,7 @@ constexpr int kPassThreads = 256;        // 4 wave64 per workgroup
 constexpr int kVec = 4;                  // consecutive columns per thread per row
 constexpr int kChunks = 2;               // column chunks of 1024 per tile
 constexpr int kTileCols = kPassThreads * kVec * kChunks;   // 2048
-constexpr int kTileRows = 128;           // rows per tile (column partials per band)
+constexpr int kTileRows = 256;           // rows per tile (column partials per band)
 constexpr int kSubRows = 8;              // rows in flight per thread
 constexpr int kVecThreads = 256;         // O(n) vector kernels
 constexpr int kMaxRedBlocks = 1024;      // partial sums per reduction

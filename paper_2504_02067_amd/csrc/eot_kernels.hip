@@ -58,52 +58,66 @@ __device__ __forceinline__ double wave_sum(double x)
     return x;
 }
 
-template <typename TC>
-__device__ __forceinline__ void load_row_vec(const TC* __restrict__ row, int64_t jb, int64_t m,
-                                             bool vec_ok, float (&out)[kVec]);
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 
-template <>
-__device__ __forceinline__ void load_row_vec<float>(const float* __restrict__ row, int64_t jb,
-                                                    int64_t m, bool vec_ok, float (&out)[kVec])
+// Loads of 4 consecutive cost entries starting at column jb of one row. They
+// never branch: addresses are clamped into the row's allocation (ldc elements)
+// and entries past column m are replaced by 0 by the caller on edge tiles, so
+// the compiler keeps all loads of a sub-band in flight. Streaming data, so
+// non-temporal (no reuse expected in the caches).
+template <bool VEC>
+__device__ __forceinline__ void load4(const float* __restrict__ row, int64_t jb, int64_t m,
+                                      int64_t ldc, float (&out)[kVec])
 {
-    if (vec_ok && jb + kVec <= m) {
-        const float4 x = *reinterpret_cast<const float4*>(row + jb);
+    if constexpr (VEC) {   // ldc % 4 == 0 and 16-byte aligned base: row + jl is aligned
+        const int64_t jl = jb < ldc - 3 ? jb : ldc - 4;
+        const f32x4 x = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(row + jl));
         out[0] = x.x; out[1] = x.y; out[2] = x.z; out[3] = x.w;
     } else {
 #pragma unroll
-        for (int q = 0; q < kVec; ++q) out[q] = (jb + q < m) ? row[jb + q] : 0.0f;
+        for (int q = 0; q < kVec; ++q) {
+            const int64_t jq = jb + q < m ? jb + q : m - 1;
+            out[q] = __builtin_nontemporal_load(row + jq);
+        }
+    }
+}
+
+template <bool VEC>
+__device__ __forceinline__ void load4(const float* __restrict__ row, int64_t jb, int64_t m,
+                                      int64_t ldc, double (&out)[kVec])
+{
+    float t[kVec];
+    load4<VEC>(row, jb, m, ldc, t);
+#pragma unroll
+    for (int q = 0; q < kVec; ++q) out[q] = (double)t[q];
+}
+
+template <bool VEC>
+__device__ __forceinline__ void load4(const double* __restrict__ row, int64_t jb, int64_t m,
+                                      int64_t ldc, double (&out)[kVec])
+{
+    if constexpr (VEC) {
+        const int64_t jl = jb < ldc - 3 ? jb : ldc - 4;
+        const f64x2 x0 = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(row + jl));
+        const f64x2 x1 = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(row + jl + 2));
+        out[0] = x0.x; out[1] = x0.y; out[2] = x1.x; out[3] = x1.y;
+    } else {
+#pragma unroll
+        for (int q = 0; q < kVec; ++q) {
+            const int64_t jq = jb + q < m ? jb + q : m - 1;
+            out[q] = __builtin_nontemporal_load(row + jq);
+        }
     }
 }
 
 template <typename TC>
 __device__ __forceinline__ void load_row_vec_d(const TC* __restrict__ row, int64_t jb, int64_t m,
-                                               bool vec_ok, double (&out)[kVec]);
-
-template <>
-__device__ __forceinline__ void load_row_vec_d<float>(const float* __restrict__ row, int64_t jb,
-                                                      int64_t m, bool vec_ok, double (&out)[kVec])
+                                               bool vec_ok, double (&out)[kVec])
 {
-    if (vec_ok && jb + kVec <= m) {
-        const float4 x = *reinterpret_cast<const float4*>(row + jb);
-        out[0] = x.x; out[1] = x.y; out[2] = x.z; out[3] = x.w;
-    } else {
 #pragma unroll
-        for (int q = 0; q < kVec; ++q) out[q] = (jb + q < m) ? (double)row[jb + q] : 0.0;
-    }
-}
-
-template <>
-__device__ __forceinline__ void load_row_vec_d<double>(const double* __restrict__ row, int64_t jb,
-                                                       int64_t m, bool vec_ok, double (&out)[kVec])
-{
-    if (vec_ok && jb + kVec <= m) {
-        const double2 x0 = *reinterpret_cast<const double2*>(row + jb);
-        const double2 x1 = *reinterpret_cast<const double2*>(row + jb + 2);
-        out[0] = x0.x; out[1] = x0.y; out[2] = x1.x; out[3] = x1.y;
-    } else {
-#pragma unroll
-        for (int q = 0; q < kVec; ++q) out[q] = (jb + q < m) ? row[jb + q] : 0.0;
-    }
+    for (int q = 0; q < kVec; ++q) out[q] = (jb + q < m) ? (double)row[jb + q] : 0.0;
+    (void)vec_ok;
 }
 
 // Transposed LDS reduction of NR x kSubRows per-thread row partials; writes
@@ -139,10 +153,11 @@ __device__ __forceinline__ void reduce_rows(double (&racc)[NR > 0 ? NR : 1][kSub
 }
 
 // ---------------------------------------------------------------- mixed pass
-template <int NR, int NC, int MODE2>
+template <int NR, int NC, int MODE2, bool VEC>
 __global__ __launch_bounds__(kPassThreads) void k_pass_mixed(PassArgs A)
 {
     constexpr int RB = kTileRows, RS = kSubRows, NCH = kChunks, V = kVec, T = kPassThreads;
+    static_assert(RB <= T, "one thread per tile row in the prologue");
     __shared__ float s_uh[RB];
     __shared__ double s_rf[RB];
     __shared__ double s_xw[2][RB];
@@ -154,7 +169,7 @@ __global__ __launch_bounds__(kPassThreads) void k_pass_mixed(PassArgs A)
     const int64_t i0 = (int64_t)blockIdx.y * RB;
     const int64_t j0 = (int64_t)blockIdx.x * kTileCols;
     const float* __restrict__ C = static_cast<const float*>(A.C);
-    const bool vec_ok = A.vec_ok != 0;
+    const bool full = j0 + kTileCols <= m;     // uniform: no column past m in this tile
 
     // Tile-local bound on |U|, |V| to pick the hi/lo grid.
     double Vd[NCH][V];
@@ -253,7 +268,13 @@ __global__ __launch_bounds__(kPassThreads) void k_pass_mixed(PassArgs A)
             for (int rr = 0; rr < RS; ++rr) {
                 int64_t i = i0 + sb + rr;
                 i = i < n ? i : n - 1;
-                load_row_vec<float>(C + i * A.ldc, jb, m, vec_ok, cv[rr]);
+                load4<VEC>(C + i * A.ldc, jb, m, A.ldc, cv[rr]);
+            }
+            if (!full) {
+#pragma unroll
+                for (int rr = 0; rr < RS; ++rr)
+#pragma unroll
+                    for (int q = 0; q < V; ++q) cv[rr][q] = (jb + q < m) ? cv[rr][q] : 0.0f;
             }
 #pragma unroll
             for (int rr = 0; rr < RS; ++rr) {
@@ -295,10 +316,11 @@ __global__ __launch_bounds__(kPassThreads) void k_pass_mixed(PassArgs A)
 }
 
 // ---------------------------------------------------------------- FP64 pass
-template <typename TC, int NR, int NC, int MODE2>
+template <typename TC, int NR, int NC, int MODE2, bool VEC>
 __global__ __launch_bounds__(kPassThreads) void k_pass_f64(PassArgs A)
 {
     constexpr int RB = kTileRows, RS = kSubRows, NCH = kChunks, V = kVec, T = kPassThreads;
+    static_assert(RB <= T, "one thread per tile row in the prologue");
     __shared__ double s_A[RB];
     __shared__ double s_rf[RB];
     __shared__ double s_xw[2][RB];
@@ -309,7 +331,7 @@ __global__ __launch_bounds__(kPassThreads) void k_pass_f64(PassArgs A)
     const int64_t i0 = (int64_t)blockIdx.y * RB;
     const int64_t j0 = (int64_t)blockIdx.x * kTileCols;
     const TC* __restrict__ C = static_cast<const TC*>(A.C);
-    const bool vec_ok = A.vec_ok != 0;
+    const bool full = j0 + kTileCols <= m;
     const double beta = A.beta;
 
     if (tid < RB) {
@@ -366,7 +388,13 @@ __global__ __launch_bounds__(kPassThreads) void k_pass_f64(PassArgs A)
             for (int rr = 0; rr < RS; ++rr) {
                 int64_t i = i0 + sb + rr;
                 i = i < n ? i : n - 1;
-                load_row_vec_d<TC>(C + i * A.ldc, jb, m, vec_ok, cv[rr]);
+                load4<VEC>(C + i * A.ldc, jb, m, A.ldc, cv[rr]);
+            }
+            if (!full) {
+#pragma unroll
+                for (int rr = 0; rr < RS; ++rr)
+#pragma unroll
+                    for (int q = 0; q < V; ++q) cv[rr][q] = (jb + q < m) ? cv[rr][q] : 0.0;
             }
 #pragma unroll
             for (int rr = 0; rr < RS; ++rr) {
@@ -807,20 +835,27 @@ inline int map_blocks(int64_t k)
     return (int)(b < 1 ? 1 : b);
 }
 
-template <typename TC, int NR, int NC, int MODE2>
-hipError_t launch_pass_t(const PassArgs& a, int prec, hipStream_t s)
+template <typename TC, int NR, int NC, int MODE2, bool VEC>
+hipError_t launch_pass_v(const PassArgs& a, int prec, hipStream_t s)
 {
     dim3 grid((unsigned)a.tiles_m, (unsigned)a.tiles_n);
     if (prec == EOT_PREC_MIXED) {
         if constexpr (sizeof(TC) == 4) {
-            hipLaunchKernelGGL((k_pass_mixed<NR, NC, MODE2>), grid, dim3(kPassThreads), 0, s, a);
+            hipLaunchKernelGGL((k_pass_mixed<NR, NC, MODE2, VEC>), grid, dim3(kPassThreads), 0, s, a);
         } else {
             return hipErrorInvalidValue;
         }
     } else {
-        hipLaunchKernelGGL((k_pass_f64<TC, NR, NC, MODE2>), grid, dim3(kPassThreads), 0, s, a);
+        hipLaunchKernelGGL((k_pass_f64<TC, NR, NC, MODE2, VEC>), grid, dim3(kPassThreads), 0, s, a);
     }
     return hipGetLastError();
+}
+
+template <typename TC, int NR, int NC, int MODE2>
+hipError_t launch_pass_t(const PassArgs& a, int prec, hipStream_t s)
+{
+    return a.vec_ok ? launch_pass_v<TC, NR, NC, MODE2, true>(a, prec, s)
+                    : launch_pass_v<TC, NR, NC, MODE2, false>(a, prec, s);
 }
 
 template <typename TC>
