@@ -163,22 +163,44 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / 1e3 / iters
 
+    def kernel_us(fn, iters, **filt):
+        """Average duration of the streaming-pass kernel alone: the library
+        brackets each pass launch with HIP events on its stream."""
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        eot.eot_pass_timing(True)
+        for _ in range(iters):
+            fn()
+        torch.cuda.synchronize()
+        k, ms = eot.eot_pass_timing_read(**filt)
+        eot.eot_pass_timing(False)
+        return ms * 1e3 / k
+
+    # Algorithmic bytes per launch: the FP32 cost once plus the FP64 vectors read
+    # (potentials, shift, weights) and written (results).
     kern = {}
     hvp_bytes = cost_bytes + 8.0 * (3 * n + 2 * m) + 8.0 * (n + m)
+    col_bytes = cost_bytes + 8.0 * (2 * n + m) + 8.0 * m
+    row_bytes = cost_bytes + 8.0 * (2 * n + m) + 8.0 * n
     for prec in ("mixed", "fp64"):
-        t = time_calls(lambda: eot.eot_hvp(C, p.gamma_final, f, g, 1.0, x, y, row_shift=shift,
-                                           precision=prec), args.hvp_iters)
-        kern[f"hvp_{prec}"] = {"us": t * 1e6, "gbs": hvp_bytes / t / 1e9}
-        t = time_calls(lambda: eot.eot_marginals(C, p.gamma_final, f, g, row_shift=shift,
-                                                 precision=prec, want=("log_cP",)),
-                       args.hvp_iters)
-        kern[f"colpass_{prec}"] = {"us": t * 1e6, "gbs": (cost_bytes + 8.0 * (2 * n + 2 * m)) / t / 1e9}
-        t = time_calls(lambda: eot.eot_marginals(C, p.gamma_final, f, g, row_shift=shift,
-                                                 precision=prec, want=("log_rP",)),
-                       args.hvp_iters)
-        kern[f"rowpass_{prec}"] = {"us": t * 1e6, "gbs": (cost_bytes + 8.0 * (3 * n + m)) / t / 1e9}
-        log(f"{prec}: hvp {kern[f'hvp_{prec}']['us']:.1f} us ({kern[f'hvp_{prec}']['gbs']:.0f} GB/s) "
-            f"col {kern[f'colpass_{prec}']['us']:.1f} us row {kern[f'rowpass_{prec}']['us']:.1f} us")
+        call_hvp = lambda: eot.eot_hvp(C, p.gamma_final, f, g, 1.0, x, y, row_shift=shift,
+                                       precision=prec)
+        call_col = lambda: eot.eot_marginals(C, p.gamma_final, f, g, row_shift=shift,
+                                             precision=prec, want=("log_cP",))
+        call_row = lambda: eot.eot_marginals(C, p.gamma_final, f, g, row_shift=shift,
+                                             precision=prec, want=("log_rP",))
+        for name, fn, nbytes, filt in (
+                ("hvp", call_hvp, hvp_bytes, dict(fused_hvp=1)),
+                ("colpass", call_col, col_bytes, dict(nr=0, nc=1)),
+                ("rowpass", call_row, row_bytes, dict(nr=1, nc=0))):
+            us = kernel_us(fn, args.hvp_iters, precision=prec, **filt)
+            call = time_calls(fn, args.hvp_iters) * 1e6
+            kern[f"{name}_{prec}"] = {"kernel_us": us, "gbs": nbytes / (us * 1e-6) / 1e9,
+                                      "call_us": call, "bytes": nbytes}
+        log(f"{prec}: hvp {kern[f'hvp_{prec}']['kernel_us']:.1f} us "
+            f"({kern[f'hvp_{prec}']['gbs']:.0f} GB/s) col {kern[f'colpass_{prec}']['kernel_us']:.1f} us "
+            f"row {kern[f'rowpass_{prec}']['kernel_us']:.1f} us (kernel only)")
     hvp = kern["hvp_mixed"]
 
     cpu = None
@@ -206,8 +228,8 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": hvp["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": hvp["gbs"] / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "eot_hvp mixed (one pass, row + column reductions)",
-                     "bytes_per_launch": hvp_bytes},
+                     "kernel": "k_pass<mixed, fused HVP>: one pass, row + column reductions",
+                     "bytes_per_launch": hvp_bytes, "kernel_us": hvp["kernel_us"]},
         "time_to_1e6": {"mixed_s": t_mixed, "fp64_s": fp64["seconds"] if fp64 else None,
                         "speedup": (fp64["seconds"] / t_mixed) if fp64 else None,
                         "mixed_err": st["err_r"] + st["err_c"],

@@ -33,7 +33,8 @@
  *  - Vectors are FP64. Dense costs are row-major with leading dimension
  *    ldc >= m (elements).
  *  - Calls on different streams with different workspaces are independent;
- *    the library keeps no global mutable state.
+ *    the library keeps no global mutable state apart from the opt-in pass
+ *    timer below (guarded by a mutex).
  */
 #ifndef EOT_H
 #define EOT_H
@@ -195,6 +196,21 @@ void eot_solve_opts_default(eot_solve_opts* opts);
 eot_status eot_solve(const eot_cost* cost, const double* r, const double* c,
                      const eot_solve_opts* opts, double* f, double* g,
                      eot_solve_stats* stats, void* ws, size_t ws_bytes, void* stream);
+
+/* Opt-in timing of the streaming passes (for benchmarks and profiling). While
+ * enabled, every streaming-pass kernel the library launches is bracketed by two
+ * HIP events recorded on the stream it is launched on. eot_pass_timing(1)
+ * enables and clears the record, eot_pass_timing(0) disables and clears it.
+ * eot_pass_timing_read waits for the recorded events and returns how many
+ * matching pass launches were recorded and their summed device time in
+ * milliseconds; a filter argument of -1 matches anything:
+ *   nr, nc  = number of row / column sums of the pass (0..2),
+ *   prec    = eot_precision of the pass,
+ *   fused_hvp = 1 for the one-pass Hessian-vector product, 0 otherwise.
+ * Not meant for production runs: it adds two event records per pass. */
+eot_status eot_pass_timing(int32_t enable);
+eot_status eot_pass_timing_read(int32_t nr, int32_t nc, int32_t prec, int32_t fused_hvp,
+                                int64_t* launches, double* milliseconds);
 
 /* Static text for a status code. */
 const char* eot_status_string(int32_t status);

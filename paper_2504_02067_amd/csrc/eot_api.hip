@@ -57,7 +57,7 @@ struct Arena {
     } while (0)
 
 struct Scratch {
-    double* row_part = nullptr;  // 2 x tiles_m x n
+    double* row_part = nullptr;  // 2 x tiles_m x waves x n
     double* col_part = nullptr;  // 2 x tiles_n x m
     double* red = nullptr;       // 2 x kMaxRedBlocks
     double* red2 = nullptr;      // 2 x kMaxRedBlocks
@@ -93,7 +93,7 @@ struct Ctx {
 void carve(Arena& ar, Ctx& x, int op)
 {
     const int64_t n = x.n, m = x.m;
-    x.sc.row_part = ar.take<double>((size_t)2 * x.tiles_m * n);
+    x.sc.row_part = ar.take<double>((size_t)2 * row_tiles(x.tiles_m) * n);
     x.sc.col_part = ar.take<double>((size_t)2 * x.tiles_n * m);
     x.sc.red = ar.take<double>(2 * kMaxRedBlocks);
     x.sc.red2 = ar.take<double>(2 * kMaxRedBlocks);
@@ -223,9 +223,9 @@ eot_status row_pass(Ctx& x, int prec, const double* u, const double* a, const do
     A.yw1 = inv_c;
     const int nr = inv_c ? 2 : 1;
     HIPCHK(launch_pass(A, prec, nr, 0, R2_SQUARE, x.s));
-    HIPCHK(launch_log_row_from_sums(x.sc.row_part, x.tiles_m, x.n, a, log_rP, x.sc.flags, x.s));
+    HIPCHK(launch_log_row_from_sums(x.sc.row_part, row_tiles(x.tiles_m), x.n, a, log_rP, x.sc.flags, x.s));
     if (inv_c && s_out)
-        HIPCHK(launch_merge_rows(x.sc.row_part, x.tiles_m, x.n, 2, a, nullptr, s_out, 1, x.s));
+        HIPCHK(launch_merge_rows(x.sc.row_part, row_tiles(x.tiles_m), x.n, 2, a, nullptr, s_out, 1, x.s));
     x.passes += 1;
     return EOT_OK;
 }
@@ -249,7 +249,7 @@ eot_status rowsum_pass(Ctx& x, int prec, const double* u, const double* a, const
     PassArgs A = make_args(x, u, a, v, beta);
     A.yw0 = yw;
     HIPCHK(launch_pass(A, prec, 1, 0, R2_WEIGHT, x.s));
-    HIPCHK(launch_merge_rows(x.sc.row_part, x.tiles_m, x.n, 1, a, out, nullptr, 0, x.s));
+    HIPCHK(launch_merge_rows(x.sc.row_part, row_tiles(x.tiles_m), x.n, 1, a, out, nullptr, 0, x.s));
     x.passes += 1;
     return EOT_OK;
 }
@@ -315,7 +315,7 @@ eot_status newton_solve(Ctx& x, int prec, const double* u, const double* v, doub
                 x.passes += 1;
             }
             int nb_pq = 0, nb = 0;
-            HIPCHK(launch_cg_rowstep(x.sc.row_part, x.tiles_m, n, lr, V.rP, V.p, rho, V.t, V.q,
+            HIPCHK(launch_cg_rowstep(x.sc.row_part, row_tiles(x.tiles_m), n, lr, V.rP, V.p, rho, V.t, V.q,
                                      x.sc.red2, &nb_pq, x.s));
             HIPCHK(launch_cg_update(x.sc.red2, nb_pq, V.dtry, V.res, V.z, V.p, V.q, V.M, V.t,
                                     V.pcptd_try, V.w, V.ptd_try, n, m, x.sc.red, &nb, x.sc.cg,
@@ -497,7 +497,7 @@ eot_status report(Ctx& x, double beta, const double* r, const double* c, eot_sol
     PassArgs A = make_args(x, S.u, S.sh, S.v, beta);
     HIPCHK(launch_pass(A, EOT_PREC_FP64, 2, 1, R2_COST, x.s));
     x.passes += 1;
-    HIPCHK(launch_merge_rows(x.sc.row_part, x.tiles_m, x.n, 2, S.sh, x.tmp_n[0], x.tmp_n[1], 0, x.s));
+    HIPCHK(launch_merge_rows(x.sc.row_part, row_tiles(x.tiles_m), x.n, 2, S.sh, x.tmp_n[0], x.tmp_n[1], 0, x.s));
     HIPCHK(launch_merge_cols(x.sc.col_part, x.tiles_n, x.m, 1, x.tmp_m[0], nullptr, x.s));
     HIPCHK(launch_log(x.tmp_n[0], x.tmp_n[2], x.n, x.s));
     HIPCHK(launch_log(x.tmp_m[0], x.tmp_m[2], x.m, x.s));
@@ -644,8 +644,8 @@ eot_status eot_marginals(const eot_cost* cost, double gamma, const double* f, co
     A.yw1 = s ? x.tmp_m[1] : nullptr;
     HIPCHK(launch_pass(A, prec, nr, nc, R2_SQUARE, x.s));
     if (rows) {
-        HIPCHK(launch_log_row_from_sums(x.sc.row_part, x.tiles_m, x.n, a, lr, x.sc.flags, x.s));
-        if (s) HIPCHK(launch_merge_rows(x.sc.row_part, x.tiles_m, x.n, 2, a, nullptr, s, 1, x.s));
+        HIPCHK(launch_log_row_from_sums(x.sc.row_part, row_tiles(x.tiles_m), x.n, a, lr, x.sc.flags, x.s));
+        if (s) HIPCHK(launch_merge_rows(x.sc.row_part, row_tiles(x.tiles_m), x.n, 2, a, nullptr, s, 1, x.s));
         if (mass) {
             int nb = 0;
             HIPCHK(launch_reduce(RED_SUM_EXP, nullptr, lr, x.n, x.sc.red, &nb, x.s));
@@ -675,12 +675,18 @@ eot_status eot_hvp(const eot_cost* cost, double gamma, const double* f, const do
     HIPCHK(launch_divs(g, gamma, v, x.m, x.s));
     if (row_shift) HIPCHK(launch_copy(row_shift, a, x.n, x.s));
     else EOTCHK(row_max(x, u, v, beta, a));
+    // One pass: row weight x_i + sqrt(rho) y_j, column weight sqrt(rho) x_i + y_j.
+    const double srho = std::sqrt(rho);
+    double* sy = x.tmp_m[1];
+    HIPCHK(launch_scale(yv, srho, sy, x.m, x.s));
     PassArgs A = make_args(x, u, a, v, beta);
+    A.yw0 = sy;
     A.yw1 = yv;
     A.xw1 = xv;
-    HIPCHK(launch_pass(A, prec, 2, 2, R2_WEIGHT, x.s));
-    HIPCHK(launch_hvp_finish(x.sc.row_part, x.tiles_m, x.sc.col_part, x.tiles_n, x.n, x.m, a, xv,
-                             yv, std::sqrt(rho), Hx, Hy, x.s));
+    A.hvp_srho = srho;
+    HIPCHK(launch_pass(A, prec, 1, 1, R2_HVP, x.s));
+    HIPCHK(launch_hvp_finish(x.sc.row_part, row_tiles(x.tiles_m), x.sc.col_part, x.tiles_n, x.n, x.m, a, Hx,
+                             Hy, x.s));
     return EOT_OK;
 }
 
@@ -770,6 +776,20 @@ eot_status eot_solve(const eot_cost* cost, const double* r, const double* c,
     st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = st;
     return status;
+}
+
+eot_status eot_pass_timing(int32_t enable)
+{
+    return set_pass_timing(enable != 0) == hipSuccess ? EOT_OK : EOT_ERR_HIP;
+}
+
+eot_status eot_pass_timing_read(int32_t nr, int32_t nc, int32_t prec, int32_t fused_hvp,
+                                int64_t* launches, double* milliseconds)
+{
+    if (!launches || !milliseconds) return EOT_ERR_INVALID_ARG;
+    return read_pass_timing(nr, nc, prec, fused_hvp, launches, milliseconds) == hipSuccess
+               ? EOT_OK
+               : EOT_ERR_HIP;
 }
 
 const char* eot_status_string(int32_t status)

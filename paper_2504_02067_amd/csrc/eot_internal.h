@@ -14,12 +14,17 @@ constexpr int kVec = 4;                  // consecutive columns per thread per r
 constexpr int kChunks = 2;               // column chunks of 1024 per tile
 constexpr int kTileCols = kPassThreads * kVec * kChunks;   // 2048
 constexpr int kTileRows = 256;           // rows per tile (column partials per band)
-constexpr int kSubRows = 8;              // rows in flight per thread
+constexpr int kSubRows = 8;              // rows per chunk in flight per thread
+constexpr int kWaves = kPassThreads / 64;
+// Row partials are written per wave: [nr][tiles_m * kWaves][n].
+inline int row_tiles(int tiles_m) { return tiles_m * kWaves; }
 constexpr int kVecThreads = 256;         // O(n) vector kernels
 constexpr int kMaxRedBlocks = 1024;      // partial sums per reduction
 
 // Weighting of the second row accumulator.
-enum RowMode2 : int { R2_WEIGHT = 0, R2_SQUARE = 1, R2_COST = 2 };
+// R2_HVP: one row and one column sum with the fused Hessian weights
+// (x_i + sqrt(rho) y_j) and (sqrt(rho) x_i + y_j); x in xw1, y in yw1.
+enum RowMode2 : int { R2_WEIGHT = 0, R2_SQUARE = 1, R2_COST = 2, R2_HVP = 3 };
 
 struct PassArgs {
     int32_t kind;          // eot_cost_kind
@@ -37,6 +42,7 @@ struct PassArgs {
     double* row_part;      // [nr][tiles_m][n]
     double* col_part;      // [nc][tiles_n][m]
     int32_t tiles_m, tiles_n;
+    double hvp_srho;       // sqrt(rho) for R2_HVP
 };
 
 inline int64_t tiles_m_of(int64_t m) { return (m + kTileCols - 1) / kTileCols; }
@@ -44,6 +50,9 @@ inline int64_t tiles_n_of(int64_t n) { return (n + kTileRows - 1) / kTileRows; }
 
 // One streaming pass: nr row sums (0..2), nc column sums (0..2).
 hipError_t launch_pass(const PassArgs& a, int prec, int nr, int nc, int mode2, hipStream_t s);
+// Opt-in event timing of every launch_pass (see eot_pass_timing in eot.h).
+hipError_t set_pass_timing(bool on);
+hipError_t read_pass_timing(int nr, int nc, int prec, int hvp, int64_t* launches, double* ms);
 // Exact row maxima of u_i + v_j - beta C_ij (robust shift): out[n].
 hipError_t launch_rowmax(const PassArgs& a, double* part, double* out, hipStream_t s);
 
@@ -63,8 +72,8 @@ hipError_t launch_divs(const double* x, double d, double* y, int64_t k, hipStrea
 hipError_t launch_log_ratio_fix(double* v, const double* va, const double* log_ct,
                                 const double* colsum, int64_t m, int32_t* flags, hipStream_t s);
 hipError_t launch_hvp_finish(const double* row_part, int tiles_m, const double* col_part,
-                             int tiles_n, int64_t n, int64_t m, const double* a, const double* x,
-                             const double* y, double srho, double* Hx, double* Hy, hipStream_t s);
+                             int tiles_n, int64_t n, int64_t m, const double* a, double* Hx,
+                             double* Hy, hipStream_t s);
 hipError_t launch_log_row_from_sums(const double* part, int tiles, int64_t n, const double* a,
                                     double* log_rP, int32_t* flags, hipStream_t s);
 // Block partial sums of an elementwise expression: writes nb partials to red.

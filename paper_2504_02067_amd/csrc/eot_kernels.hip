@@ -37,6 +37,9 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <mutex>
+#include <vector>
+
 #include "eot_internal.h"
 
 namespace eot {
@@ -44,7 +47,6 @@ namespace eot {
 namespace {
 
 constexpr double kLog2e = 1.4426950408889634074;
-constexpr int kWaves = kPassThreads / 64;
 
 __device__ __forceinline__ double wave_max(double x)
 {
@@ -120,111 +122,179 @@ __device__ __forceinline__ void load_row_vec_d(const TC* __restrict__ row, int64
     (void)vec_ok;
 }
 
-// Transposed LDS reduction of NR x kSubRows per-thread row partials; writes
-// one partial per row of the sub-band to row_part.
-template <int NR, int MODE2>
-__device__ __forceinline__ void reduce_rows(double (&racc)[NR > 0 ? NR : 1][kSubRows],
-                                            double* s_red, const double* s_rf, int sb,
-                                            int64_t i0, int64_t n, const PassArgs& A)
+// Sum over the 64 lanes of a wave of G per-lane values at once (a butterfly
+// transpose-reduction in registers, no LDS, no barrier): after it, lane l holds
+// the full sum of value g = (l >> (6 - log2 G)) & (G - 1) in v[0], valid on
+// lanes whose low (6 - log2 G) bits are zero.
+template <int G>
+__device__ __forceinline__ double wave_transpose_sum(double (&v)[G], int lane)
 {
-    constexpr int G = NR * kSubRows;
-    constexpr int TPG = kPassThreads / G;          // threads per row group (16 or 32)
-    const int tid = threadIdx.x;
+    static_assert(G == 4 || G == 8 || G == 16, "G");
+    constexpr int LG = G == 4 ? 2 : (G == 8 ? 3 : 4);
+#pragma unroll
+    for (int st = 0; st < LG; ++st) {
+        const int off = 32 >> st;
+        const int half = G >> (st + 1);
+        const bool upper = (lane & off) != 0;
+#pragma unroll
+        for (int k = 0; k < half; ++k) {
+            const double keep = upper ? v[k + half] : v[k];
+            const double give = upper ? v[k] : v[k + half];
+            v[k] = keep + __shfl_xor(give, off, 64);
+        }
+    }
+    double x = v[0];
+#pragma unroll
+    for (int off = (64 >> LG) / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// Writes one wave's row partials of a sub-band: row_part[k][tile * waves + wave][i].
+template <int NR, int RS, int MODE2>
+__device__ __forceinline__ void wave_rows_out(double (&racc)[NR][RS], const double* s_rf, int sb,
+                                              int64_t i0, int64_t n, const PassArgs& A)
+{
+    constexpr int G = NR * RS;
+    constexpr int LG = G == 4 ? 2 : (G == 8 ? 3 : 4);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double v[G];
 #pragma unroll
     for (int k = 0; k < NR; ++k)
 #pragma unroll
-        for (int rr = 0; rr < kSubRows; ++rr) s_red[(k * kSubRows + rr) * kPassThreads + tid] = racc[k][rr];
-    __syncthreads();
-    const int grp = tid / TPG, sub = tid % TPG;
-    double acc = 0.0;
-#pragma unroll
-    for (int t = 0; t < kPassThreads / TPG; ++t) acc += s_red[grp * kPassThreads + sub + t * TPG];
-    for (int off = TPG / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, TPG);
-    if (sub == 0) {
-        const int k = grp / kSubRows, rr = grp % kSubRows;
+        for (int rr = 0; rr < RS; ++rr) v[k * RS + rr] = racc[k][rr];
+    const double tot = wave_transpose_sum<G>(v, lane);
+    if ((lane & ((64 >> LG) - 1)) == 0) {
+        const int g = (lane >> (6 - LG)) & (G - 1);
+        const int k = g / RS, rr = g % RS;
         const int64_t i = i0 + sb + rr;
         if (i < n) {
             double fac = s_rf[sb + rr];
             if (k == 1 && MODE2 == R2_SQUARE) fac *= fac;
-            A.row_part[((int64_t)k * A.tiles_m + blockIdx.x) * n + i] = acc * fac;
+            A.row_part[(((int64_t)k * A.tiles_m + blockIdx.x) * kWaves + wave) * n + i] = tot * fac;
         }
     }
-    __syncthreads();
 }
 
-// ---------------------------------------------------------------- mixed pass
-template <int NR, int NC, int MODE2, bool VEC>
-__global__ __launch_bounds__(kPassThreads) void k_pass_mixed(PassArgs A)
+template <typename TC, bool VEC, int RS>
+__device__ __forceinline__ void load_rows(const TC* __restrict__ C, int64_t ldc, int64_t i0,
+                                          int64_t n, int64_t jb, int64_t m,
+                                          TC (&buf)[RS][kVec])
 {
-    constexpr int RB = kTileRows, RS = kSubRows, NCH = kChunks, V = kVec, T = kPassThreads;
-    static_assert(RB <= T, "one thread per tile row in the prologue");
-    __shared__ float s_uh[RB];
-    __shared__ double s_rf[RB];
-    __shared__ double s_xw[2][RB];
-    __shared__ double s_red[NR > 0 ? NR * RS * T : 1];
+#pragma unroll
+    for (int rr = 0; rr < RS; ++rr) {
+        int64_t i = i0 + rr;
+        i = i < n ? i : n - 1;
+        if constexpr (sizeof(TC) == 4) {
+            load4<VEC>(C + i * ldc, jb, m, ldc, buf[rr]);
+        } else {
+            load4<VEC>(C + i * ldc, jb, m, ldc, buf[rr]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- the pass
+// PREC = EOT_PREC_MIXED (FP32 exponent / exp, FP64 sums) or EOT_PREC_FP64.
+// RS rows are in flight per chunk; the next chunk's loads are issued before
+// the current chunk is computed (double buffer), and row partials are reduced
+// per wave in registers, so the loop has no workgroup barrier.
+template <int PREC, typename TC, int NR, int NC, int MODE2, bool VEC, int RS>
+__global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs A)
+{
+    constexpr bool MIXED = PREC == EOT_PREC_MIXED;
+    constexpr int RB = kTileRows, NCH = kChunks, V = kVec, T = kPassThreads;
+    static_assert(NCH == 2, "the double buffer alternates the two column chunks");
+    static_assert(RB <= T && RB % RS == 0, "tile rows");
+    constexpr int NYW = MODE2 == R2_HVP ? 1 : (NR > 0 ? NR : 1);
+    constexpr int NRA = NR > 0 ? NR : 1, NCA = NC > 0 ? NC : 1;
+    __shared__ float s_uh[RB];          // mixed: hi part of log2e (u - a)
+    __shared__ double s_A[RB];          // FP64: u - a
+    __shared__ double s_rf[RB];         // per-row factor of the row partials (2^Ul or 1)
+    __shared__ double s_xw[2][RB];      // column-sum weights
+    __shared__ double s_rr[RB];         // R_i = exp(a_i) 2^Ul (HVP)
     __shared__ double s_wmax[kWaves];
 
     const int tid = threadIdx.x;
     const int64_t n = A.n, m = A.m;
     const int64_t i0 = (int64_t)blockIdx.y * RB;
     const int64_t j0 = (int64_t)blockIdx.x * kTileCols;
-    const float* __restrict__ C = static_cast<const float*>(A.C);
+    const TC* __restrict__ C = static_cast<const TC*>(A.C);
     const bool full = j0 + kTileCols <= m;     // uniform: no column past m in this tile
 
-    // Tile-local bound on |U|, |V| to pick the hi/lo grid.
-    double Vd[NCH][V];
-    double mx = 0.0;
-#pragma unroll
-    for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-        for (int q = 0; q < V; ++q) {
-            const int64_t j = j0 + (int64_t)ch * T * V + tid * V + q;
-            Vd[ch][q] = (j < m) ? kLog2e * A.v[j] : 0.0;
-            mx = fmax(mx, fabs(Vd[ch][q]));
-        }
+    // ---- prologue: per-column values in registers, per-row values in LDS
     const int64_t irow = i0 + tid;
     const bool rvalid = tid < RB && irow < n;
-    double Ud = 0.0, arow = 0.0;
-    if (rvalid) {
-        arow = A.a[irow];
-        Ud = kLog2e * (A.u[irow] - arow);
-        mx = fmax(mx, fabs(Ud));
-    }
-    mx = wave_max(mx);
-    if ((tid & 63) == 0) s_wmax[tid >> 6] = mx;
-    __syncthreads();
-    mx = s_wmax[0];
-#pragma unroll
-    for (int w = 1; w < kWaves; ++w) mx = fmax(mx, s_wmax[w]);
-    if (!(mx < 4.0e6)) mx = 4.0e6;          // non-finite input: results flagged later
-    int e2;
-    frexp(2.0 * mx + 2.0, &e2);              // 2 mx + 2 < 2^e2
-    const int g = 23 - e2;                   // |Uh + Vh| < 2^(23-g) on a 2^-g grid: exact
-    const double sc = ldexp(1.0, g), isc = ldexp(1.0, -g);
-
     float vh[NCH][V], vl[NCH][V];
+    double vc[NCH][V];
+    double arow = 0.0, ul = 0.0, uh = 0.0;
+    if constexpr (MIXED) {
+        double Vd[NCH][V];
+        double mx = 0.0;
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch)
+        for (int ch = 0; ch < NCH; ++ch)
 #pragma unroll
-        for (int q = 0; q < V; ++q) {
-            const int64_t j = j0 + (int64_t)ch * T * V + tid * V + q;
-            const double h = rint(Vd[ch][q] * sc) * isc;
-            vh[ch][q] = (j < m) ? (float)h : -INFINITY;
-            vl[ch][q] = (j < m) ? (float)(Vd[ch][q] - h) : 0.0f;
+            for (int q = 0; q < V; ++q) {
+                const int64_t j = j0 + (int64_t)ch * T * V + tid * V + q;
+                Vd[ch][q] = (j < m) ? kLog2e * A.v[j] : 0.0;
+                mx = fmax(mx, fabs(Vd[ch][q]));
+            }
+        double Ud = 0.0;
+        if (rvalid) {
+            arow = A.a[irow];
+            Ud = kLog2e * (A.u[irow] - arow);
+            mx = fmax(mx, fabs(Ud));
         }
+        mx = wave_max(mx);
+        if ((tid & 63) == 0) s_wmax[tid >> 6] = mx;
+        __syncthreads();
+        mx = s_wmax[0];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) mx = fmax(mx, s_wmax[w]);
+        if (!(mx < 4.0e6)) mx = 4.0e6;          // non-finite input: results flagged later
+        int e2;
+        frexp(2.0 * mx + 2.0, &e2);              // 2 mx + 2 < 2^e2
+        const int g = 23 - e2;                   // |Uh + Vh| < 2^(23-g) on a 2^-g grid: exact
+        const double sc = ldexp(1.0, g), isc = ldexp(1.0, -g);
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                const int64_t j = j0 + (int64_t)ch * T * V + tid * V + q;
+                const double h = rint(Vd[ch][q] * sc) * isc;
+                vh[ch][q] = (j < m) ? (float)h : -INFINITY;
+                vl[ch][q] = (j < m) ? (float)(Vd[ch][q] - h) : 0.0f;
+            }
+        uh = rint(Ud * sc) * isc;
+        ul = Ud - uh;
+    } else {
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                const int64_t j = j0 + (int64_t)ch * T * V + tid * V + q;
+                vc[ch][q] = (j < m) ? A.v[j] : -INFINITY;
+            }
+        if (rvalid) arow = A.a[irow];
+    }
     if (tid < RB) {
         if (rvalid) {
-            const double h = rint(Ud * sc) * isc;
-            const double lo = Ud - h;
-            const double rf = exp2(lo);
+            const double rf = MIXED ? exp2(ul) : 1.0;
             const double R = exp(arow) * rf;
-            s_uh[tid] = (float)h;
+            s_uh[tid] = (float)uh;
+            s_A[tid] = MIXED ? 0.0 : A.u[irow] - arow;
             s_rf[tid] = rf;
-            s_xw[0][tid] = R * (A.xw0 ? A.xw0[irow] : 1.0);
-            s_xw[1][tid] = R * (A.xw1 ? A.xw1[irow] : 1.0);
+            s_rr[tid] = R;
+            if constexpr (MODE2 == R2_HVP) {   // xw0 = R sqrt(rho) x_i, xw1 = x_i
+                s_xw[0][tid] = R * A.hvp_srho * A.xw1[irow];
+                s_xw[1][tid] = A.xw1[irow];
+            } else {
+                s_xw[0][tid] = R * (A.xw0 ? A.xw0[irow] : 1.0);
+                s_xw[1][tid] = R * (A.xw1 ? A.xw1[irow] : 1.0);
+            }
         } else {
             s_uh[tid] = -INFINITY;
+            s_A[tid] = -INFINITY;
             s_rf[tid] = 0.0;
+            s_rr[tid] = 0.0;
             s_xw[0][tid] = 0.0;
             s_xw[1][tid] = 0.0;
         }
@@ -232,192 +302,90 @@ __global__ __launch_bounds__(kPassThreads) void k_pass_mixed(PassArgs A)
     const double Bd = kLog2e * A.beta;
     const float Bh = (float)Bd;
     const float Bl = (float)(Bd - (double)Bh);
+    const double beta = A.beta;
+    const double srho = A.hvp_srho;
 
-    double ywr[NR > 0 ? NR : 1][NCH][V];
+    double ywr[NYW][NCH][V];
 #pragma unroll
-    for (int k = 0; k < NR; ++k)
+    for (int k = 0; k < NYW; ++k)
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch)
 #pragma unroll
             for (int q = 0; q < V; ++q) {
                 const int64_t j = j0 + (int64_t)ch * T * V + tid * V + q;
-                const double* yw = k == 0 ? A.yw0 : A.yw1;
+                const double* yw = MODE2 == R2_HVP ? A.yw1 : (k == 0 ? A.yw0 : A.yw1);
                 ywr[k][ch][q] = (j < m) ? (yw ? yw[j] : 1.0) : 0.0;
             }
-    double cacc[NC > 0 ? NC : 1][NCH][V];
+    double cacc[NCA][NCH][V];
 #pragma unroll
-    for (int k = 0; k < (NC > 0 ? NC : 1); ++k)
+    for (int k = 0; k < NCA; ++k)
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch)
 #pragma unroll
             for (int q = 0; q < V; ++q) cacc[k][ch][q] = 0.0;
     __syncthreads();
 
-    for (int sb = 0; sb < RB; sb += RS) {
-        if (i0 + sb >= n) break;
-        double racc[NR > 0 ? NR : 1][RS];
+    // ---- main loop: one iteration = one sub-band of RS rows, both chunks
+    const int64_t rows = n - i0 < RB ? n - i0 : RB;
+    const int nsb = (int)((rows + RS - 1) / RS);
+    const int64_t jb0 = j0 + tid * V, jb1 = j0 + (int64_t)T * V + tid * V;
+    TC buf0[RS][V], buf1[RS][V];
+    load_rows<TC, VEC, RS>(C, A.ldc, i0, n, jb0, m, buf0);
+
+    auto compute = [&](int sb, int ch, TC (&buf)[RS][V], double (&racc)[NRA][RS]) {
+        const int64_t jb = ch == 0 ? jb0 : jb1;
 #pragma unroll
-        for (int k = 0; k < (NR > 0 ? NR : 1); ++k)
+        for (int rr = 0; rr < RS; ++rr) {
+            const double xw0 = s_xw[0][sb + rr];
+            const double xw1 = s_xw[1][sb + rr];
 #pragma unroll
-            for (int rr = 0; rr < RS; ++rr) racc[k][rr] = 0.0;
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) {
-            const int64_t jb = j0 + (int64_t)ch * T * V + tid * V;
-            float cv[RS][V];
-#pragma unroll
-            for (int rr = 0; rr < RS; ++rr) {
-                int64_t i = i0 + sb + rr;
-                i = i < n ? i : n - 1;
-                load4<VEC>(C + i * A.ldc, jb, m, A.ldc, cv[rr]);
-            }
-            if (!full) {
-#pragma unroll
-                for (int rr = 0; rr < RS; ++rr)
-#pragma unroll
-                    for (int q = 0; q < V; ++q) cv[rr][q] = (jb + q < m) ? cv[rr][q] : 0.0f;
-            }
-#pragma unroll
-            for (int rr = 0; rr < RS; ++rr) {
-                const float uh = s_uh[sb + rr];
-                const double xw0 = s_xw[0][sb + rr];
-                const double xw1 = s_xw[1][sb + rr];
-#pragma unroll
-                for (int q = 0; q < V; ++q) {
-                    const float c = cv[rr][q];
-                    const float t = fmaf(-Bh, c, uh + vh[ch][q]);
+            for (int q = 0; q < V; ++q) {
+                double e64, cd;
+                if constexpr (MIXED) {
+                    float c = (float)buf[rr][q];
+                    if (!full) c = (jb + q < m) ? c : 0.0f;
+                    const float t = fmaf(-Bh, c, s_uh[sb + rr] + vh[ch][q]);
                     const float w = fmaf(-Bl, c, vl[ch][q]);
-                    const float e = __builtin_amdgcn_exp2f(t + w);
-                    const double e64 = (double)e;
+                    e64 = (double)__builtin_amdgcn_exp2f(t + w);
+                    cd = (double)c;
+                } else {
+                    double c = (double)buf[rr][q];
+                    if (!full) c = (jb + q < m) ? c : 0.0;
+                    e64 = exp(fma(-beta, c, s_A[sb + rr] + vc[ch][q]));
+                    cd = c;
+                }
+                if constexpr (MODE2 == R2_HVP) {
+                    // rows: e (x_i + sqrt(rho) y_j); columns: R_i e (sqrt(rho) x_i + y_j)
+                    racc[0][rr] = fma(e64, fma(srho, ywr[0][ch][q], xw1), racc[0][rr]);
+                    cacc[0][ch][q] = fma(e64, fma(s_rr[sb + rr], ywr[0][ch][q], xw0), cacc[0][ch][q]);
+                } else {
                     if constexpr (NR >= 1) racc[0][rr] = fma(e64, ywr[0][ch][q], racc[0][rr]);
                     if constexpr (NR >= 2) {
                         double term = e64;
                         if constexpr (MODE2 == R2_SQUARE) term = e64 * e64;
-                        if constexpr (MODE2 == R2_COST) term = e64 * (double)c;
+                        if constexpr (MODE2 == R2_COST) term = e64 * cd;
                         racc[NR - 1][rr] = fma(term, ywr[NR - 1][ch][q], racc[NR - 1][rr]);
                     }
                     if constexpr (NC >= 1) cacc[0][ch][q] = fma(e64, xw0, cacc[0][ch][q]);
                     if constexpr (NC >= 2) cacc[NC - 1][ch][q] = fma(e64, xw1, cacc[NC - 1][ch][q]);
                 }
+                (void)cd;
             }
         }
-        if constexpr (NR > 0) reduce_rows<NR, MODE2>(racc, s_red, s_rf, sb, i0, n, A);
-    }
-    if constexpr (NC > 0) {
-#pragma unroll
-        for (int k = 0; k < NC; ++k)
-#pragma unroll
-            for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-                for (int q = 0; q < V; ++q) {
-                    const int64_t j = j0 + (int64_t)ch * T * V + tid * V + q;
-                    if (j < m) A.col_part[((int64_t)k * A.tiles_n + blockIdx.y) * m + j] = cacc[k][ch][q];
-                }
-    }
-}
+    };
 
-// ---------------------------------------------------------------- FP64 pass
-template <typename TC, int NR, int NC, int MODE2, bool VEC>
-__global__ __launch_bounds__(kPassThreads) void k_pass_f64(PassArgs A)
-{
-    constexpr int RB = kTileRows, RS = kSubRows, NCH = kChunks, V = kVec, T = kPassThreads;
-    static_assert(RB <= T, "one thread per tile row in the prologue");
-    __shared__ double s_A[RB];
-    __shared__ double s_rf[RB];
-    __shared__ double s_xw[2][RB];
-    __shared__ double s_red[NR > 0 ? NR * RS * T : 1];
-
-    const int tid = threadIdx.x;
-    const int64_t n = A.n, m = A.m;
-    const int64_t i0 = (int64_t)blockIdx.y * RB;
-    const int64_t j0 = (int64_t)blockIdx.x * kTileCols;
-    const TC* __restrict__ C = static_cast<const TC*>(A.C);
-    const bool full = j0 + kTileCols <= m;
-    const double beta = A.beta;
-
-    if (tid < RB) {
-        const int64_t i = i0 + tid;
-        if (i < n) {
-            const double a = A.a[i];
-            const double R = exp(a);
-            s_A[tid] = A.u[i] - a;
-            s_rf[tid] = 1.0;
-            s_xw[0][tid] = R * (A.xw0 ? A.xw0[i] : 1.0);
-            s_xw[1][tid] = R * (A.xw1 ? A.xw1[i] : 1.0);
-        } else {
-            s_A[tid] = -INFINITY;
-            s_rf[tid] = 0.0;
-            s_xw[0][tid] = 0.0;
-            s_xw[1][tid] = 0.0;
-        }
-    }
-    double vc[NCH][V];
-    double ywr[NR > 0 ? NR : 1][NCH][V];
+    for (int b = 0; b < nsb; ++b) {
+        const int sb = b * RS;
+        double racc[NRA][RS];
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-        for (int q = 0; q < V; ++q) {
-            const int64_t j = j0 + (int64_t)ch * T * V + tid * V + q;
-            vc[ch][q] = (j < m) ? A.v[j] : -INFINITY;
-#pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                const double* yw = k == 0 ? A.yw0 : A.yw1;
-                ywr[k][ch][q] = (j < m) ? (yw ? yw[j] : 1.0) : 0.0;
-            }
-        }
-    double cacc[NC > 0 ? NC : 1][NCH][V];
-#pragma unroll
-    for (int k = 0; k < (NC > 0 ? NC : 1); ++k)
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-            for (int q = 0; q < V; ++q) cacc[k][ch][q] = 0.0;
-    __syncthreads();
-
-    for (int sb = 0; sb < RB; sb += RS) {
-        if (i0 + sb >= n) break;
-        double racc[NR > 0 ? NR : 1][RS];
-#pragma unroll
-        for (int k = 0; k < (NR > 0 ? NR : 1); ++k)
+        for (int k = 0; k < NRA; ++k)
 #pragma unroll
             for (int rr = 0; rr < RS; ++rr) racc[k][rr] = 0.0;
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) {
-            const int64_t jb = j0 + (int64_t)ch * T * V + tid * V;
-            double cv[RS][V];
-#pragma unroll
-            for (int rr = 0; rr < RS; ++rr) {
-                int64_t i = i0 + sb + rr;
-                i = i < n ? i : n - 1;
-                load4<VEC>(C + i * A.ldc, jb, m, A.ldc, cv[rr]);
-            }
-            if (!full) {
-#pragma unroll
-                for (int rr = 0; rr < RS; ++rr)
-#pragma unroll
-                    for (int q = 0; q < V; ++q) cv[rr][q] = (jb + q < m) ? cv[rr][q] : 0.0;
-            }
-#pragma unroll
-            for (int rr = 0; rr < RS; ++rr) {
-                const double ar = s_A[sb + rr];
-                const double xw0 = s_xw[0][sb + rr];
-                const double xw1 = s_xw[1][sb + rr];
-#pragma unroll
-                for (int q = 0; q < V; ++q) {
-                    const double c = cv[rr][q];
-                    const double e = exp(fma(-beta, c, ar + vc[ch][q]));
-                    if constexpr (NR >= 1) racc[0][rr] = fma(e, ywr[0][ch][q], racc[0][rr]);
-                    if constexpr (NR >= 2) {
-                        double term = e;
-                        if constexpr (MODE2 == R2_SQUARE) term = e * e;
-                        if constexpr (MODE2 == R2_COST) term = e * c;
-                        racc[NR - 1][rr] = fma(term, ywr[NR - 1][ch][q], racc[NR - 1][rr]);
-                    }
-                    if constexpr (NC >= 1) cacc[0][ch][q] = fma(e, xw0, cacc[0][ch][q]);
-                    if constexpr (NC >= 2) cacc[NC - 1][ch][q] = fma(e, xw1, cacc[NC - 1][ch][q]);
-                }
-            }
-        }
-        if constexpr (NR > 0) reduce_rows<NR, MODE2>(racc, s_red, s_rf, sb, i0, n, A);
+        load_rows<TC, VEC, RS>(C, A.ldc, i0 + sb, n, jb1, m, buf1);
+        compute(sb, 0, buf0, racc);
+        if (b + 1 < nsb) load_rows<TC, VEC, RS>(C, A.ldc, i0 + sb + RS, n, jb0, m, buf0);
+        compute(sb, 1, buf1, racc);
+        if constexpr (NR > 0) wave_rows_out<NR, RS, MODE2>(racc, s_rf, sb, i0, n, A);
     }
     if constexpr (NC > 0) {
 #pragma unroll
@@ -496,19 +464,28 @@ __global__ void k_merge_rows(const double* part, int tiles, int64_t n, int nr, c
     }
 }
 
+// Sum of `tiles` partials strided by m, in a fixed order: eight interleaved
+// partial sums (independent loads in flight), then combined pairwise.
+__device__ __forceinline__ double sum_tiles(const double* __restrict__ part, int tiles, int64_t m,
+                                            int64_t j)
+{
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int t = 0;
+    for (; t + 8 <= tiles; t += 8) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) a[k] += part[(int64_t)(t + k) * m + j];
+    }
+    for (int k = 0; t < tiles; ++t, ++k) a[k] += part[(int64_t)t * m + j];
+    return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
 __global__ void k_merge_cols(const double* part, int tiles, int64_t m, int nc, double* out0,
                              double* out1)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m) return;
-    double s0 = 0.0;
-    for (int t = 0; t < tiles; ++t) s0 += part[(int64_t)t * m + j];
-    if (out0) out0[j] = s0;
-    if (nc > 1 && out1) {
-        double s1 = 0.0;
-        for (int t = 0; t < tiles; ++t) s1 += part[((int64_t)tiles + t) * m + j];
-        out1[j] = s1;
-    }
+    if (out0) out0[j] = sum_tiles(part, tiles, m, j);
+    if (nc > 1 && out1) out1[j] = sum_tiles(part + (int64_t)tiles * m, tiles, m, j);
 }
 
 // log r(P)_i = a_i + log sum_t part[t][i]; flags[0] set when the shifted sum
@@ -591,32 +568,21 @@ __global__ void k_log_ratio_fix(double* v, const double* va, const double* log_c
         else { v[i] = va[i]; flags[1] = 1; }
     }
 }
-// Hx = r(P) x + sqrt(rho) P y, from the (2, 2) pass: row sums 0 = sum e, 1 = sum e y.
-__global__ void k_hvp_rows(const double* part, int tiles, int64_t n, const double* a,
-                           const double* x, double srho, double* Hx)
+// Hx_i = sum_j P_ij (x_i + sqrt(rho) y_j) = r(P)_i x_i + sqrt(rho) (P y)_i
+__global__ void k_hvp_rows(const double* part, int tiles, int64_t n, const double* a, double* Hx)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double s0 = 0.0, s1 = 0.0;
-    for (int t = 0; t < tiles; ++t) {
-        s0 += part[(int64_t)t * n + i];
-        s1 += part[((int64_t)tiles + t) * n + i];
-    }
-    const double ea = exp(a[i]);
-    Hx[i] = (ea * s0) * x[i] + srho * (ea * s1);
+    double s0 = 0.0;
+    for (int t = 0; t < tiles; ++t) s0 += part[(int64_t)t * n + i];
+    Hx[i] = exp(a[i]) * s0;
 }
-// Hy = sqrt(rho) P^T x + c(P) y, column sums 0 = sum P, 1 = sum P x.
-__global__ void k_hvp_cols(const double* part, int tiles, int64_t m, const double* y, double srho,
-                           double* Hy)
+// Hy_j = sum_i P_ij (sqrt(rho) x_i + y_j) = sqrt(rho) (P^T x)_j + c(P)_j y_j
+__global__ void k_hvp_cols(const double* part, int tiles, int64_t m, double* Hy)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m) return;
-    double s0 = 0.0, s1 = 0.0;
-    for (int t = 0; t < tiles; ++t) {
-        s0 += part[(int64_t)t * m + j];
-        s1 += part[((int64_t)tiles + t) * m + j];
-    }
-    Hy[j] = srho * s1 + s0 * y[j];
+    Hy[j] = sum_tiles(part, tiles, m, j);
 }
 __global__ void k_axpy(double alpha, const double* x, double* y, int64_t k) { EW_LOOP(k) y[i] += alpha * x[i]; }
 __global__ void k_log(const double* x, double* y, int64_t k) { EW_LOOP(k) y[i] = log(x[i]); }
@@ -734,8 +700,7 @@ __global__ void k_cg_colstep(const double* part, int tiles, int64_t m, const dou
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m) return;
-    double s = 0.0;
-    for (int t = 0; t < tiles; ++t) s += part[(int64_t)t * m + j];
+    const double s = sum_tiles(part, tiles, m, j);
     w[j] = s;
     wc[j] = s / c[j];
 }
@@ -838,15 +803,18 @@ inline int map_blocks(int64_t k)
 template <typename TC, int NR, int NC, int MODE2, bool VEC>
 hipError_t launch_pass_v(const PassArgs& a, int prec, hipStream_t s)
 {
+    constexpr int RS = (MODE2 == R2_HVP || (NR > 0 && NC > 0)) ? 4 : kSubRows;
     dim3 grid((unsigned)a.tiles_m, (unsigned)a.tiles_n);
     if (prec == EOT_PREC_MIXED) {
         if constexpr (sizeof(TC) == 4) {
-            hipLaunchKernelGGL((k_pass_mixed<NR, NC, MODE2, VEC>), grid, dim3(kPassThreads), 0, s, a);
+            hipLaunchKernelGGL((k_pass<EOT_PREC_MIXED, TC, NR, NC, MODE2, VEC, RS>), grid,
+                               dim3(kPassThreads), 0, s, a);
         } else {
             return hipErrorInvalidValue;
         }
     } else {
-        hipLaunchKernelGGL((k_pass_f64<TC, NR, NC, MODE2, VEC>), grid, dim3(kPassThreads), 0, s, a);
+        hipLaunchKernelGGL((k_pass<EOT_PREC_FP64, TC, NR, NC, MODE2, VEC, RS>), grid,
+                           dim3(kPassThreads), 0, s, a);
     }
     return hipGetLastError();
 }
@@ -861,7 +829,8 @@ hipError_t launch_pass_t(const PassArgs& a, int prec, hipStream_t s)
 template <typename TC>
 hipError_t dispatch_pass(const PassArgs& a, int prec, int nr, int nc, int mode2, hipStream_t s)
 {
-    // Instantiated combinations (nr, nc, mode2):
+    // Instantiated combinations (nr, nc, mode2); the mode-specific ones first.
+    if (nr == 1 && nc == 1 && mode2 == R2_HVP) return launch_pass_t<TC, 1, 1, R2_HVP>(a, prec, s);
     if (nr == 1 && nc == 1) return launch_pass_t<TC, 1, 1, R2_WEIGHT>(a, prec, s);
     if (nr == 2 && nc == 1 && mode2 == R2_SQUARE) return launch_pass_t<TC, 2, 1, R2_SQUARE>(a, prec, s);
     if (nr == 2 && nc == 2 && mode2 == R2_WEIGHT) return launch_pass_t<TC, 2, 2, R2_WEIGHT>(a, prec, s);
@@ -875,11 +844,81 @@ hipError_t dispatch_pass(const PassArgs& a, int prec, int nr, int nc, int mode2,
 
 }  // namespace
 
+// ---------------------------------------------------------------- pass timer
+namespace {
+struct PassTiming {
+    hipEvent_t start, stop;
+    int nr, nc, prec, hvp;
+};
+std::mutex g_timing_mu;
+bool g_timing_on = false;
+std::vector<PassTiming> g_timings;
+
+void clear_timings_locked()
+{
+    for (auto& t : g_timings) {
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
+    g_timings.clear();
+}
+}  // namespace
+
+hipError_t set_pass_timing(bool on)
+{
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    clear_timings_locked();
+    g_timing_on = on;
+    return hipSuccess;
+}
+
+hipError_t read_pass_timing(int nr, int nc, int prec, int hvp, int64_t* launches, double* ms)
+{
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    int64_t k = 0;
+    double tot = 0.0;
+    for (auto& t : g_timings) {
+        if ((nr >= 0 && t.nr != nr) || (nc >= 0 && t.nc != nc) || (prec >= 0 && t.prec != prec) ||
+            (hvp >= 0 && t.hvp != hvp))
+            continue;
+        hipError_t e = hipEventSynchronize(t.stop);
+        if (e != hipSuccess) return e;
+        float x = 0.0f;
+        e = hipEventElapsedTime(&x, t.start, t.stop);
+        if (e != hipSuccess) return e;
+        tot += x;
+        ++k;
+    }
+    *launches = k;
+    *ms = tot;
+    return hipSuccess;
+}
+
 hipError_t launch_pass(const PassArgs& a, int prec, int nr, int nc, int mode2, hipStream_t s)
 {
-    if (a.kind == EOT_COST_DENSE_F32) return dispatch_pass<float>(a, prec, nr, nc, mode2, s);
-    if (a.kind == EOT_COST_DENSE_F64) return dispatch_pass<double>(a, prec, nr, nc, mode2, s);
-    return hipErrorInvalidValue;
+    auto go = [&]() -> hipError_t {
+        if (a.kind == EOT_COST_DENSE_F32) return dispatch_pass<float>(a, prec, nr, nc, mode2, s);
+        if (a.kind == EOT_COST_DENSE_F64) return dispatch_pass<double>(a, prec, nr, nc, mode2, s);
+        return hipErrorInvalidValue;
+    };
+    bool timed;
+    {
+        std::lock_guard<std::mutex> lk(g_timing_mu);
+        timed = g_timing_on;
+    }
+    if (!timed) return go();
+    PassTiming t{nullptr, nullptr, nr, nc, prec, mode2 == R2_HVP ? 1 : 0};
+    hipError_t e = hipEventCreate(&t.start);
+    if (e == hipSuccess) e = hipEventCreate(&t.stop);
+    if (e == hipSuccess) e = hipEventRecord(t.start, s);
+    if (e != hipSuccess) return e;
+    e = go();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(t.stop, s);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_timings.push_back(t);
+    return hipSuccess;
 }
 
 hipError_t launch_rowmax(const PassArgs& a, double* part, double* out, hipStream_t s)
@@ -956,11 +995,10 @@ hipError_t launch_scale(const double* x, double alpha, double* y, int64_t k, hip
 hipError_t launch_divs(const double* x, double d, double* y, int64_t k, hipStream_t s) { EW_LAUNCH(k_divs, k, x, d, y, k); }
 hipError_t launch_log_ratio_fix(double* v, const double* va, const double* log_ct, const double* colsum, int64_t m, int32_t* flags, hipStream_t s) { EW_LAUNCH(k_log_ratio_fix, m, v, va, log_ct, colsum, m, flags); }
 hipError_t launch_hvp_finish(const double* row_part, int tiles_m, const double* col_part, int tiles_n,
-                             int64_t n, int64_t m, const double* a, const double* x, const double* y,
-                             double srho, double* Hx, double* Hy, hipStream_t s)
+                             int64_t n, int64_t m, const double* a, double* Hx, double* Hy, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_hvp_rows, dim3(map_blocks(n)), dim3(kVecThreads), 0, s, row_part, tiles_m, n, a, x, srho, Hx);
-    hipLaunchKernelGGL(k_hvp_cols, dim3(map_blocks(m)), dim3(kVecThreads), 0, s, col_part, tiles_n, m, y, srho, Hy);
+    hipLaunchKernelGGL(k_hvp_rows, dim3(map_blocks(n)), dim3(kVecThreads), 0, s, row_part, tiles_m, n, a, Hx);
+    hipLaunchKernelGGL(k_hvp_cols, dim3(map_blocks(m)), dim3(kVecThreads), 0, s, col_part, tiles_n, m, Hy);
     return hipGetLastError();
 }
 hipError_t launch_axpy(double alpha, const double* x, double* y, int64_t k, hipStream_t s) { EW_LAUNCH(k_axpy, k, alpha, x, y, k); }

@@ -89,6 +89,9 @@ SIGNATURES = {
     "eot_solve": (_c_i32, [ctypes.POINTER(eot_cost), _c_vp, _c_vp,
                            ctypes.POINTER(eot_solve_opts), _c_vp, _c_vp,
                            ctypes.POINTER(eot_solve_stats), _c_vp, ctypes.c_size_t, _c_vp]),
+    "eot_pass_timing": (_c_i32, [_c_i32]),
+    "eot_pass_timing_read": (_c_i32, [_c_i32, _c_i32, _c_i32, _c_i32, ctypes.POINTER(_c_i64),
+                                      ctypes.POINTER(_c_f64)]),
     "eot_status_string": (ctypes.c_char_p, [_c_i32]),
     "eot_version": (ctypes.c_char_p, []),
 }
@@ -277,3 +280,18 @@ def eot_solve(C, r, c, opts: Optional[eot_solve_opts] = None, allow_not_converge
     allow = (EOT_OK, EOT_ERR_NOT_CONVERGED) if allow_not_converged else (EOT_OK,)
     _check(st, "eot_solve", allow)
     return f, g, stats.as_dict()
+
+
+def eot_pass_timing(enable: bool) -> None:
+    """Enable (and clear) or disable the library's per-pass event timer."""
+    _check(lib().eot_pass_timing(1 if enable else 0), "eot_pass_timing")
+
+
+def eot_pass_timing_read(nr=-1, nc=-1, precision=-1, fused_hvp=-1):
+    """(launches, total milliseconds) of the recorded pass kernels matching the filter."""
+    k = _c_i64(0)
+    ms = _c_f64(0.0)
+    prec = -1 if precision == -1 else _prec(precision)
+    _check(lib().eot_pass_timing_read(int(nr), int(nc), prec, int(fused_hvp), ctypes.byref(k),
+                                      ctypes.byref(ms)), "eot_pass_timing_read")
+    return int(k.value), float(ms.value)
