@@ -24,6 +24,8 @@ using namespace eot;
 
 namespace {
 
+static_assert(sizeof(CgScalars) % sizeof(double) == 0, "CgScalars is fetched as doubles");
+
 // Discount cap of NewtonSolve: 1 - 2^-30 (kappa(F_r) <= 2 / (1 - rho) ~ 2e9).
 constexpr double kRhoMax = 1.0 - 9.313225746154785e-10;
 
@@ -295,40 +297,43 @@ eot_status newton_solve(Ctx& x, int prec, const double* u, const double* v, doub
             ++lev;
             continue;
         }
+        // CG at this discount. The iterations are enqueued in chunks without
+        // waiting: each kernel of an iteration returns at once when the device
+        // flag sc.done is set (by the iteration that met the stop test, broke
+        // down or reached max_cg), so the host reads the scalars once per chunk.
         const double tol = 0.25 * eta * gnorm;
         HIPCHK(launch_cg_init(V.b, V.rP, s, rho, V.dtry, V.res, V.z, V.p, V.M, V.ptd_try,
-                              V.pcptd_try, n, m, x.sc.red, x.sc.cg, x.s));
+                              V.pcptd_try, n, m, x.sc.red, x.sc.cg, tol, max_cg, x.s));
+        PassArgs pa = make_args(x, u, lr, v, beta);        // pass A: column sums of P p
+        pa.xw0 = V.p;
+        pa.skip = &x.sc.cg->done;
+        PassArgs pb = make_args(x, u, lr, v, beta);        // pass B: row sums of P (w / c)
+        pb.yw0 = V.wc;
+        pb.skip = &x.sc.cg->done;
         CgScalars h{};
-        EOTCHK(fetch(x, reinterpret_cast<const double*>(x.sc.cg), reinterpret_cast<double*>(&h),
-                     sizeof(CgScalars) / sizeof(double)));
-        bool conv = h.res_l1 <= tol;
-        int k = 0;
-        bool broke = false;
-        while (!conv && k < max_cg) {
-            // pass A: w = P^T p ; pass B: t = P (w / c) ; q = r(P) p - rho t
-            EOTCHK(col_pass(x, prec, u, lr, v, beta, V.p, V.w));
-            HIPCHK(launch_div(V.w, c, V.wc, 1.0, m, x.s));
-            {
-                PassArgs A = make_args(x, u, lr, v, beta);
-                A.yw0 = V.wc;
-                HIPCHK(launch_pass(A, prec, 1, 0, R2_WEIGHT, x.s));
-                x.passes += 1;
+        int issued = 0, chunk = 4;
+        for (;;) {
+            for (int it = 0; it < chunk && issued < max_cg; ++it, ++issued) {
+                HIPCHK(launch_pass(pa, prec, 0, 1, R2_WEIGHT, x.s));
+                HIPCHK(launch_cg_colstep(x.sc.col_part, x.tiles_n, m, c, V.w, V.wc, x.sc.cg, x.s));
+                HIPCHK(launch_pass(pb, prec, 1, 0, R2_WEIGHT, x.s));
+                int nb_pq = 0, nb = 0;
+                HIPCHK(launch_cg_rowstep(x.sc.row_part, row_tiles(x.tiles_m), n, lr, V.rP, V.p,
+                                         rho, V.t, V.q, x.sc.red2, &nb_pq, x.sc.cg, x.s));
+                HIPCHK(launch_cg_update(x.sc.red2, nb_pq, V.dtry, V.res, V.z, V.p, V.q, V.M, V.t,
+                                        V.pcptd_try, V.w, V.ptd_try, n, m, x.sc.red, &nb,
+                                        x.sc.cg, x.s));
+                HIPCHK(launch_cg_direction(x.sc.red, nb, V.z, V.p, n, x.sc.cg, x.s));
             }
-            int nb_pq = 0, nb = 0;
-            HIPCHK(launch_cg_rowstep(x.sc.row_part, row_tiles(x.tiles_m), n, lr, V.rP, V.p, rho, V.t, V.q,
-                                     x.sc.red2, &nb_pq, x.s));
-            HIPCHK(launch_cg_update(x.sc.red2, nb_pq, V.dtry, V.res, V.z, V.p, V.q, V.M, V.t,
-                                    V.pcptd_try, V.w, V.ptd_try, n, m, x.sc.red, &nb, x.sc.cg,
-                                    x.s));
-            HIPCHK(launch_cg_direction(x.sc.red, nb, V.z, V.p, n, x.sc.cg, x.s));
             EOTCHK(fetch(x, reinterpret_cast<const double*>(x.sc.cg),
                          reinterpret_cast<double*>(&h), sizeof(CgScalars) / sizeof(double)));
-            ++k;
-            if (!std::isfinite(h.alpha) || !(h.pq > 0.0)) { broke = true; break; }
-            conv = h.res_l1 <= tol;
+            if (h.done || issued >= max_cg) break;
+            chunk = std::min(2 * chunk, 32);
         }
-        cgk += k;
-        if (!conv || broke) { miss = 1; break; }
+        x.passes += 2 * (int64_t)h.iters;
+        cgk += h.iters;
+        const bool conv = !h.broke && h.res_l1 <= tol;
+        if (!conv) { miss = 1; break; }
         std::swap(V.d, V.dtry);
         std::swap(V.ptd, V.ptd_try);
         std::swap(V.pcptd, V.pcptd_try);

@@ -43,6 +43,7 @@ struct PassArgs {
     double* col_part;      // [nc][tiles_n][m]
     int32_t tiles_m, tiles_n;
     double hvp_srho;       // sqrt(rho) for R2_HVP
+    const int32_t* skip;   // nullable device flag: the whole pass is skipped when set
 };
 
 inline int64_t tiles_m_of(int64_t m) { return (m + kTileCols - 1) / kTileCols; }
@@ -117,19 +118,24 @@ hipError_t launch_fill(double* x, double val, int64_t k, hipStream_t s);
 
 // CG building blocks (state lives in device scalars `sc`).
 struct CgScalars {
-    double rz, pq, alpha, beta, res_l1, rz_new;
+    double rz, pq, alpha, beta, res_l1, rz_new, tol;
+    int32_t done;      // set by the iteration that converged / broke down / hit max_iter
+    int32_t iters;     // CG iterations performed
+    int32_t broke;     // <p, F p> <= 0 or a non-finite step
+    int32_t max_iter;
 };
 hipError_t launch_cg_init(const double* b, const double* rP, const double* s, double rho,
                           double* d, double* res, double* z, double* p, double* M, double* ptd,
                           double* pcptd, int64_t n, int64_t m, double* red, CgScalars* sc,
-                          hipStream_t st);
+                          double tol, int32_t max_iter, hipStream_t st);
 // after pass A (column sums of P p): w = raw column sums, wc = w / c
 hipError_t launch_cg_colstep(const double* part, int tiles, int64_t m, const double* c,
-                             double* w, double* wc, hipStream_t st);
+                             double* w, double* wc, const CgScalars* sc, hipStream_t st);
 // after pass B (row sums of P wc): t = row sums, q = rP p - rho t; partial <p, q>
 hipError_t launch_cg_rowstep(const double* part, int tiles, int64_t n, const double* a,
                              const double* rP, const double* p, double rho, double* t,
-                             double* q, double* red, int* nb, hipStream_t st);
+                             double* q, double* red, int* nb, const CgScalars* sc,
+                             hipStream_t st);
 hipError_t launch_cg_update(const double* red_pq, int nb_pq, double* d, double* res, double* z,
                             const double* p, const double* q, const double* M, const double* t,
                             double* pcptd, const double* w, double* ptd, int64_t n, int64_t m,

@@ -200,6 +200,7 @@ __device__ __forceinline__ void load_rows(const TC* __restrict__ C, int64_t ldc,
 template <int PREC, typename TC, int NR, int NC, int MODE2, bool VEC, int RS>
 __global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs A)
 {
+    if (A.skip && *A.skip) return;             // uniform: a finished CG chunk
     constexpr bool MIXED = PREC == EOT_PREC_MIXED;
     constexpr int RB = kTileRows, NCH = kChunks, V = kVec, T = kPassThreads;
     static_assert(NCH == 2, "the double buffer alternates the two column chunks");
@@ -680,7 +681,11 @@ __global__ void k_cg_init(const double* b, const double* rP, const double* s, do
     }
 }
 
-__global__ void k_cg_init_finish(const double* red, int nb, CgScalars* sc)
+// The CG iteration kernels below all return at once when sc->done is set
+// (converged, broke down or out of iterations), so the host can enqueue a
+// chunk of iterations without waiting for each convergence test.
+__global__ void k_cg_init_finish(const double* red, int nb, CgScalars* sc, double tol,
+                                 int32_t max_iter)
 {
     __shared__ double s_w[kVecThreads / 64];
     const double rz = sum_partials(red, nb, s_w);
@@ -692,12 +697,18 @@ __global__ void k_cg_init_finish(const double* red, int nb, CgScalars* sc)
         sc->alpha = 0.0;
         sc->beta = 0.0;
         sc->pq = 0.0;
+        sc->tol = tol;
+        sc->iters = 0;
+        sc->broke = 0;
+        sc->max_iter = max_iter;
+        sc->done = (l1 <= tol || max_iter <= 0) ? 1 : 0;
     }
 }
 
 __global__ void k_cg_colstep(const double* part, int tiles, int64_t m, const double* c, double* w,
-                             double* wc)
+                             double* wc, const CgScalars* sc)
 {
+    if (sc && sc->done) return;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m) return;
     const double s = sum_tiles(part, tiles, m, j);
@@ -707,13 +718,13 @@ __global__ void k_cg_colstep(const double* part, int tiles, int64_t m, const dou
 
 __global__ void k_cg_rowstep(const double* part, int tiles, int64_t n, const double* a,
                              const double* rP, const double* p, double rho, double* t, double* q,
-                             double* red)
+                             double* red, const CgScalars* sc)
 {
+    if (sc->done) return;
     __shared__ double s_w[kVecThreads / 64];
     double pq = 0.0;
     EW_LOOP(n) {
-        double s = 0.0;
-        for (int tt = 0; tt < tiles; ++tt) s += part[(int64_t)tt * n + i];
+        const double s = sum_tiles(part, tiles, n, i);
         const double ti = exp(a[i]) * s;
         const double qi = rP[i] * p[i] - rho * ti;
         t[i] = ti;
@@ -731,6 +742,7 @@ __global__ void k_cg_update(const double* red_pq, int nb_pq, double* d, double* 
                             double* pcptd, const double* w, double* ptd, int64_t n, int64_t m,
                             double* red, CgScalars* sc)
 {
+    if (sc->done) return;
     __shared__ double s_w[kVecThreads / 64];
     const double pq = sum_partials(red_pq, nb_pq, s_w);
     const double alpha = sc->rz / pq;
@@ -766,6 +778,7 @@ __global__ void k_cg_update(const double* red_pq, int nb_pq, double* d, double* 
 __global__ void k_cg_direction(const double* red, int nb, const double* z, double* p, int64_t n,
                                CgScalars* sc)
 {
+    if (sc->done) return;
     __shared__ double s_w[kVecThreads / 64];
     const double rz_new = sum_partials(red, nb, s_w);
     const double beta = rz_new / sc->rz;
@@ -776,13 +789,22 @@ __global__ void k_cg_direction(const double* red, int nb, const double* z, doubl
     }
 }
 
+// End of one CG iteration: ||res||_1, the iteration count and the stop test.
 __global__ void k_cg_tail(const double* red, int nb, CgScalars* sc)
 {
+    if (sc->done) return;
     __shared__ double s_w[kVecThreads / 64];
     const double l1 = sum_partials(red + nb, nb, s_w);
     if (threadIdx.x == 0) {
         sc->res_l1 = l1;
         sc->rz = sc->rz_new;
+        sc->iters += 1;
+        if (!(fabs(sc->alpha) < INFINITY) || !(sc->pq > 0.0)) {
+            sc->broke = 1;
+            sc->done = 1;
+        } else if (l1 <= sc->tol || sc->iters >= sc->max_iter) {
+            sc->done = 1;
+        }
     }
 }
 
@@ -1018,30 +1040,32 @@ hipError_t launch_div(const double* x, const double* y, double* out, double sign
 
 hipError_t launch_cg_init(const double* b, const double* rP, const double* s_, double rho, double* d,
                           double* res, double* z, double* p, double* M, double* ptd, double* pcptd,
-                          int64_t n, int64_t m, double* red, CgScalars* sc, hipStream_t s)
+                          int64_t n, int64_t m, double* red, CgScalars* sc, double tol,
+                          int32_t max_iter, hipStream_t s)
 {
     const int nb = vec_blocks(n > m ? n : m);
     hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(kVecThreads), 0, s, b, rP, s_, rho, d, res, z, p,
                        M, ptd, pcptd, n, m, red);
-    hipLaunchKernelGGL(k_cg_init_finish, dim3(1), dim3(kVecThreads), 0, s, red, nb, sc);
+    hipLaunchKernelGGL(k_cg_init_finish, dim3(1), dim3(kVecThreads), 0, s, red, nb, sc, tol,
+                       max_iter);
     return hipGetLastError();
 }
 
 hipError_t launch_cg_colstep(const double* part, int tiles, int64_t m, const double* c, double* w,
-                             double* wc, hipStream_t s)
+                             double* wc, const CgScalars* sc, hipStream_t s)
 {
     hipLaunchKernelGGL(k_cg_colstep, dim3(map_blocks(m)), dim3(kVecThreads), 0, s, part, tiles, m,
-                       c, w, wc);
+                       c, w, wc, sc);
     return hipGetLastError();
 }
 
 hipError_t launch_cg_rowstep(const double* part, int tiles, int64_t n, const double* a,
                              const double* rP, const double* p, double rho, double* t, double* q,
-                             double* red, int* nb, hipStream_t s)
+                             double* red, int* nb, const CgScalars* sc, hipStream_t s)
 {
     *nb = vec_blocks(n);
     hipLaunchKernelGGL(k_cg_rowstep, dim3(*nb), dim3(kVecThreads), 0, s, part, tiles, n, a, rP, p,
-                       rho, t, q, red);
+                       rho, t, q, red, sc);
     return hipGetLastError();
 }
 
