@@ -176,6 +176,8 @@ typedef struct {
     int32_t status;
     int32_t mdot_steps, newton_steps, cg_iters, backtracks, sinkhorn_iters, levels;
     int32_t forcing_misses, range_retries;
+    int32_t mixed_stalls;   /* mixed projections ended at the FP32 error floor (the last
+                               one is then finished in FP64 when verify_fp64 is set)   */
     int64_t passes_newton, passes_linesearch, passes_sinkhorn, passes_projection, passes_other;
     double final_gamma;
     double err_r, err_c;    /* L1 marginal errors vs the unsmoothed r, c, FP64 pass     */

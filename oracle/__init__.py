@@ -123,6 +123,19 @@ def beta_of(gamma):
 
 # ---------------------------------------------------------------- wrappers
 
+def sqeuclid_points_cost(X, Y, scale, block=1024):
+    """Dense FP64 cost of a point-cloud problem (Sec. 4.2, squared Euclidean
+    ground cost): C_ij = sum_k (x_ik - y_jk)^2 / scale, evaluated in the
+    difference form, row block by row block."""
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    C = np.empty((X.shape[0], Y.shape[0]))
+    for i0 in range(0, X.shape[0], block):
+        D = X[i0:i0 + block, None, :] - Y[None, :, :]
+        C[i0:i0 + block] = (D * D).sum(-1) / scale
+    return C
+
+
 def log_row_marginal(C, beta, u, v):
     C = _C(C); u = _d(u); v = _d(v)
     out = np.empty(C.shape[0])

@@ -82,6 +82,8 @@ struct Ctx {
     eot_cost cost{};
     int64_t n = 0, m = 0;
     int tiles_m = 0, tiles_n = 0;
+    int rtiles = 0, ctiles = 0;   // partials per row / column that the merges sum
+    int atomic = 0;               // outputs accumulated atomically (huge problems)
     hipStream_t s = nullptr;
     Scratch sc;
     double* tmp_n[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -95,8 +97,8 @@ struct Ctx {
 void carve(Arena& ar, Ctx& x, int op)
 {
     const int64_t n = x.n, m = x.m;
-    x.sc.row_part = ar.take<double>((size_t)2 * row_tiles(x.tiles_m) * n);
-    x.sc.col_part = ar.take<double>((size_t)2 * x.tiles_n * m);
+    x.sc.row_part = ar.take<double>((size_t)2 * x.rtiles * n);
+    x.sc.col_part = ar.take<double>((size_t)2 * x.ctiles * m);
     x.sc.red = ar.take<double>(2 * kMaxRedBlocks);
     x.sc.red2 = ar.take<double>(2 * kMaxRedBlocks);
     x.sc.scal = ar.take<double>(64);
@@ -129,8 +131,27 @@ eot_status check_cost(const eot_cost* c)
         if (!c->C || c->ldc < c->m) return EOT_ERR_INVALID_ARG;
         return EOT_OK;
     }
-    if (c->kind == EOT_COST_SQEUCLID_POINTS) return EOT_ERR_UNSUPPORTED;
+    if (c->kind == EOT_COST_SQEUCLID_POINTS) {
+        if (!c->X || !c->Y || !(c->scale > 0.0) || !std::isfinite(c->scale) || c->d < 1)
+            return EOT_ERR_INVALID_ARG;
+        if (c->d != 2 && c->d != 3) return EOT_ERR_UNSUPPORTED;
+        return EOT_OK;
+    }
     return EOT_ERR_INVALID_ARG;
+}
+
+// Tile layout of the passes: per-tile partial sums merged in a fixed order
+// (bit-reproducible) unless those buffers would exceed 512 MB, in which case
+// the pass accumulates into one row and one column vector with FP64 atomics.
+void layout(Ctx& x)
+{
+    x.tiles_m = (int)tiles_m_of(x.m);
+    x.tiles_n = (int)tiles_n_of(x.n);
+    const double part_bytes =
+        16.0 * ((double)row_tiles(x.tiles_m) * (double)x.n + (double)x.tiles_n * (double)x.m);
+    x.atomic = part_bytes > 512.0e6 ? 1 : 0;
+    x.rtiles = x.atomic ? 1 : row_tiles(x.tiles_m);
+    x.ctiles = x.atomic ? 1 : x.tiles_n;
 }
 
 eot_status setup(Ctx& x, const eot_cost* cost, int op, int prec, void* ws, size_t ws_bytes,
@@ -142,8 +163,7 @@ eot_status setup(Ctx& x, const eot_cost* cost, int op, int prec, void* ws, size_
     x.cost = *cost;
     x.n = cost->n;
     x.m = cost->m;
-    x.tiles_m = (int)tiles_m_of(x.m);
-    x.tiles_n = (int)tiles_n_of(x.n);
+    layout(x);
     x.s = static_cast<hipStream_t>(stream);
     Arena dry;
     carve(dry, x, op);
@@ -170,12 +190,33 @@ PassArgs make_args(const Ctx& x, const double* u, const double* a, const double*
     A.u = u;
     A.a = a;
     A.v = v;
-    A.beta = beta;
+    // points: C_ij = |x_i - y_j|^2 / scale; the kernels see |x_i - y_j|^2 and beta / scale
+    A.beta = x.cost.kind == EOT_COST_SQEUCLID_POINTS ? beta / x.cost.scale : beta;
+    A.X = x.cost.X;
+    A.Y = x.cost.Y;
+    A.d = x.cost.d;
     A.row_part = x.sc.row_part;
     A.col_part = x.sc.col_part;
     A.tiles_m = x.tiles_m;
     A.tiles_n = x.tiles_n;
+    A.atomic = x.atomic;
     return A;
+}
+
+// Launch one streaming pass; in atomic mode its outputs are cleared first.
+hipError_t run_pass(Ctx& x, const PassArgs& A, int prec, int nr, int nc, int mode2)
+{
+    if (x.atomic) {
+        if (nr > 0) {
+            hipError_t e = launch_fill(A.row_part, 0.0, (int64_t)nr * x.n, x.s);
+            if (e != hipSuccess) return e;
+        }
+        if (nc > 0) {
+            hipError_t e = launch_fill(A.col_part, 0.0, (int64_t)nc * x.m, x.s);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return launch_pass(A, prec, nr, nc, mode2, x.s);
 }
 
 // Read `k` device doubles back to the host (waits for the stream).
@@ -224,10 +265,10 @@ eot_status row_pass(Ctx& x, int prec, const double* u, const double* a, const do
     PassArgs A = make_args(x, u, a, v, beta);
     A.yw1 = inv_c;
     const int nr = inv_c ? 2 : 1;
-    HIPCHK(launch_pass(A, prec, nr, 0, R2_SQUARE, x.s));
-    HIPCHK(launch_log_row_from_sums(x.sc.row_part, row_tiles(x.tiles_m), x.n, a, log_rP, x.sc.flags, x.s));
+    HIPCHK(run_pass(x, A, prec, nr, 0, R2_SQUARE));
+    HIPCHK(launch_log_row_from_sums(x.sc.row_part, x.rtiles, x.n, a, log_rP, x.sc.flags, x.s));
     if (inv_c && s_out)
-        HIPCHK(launch_merge_rows(x.sc.row_part, row_tiles(x.tiles_m), x.n, 2, a, nullptr, s_out, 1, x.s));
+        HIPCHK(launch_merge_rows(x.sc.row_part, x.rtiles, x.n, 2, a, nullptr, s_out, 1, x.s));
     x.passes += 1;
     return EOT_OK;
 }
@@ -238,8 +279,8 @@ eot_status col_pass(Ctx& x, int prec, const double* u, const double* a, const do
 {
     PassArgs A = make_args(x, u, a, v, beta);
     A.xw0 = xw;
-    HIPCHK(launch_pass(A, prec, 0, 1, R2_WEIGHT, x.s));
-    HIPCHK(launch_merge_cols(x.sc.col_part, x.tiles_n, x.m, 1, colsum, nullptr, x.s));
+    HIPCHK(run_pass(x, A, prec, 0, 1, R2_WEIGHT));
+    HIPCHK(launch_merge_cols(x.sc.col_part, x.ctiles, x.m, 1, colsum, nullptr, x.s));
     x.passes += 1;
     return EOT_OK;
 }
@@ -250,8 +291,8 @@ eot_status rowsum_pass(Ctx& x, int prec, const double* u, const double* a, const
 {
     PassArgs A = make_args(x, u, a, v, beta);
     A.yw0 = yw;
-    HIPCHK(launch_pass(A, prec, 1, 0, R2_WEIGHT, x.s));
-    HIPCHK(launch_merge_rows(x.sc.row_part, row_tiles(x.tiles_m), x.n, 1, a, out, nullptr, 0, x.s));
+    HIPCHK(run_pass(x, A, prec, 1, 0, R2_WEIGHT));
+    HIPCHK(launch_merge_rows(x.sc.row_part, x.rtiles, x.n, 1, a, out, nullptr, 0, x.s));
     x.passes += 1;
     return EOT_OK;
 }
@@ -314,11 +355,11 @@ eot_status newton_solve(Ctx& x, int prec, const double* u, const double* v, doub
         int issued = 0, chunk = 4;
         for (;;) {
             for (int it = 0; it < chunk && issued < max_cg; ++it, ++issued) {
-                HIPCHK(launch_pass(pa, prec, 0, 1, R2_WEIGHT, x.s));
-                HIPCHK(launch_cg_colstep(x.sc.col_part, x.tiles_n, m, c, V.w, V.wc, x.sc.cg, x.s));
-                HIPCHK(launch_pass(pb, prec, 1, 0, R2_WEIGHT, x.s));
+                HIPCHK(run_pass(x, pa, prec, 0, 1, R2_WEIGHT));
+                HIPCHK(launch_cg_colstep(x.sc.col_part, x.ctiles, m, c, V.w, V.wc, x.sc.cg, x.s));
+                HIPCHK(run_pass(x, pb, prec, 1, 0, R2_WEIGHT));
                 int nb_pq = 0, nb = 0;
-                HIPCHK(launch_cg_rowstep(x.sc.row_part, row_tiles(x.tiles_m), n, lr, V.rP, V.p,
+                HIPCHK(launch_cg_rowstep(x.sc.row_part, x.rtiles, n, lr, V.rP, V.p,
                                          rho, V.t, V.q, x.sc.red2, &nb_pq, x.sc.cg, x.s));
                 HIPCHK(launch_cg_update(x.sc.red2, nb_pq, V.dtry, V.res, V.z, V.p, V.q, V.M, V.t,
                                         V.pcptd_try, V.w, V.ptd_try, n, m, x.sc.red, &nb,
@@ -404,8 +445,12 @@ eot_status refresh(Ctx& x, int prec, double beta, const double* shift_guess, Sol
 
 // TruncatedNewtonProject (Alg. 4) on the smoothed marginals held in S.rt,
 // S.ct (logs S.lrt, S.lct; S.inv_ct = 1 / ct).
+// Mixed precision (stall_exit): the FP32 plan entries put a floor under the
+// measured row error; when two Newton steps in a row fail to halve it (below
+// 1e-3), or the Newton cap is reached, the projection ends with *stalled set
+// instead of failing, and the caller continues in FP64.
 eot_status tnp(Ctx& x, int prec, double beta, double eps, double* rho0, double* delta_min,
-               SolveState& ss)
+               SolveState& ss, bool stall_exit = false, bool* stalled = nullptr)
 {
     SolveVecs& S = x.sv;
     const eot_solve_opts* o = ss.o;
@@ -419,11 +464,19 @@ eot_status tnp(Ctx& x, int prec, double beta, double eps, double* rho0, double* 
     double dmin = INFINITY;
     int32_t k = 0;
     eot_status status = EOT_OK;
+    double g_prev = INFINITY;
+    int slow = 0;
+    if (stalled) *stalled = false;
     for (;;) {
         double gn = 0.0;
         EOTCHK(reduce_host(x, RED_L1_DIFF_EXP, S.rt, S.lr, n, &gn));
         if (!std::isfinite(gn)) return EOT_ERR_NONFINITE;
         if (gn <= eps) break;                                              // L3
+        if (stall_exit) {
+            slow = (gn <= 1e-3 && gn > 0.5 * g_prev) ? slow + 1 : 0;
+            if (slow >= 2 || k >= o->max_newton) { *stalled = true; break; }
+        }
+        g_prev = gn;
         if (k >= o->max_newton) { status = EOT_ERR_NOT_CONVERGED; break; }
         // L4: ChiSinkhorn(eps^(2/5))
         const double eps_chi = std::pow(eps, 0.4);
@@ -500,10 +553,10 @@ eot_status report(Ctx& x, double beta, const double* r, const double* c, eot_sol
     SolveVecs& S = x.sv;
     EOTCHK(row_max(x, S.u, S.v, beta, S.sh));
     PassArgs A = make_args(x, S.u, S.sh, S.v, beta);
-    HIPCHK(launch_pass(A, EOT_PREC_FP64, 2, 1, R2_COST, x.s));
+    HIPCHK(run_pass(x, A, EOT_PREC_FP64, 2, 1, R2_COST));
     x.passes += 1;
-    HIPCHK(launch_merge_rows(x.sc.row_part, row_tiles(x.tiles_m), x.n, 2, S.sh, x.tmp_n[0], x.tmp_n[1], 0, x.s));
-    HIPCHK(launch_merge_cols(x.sc.col_part, x.tiles_n, x.m, 1, x.tmp_m[0], nullptr, x.s));
+    HIPCHK(launch_merge_rows(x.sc.row_part, x.rtiles, x.n, 2, S.sh, x.tmp_n[0], x.tmp_n[1], 0, x.s));
+    HIPCHK(launch_merge_cols(x.sc.col_part, x.ctiles, x.m, 1, x.tmp_m[0], nullptr, x.s));
     HIPCHK(launch_log(x.tmp_n[0], x.tmp_n[2], x.n, x.s));
     HIPCHK(launch_log(x.tmp_m[0], x.tmp_m[2], x.m, x.s));
     double er = 0, ec = 0, cost = 0, mass = 0, ur = 0, vc = 0;
@@ -515,7 +568,7 @@ eot_status report(Ctx& x, double beta, const double* r, const double* c, eot_sol
     EOTCHK(reduce_host(x, RED_DOT, S.v, c, x.m, &vc));
     st->err_r = er;
     st->err_c = ec;
-    st->cost = cost;
+    st->cost = x.cost.kind == EOT_COST_SQEUCLID_POINTS ? cost / x.cost.scale : cost;
     st->dual_value = (ur + vc - mass + 1.0) / beta;
     return EOT_OK;
 }
@@ -567,10 +620,15 @@ eot_status solve_impl(Ctx& x, const double* r, const double* c, const eot_solve_
             HIPCHK(launch_copy(S.lct, S.v_prev, m, x.s));
         }
         double dmin = INFINITY;                                            // L7
-        status = tnp(x, prec, beta, 0.5 * eps_d, &rho0, &dmin, ss);
-        if (status == EOT_OK && done && prec == EOT_PREC_MIXED && o->verify_fp64) {
+        const bool mixed = prec == EOT_PREC_MIXED;
+        bool stalled = false;
+        status = tnp(x, prec, beta, 0.5 * eps_d, &rho0, &dmin, ss, mixed, &stalled);
+        st->mixed_stalls += stalled ? 1 : 0;
+        if (status == EOT_OK && done && mixed && o->verify_fp64) {
             double dmin64 = INFINITY;
             status = tnp(x, EOT_PREC_FP64, beta, 0.5 * eps_d, &rho0, &dmin64, ss);
+        } else if (status == EOT_OK && done && stalled) {
+            status = EOT_ERR_NOT_CONVERGED;
         }
         st->delta_min_last = dmin;
         st->mdot_steps = t;
@@ -614,8 +672,7 @@ eot_status eot_workspace_size(int32_t op, const eot_cost* cost, int32_t prec, si
     Ctx x;
     x.n = cost->n;
     x.m = cost->m;
-    x.tiles_m = (int)tiles_m_of(x.m);
-    x.tiles_n = (int)tiles_n_of(x.n);
+    layout(x);
     Arena dry;
     carve(dry, x, op);
     *bytes = dry.off + kAlign;
@@ -647,10 +704,10 @@ eot_status eot_marginals(const eot_cost* cost, double gamma, const double* f, co
     if (s) HIPCHK(launch_recip(c_for_s, x.tmp_m[1], x.m, x.s));
     PassArgs A = make_args(x, u, a, v, beta);
     A.yw1 = s ? x.tmp_m[1] : nullptr;
-    HIPCHK(launch_pass(A, prec, nr, nc, R2_SQUARE, x.s));
+    HIPCHK(run_pass(x, A, prec, nr, nc, R2_SQUARE));
     if (rows) {
-        HIPCHK(launch_log_row_from_sums(x.sc.row_part, row_tiles(x.tiles_m), x.n, a, lr, x.sc.flags, x.s));
-        if (s) HIPCHK(launch_merge_rows(x.sc.row_part, row_tiles(x.tiles_m), x.n, 2, a, nullptr, s, 1, x.s));
+        HIPCHK(launch_log_row_from_sums(x.sc.row_part, x.rtiles, x.n, a, lr, x.sc.flags, x.s));
+        if (s) HIPCHK(launch_merge_rows(x.sc.row_part, x.rtiles, x.n, 2, a, nullptr, s, 1, x.s));
         if (mass) {
             int nb = 0;
             HIPCHK(launch_reduce(RED_SUM_EXP, nullptr, lr, x.n, x.sc.red, &nb, x.s));
@@ -658,7 +715,7 @@ eot_status eot_marginals(const eot_cost* cost, double gamma, const double* f, co
         }
     }
     if (log_cP) {
-        HIPCHK(launch_merge_cols(x.sc.col_part, x.tiles_n, x.m, 1, x.tmp_m[2], nullptr, x.s));
+        HIPCHK(launch_merge_cols(x.sc.col_part, x.ctiles, x.m, 1, x.tmp_m[2], nullptr, x.s));
         HIPCHK(launch_log(x.tmp_m[2], log_cP, x.m, x.s));
     }
     return EOT_OK;
@@ -689,8 +746,8 @@ eot_status eot_hvp(const eot_cost* cost, double gamma, const double* f, const do
     A.yw1 = yv;
     A.xw1 = xv;
     A.hvp_srho = srho;
-    HIPCHK(launch_pass(A, prec, 1, 1, R2_HVP, x.s));
-    HIPCHK(launch_hvp_finish(x.sc.row_part, row_tiles(x.tiles_m), x.sc.col_part, x.tiles_n, x.n, x.m, a, Hx,
+    HIPCHK(run_pass(x, A, prec, 1, 1, R2_HVP));
+    HIPCHK(launch_hvp_finish(x.sc.row_part, x.rtiles, x.sc.col_part, x.ctiles, x.n, x.m, a, Hx,
                              Hy, x.s));
     return EOT_OK;
 }

@@ -44,6 +44,11 @@ struct PassArgs {
     int32_t tiles_m, tiles_n;
     double hvp_srho;       // sqrt(rho) for R2_HVP
     const int32_t* skip;   // nullable device flag: the whole pass is skipped when set
+    const float* X;        // points: n x d
+    const float* Y;        // points: m x d
+    int32_t d;             // point dimension (2 or 3)
+    int32_t atomic;        // 1: row_part = [nr][n], col_part = [nc][m], pre-zeroed, atomically
+                           //    accumulated (problems whose per-tile partials would not fit)
 };
 
 inline int64_t tiles_m_of(int64_t m) { return (m + kTileCols - 1) / kTileCols; }

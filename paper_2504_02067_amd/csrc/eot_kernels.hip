@@ -38,6 +38,7 @@
 #include <math.h>
 
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "eot_internal.h"
@@ -170,7 +171,10 @@ __device__ __forceinline__ void wave_rows_out(double (&racc)[NR][RS], const doub
         if (i < n) {
             double fac = s_rf[sb + rr];
             if (k == 1 && MODE2 == R2_SQUARE) fac *= fac;
-            A.row_part[(((int64_t)k * A.tiles_m + blockIdx.x) * kWaves + wave) * n + i] = tot * fac;
+            if (A.atomic)
+                atomicAdd(&A.row_part[(int64_t)k * n + i], tot * fac);
+            else
+                A.row_part[(((int64_t)k * A.tiles_m + blockIdx.x) * kWaves + wave) * n + i] = tot * fac;
         }
     }
 }
@@ -194,10 +198,14 @@ __device__ __forceinline__ void load_rows(const TC* __restrict__ C, int64_t ldc,
 
 // ---------------------------------------------------------------- the pass
 // PREC = EOT_PREC_MIXED (FP32 exponent / exp, FP64 sums) or EOT_PREC_FP64.
-// RS rows are in flight per chunk; the next chunk's loads are issued before
-// the current chunk is computed (double buffer), and row partials are reduced
-// per wave in registers, so the loop has no workgroup barrier.
-template <int PREC, typename TC, int NR, int NC, int MODE2, bool VEC, int RS>
+// DP = 0: dense cost streamed from memory. RS rows are in flight per chunk;
+// the next chunk's loads are issued before the current chunk is computed
+// (double buffer), and row partials are reduced per wave in registers, so the
+// loop has no workgroup barrier.
+// DP > 0: C_ij = |x_i - y_j|^2 recomputed per entry in the difference form
+// (the O(n)-memory variant of Sec. 4.2): x rows in LDS, y columns in
+// registers; the 1/scale of the cost is folded into beta by the host.
+template <int PREC, typename TC, int NR, int NC, int MODE2, bool VEC, int RS, int DP>
 __global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs A)
 {
     if (A.skip && *A.skip) return;             // uniform: a finished CG chunk
@@ -213,6 +221,7 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs A)
     __shared__ double s_xw[2][RB];      // column-sum weights
     __shared__ double s_rr[RB];         // R_i = exp(a_i) 2^Ul (HVP)
     __shared__ double s_wmax[kWaves];
+    __shared__ float s_x[DP > 0 ? RB * DP : 1];   // point rows
 
     const int tid = threadIdx.x;
     const int64_t n = A.n, m = A.m;
@@ -299,6 +308,21 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs A)
             s_xw[0][tid] = 0.0;
             s_xw[1][tid] = 0.0;
         }
+        if constexpr (DP > 0) {
+#pragma unroll
+            for (int k = 0; k < DP; ++k) s_x[tid * DP + k] = rvalid ? A.X[irow * DP + k] : 0.0f;
+        }
+    }
+    float yr[DP > 0 ? NCH : 1][DP > 0 ? V : 1][DP > 0 ? DP : 1];
+    if constexpr (DP > 0) {
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                const int64_t j = j0 + (int64_t)ch * T * V + tid * V + q;
+#pragma unroll
+                for (int k = 0; k < DP; ++k) yr[ch][q][k] = (j < m) ? A.Y[j * DP + k] : 0.0f;
+            }
     }
     const double Bd = kLog2e * A.beta;
     const float Bh = (float)Bd;
@@ -330,11 +354,9 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs A)
     const int64_t rows = n - i0 < RB ? n - i0 : RB;
     const int nsb = (int)((rows + RS - 1) / RS);
     const int64_t jb0 = j0 + tid * V, jb1 = j0 + (int64_t)T * V + tid * V;
-    TC buf0[RS][V], buf1[RS][V];
-    load_rows<TC, VEC, RS>(C, A.ldc, i0, n, jb0, m, buf0);
 
-    auto compute = [&](int sb, int ch, TC (&buf)[RS][V], double (&racc)[NRA][RS]) {
-        const int64_t jb = ch == 0 ? jb0 : jb1;
+    // getc(rr, q) -> cost entry (FP32 in mixed mode, FP64 otherwise)
+    auto compute = [&](int sb, int ch, auto&& getc, double (&racc)[NRA][RS]) {
 #pragma unroll
         for (int rr = 0; rr < RS; ++rr) {
             const double xw0 = s_xw[0][sb + rr];
@@ -343,15 +365,13 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs A)
             for (int q = 0; q < V; ++q) {
                 double e64, cd;
                 if constexpr (MIXED) {
-                    float c = (float)buf[rr][q];
-                    if (!full) c = (jb + q < m) ? c : 0.0f;
+                    const float c = getc(rr, q);
                     const float t = fmaf(-Bh, c, s_uh[sb + rr] + vh[ch][q]);
                     const float w = fmaf(-Bl, c, vl[ch][q]);
                     e64 = (double)__builtin_amdgcn_exp2f(t + w);
                     cd = (double)c;
                 } else {
-                    double c = (double)buf[rr][q];
-                    if (!full) c = (jb + q < m) ? c : 0.0;
+                    const double c = getc(rr, q);
                     e64 = exp(fma(-beta, c, s_A[sb + rr] + vc[ch][q]));
                     cd = c;
                 }
@@ -375,18 +395,63 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs A)
         }
     };
 
-    for (int b = 0; b < nsb; ++b) {
-        const int sb = b * RS;
-        double racc[NRA][RS];
+    if constexpr (DP == 0) {
+        TC buf0[RS][V], buf1[RS][V];
+        load_rows<TC, VEC, RS>(C, A.ldc, i0, n, jb0, m, buf0);
+        auto dense = [&](TC (&buf)[RS][V], int64_t jb) {
+            return [&buf, jb, full, m](int rr, int q) {
+                using E = typename std::conditional<MIXED, float, double>::type;
+                E c = (E)buf[rr][q];
+                if (!full) c = (jb + q < m) ? c : (E)0;
+                return c;
+            };
+        };
+        for (int b = 0; b < nsb; ++b) {
+            const int sb = b * RS;
+            double racc[NRA][RS];
 #pragma unroll
-        for (int k = 0; k < NRA; ++k)
+            for (int k = 0; k < NRA; ++k)
 #pragma unroll
-            for (int rr = 0; rr < RS; ++rr) racc[k][rr] = 0.0;
-        load_rows<TC, VEC, RS>(C, A.ldc, i0 + sb, n, jb1, m, buf1);
-        compute(sb, 0, buf0, racc);
-        if (b + 1 < nsb) load_rows<TC, VEC, RS>(C, A.ldc, i0 + sb + RS, n, jb0, m, buf0);
-        compute(sb, 1, buf1, racc);
-        if constexpr (NR > 0) wave_rows_out<NR, RS, MODE2>(racc, s_rf, sb, i0, n, A);
+                for (int rr = 0; rr < RS; ++rr) racc[k][rr] = 0.0;
+            load_rows<TC, VEC, RS>(C, A.ldc, i0 + sb, n, jb1, m, buf1);
+            compute(sb, 0, dense(buf0, jb0), racc);
+            if (b + 1 < nsb) load_rows<TC, VEC, RS>(C, A.ldc, i0 + sb + RS, n, jb0, m, buf0);
+            compute(sb, 1, dense(buf1, jb1), racc);
+            if constexpr (NR > 0) wave_rows_out<NR, RS, MODE2>(racc, s_rf, sb, i0, n, A);
+        }
+    } else {
+        auto pts = [&](int sb, int ch) {
+            return [&, sb, ch](int rr, int q) {
+                if constexpr (MIXED) {
+                    float d2 = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < DP; ++k) {
+                        const float df = s_x[(sb + rr) * DP + k] - yr[ch][q][k];
+                        d2 = fmaf(df, df, d2);
+                    }
+                    return d2;
+                } else {
+                    double d2 = 0.0;
+#pragma unroll
+                    for (int k = 0; k < DP; ++k) {
+                        const double df = (double)s_x[(sb + rr) * DP + k] - (double)yr[ch][q][k];
+                        d2 = fma(df, df, d2);
+                    }
+                    return d2;
+                }
+            };
+        };
+        for (int b = 0; b < nsb; ++b) {
+            const int sb = b * RS;
+            double racc[NRA][RS];
+#pragma unroll
+            for (int k = 0; k < NRA; ++k)
+#pragma unroll
+                for (int rr = 0; rr < RS; ++rr) racc[k][rr] = 0.0;
+            compute(sb, 0, pts(sb, 0), racc);
+            compute(sb, 1, pts(sb, 1), racc);
+            if constexpr (NR > 0) wave_rows_out<NR, RS, MODE2>(racc, s_rf, sb, i0, n, A);
+        }
     }
     if constexpr (NC > 0) {
 #pragma unroll
@@ -396,13 +461,32 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs A)
 #pragma unroll
                 for (int q = 0; q < V; ++q) {
                     const int64_t j = j0 + (int64_t)ch * T * V + tid * V + q;
-                    if (j < m) A.col_part[((int64_t)k * A.tiles_n + blockIdx.y) * m + j] = cacc[k][ch][q];
+                    if (j < m) {
+                        if (A.atomic)
+                            atomicAdd(&A.col_part[(int64_t)k * m + j], cacc[k][ch][q]);
+                        else
+                            A.col_part[((int64_t)k * A.tiles_n + blockIdx.y) * m + j] = cacc[k][ch][q];
+                    }
                 }
     }
 }
 
-// Exact row maxima of u_i + v_j - beta C_ij, FP64; one partial per column tile.
-template <typename TC>
+// max via compare-and-swap on the bit pattern (values are never NaN here)
+__device__ __forceinline__ void atomic_max_f64(double* addr, double val)
+{
+    unsigned long long* a = reinterpret_cast<unsigned long long*>(addr);
+    unsigned long long old = *a;
+    while (__longlong_as_double((long long)old) < val) {
+        const unsigned long long assumed = old;
+        old = atomicCAS(a, assumed, (unsigned long long)__double_as_longlong(val));
+        if (old == assumed) break;
+    }
+}
+
+// Exact row maxima of u_i + v_j - beta C_ij, FP64; one partial per column tile,
+// or (A.atomic) an atomic max into part[0..n), pre-filled with -inf.
+// DP > 0: C_ij = |x_i - y_j|^2 (beta already divided by the cost scale).
+template <typename TC, int DP>
 __global__ __launch_bounds__(kPassThreads) void k_rowmax(PassArgs A, double* part)
 {
     constexpr int NCH = kChunks, V = kVec, T = kPassThreads;
@@ -421,7 +505,22 @@ __global__ __launch_bounds__(kPassThreads) void k_rowmax(PassArgs A, double* par
         for (int ch = 0; ch < NCH; ++ch) {
             const int64_t jb = j0 + (int64_t)ch * T * V + tid * V;
             double cv[V];
-            load_row_vec_d<TC>(C + i * A.ldc, jb, m, A.vec_ok != 0, cv);
+            if constexpr (DP == 0) {
+                load_row_vec_d<TC>(C + i * A.ldc, jb, m, A.vec_ok != 0, cv);
+            } else {
+#pragma unroll
+                for (int q = 0; q < V; ++q) {
+                    double d2 = 0.0;
+                    if (jb + q < m) {
+#pragma unroll
+                        for (int k = 0; k < DP; ++k) {
+                            const double df = (double)A.X[i * DP + k] - (double)A.Y[(jb + q) * DP + k];
+                            d2 = fma(df, df, d2);
+                        }
+                    }
+                    cv[q] = d2;
+                }
+            }
 #pragma unroll
             for (int q = 0; q < V; ++q)
                 if (jb + q < m) mx = fmax(mx, fma(-A.beta, cv[q], ui + A.v[jb + q]));
@@ -432,7 +531,10 @@ __global__ __launch_bounds__(kPassThreads) void k_rowmax(PassArgs A, double* par
         if (tid == 0) {
             double r = s_w[0];
             for (int w = 1; w < kWaves; ++w) r = fmax(r, s_w[w]);
-            part[(int64_t)blockIdx.x * n + i] = r;
+            if (A.atomic)
+                atomic_max_f64(&part[i], r);
+            else
+                part[(int64_t)blockIdx.x * n + i] = r;
         }
         __syncthreads();
     }
@@ -822,20 +924,20 @@ inline int map_blocks(int64_t k)
     return (int)(b < 1 ? 1 : b);
 }
 
-template <typename TC, int NR, int NC, int MODE2, bool VEC>
+template <typename TC, int NR, int NC, int MODE2, bool VEC, int DP>
 hipError_t launch_pass_v(const PassArgs& a, int prec, hipStream_t s)
 {
     constexpr int RS = (MODE2 == R2_HVP || (NR > 0 && NC > 0)) ? 4 : kSubRows;
     dim3 grid((unsigned)a.tiles_m, (unsigned)a.tiles_n);
     if (prec == EOT_PREC_MIXED) {
         if constexpr (sizeof(TC) == 4) {
-            hipLaunchKernelGGL((k_pass<EOT_PREC_MIXED, TC, NR, NC, MODE2, VEC, RS>), grid,
+            hipLaunchKernelGGL((k_pass<EOT_PREC_MIXED, TC, NR, NC, MODE2, VEC, RS, DP>), grid,
                                dim3(kPassThreads), 0, s, a);
         } else {
             return hipErrorInvalidValue;
         }
     } else {
-        hipLaunchKernelGGL((k_pass<EOT_PREC_FP64, TC, NR, NC, MODE2, VEC, RS>), grid,
+        hipLaunchKernelGGL((k_pass<EOT_PREC_FP64, TC, NR, NC, MODE2, VEC, RS, DP>), grid,
                            dim3(kPassThreads), 0, s, a);
     }
     return hipGetLastError();
@@ -844,8 +946,15 @@ hipError_t launch_pass_v(const PassArgs& a, int prec, hipStream_t s)
 template <typename TC, int NR, int NC, int MODE2>
 hipError_t launch_pass_t(const PassArgs& a, int prec, hipStream_t s)
 {
-    return a.vec_ok ? launch_pass_v<TC, NR, NC, MODE2, true>(a, prec, s)
-                    : launch_pass_v<TC, NR, NC, MODE2, false>(a, prec, s);
+    if (a.kind == EOT_COST_SQEUCLID_POINTS) {
+        if constexpr (sizeof(TC) == 4) {
+            if (a.d == 2) return launch_pass_v<TC, NR, NC, MODE2, true, 2>(a, prec, s);
+            if (a.d == 3) return launch_pass_v<TC, NR, NC, MODE2, true, 3>(a, prec, s);
+        }
+        return hipErrorInvalidValue;
+    }
+    return a.vec_ok ? launch_pass_v<TC, NR, NC, MODE2, true, 0>(a, prec, s)
+                    : launch_pass_v<TC, NR, NC, MODE2, false, 0>(a, prec, s);
 }
 
 template <typename TC>
@@ -919,7 +1028,8 @@ hipError_t read_pass_timing(int nr, int nc, int prec, int hvp, int64_t* launches
 hipError_t launch_pass(const PassArgs& a, int prec, int nr, int nc, int mode2, hipStream_t s)
 {
     auto go = [&]() -> hipError_t {
-        if (a.kind == EOT_COST_DENSE_F32) return dispatch_pass<float>(a, prec, nr, nc, mode2, s);
+        if (a.kind == EOT_COST_DENSE_F32 || a.kind == EOT_COST_SQEUCLID_POINTS)
+            return dispatch_pass<float>(a, prec, nr, nc, mode2, s);
         if (a.kind == EOT_COST_DENSE_F64) return dispatch_pass<double>(a, prec, nr, nc, mode2, s);
         return hipErrorInvalidValue;
     };
@@ -946,14 +1056,24 @@ hipError_t launch_pass(const PassArgs& a, int prec, int nr, int nc, int mode2, h
 hipError_t launch_rowmax(const PassArgs& a, double* part, double* out, hipStream_t s)
 {
     dim3 grid((unsigned)a.tiles_m, (unsigned)a.tiles_n);
+    if (a.atomic) {
+        hipLaunchKernelGGL(k_fill, dim3(vec_blocks(a.n)), dim3(kVecThreads), 0, s, out,
+                           -INFINITY, a.n);
+        part = out;
+    }
     if (a.kind == EOT_COST_DENSE_F32)
-        hipLaunchKernelGGL(k_rowmax<float>, grid, dim3(kPassThreads), 0, s, a, part);
+        hipLaunchKernelGGL((k_rowmax<float, 0>), grid, dim3(kPassThreads), 0, s, a, part);
     else if (a.kind == EOT_COST_DENSE_F64)
-        hipLaunchKernelGGL(k_rowmax<double>, grid, dim3(kPassThreads), 0, s, a, part);
+        hipLaunchKernelGGL((k_rowmax<double, 0>), grid, dim3(kPassThreads), 0, s, a, part);
+    else if (a.kind == EOT_COST_SQEUCLID_POINTS && a.d == 2)
+        hipLaunchKernelGGL((k_rowmax<float, 2>), grid, dim3(kPassThreads), 0, s, a, part);
+    else if (a.kind == EOT_COST_SQEUCLID_POINTS && a.d == 3)
+        hipLaunchKernelGGL((k_rowmax<float, 3>), grid, dim3(kPassThreads), 0, s, a, part);
     else
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_merge_max, dim3(map_blocks(a.n)), dim3(kVecThreads), 0, s, part,
-                       a.tiles_m, a.n, out);
+    if (!a.atomic)
+        hipLaunchKernelGGL(k_merge_max, dim3(map_blocks(a.n)), dim3(kVecThreads), 0, s, part,
+                           a.tiles_m, a.n, out);
     return hipGetLastError();
 }
 

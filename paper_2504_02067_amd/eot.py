@@ -62,7 +62,7 @@ class eot_solve_stats(ctypes.Structure):
     _fields_ = [("status", _c_i32), ("mdot_steps", _c_i32), ("newton_steps", _c_i32),
                 ("cg_iters", _c_i32), ("backtracks", _c_i32), ("sinkhorn_iters", _c_i32),
                 ("levels", _c_i32), ("forcing_misses", _c_i32), ("range_retries", _c_i32),
-                ("passes_newton", _c_i64), ("passes_linesearch", _c_i64),
+                ("mixed_stalls", _c_i32), ("passes_newton", _c_i64), ("passes_linesearch", _c_i64),
                 ("passes_sinkhorn", _c_i64), ("passes_projection", _c_i64),
                 ("passes_other", _c_i64), ("final_gamma", _c_f64), ("err_r", _c_f64),
                 ("err_c", _c_f64), ("cost", _c_f64), ("dual_value", _c_f64),
@@ -144,9 +144,31 @@ def _vec(t: Optional[torch.Tensor], k: int, name: str, optional: bool = False):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def make_cost(C: torch.Tensor) -> eot_cost:
-    """Dense cost descriptor for a 2-D float32 / float64 GPU tensor (row stride
-    >= columns, unit column stride)."""
+class PointCloud:
+    """Squared-Euclidean cost between point clouds, recomputed inside every pass:
+    C_ij = |X_i - Y_j|^2 / scale with X (n x d) and Y (m x d) float32 GPU
+    tensors, d in {2, 3}. The n x m matrix is never stored."""
+
+    def __init__(self, X: torch.Tensor, Y: torch.Tensor, scale: float):
+        for name, T in (("X", X), ("Y", Y)):
+            if not T.is_cuda or T.dim() != 2 or T.dtype != torch.float32 or not T.is_contiguous():
+                raise ValueError(f"{name}: need a contiguous 2-D float32 GPU tensor")
+        if X.shape[1] != Y.shape[1] or X.shape[1] not in (2, 3):
+            raise ValueError("X and Y need the same dimension d in {2, 3}")
+        if not scale > 0:
+            raise ValueError("scale must be positive")
+        self.X, self.Y, self.scale = X, Y, float(scale)
+        self.device = X.device
+        self.shape = (X.shape[0], Y.shape[0])
+
+
+def make_cost(C) -> eot_cost:
+    """Cost descriptor: a 2-D float32 / float64 GPU tensor (row stride >= columns,
+    unit column stride) or a PointCloud."""
+    if isinstance(C, PointCloud):
+        return eot_cost(kind=EOT_COST_SQEUCLID_POINTS, d=C.X.shape[1], n=C.shape[0],
+                        m=C.shape[1], ldc=0, C=None, X=ctypes.c_void_p(C.X.data_ptr()),
+                        Y=ctypes.c_void_p(C.Y.data_ptr()), scale=C.scale)
     if not C.is_cuda or C.dim() != 2 or C.stride(1) != 1 or C.stride(0) < C.shape[1]:
         raise ValueError("C: need a 2-D GPU tensor with unit column stride")
     if C.dtype == torch.float32:

@@ -210,17 +210,29 @@ def gmm_points(rng: np.random.Generator, n: int, k: int = 8, d: int = 3) -> np.n
     return pts.astype(np.float32)
 
 
-def point_cloud_problem(n: int = 1 << 20, seed: int = 5000) -> Problem:
-    """Two 8-component Gaussian mixtures in R^3, uniform marginals, cost
-    recomputed on the fly as |x - y|^2 / s with s the exact maximum."""
+def bbox_scale(X: np.ndarray, Y: np.ndarray) -> float:
+    """Squared diagonal of the box holding both clouds: an upper bound of every
+    |x - y|^2, so C = |x - y|^2 / scale lies in [0, 1] (the exact maximum
+    would cost an n x m sweep)."""
+    Z = np.concatenate([np.asarray(X, np.float64), np.asarray(Y, np.float64)])
+    ext = Z.max(0) - Z.min(0)
+    return float((ext * ext).sum())
+
+
+def point_cloud_problem(n: int = 1 << 20, seed: int = 5000, m: Optional[int] = None,
+                        d: int = 3) -> Problem:
+    """Two 8-component Gaussian mixtures in R^d (m points in the second),
+    uniform marginals, cost recomputed on the fly as |x - y|^2 / s with s the
+    squared bounding-box diagonal (:func:`bbox_scale`)."""
+    m = n if m is None else m
     rng = np.random.default_rng(seed)
-    X = gmm_points(rng, n)
-    Y = gmm_points(rng, n)
+    X = gmm_points(rng, n, d=d)
+    Y = gmm_points(rng, m, d=d)
     r = np.full(n, 1.0 / n)
-    c = np.full(n, 1.0 / n)
-    return Problem(name=f"gmm3d_n{n}_s{seed}", n=n, m=n, r=r, c=c, X=X, Y=Y,
-                   scale=float("nan"), gamma_init=1.0 / 32.0, gamma_final=1e-4,
-                   tol=1e-4, meta={"seed": seed, "cost": "sqeuclid_points"})
+    c = np.full(m, 1.0 / m)
+    return Problem(name=f"gmm{d}d_n{n}_m{m}_s{seed}", n=n, m=m, r=r, c=c, X=X, Y=Y,
+                   scale=bbox_scale(X, Y), gamma_init=1.0 / 32.0, gamma_final=1e-4,
+                   tol=1e-4, meta={"seed": seed, "cost": "sqeuclid_points", "d": d})
 
 
 def random_potentials(rng: np.random.Generator, n: int, m: int, gamma: float,

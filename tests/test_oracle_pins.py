@@ -495,3 +495,31 @@ def test_appendix_c_worked_example():
     for ell in range(1, 6):
         w = w @ Prc
         assert np.abs(w).sum() == pytest.approx(g["decay_per_step"] ** ell * chi, rel=1e-6)
+
+
+def test_points_cost_reduces_to_integer_grid_cost():
+    # Sec. 4.2 ground cost on point clouds: for the integer grid positions the
+    # difference form is exact and must reproduce the integer grid distance
+    # dy^2 + dx^2 (computed here in integers) over 2 (side - 1)^2; the bounding
+    # box of the grid has exactly that squared diagonal.
+    from paper_2504_02067_amd import workloads as W
+    side = 9
+    P = W.grid_coords(side)
+    scale = W.bbox_scale(P, P)
+    assert scale == 2 * (side - 1) ** 2
+    C = O.sqeuclid_points_cost(P, P, scale, block=7)
+    iy, ix = np.divmod(np.arange(side * side), side)
+    D = (iy[:, None] - iy[None, :]) ** 2 + (ix[:, None] - ix[None, :]) ** 2
+    assert np.array_equal(C, D / scale)
+    # ragged clouds of different sizes in R^3: translation invariance and the
+    # bound C <= 1 of the bounding-box scale
+    rng = np.random.default_rng(4)
+    X = rng.integers(-50, 50, size=(13, 3)).astype(np.float64)
+    Y = rng.integers(-50, 50, size=(29, 3)).astype(np.float64)
+    s = W.bbox_scale(X, Y)
+    C1 = O.sqeuclid_points_cost(X, Y, s, block=5)
+    C2 = O.sqeuclid_points_cost(X + 17.0, Y + 17.0, s)
+    assert np.array_equal(C1, C2) and C1.max() <= 1.0
+    # one brute-force entry
+    i, j = 3, 11
+    assert C1[i, j] == sum(int(X[i, k] - Y[j, k]) ** 2 for k in range(3)) / s
