@@ -72,6 +72,75 @@ def cpu_baseline(p, C_rows_fn, budget_s=10.0):
                       f"{os.environ.get('OMP_NUM_THREADS', cores)}"}
 
 
+def valu_cycles_points_hvp(d):
+    """VALU issue cycles per plan element of the mixed point-cloud HVP pass
+    (one lane): d subtractions and d multiply-adds for |x - y|^2, the exponent
+    (row + column hi parts, two multiply-adds, one add), exp2 at quarter rate
+    (4), the FP32 -> FP64 conversion, and four FP64 multiply-adds for the row
+    and column accumulations."""
+    return 2 * d + 4 + 4 + 1 + 4
+
+
+def points_measure(args, eot, W, dev, iters=4):
+    """Mixed HVP pass on the n = m = 2^20 Gaussian-mixture clouds in R^3 with
+    the cost recomputed on the fly (1.1e12 plan elements per pass)."""
+    import torch
+    p = W.point_cloud_problem()
+    n, m = p.n, p.m
+    pc = eot.PointCloud(torch.from_numpy(p.X).to(dev), torch.from_numpy(p.Y).to(dev), p.scale)
+    gamma = 1e-2
+    rng = np.random.default_rng(1)
+    f = torch.from_numpy(gamma * (np.log(p.r) + 0.5 * rng.standard_normal(n))).to(dev)
+    g = torch.from_numpy(gamma * (np.log(p.c) + 0.5 * rng.standard_normal(m))).to(dev)
+    x = torch.from_numpy(rng.standard_normal(n)).to(dev)
+    y = torch.from_numpy(rng.standard_normal(m)).to(dev)
+    log(f"points: n = m = {n}, d = 3, row shift")
+    shift = eot.eot_marginals(pc, gamma, f, g, precision="mixed", want=("log_rP",))["log_rP"]
+    eot.eot_hvp(pc, gamma, f, g, 1.0, x, y, row_shift=shift, precision="mixed")
+    torch.cuda.synchronize()
+    eot.eot_pass_timing(True)
+    for _ in range(iters):
+        eot.eot_hvp(pc, gamma, f, g, 1.0, x, y, row_shift=shift, precision="mixed")
+    torch.cuda.synchronize()
+    k, ms = eot.eot_pass_timing_read(fused_hvp=1, precision="mixed")
+    eot.eot_pass_timing(False)
+    sec = ms / 1e3 / k
+    elems = float(n) * float(m)
+    cyc = valu_cycles_points_hvp(3)
+    lane_rate = 256 * 4 * 16 * 2.4e9          # CUs x SIMDs x lanes x clock
+    peak_eps = lane_rate / cyc
+    log(f"points HVP {sec * 1e3:.1f} ms per pass, {elems / sec / 1e12:.3f} T elements/s")
+    return {"workload": f"gmm3d n=m={n} d=3 on-the-fly |x-y|^2/s, mixed HVP pass",
+            "kernel_ms": sec * 1e3, "elements_per_s": elems / sec,
+            "roofline": {"bound": "alu", "achieved": elems / sec / 1e12,
+                         "peak": peak_eps / 1e12, "unit": "T elements/s",
+                         "frac": elems / sec / peak_eps,
+                         "valu_cycles_per_element": cyc}}
+
+
+def kernels_only(args, eot, W, p, C, dev):
+    """The mixed HVP pass (as in the full run) and a 1 GiB device-to-device copy
+    whose fetched / written bytes calibrate the memory counters."""
+    import torch
+    n, m = p.n, p.m
+    gamma = p.gamma_final
+    rng = np.random.default_rng(1)
+    f = torch.from_numpy(gamma * (np.log(p.r) + 0.5 * rng.standard_normal(n))).to(dev)
+    g = torch.from_numpy(gamma * (np.log(p.c) + 0.5 * rng.standard_normal(m))).to(dev)
+    x = torch.from_numpy(rng.standard_normal(n)).to(dev)
+    y = torch.from_numpy(rng.standard_normal(m)).to(dev)
+    shift = eot.eot_marginals(C, gamma, f, g, precision="mixed", want=("log_rP",))["log_rP"]
+    for _ in range(args.hvp_iters):
+        eot.eot_hvp(C, gamma, f, g, 1.0, x, y, row_shift=shift, precision="mixed")
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(args.hvp_iters):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "kernels-only", "hvp_launches": args.hvp_iters,
+                      "copy_bytes": 4 * src.numel(), "copy_launches": args.hvp_iters}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +150,9 @@ def main():
     ap.add_argument("--seed", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-points", action="store_true")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only the HVP kernel loop and a 1 GiB device copy (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); this build has no "
@@ -100,6 +172,10 @@ def main():
     c = torch.from_numpy(p.c).to(dev)
     torch.cuda.synchronize()
     cost_bytes = 4.0 * n * m
+
+    if args.kernels_only:
+        kernels_only(args, eot, W, p, C, dev)
+        return
 
     def solve(prec):
         o = eot.default_solve_opts(gamma_init=p.gamma_init, gamma_final=p.gamma_final,
@@ -203,6 +279,12 @@ def main():
             f"row {kern[f'rowpass_{prec}']['kernel_us']:.1f} us (kernel only)")
     hvp = kern["hvp_mixed"]
 
+    pts = None
+    if not args.no_points:
+        del C
+        torch.cuda.empty_cache()
+        pts = points_measure(args, eot, W, dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("CPU baseline (oracle)")
@@ -239,6 +321,7 @@ def main():
                         "fp64_newton_steps": fp64["newton_steps"] if fp64 else None,
                         "fp64_cg_iters": fp64["cg_iters"] if fp64 else None},
         "kernels": kern,
+        "points": pts,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -88,7 +88,8 @@ typedef enum {
     EOT_OP_MARGINALS = 0,
     EOT_OP_HVP = 1,
     EOT_OP_NEWTON_CG = 2,
-    EOT_OP_SOLVE = 3
+    EOT_OP_SOLVE = 3,
+    EOT_OP_GRADIENT = 4
 } eot_op;
 
 /* Scratch bytes that `op` needs for `cost` in precision `prec`.
@@ -198,6 +199,48 @@ void eot_solve_opts_default(eot_solve_opts* opts);
 eot_status eot_solve(const eot_cost* cost, const double* r, const double* c,
                      const eot_solve_opts* opts, double* f, double* g,
                      eot_solve_stats* stats, void* ws, size_t ws_bytes, void* stream);
+
+/* Derivatives at potentials (f, g) of the entropic value
+ *   W = gamma (<u, r> + <v, c> - sum_ij P_ij + 1)      (u = f / gamma, v = g / gamma;
+ *                                                      the negated dual of Sec. 2)
+ * and of the sharp transport cost S = <P, C>, combined with the weights w_W and
+ * w_S (a vector-Jacobian product; pass the upstream gradients of W and S).
+ * With G = w_W dW/dC + w_S dS/dC:
+ *   dW/dC = P, dW/dr = f, dW/dc = g               (envelope theorem, at the optimum);
+ *   dS/dC_ij = P_ij (1 + (lam_i + mu_j - C_ij) / gamma), dS/dr = lam, dS/dc = mu,
+ * where [lam; mu] solves H [lam; mu] = [(P o C) 1; (P o C)^T 1] with H the dual
+ * Hessian [[D(r(P)), P], [P^T, D(c(P))]] (Sec. 2; implicit differentiation of
+ * r(P) = r, c(P) = c). The system is solved through its row Schur complement
+ * F_r(1) lam = (P o C) 1 - P D(c(P))^-1 (P o C)^T 1 by the preconditioned CG of
+ * Alg. 2 at rho = 1, then mu = ((P o C)^T 1 - P^T lam) / c(P); skipped when
+ * w_S = 0.
+ * Outputs (device, all nullable, FP64):
+ *   grad_C: dense costs only, n x m row-major with leading dimension ldg >= m,
+ *           G itself;
+ *   grad_X, grad_Y: point clouds only, n x d and m x d row-major,
+ *           (2/s) (x_i sum_j G_ij - sum_j G_ij y_j) and the transpose analogue;
+ *   grad_r, grad_c: w_W f + w_S lam and w_W g + w_S mu with their means removed
+ *           (r and c live on the simplex; the constant part is not defined).
+ * `info` (host, required): in tol (CG stop: L1 residual <= tol * L1 of the
+ * right-hand side; FP64 1e-11 reaches ~1e-10 relative accuracy, mixed needs
+ * >= 1e-5) and max_cg; out cg_iters, the relative residual reached, and S.
+ * prec selects the CG passes' precision; the other passes are FP64.
+ * Returns EOT_ERR_NOT_CONVERGED (outputs written) when CG hits max_cg, and
+ * EOT_ERR_INVALID_ARG for grad_C with a point cloud or grad_X / grad_Y with a
+ * dense cost. Gradient atomics make the point-cloud outputs reproducible to
+ * rounding, not bitwise. */
+typedef struct {
+    double tol;              /* in  */
+    int32_t max_cg;          /* in  */
+    int32_t cg_iters;        /* out */
+    double cg_residual;      /* out */
+    double S;                /* out: <P, C> at (f, g) */
+} eot_grad_info;
+
+eot_status eot_gradient(const eot_cost* cost, double gamma, const double* f, const double* g,
+                        double w_W, double w_S, double* grad_C, int64_t ldg, double* grad_X,
+                        double* grad_Y, double* grad_r, double* grad_c, eot_grad_info* info,
+                        int32_t prec, void* ws, size_t ws_bytes, void* stream);
 
 /* Opt-in timing of the streaming passes (for benchmarks and profiling). While
  * enabled, every streaming-pass kernel the library launches is bracketed by two

@@ -78,6 +78,11 @@ struct SolveVecs {
     double *v, *ct, *lct, *inv_ct, *dv, *v_prev, *va, *colsum, *lca; // m
 };
 
+struct GradVecs {
+    double *u, *sh, *lr, *a, *s, *ra, *g0, *gy0, *gy1, *gy2;                  // n
+    double *v, *cP, *bv, *inv_c, *mu, *cb, *tm, *h0, *hy0, *hy1, *hy2;          // m
+};
+
 struct Ctx {
     eot_cost cost{};
     int64_t n = 0, m = 0;
@@ -90,6 +95,7 @@ struct Ctx {
     double* tmp_m[4] = {nullptr, nullptr, nullptr, nullptr};
     NewtonVecs nv{};
     SolveVecs sv{};
+    GradVecs gv{};
     int64_t passes = 0;
     int32_t range_retries = 0;
 };
@@ -106,7 +112,15 @@ void carve(Arena& ar, Ctx& x, int op)
     x.sc.cg = ar.take<CgScalars>(1);
     for (int k = 0; k < 4; ++k) x.tmp_n[k] = ar.take<double>(n);
     for (int k = 0; k < 4; ++k) x.tmp_m[k] = ar.take<double>(m);
-    if (op == EOT_OP_NEWTON_CG || op == EOT_OP_SOLVE) {
+    if (op == EOT_OP_GRADIENT) {
+        GradVecs& v = x.gv;
+        double** nvec[] = {&v.u, &v.sh, &v.lr, &v.a, &v.s, &v.ra, &v.g0, &v.gy0, &v.gy1, &v.gy2};
+        for (double** p : nvec) *p = ar.take<double>(n);
+        double** mvec[] = {&v.v, &v.cP, &v.bv, &v.inv_c, &v.mu, &v.cb, &v.tm, &v.h0, &v.hy0,
+                           &v.hy1, &v.hy2};
+        for (double** p : mvec) *p = ar.take<double>(m);
+    }
+    if (op == EOT_OP_NEWTON_CG || op == EOT_OP_SOLVE || op == EOT_OP_GRADIENT) {
         NewtonVecs& v = x.nv;
         double** nvec[] = {&v.rP, &v.grad, &v.b, &v.d, &v.e1, &v.dtry, &v.res, &v.z,
                            &v.p, &v.q, &v.t, &v.M, &v.pcptd_try, &v.pcptd};
@@ -305,6 +319,53 @@ struct NewtonResult {
     double forcing_ratio = 0.0;
 };
 
+// Preconditioned CG on F_r(rho) d = V.b (Alg. 2 inner loop) from d = 0, with
+// F_r(rho) p = r(P) o p - rho P ((P^T p) / c) and Jacobi preconditioner
+// M_i = r(P)_i - rho s_i; r(P) in V.rP, log r(P) in lr (also the row shift).
+// Solution in V.dtry (with P^T d in V.ptd_try and P (P^T d / c) in V.pcptd_try).
+// The iterations are enqueued in chunks without waiting: each kernel of an
+// iteration returns at once when the device flag sc.done is set (by the
+// iteration that met the stop test, broke down or reached max_cg), so the
+// host reads the scalars once per chunk.
+eot_status device_pcg(Ctx& x, int prec, const double* u, const double* lr, const double* v,
+                      double beta, const double* s, const double* c, double rho, double tol,
+                      int max_cg, CgScalars* out)
+{
+    NewtonVecs& V = x.nv;
+    const int64_t n = x.n, m = x.m;
+    HIPCHK(launch_cg_init(V.b, V.rP, s, rho, V.dtry, V.res, V.z, V.p, V.M, V.ptd_try,
+                          V.pcptd_try, n, m, x.sc.red, x.sc.cg, tol, max_cg, x.s));
+    PassArgs pa = make_args(x, u, lr, v, beta);        // pass A: column sums of P p
+    pa.xw0 = V.p;
+    pa.skip = &x.sc.cg->done;
+    PassArgs pb = make_args(x, u, lr, v, beta);        // pass B: row sums of P (w / c)
+    pb.yw0 = V.wc;
+    pb.skip = &x.sc.cg->done;
+    CgScalars h{};
+    int issued = 0, chunk = 4;
+    for (;;) {
+        for (int it = 0; it < chunk && issued < max_cg; ++it, ++issued) {
+            HIPCHK(run_pass(x, pa, prec, 0, 1, R2_WEIGHT));
+            HIPCHK(launch_cg_colstep(x.sc.col_part, x.ctiles, m, c, V.w, V.wc, x.sc.cg, x.s));
+            HIPCHK(run_pass(x, pb, prec, 1, 0, R2_WEIGHT));
+            int nb_pq = 0, nb = 0;
+            HIPCHK(launch_cg_rowstep(x.sc.row_part, x.rtiles, n, lr, V.rP, V.p, rho, V.t, V.q,
+                                     x.sc.red2, &nb_pq, x.sc.cg, x.s));
+            HIPCHK(launch_cg_update(x.sc.red2, nb_pq, V.dtry, V.res, V.z, V.p, V.q, V.M, V.t,
+                                    V.pcptd_try, V.w, V.ptd_try, n, m, x.sc.red, &nb, x.sc.cg,
+                                    x.s));
+            HIPCHK(launch_cg_direction(x.sc.red, nb, V.z, V.p, n, x.sc.cg, x.s));
+        }
+        EOTCHK(fetch(x, reinterpret_cast<const double*>(x.sc.cg), reinterpret_cast<double*>(&h),
+                     sizeof(CgScalars) / sizeof(double)));
+        if (h.done || issued >= max_cg) break;
+        chunk = std::min(2 * chunk, 32);
+    }
+    x.passes += 2 * (int64_t)h.iters;
+    *out = h;
+    return EOT_OK;
+}
+
 // Alg. 2 at (u, v) with c(P) = c: lr = log r(P) (also the row shift), s_i =
 // sum_j P_ij^2 / c_j. Writes d_u to du and d_v = -(P^T d_u) / c to dv.
 eot_status newton_solve(Ctx& x, int prec, const double* u, const double* v, double beta,
@@ -338,40 +399,9 @@ eot_status newton_solve(Ctx& x, int prec, const double* u, const double* v, doub
             ++lev;
             continue;
         }
-        // CG at this discount. The iterations are enqueued in chunks without
-        // waiting: each kernel of an iteration returns at once when the device
-        // flag sc.done is set (by the iteration that met the stop test, broke
-        // down or reached max_cg), so the host reads the scalars once per chunk.
         const double tol = 0.25 * eta * gnorm;
-        HIPCHK(launch_cg_init(V.b, V.rP, s, rho, V.dtry, V.res, V.z, V.p, V.M, V.ptd_try,
-                              V.pcptd_try, n, m, x.sc.red, x.sc.cg, tol, max_cg, x.s));
-        PassArgs pa = make_args(x, u, lr, v, beta);        // pass A: column sums of P p
-        pa.xw0 = V.p;
-        pa.skip = &x.sc.cg->done;
-        PassArgs pb = make_args(x, u, lr, v, beta);        // pass B: row sums of P (w / c)
-        pb.yw0 = V.wc;
-        pb.skip = &x.sc.cg->done;
         CgScalars h{};
-        int issued = 0, chunk = 4;
-        for (;;) {
-            for (int it = 0; it < chunk && issued < max_cg; ++it, ++issued) {
-                HIPCHK(run_pass(x, pa, prec, 0, 1, R2_WEIGHT));
-                HIPCHK(launch_cg_colstep(x.sc.col_part, x.ctiles, m, c, V.w, V.wc, x.sc.cg, x.s));
-                HIPCHK(run_pass(x, pb, prec, 1, 0, R2_WEIGHT));
-                int nb_pq = 0, nb = 0;
-                HIPCHK(launch_cg_rowstep(x.sc.row_part, x.rtiles, n, lr, V.rP, V.p,
-                                         rho, V.t, V.q, x.sc.red2, &nb_pq, x.sc.cg, x.s));
-                HIPCHK(launch_cg_update(x.sc.red2, nb_pq, V.dtry, V.res, V.z, V.p, V.q, V.M, V.t,
-                                        V.pcptd_try, V.w, V.ptd_try, n, m, x.sc.red, &nb,
-                                        x.sc.cg, x.s));
-                HIPCHK(launch_cg_direction(x.sc.red, nb, V.z, V.p, n, x.sc.cg, x.s));
-            }
-            EOTCHK(fetch(x, reinterpret_cast<const double*>(x.sc.cg),
-                         reinterpret_cast<double*>(&h), sizeof(CgScalars) / sizeof(double)));
-            if (h.done || issued >= max_cg) break;
-            chunk = std::min(2 * chunk, 32);
-        }
-        x.passes += 2 * (int64_t)h.iters;
+        EOTCHK(device_pcg(x, prec, u, lr, v, beta, s, c, rho, tol, max_cg, &h));
         cgk += h.iters;
         const bool conv = !h.broke && h.res_l1 <= tol;
         if (!conv) { miss = 1; break; }
@@ -658,6 +688,113 @@ eot_status solve_impl(Ctx& x, const double* r, const double* c, const eot_solve_
 
 bool bad_gamma(double gamma) { return !(gamma > 0.0) || !std::isfinite(gamma); }
 
+// ---------------------------------------------------------------- gradients
+// Derivatives of W and S at (f, g); see eot_gradient in eot.h for the
+// formulas. Every pass is FP64 except the CG passes (precision prec).
+eot_status gradient_impl(Ctx& x, double gamma, const double* f, const double* g, double w_W,
+                         double w_S, double* grad_C, int64_t ldg, double* grad_X, double* grad_Y,
+                         double* grad_r, double* grad_c, eot_grad_info* info, int prec)
+{
+    GradVecs& G = x.gv;
+    NewtonVecs& V = x.nv;
+    const int64_t n = x.n, m = x.m;
+    const double beta = 1.0 / gamma;
+    const bool pts = x.cost.kind == EOT_COST_SQEUCLID_POINTS;
+    const double cs = pts ? 1.0 / x.cost.scale : 1.0;     // cost sums see |x - y|^2
+    HIPCHK(launch_divs(f, gamma, G.u, n, x.s));
+    HIPCHK(launch_divs(g, gamma, G.v, m, x.s));
+    EOTCHK(row_max(x, G.u, G.v, beta, G.sh));
+    // r(P), (P o C) 1, c(P), (P o C)^T 1 in one pass
+    PassArgs A = make_args(x, G.u, G.sh, G.v, beta);
+    HIPCHK(run_pass(x, A, EOT_PREC_FP64, 2, 2, R2_COST));
+    x.passes += 1;
+    HIPCHK(launch_merge_rows(x.sc.row_part, x.rtiles, n, 2, G.sh, V.rP, G.a, 0, x.s));
+    HIPCHK(launch_merge_cols(x.sc.col_part, x.ctiles, m, 2, G.cP, G.bv, x.s));
+    if (pts) {
+        HIPCHK(launch_lincomb(G.a, n, cs, G.a, 0.0, nullptr, 0.0, x.s));
+        HIPCHK(launch_lincomb(G.bv, m, cs, G.bv, 0.0, nullptr, 0.0, x.s));
+    }
+    HIPCHK(launch_log(V.rP, G.lr, n, x.s));
+    double S = 0.0;
+    EOTCHK(reduce_host(x, RED_SUM, G.a, nullptr, n, &S));
+    eot_status status = EOT_OK;
+    info->cg_iters = 0;
+    info->cg_residual = 0.0;
+    const double* lam = nullptr;
+    const double* mu = nullptr;
+    if (w_S != 0.0) {
+        // s_i = sum_j P_ij^2 / c(P)_j and t = P (b / c(P)) in one row pass
+        HIPCHK(launch_recip(G.cP, G.inv_c, m, x.s));
+        HIPCHK(launch_div(G.bv, G.cP, G.tm, 1.0, m, x.s));
+        PassArgs B = make_args(x, G.u, G.lr, G.v, beta);
+        B.yw0 = G.tm;
+        B.yw1 = G.inv_c;
+        HIPCHK(run_pass(x, B, EOT_PREC_FP64, 2, 0, R2_SQUARE));
+        x.passes += 1;
+        HIPCHK(launch_merge_rows(x.sc.row_part, x.rtiles, n, 2, G.lr, V.grad, G.s, 1, x.s));
+        // F_r(1) lam = a - P D(c(P))^-1 b
+        HIPCHK(launch_lincomb(V.b, n, 1.0, G.a, -1.0, V.grad, 0.0, x.s));
+        double bnorm = 0.0;
+        EOTCHK(reduce_host(x, RED_L1, V.b, nullptr, n, &bnorm));
+        CgScalars h{};
+        if (bnorm > 0.0) {
+            EOTCHK(device_pcg(x, prec, G.u, G.lr, G.v, beta, G.s, G.cP, 1.0, info->tol * bnorm,
+                              info->max_cg, &h));
+            info->cg_iters = h.iters;
+            info->cg_residual = h.res_l1 / bnorm;
+            if (h.broke || !(h.res_l1 <= info->tol * bnorm)) status = EOT_ERR_NOT_CONVERGED;
+        } else {
+            HIPCHK(launch_fill(V.dtry, 0.0, n, x.s));
+        }
+        lam = V.dtry;
+        // mu = (b - P^T lam) / c(P)
+        EOTCHK(col_pass(x, EOT_PREC_FP64, G.u, G.lr, G.v, beta, lam, G.tm));
+        HIPCHK(launch_lincomb(G.mu, m, 1.0, G.bv, -1.0, G.tm, 0.0, x.s));
+        HIPCHK(launch_div(G.mu, G.cP, G.mu, 1.0, m, x.s));
+        mu = G.mu;
+    }
+    // G_ij = P_ij (ra_i + cb_j + kappa C_ij)
+    HIPCHK(launch_lincomb(G.ra, n, w_S * beta, lam, 0.0, nullptr, w_W + w_S, x.s));
+    HIPCHK(launch_lincomb(G.cb, m, w_S * beta, mu, 0.0, nullptr, 0.0, x.s));
+    const double kappa = -w_S * beta;
+    if (grad_C) HIPCHK(launch_plan_grad(A, G.ra, G.cb, kappa, grad_C, ldg, x.s));
+    const int d = x.cost.d;
+    if (grad_X) {
+        double* acc[4] = {G.g0, G.gy0, G.gy1, G.gy2};
+        for (double* p : acc) HIPCHK(launch_fill(p, 0.0, n, x.s));
+        HIPCHK(launch_points_grad_rows(x.cost.X, x.cost.Y, d, n, m, G.u, G.v, beta * cs, G.ra,
+                                       G.cb, kappa * cs, G.g0, G.gy0, G.gy1, G.gy2, x.s));
+        HIPCHK(launch_points_grad_finish(x.cost.X, n, d, 2.0 * cs, G.g0, G.gy0, G.gy1, G.gy2,
+                                         grad_X, x.s));
+        x.passes += 1;
+    }
+    if (grad_Y) {
+        double* acc[4] = {G.h0, G.hy0, G.hy1, G.hy2};
+        for (double* p : acc) HIPCHK(launch_fill(p, 0.0, m, x.s));
+        HIPCHK(launch_points_grad_rows(x.cost.Y, x.cost.X, d, m, n, G.v, G.u, beta * cs, G.cb,
+                                       G.ra, kappa * cs, G.h0, G.hy0, G.hy1, G.hy2, x.s));
+        HIPCHK(launch_points_grad_finish(x.cost.Y, m, d, 2.0 * cs, G.h0, G.hy0, G.hy1, G.hy2,
+                                         grad_Y, x.s));
+        x.passes += 1;
+    }
+    // marginal gradients, mean removed
+    if (grad_r) {
+        HIPCHK(launch_lincomb(grad_r, n, w_W, f, w_S, lam, 0.0, x.s));
+        double sum = 0.0;
+        EOTCHK(reduce_host(x, RED_SUM, grad_r, nullptr, n, &sum));
+        HIPCHK(launch_lincomb(grad_r, n, 1.0, grad_r, 0.0, nullptr, -sum / (double)n, x.s));
+    }
+    if (grad_c) {
+        HIPCHK(launch_lincomb(grad_c, m, w_W, g, w_S, mu, 0.0, x.s));
+        double sum = 0.0;
+        EOTCHK(reduce_host(x, RED_SUM, grad_c, nullptr, m, &sum));
+        HIPCHK(launch_lincomb(grad_c, m, 1.0, grad_c, 0.0, nullptr, -sum / (double)m, x.s));
+    }
+    HIPCHK(hipStreamSynchronize(x.s));
+    info->S = S;
+    return status;
+}
+
 }  // namespace
 
 extern "C" {
@@ -667,7 +804,7 @@ eot_status eot_workspace_size(int32_t op, const eot_cost* cost, int32_t prec, si
     if (!bytes) return EOT_ERR_INVALID_ARG;
     eot_status cs = check_cost(cost);
     if (cs != EOT_OK) return cs;
-    if (op < EOT_OP_MARGINALS || op > EOT_OP_SOLVE) return EOT_ERR_INVALID_ARG;
+    if (op < EOT_OP_MARGINALS || op > EOT_OP_GRADIENT) return EOT_ERR_INVALID_ARG;
     (void)prec;
     Ctx x;
     x.n = cost->n;
@@ -838,6 +975,24 @@ eot_status eot_solve(const eot_cost* cost, const double* r, const double* c,
     st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = st;
     return status;
+}
+
+eot_status eot_gradient(const eot_cost* cost, double gamma, const double* f, const double* g,
+                        double w_W, double w_S, double* grad_C, int64_t ldg, double* grad_X,
+                        double* grad_Y, double* grad_r, double* grad_c, eot_grad_info* info,
+                        int32_t prec, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!f || !g || !info || bad_gamma(gamma)) return EOT_ERR_INVALID_ARG;
+    if (!std::isfinite(w_W) || !std::isfinite(w_S)) return EOT_ERR_INVALID_ARG;
+    if (w_S != 0.0 && (!(info->tol > 0.0) || info->max_cg < 1)) return EOT_ERR_INVALID_ARG;
+    EOTCHK(check_cost(cost));
+    const bool pts = cost->kind == EOT_COST_SQEUCLID_POINTS;
+    if (grad_C && (pts || ldg < cost->m)) return EOT_ERR_INVALID_ARG;
+    if ((grad_X || grad_Y) && !pts) return EOT_ERR_INVALID_ARG;
+    Ctx x;
+    EOTCHK(setup(x, cost, EOT_OP_GRADIENT, prec, ws, ws_bytes, stream));
+    return gradient_impl(x, gamma, f, g, w_W, w_S, grad_C, ldg, grad_X, grad_Y, grad_r, grad_c,
+                         info, prec);
 }
 
 eot_status eot_pass_timing(int32_t enable)

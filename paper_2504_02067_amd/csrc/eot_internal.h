@@ -120,6 +120,23 @@ hipError_t launch_div(const double* x, const double* y, double* out, double sign
                       hipStream_t s);                                // out = sign * x / y
 hipError_t launch_copy(const double* x, double* y, int64_t k, hipStream_t s);
 hipError_t launch_fill(double* x, double val, int64_t k, hipStream_t s);
+// out = alpha x + beta y + c0 (x, y nullable)
+hipError_t launch_lincomb(double* out, int64_t k, double alpha, const double* x, double beta,
+                          const double* y, double c0, hipStream_t s);
+
+// Gradients. Dense cotangent G_ij = P_ij (ra_i + cb_j + kappa C_ij) into G (ldg).
+hipError_t launch_plan_grad(const PassArgs& a, const double* ra, const double* cb, double kappa,
+                            double* G, int64_t ldg, hipStream_t s);
+// Point clouds: g0_i += sum_j G_ij, gy[k]_i += sum_j G_ij y_jk with D_ij = |x_i - y_j|^2
+// (beta and kappa already divided by the cost scale); outputs pre-zeroed.
+hipError_t launch_points_grad_rows(const float* Xr, const float* Yc, int d, int64_t n, int64_t m,
+                                   const double* u, const double* v, double beta, const double* ra,
+                                   const double* cb, double kappa, double* g0, double* gy0,
+                                   double* gy1, double* gy2, hipStream_t s);
+// out_ik = two_over_s (x_ik g0_i - gy[k]_i), row-major n x d.
+hipError_t launch_points_grad_finish(const float* X, int64_t n, int d, double two_over_s,
+                                     const double* g0, const double* gy0, const double* gy1,
+                                     const double* gy2, double* out, hipStream_t s);
 
 // CG building blocks (state lives in device scalars `sc`).
 struct CgScalars {

@@ -388,7 +388,10 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs A)
                         racc[NR - 1][rr] = fma(term, ywr[NR - 1][ch][q], racc[NR - 1][rr]);
                     }
                     if constexpr (NC >= 1) cacc[0][ch][q] = fma(e64, xw0, cacc[0][ch][q]);
-                    if constexpr (NC >= 2) cacc[NC - 1][ch][q] = fma(e64, xw1, cacc[NC - 1][ch][q]);
+                    if constexpr (NC >= 2) {
+                        const double term = MODE2 == R2_COST ? e64 * cd : e64;
+                        cacc[NC - 1][ch][q] = fma(term, xw1, cacc[NC - 1][ch][q]);
+                    }
                 }
                 (void)cd;
             }
@@ -966,6 +969,7 @@ hipError_t dispatch_pass(const PassArgs& a, int prec, int nr, int nc, int mode2,
     if (nr == 2 && nc == 1 && mode2 == R2_SQUARE) return launch_pass_t<TC, 2, 1, R2_SQUARE>(a, prec, s);
     if (nr == 2 && nc == 2 && mode2 == R2_WEIGHT) return launch_pass_t<TC, 2, 2, R2_WEIGHT>(a, prec, s);
     if (nr == 2 && nc == 1 && mode2 == R2_COST) return launch_pass_t<TC, 2, 1, R2_COST>(a, prec, s);
+    if (nr == 2 && nc == 2 && mode2 == R2_COST) return launch_pass_t<TC, 2, 2, R2_COST>(a, prec, s);
     if (nr == 2 && nc == 0 && mode2 == R2_SQUARE) return launch_pass_t<TC, 2, 0, R2_SQUARE>(a, prec, s);
     if (nr == 2 && nc == 0 && mode2 == R2_COST) return launch_pass_t<TC, 2, 0, R2_COST>(a, prec, s);
     if (nr == 1 && nc == 0) return launch_pass_t<TC, 1, 0, R2_WEIGHT>(a, prec, s);
@@ -973,7 +977,188 @@ hipError_t dispatch_pass(const PassArgs& a, int prec, int nr, int nc, int mode2,
     return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------------------- gradients
+// Cotangent of a dense cost: G_ij = P_ij (ra_i + cb_j + kappa C_ij), FP64,
+// written row-major with leading dimension ldg. One thread: 4 consecutive
+// columns of kGradRows rows.
+constexpr int kGradRows = 16;
+
+template <typename TC>
+__global__ __launch_bounds__(256) void k_plan_grad(const TC* __restrict__ C, int64_t ldc, int64_t n,
+                                                   int64_t m, const double* __restrict__ u,
+                                                   const double* __restrict__ v, double beta,
+                                                   const double* __restrict__ ra,
+                                                   const double* __restrict__ cb, double kappa,
+                                                   double* __restrict__ G, int64_t ldg)
+{
+    const int64_t j0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    const int64_t i0 = (int64_t)blockIdx.y * kGradRows;
+    if (j0 >= m) return;
+    double vj[4], bj[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const bool ok = j0 + q < m;
+        vj[q] = ok ? v[j0 + q] : 0.0;
+        bj[q] = ok ? cb[j0 + q] : 0.0;
+    }
+    for (int r = 0; r < kGradRows; ++r) {
+        const int64_t i = i0 + r;
+        if (i >= n) break;
+        const double ui = u[i], ai = ra[i];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t j = j0 + q;
+            if (j < m) {
+                const double c = (double)C[i * ldc + j];
+                const double P = exp(fma(-beta, c, ui + vj[q]));
+                G[i * ldg + j] = P * fma(kappa, c, ai + bj[q]);
+            }
+        }
+    }
+}
+
+// Row sums of the point-cloud cotangent G_ij = P_ij (ra_i + cb_j + kappa D_ij)
+// with D_ij = |x_i - y_j|^2 (the cost scale folded into beta and kappa):
+// g0_i += sum_j G_ij and gy[k]_i += sum_j G_ij y_jk over this block's column
+// slice, FP64, accumulated atomically. One thread per row; the column slice is
+// staged through LDS 256 points at a time. Called once per side (rows = x with
+// columns = y, then rows = y with columns = x).
+template <int DP>
+__global__ __launch_bounds__(256) void k_points_grad_rows(
+    const float* __restrict__ Xr, const float* __restrict__ Yc, int64_t n, int64_t m,
+    const double* __restrict__ u, const double* __restrict__ v, double beta,
+    const double* __restrict__ ra, const double* __restrict__ cb, double kappa, int64_t slice,
+    double* g0, double* gy0, double* gy1, double* gy2)
+{
+    __shared__ double s_y[256][DP];
+    __shared__ double s_v[256], s_b[256];
+    const int tid = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+    const bool ok = i < n;
+    double xi[DP];
+#pragma unroll
+    for (int k = 0; k < DP; ++k) xi[k] = ok ? (double)Xr[i * DP + k] : 0.0;
+    const double ui = ok ? u[i] : 0.0, ai = ok ? ra[i] : 0.0;
+    double acc0 = 0.0, accy[DP];
+#pragma unroll
+    for (int k = 0; k < DP; ++k) accy[k] = 0.0;
+    const int64_t jb = (int64_t)blockIdx.y * slice;
+    const int64_t je = jb + slice < m ? jb + slice : m;
+    for (int64_t j0 = jb; j0 < je; j0 += 256) {
+        __syncthreads();
+        const int64_t j = j0 + tid;
+        const bool jok = j < je;
+#pragma unroll
+        for (int k = 0; k < DP; ++k) s_y[tid][k] = jok ? (double)Yc[j * DP + k] : 0.0;
+        s_v[tid] = jok ? v[j] : -INFINITY;
+        s_b[tid] = jok ? cb[j] : 0.0;
+        __syncthreads();
+        const int cnt = (int)(je - j0 < 256 ? je - j0 : 256);
+        for (int t = 0; t < cnt; ++t) {
+            double d2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < DP; ++k) {
+                const double df = xi[k] - s_y[t][k];
+                d2 = fma(df, df, d2);
+            }
+            const double P = exp(fma(-beta, d2, ui + s_v[t]));
+            const double Gv = P * fma(kappa, d2, ai + s_b[t]);
+            acc0 += Gv;
+#pragma unroll
+            for (int k = 0; k < DP; ++k) accy[k] = fma(Gv, s_y[t][k], accy[k]);
+        }
+    }
+    if (!ok) return;
+    atomicAdd(&g0[i], acc0);
+    atomicAdd(&gy0[i], accy[0]);
+    if constexpr (DP > 1) atomicAdd(&gy1[i], accy[1]);
+    if constexpr (DP > 2) atomicAdd(&gy2[i], accy[2]);
+}
+
+// grad_i,k = (2 / s) (x_ik g0_i - gy[k]_i), row-major n x d output.
+__global__ void k_points_grad_finish(const float* X, int64_t n, int d, double two_over_s,
+                                     const double* g0, const double* gy0, const double* gy1,
+                                     const double* gy2, double* out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double* gy[3] = {gy0, gy1, gy2};
+    for (int k = 0; k < d; ++k)
+        out[i * d + k] = two_over_s * ((double)X[i * d + k] * g0[i] - gy[k][i]);
+}
+
+// out = alpha x + beta y + c0 (x, y nullable)
+__global__ void k_lincomb(double* out, int64_t k, double alpha, const double* x, double beta,
+                          const double* y, double c0)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double t = c0;
+        if (x) t = fma(alpha, x[i], t);
+        if (y) t = fma(beta, y[i], t);
+        out[i] = t;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_plan_grad(const PassArgs& a, const double* ra, const double* cb, double kappa,
+                            double* G, int64_t ldg, hipStream_t s)
+{
+    dim3 grid((unsigned)((a.m + 1023) / 1024), (unsigned)((a.n + kGradRows - 1) / kGradRows));
+    if (a.kind == EOT_COST_DENSE_F32)
+        hipLaunchKernelGGL((k_plan_grad<float>), grid, dim3(256), 0, s,
+                           static_cast<const float*>(a.C), a.ldc, a.n, a.m, a.u, a.v, a.beta, ra,
+                           cb, kappa, G, ldg);
+    else if (a.kind == EOT_COST_DENSE_F64)
+        hipLaunchKernelGGL((k_plan_grad<double>), grid, dim3(256), 0, s,
+                           static_cast<const double*>(a.C), a.ldc, a.n, a.m, a.u, a.v, a.beta, ra,
+                           cb, kappa, G, ldg);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_points_grad_rows(const float* Xr, const float* Yc, int d, int64_t n, int64_t m,
+                                   const double* u, const double* v, double beta, const double* ra,
+                                   const double* cb, double kappa, double* g0, double* gy0,
+                                   double* gy1, double* gy2, hipStream_t s)
+{
+    const int64_t bx = (n + 255) / 256;
+    const int64_t col_blocks = (m + 255) / 256;
+    int64_t by = (4096 + bx - 1) / bx;                 // aim at >= 4096 workgroups
+    by = by < 1 ? 1 : (by > col_blocks ? col_blocks : by);
+    const int64_t slice = ((m + by - 1) / by + 255) / 256 * 256;
+    by = (m + slice - 1) / slice;
+    dim3 grid((unsigned)bx, (unsigned)by);
+    if (d == 2)
+        hipLaunchKernelGGL((k_points_grad_rows<2>), grid, dim3(256), 0, s, Xr, Yc, n, m, u, v,
+                           beta, ra, cb, kappa, slice, g0, gy0, gy1, gy2);
+    else if (d == 3)
+        hipLaunchKernelGGL((k_points_grad_rows<3>), grid, dim3(256), 0, s, Xr, Yc, n, m, u, v,
+                           beta, ra, cb, kappa, slice, g0, gy0, gy1, gy2);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_points_grad_finish(const float* X, int64_t n, int d, double two_over_s,
+                                     const double* g0, const double* gy0, const double* gy1,
+                                     const double* gy2, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_points_grad_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X,
+                       n, d, two_over_s, g0, gy0, gy1, gy2, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_lincomb(double* out, int64_t k, double alpha, const double* x, double beta,
+                          const double* y, double c0, hipStream_t s)
+{
+    const int64_t b = (k + 255) / 256;
+    hipLaunchKernelGGL(k_lincomb, dim3((unsigned)(b < 1024 ? b : 1024)), dim3(256), 0, s, out, k,
+                       alpha, x, beta, y, c0);
+    return hipGetLastError();
+}
 
 // ---------------------------------------------------------------- pass timer
 namespace {

@@ -35,6 +35,7 @@ EOT_OP_MARGINALS = 0
 EOT_OP_HVP = 1
 EOT_OP_NEWTON_CG = 2
 EOT_OP_SOLVE = 3
+EOT_OP_GRADIENT = 4
 
 _c_i32, _c_i64, _c_f64, _c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 
@@ -73,6 +74,11 @@ class eot_solve_stats(ctypes.Structure):
 
 
 # Every entry point declared in include/eot.h, with its ctypes signature.
+class eot_grad_info(ctypes.Structure):
+    _fields_ = [("tol", _c_f64), ("max_cg", _c_i32), ("cg_iters", _c_i32),
+                ("cg_residual", _c_f64), ("S", _c_f64)]
+
+
 SIGNATURES = {
     "eot_workspace_size": (_c_i32, [_c_i32, ctypes.POINTER(eot_cost), _c_i32,
                                     ctypes.POINTER(ctypes.c_size_t)]),
@@ -89,6 +95,10 @@ SIGNATURES = {
     "eot_solve": (_c_i32, [ctypes.POINTER(eot_cost), _c_vp, _c_vp,
                            ctypes.POINTER(eot_solve_opts), _c_vp, _c_vp,
                            ctypes.POINTER(eot_solve_stats), _c_vp, ctypes.c_size_t, _c_vp]),
+    "eot_gradient": (_c_i32, [ctypes.POINTER(eot_cost), _c_f64, _c_vp, _c_vp, _c_f64, _c_f64,
+                              _c_vp, _c_i64, _c_vp, _c_vp, _c_vp, _c_vp,
+                              ctypes.POINTER(eot_grad_info), _c_i32, _c_vp, ctypes.c_size_t,
+                              _c_vp]),
     "eot_pass_timing": (_c_i32, [_c_i32]),
     "eot_pass_timing_read": (_c_i32, [_c_i32, _c_i32, _c_i32, _c_i32, ctypes.POINTER(_c_i64),
                                       ctypes.POINTER(_c_f64)]),
@@ -302,6 +312,42 @@ def eot_solve(C, r, c, opts: Optional[eot_solve_opts] = None, allow_not_converge
     allow = (EOT_OK, EOT_ERR_NOT_CONVERGED) if allow_not_converged else (EOT_OK,)
     _check(st, "eot_solve", allow)
     return f, g, stats.as_dict()
+
+
+def eot_gradient(C, gamma, f, g, w_W=1.0, w_S=0.0, want=None, tol=1e-11, max_cg=5000,
+                 precision="fp64", allow_not_converged=False):
+    """Vector-Jacobian product of (W, S) at potentials (f, g) with weights
+    (w_W, w_S). ``want`` names the outputs among "C" (dense costs), "X", "Y"
+    (point clouds), "r", "c"; returns a dict of FP64 tensors plus "S",
+    "cg_iters" and "cg_residual"."""
+    cost = make_cost(C)
+    n, m = cost.n, cost.m
+    dev = C.device
+    pts = cost.kind == EOT_COST_SQEUCLID_POINTS
+    if want is None:
+        want = ("X", "Y", "r", "c") if pts else ("C", "r", "c")
+    d = cost.d
+    out = {}
+    out["C"] = torch.empty((n, m), dtype=torch.float64, device=dev) if "C" in want else None
+    out["X"] = torch.empty((n, d), dtype=torch.float64, device=dev) if "X" in want else None
+    out["Y"] = torch.empty((m, d), dtype=torch.float64, device=dev) if "Y" in want else None
+    out["r"] = torch.empty(n, dtype=torch.float64, device=dev) if "r" in want else None
+    out["c"] = torch.empty(m, dtype=torch.float64, device=dev) if "c" in want else None
+    info = eot_grad_info(tol=float(tol), max_cg=int(max_cg))
+    prec = _prec(precision)
+    ws = workspace(EOT_OP_GRADIENT, cost, prec, dev)
+
+    def ptr(t):
+        return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+    st = lib().eot_gradient(ctypes.byref(cost), float(gamma), _vec(f, n, "f"), _vec(g, m, "g"),
+                            float(w_W), float(w_S), ptr(out["C"]), m, ptr(out["X"]),
+                            ptr(out["Y"]), ptr(out["r"]), ptr(out["c"]), ctypes.byref(info),
+                            prec, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev))
+    allow = (EOT_OK, EOT_ERR_NOT_CONVERGED) if allow_not_converged else (EOT_OK,)
+    _check(st, "eot_gradient", allow)
+    out.update(S=info.S, cg_iters=info.cg_iters, cg_residual=info.cg_residual, status=st)
+    return out
 
 
 def eot_pass_timing(enable: bool) -> None:

@@ -66,7 +66,7 @@ def test_workspace_size_scales_and_validates(L):
     assert st == eot.EOT_OK and small > 0
     st, big = ws(eot.EOT_OP_SOLVE, 16384, 16384)
     assert st == eot.EOT_OK and big > 100 * small
-    for op in range(4):
+    for op in range(5):
         assert ws(op, 1, 1)[0] == eot.EOT_OK
     assert ws(eot.EOT_OP_SOLVE, 0, 5)[0] == eot.EOT_ERR_INVALID_ARG
     assert ws(7, 5, 5)[0] == eot.EOT_ERR_INVALID_ARG
@@ -121,6 +121,33 @@ def test_argument_validation_happens_before_any_device_work(L):
     o.gamma_final = 0.0
     assert L.eot_solve(ctypes.byref(c), p, p, ctypes.byref(o), p, p, ctypes.byref(st), p,
                        1 << 20, None) == eot.EOT_ERR_INVALID_ARG
+
+
+def test_gradient_and_points_validation(L):
+    from paper_2504_02067_amd import eot
+    p = ctypes.c_void_p(4096)
+    dense = eot.eot_cost(kind=0, d=0, n=8, m=8, ldc=8, C=p, X=None, Y=None, scale=0.0)
+    pts = eot.eot_cost(kind=2, d=3, n=8, m=8, ldc=0, C=None, X=p, Y=p, scale=2.0)
+    info = eot.eot_grad_info(tol=1e-10, max_cg=100)
+
+    def grad(cost, gC=None, ldg=8, gX=None, info_p=ctypes.byref(info), wS=1.0):
+        return L.eot_gradient(ctypes.byref(cost), 0.1, p, p, 1.0, wS, gC, ldg, gX, None, None,
+                              None, info_p, 0, p, 1 << 20, None)
+
+    assert grad(dense, info_p=None) == eot.EOT_ERR_INVALID_ARG
+    assert grad(pts, gC=p) == eot.EOT_ERR_INVALID_ARG            # no dense cotangent for points
+    assert grad(dense, gX=p) == eot.EOT_ERR_INVALID_ARG          # no point gradient for dense
+    assert grad(dense, gC=p, ldg=4) == eot.EOT_ERR_INVALID_ARG   # ldg < m
+    info.tol = 0.0
+    assert grad(dense) == eot.EOT_ERR_INVALID_ARG                # S needs a CG tolerance
+    # point clouds: d in {2, 3}, positive finite scale, non-null points
+    sz = ctypes.c_size_t(0)
+    for d, scale, st in ((3, 2.0, eot.EOT_OK), (2, 1.0, eot.EOT_OK), (4, 1.0, eot.EOT_ERR_UNSUPPORTED),
+                         (3, 0.0, eot.EOT_ERR_INVALID_ARG), (3, float("inf"), eot.EOT_ERR_INVALID_ARG)):
+        pts.d, pts.scale = d, scale
+        assert L.eot_workspace_size(eot.EOT_OP_GRADIENT, ctypes.byref(pts), 0, ctypes.byref(sz)) == st
+    pts.d, pts.scale, pts.X = 3, 1.0, None
+    assert L.eot_workspace_size(0, ctypes.byref(pts), 0, ctypes.byref(sz)) == eot.EOT_ERR_INVALID_ARG
 
 
 def test_binding_rejects_cpu_tensors():
