@@ -33,6 +33,26 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 
+def measured_traffic():
+    """HBM bytes per launch of the mixed HVP pass from the committed counter
+    summary, or None when the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hvp_grid16384_memory_counters.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if " = " in line:
+            k, v = line.strip().split(" = ", 1)
+            kv[k] = v
+    h = hashlib.sha256()
+    for f in ("eot_kernels.hip", "eot_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2504_02067_amd", "csrc", f), "rb").read())
+    if kv.get("kernel_sources_sha256") != h.hexdigest():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -73,12 +93,14 @@ def cpu_baseline(p, C_rows_fn, budget_s=10.0):
 
 
 def valu_cycles_points_hvp(d):
-    """VALU issue cycles per plan element of the mixed point-cloud HVP pass
-    (one lane): d subtractions and d multiply-adds for |x - y|^2, the exponent
-    (row + column hi parts, two multiply-adds, one add), exp2 at quarter rate
-    (4), the FP32 -> FP64 conversion, and four FP64 multiply-adds for the row
-    and column accumulations."""
-    return 2 * d + 4 + 4 + 1 + 4
+    """VALU instructions per plan entry that the mixed point-cloud HVP needs
+    (one lane; each issues in one cycle): d subtractions and d multiply-adds
+    for |x - y|^2, four for the exponent (hi-part sum, two multiply-adds, the
+    hi + lo add), exp2, the FP32 -> FP64 conversion, and four FP64
+    multiply-adds for the row and column accumulations. Loop control and the
+    per-row reductions come on top (the compiled loop issues 18.2 per entry
+    at d = 3)."""
+    return 2 * d + 4 + 1 + 1 + 4
 
 
 def points_measure(args, eot, W, dev, iters=4):
@@ -118,6 +140,43 @@ def points_measure(args, eot, W, dev, iters=4):
                          "valu_cycles_per_element": cyc}}
 
 
+def batch_measure(args, eot, W, dev):
+    """The ragged batch: 512 grid problems, sides uniform on 16..64 (n = side^2
+    in [256, 4096]), integer grid positions as 2-D points with the cost
+    recomputed on the fly, temperature 1/32 -> 1e-3, tol 1e-6; one
+    eot_solve_batched call per precision."""
+    import torch
+    sides = W.batch_sides()
+    items = []
+    for k in range(len(sides)):
+        p = W.batch_problem(k, sides=sides)
+        pc = eot.PointCloud(torch.from_numpy(p.X).to(dev), torch.from_numpy(p.Y).to(dev), p.scale)
+        items.append((pc, torch.from_numpy(p.r).to(dev), torch.from_numpy(p.c).to(dev)))
+    torch.cuda.synchronize()
+    res = {"workload": f"{len(items)} grid problems, n = side^2, side uniform on 16..64, "
+                       f"on-the-fly 2-D points, temperature 1/32 -> 1e-3, tol 1e-6",
+           "problems": len(items), "mean_n2": float(np.mean([float(s) ** 4 for s in sides])),
+           "workers": args.batch_workers}
+    for prec in ("mixed", "fp64"):
+        log(f"batch: {len(items)} problems, {prec}, {args.batch_workers} workers")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs, stats, status = eot.eot_solve_batched(items, workers=args.batch_workers,
+                                                    gamma_init=1.0 / 32.0, gamma_final=1e-3,
+                                                    tol=1e-6, precision=prec, check=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        errs = [st["err_r"] + st["err_c"] for st in stats]
+        res[prec] = {"seconds": dt, "problems_per_s": len(items) / dt,
+                     "failed": int(sum(1 for x in status if x != 0)),
+                     "max_err": float(max(errs)),
+                     "newton_steps": int(sum(st["newton_steps"] for st in stats)),
+                     "cg_iters": int(sum(st["cg_iters"] for st in stats))}
+        log(f"  {dt:.2f} s, failed {res[prec]['failed']}, max err {max(errs):.2e}")
+    res["speedup_mixed_vs_fp64"] = res["fp64"]["seconds"] / res["mixed"]["seconds"]
+    return res
+
+
 def kernels_only(args, eot, W, p, C, dev):
     """The mixed HVP pass (as in the full run) and a 1 GiB device-to-device copy
     whose fetched / written bytes calibrate the memory counters."""
@@ -151,6 +210,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-points", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-workers", type=int, default=8)
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the HVP kernel loop and a 1 GiB device copy (for counter runs)")
     args = ap.parse_args()
@@ -285,6 +346,10 @@ def main():
         torch.cuda.empty_cache()
         pts = points_measure(args, eot, W, dev)
 
+    batch = None
+    if not args.no_batch:
+        batch = batch_measure(args, eot, W, dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("CPU baseline (oracle)")
@@ -309,7 +374,7 @@ def main():
                    "n": n, "m": m, "passes_per_step": passes,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": hvp["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": hvp["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "frac": hvp["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_pass<mixed, fused HVP>: one pass, row + column reductions",
                      "bytes_per_launch": hvp_bytes, "kernel_us": hvp["kernel_us"]},
         "time_to_1e6": {"mixed_s": t_mixed, "fp64_s": fp64["seconds"] if fp64 else None,
@@ -322,6 +387,7 @@ def main():
                         "fp64_cg_iters": fp64["cg_iters"] if fp64 else None},
         "kernels": kern,
         "points": pts,
+        "batch": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -200,6 +200,36 @@ eot_status eot_solve(const eot_cost* cost, const double* r, const double* c,
                      const eot_solve_opts* opts, double* f, double* g,
                      eot_solve_stats* stats, void* ws, size_t ws_bytes, void* stream);
 
+/* Batched solves: many independent problems (any mix of sizes and cost kinds)
+ * solved with one shared option set. A native scheduler runs `workers` host
+ * threads, each with its own non-blocking HIP stream (default priority) and
+ * its own slice of the workspace; problems are dealt largest n m first to
+ * whichever worker is free, so small problems fill in behind large ones and
+ * the GPU runs up to `workers` solves at once. Each problem's arithmetic is
+ * exactly that of eot_solve on it (same kernels, same order): results are
+ * bitwise identical to solving the problems one by one.
+ * probs: host array of nprob entries (device pointers inside); stats and
+ * status: host arrays of nprob entries (nullable). Work on the caller's stream
+ * that precedes the call is waited for; the call returns when every problem
+ * is done, and the caller's stream is ordered after all of them. Returns
+ * EOT_OK, or the status of the lowest-numbered problem that failed (the
+ * others are still solved). ws: eot_workspace_size_batched bytes, 256-byte
+ * aligned. */
+typedef struct {
+    eot_cost cost;
+    const double* r;   /* device, n, on the simplex */
+    const double* c;   /* device, m, on the simplex */
+    double* f;         /* device, n, out (cost units) */
+    double* g;         /* device, m, out */
+} eot_batch_problem;
+
+eot_status eot_workspace_size_batched(int32_t nprob, const eot_batch_problem* probs,
+                                      int32_t workers, size_t* bytes);
+eot_status eot_solve_batched(int32_t nprob, const eot_batch_problem* probs,
+                             const eot_solve_opts* opts, int32_t workers,
+                             eot_solve_stats* stats, int32_t* status, void* ws, size_t ws_bytes,
+                             void* stream);
+
 /* Derivatives at potentials (f, g) of the entropic value
  *   W = gamma (<u, r> + <v, c> - sum_ij P_ij + 1)      (u = f / gamma, v = g / gamma;
  *                                                      the negated dual of Sec. 2)

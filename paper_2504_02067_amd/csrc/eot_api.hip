@@ -14,9 +14,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <numeric>
+#include <thread>
+#include <vector>
 
 #include "eot_internal.h"
 
@@ -688,6 +692,34 @@ eot_status solve_impl(Ctx& x, const double* r, const double* c, const eot_solve_
 
 bool bad_gamma(double gamma) { return !(gamma > 0.0) || !std::isfinite(gamma); }
 
+bool bad_opts(const eot_solve_opts& o)
+{
+    return bad_gamma(o.gamma_init) || bad_gamma(o.gamma_final) || !(o.tol > 0.0) ||
+           !(o.p >= 1.0) || !(o.q1 > 1.0) || !(o.w_r > 0.0 && o.w_r < 0.5) || o.max_cg < 1 ||
+           o.max_levels < 0 || o.max_backtrack < 0 || o.max_newton < 0 || o.max_sinkhorn < 0 ||
+           o.max_mdot < 1;
+}
+
+size_t align_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+
+// One solve on `stream` with workspace ws (options already validated).
+eot_status solve_one(const eot_cost* cost, const double* r, const double* c,
+                     const eot_solve_opts* opts, double* f, double* g, eot_solve_stats* stats,
+                     void* ws, size_t ws_bytes, void* stream)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    Ctx x;
+    EOTCHK(setup(x, cost, EOT_OP_SOLVE, opts->precision, ws, ws_bytes, stream));
+    eot_solve_stats st{};
+    eot_status status = solve_impl(x, r, c, opts, f, g, &st);
+    st.passes_other = x.passes - st.passes_newton - st.passes_linesearch - st.passes_sinkhorn -
+                      st.passes_projection;
+    st.status = status;
+    st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = st;
+    return status;
+}
+
 // ---------------------------------------------------------------- gradients
 // Derivatives of W and S at (f, g); see eot_gradient in eot.h for the
 // formulas. Every pass is FP64 except the CG passes (precision prec).
@@ -958,23 +990,103 @@ eot_status eot_solve(const eot_cost* cost, const double* r, const double* c,
                      void* ws, size_t ws_bytes, void* stream)
 {
     if (!r || !c || !opts || !f || !g) return EOT_ERR_INVALID_ARG;
-    const eot_solve_opts& o = *opts;
-    if (bad_gamma(o.gamma_init) || bad_gamma(o.gamma_final) || !(o.tol > 0.0) ||
-        !(o.p >= 1.0) || !(o.q1 > 1.0) || !(o.w_r > 0.0 && o.w_r < 0.5) || o.max_cg < 1 ||
-        o.max_levels < 0 || o.max_backtrack < 0 || o.max_newton < 0 || o.max_sinkhorn < 0 ||
-        o.max_mdot < 1)
-        return EOT_ERR_INVALID_ARG;
-    const auto t0 = std::chrono::steady_clock::now();
-    Ctx x;
-    EOTCHK(setup(x, cost, EOT_OP_SOLVE, o.precision, ws, ws_bytes, stream));
-    eot_solve_stats st{};
-    eot_status status = solve_impl(x, r, c, &o, f, g, &st);
-    st.passes_other = x.passes - st.passes_newton - st.passes_linesearch - st.passes_sinkhorn -
-                      st.passes_projection;
-    st.status = status;
-    st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    if (stats) *stats = st;
-    return status;
+    if (bad_opts(*opts)) return EOT_ERR_INVALID_ARG;
+    return solve_one(cost, r, c, opts, f, g, stats, ws, ws_bytes, stream);
+}
+
+eot_status eot_workspace_size_batched(int32_t nprob, const eot_batch_problem* probs,
+                                      int32_t workers, size_t* bytes)
+{
+    if (!bytes || nprob < 1 || !probs || workers < 1) return EOT_ERR_INVALID_ARG;
+    size_t slice = 0;
+    for (int32_t k = 0; k < nprob; ++k) {
+        size_t b = 0;
+        EOTCHK(eot_workspace_size(EOT_OP_SOLVE, &probs[k].cost, 0, &b));
+        slice = std::max(slice, align_up(b));
+    }
+    *bytes = slice * (size_t)std::min(workers, nprob) + kAlign;
+    return EOT_OK;
+}
+
+eot_status eot_solve_batched(int32_t nprob, const eot_batch_problem* probs,
+                             const eot_solve_opts* opts, int32_t workers,
+                             eot_solve_stats* stats, int32_t* status, void* ws, size_t ws_bytes,
+                             void* stream)
+{
+    if (nprob < 1 || !probs || !opts || workers < 1) return EOT_ERR_INVALID_ARG;
+    if (bad_opts(*opts)) return EOT_ERR_INVALID_ARG;
+    for (int32_t k = 0; k < nprob; ++k) {
+        const eot_batch_problem& p = probs[k];
+        if (!p.r || !p.c || !p.f || !p.g) return EOT_ERR_INVALID_ARG;
+        EOTCHK(check_cost(&p.cost));
+    }
+    size_t need = 0;
+    EOTCHK(eot_workspace_size_batched(nprob, probs, workers, &need));
+    if (!ws || ws_bytes < need - kAlign || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0)
+        return EOT_ERR_WORKSPACE;
+    const int nw = std::min(workers, nprob);
+    const size_t slice = (need - kAlign) / (size_t)nw;
+    // Longest first: problems in decreasing n m, dealt to whichever worker is free.
+    std::vector<int32_t> order((size_t)nprob);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return probs[a].cost.n * probs[a].cost.m > probs[b].cost.n * probs[b].cost.m;
+    });
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    hipStream_t caller = static_cast<hipStream_t>(stream);
+    hipEvent_t start;
+    HIPCHK(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(start, caller));
+    std::vector<hipStream_t> streams((size_t)nw, nullptr);
+    std::vector<hipEvent_t> done((size_t)nw, nullptr);
+    eot_status setup_err = EOT_OK;
+    for (int w = 0; w < nw && setup_err == EOT_OK; ++w) {
+        if (hipStreamCreateWithFlags(&streams[w], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&done[w], hipEventDisableTiming) != hipSuccess ||
+            hipStreamWaitEvent(streams[w], start, 0) != hipSuccess)
+            setup_err = EOT_ERR_HIP;
+    }
+    std::vector<eot_status> st_all((size_t)nprob, EOT_OK);
+    std::vector<eot_solve_stats> stats_all((size_t)nprob);
+    std::atomic<int32_t> next{0};
+    auto work = [&](int w) {
+        if (hipSetDevice(dev) != hipSuccess) return;
+        char* base = static_cast<char*>(ws) + (size_t)w * slice;
+        for (;;) {
+            const int32_t k = next.fetch_add(1);
+            if (k >= nprob) break;
+            const int32_t i = order[(size_t)k];
+            const eot_batch_problem& p = probs[i];
+            st_all[(size_t)i] = solve_one(&p.cost, p.r, p.c, opts, p.f, p.g, &stats_all[(size_t)i],
+                                          base, slice, streams[w]);
+        }
+    };
+    if (setup_err == EOT_OK) {
+        std::vector<std::thread> pool;
+        for (int w = 1; w < nw; ++w) pool.emplace_back(work, w);
+        work(0);
+        for (auto& t : pool) t.join();
+    }
+    eot_status first = setup_err;
+    for (int w = 0; w < nw; ++w) {
+        if (streams[w]) {
+            if (done[w] && hipEventRecord(done[w], streams[w]) == hipSuccess)
+                (void)hipStreamWaitEvent(caller, done[w], 0);
+        }
+    }
+    for (int w = 0; w < nw; ++w) {
+        if (streams[w]) (void)hipStreamSynchronize(streams[w]);
+        if (done[w]) (void)hipEventDestroy(done[w]);
+        if (streams[w]) (void)hipStreamDestroy(streams[w]);
+    }
+    (void)hipEventDestroy(start);
+    for (int32_t i = 0; i < nprob; ++i) {
+        if (status) status[i] = st_all[(size_t)i];
+        if (stats) stats[i] = stats_all[(size_t)i];
+        if (first == EOT_OK && st_all[(size_t)i] != EOT_OK) first = st_all[(size_t)i];
+    }
+    return first;
 }
 
 eot_status eot_gradient(const eot_cost* cost, double gamma, const double* f, const double* g,

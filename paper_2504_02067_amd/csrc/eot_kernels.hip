@@ -762,7 +762,9 @@ __global__ void k_cg_init(const double* b, const double* rP, const double* s, do
     const int64_t k = n > m ? n : m;
     EW_LOOP(k) {
         if (i < n) {
-            const double lo = (1.0 - rho) * rP[i];
+            // M_i >= (1 - rho) r(P)_i; at rho = 1 (the gradient's solve) a floor of
+            // 2^-40 r(P)_i keeps the preconditioner finite
+            const double lo = fmax(1.0 - rho, 9.094947017729282e-13) * rP[i];
             double mi = rP[i] - rho * s[i];
             mi = mi > lo ? mi : lo;
             const double bi = b[i];

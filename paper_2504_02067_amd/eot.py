@@ -74,6 +74,10 @@ class eot_solve_stats(ctypes.Structure):
 
 
 # Every entry point declared in include/eot.h, with its ctypes signature.
+class eot_batch_problem(ctypes.Structure):
+    _fields_ = [("cost", eot_cost), ("r", _c_vp), ("c", _c_vp), ("f", _c_vp), ("g", _c_vp)]
+
+
 class eot_grad_info(ctypes.Structure):
     _fields_ = [("tol", _c_f64), ("max_cg", _c_i32), ("cg_iters", _c_i32),
                 ("cg_residual", _c_f64), ("S", _c_f64)]
@@ -95,6 +99,12 @@ SIGNATURES = {
     "eot_solve": (_c_i32, [ctypes.POINTER(eot_cost), _c_vp, _c_vp,
                            ctypes.POINTER(eot_solve_opts), _c_vp, _c_vp,
                            ctypes.POINTER(eot_solve_stats), _c_vp, ctypes.c_size_t, _c_vp]),
+    "eot_workspace_size_batched": (_c_i32, [_c_i32, ctypes.POINTER(eot_batch_problem), _c_i32,
+                                            ctypes.POINTER(ctypes.c_size_t)]),
+    "eot_solve_batched": (_c_i32, [_c_i32, ctypes.POINTER(eot_batch_problem),
+                                   ctypes.POINTER(eot_solve_opts), _c_i32,
+                                   ctypes.POINTER(eot_solve_stats), ctypes.POINTER(_c_i32), _c_vp,
+                                   ctypes.c_size_t, _c_vp]),
     "eot_gradient": (_c_i32, [ctypes.POINTER(eot_cost), _c_f64, _c_vp, _c_vp, _c_f64, _c_f64,
                               _c_vp, _c_i64, _c_vp, _c_vp, _c_vp, _c_vp,
                               ctypes.POINTER(eot_grad_info), _c_i32, _c_vp, ctypes.c_size_t,
@@ -312,6 +322,45 @@ def eot_solve(C, r, c, opts: Optional[eot_solve_opts] = None, allow_not_converge
     allow = (EOT_OK, EOT_ERR_NOT_CONVERGED) if allow_not_converged else (EOT_OK,)
     _check(st, "eot_solve", allow)
     return f, g, stats.as_dict()
+
+
+def eot_solve_batched(problems, opts: Optional[eot_solve_opts] = None, workers=8,
+                      allow_not_converged=False, check=True, **kw):
+    """Solve many problems at once. ``problems``: sequence of (C, r, c) with C a
+    dense GPU tensor or a PointCloud. Returns (list of (f, g), list of stats
+    dicts, list of status codes); with check=False a failed problem does not
+    raise (its status says what happened)."""
+    k = len(problems)
+    o = opts if opts is not None else default_solve_opts(**kw)
+    arr = (eot_batch_problem * k)()
+    outs, keep = [], []
+    dev = None
+    for i, (C, r, c) in enumerate(problems):
+        cost = make_cost(C)
+        dev = C.device
+        f = torch.empty(cost.n, dtype=torch.float64, device=dev)
+        g = torch.empty(cost.m, dtype=torch.float64, device=dev)
+        arr[i].cost = cost
+        arr[i].r = _vec(r, cost.n, "r")
+        arr[i].c = _vec(c, cost.m, "c")
+        arr[i].f = _vec(f, cost.n, "f")
+        arr[i].g = _vec(g, cost.m, "g")
+        outs.append((f, g))
+        keep.append((C, r, c))
+    nbytes = ctypes.c_size_t(0)
+    _check(lib().eot_workspace_size_batched(k, arr, int(workers), ctypes.byref(nbytes)),
+           "eot_workspace_size_batched")
+    buf = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=dev)
+    off = (-buf.data_ptr()) % 256
+    ws = buf[off:off + int(nbytes.value)]
+    stats = (eot_solve_stats * k)()
+    status = (_c_i32 * k)()
+    st = lib().eot_solve_batched(k, arr, ctypes.byref(o), int(workers), stats, status,
+                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev))
+    allow = (EOT_OK, EOT_ERR_NOT_CONVERGED) if allow_not_converged else (EOT_OK,)
+    if check:
+        _check(st, "eot_solve_batched", allow)
+    return outs, [stats[i].as_dict() for i in range(k)], [int(status[i]) for i in range(k)]
 
 
 def eot_gradient(C, gamma, f, g, w_W=1.0, w_S=0.0, want=None, tol=1e-11, max_cg=5000,

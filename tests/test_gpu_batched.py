@@ -1,0 +1,92 @@
+"""GPU tests of eot_solve_batched: the ragged grid batch (integer grid
+positions as 2-D points, cost recomputed on the fly) solved concurrently must
+give bitwise the potentials of solving each problem alone; mixed cost kinds
+share one batch; a failing problem does not stop the others; and sampled
+problems match the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2504_02067_amd import eot
+from paper_2504_02067_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def say(msg):
+    print(f"[gpu-batch] {msg}", flush=True)
+
+
+def dvec(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def batch(count, lo=16, hi=40, seed=4000):
+    sides = W.batch_sides(seed, count, lo, hi)
+    probs, items = [], []
+    for k in range(count):
+        p = W.batch_problem(k, seed, sides)
+        pc = eot.PointCloud(torch.from_numpy(p.X).to(DEV), torch.from_numpy(p.Y).to(DEV), p.scale)
+        probs.append(p)
+        items.append((pc, dvec(p.r), dvec(p.c)))
+    return probs, items
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batched_equals_one_by_one(prec):
+    probs, items = batch(24)
+    opts = dict(gamma_init=1.0 / 32.0, gamma_final=1e-3, tol=1e-6, precision=prec)
+    say(f"batch of 24 ({prec}), 4 workers")
+    outs, stats, status = eot.eot_solve_batched(items, workers=4, **opts)
+    assert all(s == 0 for s in status)
+    for k, (pc, r, c) in enumerate(items):
+        f, g, st = eot.eot_solve(pc, r, c, **opts)
+        assert torch.equal(outs[k][0], f) and torch.equal(outs[k][1], g), k
+        assert stats[k]["newton_steps"] == st["newton_steps"]
+        assert stats[k]["cg_iters"] == st["cg_iters"]
+        assert stats[k]["err_r"] + stats[k]["err_c"] <= 1e-6
+
+
+def test_batched_matches_oracle_on_samples():
+    probs, items = batch(6, lo=16, hi=24, seed=4100)
+    say("batch of 6 vs oracle")
+    outs, stats, status = eot.eot_solve_batched(items, workers=3, gamma_init=1.0 / 32.0,
+                                                gamma_final=1e-3, tol=1e-6)
+    for k in (0, 3, 5):
+        p = probs[k]
+        C = O.sqeuclid_points_cost(p.X, p.Y, p.scale)
+        u, v, ost = O.solve(C, p.r, p.c, gamma_init=1.0 / 32.0, gamma_final=1e-3, tol=1e-6)
+        assert abs(stats[k]["cost"] - ost["cost"]) <= 1e-10 * ost["cost"]
+        assert stats[k]["newton_steps"] == ost["newton_steps"]
+
+
+def test_batched_mixed_kinds_and_failure_isolation():
+    rng = np.random.default_rng(9)
+    items = []
+    for n, m in ((300, 200), (64, 64), (1000, 700)):
+        C = torch.from_numpy(rng.uniform(0, 1, (n, m)).astype(np.float32)).to(DEV)
+        items.append((C, dvec(rng.dirichlet(np.ones(n))), dvec(rng.dirichlet(np.ones(m)))))
+    probs, pitems = batch(3, seed=4200)
+    items += pitems
+    bad_r = dvec(np.full(64, 2.0 / 64))                    # sums to 2: rejected
+    items.insert(2, (items[1][0], bad_r, items[1][2]))
+    say("mixed kinds with one invalid problem")
+    with pytest.raises(eot.EotError) as e:
+        eot.eot_solve_batched(items, workers=4, gamma_init=0.1, gamma_final=1e-2, tol=1e-6)
+    assert e.value.status == eot.EOT_ERR_BAD_MARGINALS
+    outs, stats, status = eot.eot_solve_batched(items, workers=4, gamma_init=0.1,
+                                                gamma_final=1e-2, tol=1e-6, check=False)
+    assert status[2] == eot.EOT_ERR_BAD_MARGINALS
+    assert [s for k, s in enumerate(status) if k != 2] == [0] * (len(items) - 1)
+    for k, (C, r, c) in enumerate(items):
+        if k == 2:
+            continue
+        f, g, st = eot.eot_solve(C, r, c, gamma_init=0.1, gamma_final=1e-2, tol=1e-6)
+        assert torch.equal(outs[k][0], f) and torch.equal(outs[k][1], g), k
