@@ -89,7 +89,8 @@ typedef enum {
     EOT_OP_HVP = 1,
     EOT_OP_NEWTON_CG = 2,
     EOT_OP_SOLVE = 3,
-    EOT_OP_GRADIENT = 4
+    EOT_OP_GRADIENT = 4,
+    EOT_OP_ROUND = 5
 } eot_op;
 
 /* Scratch bytes that `op` needs for `cost` in precision `prec`.
@@ -126,7 +127,7 @@ eot_status eot_hvp(const eot_cost* cost, double gamma, const double* f, const do
                    void* stream);
 
 typedef struct {
-    double rho_out;     /* discount at exit (Alg. 2 L4 after the last solve)          */
+    double rho_out;     /* discount at exit (after the update following the last solve, Alg. 2)          */
     int32_t cg_iters;   /* CG iterations over all discount levels                     */
     int32_t levels;     /* discount levels solved                                     */
     int32_t forcing_miss; /* 1 if the forcing test was unmet at the discount cap      */
@@ -139,7 +140,7 @@ typedef struct {
  * preconditioned CG on F_r(rho) d = -grad_u g from d = 0, stopped at
  * ||F_r(rho) d + grad_u g||_1 <= (eta/4) ||grad g||_1, rho annealed
  * rho <- 1 - (1 - rho)/4 from rho0 until ||F_r(1) d + grad_u g||_1 <=
- * eta ||grad g||_1, then d_v = -P_c d_u (Alg. 4 L7). Here
+ * eta ||grad g||_1, then d_v = -P_c d_u (as in Alg. 4). Here
  * F_r(rho) = D(r(P)) - rho P D(c)^-1 P^T (eq. matrix-definitions).
  * Precondition (as in Alg. 4): the columns are fixed, c(P) = c.
  * r: n, c: m (targets); outputs dir_f: n, dir_g: m in cost units
@@ -153,11 +154,13 @@ eot_status eot_newton_cg(const eot_cost* cost, double gamma, const double* f, co
                          eot_newton_stats* stats, int32_t prec, void* ws, size_t ws_bytes,
                          void* stream);
 
+typedef enum { EOT_PROJ_TNP = 0, EOT_PROJ_SINKHORN = 1 } eot_projection;
+
 typedef struct {
     double gamma_init;      /* initial temperature (1/beta_i); default 1/32            */
     double gamma_final;     /* final temperature (1/beta_f)                            */
     double tol;             /* target L1 marginal error vs the given r, c; 1e-6        */
-    double p;               /* eps_d = min(H(r), H(c)) / beta^p (Alg. 1 L4); 1.5       */
+    double p;               /* eps_d = min(H(r), H(c)) / beta^p (Alg. 1); 1.5       */
     double q1;              /* initial decay factor q^(1); 2                           */
     double w_r;             /* row smoothing weight (Sec. 3.4), w_c = 1/2 - w_r; 0.45  */
     int32_t adaptive_q;     /* AdjustSchedule (Sec. 3.3) on; 1                         */
@@ -171,6 +174,10 @@ typedef struct {
     int32_t precision;      /* eot_precision                                           */
     int32_t verify_fp64;    /* mixed: check (and if needed finish) the last projection
                                with FP64 passes so the reported error is exact; 1     */
+    int32_t projection;     /* Bregman projection inside MDOT: EOT_PROJ_TNP (Alg. 4, the
+                               paper's method) or EOT_PROJ_SINKHORN (alternating row and
+                               column fits to the same tolerance: the baseline the paper
+                               compares against); EOT_PROJ_TNP                         */
 } eot_solve_opts;
 
 typedef struct {
@@ -194,11 +201,34 @@ void eot_solve_opts_default(eot_solve_opts* opts);
  * (Sec. 3.4) and TruncatedNewtonProject (Alg. 4) as the Bregman projection;
  * returns the potentials at gamma_final in cost units (f: n, g: m). The
  * plan at the output is exp((f_i + g_j - C_ij)/gamma_final); rounding onto
- * U(r, c) (Alg. 1 L13) is not applied. r: n, c: m on the simplex.
+ * U(r, c) (the last step of Alg. 1) is not applied. r: n, c: m on the simplex.
  * opts, stats: host pointers (stats nullable). */
 eot_status eot_solve(const eot_cost* cost, const double* r, const double* c,
                      const eot_solve_opts* opts, double* f, double* g,
                      eot_solve_stats* stats, void* ws, size_t ws_bytes, void* stream);
+
+/* Rounding onto the transport polytope U(r, c) (the last step of Alg. 1; the procedure of
+ * Altschuler et al. that the paper cites for it): with P the plan at (f, g),
+ *   x = min(1, r / r(P)),  y = min(1, c / c(D(x) P)),
+ *   X = D(x) P D(y) + er ec^T / |er|_1,  er = r - r(D(x) P D(y)),  ec = c - c(D(x) P D(y)),
+ * which has marginals exactly r and c. X is returned implicitly by x (n), y (m),
+ * er (n), ec (m) (device, nullable) and, for dense costs, optionally as a dense
+ * FP64 n x m matrix `plan` with leading dimension ldp >= m (nullable). `info`
+ * (host, required) receives <X, C>, <P, C>, the L1 marginal errors of P, and
+ * |er|_1 (the mass moved by the rank-one correction). Every pass is FP64; the
+ * correction's cost er^T C ec is one extra pass over C with beta = 0.
+ * EOT_ERR_INVALID_ARG for `plan` with a point cloud. */
+typedef struct {
+    double cost_round;   /* <X, C> */
+    double cost_plan;    /* <P, C> */
+    double err_r, err_c; /* |r(P) - r|_1, |c(P) - c|_1 */
+    double mass_fix;     /* |er|_1 = |ec|_1 */
+} eot_round_info;
+
+eot_status eot_round(const eot_cost* cost, double gamma, const double* f, const double* g,
+                     const double* r, const double* c, double* x, double* y, double* er,
+                     double* ec, double* plan, int64_t ldp, eot_round_info* info, void* ws,
+                     size_t ws_bytes, void* stream);
 
 /* Batched solves: many independent problems (any mix of sizes and cost kinds)
  * solved with one shared option set. A native scheduler runs `workers` host

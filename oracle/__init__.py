@@ -34,7 +34,8 @@ class Opts(ctypes.Structure):
                 ("p", _f64), ("q1", _f64), ("w_r", _f64),
                 ("adaptive_q", _i32), ("adaptive_rho0", _i32),
                 ("max_cg", _i32), ("max_levels", _i32), ("max_backtrack", _i32),
-                ("max_newton", _i32), ("max_sinkhorn", _i32), ("max_mdot", _i32)]
+                ("max_newton", _i32), ("max_sinkhorn", _i32), ("max_mdot", _i32),
+                ("projection", _i32)]
 
 
 class Stats(ctypes.Structure):
@@ -249,7 +250,8 @@ def line_search(C, beta, u, v, grad_u, du, dv, max_backtrack=60):
 def default_opts(gamma_init=1.0 / 32.0, gamma_final=1e-3, tol=1e-6, **kw) -> Opts:
     o = Opts(gamma_init=gamma_init, gamma_final=gamma_final, tol=tol, p=1.5, q1=2.0,
              w_r=0.45, adaptive_q=1, adaptive_rho0=1, max_cg=1000, max_levels=30,
-             max_backtrack=60, max_newton=200, max_sinkhorn=10000, max_mdot=500)
+             max_backtrack=60, max_newton=200, max_sinkhorn=10000, max_mdot=500,
+             projection=0)
     for k, val in kw.items():
         setattr(o, k, val)
     return o

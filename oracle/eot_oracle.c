@@ -181,7 +181,7 @@ void orc_hvp(int64_t n, int64_t m, const double* C, double beta,
 
 /* F_r(rho) p = D(r(P)) p - rho P D(c)^-1 P^T p   (eq. matrix-definitions and
  * the proof of lemma "frprops"). Reading: the column marginal in P_c is the
- * target c, which equals c(P) after the column fix of Alg. 4 L1 / L15.
+ * target c, which equals c(P) after the column fixes of Alg. 4.
  * Two explicit passes: w = P^T p, then P (w / c). Pinned by: the dense
  * matrix D(r(P)) - rho P D(c)^-1 P^T at n <= 64, its symmetry, and the
  * Bellman form (I - rho P_rc) d = r/r(P) - 1 (eq. bellman2). */
@@ -214,7 +214,7 @@ void orc_fr_apply(int64_t n, int64_t m, const double* C, double beta,
 /* Diagonally preconditioned linear CG on F_r(rho) d = b from d = 0
  * (Sec. 3.1 and lemma "cgconv", which fixes the zero start), with the
  * preconditioner M = diag F_r(rho) = r(P) - rho s (lemma "condo").
- * Stops when the L1 norm of the residual b - F_r d is <= tol (Alg. 2 L3
+ * Stops when the L1 norm of the residual b - F_r d is <= tol (Alg. 2's CG
  * asks for ||F_r d + grad||_1 <= (eta/4)||grad||_1 with b = -grad).
  * Reading: the recursively updated residual is the one tested; M_i is
  * clamped below at (1 - rho) r(P)_i, its exact lower bound when c(P) = c.
@@ -269,8 +269,8 @@ int orc_pcg(int64_t n, int64_t m, const double* C, double beta,
  *   while ||F_r(1) d + grad_u g||_1 > eta ||grad g||_1:
  *       d <- PCG(F_r(rho), -grad_u g, tol = (eta/4) ||grad g||_1)
  *       rho <- 1 - (1 - rho)/4
- * and d_v = -P_c d_u = -(P^T d_u)/c (Alg. 4 L7).
- * Readings: ||grad g||_1 = ||r(P) - r||_1 since c(P) = c (Alg. 4 L3);
+ * and d_v = -P_c d_u = -(P^T d_u)/c (as in Alg. 4).
+ * Readings: ||grad g||_1 = ||r(P) - r||_1 since c(P) = c (Alg. 4's stopping test);
  * rho_out is the value of rho when the loop exits (one update past the last
  * solve). Alg. 2 has no exit other than the forcing test, which in floating
  * point can be unreachable when P_rc is nearly decomposable (lambda_2 within
@@ -387,7 +387,7 @@ int orc_chi_sinkhorn(int64_t n, int64_t m, const double* C, double beta,
     return status;
 }
 
-/* Backtracking line search of Alg. 4 L8-L13: alpha = 1, halve until
+/* Backtracking line search of Alg. 4: alpha = 1, halve until
  *   ||c(P(alpha))||_1 - 1 <= 0.99 alpha <-grad_u g, d_u>
  * (lemma "suffdecr": this is the Armijo condition with c1 = 0.01 when
  * c(P) = c), where log c(P(alpha)) = v + alpha d_v
@@ -423,10 +423,47 @@ int orc_line_search(int64_t n, int64_t m, const double* C, double beta,
     return status;
 }
 
-/* TruncatedNewtonProject (Alg. 4), with eps_chi = eps^(2/5) (L4) and
- * eta = max(||grad||_1, 0.8 eps / ||grad||_1) (L5).
+/* Sinkhorn projection (the baseline the paper compares against, used in
+ * place of Alg. 4 inside MDOT): column fit, row marginal; then while
+ * ||r - r(P)||_1 > eps: row fit u += log r - log r(P), column fit, row
+ * marginal; finally the closing row fit of Alg. 4. Pinned by: reaching the same
+ * optimum as the TNP projection, c(P) = c after each sweep, the dual never
+ * increasing. */
+int orc_sinkhorn_project(int64_t n, int64_t m, const double* C, double beta, double* u,
+                         double* v, const double* r, const double* c, double eps,
+                         const orc_opts* o, orc_stats* st)
+{
+    double* lr = dalloc(n);
+    double* lc = dalloc(m);
+    double* zero = dalloc(m);
+    int status = ORC_OK;
+    orc_log_col_marginal(n, m, C, beta, u, zero, lc);
+    for (int64_t j = 0; j < m; ++j) v[j] = log(c[j]) - lc[j];
+    orc_log_row_marginal(n, m, C, beta, u, v, lr);
+    st->passes_projection += 2;
+    int32_t k = 0;
+    for (;;) {
+        double gn = 0.0;
+        for (int64_t i = 0; i < n; ++i) gn += fabs(r[i] - exp(lr[i]));
+        if (gn <= eps) break;
+        if (k >= o->max_sinkhorn) { status = ORC_NOT_CONVERGED; break; }
+        for (int64_t i = 0; i < n; ++i) u[i] += log(r[i]) - lr[i];
+        orc_log_col_marginal(n, m, C, beta, u, zero, lc);
+        for (int64_t j = 0; j < m; ++j) v[j] = log(c[j]) - lc[j];
+        orc_log_row_marginal(n, m, C, beta, u, v, lr);
+        st->passes_sinkhorn += 2;
+        ++k;
+    }
+    st->sinkhorn_iters += k;
+    for (int64_t i = 0; i < n; ++i) u[i] += log(r[i]) - lr[i];   /* closing row fit */
+    free(lr); free(lc); free(zero);
+    return status;
+}
+
+/* TruncatedNewtonProject (Alg. 4), with eps_chi = eps^(2/5) and
+ * eta = max(||grad||_1, 0.8 eps / ||grad||_1).
  * delta_k (eq. delta_k-ratio) compares the norm used to set eta_k (after
- * ChiSinkhorn) with the norm after the row refresh of L16 (reading).
+ * ChiSinkhorn) with the norm after the row refresh that follows the step (reading).
  * Returns delta_min over the Newton steps (+inf when none ran). */
 int orc_tnp(int64_t n, int64_t m, const double* C, double beta, double* u,
             double* v, const double* r, const double* c, double eps,
@@ -441,10 +478,10 @@ int orc_tnp(int64_t n, int64_t m, const double* C, double beta, double* u,
     double* zero = dalloc(m);
     int status = ORC_OK;
 
-    /* L1: v <- log c - LSE_c(u 1^T - beta C) */
+    /* column fix: v <- log c - LSE_c(u 1^T - beta C) */
     orc_log_col_marginal(n, m, C, beta, u, zero, lc);
     for (int64_t j = 0; j < m; ++j) v[j] = log(c[j]) - lc[j];
-    /* L2: log r(P) <- u + LSE_r(1 v^T - beta C) */
+    /* row marginals: log r(P) <- u + LSE_r(1 v^T - beta C) */
     orc_log_row_marginal(n, m, C, beta, u, v, lr);
     st->passes_projection += 2;
 
@@ -453,9 +490,9 @@ int orc_tnp(int64_t n, int64_t m, const double* C, double beta, double* u,
     for (;;) {
         double gn = 0.0;
         for (int64_t i = 0; i < n; ++i) gn += fabs(r[i] - exp(lr[i]));
-        if (gn <= eps) break;                                   /* L3 */
+        if (gn <= eps) break;                                   /* tolerance met */
         if (k >= o->max_newton) { status = ORC_NOT_CONVERGED; break; }
-        int32_t sk = 0;                                         /* L4 */
+        int32_t sk = 0;                                         /* ChiSinkhorn */
         int s1 = orc_chi_sinkhorn(n, m, C, beta, u, v, r, c, lr, pow(eps, 0.4),
                                   o->max_sinkhorn, &sk);
         st->sinkhorn_iters += sk;
@@ -466,8 +503,8 @@ int orc_tnp(int64_t n, int64_t m, const double* C, double beta, double* u,
             grad[i] = exp(lr[i]) - r[i];
             gk += fabs(grad[i]);
         }
-        double eta = gk > 0.8 * eps / gk ? gk : 0.8 * eps / gk;   /* L5 */
-        double rho_out = 0.0;                                   /* L6-L7 */
+        double eta = gk > 0.8 * eps / gk ? gk : 0.8 * eps / gk;   /* forcing term */
+        double rho_out = 0.0;                                   /* Alg. 2, d_v */
         int32_t cgk = 0, lev = 0, miss = 0;
         int64_t np = 0;
         int s2 = orc_newton_solve(n, m, C, beta, u, v, r, c, lr, eta, *rho0_io,
@@ -480,17 +517,17 @@ int orc_tnp(int64_t n, int64_t m, const double* C, double beta, double* u,
         st->rho_last = rho_out;
         *rho0_io = o->adaptive_rho0 ? fmax(0.0, 1.0 - 4.0 * (1.0 - rho_out)) : 0.0;
         if (s2 != ORC_OK) { status = s2; break; }
-        double alpha = 1.0;                                     /* L8-L13 */
+        double alpha = 1.0;                                     /* line search */
         int32_t bt = 0;
         int s3 = orc_line_search(n, m, C, beta, u, v, grad, du, dv,
                                  o->max_backtrack, &alpha, lc, &bt);
         st->backtracks += bt;
         st->passes_linesearch += 1 + bt;
         if (s3 != ORC_OK) { status = s3; break; }
-        for (int64_t i = 0; i < n; ++i) u[i] += alpha * du[i];  /* L14 */
+        for (int64_t i = 0; i < n; ++i) u[i] += alpha * du[i];  /* step */
         for (int64_t j = 0; j < m; ++j) v[j] += alpha * dv[j];
-        for (int64_t j = 0; j < m; ++j) v[j] += log(c[j]) - lc[j]; /* L15 */
-        orc_log_row_marginal(n, m, C, beta, u, v, lr);          /* L16 */
+        for (int64_t j = 0; j < m; ++j) v[j] += log(c[j]) - lc[j]; /* column fix */
+        orc_log_row_marginal(n, m, C, beta, u, v, lr);          /* row refresh */
         st->passes_projection += 1;
         st->newton_steps += 1;
         double gk1 = 0.0;
@@ -499,7 +536,7 @@ int orc_tnp(int64_t n, int64_t m, const double* C, double beta, double* u,
         if (dk < dmin) dmin = dk;
         ++k;
     }
-    /* L18: u <- u + log r - log r(P) */
+    /* closing row fit: u <- u + log r - log r(P) */
     for (int64_t i = 0; i < n; ++i) u[i] += log(r[i]) - lr[i];
     *delta_min = dmin;
     free(lr); free(lc); free(grad); free(du); free(dv); free(zero);
@@ -524,7 +561,7 @@ static double entropy(int64_t k, const double* x)
  *   z^(t+1) = z^(t) + (beta^(t+1) - beta^(t)) / (beta^(t) - beta^(t-1)) (z^(t) - z^(t-1)).
  * Readings: at the final temperature eps_d <- min(eps_d, tol/2) so that the
  * error against the unsmoothed marginals ends below tol; the output is the
- * last projected z (Alg. 1 L12) in log units at beta_f; rounding (L13) is a
+ * last projected z of Alg. 1 in log units at beta_f; rounding (its last step) is a
  * separate routine (orc_round).
  * Pinned by: brute-force assignment as the temperature goes to 0, 2x2
  * closed form, separable costs, strong duality, marginal error <= tol. */
@@ -536,7 +573,9 @@ int orc_solve(int64_t n, int64_t m, const double* C, const double* r,
     const double beta_f = 1.0 / o->gamma_final;
     const double beta_i = 1.0 / o->gamma_init;
     const double w_c = 0.5 - o->w_r;
-    const double hmin = fmin(entropy(n, r), entropy(m, c));
+    /* min(H(r), H(c)), floored at tol: a point-mass marginal has entropy 0,
+     * which would ask for an exact projection (reading) */
+    const double hmin = fmax(fmin(entropy(n, r), entropy(m, c)), o->tol);
     double* rt = dalloc(n);
     double* ct = dalloc(m);
     double* zu_prev = dalloc(n);
@@ -550,30 +589,32 @@ int orc_solve(int64_t n, int64_t m, const double* C, const double* r,
     int done = 0;
     while (!done) {
         if (t > o->max_mdot) { status = ORC_NOT_CONVERGED; break; }
-        done = (beta == beta_f);                                   /* L3 */
-        double eps_d = hmin / pow(beta, o->p);                     /* L4 */
+        done = (beta == beta_f);                                   /* last temperature */
+        double eps_d = hmin / pow(beta, o->p);                     /* projection tolerance */
         if (done && eps_d > 0.5 * o->tol) eps_d = 0.5 * o->tol;
-        for (int64_t i = 0; i < n; ++i)                            /* L5 */
+        for (int64_t i = 0; i < n; ++i)                            /* smoothing */
             rt[i] = (1.0 - o->w_r * eps_d) * r[i] + o->w_r * eps_d / (double)n;
         for (int64_t j = 0; j < m; ++j)
             ct[j] = (1.0 - w_c * eps_d) * c[j] + w_c * eps_d / (double)m;
-        if (t == 1) {                                              /* L6 */
+        if (t == 1) {                                              /* initial potentials */
             for (int64_t i = 0; i < n; ++i) u[i] = zu_prev[i] = log(rt[i]);
             for (int64_t j = 0; j < m; ++j) v[j] = zv_prev[j] = log(ct[j]);
         }
-        double dmin = INFINITY;                                    /* L7 */
-        int s = orc_tnp(n, m, C, beta, u, v, rt, ct, 0.5 * eps_d, o, &rho0, &dmin, st);
+        double dmin = INFINITY;                                    /* projection */
+        int s = o->projection == 1
+                    ? orc_sinkhorn_project(n, m, C, beta, u, v, rt, ct, 0.5 * eps_d, o, st)
+                    : orc_tnp(n, m, C, beta, u, v, rt, ct, 0.5 * eps_d, o, &rho0, &dmin, st);
         st->delta_min_last = dmin;
         st->mdot_steps = t;
         st->final_beta = beta;
         if (s != ORC_OK) { status = s; break; }
         if (done) break;
-        if (o->adaptive_q) {                                       /* L8 */
+        if (o->adaptive_q) {                                       /* AdjustSchedule */
             if (dmin > 0.95) q = fmin(2.0, q * q);
             else if (dmin < 0.8) q = sqrt(q);
         }
-        double beta_next = fmin(q * beta, beta_f);                 /* L9 */
-        double ratio = (beta_next - beta) / (beta - beta_prev);    /* L10 */
+        double beta_next = fmin(q * beta, beta_f);                 /* next temperature */
+        double ratio = (beta_next - beta) / (beta - beta_prev);    /* extrapolation */
         for (int64_t i = 0; i < n; ++i) {
             double zn = u[i] + ratio * (u[i] - zu_prev[i]);
             zu_prev[i] = u[i];
@@ -604,8 +645,8 @@ int orc_solve(int64_t n, int64_t m, const double* C, const double* r,
     return status;
 }
 
-/* Rounding onto U(r, c) (Altschuler, Weed & Rigollet 2017, Alg. 2; Alg. 1
- * L13): scale rows by min(1, r/r(P)), then columns by min(1, c/c(P')), then
+/* Rounding onto U(r, c) (Altschuler, Weed & Rigollet 2017, Alg. 2; the last
+ * step of Alg. 1): scale rows by min(1, r/r(P)), then columns by min(1, c/c(P')), then
  * add err_r err_c^T / ||err_r||_1. Writes the dense n x m plan. */
 void orc_round(int64_t n, int64_t m, const double* C, double beta,
                const double* u, const double* v, const double* r,

@@ -32,7 +32,7 @@ typedef struct {
     double gamma_init;     /* initial temperature 1/beta_i                      */
     double gamma_final;    /* final temperature 1/beta_f                        */
     double tol;            /* target L1 marginal error vs the given r, c        */
-    double p;              /* tolerance exponent of eps_d (Alg. 1 L4), 1.5      */
+    double p;              /* tolerance exponent of eps_d (Alg. 1), 1.5      */
     double q1;             /* initial decay factor q^(1), 2                     */
     double w_r;            /* row smoothing weight (Sec. 3.4), w_c = 1/2 - w_r  */
     int32_t adaptive_q;    /* AdjustSchedule on (1) or fixed q (0)              */
@@ -43,6 +43,8 @@ typedef struct {
     int32_t max_newton;    /* Newton steps per projection                       */
     int32_t max_sinkhorn;  /* ChiSinkhorn iterations per call                   */
     int32_t max_mdot;      /* temperature steps                                 */
+    int32_t projection;    /* Bregman projection step of Alg. 1: 0 TNP (Alg. 4),
+                              1 Sinkhorn (the paper's comparison baseline)      */
 } orc_opts;
 
 typedef struct {
@@ -101,6 +103,12 @@ int  orc_line_search(int64_t n, int64_t m, const double* C, double beta,
                      const double* u, const double* v, const double* grad_u,
                      const double* du, const double* dv, int32_t max_backtrack,
                      double* alpha, double* log_cP_alpha, int32_t* backtracks);
+/* Sinkhorn as the projection: alternate row and column fits until the row
+ * marginal is within eps in L1 (the column marginal is exact after each
+ * sweep), then the closing row fit of Alg. 4. */
+int  orc_sinkhorn_project(int64_t n, int64_t m, const double* C, double beta, double* u,
+                          double* v, const double* r, const double* c, double eps,
+                          const orc_opts* o, orc_stats* st);
 int  orc_tnp(int64_t n, int64_t m, const double* C, double beta, double* u,
              double* v, const double* r, const double* c, double eps,
              const orc_opts* o, double* rho0_io, double* delta_min,

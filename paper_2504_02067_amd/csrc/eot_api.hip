@@ -116,7 +116,7 @@ void carve(Arena& ar, Ctx& x, int op)
     x.sc.cg = ar.take<CgScalars>(1);
     for (int k = 0; k < 4; ++k) x.tmp_n[k] = ar.take<double>(n);
     for (int k = 0; k < 4; ++k) x.tmp_m[k] = ar.take<double>(m);
-    if (op == EOT_OP_GRADIENT) {
+    if (op == EOT_OP_GRADIENT || op == EOT_OP_ROUND) {
         GradVecs& v = x.gv;
         double** nvec[] = {&v.u, &v.sh, &v.lr, &v.a, &v.s, &v.ra, &v.g0, &v.gy0, &v.gy1, &v.gy2};
         for (double** p : nvec) *p = ar.take<double>(n);
@@ -460,7 +460,7 @@ eot_status fix_and_refresh(Ctx& x, int prec, double beta, const double* shift_gu
     return EOT_OK;
 }
 
-// Row refresh only (Alg. 4 L16), same fallback.
+// Row refresh only (after a Newton step of Alg. 4), same fallback.
 eot_status refresh(Ctx& x, int prec, double beta, const double* shift_guess, SolveState& ss)
 {
     SolveVecs& S = x.sv;
@@ -491,7 +491,7 @@ eot_status tnp(Ctx& x, int prec, double beta, double eps, double* rho0, double* 
     eot_solve_stats* st = ss.st;
     const int64_t n = x.n, m = x.m;
     int64_t p0 = x.passes;
-    // L1-L2 from exact row maxima (the potentials were extrapolated).
+    // Column fix and row marginals from exact row maxima (the potentials were extrapolated).
     EOTCHK(row_max(x, S.u, S.v, beta, S.sh));
     EOTCHK(fix_and_refresh(x, prec, beta, S.sh, ss));
     st->passes_projection += x.passes - p0;
@@ -505,14 +505,14 @@ eot_status tnp(Ctx& x, int prec, double beta, double eps, double* rho0, double* 
         double gn = 0.0;
         EOTCHK(reduce_host(x, RED_L1_DIFF_EXP, S.rt, S.lr, n, &gn));
         if (!std::isfinite(gn)) return EOT_ERR_NONFINITE;
-        if (gn <= eps) break;                                              // L3
+        if (gn <= eps) break;                                              // tolerance met
         if (stall_exit) {
             slow = (gn <= 1e-3 && gn > 0.5 * g_prev) ? slow + 1 : 0;
             if (slow >= 2 || k >= o->max_newton) { *stalled = true; break; }
         }
         g_prev = gn;
         if (k >= o->max_newton) { status = EOT_ERR_NOT_CONVERGED; break; }
-        // L4: ChiSinkhorn(eps^(2/5))
+        // ChiSinkhorn (Alg. 3) to eps^(2/5)
         const double eps_chi = std::pow(eps, 0.4);
         for (int it = 0;; ++it) {
             double chi2 = 0.0;
@@ -528,8 +528,8 @@ eot_status tnp(Ctx& x, int prec, double beta, double eps, double* rho0, double* 
         HIPCHK(launch_newton_init(S.lr, S.rt, x.nv.rP, x.nv.grad, x.nv.b, x.nv.d, n, x.s));
         double gk = 0.0;
         EOTCHK(reduce_host(x, RED_L1, x.nv.grad, nullptr, n, &gk));
-        const double eta = std::max(gk, 0.8 * eps / gk);                  // L5
-        NewtonResult nr;                                                   // L6-L7
+        const double eta = std::max(gk, 0.8 * eps / gk);                  // forcing term
+        NewtonResult nr;                                                   // Alg. 2 and d_v
         p0 = x.passes;
         EOTCHK(newton_solve(x, prec, S.u, S.v, beta, S.lr, S.s, S.rt, S.ct, eta, *rho0,
                             o->max_cg, o->max_levels, S.du, S.dv, &nr));
@@ -539,7 +539,7 @@ eot_status tnp(Ctx& x, int prec, double beta, double eps, double* rho0, double* 
         st->forcing_misses += nr.miss;
         st->rho_last = nr.rho;
         *rho0 = o->adaptive_rho0 ? std::max(0.0, 1.0 - 4.0 * (1.0 - nr.rho)) : 0.0;
-        // L8-L13: backtracking line search on the mass, FP64 passes.
+        // Backtracking line search on the mass, FP64 passes.
         double slope = 0.0;
         EOTCHK(reduce_host(x, RED_DOT, x.nv.grad, S.du, n, &slope));
         slope = -slope;
@@ -561,11 +561,11 @@ eot_status tnp(Ctx& x, int prec, double beta, double eps, double* rho0, double* 
         st->passes_linesearch += x.passes - p0;
         st->backtracks += bt;
         if (status != EOT_OK) break;
-        // L14-L15: u <- u + alpha d_u ; v <- v + alpha d_v + log c - log c(P(alpha))
+        // Step: u <- u + alpha d_u ; v <- v + alpha d_v + log c - log c(P(alpha))
         HIPCHK(launch_copy(S.ua, S.u, n, x.s));
         EOTCHK(clear_flags(x));
         HIPCHK(launch_log_ratio_fix(S.v, S.va, S.lct, S.colsum, m, x.sc.flags, x.s));
-        // L16
+        // row refresh
         p0 = x.passes;
         EOTCHK(refresh(x, prec, beta, S.sh, ss));
         st->passes_projection += x.passes - p0;
@@ -576,8 +576,52 @@ eot_status tnp(Ctx& x, int prec, double beta, double eps, double* rho0, double* 
         dmin = std::min(dmin, dk);
         ++k;
     }
-    HIPCHK(launch_add_logdiff(S.u, S.lrt, S.lr, n, x.s));                 // L18
+    HIPCHK(launch_add_logdiff(S.u, S.lrt, S.lr, n, x.s));                 // closing row fit
     *delta_min = dmin;
+    return status;
+}
+
+// Sinkhorn as the projection (the baseline the paper compares against): while
+// |r~ - r(P)|_1 > eps, a row fit u += log r~ - log r(P), the column fix and
+// the row refresh; then the closing row fit. Mixed precision: stall_exit as
+// for tnp (no 1% improvement of the best error in 200 sweeps below 1e-3).
+eot_status sinkhorn_project(Ctx& x, int prec, double beta, double eps, SolveState& ss,
+                            bool stall_exit = false, bool* stalled = nullptr)
+{
+    SolveVecs& S = x.sv;
+    const eot_solve_opts* o = ss.o;
+    eot_solve_stats* st = ss.st;
+    const int64_t n = x.n;
+    int64_t p0 = x.passes;
+    EOTCHK(row_max(x, S.u, S.v, beta, S.sh));
+    EOTCHK(fix_and_refresh(x, prec, beta, S.sh, ss));
+    st->passes_projection += x.passes - p0;
+    if (stalled) *stalled = false;
+    eot_status status = EOT_OK;
+    double best = INFINITY;
+    int32_t k = 0, since_best = 0;
+    for (;;) {
+        double gn = 0.0;
+        EOTCHK(reduce_host(x, RED_L1_DIFF_EXP, S.rt, S.lr, n, &gn));
+        if (!std::isfinite(gn)) return EOT_ERR_NONFINITE;
+        if (gn <= eps) break;
+        if (stall_exit) {
+            if (gn < 0.99 * best) { best = gn; since_best = 0; }
+            else ++since_best;
+            if ((gn <= 1e-3 && since_best >= 200) || k >= o->max_sinkhorn) {
+                *stalled = true;
+                break;
+            }
+        }
+        if (k >= o->max_sinkhorn) { status = EOT_ERR_NOT_CONVERGED; break; }
+        p0 = x.passes;
+        HIPCHK(launch_add_logdiff(S.u, S.lrt, S.lr, n, x.s));
+        EOTCHK(fix_and_refresh(x, prec, beta, S.lrt, ss));
+        st->passes_sinkhorn += x.passes - p0;
+        st->sinkhorn_iters += 1;
+        ++k;
+    }
+    HIPCHK(launch_add_logdiff(S.u, S.lrt, S.lr, n, x.s));                 // closing row fit
     return status;
 }
 
@@ -627,7 +671,9 @@ eot_status solve_impl(Ctx& x, const double* r, const double* c, const eot_solve_
     double hr = 0.0, hc = 0.0;
     EOTCHK(reduce_host(x, RED_ENTROPY, r, nullptr, n, &hr));
     EOTCHK(reduce_host(x, RED_ENTROPY, c, nullptr, m, &hc));
-    const double hmin = std::min(hr, hc);
+    // min(H(r), H(c)), floored at tol: a point-mass marginal has entropy 0,
+    // which would ask for an exact projection
+    const double hmin = std::max(std::min(hr, hc), o->tol);
     const double beta_f = 1.0 / o->gamma_final;
     const double beta_i = 1.0 / o->gamma_init;
     const double w_c = 0.5 - o->w_r;
@@ -641,26 +687,29 @@ eot_status solve_impl(Ctx& x, const double* r, const double* c, const eot_solve_
     int32_t t = 1;
     while (!done) {
         if (t > o->max_mdot) { status = EOT_ERR_NOT_CONVERGED; break; }
-        done = (beta == beta_f);                                           // L3
-        double eps_d = hmin / std::pow(beta, o->p);                        // L4
+        done = (beta == beta_f);                                           // last temperature
+        double eps_d = hmin / std::pow(beta, o->p);                        // projection tolerance
         if (done && eps_d > 0.5 * o->tol) eps_d = 0.5 * o->tol;
-        HIPCHK(launch_smooth(r, o->w_r * eps_d, 1.0 / (double)n, S.rt, S.lrt, n, x.s));   // L5
+        HIPCHK(launch_smooth(r, o->w_r * eps_d, 1.0 / (double)n, S.rt, S.lrt, n, x.s));   // smoothing (Sec. 3.4)
         HIPCHK(launch_smooth(c, w_c * eps_d, 1.0 / (double)m, S.ct, S.lct, m, x.s));
         HIPCHK(launch_recip(S.ct, S.inv_ct, m, x.s));
-        if (t == 1) {                                                      // L6
+        if (t == 1) {                                                      // initial potentials
             HIPCHK(launch_copy(S.lrt, S.u, n, x.s));
             HIPCHK(launch_copy(S.lrt, S.u_prev, n, x.s));
             HIPCHK(launch_copy(S.lct, S.v, m, x.s));
             HIPCHK(launch_copy(S.lct, S.v_prev, m, x.s));
         }
-        double dmin = INFINITY;                                            // L7
+        double dmin = INFINITY;                                            // projection
         const bool mixed = prec == EOT_PREC_MIXED;
         bool stalled = false;
-        status = tnp(x, prec, beta, 0.5 * eps_d, &rho0, &dmin, ss, mixed, &stalled);
+        const bool sk = o->projection == EOT_PROJ_SINKHORN;
+        status = sk ? sinkhorn_project(x, prec, beta, 0.5 * eps_d, ss, mixed, &stalled)
+                    : tnp(x, prec, beta, 0.5 * eps_d, &rho0, &dmin, ss, mixed, &stalled);
         st->mixed_stalls += stalled ? 1 : 0;
         if (status == EOT_OK && done && mixed && o->verify_fp64) {
             double dmin64 = INFINITY;
-            status = tnp(x, EOT_PREC_FP64, beta, 0.5 * eps_d, &rho0, &dmin64, ss);
+            status = sk ? sinkhorn_project(x, EOT_PREC_FP64, beta, 0.5 * eps_d, ss)
+                        : tnp(x, EOT_PREC_FP64, beta, 0.5 * eps_d, &rho0, &dmin64, ss);
         } else if (status == EOT_OK && done && stalled) {
             status = EOT_ERR_NOT_CONVERGED;
         }
@@ -668,12 +717,12 @@ eot_status solve_impl(Ctx& x, const double* r, const double* c, const eot_solve_
         st->mdot_steps = t;
         st->final_gamma = 1.0 / beta;
         if (status != EOT_OK || done) break;
-        if (o->adaptive_q) {                                               // L8
+        if (o->adaptive_q) {                                               // AdjustSchedule (Sec. 3.3)
             if (dmin > 0.95) q = std::min(2.0, q * q);
             else if (dmin < 0.8) q = std::sqrt(q);
         }
-        const double beta_next = std::min(q * beta, beta_f);               // L9
-        const double ratio = (beta_next - beta) / (beta - beta_prev);      // L10
+        const double beta_next = std::min(q * beta, beta_f);               // next temperature
+        const double ratio = (beta_next - beta) / (beta - beta_prev);      // extrapolation
         HIPCHK(launch_extrapolate(S.u, S.u_prev, ratio, n, x.s));
         HIPCHK(launch_extrapolate(S.v, S.v_prev, ratio, m, x.s));
         beta_prev = beta;
@@ -697,7 +746,7 @@ bool bad_opts(const eot_solve_opts& o)
     return bad_gamma(o.gamma_init) || bad_gamma(o.gamma_final) || !(o.tol > 0.0) ||
            !(o.p >= 1.0) || !(o.q1 > 1.0) || !(o.w_r > 0.0 && o.w_r < 0.5) || o.max_cg < 1 ||
            o.max_levels < 0 || o.max_backtrack < 0 || o.max_newton < 0 || o.max_sinkhorn < 0 ||
-           o.max_mdot < 1;
+           o.max_mdot < 1 || (o.projection != EOT_PROJ_TNP && o.projection != EOT_PROJ_SINKHORN);
 }
 
 size_t align_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
@@ -827,6 +876,82 @@ eot_status gradient_impl(Ctx& x, double gamma, const double* f, const double* g,
     return status;
 }
 
+// ---------------------------------------------------------------- rounding
+// Rounding of the plan onto U(r, c), the last step of Alg. 1; see eot_round in eot.h.
+// All passes FP64. Uses the gradient's vectors: n-side u, sh, a (row sums of
+// P o C), g0 (r(P)), ra (x), gy0 (er), gy1 (zeros); m-side v, cP, tm (column
+// sums of D(x) P), cb (y), mu (ec), h0 (zeros).
+eot_status round_impl(Ctx& x, double gamma, const double* f, const double* g, const double* r,
+                      const double* c, double* xo, double* yo, double* ero, double* eco,
+                      double* plan, int64_t ldp, eot_round_info* info)
+{
+    GradVecs& G = x.gv;
+    const int64_t n = x.n, m = x.m;
+    const double beta = 1.0 / gamma;
+    const bool pts = x.cost.kind == EOT_COST_SQEUCLID_POINTS;
+    const double cs = pts ? 1.0 / x.cost.scale : 1.0;
+    double* xs = xo ? xo : G.ra;
+    double* ys = yo ? yo : G.cb;
+    double* er = ero ? ero : G.gy0;
+    double* ec = eco ? eco : G.mu;
+    HIPCHK(launch_divs(f, gamma, G.u, n, x.s));
+    HIPCHK(launch_divs(g, gamma, G.v, m, x.s));
+    EOTCHK(row_max(x, G.u, G.v, beta, G.sh));
+    // r(P), (P o C) 1, c(P)
+    PassArgs A = make_args(x, G.u, G.sh, G.v, beta);
+    HIPCHK(run_pass(x, A, EOT_PREC_FP64, 2, 1, R2_COST));
+    x.passes += 1;
+    HIPCHK(launch_merge_rows(x.sc.row_part, x.rtiles, n, 2, G.sh, G.g0, G.a, 0, x.s));
+    HIPCHK(launch_merge_cols(x.sc.col_part, x.ctiles, m, 1, G.cP, nullptr, x.s));
+    double cost_plan = 0.0, err_r = 0.0, err_c = 0.0;
+    EOTCHK(reduce_host(x, RED_SUM, G.a, nullptr, n, &cost_plan));
+    HIPCHK(launch_round_err(r, nullptr, G.g0, er, n, x.s));
+    EOTCHK(reduce_host(x, RED_L1, er, nullptr, n, &err_r));
+    HIPCHK(launch_round_err(c, nullptr, G.cP, ec, m, x.s));
+    EOTCHK(reduce_host(x, RED_L1, ec, nullptr, m, &err_c));
+    // x = min(1, r / r(P)); column sums of D(x) P; y = min(1, c / that)
+    HIPCHK(launch_round_scale(r, G.g0, xs, n, x.s));
+    PassArgs B = make_args(x, G.u, G.sh, G.v, beta);
+    B.xw0 = xs;
+    HIPCHK(run_pass(x, B, EOT_PREC_FP64, 0, 1, R2_WEIGHT));
+    x.passes += 1;
+    HIPCHK(launch_merge_cols(x.sc.col_part, x.ctiles, m, 1, G.tm, nullptr, x.s));
+    HIPCHK(launch_round_scale(c, G.tm, ys, m, x.s));
+    HIPCHK(launch_round_err(c, ys, G.tm, ec, m, x.s));
+    // row sums of P D(y) and of (P o C) D(y): er = r - x o P y, cost of D(x) P D(y)
+    PassArgs D = make_args(x, G.u, G.sh, G.v, beta);
+    D.yw0 = ys;
+    D.yw1 = ys;
+    HIPCHK(run_pass(x, D, EOT_PREC_FP64, 2, 0, R2_COST));
+    x.passes += 1;
+    HIPCHK(launch_merge_rows(x.sc.row_part, x.rtiles, n, 2, G.sh, G.g0, G.a, 0, x.s));
+    HIPCHK(launch_round_err(r, xs, G.g0, er, n, x.s));
+    double cost_scaled = 0.0, nr = 0.0;
+    EOTCHK(reduce_host(x, RED_DOT, xs, G.a, n, &cost_scaled));
+    EOTCHK(reduce_host(x, RED_L1, er, nullptr, n, &nr));
+    // er^T C ec: a pass with beta = 0 and zero potentials, so every plan entry is 1
+    double fix = 0.0;
+    if (nr > 0.0) {
+        HIPCHK(launch_fill(G.gy1, 0.0, n, x.s));
+        HIPCHK(launch_fill(G.h0, 0.0, m, x.s));
+        PassArgs Z = make_args(x, G.gy1, G.gy1, G.h0, 0.0);
+        Z.yw1 = ec;
+        HIPCHK(run_pass(x, Z, EOT_PREC_FP64, 2, 0, R2_COST));
+        x.passes += 1;
+        HIPCHK(launch_merge_rows(x.sc.row_part, x.rtiles, n, 2, G.gy1, nullptr, G.g0, 0, x.s));
+        EOTCHK(reduce_host(x, RED_DOT, er, G.g0, n, &fix));
+        fix /= nr;
+    }
+    if (plan) HIPCHK(launch_plan_round(A, xs, ys, er, ec, nr > 0.0 ? 1.0 / nr : 0.0, plan, ldp, x.s));
+    HIPCHK(hipStreamSynchronize(x.s));
+    info->cost_plan = cost_plan * cs;
+    info->cost_round = (cost_scaled + fix) * cs;
+    info->err_r = err_r;
+    info->err_c = err_c;
+    info->mass_fix = nr;
+    return EOT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -836,7 +961,7 @@ eot_status eot_workspace_size(int32_t op, const eot_cost* cost, int32_t prec, si
     if (!bytes) return EOT_ERR_INVALID_ARG;
     eot_status cs = check_cost(cost);
     if (cs != EOT_OK) return cs;
-    if (op < EOT_OP_MARGINALS || op > EOT_OP_GRADIENT) return EOT_ERR_INVALID_ARG;
+    if (op < EOT_OP_MARGINALS || op > EOT_OP_ROUND) return EOT_ERR_INVALID_ARG;
     (void)prec;
     Ctx x;
     x.n = cost->n;
@@ -983,6 +1108,7 @@ void eot_solve_opts_default(eot_solve_opts* o)
     o->max_mdot = 500;
     o->precision = EOT_PREC_FP64;
     o->verify_fp64 = 1;
+    o->projection = EOT_PROJ_TNP;
 }
 
 eot_status eot_solve(const eot_cost* cost, const double* r, const double* c,
@@ -1105,6 +1231,20 @@ eot_status eot_gradient(const eot_cost* cost, double gamma, const double* f, con
     EOTCHK(setup(x, cost, EOT_OP_GRADIENT, prec, ws, ws_bytes, stream));
     return gradient_impl(x, gamma, f, g, w_W, w_S, grad_C, ldg, grad_X, grad_Y, grad_r, grad_c,
                          info, prec);
+}
+
+eot_status eot_round(const eot_cost* cost, double gamma, const double* f, const double* g,
+                     const double* r, const double* c, double* xo, double* yo, double* ero,
+                     double* eco, double* plan, int64_t ldp, eot_round_info* info, void* ws,
+                     size_t ws_bytes, void* stream)
+{
+    if (!f || !g || !r || !c || !info || bad_gamma(gamma)) return EOT_ERR_INVALID_ARG;
+    EOTCHK(check_cost(cost));
+    if (plan && (cost->kind == EOT_COST_SQEUCLID_POINTS || ldp < cost->m))
+        return EOT_ERR_INVALID_ARG;
+    Ctx x;
+    EOTCHK(setup(x, cost, EOT_OP_ROUND, EOT_PREC_FP64, ws, ws_bytes, stream));
+    return round_impl(x, gamma, f, g, r, c, xo, yo, ero, eco, plan, ldp, info);
 }
 
 eot_status eot_pass_timing(int32_t enable)

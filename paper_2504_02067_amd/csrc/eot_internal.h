@@ -124,6 +124,16 @@ hipError_t launch_fill(double* x, double val, int64_t k, hipStream_t s);
 hipError_t launch_lincomb(double* out, int64_t k, double alpha, const double* x, double beta,
                           const double* y, double c0, hipStream_t s);
 
+// Rounding onto U(r, c) (the last step of Alg. 1): out = min(1, t / sum) (1 where sum = 0);
+// out = t - x o sum (x nullable = 1); dense rounded plan x_i P_ij y_j + er_i ec_j inv_nr.
+hipError_t launch_round_scale(const double* t, const double* sum, double* out, int64_t k,
+                              hipStream_t s);
+hipError_t launch_round_err(const double* t, const double* x, const double* sum, double* out,
+                            int64_t k, hipStream_t s);
+hipError_t launch_plan_round(const PassArgs& a, const double* x, const double* y, const double* er,
+                             const double* ec, double inv_nr, double* out, int64_t ldo,
+                             hipStream_t s);
+
 // Gradients. Dense cotangent G_ij = P_ij (ra_i + cb_j + kappa C_ij) into G (ldg).
 hipError_t launch_plan_grad(const PassArgs& a, const double* ra, const double* cb, double kappa,
                             double* G, int64_t ldg, hipStream_t s);

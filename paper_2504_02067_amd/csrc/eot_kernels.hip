@@ -3,7 +3,7 @@
 // The hot path is the streaming pass over the implicit plan
 //     P_ij = exp(u_i + v_j - beta C_ij)            (eq. lagrangian-closed-form)
 // that serves every O(nm) primitive of the method: the LSE_r / LSE_c
-// marginals (Sec. 2 Notation; Alg. 3 L3-L4, Alg. 4 L1, L2, L9, L16), the two
+// marginals (Sec. 2 Notation; used throughout Algs. 3 and 4), the two
 // halves of the reduced Newton operator F_r(rho) p = r(P) p - rho P (P^T p / c)
 // (eq. matrix-definitions) inside CG, the discounted Hessian-vector product
 // (eq. discounted-hessian) and the preconditioner diagonal sum_j P_ij^2 / c_j
@@ -1102,6 +1102,56 @@ __global__ void k_lincomb(double* out, int64_t k, double alpha, const double* x,
     }
 }
 
+// Rounding onto U(r, c): out = t / s clipped to 1 (1 where s = 0), and the
+// marginal deficits t - x s.
+__global__ void k_round_scale(const double* t, const double* sum, double* out, int64_t k)
+{
+    EW_LOOP(k) out[i] = sum[i] > 0.0 ? fmin(1.0, t[i] / sum[i]) : 1.0;
+}
+__global__ void k_round_err(const double* t, const double* x, const double* sum, double* out,
+                            int64_t k)
+{
+    EW_LOOP(k) out[i] = t[i] - (x ? x[i] : 1.0) * sum[i];
+}
+
+// Dense rounded plan: out_ij = x_i P_ij y_j + er_i ec_j / |er|_1, FP64.
+template <typename TC>
+__global__ __launch_bounds__(256) void k_plan_round(const TC* __restrict__ C, int64_t ldc,
+                                                    int64_t n, int64_t m,
+                                                    const double* __restrict__ u,
+                                                    const double* __restrict__ v, double beta,
+                                                    const double* __restrict__ x,
+                                                    const double* __restrict__ y,
+                                                    const double* __restrict__ er,
+                                                    const double* __restrict__ ec, double inv_nr,
+                                                    double* __restrict__ out, int64_t ldo)
+{
+    const int64_t j0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    const int64_t i0 = (int64_t)blockIdx.y * kGradRows;
+    if (j0 >= m) return;
+    double vj[4], yj[4], ej[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const bool ok = j0 + q < m;
+        vj[q] = ok ? v[j0 + q] : 0.0;
+        yj[q] = ok ? y[j0 + q] : 0.0;
+        ej[q] = ok ? ec[j0 + q] * inv_nr : 0.0;
+    }
+    for (int r = 0; r < kGradRows; ++r) {
+        const int64_t i = i0 + r;
+        if (i >= n) break;
+        const double ui = u[i], xi = x[i], ei = er[i];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t j = j0 + q;
+            if (j < m) {
+                const double P = exp(fma(-beta, (double)C[i * ldc + j], ui + vj[q]));
+                out[i * ldo + j] = fma(xi * P, yj[q], ei * ej[q]);
+            }
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_plan_grad(const PassArgs& a, const double* ra, const double* cb, double kappa,
@@ -1150,6 +1200,24 @@ hipError_t launch_points_grad_finish(const float* X, int64_t n, int d, double tw
 {
     hipLaunchKernelGGL(k_points_grad_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X,
                        n, d, two_over_s, g0, gy0, gy1, gy2, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_round(const PassArgs& a, const double* x, const double* y, const double* er,
+                             const double* ec, double inv_nr, double* out, int64_t ldo,
+                             hipStream_t s)
+{
+    dim3 grid((unsigned)((a.m + 1023) / 1024), (unsigned)((a.n + kGradRows - 1) / kGradRows));
+    if (a.kind == EOT_COST_DENSE_F32)
+        hipLaunchKernelGGL((k_plan_round<float>), grid, dim3(256), 0, s,
+                           static_cast<const float*>(a.C), a.ldc, a.n, a.m, a.u, a.v, a.beta, x, y,
+                           er, ec, inv_nr, out, ldo);
+    else if (a.kind == EOT_COST_DENSE_F64)
+        hipLaunchKernelGGL((k_plan_round<double>), grid, dim3(256), 0, s,
+                           static_cast<const double*>(a.C), a.ldc, a.n, a.m, a.u, a.v, a.beta, x, y,
+                           er, ec, inv_nr, out, ldo);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -1394,6 +1462,18 @@ hipError_t launch_cg_direction(const double* red, int nb, const double* z, doubl
                        n, sc);
     hipLaunchKernelGGL(k_cg_tail, dim3(1), dim3(kVecThreads), 0, s, red, nb, sc);
     return hipGetLastError();
+}
+
+hipError_t launch_round_scale(const double* t, const double* sum, double* out, int64_t k,
+                              hipStream_t s)
+{
+    EW_LAUNCH(k_round_scale, k, t, sum, out, k);
+}
+
+hipError_t launch_round_err(const double* t, const double* x, const double* sum, double* out,
+                            int64_t k, hipStream_t s)
+{
+    EW_LAUNCH(k_round_err, k, t, x, sum, out, k);
 }
 
 }  // namespace eot

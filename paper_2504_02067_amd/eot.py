@@ -36,6 +36,9 @@ EOT_OP_HVP = 1
 EOT_OP_NEWTON_CG = 2
 EOT_OP_SOLVE = 3
 EOT_OP_GRADIENT = 4
+EOT_OP_ROUND = 5
+EOT_PROJ_TNP = 0
+EOT_PROJ_SINKHORN = 1
 
 _c_i32, _c_i64, _c_f64, _c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 
@@ -56,7 +59,8 @@ class eot_solve_opts(ctypes.Structure):
                 ("q1", _c_f64), ("w_r", _c_f64), ("adaptive_q", _c_i32),
                 ("adaptive_rho0", _c_i32), ("max_cg", _c_i32), ("max_levels", _c_i32),
                 ("max_backtrack", _c_i32), ("max_newton", _c_i32), ("max_sinkhorn", _c_i32),
-                ("max_mdot", _c_i32), ("precision", _c_i32), ("verify_fp64", _c_i32)]
+                ("max_mdot", _c_i32), ("precision", _c_i32), ("verify_fp64", _c_i32),
+                ("projection", _c_i32)]
 
 
 class eot_solve_stats(ctypes.Structure):
@@ -76,6 +80,14 @@ class eot_solve_stats(ctypes.Structure):
 # Every entry point declared in include/eot.h, with its ctypes signature.
 class eot_batch_problem(ctypes.Structure):
     _fields_ = [("cost", eot_cost), ("r", _c_vp), ("c", _c_vp), ("f", _c_vp), ("g", _c_vp)]
+
+
+class eot_round_info(ctypes.Structure):
+    _fields_ = [("cost_round", _c_f64), ("cost_plan", _c_f64), ("err_r", _c_f64),
+                ("err_c", _c_f64), ("mass_fix", _c_f64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class eot_grad_info(ctypes.Structure):
@@ -105,6 +117,9 @@ SIGNATURES = {
                                    ctypes.POINTER(eot_solve_opts), _c_i32,
                                    ctypes.POINTER(eot_solve_stats), ctypes.POINTER(_c_i32), _c_vp,
                                    ctypes.c_size_t, _c_vp]),
+    "eot_round": (_c_i32, [ctypes.POINTER(eot_cost), _c_f64, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
+                           _c_vp, _c_vp, _c_vp, _c_vp, _c_i64, ctypes.POINTER(eot_round_info),
+                           _c_vp, ctypes.c_size_t, _c_vp]),
     "eot_gradient": (_c_i32, [ctypes.POINTER(eot_cost), _c_f64, _c_vp, _c_vp, _c_f64, _c_f64,
                               _c_vp, _c_i64, _c_vp, _c_vp, _c_vp, _c_vp,
                               ctypes.POINTER(eot_grad_info), _c_i32, _c_vp, ctypes.c_size_t,
@@ -299,9 +314,14 @@ def eot_newton_cg(C, gamma, f, g, r, c, eta, rho0=0.0, max_cg=1000, max_levels=3
 def default_solve_opts(**kw) -> eot_solve_opts:
     o = eot_solve_opts()
     lib().eot_solve_opts_default(ctypes.byref(o))
+    names = {k for k, _ in eot_solve_opts._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"unknown solve option {k!r}")
         if k == "precision":
             v = _prec(v)
+        if k == "projection":
+            v = {"tnp": EOT_PROJ_TNP, "sinkhorn": EOT_PROJ_SINKHORN}.get(v, v)
         setattr(o, k, v)
     return o
 
@@ -361,6 +381,31 @@ def eot_solve_batched(problems, opts: Optional[eot_solve_opts] = None, workers=8
     if check:
         _check(st, "eot_solve_batched", allow)
     return outs, [stats[i].as_dict() for i in range(k)], [int(status[i]) for i in range(k)]
+
+
+def eot_round(C, gamma, f, g, r, c, plan=False):
+    """Rounding of the plan at (f, g) onto U(r, c). Returns a dict with x, y, er,
+    ec (the implicit rounded plan D(x) P D(y) + er ec^T / |er|_1), the dense
+    rounded plan when ``plan`` (dense costs only) and the eot_round_info
+    fields."""
+    cost = make_cost(C)
+    n, m = cost.n, cost.m
+    dev = C.device
+    out = {k: torch.empty(sz, dtype=torch.float64, device=dev)
+           for k, sz in (("x", n), ("y", m), ("er", n), ("ec", m))}
+    out["plan"] = torch.empty((n, m), dtype=torch.float64, device=dev) if plan else None
+    info = eot_round_info()
+    ws = workspace(EOT_OP_ROUND, cost, EOT_PREC_FP64, dev)
+    P = out["plan"]
+    st = lib().eot_round(ctypes.byref(cost), float(gamma), _vec(f, n, "f"), _vec(g, m, "g"),
+                         _vec(r, n, "r"), _vec(c, m, "c"), _vec(out["x"], n, "x"),
+                         _vec(out["y"], m, "y"), _vec(out["er"], n, "er"), _vec(out["ec"], m, "ec"),
+                         None if P is None else ctypes.c_void_p(P.data_ptr()), m,
+                         ctypes.byref(info), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                         _stream(dev))
+    _check(st, "eot_round")
+    out.update(info.as_dict())
+    return out
 
 
 def eot_gradient(C, gamma, f, g, w_W=1.0, w_S=0.0, want=None, tol=1e-11, max_cg=5000,

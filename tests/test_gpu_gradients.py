@@ -158,3 +158,53 @@ def test_autograd_points_backward_runs_the_library():
     say("autograd points")
     close(host(X.grad).astype(np.float64), gX, 1e-6)
     close(host(Y.grad).astype(np.float64), gY, 1e-6)
+
+
+# ---------------------------------------------------------------- rounding
+
+@pytest.mark.parametrize("n,m,prec", [(150, 230, "fp64"), (300, 2100, "mixed"), (1, 7, "fp64")])
+def test_round_parity(n, m, prec):
+    gamma = 0.05
+    rng = np.random.default_rng(n * m)
+    C = rng.uniform(0, 1, size=(n, m)).astype(np.float32)
+    r = rng.dirichlet(np.ones(n)) + 1e-3; r /= r.sum()
+    c = rng.dirichlet(np.ones(m)) + 1e-3; c /= c.sum()
+    Cd = torch.from_numpy(C).to(DEV)
+    f, g, st = eot.eot_solve(Cd, dvec(r), dvec(c), gamma_init=1.0 / 8.0, gamma_final=gamma,
+                             tol=1e-4, precision=prec)
+    say(f"round n={n} m={m}")
+    out = eot.eot_round(Cd, gamma, f, g, dvec(r), dvec(c), plan=True)
+    u, v = O.to_log_units(host(f), host(g), gamma)
+    Pr = O.round_plan(C, 1.0 / gamma, u, v, r, c)
+    X = host(out["plan"])
+    # the deficits er = r - r(D(x) P D(y)) and ec cancel (they are ~tol of r and
+    # c), so their rounding, O(1e-16) of r_i and c_j, reaches the rank-one
+    # correction er_i ec_j / |er|_1 as ~1e-16 r_i c_j / |er|_1
+    nr = max(out["mass_fix"], 1e-300)
+    bound = 1e-12 * np.abs(Pr) + 1e-13 * np.outer(r, c) / nr
+    assert np.all(np.abs(X - Pr) <= bound)
+    np.testing.assert_allclose(X.sum(1), r, rtol=1e-12)
+    np.testing.assert_allclose(X.sum(0), c, rtol=1e-12)
+    Cd64 = C.astype(np.float64)
+    assert out["cost_round"] == pytest.approx((Pr * Cd64).sum(), rel=1e-12)
+    P = OG.plan(C, 1.0 / gamma, u, v)
+    assert out["cost_plan"] == pytest.approx((P * Cd64).sum(), rel=1e-12)
+    assert out["err_r"] == pytest.approx(np.abs(P.sum(1) - r).sum(), rel=1e-9, abs=1e-15)
+    # the implicit form gives the same matrix
+    Xi = (host(out["x"])[:, None] * P * host(out["y"])[None, :]
+          + np.outer(host(out["er"]), host(out["ec"])) / max(out["mass_fix"], 1e-300))
+    assert np.all(np.abs(Xi - Pr) <= bound)
+
+
+def test_round_points_cost_matches_dense():
+    gamma = 0.02
+    p = W.point_cloud_problem(n=500, m=300, d=3, seed=90)
+    pc = eot.PointCloud(torch.from_numpy(p.X).to(DEV), torch.from_numpy(p.Y).to(DEV), p.scale)
+    f, g, st = eot.eot_solve(pc, dvec(p.r), dvec(p.c), gamma_init=1.0 / 8.0, gamma_final=gamma,
+                             tol=1e-3)
+    say("round points")
+    out = eot.eot_round(pc, gamma, f, g, dvec(p.r), dvec(p.c))
+    C = O.sqeuclid_points_cost(p.X, p.Y, p.scale)
+    u, v = O.to_log_units(host(f), host(g), gamma)
+    Pr = O.round_plan(C, 1.0 / gamma, u, v, p.r, p.c)
+    assert out["cost_round"] == pytest.approx((Pr * C).sum(), rel=1e-11)

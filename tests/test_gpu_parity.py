@@ -262,3 +262,34 @@ def test_full_size_sampled_marginals():
         assert abs(m1 - m2) <= 10 * tol * m1
     del C
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("seed", [1000, 1001])
+def test_sinkhorn_projection_parity_fp64(seed):
+    """MDOT with the Sinkhorn projection (the paper's baseline) on the same
+    streaming passes, against the oracle's MDOT-Sinkhorn: same number of
+    sweeps and temperature steps, cost within 1e-10."""
+    p = W.small_points_problem(seed)
+    kw = dict(gamma_init=1e-1, gamma_final=1e-2, tol=1e-9)
+    say(f"MDOT-Sinkhorn {p.name}")
+    C = torch.from_numpy(p.C).to(DEV)
+    f, g, st = eot.eot_solve(C, dvec(p.r), dvec(p.c), projection="sinkhorn", **kw)
+    u, v, ost = O.solve(p.C, p.r, p.c, projection=1, **kw)
+    assert st["status"] == 0 and ost["status"] == 0
+    assert st["sinkhorn_iters"] == ost["sinkhorn_iters"] and st["mdot_steps"] == ost["mdot_steps"]
+    assert st["newton_steps"] == 0
+    assert abs(st["cost"] - ost["cost"]) <= 1e-10 * ost["cost"]
+
+
+def test_sinkhorn_projection_mixed_grid784():
+    p = W.mnist_like_problem(2000, "sqeuclid")
+    kw = dict(gamma_init=p.gamma_init, gamma_final=1e-2, tol=1e-6)
+    say("MDOT-Sinkhorn grid784 mixed vs fp64")
+    C = torch.from_numpy(p.C).to(DEV)
+    f, g, st = eot.eot_solve(C, dvec(p.r), dvec(p.c), projection="sinkhorn", precision="mixed", **kw)
+    f2, g2, st2 = eot.eot_solve(C, dvec(p.r), dvec(p.c), projection="sinkhorn", **kw)
+    say(f"  mixed {st['seconds']:.2f}s sweeps={st['sinkhorn_iters']} | fp64 {st2['seconds']:.2f}s "
+        f"sweeps={st2['sinkhorn_iters']}")
+    assert st["status"] == 0 and st2["status"] == 0
+    assert st["err_r"] + st["err_c"] <= 1e-6
+    assert abs(st["cost"] - st2["cost"]) <= 1e-5 * st2["cost"]

@@ -34,7 +34,7 @@ def instance(n, m, seed, beta=5.0, spread=1.0):
 
 
 def fixed_cols(C, beta, u, c):
-    """v with c(P) = c (the column fix of Alg. 4 L1), from the oracle's
+    """v with c(P) = c (the column fix that opens Alg. 4), from the oracle's
     column LSE."""
     lc = O.log_col_marginal(C, beta, u, np.zeros(C.shape[1]))
     return np.log(c) - lc
@@ -288,7 +288,7 @@ def test_newton_solve_warm_discount_starts_at_rho0():
 # ------------------------------------------------------------ line search
 
 def test_line_search_is_armijo_on_the_dual():
-    # lemma "suffdecr": the mass test of Alg. 4 L10 is Armijo with c1 = 0.01
+    # lemma "suffdecr": the mass test of Alg. 4's line search is Armijo with c1 = 0.01
     C, r, c, u, v, beta = instance(7, 9, 12, beta=25.0, spread=1.0)
     v = fixed_cols(C, beta, u, c)
     lr = O.log_row_marginal(C, beta, u, v)
@@ -333,7 +333,7 @@ def test_tnp_reaches_tolerance_and_dual_decreases():
     assert status == 0 and st["newton_steps"] >= 1
     rP = np.exp(O.log_row_marginal(C, beta, u2, v2))
     cP = np.exp(O.log_col_marginal(C, beta, u2, v2))
-    assert np.abs(rP - r).sum() <= 1e-14          # L18 matches the rows exactly
+    assert np.abs(rP - r).sum() <= 1e-14          # the closing row fit matches the rows exactly
     assert np.abs(cP - c).sum() <= eps * 1.001     # columns moved by < ||r - r(P)||_1
     assert O.dual(C, beta, u2, v2, r, c) <= g_start
 
@@ -523,3 +523,30 @@ def test_points_cost_reduces_to_integer_grid_cost():
     # one brute-force entry
     i, j = 3, 11
     assert C1[i, j] == sum(int(X[i, k] - Y[j, k]) ** 2 for k in range(3)) / s
+
+
+def test_sinkhorn_projection_reaches_the_same_optimum():
+    # MDOT with Sinkhorn as the projection (the paper's comparison baseline)
+    # must reach the unique entropic optimum that MDOT + TNP reaches.
+    from paper_2504_02067_amd import workloads as W
+    p = W.small_points_problem(1003, n=24)
+    kw = dict(gamma_init=1e-1, gamma_final=2e-2, tol=1e-11)
+    u1, v1, s1 = O.solve(p.C, p.r, p.c, **kw)
+    u2, v2, s2 = O.solve(p.C, p.r, p.c, projection=1, **kw)
+    assert s1["status"] == 0 and s2["status"] == 0
+    assert s2["newton_steps"] == 0 and s2["sinkhorn_iters"] > s1["sinkhorn_iters"]
+    assert s2["cost"] == pytest.approx(s1["cost"], rel=1e-9)
+    t = np.mean(u1 - u2)                      # potentials agree up to the gauge
+    np.testing.assert_allclose(u1 - t, u2, atol=1e-8)
+    np.testing.assert_allclose(v1 + t, v2, atol=1e-8)
+
+
+def test_point_mass_marginal_has_the_only_feasible_plan():
+    # n = 1: U(r, c) holds the single plan P_1j = c_j, so any temperature gives
+    # cost sum_j c_j C_1j (the entropy floor keeps the projection reachable)
+    rng = np.random.default_rng(7)
+    C = rng.uniform(0, 1, (1, 7)); r = np.array([1.0])
+    c = rng.dirichlet(np.ones(7)) + 1e-3; c /= c.sum()
+    u, v, st = O.solve(C, r, c, gamma_init=1 / 8, gamma_final=0.05, tol=1e-8)
+    assert st["status"] == 0
+    assert st["cost"] == pytest.approx(float(c @ C[0]), rel=1e-7)
