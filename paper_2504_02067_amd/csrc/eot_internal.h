@@ -14,7 +14,22 @@ constexpr int kVec = 4;                  // consecutive columns per thread per r
 constexpr int kChunks = 2;               // column chunks of 1024 per tile
 constexpr int kTileCols = kPassThreads * kVec * kChunks;   // 2048
 constexpr int kTileRows = 256;           // rows per tile (column partials per band)
-constexpr int kSubRows = 8;              // rows per chunk in flight per thread
+// Rows per chunk in flight per thread: passes with one kind of sum, and passes
+// with both row and column sums (more accumulators). Build-time tunables.
+#ifndef EOT_SUB_ROWS
+#define EOT_SUB_ROWS 4
+#endif
+#ifndef EOT_SUB_ROWS_FUSED
+#define EOT_SUB_ROWS_FUSED 4
+#endif
+constexpr int kSubRows = EOT_SUB_ROWS;
+constexpr int kSubRowsFused = EOT_SUB_ROWS_FUSED;
+// Optional occupancy request (waves per SIMD) for the fused passes, build-time.
+#if defined(EOT_FUSED_WAVES_PER_EU) && EOT_FUSED_WAVES_PER_EU > 0
+#define EOT_FUSED_OCCUPANCY __attribute__((amdgpu_waves_per_eu(EOT_FUSED_WAVES_PER_EU)))
+#else
+#define EOT_FUSED_OCCUPANCY
+#endif
 constexpr int kWaves = kPassThreads / 64;
 // Row partials are written per wave: [nr][tiles_m * kWaves][n].
 inline int row_tiles(int tiles_m) { return tiles_m * kWaves; }

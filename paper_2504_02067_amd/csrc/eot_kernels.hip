@@ -114,15 +114,6 @@ __device__ __forceinline__ void load4(const double* __restrict__ row, int64_t jb
     }
 }
 
-template <typename TC>
-__device__ __forceinline__ void load_row_vec_d(const TC* __restrict__ row, int64_t jb, int64_t m,
-                                               bool vec_ok, double (&out)[kVec])
-{
-#pragma unroll
-    for (int q = 0; q < kVec; ++q) out[q] = (jb + q < m) ? (double)row[jb + q] : 0.0;
-    (void)vec_ok;
-}
-
 // Sum over the 64 lanes of a wave of G per-lane values at once (a butterfly
 // transpose-reduction in registers, no LDS, no barrier): after it, lane l holds
 // the full sum of value g = (l >> (6 - log2 G)) & (G - 1) in v[0], valid on
@@ -206,7 +197,7 @@ __device__ __forceinline__ void load_rows(const TC* __restrict__ C, int64_t ldc,
 // (the O(n)-memory variant of Sec. 4.2): x rows in LDS, y columns in
 // registers; the 1/scale of the cost is folded into beta by the host.
 template <int PREC, typename TC, int NR, int NC, int MODE2, bool VEC, int RS, int DP>
-__global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs A)
+__device__ __forceinline__ void pass_body(const PassArgs& A)
 {
     if (A.skip && *A.skip) return;             // uniform: a finished CG chunk
     constexpr bool MIXED = PREC == EOT_PREC_MIXED;
@@ -474,73 +465,156 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs A)
     }
 }
 
-// max via compare-and-swap on the bit pattern (values are never NaN here)
-__device__ __forceinline__ void atomic_max_f64(double* addr, double val)
+template <int PREC, typename TC, int NR, int NC, int MODE2, bool VEC, int RS, int DP>
+__global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs A)
 {
-    unsigned long long* a = reinterpret_cast<unsigned long long*>(addr);
-    unsigned long long old = *a;
-    while (__longlong_as_double((long long)old) < val) {
-        const unsigned long long assumed = old;
-        old = atomicCAS(a, assumed, (unsigned long long)__double_as_longlong(val));
-        if (old == assumed) break;
-    }
+    pass_body<PREC, TC, NR, NC, MODE2, VEC, RS, DP>(A);
 }
 
-// Exact row maxima of u_i + v_j - beta C_ij, FP64; one partial per column tile,
-// or (A.atomic) an atomic max into part[0..n), pre-filled with -inf.
-// DP > 0: C_ij = |x_i - y_j|^2 (beta already divided by the cost scale).
-template <typename TC, int DP>
-__global__ __launch_bounds__(kPassThreads) void k_rowmax(PassArgs A, double* part)
+// The fused passes (row and column sums) hold the most registers; their
+// occupancy request is a separate build-time tunable.
+template <int PREC, typename TC, int NR, int NC, int MODE2, bool VEC, int RS, int DP>
+__global__ __launch_bounds__(kPassThreads) EOT_FUSED_OCCUPANCY void k_pass_fused(PassArgs A)
 {
-    constexpr int NCH = kChunks, V = kVec, T = kPassThreads;
-    __shared__ double s_w[kWaves];
-    const int tid = threadIdx.x;
+    pass_body<PREC, TC, NR, NC, MODE2, VEC, RS, DP>(A);
+}
+
+
+// Row shifts a_i ~ max_j (u_i + v_j - beta C_ij). They only keep the shifted
+// row sums of the passes in range (every pass evaluates exp(x_ij - a_i) from the
+// FP64 potentials, whatever a_i is), so they are computed in FP32: for |x| up
+// to ~1e5 the error is ~1e-2, far inside the range guard. A block covers 256
+// rows and `span` consecutive column tiles; each wave keeps per-row maxima in
+// LDS; one output per (block, row): a partial [gridDim.x][n], or (A.atomic) an
+// atomic max into out32[0..n) (float bits, pre-filled with -inf).
+// DP > 0: C_ij = |x_i - y_j|^2 (beta already divided by the cost scale).
+__device__ __forceinline__ float wave_max_f(float x)
+{
+    for (int off = 32; off > 0; off >>= 1) x = fmaxf(x, __shfl_xor(x, off, 64));
+    return x;
+}
+
+// atomic max of a float through the integer order of its bits
+__device__ __forceinline__ void atomic_max_f32(float* addr, float val)
+{
+    if (val >= 0.0f)
+        atomicMax(reinterpret_cast<int*>(addr), __float_as_int(val));
+    else
+        atomicMin(reinterpret_cast<unsigned int*>(addr), __float_as_uint(val));
+}
+
+template <typename TC, int DP, bool VEC>
+__global__ __launch_bounds__(kPassThreads) void k_rowmax(PassArgs A, int span, double* part,
+                                                         float* out32)
+{
+    constexpr int NCH = kChunks, V = kVec, T = kPassThreads, RB = kTileRows, RU = 4;
+    __shared__ float s_u[RB];
+    __shared__ float s_x[DP > 0 ? RB * DP : 1];
+    __shared__ float s_wm[kWaves][RB];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t n = A.n, m = A.m;
-    const int64_t i0 = (int64_t)blockIdx.y * kTileRows;
-    const int64_t j0 = (int64_t)blockIdx.x * kTileCols;
+    const int64_t i0 = (int64_t)blockIdx.y * RB;
+    const int rows = (int)(n - i0 < RB ? n - i0 : RB);
+    if (tid < RB) {
+        const int64_t i = i0 + tid;
+        const bool ok = i < n;
+        s_u[tid] = ok ? (float)A.u[i] : 0.0f;
+        if constexpr (DP > 0) {
+#pragma unroll
+            for (int k = 0; k < DP; ++k) s_x[tid * DP + k] = ok ? A.X[i * DP + k] : 0.0f;
+        }
+        s_wm[0][tid] = s_wm[1][tid] = s_wm[2][tid] = s_wm[3][tid] = -INFINITY;
+    }
+    const float bf = (float)A.beta;
     const TC* __restrict__ C = static_cast<const TC*>(A.C);
-    for (int rr = 0; rr < kTileRows; ++rr) {
-        const int64_t i = i0 + rr;
-        if (i >= n) break;
-        double mx = -INFINITY;
-        const double ui = A.u[i];
+    const int64_t tile_end = ((int64_t)blockIdx.x + 1) * span;
+    const int64_t tiles_m = (m + kTileCols - 1) / kTileCols;
+    const int64_t t_hi = tile_end < tiles_m ? tile_end : tiles_m;
+    __syncthreads();
+    for (int64_t t = (int64_t)blockIdx.x * span; t < t_hi; ++t) {
+        const int64_t j0 = t * kTileCols;
+        float vj[NCH][V];
+        float yj[DP > 0 ? NCH : 1][DP > 0 ? V : 1][DP > 0 ? DP : 1];
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) {
-            const int64_t jb = j0 + (int64_t)ch * T * V + tid * V;
-            double cv[V];
-            if constexpr (DP == 0) {
-                load_row_vec_d<TC>(C + i * A.ldc, jb, m, A.vec_ok != 0, cv);
-            } else {
+        for (int ch = 0; ch < NCH; ++ch)
 #pragma unroll
-                for (int q = 0; q < V; ++q) {
-                    double d2 = 0.0;
-                    if (jb + q < m) {
+            for (int q = 0; q < V; ++q) {
+                const int64_t j = j0 + (int64_t)ch * T * V + tid * V + q;
+                vj[ch][q] = j < m ? (float)A.v[j] : -INFINITY;
+                if constexpr (DP > 0) {
 #pragma unroll
-                        for (int k = 0; k < DP; ++k) {
-                            const double df = (double)A.X[i * DP + k] - (double)A.Y[(jb + q) * DP + k];
-                            d2 = fma(df, df, d2);
+                    for (int k = 0; k < DP; ++k) yj[ch][q][k] = j < m ? A.Y[j * DP + k] : 0.0f;
+                }
+            }
+        for (int r0 = 0; r0 < rows; r0 += RU) {
+            float mx[RU];
+#pragma unroll
+            for (int rr = 0; rr < RU; ++rr) {
+                mx[rr] = -INFINITY;
+                const int r = r0 + rr < rows ? r0 + rr : rows - 1;     // clamped, in bounds
+                const float ur = s_u[r];
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) {
+                    const int64_t jb = j0 + (int64_t)ch * T * V + tid * V;
+                    float c[V];
+                    if constexpr (DP == 0) {
+                        if constexpr (sizeof(TC) == 4) {
+                            load4<VEC>(reinterpret_cast<const float*>(C) + (i0 + r) * A.ldc, jb, m,
+                                       A.ldc, c);
+                        } else {
+                            double cd[V];
+                            load4<VEC>(reinterpret_cast<const double*>(C) + (i0 + r) * A.ldc, jb,
+                                       m, A.ldc, cd);
+#pragma unroll
+                            for (int q = 0; q < V; ++q) c[q] = (float)cd[q];
+                        }
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < V; ++q) {
+                            float d2 = 0.0f;
+#pragma unroll
+                            for (int k = 0; k < DP; ++k) {
+                                const float df = s_x[r * DP + k] - yj[ch][q][k];
+                                d2 = fmaf(df, df, d2);
+                            }
+                            c[q] = d2;
                         }
                     }
-                    cv[q] = d2;
+#pragma unroll
+                    for (int q = 0; q < V; ++q)   // vj = -inf past m masks the clamped loads
+                        mx[rr] = fmaxf(mx[rr], fmaf(-bf, c[q], ur + vj[ch][q]));
                 }
             }
 #pragma unroll
-            for (int q = 0; q < V; ++q)
-                if (jb + q < m) mx = fmax(mx, fma(-A.beta, cv[q], ui + A.v[jb + q]));
+            for (int rr = 0; rr < RU; ++rr) {
+                const float w = wave_max_f(mx[rr]);
+                if (lane == 0 && r0 + rr < rows) s_wm[wave][r0 + rr] = fmaxf(s_wm[wave][r0 + rr], w);
+            }
         }
-        mx = wave_max(mx);
-        if ((tid & 63) == 0) s_w[tid >> 6] = mx;
-        __syncthreads();
-        if (tid == 0) {
-            double r = s_w[0];
-            for (int w = 1; w < kWaves; ++w) r = fmax(r, s_w[w]);
-            if (A.atomic)
-                atomic_max_f64(&part[i], r);
-            else
-                part[(int64_t)blockIdx.x * n + i] = r;
-        }
-        __syncthreads();
     }
+    __syncthreads();
+    if (tid < rows) {
+        float r = fmaxf(fmaxf(s_wm[0][tid], s_wm[1][tid]), fmaxf(s_wm[2][tid], s_wm[3][tid]));
+        const int64_t i = i0 + tid;
+        if (A.atomic)
+            atomic_max_f32(&out32[i], r);
+        else
+            part[(int64_t)blockIdx.x * n + i] = (double)r;
+    }
+}
+
+__global__ void k_f32_to_f64(const float* x, double* y, int64_t k)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (double)x[i];
+}
+
+__global__ void k_fill_f32(float* x, float val, int64_t k)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = val;
 }
 
 __global__ void k_merge_max(const double* part, int tiles, int64_t n, double* out)
@@ -932,18 +1006,27 @@ inline int map_blocks(int64_t k)
 template <typename TC, int NR, int NC, int MODE2, bool VEC, int DP>
 hipError_t launch_pass_v(const PassArgs& a, int prec, hipStream_t s)
 {
-    constexpr int RS = (MODE2 == R2_HVP || (NR > 0 && NC > 0)) ? 4 : kSubRows;
+    constexpr bool FUSED = MODE2 == R2_HVP || (NR > 0 && NC > 0);
+    constexpr int RS = FUSED ? kSubRowsFused : kSubRows;
     dim3 grid((unsigned)a.tiles_m, (unsigned)a.tiles_n);
     if (prec == EOT_PREC_MIXED) {
         if constexpr (sizeof(TC) == 4) {
-            hipLaunchKernelGGL((k_pass<EOT_PREC_MIXED, TC, NR, NC, MODE2, VEC, RS, DP>), grid,
-                               dim3(kPassThreads), 0, s, a);
+            if constexpr (FUSED)
+                hipLaunchKernelGGL((k_pass_fused<EOT_PREC_MIXED, TC, NR, NC, MODE2, VEC, RS, DP>),
+                                   grid, dim3(kPassThreads), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_pass<EOT_PREC_MIXED, TC, NR, NC, MODE2, VEC, RS, DP>), grid,
+                                   dim3(kPassThreads), 0, s, a);
         } else {
             return hipErrorInvalidValue;
         }
     } else {
-        hipLaunchKernelGGL((k_pass<EOT_PREC_FP64, TC, NR, NC, MODE2, VEC, RS, DP>), grid,
-                           dim3(kPassThreads), 0, s, a);
+        if constexpr (FUSED)
+            hipLaunchKernelGGL((k_pass_fused<EOT_PREC_FP64, TC, NR, NC, MODE2, VEC, RS, DP>), grid,
+                               dim3(kPassThreads), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_pass<EOT_PREC_FP64, TC, NR, NC, MODE2, VEC, RS, DP>), grid,
+                               dim3(kPassThreads), 0, s, a);
     }
     return hipGetLastError();
 }
@@ -1310,25 +1393,38 @@ hipError_t launch_pass(const PassArgs& a, int prec, int nr, int nc, int mode2, h
 
 hipError_t launch_rowmax(const PassArgs& a, double* part, double* out, hipStream_t s)
 {
-    dim3 grid((unsigned)a.tiles_m, (unsigned)a.tiles_n);
-    if (a.atomic) {
-        hipLaunchKernelGGL(k_fill, dim3(vec_blocks(a.n)), dim3(kVecThreads), 0, s, out,
+    // a block spans `span` column tiles so that at most 64 partials (or atomics) per row remain
+    const int span = (a.tiles_m + 63) / 64;
+    const int gx = (a.tiles_m + span - 1) / span;
+    dim3 grid((unsigned)gx, (unsigned)a.tiles_n);
+    float* out32 = reinterpret_cast<float*>(part);     // atomic mode: n floats of scratch
+    if (a.atomic)
+        hipLaunchKernelGGL(k_fill_f32, dim3(vec_blocks(a.n)), dim3(kVecThreads), 0, s, out32,
                            -INFINITY, a.n);
-        part = out;
-    }
-    if (a.kind == EOT_COST_DENSE_F32)
-        hipLaunchKernelGGL((k_rowmax<float, 0>), grid, dim3(kPassThreads), 0, s, a, part);
-    else if (a.kind == EOT_COST_DENSE_F64)
-        hipLaunchKernelGGL((k_rowmax<double, 0>), grid, dim3(kPassThreads), 0, s, a, part);
-    else if (a.kind == EOT_COST_SQEUCLID_POINTS && a.d == 2)
-        hipLaunchKernelGGL((k_rowmax<float, 2>), grid, dim3(kPassThreads), 0, s, a, part);
-    else if (a.kind == EOT_COST_SQEUCLID_POINTS && a.d == 3)
-        hipLaunchKernelGGL((k_rowmax<float, 3>), grid, dim3(kPassThreads), 0, s, a, part);
-    else
+    const bool vec = a.vec_ok != 0;
+    if (a.kind == EOT_COST_DENSE_F32) {
+        if (vec)
+            hipLaunchKernelGGL((k_rowmax<float, 0, true>), grid, dim3(kPassThreads), 0, s, a, span, part, out32);
+        else
+            hipLaunchKernelGGL((k_rowmax<float, 0, false>), grid, dim3(kPassThreads), 0, s, a, span, part, out32);
+    } else if (a.kind == EOT_COST_DENSE_F64) {
+        if (vec)
+            hipLaunchKernelGGL((k_rowmax<double, 0, true>), grid, dim3(kPassThreads), 0, s, a, span, part, out32);
+        else
+            hipLaunchKernelGGL((k_rowmax<double, 0, false>), grid, dim3(kPassThreads), 0, s, a, span, part, out32);
+    } else if (a.kind == EOT_COST_SQEUCLID_POINTS && a.d == 2) {
+        hipLaunchKernelGGL((k_rowmax<float, 2, false>), grid, dim3(kPassThreads), 0, s, a, span, part, out32);
+    } else if (a.kind == EOT_COST_SQEUCLID_POINTS && a.d == 3) {
+        hipLaunchKernelGGL((k_rowmax<float, 3, false>), grid, dim3(kPassThreads), 0, s, a, span, part, out32);
+    } else {
         return hipErrorInvalidValue;
-    if (!a.atomic)
-        hipLaunchKernelGGL(k_merge_max, dim3(map_blocks(a.n)), dim3(kVecThreads), 0, s, part,
-                           a.tiles_m, a.n, out);
+    }
+    if (a.atomic)
+        hipLaunchKernelGGL(k_f32_to_f64, dim3(vec_blocks(a.n)), dim3(kVecThreads), 0, s, out32,
+                           out, a.n);
+    else
+        hipLaunchKernelGGL(k_merge_max, dim3(map_blocks(a.n)), dim3(kVecThreads), 0, s, part, gx,
+                           a.n, out);
     return hipGetLastError();
 }
 
