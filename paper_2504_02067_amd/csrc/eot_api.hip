@@ -91,6 +91,7 @@ struct Ctx {
     eot_cost cost{};
     int64_t n = 0, m = 0;
     int tiles_m = 0, tiles_n = 0;
+    int rb = kTileRows;           // rows per tile
     int rtiles = 0, ctiles = 0;   // partials per row / column that the merges sum
     int atomic = 0;               // outputs accumulated atomically (huge problems)
     hipStream_t s = nullptr;
@@ -158,13 +159,27 @@ eot_status check_cost(const eot_cost* c)
     return EOT_ERR_INVALID_ARG;
 }
 
-// Tile layout of the passes: per-tile partial sums merged in a fixed order
+// Tile layout of the passes. Tiles are 2048 columns wide and rb rows high:
+// rb = 256 unless that leaves fewer than kMinTiles workgroups (small
+// problems), then halved down to 8, so that small problems still spread over
+// the chip. Per-tile partial sums are merged in a fixed order
 // (bit-reproducible) unless those buffers would exceed 512 MB, in which case
 // the pass accumulates into one row and one column vector with FP64 atomics.
+constexpr int64_t kMinTiles = 512;
+
+int pick_rows_per_tile(int64_t n, int64_t m)
+{
+    const int64_t tm = tiles_m_of(m);
+    int rb = kTileRows;
+    while (rb > 8 && tm * tiles_n_of(n, rb) < kMinTiles) rb /= 2;
+    return rb;
+}
+
 void layout(Ctx& x)
 {
     x.tiles_m = (int)tiles_m_of(x.m);
-    x.tiles_n = (int)tiles_n_of(x.n);
+    x.rb = pick_rows_per_tile(x.n, x.m);
+    x.tiles_n = (int)tiles_n_of(x.n, x.rb);
     const double part_bytes =
         16.0 * ((double)row_tiles(x.tiles_m) * (double)x.n + (double)x.tiles_n * (double)x.m);
     x.atomic = part_bytes > 512.0e6 ? 1 : 0;
@@ -218,6 +233,7 @@ PassArgs make_args(const Ctx& x, const double* u, const double* a, const double*
     A.tiles_m = x.tiles_m;
     A.tiles_n = x.tiles_n;
     A.atomic = x.atomic;
+    A.rb = x.rb;
     return A;
 }
 

@@ -13,7 +13,8 @@ constexpr int kPassThreads = 256;        // 4 wave64 per workgroup
 constexpr int kVec = 4;                  // consecutive columns per thread per row
 constexpr int kChunks = 2;               // column chunks of 1024 per tile
 constexpr int kTileCols = kPassThreads * kVec * kChunks;   // 2048
-constexpr int kTileRows = 256;           // rows per tile (column partials per band)
+constexpr int kTileRows = 256;           // maximum rows per tile (column partials per band);
+                                         // a launch uses PassArgs::rb <= kTileRows rows
 // Rows per chunk in flight per thread: passes with one kind of sum, and passes
 // with both row and column sums (more accumulators). Build-time tunables.
 #ifndef EOT_SUB_ROWS
@@ -62,12 +63,13 @@ struct PassArgs {
     const float* X;        // points: n x d
     const float* Y;        // points: m x d
     int32_t d;             // point dimension (2 or 3)
+    int32_t rb;            // rows per tile: 8, 16, ..., kTileRows (grid.y = ceil(n / rb))
     int32_t atomic;        // 1: row_part = [nr][n], col_part = [nc][m], pre-zeroed, atomically
                            //    accumulated (problems whose per-tile partials would not fit)
 };
 
 inline int64_t tiles_m_of(int64_t m) { return (m + kTileCols - 1) / kTileCols; }
-inline int64_t tiles_n_of(int64_t n) { return (n + kTileRows - 1) / kTileRows; }
+inline int64_t tiles_n_of(int64_t n, int rb) { return (n + rb - 1) / rb; }
 
 // One streaming pass: nr row sums (0..2), nc column sums (0..2).
 hipError_t launch_pass(const PassArgs& a, int prec, int nr, int nc, int mode2, hipStream_t s);

@@ -216,14 +216,15 @@ __device__ __forceinline__ void pass_body(const PassArgs& A)
 
     const int tid = threadIdx.x;
     const int64_t n = A.n, m = A.m;
-    const int64_t i0 = (int64_t)blockIdx.y * RB;
+    const int rbt = A.rb;                      // rows of this launch's tiles (<= RB, % 8 == 0)
+    const int64_t i0 = (int64_t)blockIdx.y * rbt;
     const int64_t j0 = (int64_t)blockIdx.x * kTileCols;
     const TC* __restrict__ C = static_cast<const TC*>(A.C);
     const bool full = j0 + kTileCols <= m;     // uniform: no column past m in this tile
 
     // ---- prologue: per-column values in registers, per-row values in LDS
     const int64_t irow = i0 + tid;
-    const bool rvalid = tid < RB && irow < n;
+    const bool rvalid = tid < rbt && irow < n;
     float vh[NCH][V], vl[NCH][V];
     double vc[NCH][V];
     double arow = 0.0, ul = 0.0, uh = 0.0;
@@ -342,7 +343,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& A)
     __syncthreads();
 
     // ---- main loop: one iteration = one sub-band of RS rows, both chunks
-    const int64_t rows = n - i0 < RB ? n - i0 : RB;
+    const int64_t rows = n - i0 < rbt ? n - i0 : rbt;
     const int nsb = (int)((rows + RS - 1) / RS);
     const int64_t jb0 = j0 + tid * V, jb1 = j0 + (int64_t)T * V + tid * V;
 
@@ -513,8 +514,9 @@ __global__ __launch_bounds__(kPassThreads) void k_rowmax(PassArgs A, int span, d
     __shared__ float s_wm[kWaves][RB];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t n = A.n, m = A.m;
-    const int64_t i0 = (int64_t)blockIdx.y * RB;
-    const int rows = (int)(n - i0 < RB ? n - i0 : RB);
+    const int rbt = A.rb;
+    const int64_t i0 = (int64_t)blockIdx.y * rbt;
+    const int rows = (int)(n - i0 < rbt ? n - i0 : rbt);
     if (tid < RB) {
         const int64_t i = i0 + tid;
         const bool ok = i < n;
