@@ -302,6 +302,13 @@ eot_status eot_gradient(const eot_cost* cost, double gamma, const double* f, con
                         double* grad_Y, double* grad_r, double* grad_c, eot_grad_info* info,
                         int32_t prec, void* ws, size_t ws_bytes, void* stream);
 
+/* Rows per tile of the streaming passes (a power of two in [8, 256]) used by
+ * every later call in this process, or 0 to restore the default choice (the
+ * measured table compiled into the library, else the smallest halving of 256
+ * that launches at least 512 workgroups). For the autotuner and tests; size
+ * workspaces after changing it. */
+eot_status eot_set_rows_per_tile(int32_t rows);
+
 /* Opt-in timing of the streaming passes (for benchmarks and profiling). While
  * enabled, every streaming-pass kernel the library launches is bracketed by two
  * HIP events recorded on the stream it is launched on. eot_pass_timing(1)

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "eot_internal.h"
+#include "eot_tile_table.h"
 
 using namespace eot;
 
@@ -165,10 +166,20 @@ eot_status check_cost(const eot_cost* c)
 // the chip. Per-tile partial sums are merged in a fixed order
 // (bit-reproducible) unless those buffers would exceed 512 MB, in which case
 // the pass accumulates into one row and one column vector with FP64 atomics.
+// The measured table (eot_tile_table.h) takes precedence where it has an
+// entry; eot_set_rows_per_tile overrides both (autotuning and tests).
 constexpr int64_t kMinTiles = 512;
+std::atomic<int> g_rows_override{0};
 
-int pick_rows_per_tile(int64_t n, int64_t m)
+int pick_rows_per_tile(int64_t n, int64_t m, int kind)
 {
+    const int ov = g_rows_override.load();
+    if (ov > 0) return ov;
+    const int k = (int)std::lround(0.5 * std::log2((double)n * (double)m)) - kTileTableK0;
+    if (k >= 0 && k < kTileTableN) {
+        const int t = kind == EOT_COST_SQEUCLID_POINTS ? kTileTablePoints[k] : kTileTableDense[k];
+        if (t > 0) return t;
+    }
     const int64_t tm = tiles_m_of(m);
     int rb = kTileRows;
     while (rb > 8 && tm * tiles_n_of(n, rb) < kMinTiles) rb /= 2;
@@ -178,7 +189,7 @@ int pick_rows_per_tile(int64_t n, int64_t m)
 void layout(Ctx& x)
 {
     x.tiles_m = (int)tiles_m_of(x.m);
-    x.rb = pick_rows_per_tile(x.n, x.m);
+    x.rb = pick_rows_per_tile(x.n, x.m, x.cost.kind);
     x.tiles_n = (int)tiles_n_of(x.n, x.rb);
     const double part_bytes =
         16.0 * ((double)row_tiles(x.tiles_m) * (double)x.n + (double)x.tiles_n * (double)x.m);
@@ -980,6 +991,7 @@ eot_status eot_workspace_size(int32_t op, const eot_cost* cost, int32_t prec, si
     if (op < EOT_OP_MARGINALS || op > EOT_OP_ROUND) return EOT_ERR_INVALID_ARG;
     (void)prec;
     Ctx x;
+    x.cost = *cost;
     x.n = cost->n;
     x.m = cost->m;
     layout(x);
@@ -1261,6 +1273,14 @@ eot_status eot_round(const eot_cost* cost, double gamma, const double* f, const 
     Ctx x;
     EOTCHK(setup(x, cost, EOT_OP_ROUND, EOT_PREC_FP64, ws, ws_bytes, stream));
     return round_impl(x, gamma, f, g, r, c, xo, yo, ero, eco, plan, ldp, info);
+}
+
+eot_status eot_set_rows_per_tile(int32_t rows)
+{
+    if (rows != 0 && (rows < 8 || rows > kTileRows || (rows & (rows - 1)) != 0))
+        return EOT_ERR_INVALID_ARG;
+    g_rows_override.store(rows);
+    return EOT_OK;
 }
 
 eot_status eot_pass_timing(int32_t enable)

@@ -124,6 +124,7 @@ SIGNATURES = {
                               _c_vp, _c_i64, _c_vp, _c_vp, _c_vp, _c_vp,
                               ctypes.POINTER(eot_grad_info), _c_i32, _c_vp, ctypes.c_size_t,
                               _c_vp]),
+    "eot_set_rows_per_tile": (_c_i32, [_c_i32]),
     "eot_pass_timing": (_c_i32, [_c_i32]),
     "eot_pass_timing_read": (_c_i32, [_c_i32, _c_i32, _c_i32, _c_i32, ctypes.POINTER(_c_i64),
                                       ctypes.POINTER(_c_f64)]),
@@ -442,6 +443,12 @@ def eot_gradient(C, gamma, f, g, w_W=1.0, w_S=0.0, want=None, tol=1e-11, max_cg=
     _check(st, "eot_gradient", allow)
     out.update(S=info.S, cg_iters=info.cg_iters, cg_residual=info.cg_residual, status=st)
     return out
+
+
+def eot_set_rows_per_tile(rows: int) -> None:
+    """Force the tile height of the passes (power of two in [8, 256]); 0 restores
+    the library's choice."""
+    _check(lib().eot_set_rows_per_tile(int(rows)), "eot_set_rows_per_tile")
 
 
 def eot_pass_timing(enable: bool) -> None:

@@ -155,3 +155,18 @@ def test_binding_rejects_cpu_tensors():
     from paper_2504_02067_amd import eot
     with pytest.raises(ValueError):
         eot.make_cost(torch.zeros(4, 4))
+
+
+def test_rows_per_tile_override_validation(L):
+    from paper_2504_02067_amd import eot
+    for bad in (7, 12, 512, -8):
+        assert L.eot_set_rows_per_tile(bad) == eot.EOT_ERR_INVALID_ARG
+    sz = ctypes.c_size_t(0)
+    c = eot.eot_cost(kind=0, d=0, n=4096, m=4096, ldc=4096, C=ctypes.c_void_p(4096), X=None,
+                     Y=None, scale=0.0)
+    sizes = []
+    for rb in (8, 256, 0):
+        assert L.eot_set_rows_per_tile(rb) == eot.EOT_OK
+        assert L.eot_workspace_size(eot.EOT_OP_SOLVE, ctypes.byref(c), 0, ctypes.byref(sz)) == 0
+        sizes.append(sz.value)
+    assert sizes[0] > sizes[1]          # 8-row tiles need more column partials

@@ -293,3 +293,23 @@ def test_sinkhorn_projection_mixed_grid784():
     assert st["status"] == 0 and st2["status"] == 0
     assert st["err_r"] + st["err_c"] <= 1e-6
     assert abs(st["cost"] - st2["cost"]) <= 1e-5 * st2["cost"]
+
+
+@pytest.mark.parametrize("rb", [8, 32, 256])
+def test_every_tile_height_gives_the_same_marginals(rb):
+    n, m, gamma = 700, 2500, 0.02
+    C, f, g, r, c = random_case(n, m, 77, gamma)
+    u, v = to_log(f, g, gamma)
+    say(f"tile height {rb}")
+    eot.eot_set_rows_per_tile(rb)
+    try:
+        out = eot.eot_marginals(torch.from_numpy(C).to(DEV), gamma, dvec(f), dvec(g), precision="fp64")
+        Hx, Hy = eot.eot_hvp(torch.from_numpy(C).to(DEV), gamma, dvec(f), dvec(g), 0.5,
+                             dvec(np.ones(n)), dvec(np.ones(m)), precision="mixed")
+    finally:
+        eot.eot_set_rows_per_tile(0)
+    np.testing.assert_allclose(host(out["log_rP"]), O.log_row_marginal(C, 1 / gamma, u, v), atol=1e-12, rtol=0)
+    np.testing.assert_allclose(host(out["log_cP"]), O.log_col_marginal(C, 1 / gamma, u, v), atol=1e-12, rtol=0)
+    Hx_ref, Hy_ref = O.hvp(C, 1 / gamma, u, v, 0.5, np.ones(n), np.ones(m))
+    np.testing.assert_allclose(host(Hx), Hx_ref, rtol=4e-6)
+    np.testing.assert_allclose(host(Hy), Hy_ref, rtol=4e-6)
