@@ -373,12 +373,19 @@ eot_status device_pcg(Ctx& x, int prec, const double* u, const double* lr, const
     pb.yw0 = V.wc;
     pb.skip = &x.sc.cg->done;
     CgScalars h{};
+    const bool small = std::max(n, m) <= kCgSmallMax;
     int issued = 0, chunk = 4;
     for (;;) {
         for (int it = 0; it < chunk && issued < max_cg; ++it, ++issued) {
             HIPCHK(run_pass(x, pa, prec, 0, 1, R2_WEIGHT));
             HIPCHK(launch_cg_colstep(x.sc.col_part, x.ctiles, m, c, V.w, V.wc, x.sc.cg, x.s));
             HIPCHK(run_pass(x, pb, prec, 1, 0, R2_WEIGHT));
+            if (small) {
+                HIPCHK(launch_cg_small(x.sc.row_part, x.rtiles, n, m, lr, V.rP, V.p, rho, V.t,
+                                       V.q, V.dtry, V.res, V.z, V.M, V.pcptd_try, V.w, V.ptd_try,
+                                       x.sc.cg, x.s));
+                continue;
+            }
             int nb_pq = 0, nb = 0;
             HIPCHK(launch_cg_rowstep(x.sc.row_part, x.rtiles, n, lr, V.rP, V.p, rho, V.t, V.q,
                                      x.sc.red2, &nb_pq, x.sc.cg, x.s));

@@ -191,5 +191,13 @@ hipError_t launch_cg_update(const double* red_pq, int nb_pq, double* d, double* 
                             double* red, int* nb, CgScalars* sc, hipStream_t st);
 hipError_t launch_cg_direction(const double* red, int nb, const double* z, double* p,
                                int64_t n, CgScalars* sc, hipStream_t st);
+// Small problems (n, m <= kCgSmallMax): row step, update, direction and stop
+// test of one CG iteration in a single workgroup launch.
+constexpr int64_t kCgSmallMax = 8192;
+hipError_t launch_cg_small(const double* part, int tiles, int64_t n, int64_t m, const double* a,
+                           const double* rP, double* p, double rho, double* t, double* q,
+                           double* d, double* res, double* z, const double* M, double* pcptd,
+                           const double* w, double* ptd, CgScalars* sc, hipStream_t s);
+
 
 }  // namespace eot
