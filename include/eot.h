@@ -178,6 +178,9 @@ typedef struct {
                                paper's method) or EOT_PROJ_SINKHORN (alternating row and
                                column fits to the same tolerance: the baseline the paper
                                compares against); EOT_PROJ_TNP                         */
+    int32_t cg_graph;       /* 1: each CG solve records one chunk of 8 iterations as a HIP
+                               graph and replays it (streams other than the legacy default
+                               stream, pass timing off; otherwise direct launches); 0    */
 } eot_solve_opts;
 
 typedef struct {

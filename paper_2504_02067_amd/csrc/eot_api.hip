@@ -104,6 +104,7 @@ struct Ctx {
     GradVecs gv{};
     int64_t passes = 0;
     int32_t range_retries = 0;
+    bool cg_graph = false;        // replay CG chunks from a recorded HIP graph
 };
 
 void carve(Arena& ar, Ctx& x, int op)
@@ -374,30 +375,67 @@ eot_status device_pcg(Ctx& x, int prec, const double* u, const double* lr, const
     pb.skip = &x.sc.cg->done;
     CgScalars h{};
     const bool small = std::max(n, m) <= kCgSmallMax;
-    int issued = 0, chunk = 4;
-    for (;;) {
-        for (int it = 0; it < chunk && issued < max_cg; ++it, ++issued) {
-            HIPCHK(run_pass(x, pa, prec, 0, 1, R2_WEIGHT));
-            HIPCHK(launch_cg_colstep(x.sc.col_part, x.ctiles, m, c, V.w, V.wc, x.sc.cg, x.s));
-            HIPCHK(run_pass(x, pb, prec, 1, 0, R2_WEIGHT));
-            if (small) {
-                HIPCHK(launch_cg_small(x.sc.row_part, x.rtiles, n, m, lr, V.rP, V.p, rho, V.t,
-                                       V.q, V.dtry, V.res, V.z, V.M, V.pcptd_try, V.w, V.ptd_try,
-                                       x.sc.cg, x.s));
-                continue;
-            }
-            int nb_pq = 0, nb = 0;
-            HIPCHK(launch_cg_rowstep(x.sc.row_part, x.rtiles, n, lr, V.rP, V.p, rho, V.t, V.q,
-                                     x.sc.red2, &nb_pq, x.sc.cg, x.s));
-            HIPCHK(launch_cg_update(x.sc.red2, nb_pq, V.dtry, V.res, V.z, V.p, V.q, V.M, V.t,
-                                    V.pcptd_try, V.w, V.ptd_try, n, m, x.sc.red, &nb, x.sc.cg,
-                                    x.s));
-            HIPCHK(launch_cg_direction(x.sc.red, nb, V.z, V.p, n, x.sc.cg, x.s));
+    // one CG iteration; every kernel returns at once once sc.done is set
+    auto iteration = [&]() -> hipError_t {
+        hipError_t e = run_pass(x, pa, prec, 0, 1, R2_WEIGHT);
+        if (e == hipSuccess)
+            e = launch_cg_colstep(x.sc.col_part, x.ctiles, m, c, V.w, V.wc, x.sc.cg, x.s);
+        if (e == hipSuccess) e = run_pass(x, pb, prec, 1, 0, R2_WEIGHT);
+        if (e != hipSuccess) return e;
+        if (small)
+            return launch_cg_small(x.sc.row_part, x.rtiles, n, m, lr, V.rP, V.p, rho, V.t, V.q,
+                                   V.dtry, V.res, V.z, V.M, V.pcptd_try, V.w, V.ptd_try, x.sc.cg,
+                                   x.s);
+        int nb_pq = 0, nb = 0;
+        e = launch_cg_rowstep(x.sc.row_part, x.rtiles, n, lr, V.rP, V.p, rho, V.t, V.q, x.sc.red2,
+                              &nb_pq, x.sc.cg, x.s);
+        if (e == hipSuccess)
+            e = launch_cg_update(x.sc.red2, nb_pq, V.dtry, V.res, V.z, V.p, V.q, V.M, V.t,
+                                 V.pcptd_try, V.w, V.ptd_try, n, m, x.sc.red, &nb, x.sc.cg, x.s);
+        if (e == hipSuccess) e = launch_cg_direction(x.sc.red, nb, V.z, V.p, n, x.sc.cg, x.s);
+        return e;
+    };
+    auto read_scalars = [&]() -> eot_status {
+        return fetch(x, reinterpret_cast<const double*>(x.sc.cg), reinterpret_cast<double*>(&h),
+                     sizeof(CgScalars) / sizeof(double));
+    };
+    int issued = 0;
+    // Graph mode: record kGraphChunk iterations once, replay until the device flag is set.
+    bool graphed = false;
+    if (x.cg_graph && x.s != nullptr && !pass_timing_on()) {
+        constexpr int kGraphChunk = 8;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipError_t e = hipStreamBeginCapture(x.s, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t ee = hipSuccess;
+            for (int it = 0; it < kGraphChunk && ee == hipSuccess; ++it) ee = iteration();
+            e = hipStreamEndCapture(x.s, &graph);
+            if (ee != hipSuccess) e = ee;
         }
-        EOTCHK(fetch(x, reinterpret_cast<const double*>(x.sc.cg), reinterpret_cast<double*>(&h),
-                     sizeof(CgScalars) / sizeof(double)));
-        if (h.done || issued >= max_cg) break;
-        chunk = std::min(2 * chunk, 32);
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e == hipSuccess) {
+            graphed = true;
+            for (;;) {
+                HIPCHK(hipGraphLaunch(exec, x.s));
+                issued += kGraphChunk;
+                EOTCHK(read_scalars());
+                if (h.done || issued >= max_cg) break;
+            }
+        } else {
+            (void)hipGetLastError();                  // capture unsupported: direct launches
+        }
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+    if (!graphed) {
+        int chunk = 4;
+        for (;;) {
+            for (int it = 0; it < chunk && issued < max_cg; ++it, ++issued) HIPCHK(iteration());
+            EOTCHK(read_scalars());
+            if (h.done || issued >= max_cg) break;
+            chunk = std::min(2 * chunk, 32);
+        }
     }
     x.passes += 2 * (int64_t)h.iters;
     *out = h;
@@ -697,6 +735,7 @@ eot_status check_marginal(Ctx& x, const double* p, int64_t k)
 eot_status solve_impl(Ctx& x, const double* r, const double* c, const eot_solve_opts* o,
                       double* f_out, double* g_out, eot_solve_stats* st)
 {
+    x.cg_graph = o->cg_graph != 0;
     SolveVecs& S = x.sv;
     const int64_t n = x.n, m = x.m;
     const int prec = o->precision;
@@ -1144,6 +1183,7 @@ void eot_solve_opts_default(eot_solve_opts* o)
     o->precision = EOT_PREC_FP64;
     o->verify_fp64 = 1;
     o->projection = EOT_PROJ_TNP;
+    o->cg_graph = 0;
 }
 
 eot_status eot_solve(const eot_cost* cost, const double* r, const double* c,

@@ -75,6 +75,7 @@ inline int64_t tiles_n_of(int64_t n, int rb) { return (n + rb - 1) / rb; }
 hipError_t launch_pass(const PassArgs& a, int prec, int nr, int nc, int mode2, hipStream_t s);
 // Opt-in event timing of every launch_pass (see eot_pass_timing in eot.h).
 hipError_t set_pass_timing(bool on);
+bool pass_timing_on();
 hipError_t read_pass_timing(int nr, int nc, int prec, int hvp, int64_t* launches, double* ms);
 // Exact row maxima of u_i + v_j - beta C_ij (robust shift): out[n].
 hipError_t launch_rowmax(const PassArgs& a, double* part, double* out, hipStream_t s);

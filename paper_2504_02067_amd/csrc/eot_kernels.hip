@@ -1410,6 +1410,12 @@ void clear_timings_locked()
 }
 }  // namespace
 
+bool pass_timing_on()
+{
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    return g_timing_on;
+}
+
 hipError_t set_pass_timing(bool on)
 {
     std::lock_guard<std::mutex> lk(g_timing_mu);

@@ -90,3 +90,26 @@ def test_batched_mixed_kinds_and_failure_isolation():
             continue
         f, g, st = eot.eot_solve(C, r, c, gamma_init=0.1, gamma_final=1e-2, tol=1e-6)
         assert torch.equal(outs[k][0], f) and torch.equal(outs[k][1], g), k
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_cg_graph_replay_matches_direct_launches(prec):
+    """CG chunks recorded once as a HIP graph and replayed give bitwise the
+    potentials of direct launches: in the batch (worker streams) and for a
+    single solve on a non-default stream."""
+    probs, items = batch(10, seed=4300)
+    kw = dict(gamma_init=1.0 / 32.0, gamma_final=1e-3, tol=1e-6, precision=prec)
+    say(f"cg graph batch ({prec})")
+    outs0, stats0, _ = eot.eot_solve_batched(items, workers=3, **kw)
+    outs1, stats1, st1 = eot.eot_solve_batched(items, workers=3, cg_graph=1, **kw)
+    assert st1 == [0] * len(items)
+    for k in range(len(items)):
+        assert torch.equal(outs0[k][0], outs1[k][0]) and torch.equal(outs0[k][1], outs1[k][1]), k
+        assert stats0[k]["cg_iters"] == stats1[k]["cg_iters"]
+    pc, r, c = items[0]
+    f0, g0, _ = eot.eot_solve(pc, r, c, **kw)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        f1, g1, _ = eot.eot_solve(pc, r, c, cg_graph=1, **kw)
+    side.synchronize()
+    assert torch.equal(f0, f1) and torch.equal(g0, g1)
