@@ -10,18 +10,21 @@
 // (lemma "condo").
 //
 // Design (gfx950):
-//  * A workgroup of 256 threads (4 wave64) owns a tile of kTileRows x
-//    kTileCols entries. Each thread owns 4 consecutive columns in each of 2
+//  * A workgroup of 256 threads (4 wave64) owns a tile of rb x kTileCols
+//    entries (rb = 8 .. kTileRows rows, chosen per problem by the host from a
+//    measured table). Each thread owns 4 consecutive columns in each of 2
 //    column chunks, so every row of the tile is read as 16-byte, fully
-//    coalesced loads; kSubRows rows are loaded before any is used, keeping
-//    8 x 16 bytes per thread in flight.
-//  * One read of C feeds both directions: column sums accumulate in
-//    registers across the whole row band (written once per band), row sums
-//    accumulate per thread over its 8 columns and are reduced across the
-//    workgroup through LDS every kSubRows rows (a transposed reduction: 16-32
-//    threads per row, then a shuffle inside the wave).
-//  * No atomics: per-tile partial sums are merged in a fixed order by small
-//    epilogue kernels, so results are bit-reproducible.
+//    coalesced non-temporal loads; RS rows of one chunk load while the other
+//    chunk computes (double buffer), and loads never sit behind a branch.
+//  * One read of C feeds both directions: column sums accumulate in FP64
+//    registers across the tile's rows (written once per tile), row sums
+//    accumulate per thread over its 8 columns and are reduced per wave by a
+//    butterfly transpose in registers (no LDS, no barrier in the loop).
+//  * Per-tile partial sums are merged in a fixed order by small epilogue
+//    kernels (bit-reproducible), except for problems whose partials would
+//    exceed 512 MB, which accumulate with FP64 atomics.
+//  * Point clouds: |x_i - y_j|^2 is recomputed per entry (difference form);
+//    no cost bytes are read, so those passes are bound by VALU issue.
 //  * Mixed precision: the exponent is assembled in FP32 without losing the
 //    FP64 potentials. In base 2, U_i = log2(e)(u_i - a_i) and V_j = log2(e) v_j
 //    are split per tile into a hi part on a grid 2^-g (g chosen from the

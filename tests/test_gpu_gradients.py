@@ -208,3 +208,37 @@ def test_round_points_cost_matches_dense():
     u, v = O.to_log_units(host(f), host(g), gamma)
     Pr = O.round_plan(C, 1.0 / gamma, u, v, p.r, p.c)
     assert out["cost_round"] == pytest.approx((Pr * C).sum(), rel=1e-11)
+
+
+def test_autograd_points_matches_finite_differences():
+    """d(0.3 W + 2 S)/dX and /dY of GPU solves against central differences of GPU
+    solves; coordinates on a 2^-10 grid and a step of 2^-8, so X +- h is exact in
+    FP32."""
+    gamma = 0.1
+    rng = np.random.default_rng(21)
+    n, m, d = 30, 40, 2
+    Xh = np.round(rng.uniform(0, 1, (n, d)) * 1024) / 1024
+    Yh = np.round(rng.uniform(0, 1, (m, d)) * 1024) / 1024
+    scale = 2.0
+    r = dvec(np.full(n, 1.0 / n)); c = dvec(np.full(m, 1.0 / m))
+    kw = dict(gamma_init=gamma, tol=1e-13, grad_tol=1e-12)
+
+    def loss(X, Y):
+        Wv, Sv = AG.entropic_ot_points(X, Y, r, c, gamma, scale, **kw)
+        return 0.3 * Wv + 2.0 * Sv
+
+    X = torch.from_numpy(Xh.astype(np.float32)).to(DEV).requires_grad_(True)
+    Y = torch.from_numpy(Yh.astype(np.float32)).to(DEV).requires_grad_(True)
+    loss(X, Y).backward()
+    gX, gY = host(X.grad).astype(np.float64), host(Y.grad).astype(np.float64)
+    say("autograd points vs finite differences")
+    h = 2.0 ** -8
+    for (T, G, idx) in ((X, gX, [(0, 0), (17, 1), (29, 0)]), (Y, gY, [(3, 1), (39, 0)])):
+        for (i, k) in idx:
+            E = torch.zeros_like(T); E[i, k] = h
+            if T is X:
+                fd = (loss((X + E).detach(), Y.detach()) - loss((X - E).detach(), Y.detach())).item()
+            else:
+                fd = (loss(X.detach(), (Y + E).detach()) - loss(X.detach(), (Y - E).detach())).item()
+            fd /= 2 * h
+            assert fd == pytest.approx(G[i, k], rel=2e-3, abs=1e-5)
