@@ -414,19 +414,21 @@ eot_status device_pcg(Ctx& x, int prec, const double* u, const double* lr, const
             if (ee != hipSuccess) e = ee;
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        eot_status gs = EOT_OK;
         if (e == hipSuccess) {
             graphed = true;
             for (;;) {
-                HIPCHK(hipGraphLaunch(exec, x.s));
+                if (hipGraphLaunch(exec, x.s) != hipSuccess) { gs = EOT_ERR_HIP; break; }
                 issued += kGraphChunk;
-                EOTCHK(read_scalars());
-                if (h.done || issued >= max_cg) break;
+                gs = read_scalars();
+                if (gs != EOT_OK || h.done || issued >= max_cg) break;
             }
         } else {
             (void)hipGetLastError();                  // capture unsupported: direct launches
         }
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+        EOTCHK(gs);
     }
     if (!graphed) {
         int chunk = 4;
@@ -447,14 +449,14 @@ eot_status device_pcg(Ctx& x, int prec, const double* u, const double* lr, const
 eot_status newton_solve(Ctx& x, int prec, const double* u, const double* v, double beta,
                         const double* lr, const double* s, const double* r, const double* c,
                         double eta, double rho0, int max_cg, int max_levels, double* du,
-                        double* dv, NewtonResult* out)
+                        double* dv, NewtonResult* out, double gnorm_known = -1.0)
 {
     NewtonVecs& V = x.nv;
     const int64_t n = x.n, m = x.m;
     const int64_t p0 = x.passes;
     HIPCHK(launch_newton_init(lr, r, V.rP, V.grad, V.b, V.d, n, x.s));
-    double gnorm = 0.0;
-    EOTCHK(reduce_host(x, RED_L1, V.grad, nullptr, n, &gnorm));
+    double gnorm = gnorm_known;                 // ||grad||_1, when the caller has it
+    if (!(gnorm >= 0.0)) EOTCHK(reduce_host(x, RED_L1, V.grad, nullptr, n, &gnorm));
     // F_r(1) d for the rho = 0 direction: two explicit passes
     EOTCHK(col_pass(x, prec, u, lr, v, beta, V.d, V.ptd));
     HIPCHK(launch_div(V.ptd, c, V.wc, 1.0, m, x.s));
@@ -532,21 +534,30 @@ eot_status fix_and_refresh(Ctx& x, int prec, double beta, const double* shift_gu
     return EOT_OK;
 }
 
-// Row refresh only (after a Newton step of Alg. 4), same fallback.
-eot_status refresh(Ctx& x, int prec, double beta, const double* shift_guess, SolveState& ss)
+// Row refresh only (after a Newton step of Alg. 4), same fallback. Also
+// returns ||r~ - r(P)||_1 of the refreshed plan (read with the range flags in
+// one wait).
+eot_status refresh(Ctx& x, int prec, double beta, const double* shift_guess, SolveState& ss,
+                   double* gn_out)
 {
     SolveVecs& S = x.sv;
     EOTCHK(clear_flags(x));
     EOTCHK(row_pass(x, prec, S.u, shift_guess, S.v, beta, S.inv_ct, S.lr, S.s));
     int32_t fl[2] = {0, 0};
-    EOTCHK(fetch_flags(x, fl));
+    int nb = 0;
+    HIPCHK(launch_reduce(RED_L1_DIFF_EXP, S.rt, S.lr, x.n, x.sc.red, &nb, x.s));
+    HIPCHK(launch_finish_sum(x.sc.red, nb, x.sc.scal, x.s));
+    HIPCHK(hipMemcpyAsync(fl, x.sc.flags, sizeof(fl), hipMemcpyDeviceToHost, x.s));
+    HIPCHK(hipMemcpyAsync(gn_out, x.sc.scal, sizeof(double), hipMemcpyDeviceToHost, x.s));
+    HIPCHK(hipStreamSynchronize(x.s));
     if (fl[0] == 0) return EOT_OK;
     ss.st->range_retries += 1;
     EOTCHK(clear_flags(x));
     EOTCHK(row_max(x, S.u, S.v, beta, S.sh2));
     EOTCHK(row_pass(x, EOT_PREC_FP64, S.u, S.sh2, S.v, beta, S.inv_ct, S.lr, S.s));
     EOTCHK(fetch_flags(x, fl));
-    return fl[0] ? EOT_ERR_NONFINITE : EOT_OK;
+    if (fl[0]) return EOT_ERR_NONFINITE;
+    return reduce_host(x, RED_L1_DIFF_EXP, S.rt, S.lr, x.n, gn_out);
 }
 
 // TruncatedNewtonProject (Alg. 4) on the smoothed marginals held in S.rt,
@@ -573,9 +584,11 @@ eot_status tnp(Ctx& x, int prec, double beta, double eps, double* rho0, double* 
     double g_prev = INFINITY;
     int slow = 0;
     if (stalled) *stalled = false;
+    double gn_known = -1.0;                    // ||r~ - r(P)||_1 from the last row refresh
     for (;;) {
-        double gn = 0.0;
-        EOTCHK(reduce_host(x, RED_L1_DIFF_EXP, S.rt, S.lr, n, &gn));
+        double gn = gn_known;
+        gn_known = -1.0;
+        if (!(gn >= 0.0)) EOTCHK(reduce_host(x, RED_L1_DIFF_EXP, S.rt, S.lr, n, &gn));
         if (!std::isfinite(gn)) return EOT_ERR_NONFINITE;
         if (gn <= eps) break;                                              // tolerance met
         if (stall_exit) {
@@ -586,6 +599,7 @@ eot_status tnp(Ctx& x, int prec, double beta, double eps, double* rho0, double* 
         if (k >= o->max_newton) { status = EOT_ERR_NOT_CONVERGED; break; }
         // ChiSinkhorn (Alg. 3) to eps^(2/5)
         const double eps_chi = std::pow(eps, 0.4);
+        int sweeps = 0;
         for (int it = 0;; ++it) {
             double chi2 = 0.0;
             EOTCHK(reduce_host(x, RED_CHI2, S.rt, S.lr, n, &chi2));
@@ -596,15 +610,17 @@ eot_status tnp(Ctx& x, int prec, double beta, double eps, double* rho0, double* 
             EOTCHK(fix_and_refresh(x, prec, beta, S.lrt, ss));
             st->passes_sinkhorn += x.passes - p0;
             st->sinkhorn_iters += 1;
+            ++sweeps;
         }
         HIPCHK(launch_newton_init(S.lr, S.rt, x.nv.rP, x.nv.grad, x.nv.b, x.nv.d, n, x.s));
-        double gk = 0.0;
-        EOTCHK(reduce_host(x, RED_L1, x.nv.grad, nullptr, n, &gk));
+        // ||grad||_1 = ||r(P) - r~||_1 (c(P) = c): the gn above unless ChiSinkhorn moved u
+        double gk = gn;
+        if (sweeps > 0) EOTCHK(reduce_host(x, RED_L1, x.nv.grad, nullptr, n, &gk));
         const double eta = std::max(gk, 0.8 * eps / gk);                  // forcing term
         NewtonResult nr;                                                   // Alg. 2 and d_v
         p0 = x.passes;
         EOTCHK(newton_solve(x, prec, S.u, S.v, beta, S.lr, S.s, S.rt, S.ct, eta, *rho0,
-                            o->max_cg, o->max_levels, S.du, S.dv, &nr));
+                            o->max_cg, o->max_levels, S.du, S.dv, &nr, gk));
         st->passes_newton += x.passes - p0;
         st->cg_iters += nr.cg_iters;
         st->levels += nr.levels;
@@ -639,11 +655,11 @@ eot_status tnp(Ctx& x, int prec, double beta, double eps, double* rho0, double* 
         HIPCHK(launch_log_ratio_fix(S.v, S.va, S.lct, S.colsum, m, x.sc.flags, x.s));
         // row refresh
         p0 = x.passes;
-        EOTCHK(refresh(x, prec, beta, S.sh, ss));
+        double gk1 = 0.0;
+        EOTCHK(refresh(x, prec, beta, S.sh, ss, &gk1));
         st->passes_projection += x.passes - p0;
         st->newton_steps += 1;
-        double gk1 = 0.0;
-        EOTCHK(reduce_host(x, RED_L1_DIFF_EXP, S.rt, S.lr, n, &gk1));
+        gn_known = gk1;
         const double dk = (gk - gk1) / ((1.0 - eta) * gk);
         dmin = std::min(dmin, dk);
         ++k;
@@ -1248,7 +1264,8 @@ eot_status eot_solve_batched(int32_t nprob, const eot_batch_problem* probs,
             hipStreamWaitEvent(streams[w], start, 0) != hipSuccess)
             setup_err = EOT_ERR_HIP;
     }
-    std::vector<eot_status> st_all((size_t)nprob, EOT_OK);
+    // a problem no worker reached (a worker that could not select the device) reports EOT_ERR_HIP
+    std::vector<eot_status> st_all((size_t)nprob, EOT_ERR_HIP);
     std::vector<eot_solve_stats> stats_all((size_t)nprob);
     std::atomic<int32_t> next{0};
     auto work = [&](int w) {

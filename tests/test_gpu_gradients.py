@@ -242,3 +242,44 @@ def test_autograd_points_matches_finite_differences():
                 fd = (loss(X.detach(), (Y + E).detach()) - loss(X.detach(), (Y - E).detach())).item()
             fd /= 2 * h
             assert fd == pytest.approx(G[i, k], rel=2e-3, abs=1e-5)
+
+
+def test_gradient_mixed_cg_matches_fp64():
+    gamma = 0.05
+    C, Cd, r, c, f, g, st = dense_case(300, 200, 5, gamma)
+    say("gradient with mixed-precision CG")
+    a = eot.eot_gradient(Cd, gamma, f, g, w_W=0.5, w_S=1.0)
+    b = eot.eot_gradient(Cd, gamma, f, g, w_W=0.5, w_S=1.0, precision="mixed", tol=1e-6)
+    # the CG solve stops at a 1e-6 relative residual in FP32-plan passes: lam, mu to ~1e-5
+    close(host(b["C"]), host(a["C"]), 1e-4)
+    close(host(b["r"]), host(a["r"]), 1e-4)
+    assert b["S"] == pytest.approx(a["S"], rel=1e-12)
+
+
+def test_round_fp64_cost():
+    gamma = 0.1
+    rng = np.random.default_rng(3)
+    C = rng.uniform(0, 1, (90, 70))
+    r = rng.dirichlet(np.ones(90)); c = rng.dirichlet(np.ones(70))
+    Cd = torch.from_numpy(C).to(DEV)
+    f, g, _ = eot.eot_solve(Cd, dvec(r), dvec(c), gamma_init=gamma, gamma_final=gamma, tol=1e-3)
+    out = eot.eot_round(Cd, gamma, f, g, dvec(r), dvec(c), plan=True)
+    u, v = O.to_log_units(host(f), host(g), gamma)
+    Pr = O.round_plan(C, 1 / gamma, u, v, r, c)
+    nr = max(out["mass_fix"], 1e-300)
+    assert np.all(np.abs(host(out["plan"]) - Pr) <= 1e-12 * np.abs(Pr) + 1e-13 * np.outer(r, c) / nr)
+    assert out["cost_round"] == pytest.approx((Pr * C).sum(), rel=1e-12)
+
+
+def test_nonfinite_cost_is_reported():
+    """A NaN in the cost ends the solve with EOT_ERR_NONFINITE instead of a
+    silent result (the passes' range guard sees the non-finite sums)."""
+    rng = np.random.default_rng(4)
+    C = rng.uniform(0, 1, (64, 64)).astype(np.float32)
+    C[10, 20] = np.nan
+    r = np.full(64, 1 / 64); c = np.full(64, 1 / 64)
+    say("NaN cost")
+    with pytest.raises(eot.EotError) as e:
+        eot.eot_solve(torch.from_numpy(C).to(DEV), dvec(r), dvec(c), gamma_init=0.1,
+                      gamma_final=0.01, tol=1e-6, max_mdot=20)
+    assert e.value.status == eot.EOT_ERR_NONFINITE
