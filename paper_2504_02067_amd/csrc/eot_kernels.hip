@@ -664,13 +664,46 @@ __device__ __forceinline__ double sum_tiles(const double* __restrict__ part, int
     return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
+// Column merges: a workgroup of 256 threads sums the partials of 32
+// consecutive columns, 8 threads per column, each over every 8th partial;
+// the 8 group sums are added in a fixed order through LDS. Keeps many loads in
+// flight when there are many row tiles (small tile heights).
+constexpr int kColsPerBlock = 32, kColGroups = kVecThreads / kColsPerBlock;
+
+__device__ __forceinline__ double col_sum_2d(const double* __restrict__ part, int tiles, int64_t m,
+                                             int64_t j, double* s_p)
+{
+    const int c = threadIdx.x % kColsPerBlock, g = threadIdx.x / kColsPerBlock;
+    double a = 0.0, b = 0.0;
+    if (j < m) {
+        int t = g;
+        for (; t + kColGroups < tiles; t += 2 * kColGroups) {
+            a += part[(int64_t)t * m + j];
+            b += part[(int64_t)(t + kColGroups) * m + j];
+        }
+        if (t < tiles) a += part[(int64_t)t * m + j];
+    }
+    s_p[g * kColsPerBlock + c] = a + b;
+    __syncthreads();
+    double r = 0.0;
+#pragma unroll
+    for (int k = 0; k < kColGroups; ++k) r += s_p[k * kColsPerBlock + c];
+    __syncthreads();
+    return r;                                   // the column total, on every group
+}
+
 __global__ void k_merge_cols(const double* part, int tiles, int64_t m, int nc, double* out0,
                              double* out1)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= m) return;
-    if (out0) out0[j] = sum_tiles(part, tiles, m, j);
-    if (nc > 1 && out1) out1[j] = sum_tiles(part + (int64_t)tiles * m, tiles, m, j);
+    __shared__ double s_p[kVecThreads];
+    const int64_t j = (int64_t)blockIdx.x * kColsPerBlock + threadIdx.x % kColsPerBlock;
+    const bool w = threadIdx.x < kColsPerBlock && j < m;
+    const double s0 = col_sum_2d(part, tiles, m, j, s_p);
+    if (w && out0) out0[j] = s0;
+    if (nc > 1) {
+        const double s1 = col_sum_2d(part + (int64_t)tiles * m, tiles, m, j, s_p);
+        if (w && out1) out1[j] = s1;
+    }
 }
 
 // log r(P)_i = a_i + log sum_t part[t][i]; flags[0] set when the shifted sum
@@ -765,9 +798,10 @@ __global__ void k_hvp_rows(const double* part, int tiles, int64_t n, const doubl
 // Hy_j = sum_i P_ij (sqrt(rho) x_i + y_j) = sqrt(rho) (P^T x)_j + c(P)_j y_j
 __global__ void k_hvp_cols(const double* part, int tiles, int64_t m, double* Hy)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= m) return;
-    Hy[j] = sum_tiles(part, tiles, m, j);
+    __shared__ double s_p[kVecThreads];
+    const int64_t j = (int64_t)blockIdx.x * kColsPerBlock + threadIdx.x % kColsPerBlock;
+    const double sj = col_sum_2d(part, tiles, m, j, s_p);
+    if (threadIdx.x < kColsPerBlock && j < m) Hy[j] = sj;
 }
 __global__ void k_axpy(double alpha, const double* x, double* y, int64_t k) { EW_LOOP(k) y[i] += alpha * x[i]; }
 __global__ void k_log(const double* x, double* y, int64_t k) { EW_LOOP(k) y[i] = log(x[i]); }
@@ -894,12 +928,14 @@ __global__ void k_cg_init_finish(const double* red, int nb, CgScalars* sc, doubl
 __global__ void k_cg_colstep(const double* part, int tiles, int64_t m, const double* c, double* w,
                              double* wc, const CgScalars* sc)
 {
-    if (sc && sc->done) return;
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= m) return;
-    const double s = sum_tiles(part, tiles, m, j);
-    w[j] = s;
-    wc[j] = s / c[j];
+    if (sc && sc->done) return;                // uniform
+    __shared__ double s_p[kVecThreads];
+    const int64_t j = (int64_t)blockIdx.x * kColsPerBlock + threadIdx.x % kColsPerBlock;
+    const double sj = col_sum_2d(part, tiles, m, j, s_p);
+    if (threadIdx.x < kColsPerBlock && j < m) {
+        w[j] = sj;
+        wc[j] = sj / c[j];
+    }
 }
 
 __global__ void k_cg_rowstep(const double* part, int tiles, int64_t n, const double* a,
@@ -1075,6 +1111,11 @@ inline int vec_blocks(int64_t k)
     if (b < 1) b = 1;
     if (b > kMaxRedBlocks) b = kMaxRedBlocks;
     return (int)b;
+}
+
+inline int col_blocks(int64_t m)
+{
+    return (int)((m + kColsPerBlock - 1) / kColsPerBlock);
 }
 
 inline int map_blocks(int64_t k)
@@ -1525,7 +1566,7 @@ hipError_t launch_merge_rows(const double* part, int tiles, int64_t n, int nr, c
 hipError_t launch_merge_cols(const double* part, int tiles, int64_t m, int nc, double* out0,
                              double* out1, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_merge_cols, dim3(map_blocks(m)), dim3(kVecThreads), 0, s, part, tiles, m,
+    hipLaunchKernelGGL(k_merge_cols, dim3(col_blocks(m)), dim3(kVecThreads), 0, s, part, tiles, m,
                        nc, out0, out1);
     return hipGetLastError();
 }
@@ -1577,7 +1618,7 @@ hipError_t launch_hvp_finish(const double* row_part, int tiles_m, const double* 
                              int64_t n, int64_t m, const double* a, double* Hx, double* Hy, hipStream_t s)
 {
     hipLaunchKernelGGL(k_hvp_rows, dim3(map_blocks(n)), dim3(kVecThreads), 0, s, row_part, tiles_m, n, a, Hx);
-    hipLaunchKernelGGL(k_hvp_cols, dim3(map_blocks(m)), dim3(kVecThreads), 0, s, col_part, tiles_n, m, Hy);
+    hipLaunchKernelGGL(k_hvp_cols, dim3(col_blocks(m)), dim3(kVecThreads), 0, s, col_part, tiles_n, m, Hy);
     return hipGetLastError();
 }
 hipError_t launch_axpy(double alpha, const double* x, double* y, int64_t k, hipStream_t s) { EW_LAUNCH(k_axpy, k, alpha, x, y, k); }
@@ -1611,7 +1652,7 @@ hipError_t launch_cg_init(const double* b, const double* rP, const double* s_, d
 hipError_t launch_cg_colstep(const double* part, int tiles, int64_t m, const double* c, double* w,
                              double* wc, const CgScalars* sc, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cg_colstep, dim3(map_blocks(m)), dim3(kVecThreads), 0, s, part, tiles, m,
+    hipLaunchKernelGGL(k_cg_colstep, dim3(col_blocks(m)), dim3(kVecThreads), 0, s, part, tiles, m,
                        c, w, wc, sc);
     return hipGetLastError();
 }
