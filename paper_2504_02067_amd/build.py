@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libeot.so")
-SOURCES = ["eot_kernels.hip", "eot_api.hip"]
+SOURCES = ["eot_kernels.hip", "eot_highd.hip", "eot_api.hip"]
 ARCH = os.environ.get("EOT_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled: they are generated from ordinary

@@ -88,6 +88,11 @@ struct GradVecs {
     double *v, *cP, *bv, *inv_c, *mu, *cb, *tm, *h0, *hy0, *hy1, *hy2;          // m
 };
 
+struct HdVecs {
+    void *xh = nullptr, *xl = nullptr, *yh = nullptr, *yl = nullptr;   // BF16, n x d / m x d
+    float *xx = nullptr, *yy = nullptr;
+};
+
 struct Ctx {
     eot_cost cost{};
     int64_t n = 0, m = 0;
@@ -102,6 +107,7 @@ struct Ctx {
     NewtonVecs nv{};
     SolveVecs sv{};
     GradVecs gv{};
+    HdVecs hd{};
     int64_t passes = 0;
     int32_t range_retries = 0;
     bool cg_graph = false;        // replay CG chunks from a recorded HIP graph
@@ -110,6 +116,15 @@ struct Ctx {
 void carve(Arena& ar, Ctx& x, int op)
 {
     const int64_t n = x.n, m = x.m;
+    if (x.cost.kind == EOT_COST_SQEUCLID_POINTS && x.cost.d > 3) {
+        const size_t d = (size_t)x.cost.d;
+        x.hd.xh = ar.take<uint16_t>((size_t)n * d);
+        x.hd.xl = ar.take<uint16_t>((size_t)n * d);
+        x.hd.yh = ar.take<uint16_t>((size_t)m * d);
+        x.hd.yl = ar.take<uint16_t>((size_t)m * d);
+        x.hd.xx = ar.take<float>(n);
+        x.hd.yy = ar.take<float>(m);
+    }
     x.sc.row_part = ar.take<double>((size_t)2 * x.rtiles * n);
     x.sc.col_part = ar.take<double>((size_t)2 * x.ctiles * m);
     x.sc.red = ar.take<double>(2 * kMaxRedBlocks);
@@ -155,7 +170,9 @@ eot_status check_cost(const eot_cost* c)
     if (c->kind == EOT_COST_SQEUCLID_POINTS) {
         if (!c->X || !c->Y || !(c->scale > 0.0) || !std::isfinite(c->scale) || c->d < 1)
             return EOT_ERR_INVALID_ARG;
-        if (c->d != 2 && c->d != 3) return EOT_ERR_UNSUPPORTED;
+        const bool low = c->d == 2 || c->d == 3;
+        const bool high = c->d >= 16 && c->d <= 64 && c->d % 16 == 0;
+        if (!low && !high) return EOT_ERR_UNSUPPORTED;
         return EOT_OK;
     }
     return EOT_ERR_INVALID_ARG;
@@ -189,13 +206,23 @@ int pick_rows_per_tile(int64_t n, int64_t m, int kind)
 
 void layout(Ctx& x)
 {
-    x.tiles_m = (int)tiles_m_of(x.m);
-    x.rb = pick_rows_per_tile(x.n, x.m, x.cost.kind);
-    x.tiles_n = (int)tiles_n_of(x.n, x.rb);
+    const bool high_d = x.cost.kind == EOT_COST_SQEUCLID_POINTS && x.cost.d > 3;
+    int row_parts;
+    if (high_d) {                      // matrix-core tiles: one row partial per tile
+        x.tiles_m = (int)((x.m + kHdTileCols - 1) / kHdTileCols);
+        x.rb = kHdTileRows;
+        x.tiles_n = (int)tiles_n_of(x.n, x.rb);
+        row_parts = x.tiles_m;
+    } else {
+        x.tiles_m = (int)tiles_m_of(x.m);
+        x.rb = pick_rows_per_tile(x.n, x.m, x.cost.kind);
+        x.tiles_n = (int)tiles_n_of(x.n, x.rb);
+        row_parts = row_tiles(x.tiles_m);
+    }
     const double part_bytes =
-        16.0 * ((double)row_tiles(x.tiles_m) * (double)x.n + (double)x.tiles_n * (double)x.m);
+        16.0 * ((double)row_parts * (double)x.n + (double)x.tiles_n * (double)x.m);
     x.atomic = part_bytes > 512.0e6 ? 1 : 0;
-    x.rtiles = x.atomic ? 1 : row_tiles(x.tiles_m);
+    x.rtiles = x.atomic ? 1 : row_parts;
     x.ctiles = x.atomic ? 1 : x.tiles_n;
 }
 
@@ -220,6 +247,10 @@ eot_status setup(Ctx& x, const eot_cost* cost, int op, int prec, void* ws, size_
     ar.dry = false;
     carve(ar, x, op);
     HIPCHK(hipMemsetAsync(x.sc.flags, 0, 16 * sizeof(int32_t), x.s));
+    if (x.hd.xh) {
+        HIPCHK(launch_hd_prep(x.cost.X, x.n, x.cost.d, x.hd.xh, x.hd.xl, x.hd.xx, x.s));
+        HIPCHK(launch_hd_prep(x.cost.Y, x.m, x.cost.d, x.hd.yh, x.hd.yl, x.hd.yy, x.s));
+    }
     return EOT_OK;
 }
 
@@ -246,6 +277,12 @@ PassArgs make_args(const Ctx& x, const double* u, const double* a, const double*
     A.tiles_n = x.tiles_n;
     A.atomic = x.atomic;
     A.rb = x.rb;
+    A.hd_xh = x.hd.xh;
+    A.hd_xl = x.hd.xl;
+    A.hd_yh = x.hd.yh;
+    A.hd_yl = x.hd.yl;
+    A.hd_xx = x.hd.xx;
+    A.hd_yy = x.hd.yy;
     return A;
 }
 
@@ -1319,6 +1356,7 @@ eot_status eot_gradient(const eot_cost* cost, double gamma, const double* f, con
     const bool pts = cost->kind == EOT_COST_SQEUCLID_POINTS;
     if (grad_C && (pts || ldg < cost->m)) return EOT_ERR_INVALID_ARG;
     if ((grad_X || grad_Y) && !pts) return EOT_ERR_INVALID_ARG;
+    if ((grad_X || grad_Y) && cost->d > 3) return EOT_ERR_UNSUPPORTED;
     Ctx x;
     EOTCHK(setup(x, cost, EOT_OP_GRADIENT, prec, ws, ws_bytes, stream));
     return gradient_impl(x, gamma, f, g, w_W, w_S, grad_C, ldg, grad_X, grad_Y, grad_r, grad_c,

@@ -1,0 +1,496 @@
+// Streaming passes for high-dimensional point clouds (d = 16, 32, 48, 64):
+// C_ij = |x_i - y_j|^2 / s recomputed on the fly, with the x . y contraction on
+// the matrix cores in mixed precision.
+//
+// |x_i - y_j|^2 = |x_i|^2 + |y_j|^2 - 2 x_i . y_j. A workgroup (4 wave64) owns
+// 128 rows x 512 columns; each wave owns 32 rows and walks the 512 columns in
+// steps of 32, computing the 32 x 32 block of dot products with
+// v_mfma_f32_32x32x16_bf16. FP32 coordinates are split as x = xh + xl with xh
+// = bf16(x), xl = bf16(x - xh), prepared once per call together with the
+// squared norms; x . y ~ xh.yh + xh.yl + xl.yh (three MFMAs per 16 dimensions,
+// FP32 accumulation; the dropped xl.yl term is ~2^-16 relative). Each step's
+// 32 columns are staged in LDS once for the 4 waves.
+// The plan entries then go through the same mixed-precision exponent and FP64
+// accumulation as the dense pass. In FP64 mode the squared distance is formed
+// per entry in FP64 (difference form, VALU), for the line search and the final
+// verification of a solve.
+//
+// Lane layout of the 32 x 32 MFMA result (checked on the target): lane l holds
+// the entries (row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32), r = 0..15;
+// operand A lane l supplies row l % 32, dimensions 8 (l / 32) + 0..7 of each
+// 16-dimension chunk, operand B lane l the same dimensions of column l % 32.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "eot_internal.h"
+
+namespace eot {
+namespace {
+
+constexpr int kHdRows = kHdTileRows;        // 128: 4 waves x 32 rows
+constexpr int kHdCols = kHdTileCols;        // 512: 16 steps of 32 columns
+constexpr int kHdStep = 32;
+constexpr int kHdMaxD = 64;
+constexpr double kLog2eHd = 1.4426950408889634074;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ double hd_wave_max(double x)
+{
+    for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
+    return x;
+}
+
+
+// OP = 0: the pass (sums); OP = 1: row maxima of u_i + v_j - beta C_ij (FP32,
+// a range shift only), into part[blockIdx.x][n] or atomically into out32.
+template <int PREC, int NR, int NC, int MODE2, int OP>
+__global__ __launch_bounds__(256) void k_pass_hd(PassArgs A, float* out32)
+{
+    if (A.skip && *A.skip) return;
+    constexpr bool MIXED = PREC == EOT_PREC_MIXED;
+    constexpr bool MAXOP = OP == 1;
+    constexpr int NRA = NR > 0 ? NR : 1, NCA = NC > 0 ? NC : 1;
+    __shared__ float s_x[MIXED && !MAXOP ? 1 : kHdRows * kHdMaxD];   // FP64 / max: row points
+    __shared__ float s_y[MIXED && !MAXOP ? 1 : kHdStep * kHdMaxD];   // FP64 / max: step columns
+    __shared__ float s_xx[kHdRows];
+    __shared__ float s_uh[kHdRows];
+    __shared__ double s_A[kHdRows];
+    __shared__ double s_rf[kHdRows];
+    __shared__ double s_xw[2][kHdRows];
+    __shared__ double s_rr[kHdRows];
+    __shared__ double s_col[kWaves][NCA][kHdStep];
+    __shared__ double s_wmax[kWaves];
+    // mixed: the step's 32 columns as BF16 hi / lo, rows padded by 8 (no bank conflicts)
+    constexpr int kLd = kHdMaxD + 8;
+    __shared__ __attribute__((aligned(16))) __bf16 s_bh[MIXED && !MAXOP ? kHdStep * kLd : 1];
+    __shared__ __attribute__((aligned(16))) __bf16 s_bl[MIXED && !MAXOP ? kHdStep * kLd : 1];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t n = A.n, m = A.m;
+    const int d = A.d;
+    const int kch = d / 16;
+    const int64_t i0 = (int64_t)blockIdx.y * kHdRows;
+    const int64_t j0 = (int64_t)blockIdx.x * kHdCols;
+
+    // ---- prologue: row values (LDS), the tile's exponent grid (mixed)
+    const int64_t irow = i0 + tid;
+    const bool rvalid = tid < kHdRows && irow < n;
+    double arow = 0.0, Ud = 0.0, uh = 0.0, ul = 0.0, sc = 1.0, isc = 1.0;
+    if (tid < kHdRows) {
+        if constexpr (MIXED && !MAXOP) {
+            s_xx[tid] = rvalid ? A.hd_xx[irow] : 0.0f;
+        } else {
+            for (int k = 0; k < d; ++k) s_x[tid * kHdMaxD + k] = rvalid ? A.X[irow * d + k] : 0.0f;
+        }
+    }
+    if constexpr (MIXED && !MAXOP) {
+        double mx = 0.0;
+        for (int c = tid; c < kHdCols; c += 256) {
+            const int64_t j = j0 + c;
+            if (j < m) mx = fmax(mx, fabs(kLog2eHd * A.v[j]));
+        }
+        if (rvalid) {
+            arow = A.a[irow];
+            Ud = kLog2eHd * (A.u[irow] - arow);
+            mx = fmax(mx, fabs(Ud));
+        }
+        mx = hd_wave_max(mx);
+        if (lane == 0) s_wmax[wave] = mx;
+        __syncthreads();
+        mx = fmax(fmax(s_wmax[0], s_wmax[1]), fmax(s_wmax[2], s_wmax[3]));
+        if (!(mx < 4.0e6)) mx = 4.0e6;
+        int e2;
+        frexp(2.0 * mx + 2.0, &e2);
+        const int g = 23 - e2;
+        sc = ldexp(1.0, g);
+        isc = ldexp(1.0, -g);
+        uh = rint(Ud * sc) * isc;
+        ul = Ud - uh;
+    } else if (rvalid) {
+        arow = MAXOP ? 0.0 : A.a[irow];
+    }
+    if (tid < kHdRows) {
+        if (rvalid) {
+            const double rf = MIXED && !MAXOP ? exp2(ul) : 1.0;
+            const double R = MAXOP ? 0.0 : exp(arow) * rf;
+            s_uh[tid] = MAXOP ? (float)A.u[irow] : (float)uh;
+            s_A[tid] = MIXED ? 0.0 : A.u[irow] - arow;
+            s_rf[tid] = rf;
+            s_rr[tid] = R;
+            if constexpr (MODE2 == R2_HVP) {
+                s_xw[0][tid] = R * A.hvp_srho * A.xw1[irow];
+                s_xw[1][tid] = A.xw1[irow];
+            } else {
+                s_xw[0][tid] = R * (A.xw0 ? A.xw0[irow] : 1.0);
+                s_xw[1][tid] = R * (A.xw1 ? A.xw1[irow] : 1.0);
+            }
+        } else {
+            s_uh[tid] = -INFINITY;
+            s_A[tid] = -INFINITY;
+            s_rf[tid] = 0.0;
+            s_rr[tid] = 0.0;
+            s_xw[0][tid] = 0.0;
+            s_xw[1][tid] = 0.0;
+        }
+    }
+    __syncthreads();
+
+    // ---- this wave's 32 rows: MFMA operand A (mixed) for every 16-dimension chunk
+    const int rl = lane & 31, half = lane >> 5;
+    const int64_t arow_i = i0 + wave * 32 + rl;
+    bf16x8 ah[kHdMaxD / 16], al[kHdMaxD / 16];
+    if constexpr (MIXED && !MAXOP) {
+        const __bf16* xh = static_cast<const __bf16*>(A.hd_xh);
+        const __bf16* xl = static_cast<const __bf16*>(A.hd_xl);
+        const bool ok = arow_i < n;
+#pragma unroll
+        for (int kc = 0; kc < kHdMaxD / 16; ++kc) {
+            if (kc < kch) {
+                const int64_t off = arow_i * d + kc * 16 + 8 * half;
+                if (ok) {
+                    ah[kc] = *reinterpret_cast<const bf16x8*>(xh + off);
+                    al[kc] = *reinterpret_cast<const bf16x8*>(xl + off);
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) ah[kc][t] = al[kc][t] = (__bf16)0.0f;
+                }
+            }
+        }
+    }
+    // rows of the 16 result entries of this lane (tile-local)
+    int rowl[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) rowl[r] = wave * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+
+    const double Bd = kLog2eHd * A.beta;
+    const float Bh = (float)Bd;
+    const float Bl = (float)(Bd - (double)Bh);
+    const double beta = A.beta;
+    const double srho = A.hvp_srho;
+
+    double racc[NRA][16];
+#pragma unroll
+    for (int k = 0; k < NRA; ++k)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) racc[k][r] = MAXOP ? -INFINITY : 0.0;
+
+    // mixed: one 16-byte chunk of a step's columns per thread (32 columns x d / 8 chunks <= 256)
+    const int per = d / 8;
+    const int sc_c = tid / (per > 0 ? per : 1), sc_q = tid % (per > 0 ? per : 1);
+    const bool stager = tid < kHdStep * per;
+
+    const int nsteps = kHdCols / kHdStep;
+    for (int st = 0; st < nsteps; ++st) {
+        const int64_t jc = j0 + (int64_t)st * kHdStep;
+        if (jc >= m) break;                                  // uniform
+        const int64_t j = jc + rl;                           // this lane's column
+        const bool jok = j < m;
+        // column values of this lane
+        float vh = -INFINITY, vl = 0.0f, vf = -INFINITY;
+        double vc = -INFINITY;
+        double yw0 = 0.0, yw1 = 0.0;
+        if (jok) {
+            const double Vd = kLog2eHd * A.v[j];
+            if constexpr (MIXED && !MAXOP) {
+                const double h = rint(Vd * sc) * isc;
+                vh = (float)h;
+                vl = (float)(Vd - h);
+            }
+            vf = (float)A.v[j];
+            vc = A.v[j];
+            if constexpr (MODE2 == R2_HVP) {
+                yw0 = A.yw1[j];
+            } else {
+                yw0 = A.yw0 ? A.yw0[j] : 1.0;
+                yw1 = A.yw1 ? A.yw1[j] : 1.0;
+            }
+        }
+        // squared distances of the lane's 16 entries
+        float d2f[16];
+        double d2d[16];
+        if constexpr (MIXED && !MAXOP) {
+            // stage the step's columns (BF16 hi / lo) once for the 4 waves
+            __syncthreads();
+            if (stager) {
+                const int64_t jj = jc + sc_c;
+                bf16x8 h8, l8;
+                if (jj < m) {
+                    const int64_t o = jj * d + sc_q * 8;
+                    h8 = *reinterpret_cast<const bf16x8*>(static_cast<const __bf16*>(A.hd_yh) + o);
+                    l8 = *reinterpret_cast<const bf16x8*>(static_cast<const __bf16*>(A.hd_yl) + o);
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) h8[t] = l8[t] = (__bf16)0.0f;
+                }
+                *reinterpret_cast<bf16x8*>(&s_bh[sc_c * kLd + sc_q * 8]) = h8;
+                *reinterpret_cast<bf16x8*>(&s_bl[sc_c * kLd + sc_q * 8]) = l8;
+            }
+            __syncthreads();
+            const float yy = jok ? A.hd_yy[j] : 0.0f;
+            f32x16 acc = {};
+#pragma unroll
+            for (int kc = 0; kc < kHdMaxD / 16; ++kc) {
+                if (kc < kch) {
+                    const int o = rl * kLd + kc * 16 + 8 * half;
+                    const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&s_bh[o]);
+                    const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&s_bl[o]);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kc], bh, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kc], bl, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[kc], bh, acc, 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                d2f[r] = fmaxf(s_xx[rowl[r]] + yy - 2.0f * acc[r], 0.0f);
+        } else {
+            // stage this step's 32 columns in LDS, then per-entry difference form
+            __syncthreads();
+            for (int e = tid; e < kHdStep * d; e += 256) {
+                const int c = e / d, k = e % d;
+                const int64_t jj = jc + c;
+                s_y[c * kHdMaxD + k] = jj < m ? A.Y[jj * d + k] : 0.0f;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                if constexpr (MAXOP) {
+                    float acc = 0.0f;
+                    for (int k = 0; k < d; ++k) {
+                        const float df = s_x[rowl[r] * kHdMaxD + k] - s_y[rl * kHdMaxD + k];
+                        acc = fmaf(df, df, acc);
+                    }
+                    d2f[r] = acc;
+                } else {
+                    double acc = 0.0;
+                    for (int k = 0; k < d; ++k) {
+                        const double df =
+                            (double)s_x[rowl[r] * kHdMaxD + k] - (double)s_y[rl * kHdMaxD + k];
+                        acc = fma(df, df, acc);
+                    }
+                    d2d[r] = acc;
+                }
+            }
+        }
+        // epilogue: plan entries, row and column accumulation
+        double cacc[NCA];
+#pragma unroll
+        for (int k = 0; k < NCA; ++k) cacc[k] = 0.0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = rowl[r];
+            if constexpr (MAXOP) {
+                const float x = fmaf(-(float)beta, d2f[r], s_uh[row] + vf);
+                racc[0][r] = fmax(racc[0][r], (double)x);
+                continue;
+            } else {
+                double e64, cd;
+                if constexpr (MIXED) {
+                    const float c = d2f[r];
+                    const float t = fmaf(-Bh, c, s_uh[row] + vh);
+                    const float w = fmaf(-Bl, c, vl);
+                    e64 = (double)__builtin_amdgcn_exp2f(t + w);
+                    cd = (double)c;
+                } else {
+                    const double c = d2d[r];
+                    e64 = exp(fma(-beta, c, s_A[row] + vc));
+                    cd = c;
+                }
+                const double xw0 = s_xw[0][row], xw1 = s_xw[1][row];
+                if constexpr (MODE2 == R2_HVP) {
+                    racc[0][r] = fma(e64, fma(srho, yw0, xw1), racc[0][r]);
+                    cacc[0] = fma(e64, fma(s_rr[row], yw0, xw0), cacc[0]);
+                } else {
+                    if constexpr (NR >= 1) racc[0][r] = fma(e64, yw0, racc[0][r]);
+                    if constexpr (NR >= 2) {
+                        double term = e64;
+                        if constexpr (MODE2 == R2_SQUARE) term = e64 * e64;
+                        if constexpr (MODE2 == R2_COST) term = e64 * cd;
+                        racc[NR - 1][r] = fma(term, yw1, racc[NR - 1][r]);
+                    }
+                    if constexpr (NC >= 1) cacc[0] = fma(e64, xw0, cacc[0]);
+                    if constexpr (NC >= 2) {
+                        const double term = MODE2 == R2_COST ? e64 * cd : e64;
+                        cacc[NC - 1] = fma(term, xw1, cacc[NC - 1]);
+                    }
+                }
+            }
+        }
+        if constexpr (NC > 0 && !MAXOP) {
+            // the wave's 32-row column sums: both lane halves, then the 4 waves
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                const double tot = cacc[k] + __shfl_xor(cacc[k], 32, 64);
+                if (half == 0) s_col[wave][k][rl] = tot;
+            }
+            __syncthreads();
+            if (tid < kHdStep) {
+                const int64_t jj = jc + tid;
+                if (jj < m) {
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) {
+                        const double v =
+                            (s_col[0][k][tid] + s_col[1][k][tid]) + (s_col[2][k][tid] + s_col[3][k][tid]);
+                        if (A.atomic)
+                            atomicAdd(&A.col_part[(int64_t)k * m + jj], v);
+                        else
+                            A.col_part[((int64_t)k * A.tiles_n + blockIdx.y) * m + jj] = v;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    // ---- row outputs: reduce each of the lane's 16 rows over the 32 lanes of its half
+    if constexpr (NR > 0 || MAXOP) {
+#pragma unroll
+        for (int k = 0; k < NRA; ++k) {
+            if constexpr (!MAXOP) {
+                if (k >= NR) break;
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                double v = racc[k][r];
+#pragma unroll
+                for (int off = 16; off > 0; off >>= 1) {
+                    const double o = __shfl_xor(v, off, 64);
+                    v = MAXOP ? fmax(v, o) : v + o;
+                }
+                racc[k][r] = v;
+            }
+            if (rl == 0) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int row = rowl[r];
+                    const int64_t i = i0 + row;
+                    if (i >= n) continue;
+                    if constexpr (MAXOP) {
+                        const float x = (float)racc[0][r];
+                        if (A.atomic) {
+                            if (x >= 0.0f)
+                                atomicMax(reinterpret_cast<int*>(&out32[i]), __float_as_int(x));
+                            else
+                                atomicMin(reinterpret_cast<unsigned int*>(&out32[i]), __float_as_uint(x));
+                        } else {
+                            A.row_part[(int64_t)blockIdx.x * n + i] = (double)x;
+                        }
+                    } else {
+                        double fac = s_rf[row];
+                        if (k == 1 && MODE2 == R2_SQUARE) fac *= fac;
+                        const double v = racc[k][r] * fac;
+                        if (A.atomic)
+                            atomicAdd(&A.row_part[(int64_t)k * n + i], v);
+                        else
+                            A.row_part[((int64_t)k * A.tiles_m + blockIdx.x) * n + i] = v;
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int NR, int NC, int MODE2>
+hipError_t launch_hd(const PassArgs& a, int prec, hipStream_t s)
+{
+    dim3 grid((unsigned)a.tiles_m, (unsigned)a.tiles_n);
+    if (prec == EOT_PREC_MIXED)
+        hipLaunchKernelGGL((k_pass_hd<EOT_PREC_MIXED, NR, NC, MODE2, 0>), grid, dim3(256), 0, s, a,
+                           nullptr);
+    else
+        hipLaunchKernelGGL((k_pass_hd<EOT_PREC_FP64, NR, NC, MODE2, 0>), grid, dim3(256), 0, s, a,
+                           nullptr);
+    return hipGetLastError();
+}
+
+// BF16 hi / lo parts and squared norm of each of k points (one thread per point)
+__global__ void k_hd_prep(const float* __restrict__ P, int64_t k, int d, __bf16* hi, __bf16* lo,
+                          float* sq)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float s2 = 0.0f;
+        for (int t = 0; t < d; ++t) {
+            const float v = P[i * d + t];
+            const __bf16 h = (__bf16)v;
+            hi[i * d + t] = h;
+            lo[i * d + t] = (__bf16)(v - (float)h);
+            s2 = fmaf(v, v, s2);
+        }
+        sq[i] = s2;
+    }
+}
+
+__global__ void k_hd_fill_f32(float* x, float v, int64_t k)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+
+__global__ void k_hd_to_f64(const float* x, double* y, int64_t k)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (double)x[i];
+}
+
+__global__ void k_hd_merge_max(const double* part, int tiles, int64_t n, double* out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double r = part[i];
+    for (int t = 1; t < tiles; ++t) r = fmax(r, part[(int64_t)t * n + i]);
+    out[i] = r;
+}
+
+}  // namespace
+
+bool is_high_d(const PassArgs& a) { return a.kind == EOT_COST_SQEUCLID_POINTS && a.d > 3; }
+
+hipError_t launch_hd_prep(const float* P, int64_t k, int d, void* hi, void* lo, float* sq,
+                          hipStream_t s)
+{
+    const int64_t b = (k + 255) / 256;
+    hipLaunchKernelGGL(k_hd_prep, dim3((unsigned)(b < 4096 ? (b < 1 ? 1 : b) : 4096)), dim3(256), 0,
+                       s, P, k, d, static_cast<__bf16*>(hi), static_cast<__bf16*>(lo), sq);
+    return hipGetLastError();
+}
+
+hipError_t launch_pass_hd(const PassArgs& a, int prec, int nr, int nc, int mode2, hipStream_t s)
+{
+    if (a.d % 16 != 0 || a.d < 16 || a.d > kHdMaxD) return hipErrorInvalidValue;
+    if (nr == 1 && nc == 1 && mode2 == R2_HVP) return launch_hd<1, 1, R2_HVP>(a, prec, s);
+    if (nr == 1 && nc == 1) return launch_hd<1, 1, R2_WEIGHT>(a, prec, s);
+    if (nr == 2 && nc == 1 && mode2 == R2_SQUARE) return launch_hd<2, 1, R2_SQUARE>(a, prec, s);
+    if (nr == 2 && nc == 2 && mode2 == R2_WEIGHT) return launch_hd<2, 2, R2_WEIGHT>(a, prec, s);
+    if (nr == 2 && nc == 1 && mode2 == R2_COST) return launch_hd<2, 1, R2_COST>(a, prec, s);
+    if (nr == 2 && nc == 2 && mode2 == R2_COST) return launch_hd<2, 2, R2_COST>(a, prec, s);
+    if (nr == 2 && nc == 0 && mode2 == R2_SQUARE) return launch_hd<2, 0, R2_SQUARE>(a, prec, s);
+    if (nr == 2 && nc == 0 && mode2 == R2_COST) return launch_hd<2, 0, R2_COST>(a, prec, s);
+    if (nr == 1 && nc == 0) return launch_hd<1, 0, R2_WEIGHT>(a, prec, s);
+    if (nr == 0 && nc == 1) return launch_hd<0, 1, R2_WEIGHT>(a, prec, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_rowmax_hd(const PassArgs& a, double* part, double* out, hipStream_t s)
+{
+    if (a.d % 16 != 0 || a.d < 16 || a.d > kHdMaxD) return hipErrorInvalidValue;
+    dim3 grid((unsigned)a.tiles_m, (unsigned)a.tiles_n);
+    float* out32 = reinterpret_cast<float*>(part);
+    const unsigned eb = (unsigned)((a.n + 255) / 256 < 1024 ? (a.n + 255) / 256 : 1024);
+    if (a.atomic)
+        hipLaunchKernelGGL(k_hd_fill_f32, dim3(eb), dim3(256), 0, s, out32, -INFINITY, a.n);
+    hipLaunchKernelGGL((k_pass_hd<EOT_PREC_FP64, 1, 0, R2_WEIGHT, 1>), grid, dim3(256), 0, s, a,
+                       out32);
+    if (a.atomic)
+        hipLaunchKernelGGL(k_hd_to_f64, dim3(eb), dim3(256), 0, s, out32, out, a.n);
+    else
+        hipLaunchKernelGGL(k_hd_merge_max, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s,
+                           part, a.tiles_m, a.n, out);
+    return hipGetLastError();
+}
+
+}  // namespace eot

@@ -64,9 +64,22 @@ struct PassArgs {
     const float* Y;        // points: m x d
     int32_t d;             // point dimension (2 or 3)
     int32_t rb;            // rows per tile: 8, 16, ..., kTileRows (grid.y = ceil(n / rb))
+    // high-dimensional point clouds, mixed precision: BF16 hi / lo parts of X, Y
+    // (n x d, m x d) and the squared norms, prepared once per call
+    const void* hd_xh;
+    const void* hd_xl;
+    const void* hd_yh;
+    const void* hd_yl;
+    const float* hd_xx;
+    const float* hd_yy;
     int32_t atomic;        // 1: row_part = [nr][n], col_part = [nc][m], pre-zeroed, atomically
                            //    accumulated (problems whose per-tile partials would not fit)
 };
+
+// High-dimensional point clouds (d = 16 .. 64, x . y on the matrix cores):
+// 128-row x 512-column tiles, one row partial per tile.
+constexpr int kHdTileRows = 128;
+constexpr int kHdTileCols = 512;
 
 inline int64_t tiles_m_of(int64_t m) { return (m + kTileCols - 1) / kTileCols; }
 inline int64_t tiles_n_of(int64_t n, int rb) { return (n + rb - 1) / rb; }
@@ -77,8 +90,16 @@ hipError_t launch_pass(const PassArgs& a, int prec, int nr, int nc, int mode2, h
 hipError_t set_pass_timing(bool on);
 bool pass_timing_on();
 hipError_t read_pass_timing(int nr, int nc, int prec, int hvp, int64_t* launches, double* ms);
-// Exact row maxima of u_i + v_j - beta C_ij (robust shift): out[n].
+// Row shifts ~ max_j (u_i + v_j - beta C_ij): out[n].
 hipError_t launch_rowmax(const PassArgs& a, double* part, double* out, hipStream_t s);
+// High-dimensional point clouds (eot_highd.hip).
+bool is_high_d(const PassArgs& a);
+hipError_t launch_pass_hd(const PassArgs& a, int prec, int nr, int nc, int mode2, hipStream_t s);
+hipError_t launch_rowmax_hd(const PassArgs& a, double* part, double* out, hipStream_t s);
+// BF16 hi / lo split of k points of dimension d (hi = bf16(p), lo = bf16(p - hi))
+// and their squared norms.
+hipError_t launch_hd_prep(const float* P, int64_t k, int d, void* hi, void* lo, float* sq,
+                          hipStream_t s);
 
 // ---- merges / epilogues (all FP64) ----------------------------------------
 // out_k[i] = exp(a_i) * sum_t part[k][t][i]   (nr row sums)

@@ -1493,6 +1493,7 @@ hipError_t read_pass_timing(int nr, int nc, int prec, int hvp, int64_t* launches
 hipError_t launch_pass(const PassArgs& a, int prec, int nr, int nc, int mode2, hipStream_t s)
 {
     auto go = [&]() -> hipError_t {
+        if (is_high_d(a)) return launch_pass_hd(a, prec, nr, nc, mode2, s);
         if (a.kind == EOT_COST_DENSE_F32 || a.kind == EOT_COST_SQEUCLID_POINTS)
             return dispatch_pass<float>(a, prec, nr, nc, mode2, s);
         if (a.kind == EOT_COST_DENSE_F64) return dispatch_pass<double>(a, prec, nr, nc, mode2, s);
@@ -1520,6 +1521,7 @@ hipError_t launch_pass(const PassArgs& a, int prec, int nr, int nc, int mode2, h
 
 hipError_t launch_rowmax(const PassArgs& a, double* part, double* out, hipStream_t s)
 {
+    if (is_high_d(a)) return launch_rowmax_hd(a, part, out, s);
     // a block spans `span` column tiles so that at most 64 partials (or atomics) per row remain
     const int span = (a.tiles_m + 63) / 64;
     const int gx = (a.tiles_m + span - 1) / span;

@@ -183,14 +183,16 @@ def _vec(t: Optional[torch.Tensor], k: int, name: str, optional: bool = False):
 class PointCloud:
     """Squared-Euclidean cost between point clouds, recomputed inside every pass:
     C_ij = |X_i - Y_j|^2 / scale with X (n x d) and Y (m x d) float32 GPU
-    tensors, d in {2, 3}. The n x m matrix is never stored."""
+    tensors, d in {2, 3} (difference form on the vector units) or d in
+    {16, 32, 48, 64} (x . y on the matrix cores in mixed precision). The n x m
+    matrix is never stored."""
 
     def __init__(self, X: torch.Tensor, Y: torch.Tensor, scale: float):
         for name, T in (("X", X), ("Y", Y)):
             if not T.is_cuda or T.dim() != 2 or T.dtype != torch.float32 or not T.is_contiguous():
                 raise ValueError(f"{name}: need a contiguous 2-D float32 GPU tensor")
-        if X.shape[1] != Y.shape[1] or X.shape[1] not in (2, 3):
-            raise ValueError("X and Y need the same dimension d in {2, 3}")
+        if X.shape[1] != Y.shape[1] or X.shape[1] not in (2, 3, 16, 32, 48, 64):
+            raise ValueError("X and Y need the same dimension d in {2, 3, 16, 32, 48, 64}")
         if not scale > 0:
             raise ValueError("scale must be positive")
         self.X, self.Y, self.scale = X, Y, float(scale)

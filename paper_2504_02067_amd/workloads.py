@@ -235,6 +235,33 @@ def point_cloud_problem(n: int = 1 << 20, seed: int = 5000, m: Optional[int] = N
                    tol=1e-4, meta={"seed": seed, "cost": "sqeuclid_points", "d": d})
 
 
+def embedding_points(rng: np.random.Generator, n: int, d: int, k: int = 8,
+                     spread: float = 0.5) -> np.ndarray:
+    """n unit vectors in R^d around k random unit directions (normalised
+    direction + spread * N(0, I / d)), FP32."""
+    mu = rng.standard_normal((k, d))
+    mu /= np.linalg.norm(mu, axis=1, keepdims=True)
+    comp = rng.integers(0, k, size=n)
+    P = mu[comp] + spread * rng.standard_normal((n, d)) / np.sqrt(d)
+    P /= np.linalg.norm(P, axis=1, keepdims=True)
+    return P.astype(np.float32)
+
+
+def embedding_problem(n: int = 1 << 16, m: Optional[int] = None, d: int = 64,
+                      seed: int = 6000) -> Problem:
+    """Two clouds of unit-norm embeddings in R^d (8 shared directions),
+    uniform marginals, cost |x - y|^2 / 4 (4 bounds the squared distance of
+    unit vectors), recomputed on the fly."""
+    m = n if m is None else m
+    rng = np.random.default_rng(seed)
+    X = embedding_points(rng, n, d)
+    Y = embedding_points(rng, m, d)
+    return Problem(name=f"emb{d}d_n{n}_m{m}_s{seed}", n=n, m=m, r=np.full(n, 1.0 / n),
+                   c=np.full(m, 1.0 / m), X=X, Y=Y, scale=4.0, gamma_init=1.0 / 8.0,
+                   gamma_final=1e-2, tol=1e-5,
+                   meta={"seed": seed, "cost": "sqeuclid_points", "d": d})
+
+
 def random_potentials(rng: np.random.Generator, n: int, m: int, gamma: float,
                       spread: float = 1.0):
     """Potentials in cost units for kernel-level tests: f, g ~ spread * N(0,1)

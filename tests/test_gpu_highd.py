@@ -1,0 +1,99 @@
+"""GPU parity of the high-dimensional point-cloud passes (d = 16 .. 64, the
+x . y contraction on the matrix cores) against the FP64 oracle on the dense
+cost it builds from the same FP32 points.
+
+Tolerances. FP64 mode forms |x - y|^2 per entry in FP64: 1e-12, as for d <= 3.
+Mixed mode: x . y from BF16 hi/lo parts (three products, FP32 accumulation)
+errs by at most ~3 * 2^-17 sum_k |x_k y_k| <= 1.2e-5 (|x|^2 + |y|^2) / 1, and
+|x|^2 + |y|^2 - 2 x . y adds ~3 * 2^-24 (|x|^2 + |y|^2); for unit vectors
+(|x|^2 + |y|^2 = 2, scale 4) an entry's exponent moves by <= 1.2e-5 beta, so a
+log-marginal by at most that plus the 4e-6 of the FP32 exponent.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2504_02067_amd import eot
+from paper_2504_02067_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def say(msg):
+    print(f"[gpu-highd] {msg}", flush=True)
+
+
+def dvec(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def mixed_tol(beta):
+    return 4e-6 + 1.2e-5 * beta
+
+
+def cloud(n, m, d, seed):
+    p = W.embedding_problem(n, m, d, seed)
+    pc = eot.PointCloud(torch.from_numpy(p.X).to(DEV), torch.from_numpy(p.Y).to(DEV), p.scale)
+    return p, pc, O.sqeuclid_points_cost(p.X, p.Y, p.scale)
+
+
+@pytest.mark.parametrize("d", [16, 64])
+@pytest.mark.parametrize("n,m", [(300, 700), (129, 513), (1, 40)])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_highd_marginals_parity(d, n, m, prec):
+    gamma = 0.05
+    beta = 1.0 / gamma
+    p, pc, C = cloud(n, m, d, 10 * d + n)
+    rng = np.random.default_rng(d + m)
+    u = np.log(p.r) + rng.standard_normal(n)
+    v = np.log(p.c) - O.log_col_marginal(C, beta, u, np.zeros(m))
+    f, g = u * gamma, v * gamma
+    u, v = O.to_log_units(f, g, gamma)
+    say(f"high-d marginals d={d} n={n} m={m} {prec}")
+    out = eot.eot_marginals(pc, gamma, dvec(f), dvec(g), c_for_s=dvec(p.c), precision=prec)
+    torch.cuda.synchronize()
+    tol = 1e-12 if prec == "fp64" else mixed_tol(beta)
+    np.testing.assert_allclose(host(out["log_rP"]), O.log_row_marginal(C, beta, u, v), atol=tol, rtol=0)
+    np.testing.assert_allclose(host(out["log_cP"]), O.log_col_marginal(C, beta, u, v), atol=tol, rtol=0)
+    np.testing.assert_allclose(host(out["s"]), O.row_square_sum(C, beta, u, v, p.c), rtol=3 * tol, atol=0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_highd_hvp_parity(prec):
+    n, m, d, gamma, rho = 400, 600, 32, 0.05, 0.5
+    beta = 1.0 / gamma
+    p, pc, C = cloud(n, m, d, 3)
+    rng = np.random.default_rng(5)
+    u = np.log(p.r) + 0.5 * rng.standard_normal(n)
+    v = np.log(p.c) - O.log_col_marginal(C, beta, u, np.zeros(m))
+    f, g = u * gamma, v * gamma
+    u, v = O.to_log_units(f, g, gamma)
+    x = rng.standard_normal(n); y = rng.standard_normal(m)
+    say(f"high-d hvp {prec}")
+    Hx, Hy = eot.eot_hvp(pc, gamma, dvec(f), dvec(g), rho, dvec(x), dvec(y), precision=prec)
+    Hx_ref, Hy_ref = O.hvp(C, beta, u, v, rho, x, y)
+    ax, ay = O.hvp(C, beta, u, v, rho, np.abs(x), np.abs(y))
+    tol = 1e-12 if prec == "fp64" else mixed_tol(beta)
+    assert np.all(np.abs(host(Hx) - Hx_ref) <= tol * ax + 1e-300)
+    assert np.all(np.abs(host(Hy) - Hy_ref) <= tol * ay + 1e-300)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_highd_solve_parity(prec):
+    p, pc, C = cloud(300, 400, 64, 11)
+    kw = dict(gamma_init=1.0 / 8.0, gamma_final=0.02, tol=1e-6)
+    say(f"high-d solve {prec}")
+    f, g, st = eot.eot_solve(pc, dvec(p.r), dvec(p.c), precision=prec, **kw)
+    u, v, ost = O.solve(C, p.r, p.c, **kw)
+    assert st["status"] == 0 and ost["status"] == 0
+    assert st["err_r"] + st["err_c"] <= kw["tol"]
+    rel = abs(st["cost"] - ost["cost"]) / ost["cost"]
+    say(f"  cost rel diff {rel:.2e}")
+    assert rel <= (1e-10 if prec == "fp64" else 1e-5)
