@@ -95,12 +95,11 @@ def cpu_baseline(p, C_rows_fn, budget_s=10.0):
 def valu_cycles_points_hvp(d):
     """VALU instructions per plan entry that the mixed point-cloud HVP needs
     (one lane; each issues in one cycle): d subtractions and d multiply-adds
-    for |x - y|^2, four for the exponent (hi-part sum, two multiply-adds, the
-    hi + lo add), exp2, the FP32 -> FP64 conversion, and four FP64
-    multiply-adds for the row and column accumulations. Loop control and the
-    per-row reductions come on top (the compiled loop issues 18.2 per entry
-    at d = 3)."""
-    return 2 * d + 4 + 1 + 1 + 4
+    for |x - y|^2, three for the exponent (hi-part sum, two multiply-adds),
+    exp2, the FP32 -> FP64 conversion, and four FP64 multiply-adds for the row
+    and column accumulations. Loop control and the per-row reductions come on
+    top (the compiled loop issues 15.75 per entry at d = 3)."""
+    return 2 * d + 3 + 1 + 1 + 4
 
 
 def points_measure(args, eot, W, dev, iters=4):

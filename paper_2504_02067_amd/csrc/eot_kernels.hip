@@ -30,10 +30,11 @@
 //    are split per tile into a hi part on a grid 2^-g (g chosen from the
 //    tile's largest |U|, |V|) and an FP32 lo part, and log2(e) beta into
 //    Bh + Bl, so that Uh + Vh is exact in FP32 and
-//        x = fma(-Bh, C, Uh + Vh) + fma(-Bl, C, Vl)
-//    carries one rounding of a number close to log2(P_ij / r(P)_i). 2^Ul and
-//    exp(a_i) become an FP64 per-row factor. exp2 is v_exp_f32; every sum is
-//    accumulated in FP64.
+//        x = fma(-Bl, C, fma(-Bh, C, Uh + Vh))
+//    carries two roundings of a number close to log2(P_ij / r(P)_i). 2^Ul and
+//    exp(a_i) become an FP64 per-row factor, 2^Vl an FP64 per-column factor
+//    (folded into the row weights and applied to the column totals). exp2 is
+//    v_exp_f32; every sum is accumulated in FP64.
 //  * FP64 mode evaluates x = fma(-beta, C, (u_i - a_i) + v_j) and exp in FP64.
 // The row shift a_i (about log r(P)_i) only keeps exponentials in range.
 
@@ -376,7 +377,12 @@ __device__ __forceinline__ void pass_body(const PassArgs& A)
     const double beta = A.beta;
     const double srho = A.hvp_srho;
 
+    // Mixed: the column's lo exponent enters as the factor f_j = 2^Vl_j, folded
+    // into the row weights here and applied to the column totals at the end,
+    // so a plan entry costs exp2(fma(-Bl, C, fma(-Bh, C, Uh + Vh))) * f_j.
     double ywr[NYW][NCH][V];
+    double fj[MODE2 == R2_HVP && MIXED ? NCH : 1][MODE2 == R2_HVP && MIXED ? V : 1];
+    double ayw[MODE2 == R2_HVP && MIXED ? NCH : 1][MODE2 == R2_HVP && MIXED ? V : 1];
 #pragma unroll
     for (int k = 0; k < NYW; ++k)
 #pragma unroll
@@ -385,7 +391,17 @@ __device__ __forceinline__ void pass_body(const PassArgs& A)
             for (int q = 0; q < V; ++q) {
                 const int64_t j = j0 + (int64_t)ch * T * V + tid * V + q;
                 const double* yw = MODE2 == R2_HVP ? A.yw1 : (k == 0 ? A.yw0 : A.yw1);
-                ywr[k][ch][q] = (j < m) ? (yw ? yw[j] : 1.0) : 0.0;
+                double w = (j < m) ? (yw ? yw[j] : 1.0) : 0.0;
+                if constexpr (MIXED) {
+                    const double f = exp2((double)vl[ch][q]);
+                    if constexpr (MODE2 == R2_HVP) {
+                        fj[ch][q] = f;
+                        ayw[ch][q] = srho * w * f;
+                    } else {
+                        w *= (k == NR - 1 && NR >= 2 && MODE2 == R2_SQUARE) ? f * f : f;
+                    }
+                }
+                ywr[k][ch][q] = w;
             }
     double cacc[NCA][NCH][V];
 #pragma unroll
@@ -413,8 +429,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& A)
                 if constexpr (MIXED) {
                     const float c = getc(rr, q);
                     const float t = fmaf(-Bh, c, s_uh[sb + rr] + vh[ch][q]);
-                    const float w = fmaf(-Bl, c, vl[ch][q]);
-                    e64 = (double)__builtin_amdgcn_exp2f(t + w);
+                    e64 = (double)__builtin_amdgcn_exp2f(fmaf(-Bl, c, t));
                     cd = (double)c;
                 } else {
                     const double c = getc(rr, q);
@@ -423,7 +438,10 @@ __device__ __forceinline__ void pass_body(const PassArgs& A)
                 }
                 if constexpr (MODE2 == R2_HVP) {
                     // rows: e (x_i + sqrt(rho) y_j); columns: R_i e (sqrt(rho) x_i + y_j)
-                    racc[0][rr] = fma(e64, fma(srho, ywr[0][ch][q], xw1), racc[0][rr]);
+                    if constexpr (MIXED)
+                        racc[0][rr] = fma(e64, fma(xw1, fj[ch][q], ayw[ch][q]), racc[0][rr]);
+                    else
+                        racc[0][rr] = fma(e64, fma(srho, ywr[0][ch][q], xw1), racc[0][rr]);
                     cacc[0][ch][q] = fma(e64, fma(s_rr[sb + rr], ywr[0][ch][q], xw0), cacc[0][ch][q]);
                 } else {
                     if constexpr (NR >= 1) racc[0][rr] = fma(e64, ywr[0][ch][q], racc[0][rr]);
@@ -517,10 +535,12 @@ __device__ __forceinline__ void pass_body(const PassArgs& A)
                 for (int q = 0; q < V; ++q) {
                     const int64_t j = j0 + (int64_t)ch * T * V + tid * V + q;
                     if (j < m) {
+                        double v = cacc[k][ch][q];
+                        if constexpr (MIXED) v *= exp2((double)vl[ch][q]);
                         if (A.atomic)
-                            atomicAdd(&A.col_part[(int64_t)k * m + j], cacc[k][ch][q]);
+                            atomicAdd(&A.col_part[(int64_t)k * m + j], v);
                         else
-                            A.col_part[((int64_t)k * A.tiles_n + blockIdx.y) * m + j] = cacc[k][ch][q];
+                            A.col_part[((int64_t)k * A.tiles_n + blockIdx.y) * m + j] = v;
                     }
                 }
     }
