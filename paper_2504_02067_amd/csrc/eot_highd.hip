@@ -24,6 +24,7 @@
 #include <math.h>
 
 #include "eot_internal.h"
+#include "eot_lanes.h"
 
 namespace eot {
 namespace {
@@ -392,10 +393,287 @@ __global__ __launch_bounds__(256) void k_pass_hd(PassArgs A, float* out32)
     }
 }
 
+
+// ---- mixed precision, column blocks staged once per 4 steps -------------------
+// The norms are folded into the potentials before the hi / lo split:
+//     log2 P_ij - a_i log2 e = (U_i - B |x_i|^2) + (V_j - B |y_j|^2) + 2 B x_i . y_j
+// with B = log2(e) beta / s, so a plan entry costs
+//     e = exp2(fma(2 Bl, xy, fma(2 Bh, xy, Uh_i + Vh_j)))
+// (Uh + Vh exact on the tile's grid, xy the MFMA result), and the lo parts
+// become the FP64 factors 2^Ul_i (row totals) and 2^Vl_j (column weights and
+// column totals). Each lane keeps the per-row values of its 16 result rows in
+// registers for the whole tile; the 4 waves share a block of 128 staged
+// columns (BF16 hi / lo and a 16-byte record per column), so the step loop
+// has no barrier and reads LDS only for the MFMA operands and the record.
+// Within a lane, the 16 entries of a step (column sums) and the tile's 16
+// steps (row sums) accumulate in FP32; every sum across lanes, waves and tiles
+// is FP64.
+constexpr int kHdBlk = 128;                  // staged columns: 4 steps of 32
+constexpr int kHdCs = kHdMaxD / 8 + 1;       // 16-byte chunks per staged column (odd: no conflicts)
+
+template <int NR, int NC, int MODE2, int KC>
+__global__ __launch_bounds__(256) EOT_HD_OCCUPANCY void k_pass_hd_mx(PassArgs A)
+{
+    static_assert(KC >= 1 && KC * 16 <= kHdMaxD, "KC = d / 16");
+    if (A.skip && *A.skip) return;
+    constexpr bool HVP = MODE2 == R2_HVP;
+    constexpr int NV = HVP ? 4 : 1 + NC;      // per-row register values
+    constexpr int NRA = NR > 0 ? NR : 1, NCA = NC > 0 ? NC : 1;
+    __shared__ __attribute__((aligned(16))) __bf16 s_bh[kHdBlk * kHdCs * 8];
+    __shared__ __attribute__((aligned(16))) __bf16 s_bl[kHdBlk * kHdCs * 8];
+    __shared__ __attribute__((aligned(16))) float4 s_rec[kHdBlk];
+    __shared__ float s_cp[NCA][kWaves][kHdBlk];
+    __shared__ __attribute__((aligned(16))) float s_rv[NV][kHdRows];
+    __shared__ double s_rf[kHdRows];
+    __shared__ double s_wmax[kWaves];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int rl = lane & 31, half = lane >> 5;
+    const int64_t n = A.n, m = A.m;
+    constexpr int d = KC * 16, nch = d / 8, cs = nch + 1;
+    const int64_t i0 = (int64_t)blockIdx.y * kHdRows;
+    const int64_t j0 = (int64_t)blockIdx.x * kHdCols;
+    const double Bd = kLog2eHd * A.beta;
+    const double srho = A.hvp_srho;
+
+    // ---- the tile's exponent grid from its largest |U - B xx|, |V - B yy|
+    const int64_t irow = i0 + tid;
+    const bool rvalid = tid < kHdRows && irow < n;
+    double Ud = 0.0, arow = 0.0;
+    double mx = 0.0;
+    for (int c = tid; c < kHdCols; c += 256) {
+        const int64_t j = j0 + c;
+        if (j < m) mx = fmax(mx, fabs(kLog2eHd * A.v[j] - Bd * (double)A.hd_yy[j]));
+    }
+    if (rvalid) {
+        arow = A.a[irow];
+        Ud = kLog2eHd * (A.u[irow] - arow) - Bd * (double)A.hd_xx[irow];
+        mx = fmax(mx, fabs(Ud));
+    }
+    mx = hd_wave_max(mx);
+    if (lane == 0) s_wmax[wave] = mx;
+    __syncthreads();
+    mx = fmax(fmax(s_wmax[0], s_wmax[1]), fmax(s_wmax[2], s_wmax[3]));
+    if (!(mx < 4.0e6)) mx = 4.0e6;           // non-finite input: results flagged later
+    int e2;
+    frexp(2.0 * mx + 2.0, &e2);
+    const int g = 23 - e2;                     // |Uh + Vh| < 2^(23 - g) on a 2^-g grid: exact
+    const double sc = ldexp(1.0, g), isc = ldexp(1.0, -g);
+
+    // ---- per-row values
+    if (tid < kHdRows) {
+        if (rvalid) {
+            const double uh = rint(Ud * sc) * isc;
+            const double rf = exp2(Ud - uh);
+            const double R = exp(arow) * rf;
+            s_rf[tid] = rf;
+            s_rv[0][tid] = (float)uh;
+            if constexpr (HVP) {
+                const double x = A.xw1[irow];
+                s_rv[1][tid] = (float)x;
+                s_rv[2][tid] = (float)R;
+                s_rv[3][tid] = (float)(R * srho * x);
+            } else {
+                if constexpr (NC >= 1) s_rv[1][tid] = (float)(R * (A.xw0 ? A.xw0[irow] : 1.0));
+                if constexpr (NC >= 2) s_rv[2][tid] = (float)(R * (A.xw1 ? A.xw1[irow] : 1.0));
+            }
+        } else {
+            s_rf[tid] = 0.0;
+            s_rv[0][tid] = -INFINITY;
+#pragma unroll
+            for (int k = 1; k < NV; ++k) s_rv[k][tid] = 0.0f;
+        }
+    }
+    // MFMA operand A: this wave's 32 rows, every 16-dimension chunk
+    bf16x8 ah[KC], al[KC];
+    {
+        const int64_t ai = i0 + wave * 32 + rl;
+        const __bf16* xh = static_cast<const __bf16*>(A.hd_xh);
+        const __bf16* xl = static_cast<const __bf16*>(A.hd_xl);
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+            if (ai < n) {
+                const int64_t off = ai * d + kc * 16 + 8 * half;
+                ah[kc] = *reinterpret_cast<const bf16x8*>(xh + off);
+                al[kc] = *reinterpret_cast<const bf16x8*>(xl + off);
+            } else {
+#pragma unroll
+                for (int t = 0; t < 8; ++t) ah[kc][t] = al[kc][t] = (__bf16)0.0f;
+            }
+        }
+    }
+    __syncthreads();
+    // the lane's 16 result rows: 4 groups of 4 consecutive rows
+    float rv[NV][16];
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 t4 = *reinterpret_cast<const float4*>(&s_rv[k][wave * 32 + 8 * q + 4 * half]);
+            rv[k][4 * q + 0] = t4.x;
+            rv[k][4 * q + 1] = t4.y;
+            rv[k][4 * q + 2] = t4.z;
+            rv[k][4 * q + 3] = t4.w;
+        }
+
+    const float B2h = (float)(2.0 * Bd);
+    const float B2l = (float)(2.0 * Bd - (double)B2h);
+    float racc[NRA][16];
+#pragma unroll
+    for (int k = 0; k < NRA; ++k)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) racc[k][r] = 0.0f;
+
+    const __bf16* yh = static_cast<const __bf16*>(A.hd_yh);
+    const __bf16* yl = static_cast<const __bf16*>(A.hd_yl);
+    auto flush_cols = [&](int64_t jb) {        // column totals of a finished block
+        if constexpr (NC > 0) {
+            if (tid < kHdBlk) {
+                const int64_t j = jb + tid;
+                if (j < m) {
+                    const double V = kLog2eHd * A.v[j] - Bd * (double)A.hd_yy[j];
+                    const double f = exp2(V - rint(V * sc) * isc);
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) {
+                        const double t = ((double)s_cp[k][0][tid] + (double)s_cp[k][1][tid]) +
+                                         ((double)s_cp[k][2][tid] + (double)s_cp[k][3][tid]);
+                        if (A.atomic)
+                            atomicAdd(&A.col_part[(int64_t)k * m + j], t * f);
+                        else
+                            A.col_part[((int64_t)k * A.tiles_n + blockIdx.y) * m + j] = t * f;
+                    }
+                }
+            }
+        }
+    };
+
+    const int nblk = kHdCols / kHdBlk;
+    int64_t jprev = -1;
+    for (int blk = 0; blk < nblk; ++blk) {
+        const int64_t jb = j0 + (int64_t)blk * kHdBlk;
+        if (jb >= m) break;                                  // uniform
+        if (blk > 0) {
+            __syncthreads();                                 // the previous block is consumed
+            flush_cols(jprev);
+        }
+        // stage the block's columns: BF16 hi / lo, 16-byte chunks, odd column stride
+        for (int e = tid; e < kHdBlk * nch; e += 256) {
+            const int c = e / nch, k = e % nch;
+            int64_t j = jb + c;
+            j = j < m ? j : m - 1;                           // finite filler past m
+            const int64_t o = j * d + k * 8;
+            *reinterpret_cast<bf16x8*>(&s_bh[(c * cs + k) * 8]) = *reinterpret_cast<const bf16x8*>(yh + o);
+            *reinterpret_cast<bf16x8*>(&s_bl[(c * cs + k) * 8]) = *reinterpret_cast<const bf16x8*>(yl + o);
+        }
+        if (tid < kHdBlk) {
+            const int64_t j = jb + tid;
+            float4 rec = make_float4(-INFINITY, 1.0f, 0.0f, 0.0f);
+            if (j < m) {
+                const double V = kLog2eHd * A.v[j] - Bd * (double)A.hd_yy[j];
+                const double vh = rint(V * sc) * isc;
+                const double f = exp2(V - vh);
+                rec.x = (float)vh;
+                rec.y = (float)f;
+                if constexpr (HVP) {
+                    const double y = A.yw1[j];
+                    rec.z = (float)(srho * y * f);
+                    rec.w = (float)y;
+                } else {
+                    if constexpr (NR >= 1) rec.z = (float)((A.yw0 ? A.yw0[j] : 1.0) * f);
+                    if constexpr (NR >= 2)
+                        rec.w = (float)((A.yw1 ? A.yw1[j] : 1.0) * (MODE2 == R2_SQUARE ? f * f : f));
+                }
+            }
+            s_rec[tid] = rec;
+        }
+        __syncthreads();
+        jprev = jb;
+
+#pragma unroll 1
+        for (int st = 0; st < kHdBlk / kHdStep; ++st) {
+            const int c = st * kHdStep + rl;                 // this lane's column in the block
+            const float4 rec = s_rec[c];
+            f32x16 acc = {};
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) {
+                const int o = (c * cs + 2 * kc + half) * 8;
+                const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&s_bh[o]);
+                const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&s_bl[o]);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kc], bh, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kc], bl, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[kc], bh, acc, 0, 0, 0);
+            }
+            float cacc[NCA];
+#pragma unroll
+            for (int k = 0; k < NCA; ++k) cacc[k] = 0.0f;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const float t = fmaf(B2h, acc[r], rv[0][r] + rec.x);
+                const float e = __builtin_amdgcn_exp2f(fmaf(B2l, acc[r], t));
+                if constexpr (HVP) {
+                    // rows: e f_j (x_i + sqrt(rho) y_j); columns: R_i e (y_j + sqrt(rho) x_i)
+                    racc[0][r] = fmaf(e, fmaf(rv[1][r], rec.y, rec.z), racc[0][r]);
+                    cacc[0] = fmaf(e, fmaf(rv[2][r], rec.w, rv[3][r]), cacc[0]);
+                } else {
+                    if constexpr (NR >= 1) racc[0][r] = fmaf(e, rec.z, racc[0][r]);
+                    if constexpr (NR >= 2)
+                        racc[1][r] = fmaf(MODE2 == R2_SQUARE ? e * e : e, rec.w, racc[1][r]);
+                    if constexpr (NC >= 1) cacc[0] = fmaf(e, rv[1][r], cacc[0]);
+                    if constexpr (NC >= 2) cacc[1] = fmaf(e, rv[2][r], cacc[1]);
+                }
+            }
+            if constexpr (NC > 0) {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) {
+                    const float tot = pair_total32(cacc[k]);
+                    if (half == 0) s_cp[k][wave][c] = tot;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    flush_cols(jprev);
+
+    // ---- row totals: each half's 32 lanes hold the same 16 rows
+    if constexpr (NR > 0) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            double v[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) v[r] = (double)racc[k][r];
+            const double tot = half_transpose_sum16(v, lane);
+            if ((lane & 1) == 0) {
+                const int r = (lane & 31) >> 1;
+                const int row = wave * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+                const int64_t i = i0 + row;
+                if (i < n) {
+                    double fac = s_rf[row];
+                    if (k == 1 && MODE2 == R2_SQUARE) fac *= fac;
+                    if (A.atomic)
+                        atomicAdd(&A.row_part[(int64_t)k * n + i], tot * fac);
+                    else
+                        A.row_part[((int64_t)k * A.tiles_m + blockIdx.x) * n + i] = tot * fac;
+                }
+            }
+        }
+    }
+}
+
 template <int NR, int NC, int MODE2>
 hipError_t launch_hd(const PassArgs& a, int prec, hipStream_t s)
 {
     dim3 grid((unsigned)a.tiles_m, (unsigned)a.tiles_n);
+    if constexpr (MODE2 != R2_COST) {
+        if (prec == EOT_PREC_MIXED) {
+            switch (a.d) {
+            case 16: hipLaunchKernelGGL((k_pass_hd_mx<NR, NC, MODE2, 1>), grid, dim3(256), 0, s, a); break;
+            case 32: hipLaunchKernelGGL((k_pass_hd_mx<NR, NC, MODE2, 2>), grid, dim3(256), 0, s, a); break;
+            case 48: hipLaunchKernelGGL((k_pass_hd_mx<NR, NC, MODE2, 3>), grid, dim3(256), 0, s, a); break;
+            default: hipLaunchKernelGGL((k_pass_hd_mx<NR, NC, MODE2, 4>), grid, dim3(256), 0, s, a); break;
+            }
+            return hipGetLastError();
+        }
+    }
     if (prec == EOT_PREC_MIXED)
         hipLaunchKernelGGL((k_pass_hd<EOT_PREC_MIXED, NR, NC, MODE2, 0>), grid, dim3(256), 0, s, a,
                            nullptr);

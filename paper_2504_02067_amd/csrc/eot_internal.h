@@ -31,6 +31,12 @@ constexpr int kSubRowsFused = EOT_SUB_ROWS_FUSED;
 #else
 #define EOT_FUSED_OCCUPANCY
 #endif
+// Optional occupancy target of the mixed high-dimensional pass (waves per SIMD).
+#if defined(EOT_HD_WAVES_PER_EU) && EOT_HD_WAVES_PER_EU > 0
+#define EOT_HD_OCCUPANCY __attribute__((amdgpu_waves_per_eu(EOT_HD_WAVES_PER_EU)))
+#else
+#define EOT_HD_OCCUPANCY
+#endif
 constexpr int kWaves = kPassThreads / 64;
 // Row partials are written per wave: [nr][tiles_m * kWaves][n].
 inline int row_tiles(int tiles_m) { return tiles_m * kWaves; }
