@@ -394,22 +394,26 @@ __global__ __launch_bounds__(256) void k_pass_hd(PassArgs A, float* out32)
 }
 
 
-// ---- mixed precision, column blocks staged once per 4 steps -------------------
+// ---- mixed precision, column blocks copied asynchronously ----------------------
 // The norms are folded into the potentials before the hi / lo split:
 //     log2 P_ij - a_i log2 e = (U_i - B |x_i|^2) + (V_j - B |y_j|^2) + 2 B x_i . y_j
 // with B = log2(e) beta / s, so a plan entry costs
 //     e = exp2(fma(2 Bl, xy, fma(2 Bh, xy, Uh_i + Vh_j)))
 // (Uh + Vh exact on the tile's grid, xy the MFMA result), and the lo parts
-// become the FP64 factors 2^Ul_i (row totals) and 2^Vl_j (column weights and
+// become the factors 2^Ul_i (row totals) and 2^Vl_j (column weights and
 // column totals). Each lane keeps the per-row values of its 16 result rows in
-// registers for the whole tile; the 4 waves share a block of 128 staged
-// columns (BF16 hi / lo and a 16-byte record per column), so the step loop
-// has no barrier and reads LDS only for the MFMA operands and the record.
-// Within a lane, the 16 entries of a step (column sums) and the tile's 16
-// steps (row sums) accumulate in FP32; every sum across lanes, waves and tiles
-// is FP64.
-constexpr int kHdBlk = 128;                  // staged columns: 4 steps of 32
-constexpr int kHdCs = kHdMaxD / 8 + 1;       // 16-byte chunks per staged column (odd: no conflicts)
+// registers for the whole tile. The tile's 512 columns go through LDS in 4
+// blocks of 128, double-buffered: the next block is copied global -> LDS by
+// the DMA path (global_load_lds, no registers) while the current one is
+// computed, one barrier per block. A block is stored as 1 KB fragments, one
+// per (step, 16-dimension chunk, hi / lo), each holding what the 64 lanes read
+// for that MFMA operand in lane order. Within a lane, the 16 entries of a step
+// (column sums) and the tile's 16 steps (row sums) accumulate in FP32; every
+// sum across lanes, waves and tiles is FP64.
+constexpr int kHdBlk = 128;                   // columns per block: 4 steps of 32
+constexpr int kHdBlkSteps = kHdBlk / kHdStep;
+typedef __attribute__((address_space(3))) void hd_lds_void;
+typedef __attribute__((address_space(1))) const void hd_gbl_void;
 
 template <int NR, int NC, int MODE2, int KC>
 __global__ __launch_bounds__(256) EOT_HD_OCCUPANCY void k_pass_hd_mx(PassArgs A)
@@ -417,12 +421,13 @@ __global__ __launch_bounds__(256) EOT_HD_OCCUPANCY void k_pass_hd_mx(PassArgs A)
     static_assert(KC >= 1 && KC * 16 <= kHdMaxD, "KC = d / 16");
     if (A.skip && *A.skip) return;
     constexpr bool HVP = MODE2 == R2_HVP;
-    constexpr int NV = HVP ? 4 : 1 + NC;      // per-row register values
+    constexpr int NV = HVP ? 4 : 1 + NC;       // per-row register values
     constexpr int NRA = NR > 0 ? NR : 1, NCA = NC > 0 ? NC : 1;
-    __shared__ __attribute__((aligned(16))) __bf16 s_bh[kHdBlk * kHdCs * 8];
-    __shared__ __attribute__((aligned(16))) __bf16 s_bl[kHdBlk * kHdCs * 8];
-    __shared__ __attribute__((aligned(16))) float4 s_rec[kHdBlk];
-    __shared__ float s_cp[NCA][kWaves][kHdBlk];
+    constexpr int d = KC * 16;
+    // [buffer][hi, lo][step][chunk][lane]: 16 bytes each
+    __shared__ __attribute__((aligned(16))) bf16x8 s_b[2][2][kHdBlkSteps][KC][64];
+    __shared__ __attribute__((aligned(16))) float4 s_rec[kHdCols];
+    __shared__ float s_cp[2][NCA][kWaves][kHdBlk];
     __shared__ __attribute__((aligned(16))) float s_rv[NV][kHdRows];
     __shared__ double s_rf[kHdRows];
     __shared__ double s_wmax[kWaves];
@@ -430,37 +435,56 @@ __global__ __launch_bounds__(256) EOT_HD_OCCUPANCY void k_pass_hd_mx(PassArgs A)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int rl = lane & 31, half = lane >> 5;
     const int64_t n = A.n, m = A.m;
-    constexpr int d = KC * 16, nch = d / 8, cs = nch + 1;
     const int64_t i0 = (int64_t)blockIdx.y * kHdRows;
     const int64_t j0 = (int64_t)blockIdx.x * kHdCols;
     const double Bd = kLog2eHd * A.beta;
     const double srho = A.hvp_srho;
+    const __bf16* yh = static_cast<const __bf16*>(A.hd_yh);
+    const __bf16* yl = static_cast<const __bf16*>(A.hd_yl);
+
+    // async copy of block blk into buffer p: each wave copies every 4th fragment
+    auto copy_block = [&](int blk, int p) {
+        const int64_t jb = j0 + (int64_t)blk * kHdBlk;
+#pragma unroll
+        for (int f = wave; f < 2 * kHdBlkSteps * KC; f += kWaves) {
+            const int hl = f / (kHdBlkSteps * KC), st = (f / KC) % kHdBlkSteps, kc = f % KC;
+            int64_t j = jb + st * kHdStep + rl;
+            j = j < m ? j : m - 1;                             // finite filler past m
+            const __bf16* src = (hl ? yl : yh) + j * d + kc * 16 + 8 * half;
+            __builtin_amdgcn_global_load_lds((hd_gbl_void*)src, (hd_lds_void*)&s_b[p][hl][st][kc][0],
+                                             16, 0, 0);
+        }
+    };
 
     // ---- the tile's exponent grid from its largest |U - B xx|, |V - B yy|
     const int64_t irow = i0 + tid;
     const bool rvalid = tid < kHdRows && irow < n;
     double Ud = 0.0, arow = 0.0;
+    double Vc[kHdCols / 256];
     double mx = 0.0;
-    for (int c = tid; c < kHdCols; c += 256) {
-        const int64_t j = j0 + c;
-        if (j < m) mx = fmax(mx, fabs(kLog2eHd * A.v[j] - Bd * (double)A.hd_yy[j]));
+#pragma unroll
+    for (int q = 0; q < kHdCols / 256; ++q) {
+        const int64_t j = j0 + tid + 256 * q;
+        Vc[q] = j < m ? kLog2eHd * A.v[j] - Bd * (double)A.hd_yy[j] : 0.0;
+        mx = fmax(mx, fabs(Vc[q]));
     }
     if (rvalid) {
         arow = A.a[irow];
         Ud = kLog2eHd * (A.u[irow] - arow) - Bd * (double)A.hd_xx[irow];
         mx = fmax(mx, fabs(Ud));
     }
+    copy_block(0, 0);
     mx = hd_wave_max(mx);
     if (lane == 0) s_wmax[wave] = mx;
     __syncthreads();
     mx = fmax(fmax(s_wmax[0], s_wmax[1]), fmax(s_wmax[2], s_wmax[3]));
-    if (!(mx < 4.0e6)) mx = 4.0e6;           // non-finite input: results flagged later
+    if (!(mx < 4.0e6)) mx = 4.0e6;            // non-finite input: results flagged later
     int e2;
     frexp(2.0 * mx + 2.0, &e2);
-    const int g = 23 - e2;                     // |Uh + Vh| < 2^(23 - g) on a 2^-g grid: exact
+    const int g = 23 - e2;                      // |Uh + Vh| < 2^(23 - g) on a 2^-g grid: exact
     const double sc = ldexp(1.0, g), isc = ldexp(1.0, -g);
 
-    // ---- per-row values
+    // ---- per-row values and the column records of the whole tile
     if (tid < kHdRows) {
         if (rvalid) {
             const double uh = rint(Ud * sc) * isc;
@@ -484,6 +508,28 @@ __global__ __launch_bounds__(256) EOT_HD_OCCUPANCY void k_pass_hd_mx(PassArgs A)
             for (int k = 1; k < NV; ++k) s_rv[k][tid] = 0.0f;
         }
     }
+#pragma unroll
+    for (int q = 0; q < kHdCols / 256; ++q) {
+        const int c = tid + 256 * q;
+        const int64_t j = j0 + c;
+        float4 rec = make_float4(-INFINITY, 1.0f, 0.0f, 0.0f);
+        if (j < m) {
+            const double vh = rint(Vc[q] * sc) * isc;
+            const double f = exp2(Vc[q] - vh);
+            rec.x = (float)vh;
+            rec.y = (float)f;
+            if constexpr (HVP) {
+                const double y = A.yw1[j];
+                rec.z = (float)(srho * y * f);
+                rec.w = (float)y;
+            } else {
+                if constexpr (NR >= 1) rec.z = (float)((A.yw0 ? A.yw0[j] : 1.0) * f);
+                if constexpr (NR >= 2)
+                    rec.w = (float)((A.yw1 ? A.yw1[j] : 1.0) * (MODE2 == R2_SQUARE ? f * f : f));
+            }
+        }
+        s_rec[c] = rec;
+    }
     // MFMA operand A: this wave's 32 rows, every 16-dimension chunk
     bf16x8 ah[KC], al[KC];
     {
@@ -502,6 +548,7 @@ __global__ __launch_bounds__(256) EOT_HD_OCCUPANCY void k_pass_hd_mx(PassArgs A)
             }
         }
     }
+    __builtin_amdgcn_s_waitcnt(0);             // block 0 has landed in LDS
     __syncthreads();
     // the lane's 16 result rows: 4 groups of 4 consecutive rows
     float rv[NV][16];
@@ -524,81 +571,20 @@ __global__ __launch_bounds__(256) EOT_HD_OCCUPANCY void k_pass_hd_mx(PassArgs A)
 #pragma unroll
         for (int r = 0; r < 16; ++r) racc[k][r] = 0.0f;
 
-    const __bf16* yh = static_cast<const __bf16*>(A.hd_yh);
-    const __bf16* yl = static_cast<const __bf16*>(A.hd_yl);
-    auto flush_cols = [&](int64_t jb) {        // column totals of a finished block
-        if constexpr (NC > 0) {
-            if (tid < kHdBlk) {
-                const int64_t j = jb + tid;
-                if (j < m) {
-                    const double V = kLog2eHd * A.v[j] - Bd * (double)A.hd_yy[j];
-                    const double f = exp2(V - rint(V * sc) * isc);
-#pragma unroll
-                    for (int k = 0; k < NC; ++k) {
-                        const double t = ((double)s_cp[k][0][tid] + (double)s_cp[k][1][tid]) +
-                                         ((double)s_cp[k][2][tid] + (double)s_cp[k][3][tid]);
-                        if (A.atomic)
-                            atomicAdd(&A.col_part[(int64_t)k * m + j], t * f);
-                        else
-                            A.col_part[((int64_t)k * A.tiles_n + blockIdx.y) * m + j] = t * f;
-                    }
-                }
-            }
-        }
-    };
-
-    const int nblk = kHdCols / kHdBlk;
-    int64_t jprev = -1;
+    const int nblk = (int)((m - j0 + kHdBlk - 1) / kHdBlk < kHdCols / kHdBlk
+                               ? (m - j0 + kHdBlk - 1) / kHdBlk : kHdCols / kHdBlk);
     for (int blk = 0; blk < nblk; ++blk) {
-        const int64_t jb = j0 + (int64_t)blk * kHdBlk;
-        if (jb >= m) break;                                  // uniform
-        if (blk > 0) {
-            __syncthreads();                                 // the previous block is consumed
-            flush_cols(jprev);
-        }
-        // stage the block's columns: BF16 hi / lo, 16-byte chunks, odd column stride
-        for (int e = tid; e < kHdBlk * nch; e += 256) {
-            const int c = e / nch, k = e % nch;
-            int64_t j = jb + c;
-            j = j < m ? j : m - 1;                           // finite filler past m
-            const int64_t o = j * d + k * 8;
-            *reinterpret_cast<bf16x8*>(&s_bh[(c * cs + k) * 8]) = *reinterpret_cast<const bf16x8*>(yh + o);
-            *reinterpret_cast<bf16x8*>(&s_bl[(c * cs + k) * 8]) = *reinterpret_cast<const bf16x8*>(yl + o);
-        }
-        if (tid < kHdBlk) {
-            const int64_t j = jb + tid;
-            float4 rec = make_float4(-INFINITY, 1.0f, 0.0f, 0.0f);
-            if (j < m) {
-                const double V = kLog2eHd * A.v[j] - Bd * (double)A.hd_yy[j];
-                const double vh = rint(V * sc) * isc;
-                const double f = exp2(V - vh);
-                rec.x = (float)vh;
-                rec.y = (float)f;
-                if constexpr (HVP) {
-                    const double y = A.yw1[j];
-                    rec.z = (float)(srho * y * f);
-                    rec.w = (float)y;
-                } else {
-                    if constexpr (NR >= 1) rec.z = (float)((A.yw0 ? A.yw0[j] : 1.0) * f);
-                    if constexpr (NR >= 2)
-                        rec.w = (float)((A.yw1 ? A.yw1[j] : 1.0) * (MODE2 == R2_SQUARE ? f * f : f));
-                }
-            }
-            s_rec[tid] = rec;
-        }
-        __syncthreads();
-        jprev = jb;
-
+        const int p = blk & 1;
+        if (blk + 1 < nblk) copy_block(blk + 1, p ^ 1);
 #pragma unroll 1
-        for (int st = 0; st < kHdBlk / kHdStep; ++st) {
+        for (int st = 0; st < kHdBlkSteps; ++st) {
             const int c = st * kHdStep + rl;                 // this lane's column in the block
-            const float4 rec = s_rec[c];
+            const float4 rec = s_rec[blk * kHdBlk + c];
             f32x16 acc = {};
 #pragma unroll
             for (int kc = 0; kc < KC; ++kc) {
-                const int o = (c * cs + 2 * kc + half) * 8;
-                const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&s_bh[o]);
-                const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&s_bl[o]);
+                const bf16x8 bh = s_b[p][0][st][kc][lane];
+                const bf16x8 bl = s_b[p][1][st][kc][lane];
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kc], bh, acc, 0, 0, 0);
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kc], bl, acc, 0, 0, 0);
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[kc], bh, acc, 0, 0, 0);
@@ -626,13 +612,32 @@ __global__ __launch_bounds__(256) EOT_HD_OCCUPANCY void k_pass_hd_mx(PassArgs A)
 #pragma unroll
                 for (int k = 0; k < NC; ++k) {
                     const float tot = pair_total32(cacc[k]);
-                    if (half == 0) s_cp[k][wave][c] = tot;
+                    if (half == 0) s_cp[p][k][wave][c] = tot;
+                }
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);         // the next block has landed in LDS
+        __syncthreads();
+        // column totals of this block (the partials of the next block go to the other buffer)
+        if constexpr (NC > 0) {
+            if (tid < kHdBlk) {
+                const int c = blk * kHdBlk + tid;
+                const int64_t j = j0 + c;
+                if (j < m) {
+                    const double f = (double)s_rec[c].y;
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) {
+                        const double t = ((double)s_cp[p][k][0][tid] + (double)s_cp[p][k][1][tid]) +
+                                         ((double)s_cp[p][k][2][tid] + (double)s_cp[p][k][3][tid]);
+                        if (A.atomic)
+                            atomicAdd(&A.col_part[(int64_t)k * m + j], t * f);
+                        else
+                            A.col_part[((int64_t)k * A.tiles_n + blockIdx.y) * m + j] = t * f;
+                    }
                 }
             }
         }
     }
-    __syncthreads();
-    flush_cols(jprev);
 
     // ---- row totals: each half's 32 lanes hold the same 16 rows
     if constexpr (NR > 0) {
