@@ -91,6 +91,12 @@ struct GradVecs {
 struct HdVecs {
     void *xh = nullptr, *xl = nullptr, *yh = nullptr, *yl = nullptr;   // BF16, n x d / m x d
     float *xx = nullptr, *yy = nullptr;
+    int cols = kHdTileCols;                       // columns per tile
+    int64_t npad = 0, mpad = 0;                   // rows / columns padded to whole tiles
+    float* rt = nullptr;                          // [4][npad] per-row values (mixed pass)
+    double* rf = nullptr;                         // [npad] per-row factors
+    float* ct = nullptr;                          // [mpad][4] column records
+    double* gpart = nullptr;                      // [kHdMaxPart] grid maxima
 };
 
 struct Ctx {
@@ -124,6 +130,10 @@ void carve(Arena& ar, Ctx& x, int op)
         x.hd.yl = ar.take<uint16_t>((size_t)m * d);
         x.hd.xx = ar.take<float>(n);
         x.hd.yy = ar.take<float>(m);
+        x.hd.rt = ar.take<float>((size_t)4 * x.hd.npad);
+        x.hd.rf = ar.take<double>((size_t)x.hd.npad);
+        x.hd.ct = ar.take<float>((size_t)4 * x.hd.mpad);
+        x.hd.gpart = ar.take<double>(kHdMaxPart);
     }
     x.sc.row_part = ar.take<double>((size_t)2 * x.rtiles * n);
     x.sc.col_part = ar.take<double>((size_t)2 * x.ctiles * m);
@@ -209,9 +219,15 @@ void layout(Ctx& x)
     const bool high_d = x.cost.kind == EOT_COST_SQEUCLID_POINTS && x.cost.d > 3;
     int row_parts;
     if (high_d) {                      // matrix-core tiles: one row partial per tile
-        x.tiles_m = (int)((x.m + kHdTileCols - 1) / kHdTileCols);
         x.rb = kHdTileRows;
         x.tiles_n = (int)tiles_n_of(x.n, x.rb);
+        // the widest tiles (fewest per-tile set-ups) that still launch >= 2048 workgroups
+        int cols = kHdTileColsMax;
+        while (cols > kHdTileCols && ((x.m + cols - 1) / cols) * (int64_t)x.tiles_n < 2048) cols /= 2;
+        x.hd.cols = cols;
+        x.tiles_m = (int)((x.m + cols - 1) / cols);
+        x.hd.npad = (int64_t)x.tiles_n * kHdTileRows;
+        x.hd.mpad = (int64_t)x.tiles_m * cols;
         row_parts = x.tiles_m;
     } else {
         x.tiles_m = (int)tiles_m_of(x.m);
@@ -283,6 +299,12 @@ PassArgs make_args(const Ctx& x, const double* u, const double* a, const double*
     A.hd_yl = x.hd.yl;
     A.hd_xx = x.hd.xx;
     A.hd_yy = x.hd.yy;
+    A.hd_cols = x.hd.cols;
+    A.hd_npad = x.hd.npad;
+    A.hd_rt = x.hd.rt;
+    A.hd_rf = x.hd.rf;
+    A.hd_ct = x.hd.ct;
+    A.hd_gpart = x.hd.gpart;
     return A;
 }
 

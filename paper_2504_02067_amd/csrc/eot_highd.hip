@@ -30,7 +30,6 @@ namespace eot {
 namespace {
 
 constexpr int kHdRows = kHdTileRows;        // 128: 4 waves x 32 rows
-constexpr int kHdCols = kHdTileCols;        // 512: 16 steps of 32 columns
 constexpr int kHdStep = 32;
 constexpr int kHdMaxD = 64;
 constexpr double kLog2eHd = 1.4426950408889634074;
@@ -74,7 +73,7 @@ __global__ __launch_bounds__(256) void k_pass_hd(PassArgs A, float* out32)
     const int d = A.d;
     const int kch = d / 16;
     const int64_t i0 = (int64_t)blockIdx.y * kHdRows;
-    const int64_t j0 = (int64_t)blockIdx.x * kHdCols;
+    const int64_t j0 = (int64_t)blockIdx.x * A.hd_cols;
 
     // ---- prologue: row values (LDS), the tile's exponent grid (mixed)
     const int64_t irow = i0 + tid;
@@ -89,7 +88,7 @@ __global__ __launch_bounds__(256) void k_pass_hd(PassArgs A, float* out32)
     }
     if constexpr (MIXED && !MAXOP) {
         double mx = 0.0;
-        for (int c = tid; c < kHdCols; c += 256) {
+        for (int c = tid; c < A.hd_cols; c += 256) {
             const int64_t j = j0 + c;
             if (j < m) mx = fmax(mx, fabs(kLog2eHd * A.v[j]));
         }
@@ -183,7 +182,7 @@ __global__ __launch_bounds__(256) void k_pass_hd(PassArgs A, float* out32)
     const int sc_c = tid / (per > 0 ? per : 1), sc_q = tid % (per > 0 ? per : 1);
     const bool stager = tid < kHdStep * per;
 
-    const int nsteps = kHdCols / kHdStep;
+    const int nsteps = A.hd_cols / kHdStep;
     for (int st = 0; st < nsteps; ++st) {
         const int64_t jc = j0 + (int64_t)st * kHdStep;
         if (jc >= m) break;                                  // uniform
@@ -394,27 +393,118 @@ __global__ __launch_bounds__(256) void k_pass_hd(PassArgs A, float* out32)
 }
 
 
-// ---- mixed precision, column blocks copied asynchronously ----------------------
+// ---- mixed precision: per-pass tables, then the matrix-core pass ---------------
 // The norms are folded into the potentials before the hi / lo split:
 //     log2 P_ij - a_i log2 e = (U_i - B |x_i|^2) + (V_j - B |y_j|^2) + 2 B x_i . y_j
-// with B = log2(e) beta / s, so a plan entry costs
-//     e = exp2(fma(2 Bl, xy, fma(2 Bh, xy, Uh_i + Vh_j)))
-// (Uh + Vh exact on the tile's grid, xy the MFMA result), and the lo parts
-// become the factors 2^Ul_i (row totals) and 2^Vl_j (column weights and
-// column totals). Each lane keeps the per-row values of its 16 result rows in
-// registers for the whole tile. The tile's 512 columns go through LDS in 4
-// blocks of 128, double-buffered: the next block is copied global -> LDS by
-// the DMA path (global_load_lds, no registers) while the current one is
-// computed, one barrier per block. A block is stored as 1 KB fragments, one
-// per (step, 16-dimension chunk, hi / lo), each holding what the 64 lanes read
-// for that MFMA operand in lane order. Within a lane, the 16 entries of a step
-// (column sums) and the tile's 16 steps (row sums) accumulate in FP32; every
-// sum across lanes, waves and tiles is FP64.
+// with B = log2(e) beta / s. Two small kernels per pass split every
+// U_i - B |x_i|^2 and V_j - B |y_j|^2 into a hi part on one grid 2^-g (from
+// the largest magnitude, so that Uh + Vh is exact in FP32) and a lo part,
+// and store per row the hi part, the FP32 weights and the FP64 factor 2^Ul,
+// per column a 16-byte record {Vh, 2^Vl, row weight(s)}. A plan entry then
+// costs e = exp2(fma(2B, xy, Uh_i + Vh_j)) with xy the MFMA result (the lo
+// part of 2B would move the exponent by at most 2^-24 2B |x . y|, far below
+// the BF16 hi / lo error of xy, and is dropped), and 2^Vl_j multiplies the
+// column weights and the column totals.
 constexpr int kHdBlk = 128;                   // columns per block: 4 steps of 32
 constexpr int kHdBlkSteps = kHdBlk / kHdStep;
 typedef __attribute__((address_space(3))) void hd_lds_void;
 typedef __attribute__((address_space(1))) const void hd_gbl_void;
 
+__global__ __launch_bounds__(256) void k_hd_grid_max(PassArgs A)
+{
+    const double Bd = kLog2eHd * A.beta;
+    double mx = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += stride)
+        mx = fmax(mx, fabs(kLog2eHd * (A.u[i] - A.a[i]) - Bd * (double)A.hd_xx[i]));
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < A.m; j += stride)
+        mx = fmax(mx, fabs(kLog2eHd * A.v[j] - Bd * (double)A.hd_yy[j]));
+    __shared__ double s_w[4];
+    mx = hd_wave_max(mx);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) A.hd_gpart[blockIdx.x] = fmax(fmax(s_w[0], s_w[1]), fmax(s_w[2], s_w[3]));
+}
+
+// hvp: rows {Uh, x, R, R sqrt(rho) x}, columns {Vh, f, sqrt(rho) y f, y};
+// otherwise rows {Uh, R xw0, R xw1}, columns {Vh, f, yw0 f, yw1 f (f^2 if sq)}.
+__global__ __launch_bounds__(256) void k_hd_tables(PassArgs A, int nparts, int hvp, int nr, int nc,
+                                                    int sq)
+{
+    __shared__ double s_w[4];
+    double mx = 0.0;
+    for (int t = threadIdx.x; t < nparts; t += blockDim.x) mx = fmax(mx, A.hd_gpart[t]);
+    mx = hd_wave_max(mx);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    mx = fmax(fmax(s_w[0], s_w[1]), fmax(s_w[2], s_w[3]));
+    if (!(mx < 4.0e6)) mx = 4.0e6;             // non-finite input: results flagged later
+    int e2;
+    frexp(2.0 * mx + 2.0, &e2);
+    const int g = 23 - e2;                       // |Uh + Vh| < 2^(23 - g) on a 2^-g grid: exact
+    const double sc = ldexp(1.0, g), isc = ldexp(1.0, -g);
+    const double Bd = kLog2eHd * A.beta;
+    const double srho = A.hvp_srho;
+    const int64_t np = A.hd_npad, mp = (int64_t)A.tiles_m * A.hd_cols;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    float* rt = A.hd_rt;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += stride) {
+        float r0 = -INFINITY, r1 = 0.0f, r2 = 0.0f, r3 = 0.0f;
+        double rf = 0.0;
+        if (i < A.n) {
+            const double a = A.a[i];
+            const double U = kLog2eHd * (A.u[i] - a) - Bd * (double)A.hd_xx[i];
+            const double uh = rint(U * sc) * isc;
+            rf = exp2(U - uh);
+            const double R = exp(a) * rf;
+            r0 = (float)uh;
+            if (hvp) {
+                const double x = A.xw1[i];
+                r1 = (float)x;
+                r2 = (float)R;
+                r3 = (float)(R * srho * x);
+            } else {
+                if (nc >= 1) r1 = (float)(R * (A.xw0 ? A.xw0[i] : 1.0));
+                if (nc >= 2) r2 = (float)(R * (A.xw1 ? A.xw1[i] : 1.0));
+            }
+        }
+        rt[i] = r0;
+        rt[np + i] = r1;
+        rt[2 * np + i] = r2;
+        rt[3 * np + i] = r3;
+        A.hd_rf[i] = rf;
+    }
+    float4* ct = static_cast<float4*>(A.hd_ct);
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < mp; j += stride) {
+        float4 rec = make_float4(-INFINITY, 1.0f, 0.0f, 0.0f);
+        if (j < A.m) {
+            const double V = kLog2eHd * A.v[j] - Bd * (double)A.hd_yy[j];
+            const double vh = rint(V * sc) * isc;
+            const double f = exp2(V - vh);
+            rec.x = (float)vh;
+            rec.y = (float)f;
+            if (hvp) {
+                const double y = A.yw1[j];
+                rec.z = (float)(srho * y * f);
+                rec.w = (float)y;
+            } else {
+                if (nr >= 1) rec.z = (float)((A.yw0 ? A.yw0[j] : 1.0) * f);
+                if (nr >= 2) rec.w = (float)((A.yw1 ? A.yw1[j] : 1.0) * (sq ? f * f : f));
+            }
+        }
+        ct[j] = rec;
+    }
+}
+
+// The pass. A workgroup owns 128 rows x hd_cols columns; each lane keeps the
+// table values of its 16 result rows in registers. The columns go through LDS
+// in blocks of 128, double-buffered: the next block (BF16 hi / lo operands and
+// the column records) is copied global -> LDS by the DMA path (no registers)
+// while the current one is computed, one barrier per block. A block is stored
+// as 1 KB fragments in the MFMA operand's lane order, so the copy writes
+// linearly and the reads are conflict-free. Within a lane, the 16 entries of a
+// step (column sums) and the tile's steps (row sums) accumulate in FP32; every
+// sum across lanes, waves and tiles is FP64.
 template <int NR, int NC, int MODE2, int KC>
 __global__ __launch_bounds__(256) EOT_HD_OCCUPANCY void k_pass_hd_mx(PassArgs A)
 {
@@ -426,21 +516,17 @@ __global__ __launch_bounds__(256) EOT_HD_OCCUPANCY void k_pass_hd_mx(PassArgs A)
     constexpr int d = KC * 16;
     // [buffer][hi, lo][step][chunk][lane]: 16 bytes each
     __shared__ __attribute__((aligned(16))) bf16x8 s_b[2][2][kHdBlkSteps][KC][64];
-    __shared__ __attribute__((aligned(16))) float4 s_rec[kHdCols];
+    __shared__ __attribute__((aligned(16))) float4 s_rec[2][kHdBlk];
     __shared__ float s_cp[2][NCA][kWaves][kHdBlk];
-    __shared__ __attribute__((aligned(16))) float s_rv[NV][kHdRows];
-    __shared__ double s_rf[kHdRows];
-    __shared__ double s_wmax[kWaves];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int rl = lane & 31, half = lane >> 5;
     const int64_t n = A.n, m = A.m;
     const int64_t i0 = (int64_t)blockIdx.y * kHdRows;
-    const int64_t j0 = (int64_t)blockIdx.x * kHdCols;
-    const double Bd = kLog2eHd * A.beta;
-    const double srho = A.hvp_srho;
+    const int64_t j0 = (int64_t)blockIdx.x * A.hd_cols;
     const __bf16* yh = static_cast<const __bf16*>(A.hd_yh);
     const __bf16* yl = static_cast<const __bf16*>(A.hd_yl);
+    const float4* ct = static_cast<const float4*>(A.hd_ct);
 
     // async copy of block blk into buffer p: each wave copies every 4th fragment
     auto copy_block = [&](int blk, int p) {
@@ -454,82 +540,25 @@ __global__ __launch_bounds__(256) EOT_HD_OCCUPANCY void k_pass_hd_mx(PassArgs A)
             __builtin_amdgcn_global_load_lds((hd_gbl_void*)src, (hd_lds_void*)&s_b[p][hl][st][kc][0],
                                              16, 0, 0);
         }
+        if (wave < kHdBlk / 64)                              // records (padded table)
+            __builtin_amdgcn_global_load_lds((hd_gbl_void*)(ct + jb + 64 * wave + lane),
+                                             (hd_lds_void*)&s_rec[p][64 * wave], 16, 0, 0);
     };
-
-    // ---- the tile's exponent grid from its largest |U - B xx|, |V - B yy|
-    const int64_t irow = i0 + tid;
-    const bool rvalid = tid < kHdRows && irow < n;
-    double Ud = 0.0, arow = 0.0;
-    double Vc[kHdCols / 256];
-    double mx = 0.0;
-#pragma unroll
-    for (int q = 0; q < kHdCols / 256; ++q) {
-        const int64_t j = j0 + tid + 256 * q;
-        Vc[q] = j < m ? kLog2eHd * A.v[j] - Bd * (double)A.hd_yy[j] : 0.0;
-        mx = fmax(mx, fabs(Vc[q]));
-    }
-    if (rvalid) {
-        arow = A.a[irow];
-        Ud = kLog2eHd * (A.u[irow] - arow) - Bd * (double)A.hd_xx[irow];
-        mx = fmax(mx, fabs(Ud));
-    }
     copy_block(0, 0);
-    mx = hd_wave_max(mx);
-    if (lane == 0) s_wmax[wave] = mx;
-    __syncthreads();
-    mx = fmax(fmax(s_wmax[0], s_wmax[1]), fmax(s_wmax[2], s_wmax[3]));
-    if (!(mx < 4.0e6)) mx = 4.0e6;            // non-finite input: results flagged later
-    int e2;
-    frexp(2.0 * mx + 2.0, &e2);
-    const int g = 23 - e2;                      // |Uh + Vh| < 2^(23 - g) on a 2^-g grid: exact
-    const double sc = ldexp(1.0, g), isc = ldexp(1.0, -g);
 
-    // ---- per-row values and the column records of the whole tile
-    if (tid < kHdRows) {
-        if (rvalid) {
-            const double uh = rint(Ud * sc) * isc;
-            const double rf = exp2(Ud - uh);
-            const double R = exp(arow) * rf;
-            s_rf[tid] = rf;
-            s_rv[0][tid] = (float)uh;
-            if constexpr (HVP) {
-                const double x = A.xw1[irow];
-                s_rv[1][tid] = (float)x;
-                s_rv[2][tid] = (float)R;
-                s_rv[3][tid] = (float)(R * srho * x);
-            } else {
-                if constexpr (NC >= 1) s_rv[1][tid] = (float)(R * (A.xw0 ? A.xw0[irow] : 1.0));
-                if constexpr (NC >= 2) s_rv[2][tid] = (float)(R * (A.xw1 ? A.xw1[irow] : 1.0));
-            }
-        } else {
-            s_rf[tid] = 0.0;
-            s_rv[0][tid] = -INFINITY;
+    // the lane's 16 result rows (4 groups of 4 consecutive rows) from the padded table
+    float rv[NV][16];
 #pragma unroll
-            for (int k = 1; k < NV; ++k) s_rv[k][tid] = 0.0f;
-        }
-    }
+    for (int k = 0; k < NV; ++k)
 #pragma unroll
-    for (int q = 0; q < kHdCols / 256; ++q) {
-        const int c = tid + 256 * q;
-        const int64_t j = j0 + c;
-        float4 rec = make_float4(-INFINITY, 1.0f, 0.0f, 0.0f);
-        if (j < m) {
-            const double vh = rint(Vc[q] * sc) * isc;
-            const double f = exp2(Vc[q] - vh);
-            rec.x = (float)vh;
-            rec.y = (float)f;
-            if constexpr (HVP) {
-                const double y = A.yw1[j];
-                rec.z = (float)(srho * y * f);
-                rec.w = (float)y;
-            } else {
-                if constexpr (NR >= 1) rec.z = (float)((A.yw0 ? A.yw0[j] : 1.0) * f);
-                if constexpr (NR >= 2)
-                    rec.w = (float)((A.yw1 ? A.yw1[j] : 1.0) * (MODE2 == R2_SQUARE ? f * f : f));
-            }
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = i0 + wave * 32 + 8 * q + 4 * half;
+            const float4 t4 = *reinterpret_cast<const float4*>(A.hd_rt + k * A.hd_npad + i);
+            rv[k][4 * q + 0] = t4.x;
+            rv[k][4 * q + 1] = t4.y;
+            rv[k][4 * q + 2] = t4.z;
+            rv[k][4 * q + 3] = t4.w;
         }
-        s_rec[c] = rec;
-    }
     // MFMA operand A: this wave's 32 rows, every 16-dimension chunk
     bf16x8 ah[KC], al[KC];
     {
@@ -548,38 +577,24 @@ __global__ __launch_bounds__(256) EOT_HD_OCCUPANCY void k_pass_hd_mx(PassArgs A)
             }
         }
     }
-    __builtin_amdgcn_s_waitcnt(0);             // block 0 has landed in LDS
-    __syncthreads();
-    // the lane's 16 result rows: 4 groups of 4 consecutive rows
-    float rv[NV][16];
-#pragma unroll
-    for (int k = 0; k < NV; ++k)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float4 t4 = *reinterpret_cast<const float4*>(&s_rv[k][wave * 32 + 8 * q + 4 * half]);
-            rv[k][4 * q + 0] = t4.x;
-            rv[k][4 * q + 1] = t4.y;
-            rv[k][4 * q + 2] = t4.z;
-            rv[k][4 * q + 3] = t4.w;
-        }
-
-    const float B2h = (float)(2.0 * Bd);
-    const float B2l = (float)(2.0 * Bd - (double)B2h);
+    const float B2 = (float)(2.0 * kLog2eHd * A.beta);
     float racc[NRA][16];
 #pragma unroll
     for (int k = 0; k < NRA; ++k)
 #pragma unroll
         for (int r = 0; r < 16; ++r) racc[k][r] = 0.0f;
+    __builtin_amdgcn_s_waitcnt(0);             // block 0 has landed in LDS
+    __syncthreads();
 
-    const int nblk = (int)((m - j0 + kHdBlk - 1) / kHdBlk < kHdCols / kHdBlk
-                               ? (m - j0 + kHdBlk - 1) / kHdBlk : kHdCols / kHdBlk);
+    const int64_t cols = m - j0 < A.hd_cols ? m - j0 : A.hd_cols;
+    const int nblk = (int)((cols + kHdBlk - 1) / kHdBlk);
     for (int blk = 0; blk < nblk; ++blk) {
         const int p = blk & 1;
         if (blk + 1 < nblk) copy_block(blk + 1, p ^ 1);
 #pragma unroll 1
         for (int st = 0; st < kHdBlkSteps; ++st) {
             const int c = st * kHdStep + rl;                 // this lane's column in the block
-            const float4 rec = s_rec[blk * kHdBlk + c];
+            const float4 rec = s_rec[p][c];
             f32x16 acc = {};
 #pragma unroll
             for (int kc = 0; kc < KC; ++kc) {
@@ -594,8 +609,7 @@ __global__ __launch_bounds__(256) EOT_HD_OCCUPANCY void k_pass_hd_mx(PassArgs A)
             for (int k = 0; k < NCA; ++k) cacc[k] = 0.0f;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const float t = fmaf(B2h, acc[r], rv[0][r] + rec.x);
-                const float e = __builtin_amdgcn_exp2f(fmaf(B2l, acc[r], t));
+                const float e = __builtin_amdgcn_exp2f(fmaf(B2, acc[r], rv[0][r] + rec.x));
                 if constexpr (HVP) {
                     // rows: e f_j (x_i + sqrt(rho) y_j); columns: R_i e (y_j + sqrt(rho) x_i)
                     racc[0][r] = fmaf(e, fmaf(rv[1][r], rec.y, rec.z), racc[0][r]);
@@ -621,10 +635,9 @@ __global__ __launch_bounds__(256) EOT_HD_OCCUPANCY void k_pass_hd_mx(PassArgs A)
         // column totals of this block (the partials of the next block go to the other buffer)
         if constexpr (NC > 0) {
             if (tid < kHdBlk) {
-                const int c = blk * kHdBlk + tid;
-                const int64_t j = j0 + c;
+                const int64_t j = j0 + (int64_t)blk * kHdBlk + tid;
                 if (j < m) {
-                    const double f = (double)s_rec[c].y;
+                    const double f = (double)s_rec[p][tid].y;
 #pragma unroll
                     for (int k = 0; k < NC; ++k) {
                         const double t = ((double)s_cp[p][k][0][tid] + (double)s_cp[p][k][1][tid]) +
@@ -649,10 +662,9 @@ __global__ __launch_bounds__(256) EOT_HD_OCCUPANCY void k_pass_hd_mx(PassArgs A)
             const double tot = half_transpose_sum16(v, lane);
             if ((lane & 1) == 0) {
                 const int r = (lane & 31) >> 1;
-                const int row = wave * 32 + 8 * (r / 4) + 4 * half + (r % 4);
-                const int64_t i = i0 + row;
+                const int64_t i = i0 + wave * 32 + 8 * (r / 4) + 4 * half + (r % 4);
                 if (i < n) {
-                    double fac = s_rf[row];
+                    double fac = A.hd_rf[i];
                     if (k == 1 && MODE2 == R2_SQUARE) fac *= fac;
                     if (A.atomic)
                         atomicAdd(&A.row_part[(int64_t)k * n + i], tot * fac);
@@ -670,6 +682,15 @@ hipError_t launch_hd(const PassArgs& a, int prec, hipStream_t s)
     dim3 grid((unsigned)a.tiles_m, (unsigned)a.tiles_n);
     if constexpr (MODE2 != R2_COST) {
         if (prec == EOT_PREC_MIXED) {
+            const int64_t work = a.n > a.m ? a.n : a.m;
+            int nb = (int)((work + 255) / 256);
+            nb = nb < 1 ? 1 : (nb > kHdMaxPart ? kHdMaxPart : nb);
+            hipLaunchKernelGGL(k_hd_grid_max, dim3(nb), dim3(256), 0, s, a);
+            const int64_t tw = a.hd_npad > (int64_t)a.tiles_m * a.hd_cols ? a.hd_npad
+                                                                          : (int64_t)a.tiles_m * a.hd_cols;
+            const unsigned tb = (unsigned)((tw + 255) / 256 < 4096 ? (tw + 255) / 256 : 4096);
+            hipLaunchKernelGGL(k_hd_tables, dim3(tb), dim3(256), 0, s, a, nb, MODE2 == R2_HVP ? 1 : 0,
+                               NR, NC, MODE2 == R2_SQUARE ? 1 : 0);
             switch (a.d) {
             case 16: hipLaunchKernelGGL((k_pass_hd_mx<NR, NC, MODE2, 1>), grid, dim3(256), 0, s, a); break;
             case 32: hipLaunchKernelGGL((k_pass_hd_mx<NR, NC, MODE2, 2>), grid, dim3(256), 0, s, a); break;

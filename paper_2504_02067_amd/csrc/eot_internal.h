@@ -80,12 +80,23 @@ struct PassArgs {
     const float* hd_yy;
     int32_t atomic;        // 1: row_part = [nr][n], col_part = [nc][m], pre-zeroed, atomically
                            //    accumulated (problems whose per-tile partials would not fit)
+    // high-dimensional point clouds: columns per tile, and the per-pass tables of
+    // the mixed pass (rows padded to whole tiles: [4][hd_npad] FP32 + [hd_npad]
+    // FP64; columns padded to whole tiles: 16-byte records) and its grid maxima
+    int32_t hd_cols;
+    int64_t hd_npad;
+    float* hd_rt;
+    double* hd_rf;
+    void* hd_ct;
+    double* hd_gpart;
 };
 
 // High-dimensional point clouds (d = 16 .. 64, x . y on the matrix cores):
-// 128-row x 512-column tiles, one row partial per tile.
+// 128-row tiles of 512 .. 2048 columns, one row partial per tile.
 constexpr int kHdTileRows = 128;
 constexpr int kHdTileCols = 512;
+constexpr int kHdTileColsMax = 2048;
+constexpr int kHdMaxPart = 1024;         // grid-maximum partials of the mixed pass
 
 inline int64_t tiles_m_of(int64_t m) { return (m + kTileCols - 1) / kTileCols; }
 inline int64_t tiles_n_of(int64_t n, int rb) { return (n + rb - 1) / rb; }
