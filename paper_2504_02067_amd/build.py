@@ -13,6 +13,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libeot.so")
 SOURCES = ["eot_kernels.hip", "eot_highd.hip", "eot_api.hip"]
+# Per-source options: the matrix-core pass keeps its MFMA accumulators in
+# ordinary VGPRs (no accumulator-register copies before the epilogue reads them).
+EXTRA = {"eot_highd.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 ARCH = os.environ.get("EOT_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled: they are generated from ordinary
@@ -28,7 +31,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     procs = []
     for src in SOURCES:
         obj = os.path.join(CSRC, src.replace(".hip", ".o"))
-        cmd = ["hipcc", *HIPFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = ["hipcc", *HIPFLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append(subprocess.Popen(cmd))
