@@ -46,7 +46,7 @@ def measured_traffic():
             k, v = line.strip().split(" = ", 1)
             kv[k] = v
     h = hashlib.sha256()
-    for f in ("eot_kernels.hip", "eot_internal.h"):
+    for f in ("eot_kernels.hip", "eot_internal.h", "eot_lanes.h"):
         h.update(open(os.path.join(ROOT, "paper_2504_02067_amd", "csrc", f), "rb").read())
     if kv.get("kernel_sources_sha256") != h.hexdigest():
         return None

@@ -407,8 +407,6 @@ __global__ __launch_bounds__(256) void k_pass_hd(PassArgs A, float* out32)
 // column weights and the column totals.
 constexpr int kHdBlk = 128;                   // columns per block: 4 steps of 32
 constexpr int kHdBlkSteps = kHdBlk / kHdStep;
-typedef __attribute__((address_space(3))) void hd_lds_void;
-typedef __attribute__((address_space(1))) const void hd_gbl_void;
 
 __global__ __launch_bounds__(256) void k_hd_grid_max(PassArgs A)
 {
@@ -537,12 +535,10 @@ __global__ __launch_bounds__(256) EOT_HD_OCCUPANCY void k_pass_hd_mx(PassArgs A)
             int64_t j = jb + st * kHdStep + rl;
             j = j < m ? j : m - 1;                             // finite filler past m
             const __bf16* src = (hl ? yl : yh) + j * d + kc * 16 + 8 * half;
-            __builtin_amdgcn_global_load_lds((hd_gbl_void*)src, (hd_lds_void*)&s_b[p][hl][st][kc][0],
-                                             16, 0, 0);
+            lds_dma16(src, lds_addr(&s_b[p][hl][st][kc][0]));
         }
         if (wave < kHdBlk / 64)                              // records (padded table)
-            __builtin_amdgcn_global_load_lds((hd_gbl_void*)(ct + jb + 64 * wave + lane),
-                                             (hd_lds_void*)&s_rec[p][64 * wave], 16, 0, 0);
+            lds_dma16(ct + jb + 64 * wave + lane, lds_addr(&s_rec[p][64 * wave]));
     };
     copy_block(0, 0);
 

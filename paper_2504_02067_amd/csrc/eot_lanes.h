@@ -1,7 +1,9 @@
-// Cross-lane sums of a wave64 in registers (gfx950): no LDS, no barrier.
+// Cross-lane sums of a wave64 in registers (gfx950): no LDS, no barrier; and
+// the global -> LDS copy used to stage tiles.
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <cstdint>
 
 namespace eot {
 
@@ -107,6 +109,27 @@ __device__ __forceinline__ float pair_total32(float x)
     const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false,
                                                     false);
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// LDS byte address of a __shared__ object.
+template <typename T>
+__device__ __forceinline__ uint32_t lds_addr(const T* p)
+{
+    return (uint32_t)(uintptr_t)((const __attribute__((address_space(3))) T*)p);
+}
+
+// Copies 16 bytes per lane from gptr (per lane) to LDS at lds_base + 16 * lane
+// (global_load_lds_dwordx4; lds_base is the same on every lane). Written as
+// inline assembly so that the compiler's wait-count pass does not make every
+// later LDS read wait for it: the caller waits for its own copies (s_waitcnt
+// vmcnt) before the barrier that publishes them. M0 written by a scalar op
+// needs one wait state before an LDS copy uses it.
+__device__ __forceinline__ void lds_dma16(const void* gptr, uint32_t lds_base)
+{
+    asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off"
+                 :
+                 : "s"(__builtin_amdgcn_readfirstlane(lds_base)), "v"(gptr)
+                 : "memory", "m0");
 }
 
 }  // namespace eot
