@@ -44,7 +44,7 @@ def cloud(n, m, d, seed):
     return p, pc, O.sqeuclid_points_cost(p.X, p.Y, p.scale)
 
 
-@pytest.mark.parametrize("d", [16, 64])
+@pytest.mark.parametrize("d", [16, 48, 64])
 @pytest.mark.parametrize("n,m", [(300, 700), (129, 513), (1, 40)])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_highd_marginals_parity(d, n, m, prec):
@@ -97,3 +97,40 @@ def test_highd_solve_parity(prec):
     rel = abs(st["cost"] - ost["cost"]) / ost["cost"]
     say(f"  cost rel diff {rel:.2e}")
     assert rel <= (1e-10 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_highd_wide_tiles_sampled(prec):
+    """n x m large enough that the pass takes 2048-column tiles (>= 2048 workgroups),
+    with a ragged last tile (2500 = 2048 + 452): marginals and the HVP checked on
+    sampled rows and columns, each computed by the oracle from its own slice of the
+    cost."""
+    n, m, d, gamma, rho = 128 * 2048, 2500, 64, 0.05, 0.7
+    beta = 1.0 / gamma
+    p = W.embedding_problem(n, m, d, 21)
+    pc = eot.PointCloud(torch.from_numpy(p.X).to(DEV), torch.from_numpy(p.Y).to(DEV), p.scale)
+    rng = np.random.default_rng(22)
+    u = np.log(p.r) + 0.5 * rng.standard_normal(n)
+    v = np.log(p.c) + 0.5 * rng.standard_normal(m)
+    x = rng.standard_normal(n); y = rng.standard_normal(m)
+    f, g = u * gamma, v * gamma
+    u, v = O.to_log_units(f, g, gamma)
+    say(f"high-d wide tiles n={n} m={m} d={d} {prec}")
+    out = eot.eot_marginals(pc, gamma, dvec(f), dvec(g), precision=prec)
+    Hx, Hy = eot.eot_hvp(pc, gamma, dvec(f), dvec(g), rho, dvec(x), dvec(y), precision=prec)
+    torch.cuda.synchronize()
+    rows = np.sort(rng.choice(n, 40, replace=False))
+    cols = np.concatenate([np.sort(rng.choice(m, 36, replace=False)), [0, 2047, 2048, m - 1]])
+    C_rows = O.sqeuclid_points_cost(p.X[rows], p.Y, p.scale)          # 40 x m
+    C_cols = O.sqeuclid_points_cost(p.X, p.Y[cols], p.scale)          # n x 40
+    tol = 1e-12 if prec == "fp64" else mixed_tol(beta)
+    np.testing.assert_allclose(host(out["log_rP"])[rows], O.log_row_marginal(C_rows, beta, u[rows], v),
+                               atol=tol, rtol=0)
+    np.testing.assert_allclose(host(out["log_cP"])[cols], O.log_col_marginal(C_cols, beta, u, v[cols]),
+                               atol=tol, rtol=0)
+    hx_ref, _ = O.hvp(C_rows, beta, u[rows], v, rho, x[rows], y)
+    ax, _ = O.hvp(C_rows, beta, u[rows], v, rho, np.abs(x[rows]), np.abs(y))
+    _, hy_ref = O.hvp(C_cols, beta, u, v[cols], rho, x, y[cols])
+    _, ay = O.hvp(C_cols, beta, u, v[cols], rho, np.abs(x), np.abs(y[cols]))
+    assert np.all(np.abs(host(Hx)[rows] - hx_ref) <= tol * ax + 1e-300)
+    assert np.all(np.abs(host(Hy)[cols] - hy_ref) <= tol * ay + 1e-300)
