@@ -672,6 +672,240 @@ __global__ __launch_bounds__(256) EOT_HD_OCCUPANCY void k_pass_hd_mx(PassArgs A)
     }
 }
 
+// ---- FP64: x . y on the FP64 matrix cores -----------------------------------
+// v_mfma_f64_16x16x4_f64 (IEEE FP64 products and sums; lane layout checked on the
+// target: A[i][k] from lane i + 16 k, B[k][j] from lane j + 16 k, D[i][j] in lane
+// j + 16 (i % 4), element i / 4). The shared dimension is permuted so that lane
+// group g = l / 16 supplies dimensions g D4 .. g D4 + D4 - 1 (one per product),
+// which makes each lane's operand slice contiguous; the products are then
+//     u_i - a_i + v_j - beta |x_i - y_j|^2
+//   = ((u_i - a_i) - beta |x_i|^2) + (v_j - beta |y_j|^2) + 2 beta x_i . y_j
+// with the norms in FP64, and exp in FP64. A workgroup owns 128 rows (the FP32
+// points staged in LDS, converted exactly when read); each wave owns two 16-row
+// blocks and walks the tile's columns 16 at a time, its next step's column
+// operands loaded during the current step. Column sums reduce over the 4 lane
+// groups in registers and over the waves in LDS, one barrier per 128 columns.
+constexpr int kF64Blk = 128;
+constexpr int kF64Step = 16;
+
+template <int NR, int NC, int MODE2, int D4>
+__global__ __launch_bounds__(256) void k_pass_hd_f64(PassArgs A)
+{
+    if (A.skip && *A.skip) return;
+    constexpr bool HVP = MODE2 == R2_HVP;
+    constexpr int d = 4 * D4;
+    constexpr int XS = d + 1;                          // padded row stride (floats)
+    constexpr int NRA = NR > 0 ? NR : 1, NCA = NC > 0 ? NC : 1;
+    __shared__ float s_x[kHdRows * XS];
+    __shared__ double s_E[kHdRows];                    // (u - a) - beta |x|^2
+    __shared__ double s_xx[kHdRows];                   // |x|^2
+    __shared__ double s_w0[kHdRows], s_w1[kHdRows];    // column weights (R_i included)
+    __shared__ double s_hx[kHdRows];                   // HVP: x_i
+    __shared__ double s_cp[2][NCA][kWaves][kF64Blk];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int jl = lane & 15, g = lane >> 4;
+    const int64_t n = A.n, m = A.m;
+    const int64_t i0 = (int64_t)blockIdx.y * kHdRows;
+    const int64_t j0 = (int64_t)blockIdx.x * A.hd_cols;
+    const double beta = A.beta;                        // 1 / (temperature x scale)
+    const double srho = A.hvp_srho;
+
+    // ---- the tile's rows: points in LDS, per-row values
+    for (int e = tid; e < kHdRows * d; e += 256) {
+        const int r = e / d, k = e % d;
+        const int64_t i = i0 + r;
+        s_x[r * XS + k] = i < n ? A.X[i * d + k] : 0.0f;
+    }
+    __syncthreads();
+    if (tid < kHdRows) {
+        const int64_t i = i0 + tid;
+        double xx = 0.0;
+        for (int k = 0; k < d; ++k) {
+            const double t = (double)s_x[tid * XS + k];
+            xx = fma(t, t, xx);
+        }
+        s_xx[tid] = xx;
+        if (i < n) {
+            const double a = A.a[i];
+            const double R = exp(a);
+            s_E[tid] = (A.u[i] - a) - beta * xx;
+            if constexpr (HVP) {
+                const double x = A.xw1[i];
+                s_hx[tid] = x;
+                s_w0[tid] = R * srho * x;
+                s_w1[tid] = R;
+            } else {
+                s_hx[tid] = 0.0;
+                s_w0[tid] = R * (A.xw0 ? A.xw0[i] : 1.0);
+                s_w1[tid] = R * (A.xw1 ? A.xw1[i] : 1.0);
+            }
+        } else {
+            s_E[tid] = -INFINITY;
+            s_hx[tid] = 0.0;
+            s_w0[tid] = 0.0;
+            s_w1[tid] = 0.0;
+        }
+    }
+    __syncthreads();
+
+    // the lane's column operand slice (FP32) of step st of block blk
+    auto load_cols = [&](int64_t jc, float (&yf)[D4]) {
+        int64_t j = jc + jl;
+        j = j < m ? j : m - 1;                         // finite filler past m
+        const float4* src = reinterpret_cast<const float4*>(A.Y + j * d + g * D4);
+#pragma unroll
+        for (int q = 0; q < D4 / 4; ++q) {
+            const float4 t = src[q];
+            yf[4 * q + 0] = t.x;
+            yf[4 * q + 1] = t.y;
+            yf[4 * q + 2] = t.z;
+            yf[4 * q + 3] = t.w;
+        }
+    };
+
+    double racc[NRA][2][4];
+#pragma unroll
+    for (int k = 0; k < NRA; ++k)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) racc[k][b][r] = 0.0;
+
+    const int64_t cols = m - j0 < A.hd_cols ? m - j0 : A.hd_cols;
+    const int nblk = (int)((cols + kF64Blk - 1) / kF64Blk);
+    const int ra = wave * 32 + jl;                     // MFMA operand A rows (block 0 / +16)
+    float ycur[D4], ynext[D4];
+    load_cols(j0, ycur);
+    for (int blk = 0; blk < nblk; ++blk) {
+        const int p = blk & 1;
+        const int64_t jb = j0 + (int64_t)blk * kF64Blk;
+        for (int st = 0; st < kF64Blk / kF64Step; ++st) {
+            const int64_t jc = jb + st * kF64Step;
+            const bool more = st + 1 < kF64Blk / kF64Step || blk + 1 < nblk;
+            if (more) load_cols(jc + kF64Step, ynext);
+            // x . y for the two 16-row blocks, and this lane's share of |y_j|^2
+            typedef double d4 __attribute__((ext_vector_type(4)));
+            d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+            double yy = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < D4; ++kk) {
+                const double b = (double)ycur[kk];
+                const double a0 = (double)s_x[ra * XS + g * D4 + kk];
+                const double a1 = (double)s_x[(ra + 16) * XS + g * D4 + kk];
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc1, 0, 0, 0);
+                yy = fma(b, b, yy);
+            }
+            yy = quad_total_f64(yy);
+            const int64_t j = jc + jl;
+            const bool jok = j < m;
+            const double F = jok ? A.v[j] - beta * yy : -INFINITY;
+            double yw0 = 0.0, yw1 = 0.0;
+            if (jok) {
+                if constexpr (HVP) {
+                    yw0 = A.yw1[j];
+                } else {
+                    yw0 = A.yw0 ? A.yw0[j] : 1.0;
+                    yw1 = A.yw1 ? A.yw1[j] : 1.0;
+                }
+            }
+            double cacc[NCA];
+#pragma unroll
+            for (int k = 0; k < NCA; ++k) cacc[k] = 0.0;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = wave * 32 + 16 * b + 4 * r + g;
+                    const double xy = b == 0 ? acc0[r] : acc1[r];
+                    const double e = exp(fma(2.0 * beta, xy, s_E[row] + F));
+                    if constexpr (HVP) {
+                        racc[0][b][r] = fma(e, fma(srho, yw0, s_hx[row]), racc[0][b][r]);
+                        cacc[0] = fma(e, fma(s_w1[row], yw0, s_w0[row]), cacc[0]);
+                    } else {
+                        double cd = 0.0;
+                        if constexpr (MODE2 == R2_COST) cd = fmax(s_xx[row] + yy - 2.0 * xy, 0.0);
+                        if constexpr (NR >= 1) racc[0][b][r] = fma(e, yw0, racc[0][b][r]);
+                        if constexpr (NR >= 2) {
+                            double term = e;
+                            if constexpr (MODE2 == R2_SQUARE) term = e * e;
+                            if constexpr (MODE2 == R2_COST) term = e * cd;
+                            racc[NR - 1][b][r] = fma(term, yw1, racc[NR - 1][b][r]);
+                        }
+                        if constexpr (NC >= 1) cacc[0] = fma(e, s_w0[row], cacc[0]);
+                        if constexpr (NC >= 2) {
+                            const double term = MODE2 == R2_COST ? e * cd : e;
+                            cacc[NC - 1] = fma(term, s_w1[row], cacc[NC - 1]);
+                        }
+                    }
+                }
+            }
+            if constexpr (NC > 0) {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) {
+                    const double tot = quad_total_f64(cacc[k]);
+                    if (g == 0) s_cp[p][k][wave][st * kF64Step + jl] = tot;
+                }
+            }
+            if (more) {
+#pragma unroll
+                for (int kk = 0; kk < D4; ++kk) ycur[kk] = ynext[kk];
+            }
+        }
+        __syncthreads();
+        if constexpr (NC > 0) {
+            if (tid < kF64Blk) {
+                const int64_t j = jb + tid;
+                if (j < m) {
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) {
+                        const double t = (s_cp[p][k][0][tid] + s_cp[p][k][1][tid]) +
+                                         (s_cp[p][k][2][tid] + s_cp[p][k][3][tid]);
+                        if (A.atomic)
+                            atomicAdd(&A.col_part[(int64_t)k * m + j], t);
+                        else
+                            A.col_part[((int64_t)k * A.tiles_n + blockIdx.y) * m + j] = t;
+                    }
+                }
+            }
+        }
+    }
+
+    // ---- row totals: the 16 lanes of a group g hold the same rows (4 r + g) of each block
+    if constexpr (NR > 0) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    double x = racc[k][b][r];
+                    x += dpp_f64<kDppXor1>(x);
+                    x += dpp_f64<kDppXor2>(x);
+                    x += dpp_f64<kDppHalfMirror>(x);
+                    x += dpp_f64<kDppMirror>(x);
+                    racc[k][b][r] = x;
+                }
+        if (jl == 0) {
+#pragma unroll
+            for (int k = 0; k < NR; ++k)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t i = i0 + wave * 32 + 16 * b + 4 * r + g;
+                        if (i < n) {
+                            if (A.atomic)
+                                atomicAdd(&A.row_part[(int64_t)k * n + i], racc[k][b][r]);
+                            else
+                                A.row_part[((int64_t)k * A.tiles_m + blockIdx.x) * n + i] = racc[k][b][r];
+                        }
+                    }
+        }
+    }
+}
+
 template <int NR, int NC, int MODE2>
 hipError_t launch_hd(const PassArgs& a, int prec, hipStream_t s)
 {
@@ -696,12 +930,20 @@ hipError_t launch_hd(const PassArgs& a, int prec, hipStream_t s)
             return hipGetLastError();
         }
     }
-    if (prec == EOT_PREC_MIXED)
+    if (prec == EOT_PREC_MIXED) {
         hipLaunchKernelGGL((k_pass_hd<EOT_PREC_MIXED, NR, NC, MODE2, 0>), grid, dim3(256), 0, s, a,
                            nullptr);
-    else
+    } else if (reinterpret_cast<uintptr_t>(a.Y) % 16 != 0) {   // the FP64 kernel reads Y as float4
         hipLaunchKernelGGL((k_pass_hd<EOT_PREC_FP64, NR, NC, MODE2, 0>), grid, dim3(256), 0, s, a,
                            nullptr);
+    } else {
+        switch (a.d) {
+        case 16: hipLaunchKernelGGL((k_pass_hd_f64<NR, NC, MODE2, 4>), grid, dim3(256), 0, s, a); break;
+        case 32: hipLaunchKernelGGL((k_pass_hd_f64<NR, NC, MODE2, 8>), grid, dim3(256), 0, s, a); break;
+        case 48: hipLaunchKernelGGL((k_pass_hd_f64<NR, NC, MODE2, 12>), grid, dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_pass_hd_f64<NR, NC, MODE2, 16>), grid, dim3(256), 0, s, a); break;
+        }
+    }
     return hipGetLastError();
 }
 

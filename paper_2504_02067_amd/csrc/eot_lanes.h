@@ -111,6 +111,18 @@ __device__ __forceinline__ float pair_total32(float x)
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
+// x summed over the lane pair (l, l ^ 32), on both lanes (FP64).
+__device__ __forceinline__ double pair_total32_f64(double x)
+{
+    return pair_sum32(x, x);
+}
+
+// x summed over the lanes l, l ^ 16, l ^ 32, l ^ 48, on all four (FP64).
+__device__ __forceinline__ double quad_total_f64(double x)
+{
+    return pair_sum32(pair_sum16(x, x), pair_sum16(x, x));
+}
+
 // LDS byte address of a __shared__ object.
 template <typename T>
 __device__ __forceinline__ uint32_t lds_addr(const T* p)
