@@ -18,6 +18,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <thread>
 #include <vector>
@@ -99,7 +100,41 @@ struct HdVecs {
     double* gpart = nullptr;                      // [kHdMaxPart] grid maxima
 };
 
+// Pinned host staging for the scalars the host driver reads back (CG scalars,
+// reductions, flags): device -> pinned copies skip the runtime's pageable
+// staging. A process-wide pool of small buffers, leased by a call for its
+// lifetime; buffers are reused and never freed (at most one per concurrently
+// running call). Without pinned memory the copies go to pageable memory.
+constexpr int kPinBytes = 512;
+std::mutex g_pin_mu;
+std::vector<void*>* g_pin_free = nullptr;      // never destroyed: safe at process exit
+
+struct PinLease {
+    void* p = nullptr;
+    PinLease()
+    {
+        std::lock_guard<std::mutex> lk(g_pin_mu);
+        if (!g_pin_free) g_pin_free = new std::vector<void*>();
+        if (!g_pin_free->empty()) {
+            p = g_pin_free->back();
+            g_pin_free->pop_back();
+        } else if (hipHostMalloc(&p, kPinBytes, hipHostMallocDefault) != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();            // do not leave the failure for a later check
+        }
+    }
+    ~PinLease()
+    {
+        if (!p) return;
+        std::lock_guard<std::mutex> lk(g_pin_mu);
+        g_pin_free->push_back(p);
+    }
+    PinLease(const PinLease&) = delete;
+    PinLease& operator=(const PinLease&) = delete;
+};
+
 struct Ctx {
+    PinLease pin;
     eot_cost cost{};
     int64_t n = 0, m = 0;
     int tiles_m = 0, tiles_n = 0;
@@ -325,18 +360,29 @@ hipError_t run_pass(Ctx& x, const PassArgs& A, int prec, int nr, int nc, int mod
 }
 
 // Read `k` device doubles back to the host (waits for the stream).
-eot_status fetch(Ctx& x, const double* d, double* h, int k)
+// Device -> host copy of `bytes` bytes and a wait on the stream (through the
+// call's pinned buffer when it has one and the data fit).
+eot_status fetch_bytes(Ctx& x, const void* d, void* h, size_t bytes)
 {
-    HIPCHK(hipMemcpyAsync(h, d, sizeof(double) * k, hipMemcpyDeviceToHost, x.s));
+    if (x.pin.p && bytes <= (size_t)kPinBytes) {
+        HIPCHK(hipMemcpyAsync(x.pin.p, d, bytes, hipMemcpyDeviceToHost, x.s));
+        HIPCHK(hipStreamSynchronize(x.s));
+        std::memcpy(h, x.pin.p, bytes);
+        return EOT_OK;
+    }
+    HIPCHK(hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, x.s));
     HIPCHK(hipStreamSynchronize(x.s));
     return EOT_OK;
 }
 
+eot_status fetch(Ctx& x, const double* d, double* h, int k)
+{
+    return fetch_bytes(x, d, h, sizeof(double) * (size_t)k);
+}
+
 eot_status fetch_flags(Ctx& x, int32_t* h)
 {
-    HIPCHK(hipMemcpyAsync(h, x.sc.flags, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, x.s));
-    HIPCHK(hipStreamSynchronize(x.s));
-    return EOT_OK;
+    return fetch_bytes(x, x.sc.flags, h, sizeof(int32_t) * 2);
 }
 
 eot_status clear_flags(Ctx& x)
@@ -606,9 +652,18 @@ eot_status refresh(Ctx& x, int prec, double beta, const double* shift_guess, Sol
     int nb = 0;
     HIPCHK(launch_reduce(RED_L1_DIFF_EXP, S.rt, S.lr, x.n, x.sc.red, &nb, x.s));
     HIPCHK(launch_finish_sum(x.sc.red, nb, x.sc.scal, x.s));
-    HIPCHK(hipMemcpyAsync(fl, x.sc.flags, sizeof(fl), hipMemcpyDeviceToHost, x.s));
-    HIPCHK(hipMemcpyAsync(gn_out, x.sc.scal, sizeof(double), hipMemcpyDeviceToHost, x.s));
-    HIPCHK(hipStreamSynchronize(x.s));
+    if (x.pin.p) {
+        char* pb = static_cast<char*>(x.pin.p);
+        HIPCHK(hipMemcpyAsync(pb, x.sc.flags, sizeof(fl), hipMemcpyDeviceToHost, x.s));
+        HIPCHK(hipMemcpyAsync(pb + 64, x.sc.scal, sizeof(double), hipMemcpyDeviceToHost, x.s));
+        HIPCHK(hipStreamSynchronize(x.s));
+        std::memcpy(fl, pb, sizeof(fl));
+        std::memcpy(gn_out, pb + 64, sizeof(double));
+    } else {
+        HIPCHK(hipMemcpyAsync(fl, x.sc.flags, sizeof(fl), hipMemcpyDeviceToHost, x.s));
+        HIPCHK(hipMemcpyAsync(gn_out, x.sc.scal, sizeof(double), hipMemcpyDeviceToHost, x.s));
+        HIPCHK(hipStreamSynchronize(x.s));
+    }
     if (fl[0] == 0) return EOT_OK;
     ss.st->range_retries += 1;
     EOTCHK(clear_flags(x));

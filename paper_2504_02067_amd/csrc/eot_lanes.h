@@ -134,14 +134,15 @@ __device__ __forceinline__ uint32_t lds_addr(const T* p)
 // (global_load_lds_dwordx4; lds_base is the same on every lane). Written as
 // inline assembly so that the compiler's wait-count pass does not make every
 // later LDS read wait for it: the caller waits for its own copies (s_waitcnt
-// vmcnt) before the barrier that publishes them. M0 written by a scalar op
-// needs one wait state before an LDS copy uses it.
+// vmcnt) before the barrier that publishes them. The base goes in through M0
+// (an operand, so the compiler sets it and knows it is used); a scalar write
+// of M0 needs one wait state before an LDS copy uses it.
 __device__ __forceinline__ void lds_dma16(const void* gptr, uint32_t lds_base)
 {
-    asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off"
+    asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
                  :
-                 : "s"(__builtin_amdgcn_readfirstlane(lds_base)), "v"(gptr)
-                 : "memory", "m0");
+                 : "v"(gptr), "{m0}"(__builtin_amdgcn_readfirstlane(lds_base))
+                 : "memory");
 }
 
 }  // namespace eot
