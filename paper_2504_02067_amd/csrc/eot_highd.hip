@@ -688,9 +688,12 @@ __global__ __launch_bounds__(256) EOT_HD_OCCUPANCY void k_pass_hd_mx(PassArgs A)
 constexpr int kF64Blk = 128;
 constexpr int kF64Step = 16;
 
-template <int NR, int NC, int MODE2, int D4>
-__global__ __launch_bounds__(256) void k_pass_hd_f64(PassArgs A)
+// OP = 1: row maxima of u_i + v_j - beta C_ij (FP64; no row shift, no sums), into
+// part[blockIdx.x][n] or atomically into out32 (FP32, a range shift only).
+template <int NR, int NC, int MODE2, int D4, int OP = 0>
+__global__ __launch_bounds__(256) void k_pass_hd_f64(PassArgs A, float* out32)
 {
+    constexpr bool MAXOP = OP == 1;
     if (A.skip && *A.skip) return;
     constexpr bool HVP = MODE2 == R2_HVP;
     constexpr int d = 4 * D4;
@@ -727,10 +730,14 @@ __global__ __launch_bounds__(256) void k_pass_hd_f64(PassArgs A)
         }
         s_xx[tid] = xx;
         if (i < n) {
-            const double a = A.a[i];
-            const double R = exp(a);
+            const double a = MAXOP ? 0.0 : A.a[i];
+            const double R = MAXOP ? 0.0 : exp(a);
             s_E[tid] = (A.u[i] - a) - beta * xx;
-            if constexpr (HVP) {
+            if constexpr (MAXOP) {
+                s_hx[tid] = 0.0;
+                s_w0[tid] = 0.0;
+                s_w1[tid] = 0.0;
+            } else if constexpr (HVP) {
                 const double x = A.xw1[i];
                 s_hx[tid] = x;
                 s_w0[tid] = R * srho * x;
@@ -770,7 +777,7 @@ __global__ __launch_bounds__(256) void k_pass_hd_f64(PassArgs A)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) racc[k][b][r] = 0.0;
+            for (int r = 0; r < 4; ++r) racc[k][b][r] = MAXOP ? -INFINITY : 0.0;
 
     const int64_t cols = m - j0 < A.hd_cols ? m - j0 : A.hd_cols;
     const int nblk = (int)((cols + kF64Blk - 1) / kF64Blk);
@@ -780,6 +787,7 @@ __global__ __launch_bounds__(256) void k_pass_hd_f64(PassArgs A)
     for (int blk = 0; blk < nblk; ++blk) {
         const int p = blk & 1;
         const int64_t jb = j0 + (int64_t)blk * kF64Blk;
+#pragma unroll 1
         for (int st = 0; st < kF64Blk / kF64Step; ++st) {
             const int64_t jc = jb + st * kF64Step;
             const bool more = st + 1 < kF64Blk / kF64Step || blk + 1 < nblk;
@@ -802,7 +810,7 @@ __global__ __launch_bounds__(256) void k_pass_hd_f64(PassArgs A)
             const bool jok = j < m;
             const double F = jok ? A.v[j] - beta * yy : -INFINITY;
             double yw0 = 0.0, yw1 = 0.0;
-            if (jok) {
+            if (jok && !MAXOP) {
                 if constexpr (HVP) {
                     yw0 = A.yw1[j];
                 } else {
@@ -819,6 +827,10 @@ __global__ __launch_bounds__(256) void k_pass_hd_f64(PassArgs A)
                 for (int r = 0; r < 4; ++r) {
                     const int row = wave * 32 + 16 * b + 4 * r + g;
                     const double xy = b == 0 ? acc0[r] : acc1[r];
+                    if constexpr (MAXOP) {
+                        racc[0][b][r] = fmax(racc[0][b][r], fma(2.0 * beta, xy, s_E[row] + F));
+                        continue;
+                    }
                     const double e = exp(fma(2.0 * beta, xy, s_E[row] + F));
                     if constexpr (HVP) {
                         racc[0][b][r] = fma(e, fma(srho, yw0, s_hx[row]), racc[0][b][r]);
@@ -881,10 +893,17 @@ __global__ __launch_bounds__(256) void k_pass_hd_f64(PassArgs A)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     double x = racc[k][b][r];
-                    x += dpp_f64<kDppXor1>(x);
-                    x += dpp_f64<kDppXor2>(x);
-                    x += dpp_f64<kDppHalfMirror>(x);
-                    x += dpp_f64<kDppMirror>(x);
+                    if constexpr (MAXOP) {
+                        x = fmax(x, dpp_f64<kDppXor1>(x));
+                        x = fmax(x, dpp_f64<kDppXor2>(x));
+                        x = fmax(x, dpp_f64<kDppHalfMirror>(x));
+                        x = fmax(x, dpp_f64<kDppMirror>(x));
+                    } else {
+                        x += dpp_f64<kDppXor1>(x);
+                        x += dpp_f64<kDppXor2>(x);
+                        x += dpp_f64<kDppHalfMirror>(x);
+                        x += dpp_f64<kDppMirror>(x);
+                    }
                     racc[k][b][r] = x;
                 }
         if (jl == 0) {
@@ -895,7 +914,17 @@ __global__ __launch_bounds__(256) void k_pass_hd_f64(PassArgs A)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int64_t i = i0 + wave * 32 + 16 * b + 4 * r + g;
-                        if (i < n) {
+                        if (i < n && MAXOP) {
+                            const float xf = (float)racc[k][b][r];
+                            if (A.atomic) {
+                                if (xf >= 0.0f)
+                                    atomicMax(reinterpret_cast<int*>(&out32[i]), __float_as_int(xf));
+                                else
+                                    atomicMin(reinterpret_cast<unsigned int*>(&out32[i]), __float_as_uint(xf));
+                            } else {
+                                A.row_part[(int64_t)blockIdx.x * n + i] = (double)xf;
+                            }
+                        } else if (i < n) {
                             if (A.atomic)
                                 atomicAdd(&A.row_part[(int64_t)k * n + i], racc[k][b][r]);
                             else
@@ -938,10 +967,10 @@ hipError_t launch_hd(const PassArgs& a, int prec, hipStream_t s)
                            nullptr);
     } else {
         switch (a.d) {
-        case 16: hipLaunchKernelGGL((k_pass_hd_f64<NR, NC, MODE2, 4>), grid, dim3(256), 0, s, a); break;
-        case 32: hipLaunchKernelGGL((k_pass_hd_f64<NR, NC, MODE2, 8>), grid, dim3(256), 0, s, a); break;
-        case 48: hipLaunchKernelGGL((k_pass_hd_f64<NR, NC, MODE2, 12>), grid, dim3(256), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_pass_hd_f64<NR, NC, MODE2, 16>), grid, dim3(256), 0, s, a); break;
+        case 16: hipLaunchKernelGGL((k_pass_hd_f64<NR, NC, MODE2, 4>), grid, dim3(256), 0, s, a, nullptr); break;
+        case 32: hipLaunchKernelGGL((k_pass_hd_f64<NR, NC, MODE2, 8>), grid, dim3(256), 0, s, a, nullptr); break;
+        case 48: hipLaunchKernelGGL((k_pass_hd_f64<NR, NC, MODE2, 12>), grid, dim3(256), 0, s, a, nullptr); break;
+        default: hipLaunchKernelGGL((k_pass_hd_f64<NR, NC, MODE2, 16>), grid, dim3(256), 0, s, a, nullptr); break;
         }
     }
     return hipGetLastError();
@@ -1025,8 +1054,17 @@ hipError_t launch_rowmax_hd(const PassArgs& a, double* part, double* out, hipStr
     const unsigned eb = (unsigned)((a.n + 255) / 256 < 1024 ? (a.n + 255) / 256 : 1024);
     if (a.atomic)
         hipLaunchKernelGGL(k_hd_fill_f32, dim3(eb), dim3(256), 0, s, out32, -INFINITY, a.n);
-    hipLaunchKernelGGL((k_pass_hd<EOT_PREC_FP64, 1, 0, R2_WEIGHT, 1>), grid, dim3(256), 0, s, a,
-                       out32);
+    if (reinterpret_cast<uintptr_t>(a.Y) % 16 != 0) {   // the matrix-core kernel reads Y as float4
+        hipLaunchKernelGGL((k_pass_hd<EOT_PREC_FP64, 1, 0, R2_WEIGHT, 1>), grid, dim3(256), 0, s, a,
+                           out32);
+    } else {
+        switch (a.d) {
+        case 16: hipLaunchKernelGGL((k_pass_hd_f64<1, 0, R2_WEIGHT, 4, 1>), grid, dim3(256), 0, s, a, out32); break;
+        case 32: hipLaunchKernelGGL((k_pass_hd_f64<1, 0, R2_WEIGHT, 8, 1>), grid, dim3(256), 0, s, a, out32); break;
+        case 48: hipLaunchKernelGGL((k_pass_hd_f64<1, 0, R2_WEIGHT, 12, 1>), grid, dim3(256), 0, s, a, out32); break;
+        default: hipLaunchKernelGGL((k_pass_hd_f64<1, 0, R2_WEIGHT, 16, 1>), grid, dim3(256), 0, s, a, out32); break;
+        }
+    }
     if (a.atomic)
         hipLaunchKernelGGL(k_hd_to_f64, dim3(eb), dim3(256), 0, s, out32, out, a.n);
     else
