@@ -134,3 +134,42 @@ def test_highd_wide_tiles_sampled(prec):
     _, ay = O.hvp(C_cols, beta, u, v[cols], rho, np.abs(x), np.abs(y[cols]))
     assert np.all(np.abs(host(Hx)[rows] - hx_ref) <= tol * ax + 1e-300)
     assert np.all(np.abs(host(Hy)[cols] - hy_ref) <= tol * ay + 1e-300)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_highd_atomic_outputs_sampled(prec):
+    """n = m = 65536, d = 64 (the benchmark's embedding size): the per-tile partials
+    would exceed the library's limit, so the passes accumulate their outputs
+    atomically. Marginals (with the row-maximum shift), the HVP and the mass
+    identity, checked on sampled rows and columns against the oracle."""
+    n = m = 1 << 16
+    d, gamma, rho = 64, 0.05, 0.6
+    beta = 1.0 / gamma
+    p = W.embedding_problem(n, m, d, 31)
+    pc = eot.PointCloud(torch.from_numpy(p.X).to(DEV), torch.from_numpy(p.Y).to(DEV), p.scale)
+    rng = np.random.default_rng(32)
+    u = np.log(p.r) + 0.5 * rng.standard_normal(n)
+    v = np.log(p.c) + 0.5 * rng.standard_normal(m)
+    x = rng.standard_normal(n); y = rng.standard_normal(m)
+    f, g = u * gamma, v * gamma
+    u, v = O.to_log_units(f, g, gamma)
+    say(f"high-d atomic outputs n=m={n} d={d} {prec}")
+    out = eot.eot_marginals(pc, gamma, dvec(f), dvec(g), precision=prec, want=("log_rP", "log_cP"))
+    Hx, Hy = eot.eot_hvp(pc, gamma, dvec(f), dvec(g), rho, dvec(x), dvec(y), precision=prec)
+    torch.cuda.synchronize()
+    rows = np.concatenate([np.sort(rng.choice(n, 36, replace=False)), [0, n - 1]])
+    cols = np.concatenate([np.sort(rng.choice(m, 36, replace=False)), [0, m - 1]])
+    C_rows = O.sqeuclid_points_cost(p.X[rows], p.Y, p.scale)
+    C_cols = O.sqeuclid_points_cost(p.X, p.Y[cols], p.scale)
+    tol = 1e-12 if prec == "fp64" else mixed_tol(beta)
+    lr, lc = host(out["log_rP"]), host(out["log_cP"])
+    np.testing.assert_allclose(lr[rows], O.log_row_marginal(C_rows, beta, u[rows], v), atol=tol, rtol=0)
+    np.testing.assert_allclose(lc[cols], O.log_col_marginal(C_cols, beta, u, v[cols]), atol=tol, rtol=0)
+    m1 = np.exp(lr).sum(); m2 = np.exp(lc).sum()
+    assert abs(m1 - m2) <= 10 * tol * m1
+    hx_ref, _ = O.hvp(C_rows, beta, u[rows], v, rho, x[rows], y)
+    ax, _ = O.hvp(C_rows, beta, u[rows], v, rho, np.abs(x[rows]), np.abs(y))
+    _, hy_ref = O.hvp(C_cols, beta, u, v[cols], rho, x, y[cols])
+    _, ay = O.hvp(C_cols, beta, u, v[cols], rho, np.abs(x), np.abs(y[cols]))
+    assert np.all(np.abs(host(Hx)[rows] - hx_ref) <= tol * ax + 1e-300)
+    assert np.all(np.abs(host(Hy)[cols] - hy_ref) <= tol * ay + 1e-300)
