@@ -23,7 +23,9 @@
  *    marked "host" point to host memory.
  *  - Scratch memory comes from the caller-provided `ws` (device, 256-byte
  *    aligned) of at least the size eot_workspace_size() reports; the library
- *    calls no hipMalloc.
+ *    calls no hipMalloc. The only memory it takes itself is a small pool of
+ *    512-byte pinned host buffers that receive the scalars a call reads back
+ *    (one per concurrently running call, reused, never freed).
  *  - `stream` is a hipStream_t (NULL = the default stream). eot_marginals
  *    and eot_hvp are asynchronous on it; eot_newton_cg and eot_solve make
  *    host-side decisions and return after their work on `stream` finished.
@@ -34,7 +36,8 @@
  *    ldc >= m (elements).
  *  - Calls on different streams with different workspaces are independent;
  *    the library keeps no global mutable state apart from the opt-in pass
- *    timer below (guarded by a mutex).
+ *    timer (guarded by a mutex), the tile-height override below (an atomic)
+ *    and the pinned-buffer pool (guarded by a mutex).
  */
 #ifndef EOT_H
 #define EOT_H
@@ -74,7 +77,8 @@ typedef enum {
 
 typedef struct {
     int32_t kind;      /* eot_cost_kind                                            */
-    int32_t d;         /* point dimension (points only), 1..16                      */
+    int32_t d;         /* point dimension (points only): 2, 3 (vector units) or     */
+                       /* 16, 32, 48, 64 (x . y on the matrix cores)               */
     int64_t n;         /* rows    (length of r, f)                                  */
     int64_t m;         /* columns (length of c, g)                                  */
     int64_t ldc;       /* dense: leading dimension in elements, >= m                */
