@@ -1,24 +1,24 @@
 // Streaming passes for high-dimensional point clouds (d = 16, 32, 48, 64):
-// C_ij = |x_i - y_j|^2 / s recomputed on the fly, with the x . y contraction on
-// the matrix cores in mixed precision.
+// C_ij = |x_i - y_j|^2 / s recomputed on the fly as |x_i|^2 + |y_j|^2 -
+// 2 x_i . y_j, with the x . y contraction on the matrix cores. Three kernels:
 //
-// |x_i - y_j|^2 = |x_i|^2 + |y_j|^2 - 2 x_i . y_j. A workgroup (4 wave64) owns
-// 128 rows x 512 columns; each wave owns 32 rows and walks the 512 columns in
-// steps of 32, computing the 32 x 32 block of dot products with
-// v_mfma_f32_32x32x16_bf16. FP32 coordinates are split as x = xh + xl with xh
-// = bf16(x), xl = bf16(x - xh), prepared once per call together with the
-// squared norms; x . y ~ xh.yh + xh.yl + xl.yh (three MFMAs per 16 dimensions,
-// FP32 accumulation; the dropped xl.yl term is ~2^-16 relative). Each step's
-// 32 columns are staged in LDS once for the 4 waves.
-// The plan entries then go through the same mixed-precision exponent and FP64
-// accumulation as the dense pass. In FP64 mode the squared distance is formed
-// per entry in FP64 (difference form, VALU), for the line search and the final
-// verification of a solve.
+//  * k_pass_hd_mx (mixed precision, every sum except cost-weighted ones): FP32
+//    coordinates split once per call as x = xh + xl (xh = bf16(x), xl =
+//    bf16(x - xh)); x . y ~ xh.yh + xh.yl + xl.yh, three
+//    v_mfma_f32_32x32x16_bf16 per 16 dimensions with FP32 accumulation (the
+//    dropped xl.yl term is ~2^-16 relative). Per-pass tables hold the rows' and
+//    columns' exponent parts; column operands are copied global -> LDS by DMA,
+//    double-buffered. Details at the kernel.
+//  * k_pass_hd_f64 (FP64 mode and row maxima): x . y from
+//    v_mfma_f64_16x16x4_f64, norms and exp in FP64.
+//  * k_pass_hd (the mixed cost-weighted sums, and the fallback when a point
+//    array is not 16-byte aligned): the 32 x 32 BF16 hi/lo products staged per
+//    step in mixed mode, |x - y|^2 per entry in FP64 (difference form) in FP64.
 //
-// Lane layout of the 32 x 32 MFMA result (checked on the target): lane l holds
-// the entries (row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32), r = 0..15;
-// operand A lane l supplies row l % 32, dimensions 8 (l / 32) + 0..7 of each
-// 16-dimension chunk, operand B lane l the same dimensions of column l % 32.
+// Lane layout of the 32 x 32 BF16 MFMA result (checked on the target): lane l
+// holds the entries (row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32), r =
+// 0..15; operand A lane l supplies row l % 32, dimensions 8 (l / 32) + 0..7 of
+// each 16-dimension chunk, operand B lane l the same dimensions of column l % 32.
 
 #include <hip/hip_runtime.h>
 #include <math.h>
