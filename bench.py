@@ -264,7 +264,7 @@ def main():
                     help="only the HVP kernel loop and a 1 GiB device copy (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); this build has no "
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the library has no "
               f"multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
