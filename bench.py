@@ -168,6 +168,21 @@ def highd_measure(args, eot, W, dev, iters=5):
         sec = ms / 1e3 / k
         res[f"{prec}_ms"] = sec * 1e3
         res[f"{prec}_entries_per_s"] = float(n) * m / sec
+    # the CG's single-sum passes (column sums, then row sums), mixed
+    for name, want, filt in (("colpass", ("log_cP",), dict(nr=0, nc=1)),
+                             ("rowpass", ("log_rP",), dict(nr=1, nc=0))):
+        fn = lambda: eot.eot_marginals(pc, gamma, f, g, row_shift=shift, precision="mixed", want=want)
+        fn()
+        torch.cuda.synchronize()
+        eot.eot_pass_timing(True)
+        for _ in range(iters):
+            fn()
+        torch.cuda.synchronize()
+        k, ms = eot.eot_pass_timing_read(precision="mixed", **filt)
+        eot.eot_pass_timing(False)
+        sec = ms / 1e3 / k
+        res[f"{name}_mixed_ms"] = sec * 1e3
+        res[f"{name}_mfma_frac"] = 3 * 2 * d * float(n) * m / sec / 2.5e15
     eps = res["mixed_entries_per_s"]
     mfma = 3 * 2 * d * eps                      # BF16 hi/lo: three products per dimension pair
     res["mfma"] = {"achieved": mfma / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
@@ -182,6 +197,9 @@ def highd_measure(args, eot, W, dev, iters=5):
     log(f"high-d HVP mixed {res['mixed_ms']:.2f} ms ({eps / 1e12:.2f} T entries/s, MFMA "
         f"{mfma / 1e12:.0f} TFLOP/s = {100 * mfma / 2.5e15:.1f}% of BF16 peak), FP64 {res['fp64_ms']:.2f} ms "
         f"(FP64 MFMA {mfma64 / 1e12:.1f} TFLOP/s = {100 * mfma64 / 78.6e12:.0f}% of FP64 peak)")
+    log(f"high-d CG passes mixed: column {res['colpass_mixed_ms']:.2f} ms "
+        f"({100 * res['colpass_mfma_frac']:.1f}% of BF16 peak), row {res['rowpass_mixed_ms']:.2f} ms "
+        f"({100 * res['rowpass_mfma_frac']:.1f}%)")
     return res
 
 
