@@ -203,6 +203,49 @@ def highd_measure(args, eot, W, dev, iters=5):
     return res
 
 
+def round_measure(eot, C, gamma, f, g, r, c):
+    """Rounding of the solve's plan onto U(r, c) (three FP64 passes over the
+    cost): time, the cost of the rounded plan and its gap to <P, C>."""
+    import torch
+    eot.eot_round(C, gamma, f, g, r, c)                  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = eot.eot_round(C, gamma, f, g, r, c)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log(f"round: {dt * 1e3:.2f} ms, cost {out['cost_round']:.9f} (plan {out['cost_plan']:.9f})")
+    return {"seconds": dt, "cost_round": out["cost_round"], "cost_plan": out["cost_plan"],
+            "rel_gap": (out["cost_round"] - out["cost_plan"]) / out["cost_plan"]}
+
+
+def grad_measure(eot, W, dev):
+    """Backward of (W, S) for the largest batch problem (64 x 64 grid, 2-D
+    points, temperature 1e-3): the S part solves the Hessian system by CG;
+    gradients for X, Y, r and c, in FP64 and in mixed precision."""
+    import torch
+    sides = W.batch_sides()
+    k = int(np.argmax(sides))
+    p = W.batch_problem(k, sides=sides)
+    pc = eot.PointCloud(torch.from_numpy(p.X).to(dev), torch.from_numpy(p.Y).to(dev), p.scale)
+    r = torch.from_numpy(p.r).to(dev)
+    c = torch.from_numpy(p.c).to(dev)
+    gamma = 1e-3
+    f, g, st = eot.eot_solve(pc, r, c, gamma_init=1.0 / 32.0, gamma_final=gamma, tol=1e-6)
+    res = {"workload": f"batch problem {k}: n = m = {p.n} (2-D points), temperature {gamma}, "
+                       f"w_W = w_S = 1, outputs X, Y, r, c"}
+    for prec in ("fp64", "mixed"):
+        eot.eot_gradient(pc, gamma, f, g, 1.0, 1.0, want=("X", "Y", "r", "c"), precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = eot.eot_gradient(pc, gamma, f, g, 1.0, 1.0, want=("X", "Y", "r", "c"), precision=prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[prec] = {"seconds": dt, "cg_iters": int(out["cg_iters"]),
+                     "cg_residual": float(out["cg_residual"])}
+        log(f"gradient {prec}: {dt * 1e3:.1f} ms, {out['cg_iters']} CG iterations")
+    return res
+
+
 def batch_measure(args, eot, W, dev):
     """The ragged batch: 512 grid problems, sides uniform on 16..64 (n = side^2
     in [256, 4096]), integer grid positions as 2-D points with the cost
@@ -425,6 +468,8 @@ def main():
         log(f"  {dts:.2f} s status={sst['status']} err={sink['err']:.2e} sweeps={sst['sinkhorn_iters']} "
             f"final gamma={sst['final_gamma']:.1e}")
 
+    rnd = round_measure(eot, C, p.gamma_final, f, g, r, c)
+
     pts = None
     if not args.no_points:
         del C
@@ -436,8 +481,10 @@ def main():
         highd = highd_measure(args, eot, W, dev)
 
     batch = None
+    grad = None
     if not args.no_batch:
         batch = batch_measure(args, eot, W, dev)
+        grad = grad_measure(eot, W, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -476,6 +523,8 @@ def main():
                         "fp64_cg_iters": fp64["cg_iters"] if fp64 else None},
         "sinkhorn_baseline": sink,
         "kernels": kern,
+        "round": rnd,
+        "gradient": grad,
         "points": pts,
         "highd": highd,
         "batch": batch,
