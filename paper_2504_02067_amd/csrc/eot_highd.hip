@@ -672,6 +672,203 @@ __global__ __launch_bounds__(256) EOT_HD_OCCUPANCY void k_pass_hd_mx(PassArgs A)
     }
 }
 
+// The same pass with v_mfma_f32_16x16x32_bf16 for d = 32, 64 (whole 32-deep
+// chunks): each wave owns two 16-row blocks and takes 16 columns per step, so a
+// lane holds the table values of 8 rows instead of 16 and fewer registers are
+// live. Lane layout (checked on the target): A[i][k] in lane i + 16 (k / 8),
+// element k % 8; B[k][j] in lane j + 16 (k / 8), element k % 8; D[i][j] in lane
+// j + 16 (i / 4), element i % 4. Columns go through LDS in blocks of 64 (4 steps),
+// double-buffered, copied by DMA as 1 KB fragments in operand lane order (the
+// 64 records of a block are one more fragment).
+constexpr int kHd16Step = 16;
+constexpr int kHd16Blk = 64;
+constexpr int kHd16Steps = kHd16Blk / kHd16Step;
+
+template <int NR, int NC, int MODE2, int KC2>
+__global__ __launch_bounds__(256) EOT_HD_OCCUPANCY void k_pass_hd_mx16(PassArgs A)
+{
+    static_assert(KC2 == 1 || KC2 == 2, "KC2 = d / 32");
+    if (A.skip && *A.skip) return;
+    constexpr bool HVP = MODE2 == R2_HVP;
+    constexpr int NV = HVP ? 4 : 1 + NC;
+    constexpr int NRA = NR > 0 ? NR : 1, NCA = NC > 0 ? NC : 1;
+    constexpr int d = KC2 * 32;
+    // [buffer][hi, lo][step][chunk][lane]: 16 bytes each
+    __shared__ __attribute__((aligned(16))) bf16x8 s_b[2][2][kHd16Steps][KC2][64];
+    __shared__ __attribute__((aligned(16))) float4 s_rec[2][kHd16Blk];
+    __shared__ float s_cp[2][NCA][kWaves][kHd16Blk];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int jl = lane & 15, g = lane >> 4;
+    const int64_t n = A.n, m = A.m;
+    const int64_t i0 = (int64_t)blockIdx.y * kHdRows;
+    const int64_t j0 = (int64_t)blockIdx.x * A.hd_cols;
+    const __bf16* yh = static_cast<const __bf16*>(A.hd_yh);
+    const __bf16* yl = static_cast<const __bf16*>(A.hd_yl);
+    const float4* ct = static_cast<const float4*>(A.hd_ct);
+
+    auto copy_block = [&](int blk, int p) {
+        const int64_t jb = j0 + (int64_t)blk * kHd16Blk;
+        constexpr int NF = 2 * kHd16Steps * KC2;
+#pragma unroll
+        for (int f = wave; f < NF + 1; f += kWaves) {
+            if (f == NF) {                                   // the block's records
+                lds_dma16(ct + jb + lane, lds_addr(&s_rec[p][0]));
+                continue;
+            }
+            const int hl = f / (kHd16Steps * KC2), st = (f / KC2) % kHd16Steps, kc = f % KC2;
+            int64_t j = jb + st * kHd16Step + jl;
+            j = j < m ? j : m - 1;                           // finite filler past m
+            const __bf16* src = (hl ? yl : yh) + j * d + kc * 32 + 8 * g;
+            lds_dma16(src, lds_addr(&s_b[p][hl][st][kc][0]));
+        }
+    };
+    copy_block(0, 0);
+
+    // the lane's 8 result rows: block b, rows 4 g + r
+    float rv[NV][8];
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int64_t i = i0 + wave * 32 + 16 * b + 4 * g;
+            const float4 t4 = *reinterpret_cast<const float4*>(A.hd_rt + k * A.hd_npad + i);
+            rv[k][4 * b + 0] = t4.x;
+            rv[k][4 * b + 1] = t4.y;
+            rv[k][4 * b + 2] = t4.z;
+            rv[k][4 * b + 3] = t4.w;
+        }
+    // MFMA operand A: block b, row 16 b + jl, dimensions 32 kc + 8 g .. + 7
+    bf16x8 ah[2][KC2], al[2][KC2];
+    {
+        const __bf16* xh = static_cast<const __bf16*>(A.hd_xh);
+        const __bf16* xl = static_cast<const __bf16*>(A.hd_xl);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int64_t ai = i0 + wave * 32 + 16 * b + jl;
+#pragma unroll
+            for (int kc = 0; kc < KC2; ++kc) {
+                if (ai < n) {
+                    const int64_t off = ai * d + kc * 32 + 8 * g;
+                    ah[b][kc] = *reinterpret_cast<const bf16x8*>(xh + off);
+                    al[b][kc] = *reinterpret_cast<const bf16x8*>(xl + off);
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) ah[b][kc][t] = al[b][kc][t] = (__bf16)0.0f;
+                }
+            }
+        }
+    }
+    const float B2 = (float)(2.0 * kLog2eHd * A.beta);
+    float racc[NRA][8];
+#pragma unroll
+    for (int k = 0; k < NRA; ++k)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) racc[k][r] = 0.0f;
+    __builtin_amdgcn_s_waitcnt(0);             // block 0 has landed in LDS
+    __syncthreads();
+
+    typedef float f32x4 __attribute__((ext_vector_type(4)));
+    const int64_t cols = m - j0 < A.hd_cols ? m - j0 : A.hd_cols;
+    const int nblk = (int)((cols + kHd16Blk - 1) / kHd16Blk);
+    for (int blk = 0; blk < nblk; ++blk) {
+        const int p = blk & 1;
+        if (blk + 1 < nblk) copy_block(blk + 1, p ^ 1);
+#pragma unroll 1
+        for (int st = 0; st < kHd16Steps; ++st) {
+            const int c = st * kHd16Step + jl;               // this lane's column in the block
+            const float4 rec = s_rec[p][c];
+            f32x4 acc[2];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[b] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int kc = 0; kc < KC2; ++kc) {
+                const bf16x8 bh = s_b[p][0][st][kc][lane];
+                const bf16x8 bl = s_b[p][1][st][kc][lane];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[b][kc], bh, acc[b], 0, 0, 0);
+                    acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[b][kc], bl, acc[b], 0, 0, 0);
+                    acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[b][kc], bh, acc[b], 0, 0, 0);
+                }
+            }
+            float cacc[NCA];
+#pragma unroll
+            for (int k = 0; k < NCA; ++k) cacc[k] = 0.0f;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+#pragma unroll
+                for (int r4 = 0; r4 < 4; ++r4) {
+                    const int r = 4 * b + r4;
+                    const float e = __builtin_amdgcn_exp2f(fmaf(B2, acc[b][r4], rv[0][r] + rec.x));
+                    if constexpr (HVP) {
+                        racc[0][r] = fmaf(e, fmaf(rv[1][r], rec.y, rec.z), racc[0][r]);
+                        cacc[0] = fmaf(e, fmaf(rv[2][r], rec.w, rv[3][r]), cacc[0]);
+                    } else {
+                        if constexpr (NR >= 1) racc[0][r] = fmaf(e, rec.z, racc[0][r]);
+                        if constexpr (NR >= 2)
+                            racc[1][r] = fmaf(MODE2 == R2_SQUARE ? e * e : e, rec.w, racc[1][r]);
+                        if constexpr (NC >= 1) cacc[0] = fmaf(e, rv[1][r], cacc[0]);
+                        if constexpr (NC >= 2) cacc[1] = fmaf(e, rv[2][r], cacc[1]);
+                    }
+                }
+            }
+            if constexpr (NC > 0) {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) {
+                    const float tot = quad_total_f32(cacc[k]);
+                    if (g == 0) s_cp[p][k][wave][c] = tot;
+                }
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);         // the next block has landed in LDS
+        __syncthreads();
+        if constexpr (NC > 0) {
+            if (tid < kHd16Blk) {
+                const int64_t j = j0 + (int64_t)blk * kHd16Blk + tid;
+                if (j < m) {
+                    const double f = (double)s_rec[p][tid].y;
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) {
+                        const double t = ((double)s_cp[p][k][0][tid] + (double)s_cp[p][k][1][tid]) +
+                                         ((double)s_cp[p][k][2][tid] + (double)s_cp[p][k][3][tid]);
+                        if (A.atomic)
+                            atomicAdd(&A.col_part[(int64_t)k * m + j], t * f);
+                        else
+                            A.col_part[((int64_t)k * A.tiles_n + blockIdx.y) * m + j] = t * f;
+                    }
+                }
+            }
+        }
+    }
+
+    // ---- row totals: the 16 lanes of a group g hold the same 8 rows
+    if constexpr (NR > 0) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                double x = (double)racc[k][r];
+                x += dpp_f64<kDppXor1>(x);
+                x += dpp_f64<kDppXor2>(x);
+                x += dpp_f64<kDppHalfMirror>(x);
+                x += dpp_f64<kDppMirror>(x);
+                if (jl == 0) {
+                    const int64_t i = i0 + wave * 32 + 16 * (r / 4) + 4 * g + (r % 4);
+                    if (i < n) {
+                        double fac = A.hd_rf[i];
+                        if (k == 1 && MODE2 == R2_SQUARE) fac *= fac;
+                        if (A.atomic)
+                            atomicAdd(&A.row_part[(int64_t)k * n + i], x * fac);
+                        else
+                            A.row_part[((int64_t)k * A.tiles_m + blockIdx.x) * n + i] = x * fac;
+                    }
+                }
+            }
+        }
+    }
+}
+
 // ---- FP64: x . y on the FP64 matrix cores -----------------------------------
 // v_mfma_f64_16x16x4_f64 (IEEE FP64 products and sums; lane layout checked on the
 // target: A[i][k] from lane i + 16 k, B[k][j] from lane j + 16 k, D[i][j] in lane
@@ -952,9 +1149,9 @@ hipError_t launch_hd(const PassArgs& a, int prec, hipStream_t s)
                                NR, NC, MODE2 == R2_SQUARE ? 1 : 0);
             switch (a.d) {
             case 16: hipLaunchKernelGGL((k_pass_hd_mx<NR, NC, MODE2, 1>), grid, dim3(256), 0, s, a); break;
-            case 32: hipLaunchKernelGGL((k_pass_hd_mx<NR, NC, MODE2, 2>), grid, dim3(256), 0, s, a); break;
+            case 32: hipLaunchKernelGGL((k_pass_hd_mx16<NR, NC, MODE2, 1>), grid, dim3(256), 0, s, a); break;
             case 48: hipLaunchKernelGGL((k_pass_hd_mx<NR, NC, MODE2, 3>), grid, dim3(256), 0, s, a); break;
-            default: hipLaunchKernelGGL((k_pass_hd_mx<NR, NC, MODE2, 4>), grid, dim3(256), 0, s, a); break;
+            default: hipLaunchKernelGGL((k_pass_hd_mx16<NR, NC, MODE2, 2>), grid, dim3(256), 0, s, a); break;
             }
             return hipGetLastError();
         }

@@ -123,6 +123,17 @@ __device__ __forceinline__ double quad_total_f64(double x)
     return pair_sum32(pair_sum16(x, x), pair_sum16(x, x));
 }
 
+// x summed over the lanes l, l ^ 16, l ^ 32, l ^ 48, on all four (FP32).
+__device__ __forceinline__ float quad_total_f32(float x)
+{
+    const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false,
+                                                    false);
+    const float y = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(y), __float_as_uint(y), false,
+                                                    false);
+    return __uint_as_float(b[0]) + __uint_as_float(b[1]);
+}
+
 // LDS byte address of a __shared__ object.
 template <typename T>
 __device__ __forceinline__ uint32_t lds_addr(const T* p)
