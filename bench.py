@@ -142,7 +142,7 @@ def points_measure(args, eot, W, dev, iters=4):
 def highd_measure(args, eot, W, dev, iters=5):
     """Mixed HVP pass on n = m = 65536 unit-norm embeddings in R^64, cost recomputed
     on the fly with the x . y contraction on the matrix cores (BF16 hi/lo, three
-    MFMAs per 16 dimensions)."""
+    MFMAs per 32 dimensions)."""
     import torch
     p = W.embedding_problem(1 << 16, d=64)
     n, m, d = p.n, p.m, 64

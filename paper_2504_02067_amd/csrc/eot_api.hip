@@ -158,11 +158,11 @@ void carve(Arena& ar, Ctx& x, int op)
 {
     const int64_t n = x.n, m = x.m;
     if (x.cost.kind == EOT_COST_SQEUCLID_POINTS && x.cost.d > 3) {
-        const size_t d = (size_t)x.cost.d;
-        x.hd.xh = ar.take<uint16_t>((size_t)n * d);
-        x.hd.xl = ar.take<uint16_t>((size_t)n * d);
-        x.hd.yh = ar.take<uint16_t>((size_t)m * d);
-        x.hd.yl = ar.take<uint16_t>((size_t)m * d);
+        const size_t dp = (size_t)hd_padded_dim(x.cost.d);
+        x.hd.xh = ar.take<uint16_t>((size_t)n * dp);
+        x.hd.xl = ar.take<uint16_t>((size_t)n * dp);
+        x.hd.yh = ar.take<uint16_t>((size_t)m * dp);
+        x.hd.yl = ar.take<uint16_t>((size_t)m * dp);
         x.hd.xx = ar.take<float>(n);
         x.hd.yy = ar.take<float>(m);
         x.hd.rt = ar.take<float>((size_t)4 * x.hd.npad);

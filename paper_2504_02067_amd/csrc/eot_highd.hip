@@ -2,23 +2,25 @@
 // C_ij = |x_i - y_j|^2 / s recomputed on the fly as |x_i|^2 + |y_j|^2 -
 // 2 x_i . y_j, with the x . y contraction on the matrix cores. Three kernels:
 //
-//  * k_pass_hd_mx (mixed precision, every sum except cost-weighted ones): FP32
-//    coordinates split once per call as x = xh + xl (xh = bf16(x), xl =
-//    bf16(x - xh)); x . y ~ xh.yh + xh.yl + xl.yh, three
-//    v_mfma_f32_32x32x16_bf16 per 16 dimensions with FP32 accumulation (the
-//    dropped xl.yl term is ~2^-16 relative). Per-pass tables hold the rows' and
-//    columns' exponent parts; column operands are copied global -> LDS by DMA,
-//    double-buffered. Details at the kernel.
+//  * k_pass_hd_mx16 (mixed precision, every sum except cost-weighted ones):
+//    FP32 coordinates split once per call as x = xh + xl (xh = bf16(x), xl =
+//    bf16(x - xh)), stored zero-padded to whole 32-dimension chunks;
+//    x . y ~ xh.yh + xh.yl + xl.yh, three v_mfma_f32_16x16x32_bf16 per chunk
+//    with FP32 accumulation (the dropped xl.yl term is ~2^-16 relative).
+//    Per-pass tables hold the rows' and columns' exponent parts; column
+//    operands are copied global -> LDS by DMA, double-buffered. Details at the
+//    kernel.
 //  * k_pass_hd_f64 (FP64 mode and row maxima): x . y from
 //    v_mfma_f64_16x16x4_f64, norms and exp in FP64.
 //  * k_pass_hd (the mixed cost-weighted sums, and the fallback when a point
 //    array is not 16-byte aligned): the 32 x 32 BF16 hi/lo products staged per
 //    step in mixed mode, |x - y|^2 per entry in FP64 (difference form) in FP64.
 //
-// Lane layout of the 32 x 32 BF16 MFMA result (checked on the target): lane l
-// holds the entries (row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32), r =
-// 0..15; operand A lane l supplies row l % 32, dimensions 8 (l / 32) + 0..7 of
-// each 16-dimension chunk, operand B lane l the same dimensions of column l % 32.
+// Lane layout of the 32 x 32 BF16 MFMA result used by k_pass_hd (checked on the
+// target): lane l holds the entries (row 8 (r / 4) + 4 (l / 32) + r % 4, column
+// l % 32), r = 0..15; operand A lane l supplies row l % 32, dimensions
+// 8 (l / 32) + 0..7 of each 16-dimension chunk, operand B lane l the same
+// dimensions of column l % 32.
 
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -149,7 +151,7 @@ __global__ __launch_bounds__(256) void k_pass_hd(PassArgs A, float* out32)
 #pragma unroll
         for (int kc = 0; kc < kHdMaxD / 16; ++kc) {
             if (kc < kch) {
-                const int64_t off = arow_i * d + kc * 16 + 8 * half;
+                const int64_t off = arow_i * hd_padded_dim(d) + kc * 16 + 8 * half;
                 if (ok) {
                     ah[kc] = *reinterpret_cast<const bf16x8*>(xh + off);
                     al[kc] = *reinterpret_cast<const bf16x8*>(xl + off);
@@ -218,7 +220,7 @@ __global__ __launch_bounds__(256) void k_pass_hd(PassArgs A, float* out32)
                 const int64_t jj = jc + sc_c;
                 bf16x8 h8, l8;
                 if (jj < m) {
-                    const int64_t o = jj * d + sc_q * 8;
+                    const int64_t o = jj * hd_padded_dim(d) + sc_q * 8;
                     h8 = *reinterpret_cast<const bf16x8*>(static_cast<const __bf16*>(A.hd_yh) + o);
                     l8 = *reinterpret_cast<const bf16x8*>(static_cast<const __bf16*>(A.hd_yl) + o);
                 } else {
@@ -405,8 +407,6 @@ __global__ __launch_bounds__(256) void k_pass_hd(PassArgs A, float* out32)
 // part of 2B would move the exponent by at most 2^-24 2B |x . y|, far below
 // the BF16 hi / lo error of xy, and is dropped), and 2^Vl_j multiplies the
 // column weights and the column totals.
-constexpr int kHdBlk = 128;                   // columns per block: 4 steps of 32
-constexpr int kHdBlkSteps = kHdBlk / kHdStep;
 
 __global__ __launch_bounds__(256) void k_hd_grid_max(PassArgs A)
 {
@@ -494,192 +494,21 @@ __global__ __launch_bounds__(256) void k_hd_tables(PassArgs A, int nparts, int h
     }
 }
 
-// The pass. A workgroup owns 128 rows x hd_cols columns; each lane keeps the
-// table values of its 16 result rows in registers. The columns go through LDS
-// in blocks of 128, double-buffered: the next block (BF16 hi / lo operands and
-// the column records) is copied global -> LDS by the DMA path (no registers)
-// while the current one is computed, one barrier per block. A block is stored
-// as 1 KB fragments in the MFMA operand's lane order, so the copy writes
-// linearly and the reads are conflict-free. Within a lane, the 16 entries of a
-// step (column sums) and the tile's steps (row sums) accumulate in FP32; every
-// sum across lanes, waves and tiles is FP64.
-template <int NR, int NC, int MODE2, int KC>
-__global__ __launch_bounds__(256) EOT_HD_OCCUPANCY void k_pass_hd_mx(PassArgs A)
-{
-    static_assert(KC >= 1 && KC * 16 <= kHdMaxD, "KC = d / 16");
-    if (A.skip && *A.skip) return;
-    constexpr bool HVP = MODE2 == R2_HVP;
-    constexpr int NV = HVP ? 4 : 1 + NC;       // per-row register values
-    constexpr int NRA = NR > 0 ? NR : 1, NCA = NC > 0 ? NC : 1;
-    constexpr int d = KC * 16;
-    // [buffer][hi, lo][step][chunk][lane]: 16 bytes each
-    __shared__ __attribute__((aligned(16))) bf16x8 s_b[2][2][kHdBlkSteps][KC][64];
-    __shared__ __attribute__((aligned(16))) float4 s_rec[2][kHdBlk];
-    __shared__ float s_cp[2][NCA][kWaves][kHdBlk];
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int rl = lane & 31, half = lane >> 5;
-    const int64_t n = A.n, m = A.m;
-    const int64_t i0 = (int64_t)blockIdx.y * kHdRows;
-    const int64_t j0 = (int64_t)blockIdx.x * A.hd_cols;
-    const __bf16* yh = static_cast<const __bf16*>(A.hd_yh);
-    const __bf16* yl = static_cast<const __bf16*>(A.hd_yl);
-    const float4* ct = static_cast<const float4*>(A.hd_ct);
-
-    // async copy of block blk into buffer p: each wave copies every 4th fragment
-    auto copy_block = [&](int blk, int p) {
-        const int64_t jb = j0 + (int64_t)blk * kHdBlk;
-#pragma unroll
-        for (int f = wave; f < 2 * kHdBlkSteps * KC; f += kWaves) {
-            const int hl = f / (kHdBlkSteps * KC), st = (f / KC) % kHdBlkSteps, kc = f % KC;
-            int64_t j = jb + st * kHdStep + rl;
-            j = j < m ? j : m - 1;                             // finite filler past m
-            const __bf16* src = (hl ? yl : yh) + j * d + kc * 16 + 8 * half;
-            lds_dma16(src, lds_addr(&s_b[p][hl][st][kc][0]));
-        }
-        if (wave < kHdBlk / 64)                              // records (padded table)
-            lds_dma16(ct + jb + 64 * wave + lane, lds_addr(&s_rec[p][64 * wave]));
-    };
-    copy_block(0, 0);
-
-    // the lane's 16 result rows (4 groups of 4 consecutive rows) from the padded table
-    float rv[NV][16];
-#pragma unroll
-    for (int k = 0; k < NV; ++k)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t i = i0 + wave * 32 + 8 * q + 4 * half;
-            const float4 t4 = *reinterpret_cast<const float4*>(A.hd_rt + k * A.hd_npad + i);
-            rv[k][4 * q + 0] = t4.x;
-            rv[k][4 * q + 1] = t4.y;
-            rv[k][4 * q + 2] = t4.z;
-            rv[k][4 * q + 3] = t4.w;
-        }
-    // MFMA operand A: this wave's 32 rows, every 16-dimension chunk
-    bf16x8 ah[KC], al[KC];
-    {
-        const int64_t ai = i0 + wave * 32 + rl;
-        const __bf16* xh = static_cast<const __bf16*>(A.hd_xh);
-        const __bf16* xl = static_cast<const __bf16*>(A.hd_xl);
-#pragma unroll
-        for (int kc = 0; kc < KC; ++kc) {
-            if (ai < n) {
-                const int64_t off = ai * d + kc * 16 + 8 * half;
-                ah[kc] = *reinterpret_cast<const bf16x8*>(xh + off);
-                al[kc] = *reinterpret_cast<const bf16x8*>(xl + off);
-            } else {
-#pragma unroll
-                for (int t = 0; t < 8; ++t) ah[kc][t] = al[kc][t] = (__bf16)0.0f;
-            }
-        }
-    }
-    const float B2 = (float)(2.0 * kLog2eHd * A.beta);
-    float racc[NRA][16];
-#pragma unroll
-    for (int k = 0; k < NRA; ++k)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) racc[k][r] = 0.0f;
-    __builtin_amdgcn_s_waitcnt(0);             // block 0 has landed in LDS
-    __syncthreads();
-
-    const int64_t cols = m - j0 < A.hd_cols ? m - j0 : A.hd_cols;
-    const int nblk = (int)((cols + kHdBlk - 1) / kHdBlk);
-    for (int blk = 0; blk < nblk; ++blk) {
-        const int p = blk & 1;
-        if (blk + 1 < nblk) copy_block(blk + 1, p ^ 1);
-#pragma unroll 1
-        for (int st = 0; st < kHdBlkSteps; ++st) {
-            const int c = st * kHdStep + rl;                 // this lane's column in the block
-            const float4 rec = s_rec[p][c];
-            f32x16 acc = {};
-#pragma unroll
-            for (int kc = 0; kc < KC; ++kc) {
-                const bf16x8 bh = s_b[p][0][st][kc][lane];
-                const bf16x8 bl = s_b[p][1][st][kc][lane];
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kc], bh, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kc], bl, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[kc], bh, acc, 0, 0, 0);
-            }
-            float cacc[NCA];
-#pragma unroll
-            for (int k = 0; k < NCA; ++k) cacc[k] = 0.0f;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const float e = __builtin_amdgcn_exp2f(fmaf(B2, acc[r], rv[0][r] + rec.x));
-                if constexpr (HVP) {
-                    // rows: e f_j (x_i + sqrt(rho) y_j); columns: R_i e (y_j + sqrt(rho) x_i)
-                    racc[0][r] = fmaf(e, fmaf(rv[1][r], rec.y, rec.z), racc[0][r]);
-                    cacc[0] = fmaf(e, fmaf(rv[2][r], rec.w, rv[3][r]), cacc[0]);
-                } else {
-                    if constexpr (NR >= 1) racc[0][r] = fmaf(e, rec.z, racc[0][r]);
-                    if constexpr (NR >= 2)
-                        racc[1][r] = fmaf(MODE2 == R2_SQUARE ? e * e : e, rec.w, racc[1][r]);
-                    if constexpr (NC >= 1) cacc[0] = fmaf(e, rv[1][r], cacc[0]);
-                    if constexpr (NC >= 2) cacc[1] = fmaf(e, rv[2][r], cacc[1]);
-                }
-            }
-            if constexpr (NC > 0) {
-#pragma unroll
-                for (int k = 0; k < NC; ++k) {
-                    const float tot = pair_total32(cacc[k]);
-                    if (half == 0) s_cp[p][k][wave][c] = tot;
-                }
-            }
-        }
-        __builtin_amdgcn_s_waitcnt(0);         // the next block has landed in LDS
-        __syncthreads();
-        // column totals of this block (the partials of the next block go to the other buffer)
-        if constexpr (NC > 0) {
-            if (tid < kHdBlk) {
-                const int64_t j = j0 + (int64_t)blk * kHdBlk + tid;
-                if (j < m) {
-                    const double f = (double)s_rec[p][tid].y;
-#pragma unroll
-                    for (int k = 0; k < NC; ++k) {
-                        const double t = ((double)s_cp[p][k][0][tid] + (double)s_cp[p][k][1][tid]) +
-                                         ((double)s_cp[p][k][2][tid] + (double)s_cp[p][k][3][tid]);
-                        if (A.atomic)
-                            atomicAdd(&A.col_part[(int64_t)k * m + j], t * f);
-                        else
-                            A.col_part[((int64_t)k * A.tiles_n + blockIdx.y) * m + j] = t * f;
-                    }
-                }
-            }
-        }
-    }
-
-    // ---- row totals: each half's 32 lanes hold the same 16 rows
-    if constexpr (NR > 0) {
-#pragma unroll
-        for (int k = 0; k < NR; ++k) {
-            double v[16];
-#pragma unroll
-            for (int r = 0; r < 16; ++r) v[r] = (double)racc[k][r];
-            const double tot = half_transpose_sum16(v, lane);
-            if ((lane & 1) == 0) {
-                const int r = (lane & 31) >> 1;
-                const int64_t i = i0 + wave * 32 + 8 * (r / 4) + 4 * half + (r % 4);
-                if (i < n) {
-                    double fac = A.hd_rf[i];
-                    if (k == 1 && MODE2 == R2_SQUARE) fac *= fac;
-                    if (A.atomic)
-                        atomicAdd(&A.row_part[(int64_t)k * n + i], tot * fac);
-                    else
-                        A.row_part[((int64_t)k * A.tiles_m + blockIdx.x) * n + i] = tot * fac;
-                }
-            }
-        }
-    }
-}
-
-// The same pass with v_mfma_f32_16x16x32_bf16 for d = 32, 64 (whole 32-deep
-// chunks): each wave owns two 16-row blocks and takes 16 columns per step, so a
-// lane holds the table values of 8 rows instead of 16 and fewer registers are
-// live. Lane layout (checked on the target): A[i][k] in lane i + 16 (k / 8),
-// element k % 8; B[k][j] in lane j + 16 (k / 8), element k % 8; D[i][j] in lane
-// j + 16 (i / 4), element i % 4. Columns go through LDS in blocks of 64 (4 steps),
-// double-buffered, copied by DMA as 1 KB fragments in operand lane order (the
-// 64 records of a block are one more fragment).
+// The pass, with v_mfma_f32_16x16x32_bf16 over the zero-padded 32-dimension
+// chunks of the BF16 copies (d = 16 .. 64 -> 1 or 2 chunks). A workgroup owns
+// 128 rows x hd_cols columns; each wave owns two 16-row blocks and takes 16
+// columns per step, and each lane keeps the table values of its 8 result rows
+// in registers for the whole tile. Lane layout (checked on the target): A[i][k]
+// in lane i + 16 (k / 8), element k % 8; B[k][j] in lane j + 16 (k / 8), element
+// k % 8; D[i][j] in lane j + 16 (i / 4), element i % 4. The columns go through
+// LDS in blocks of 64 (4 steps), double-buffered: the next block (BF16 operands
+// and the column records) is copied global -> LDS by the DMA path (no
+// registers) while the current one is computed, one barrier per block. A block
+// is stored as 1 KB fragments in the MFMA operand's lane order (the 64 records
+// are one more fragment), so the copy writes linearly and the reads are
+// conflict-free. Within a lane, the 8 entries of a step (column sums) and the
+// tile's steps (row sums) accumulate in FP32; every sum across lanes, waves and
+// tiles is FP64.
 constexpr int kHd16Step = 16;
 constexpr int kHd16Blk = 64;
 constexpr int kHd16Steps = kHd16Blk / kHd16Step;
@@ -1147,12 +976,10 @@ hipError_t launch_hd(const PassArgs& a, int prec, hipStream_t s)
             const unsigned tb = (unsigned)((tw + 255) / 256 < 4096 ? (tw + 255) / 256 : 4096);
             hipLaunchKernelGGL(k_hd_tables, dim3(tb), dim3(256), 0, s, a, nb, MODE2 == R2_HVP ? 1 : 0,
                                NR, NC, MODE2 == R2_SQUARE ? 1 : 0);
-            switch (a.d) {
-            case 16: hipLaunchKernelGGL((k_pass_hd_mx<NR, NC, MODE2, 1>), grid, dim3(256), 0, s, a); break;
-            case 32: hipLaunchKernelGGL((k_pass_hd_mx16<NR, NC, MODE2, 1>), grid, dim3(256), 0, s, a); break;
-            case 48: hipLaunchKernelGGL((k_pass_hd_mx<NR, NC, MODE2, 3>), grid, dim3(256), 0, s, a); break;
-            default: hipLaunchKernelGGL((k_pass_hd_mx16<NR, NC, MODE2, 2>), grid, dim3(256), 0, s, a); break;
-            }
+            if (hd_padded_dim(a.d) == 32)
+                hipLaunchKernelGGL((k_pass_hd_mx16<NR, NC, MODE2, 1>), grid, dim3(256), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_pass_hd_mx16<NR, NC, MODE2, 2>), grid, dim3(256), 0, s, a);
             return hipGetLastError();
         }
     }
@@ -1173,20 +1000,23 @@ hipError_t launch_hd(const PassArgs& a, int prec, hipStream_t s)
     return hipGetLastError();
 }
 
-// BF16 hi / lo parts and squared norm of each of k points (one thread per point)
+// BF16 hi / lo parts (rows of hd_padded_dim(d), zeros beyond d) and squared norm of
+// each of k points (one thread per point)
 __global__ void k_hd_prep(const float* __restrict__ P, int64_t k, int d, __bf16* hi, __bf16* lo,
                           float* sq)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
          i += (int64_t)gridDim.x * blockDim.x) {
+        const int dp = hd_padded_dim(d);
         float s2 = 0.0f;
         for (int t = 0; t < d; ++t) {
             const float v = P[i * d + t];
             const __bf16 h = (__bf16)v;
-            hi[i * d + t] = h;
-            lo[i * d + t] = (__bf16)(v - (float)h);
+            hi[i * dp + t] = h;
+            lo[i * dp + t] = (__bf16)(v - (float)h);
             s2 = fmaf(v, v, s2);
         }
+        for (int t = d; t < dp; ++t) hi[i * dp + t] = lo[i * dp + t] = (__bf16)0.0f;
         sq[i] = s2;
     }
 }

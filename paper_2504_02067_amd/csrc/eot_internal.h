@@ -97,6 +97,9 @@ constexpr int kHdTileRows = 128;
 constexpr int kHdTileCols = 512;
 constexpr int kHdTileColsMax = 2048;
 constexpr int kHdMaxPart = 1024;         // grid-maximum partials of the mixed pass
+// Row stride of the BF16 hi / lo copies of high-dimensional points: d rounded up
+// to whole 32-dimension MFMA chunks (zeros beyond d).
+__host__ __device__ constexpr int hd_padded_dim(int d) { return (d + 31) / 32 * 32; }
 
 inline int64_t tiles_m_of(int64_t m) { return (m + kTileCols - 1) / kTileCols; }
 inline int64_t tiles_n_of(int64_t n, int rb) { return (n + rb - 1) / rb; }
@@ -116,7 +119,7 @@ hipError_t launch_rowmax_hd(const PassArgs& a, double* part, double* out, hipStr
 // BF16 hi / lo split of k points of dimension d (hi = bf16(p), lo = bf16(p - hi))
 // and their squared norms.
 hipError_t launch_hd_prep(const float* P, int64_t k, int d, void* hi, void* lo, float* sq,
-                          hipStream_t s);
+                          hipStream_t s);     // hi / lo rows of hd_padded_dim(d), zero-padded
 
 // ---- merges / epilogues (all FP64) ----------------------------------------
 // out_k[i] = exp(a_i) * sum_t part[k][t][i]   (nr row sums)
