@@ -90,7 +90,7 @@ struct GradVecs {
 };
 
 struct HdVecs {
-    void *xh = nullptr, *xl = nullptr, *yh = nullptr, *yl = nullptr;   // BF16, n x d / m x d
+    void *xh = nullptr, *xl = nullptr, *yh = nullptr, *yl = nullptr;   // BF16, n (m) x hd_padded_dim(d)
     float *xx = nullptr, *yy = nullptr;
     int cols = kHdTileCols;                       // columns per tile
     int64_t npad = 0, mpad = 0;                   // rows / columns padded to whole tiles
@@ -1043,7 +1043,26 @@ eot_status gradient_impl(Ctx& x, double gamma, const double* f, const double* g,
     const double kappa = -w_S * beta;
     if (grad_C) HIPCHK(launch_plan_grad(A, G.ra, G.cb, kappa, grad_C, ldg, x.s));
     const int d = x.cost.d;
-    if (grad_X) {
+    if ((grad_X || grad_Y) && d > 3) {
+        // high-dimensional points: the n x d (m x d) output is the accumulator
+        if (grad_X) {
+            HIPCHK(launch_fill(G.g0, 0.0, n, x.s));
+            HIPCHK(launch_fill(grad_X, 0.0, n * d, x.s));
+            HIPCHK(launch_points_grad_rows_hd(x.cost.X, x.cost.Y, d, n, m, G.u, G.v, beta * cs,
+                                              G.ra, G.cb, kappa * cs, G.g0, grad_X, x.s));
+            HIPCHK(launch_points_grad_finish_hd(x.cost.X, n, d, 2.0 * cs, G.g0, grad_X, x.s));
+            x.passes += 1;
+        }
+        if (grad_Y) {
+            HIPCHK(launch_fill(G.h0, 0.0, m, x.s));
+            HIPCHK(launch_fill(grad_Y, 0.0, m * d, x.s));
+            HIPCHK(launch_points_grad_rows_hd(x.cost.Y, x.cost.X, d, m, n, G.v, G.u, beta * cs,
+                                              G.cb, G.ra, kappa * cs, G.h0, grad_Y, x.s));
+            HIPCHK(launch_points_grad_finish_hd(x.cost.Y, m, d, 2.0 * cs, G.h0, grad_Y, x.s));
+            x.passes += 1;
+        }
+    }
+    if (grad_X && d <= 3) {
         double* acc[4] = {G.g0, G.gy0, G.gy1, G.gy2};
         for (double* p : acc) HIPCHK(launch_fill(p, 0.0, n, x.s));
         HIPCHK(launch_points_grad_rows(x.cost.X, x.cost.Y, d, n, m, G.u, G.v, beta * cs, G.ra,
@@ -1052,7 +1071,7 @@ eot_status gradient_impl(Ctx& x, double gamma, const double* f, const double* g,
                                          grad_X, x.s));
         x.passes += 1;
     }
-    if (grad_Y) {
+    if (grad_Y && d <= 3) {
         double* acc[4] = {G.h0, G.hy0, G.hy1, G.hy2};
         for (double* p : acc) HIPCHK(launch_fill(p, 0.0, m, x.s));
         HIPCHK(launch_points_grad_rows(x.cost.Y, x.cost.X, d, m, n, G.v, G.u, beta * cs, G.cb,
@@ -1433,7 +1452,6 @@ eot_status eot_gradient(const eot_cost* cost, double gamma, const double* f, con
     const bool pts = cost->kind == EOT_COST_SQEUCLID_POINTS;
     if (grad_C && (pts || ldg < cost->m)) return EOT_ERR_INVALID_ARG;
     if ((grad_X || grad_Y) && !pts) return EOT_ERR_INVALID_ARG;
-    if ((grad_X || grad_Y) && cost->d > 3) return EOT_ERR_UNSUPPORTED;
     Ctx x;
     EOTCHK(setup(x, cost, EOT_OP_GRADIENT, prec, ws, ws_bytes, stream));
     return gradient_impl(x, gamma, f, g, w_W, w_S, grad_C, ldg, grad_X, grad_Y, grad_r, grad_c,

@@ -1044,6 +1044,90 @@ __global__ void k_hd_merge_max(const double* part, int tiles, int64_t n, double*
     out[i] = r;
 }
 
+
+// Row sums of the point-cloud cotangent G_ij = P_ij (ra_i + cb_j + kappa D_ij),
+// D_ij = |x_i - y_j|^2 (cost scale folded into beta and kappa), for d = 16 .. 64,
+// in FP64 with the difference form: g0_i += sum_j G_ij and gy_ik += sum_j G_ij
+// y_jk over this block's column slice, accumulated atomically. TPR adjacent
+// lanes share a row, each owning 16 dimensions (zero beyond d); the partial
+// squared distances are summed across them by lane exchanges, so all TPR lanes
+// hold the same D_ij and G_ij, and each accumulates its own 16 dimensions.
+// Column points are staged in LDS as FP64, 64 at a time, dimension-interleaved
+// (dimension 16 q + k at k TPR + q) so that the TPR lanes of a row read
+// adjacent words.
+template <int TPR>
+__global__ __launch_bounds__(256) void k_points_grad_rows_hd(
+    const float* __restrict__ Xr, const float* __restrict__ Yc, int d, int64_t n, int64_t m,
+    const double* __restrict__ u, const double* __restrict__ v, double beta,
+    const double* __restrict__ ra, const double* __restrict__ cb, double kappa, int64_t slice,
+    double* g0, double* gy)
+{
+    constexpr int kCols = 64;
+    constexpr int kDim = 16 * TPR;
+    __shared__ double s_y[kCols][kDim];
+    __shared__ double s_v[kCols], s_b[kCols];
+    const int tid = threadIdx.x;
+    const int q = tid % TPR;
+    const int64_t i = (int64_t)blockIdx.x * (256 / TPR) + tid / TPR;
+    const bool ok = i < n;
+    double xi[16], accy[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int e = 16 * q + k;
+        xi[k] = ok && e < d ? (double)Xr[i * d + e] : 0.0;
+        accy[k] = 0.0;
+    }
+    const double ui = ok ? u[i] : 0.0, ai = ok ? ra[i] : 0.0;
+    double acc0 = 0.0;
+    const int64_t jb = (int64_t)blockIdx.y * slice;
+    const int64_t je = jb + slice < m ? jb + slice : m;
+    for (int64_t j0 = jb; j0 < je; j0 += kCols) {
+        __syncthreads();
+        for (int idx = tid; idx < kCols * kDim; idx += 256) {
+            const int c = idx / kDim, e = idx % kDim;
+            const int64_t j = j0 + c;
+            s_y[c][(e % 16) * TPR + e / 16] = j < je && e < d ? (double)Yc[j * d + e] : 0.0;
+        }
+        if (tid < kCols) {
+            const int64_t j = j0 + tid;
+            s_v[tid] = j < je ? v[j] : -INFINITY;
+            s_b[tid] = j < je ? cb[j] : 0.0;
+        }
+        __syncthreads();
+        const int cnt = (int)(je - j0 < kCols ? je - j0 : kCols);
+        for (int t = 0; t < cnt; ++t) {
+            double d2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const double df = xi[k] - s_y[t][k * TPR + q];
+                d2 = fma(df, df, d2);
+            }
+            if constexpr (TPR >= 2) d2 += __shfl_xor(d2, 1);
+            if constexpr (TPR >= 4) d2 += __shfl_xor(d2, 2);
+            const double P = exp(fma(-beta, d2, ui + s_v[t]));
+            const double Gv = P * fma(kappa, d2, ai + s_b[t]);
+            acc0 += Gv;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) accy[k] = fma(Gv, s_y[t][k * TPR + q], accy[k]);
+        }
+    }
+    if (!ok) return;
+    if (q == 0) atomicAdd(&g0[i], acc0);
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        if (16 * q + k < d) atomicAdd(&gy[i * d + 16 * q + k], accy[k]);
+}
+
+// out_ik = two_over_s (x_ik g0_i - out_ik) in place, row-major n x d.
+__global__ void k_points_grad_finish_hd(const float* X, int64_t n, int d, double two_over_s,
+                                        const double* g0, double* out)
+{
+    const int64_t total = n * d;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x)
+        out[idx] = two_over_s * ((double)X[idx] * g0[idx / d] - out[idx]);
+}
+
 }  // namespace
 
 bool is_high_d(const PassArgs& a) { return a.kind == EOT_COST_SQEUCLID_POINTS && a.d > 3; }
@@ -1097,6 +1181,43 @@ hipError_t launch_rowmax_hd(const PassArgs& a, double* part, double* out, hipStr
     else
         hipLaunchKernelGGL(k_hd_merge_max, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s,
                            part, a.tiles_m, a.n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_points_grad_rows_hd(const float* Xr, const float* Yc, int d, int64_t n,
+                                      int64_t m, const double* u, const double* v, double beta,
+                                      const double* ra, const double* cb, double kappa, double* g0,
+                                      double* gy, hipStream_t s)
+{
+    if (d < 4 || d > kHdMaxD) return hipErrorInvalidValue;
+    const int tpr = d <= 16 ? 1 : d <= 32 ? 2 : 4;
+    const int64_t rows = 256 / tpr;
+    const int64_t bx = (n + rows - 1) / rows;
+    const int64_t col_blocks = (m + 63) / 64;
+    int64_t by = (4096 + bx - 1) / bx;                 // aim at >= 4096 workgroups
+    by = by < 1 ? 1 : (by > col_blocks ? col_blocks : by);
+    const int64_t slice = ((m + by - 1) / by + 63) / 64 * 64;
+    by = (m + slice - 1) / slice;
+    dim3 grid((unsigned)bx, (unsigned)by);
+    if (tpr == 1)
+        hipLaunchKernelGGL((k_points_grad_rows_hd<1>), grid, dim3(256), 0, s, Xr, Yc, d, n, m, u, v,
+                           beta, ra, cb, kappa, slice, g0, gy);
+    else if (tpr == 2)
+        hipLaunchKernelGGL((k_points_grad_rows_hd<2>), grid, dim3(256), 0, s, Xr, Yc, d, n, m, u, v,
+                           beta, ra, cb, kappa, slice, g0, gy);
+    else
+        hipLaunchKernelGGL((k_points_grad_rows_hd<4>), grid, dim3(256), 0, s, Xr, Yc, d, n, m, u, v,
+                           beta, ra, cb, kappa, slice, g0, gy);
+    return hipGetLastError();
+}
+
+hipError_t launch_points_grad_finish_hd(const float* X, int64_t n, int d, double two_over_s,
+                                        const double* g0, double* out, hipStream_t s)
+{
+    const int64_t total = n * d;
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_points_grad_finish_hd, dim3((unsigned)blocks), dim3(256), 0, s, X, n, d,
+                       two_over_s, g0, out);
     return hipGetLastError();
 }
 

@@ -206,6 +206,14 @@ hipError_t launch_points_grad_rows(const float* Xr, const float* Yc, int d, int6
 hipError_t launch_points_grad_finish(const float* X, int64_t n, int d, double two_over_s,
                                      const double* g0, const double* gy0, const double* gy1,
                                      const double* gy2, double* out, hipStream_t s);
+// The same for d = 16 .. 64: gy is row-major n x d (pre-zeroed, like g0), and the
+// finish turns it into the gradient in place.
+hipError_t launch_points_grad_rows_hd(const float* Xr, const float* Yc, int d, int64_t n,
+                                      int64_t m, const double* u, const double* v, double beta,
+                                      const double* ra, const double* cb, double kappa, double* g0,
+                                      double* gy, hipStream_t s);
+hipError_t launch_points_grad_finish_hd(const float* X, int64_t n, int d, double two_over_s,
+                                        const double* g0, double* out, hipStream_t s);
 
 // CG building blocks (state lives in device scalars `sc`).
 struct CgScalars {

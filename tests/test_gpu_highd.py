@@ -14,6 +14,7 @@ import pytest
 import torch
 
 import oracle as O
+from oracle import gradients as OG
 from paper_2504_02067_amd import eot
 from paper_2504_02067_amd import workloads as W
 
@@ -65,24 +66,97 @@ def test_highd_marginals_parity(d, n, m, prec):
     np.testing.assert_allclose(host(out["s"]), O.row_square_sum(C, beta, u, v, p.c), rtol=3 * tol, atol=0)
 
 
+@pytest.mark.parametrize("d,n,m", [(16, 130, 517), (32, 400, 600), (48, 257, 129), (64, 333, 1100)])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_highd_hvp_parity(prec):
-    n, m, d, gamma, rho = 400, 600, 32, 0.05, 0.5
+def test_highd_hvp_parity(d, n, m, prec):
+    gamma, rho = 0.05, 0.5
     beta = 1.0 / gamma
-    p, pc, C = cloud(n, m, d, 3)
+    p, pc, C = cloud(n, m, d, 3 + d)
     rng = np.random.default_rng(5)
     u = np.log(p.r) + 0.5 * rng.standard_normal(n)
     v = np.log(p.c) - O.log_col_marginal(C, beta, u, np.zeros(m))
     f, g = u * gamma, v * gamma
     u, v = O.to_log_units(f, g, gamma)
     x = rng.standard_normal(n); y = rng.standard_normal(m)
-    say(f"high-d hvp {prec}")
+    say(f"high-d hvp d={d} n={n} m={m} {prec}")
     Hx, Hy = eot.eot_hvp(pc, gamma, dvec(f), dvec(g), rho, dvec(x), dvec(y), precision=prec)
     Hx_ref, Hy_ref = O.hvp(C, beta, u, v, rho, x, y)
     ax, ay = O.hvp(C, beta, u, v, rho, np.abs(x), np.abs(y))
     tol = 1e-12 if prec == "fp64" else mixed_tol(beta)
     assert np.all(np.abs(host(Hx) - Hx_ref) <= tol * ax + 1e-300)
     assert np.all(np.abs(host(Hy) - Hy_ref) <= tol * ay + 1e-300)
+
+
+@pytest.mark.parametrize("d", [16, 48])
+def test_highd_newton_cg_parity_fp64(d):
+    """NewtonSolve (Alg. 2) on the matrix-core passes: the same rho levels as the
+    oracle and the same direction to CG rounding (the FP64 passes agree with the
+    oracle to 1e-12, so the CG iterates track the oracle's)."""
+    n, m, gamma, eta = 300, 420, 0.05, 0.05
+    beta = 1.0 / gamma
+    p, pc, C = cloud(n, m, d, 60 + d)
+    rng = np.random.default_rng(61 + d)
+    r, c = p.r, p.c
+    u = np.log(r) + 0.5 * rng.standard_normal(n)
+    v = np.log(c) - O.log_col_marginal(C, beta, u, np.zeros(m))
+    f, g = u * gamma, v * gamma
+    u, v = O.to_log_units(f, g, gamma)
+    lr = O.log_row_marginal(C, beta, u, v)
+    R = O.newton_solve(C, beta, u, v, r, c, lr, eta, 0.0)
+    say(f"high-d newton_cg d={d} fp64")
+    out = eot.eot_newton_cg(pc, gamma, dvec(f), dvec(g), dvec(r), dvec(c), eta, 0.0,
+                            precision="fp64")
+    assert out.levels == R.levels and out.rho_out == R.rho
+    scale = np.abs(R.du).max()
+    np.testing.assert_allclose(host(out.dir_f) / gamma, R.du, rtol=0, atol=1e-9 * scale)
+    np.testing.assert_allclose(host(out.dir_g) / gamma, R.dv, rtol=0, atol=1e-9 * scale)
+
+
+def test_highd_newton_cg_mixed_meets_forcing():
+    """Mixed CG on the BF16 hi / lo passes: its direction meets the forcing
+    inequality of Alg. 2 when checked by the oracle in FP64."""
+    n, m, d, gamma, eta = 350, 300, 64, 0.05, 0.1
+    beta = 1.0 / gamma
+    p, pc, C = cloud(n, m, d, 77)
+    rng = np.random.default_rng(78)
+    r, c = p.r, p.c
+    u = np.log(r) + 0.5 * rng.standard_normal(n)
+    v = np.log(c) - O.log_col_marginal(C, beta, u, np.zeros(m))
+    f, g = u * gamma, v * gamma
+    u, v = O.to_log_units(f, g, gamma)
+    lr = O.log_row_marginal(C, beta, u, v)
+    say("high-d newton_cg d=64 mixed")
+    out = eot.eot_newton_cg(pc, gamma, dvec(f), dvec(g), dvec(r), dvec(c), eta, 0.0,
+                            precision="mixed")
+    du = host(out.dir_f) / gamma
+    rP = np.exp(lr)
+    e = O.fr_apply(C, beta, u, v, rP, c, 1.0, du) + (rP - r)
+    assert np.abs(e).sum() <= eta * np.abs(rP - r).sum() * 1.01
+
+
+@pytest.mark.parametrize("d", [16, 32, 48, 64])
+def test_highd_gradient_parity(d):
+    """eot_gradient on high-dimensional points (FP64 row sums of the cotangent,
+    d / 16 lanes per row): dX, dY, dr, dc and S against the oracle's derivative
+    formulas on the dense cost built from the same points, at the GPU potentials.
+    Tolerance 1e-8 of the largest entry: the S part goes through a CG solve to a
+    relative residual of 1e-11."""
+    n, m, gamma = 150, 230, 0.05
+    p, pc, C = cloud(n, m, d, 90 + d)
+    f, g, st = eot.eot_solve(pc, dvec(p.r), dvec(p.c), gamma_init=1.0 / 8.0, gamma_final=gamma,
+                             tol=1e-9, precision="fp64")
+    assert st["status"] == 0
+    say(f"high-d gradient d={d}")
+    out = eot.eot_gradient(pc, gamma, f, g, w_W=0.4, w_S=1.1)
+    u, v = O.to_log_units(host(f), host(g), gamma)
+    G, gr, gc, S, _, _ = OG.vjp(C, 1.0 / gamma, u, v, 0.4, 1.1)
+    gX, gY = OG.points_grad(p.X, p.Y, p.scale, G)
+    assert abs(out["S"] - S) <= 1e-12 * S
+    for key, ref in (("X", gX), ("Y", gY), ("r", gr), ("c", gc)):
+        a = host(out[key])
+        assert a.shape == ref.shape
+        err = np.abs(a - ref).max() / max(np.abs(ref).max(), 1e-300)
+        assert err <= 1e-8, (key, err)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
