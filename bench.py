@@ -246,6 +246,46 @@ def grad_measure(eot, W, dev):
     return res
 
 
+def grid28_measure(eot, W, dev, seeds=3):
+    """Time to 1e-6 marginal error on the 28 x 28 grid (n = m = 784, dense FP32
+    cost, temperature 1/32 -> 1e-4), L1 and squared-L2 costs, mixed against plain
+    FP64; medians over seeds 2000.. (each solve timed after one untimed solve of
+    the same instance). Small problems: the solve is bound by launches and host
+    round trips, not by the passes."""
+    import torch
+    res = {"workload": f"grid28 n=m=784 dense FP32 cost, 3-blob marginals seeds 2000..{2000 + seeds - 1}, "
+                       "temperature 1/32 -> 1e-4, tol 1e-6"}
+    for kind in ("l1", "sqeuclid"):
+        rows = {"mixed": [], "fp64": []}
+        costs = {"mixed": [], "fp64": []}
+        errs = {"mixed": [], "fp64": []}
+        for s in range(seeds):
+            p = W.mnist_like_problem(2000 + s, kind)
+            C = torch.from_numpy(p.C).to(dev)
+            r = torch.from_numpy(p.r).to(dev)
+            c = torch.from_numpy(p.c).to(dev)
+            for prec in ("mixed", "fp64"):
+                o = eot.default_solve_opts(gamma_init=p.gamma_init, gamma_final=p.gamma_final,
+                                           tol=p.tol, precision=prec)
+                eot.eot_solve(C, r, c, opts=o)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, _, st = eot.eot_solve(C, r, c, opts=o)
+                torch.cuda.synchronize()
+                rows[prec].append(time.perf_counter() - t0)
+                costs[prec].append(st["cost"])
+                errs[prec].append(st["err_r"] + st["err_c"])
+        med = {k: float(np.median(v)) for k, v in rows.items()}
+        res[kind] = {"mixed_ms": 1e3 * med["mixed"], "fp64_ms": 1e3 * med["fp64"],
+                     "speedup_mixed_vs_fp64": med["fp64"] / med["mixed"],
+                     "max_err": float(max(errs["mixed"] + errs["fp64"])),
+                     "max_cost_rel_diff": float(max(abs(a - b) / b for a, b in
+                                                    zip(costs["mixed"], costs["fp64"])))}
+        log(f"grid28 {kind}: mixed {res[kind]['mixed_ms']:.1f} ms, fp64 {res[kind]['fp64_ms']:.1f} ms, "
+            f"cost rel diff {res[kind]['max_cost_rel_diff']:.1e}")
+    return res
+
+
 def batch_measure(args, eot, W, dev):
     """The ragged batch: 512 grid problems, sides uniform on 16..64 (n = side^2
     in [256, 4096]), integer grid positions as 2-D points with the cost
@@ -317,6 +357,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-points", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-grid28", action="store_true")
     ap.add_argument("--no-sinkhorn", action="store_true")
     ap.add_argument("--sinkhorn-sweeps", type=int, default=2000,
                     help="cap of Sinkhorn sweeps per temperature for the baseline run")
@@ -480,6 +521,8 @@ def main():
     if not args.no_points:
         highd = highd_measure(args, eot, W, dev)
 
+    grid28 = None if (args.no_fp64 or args.no_grid28) else grid28_measure(eot, W, dev)
+
     batch = None
     grad = None
     if not args.no_batch:
@@ -521,6 +564,7 @@ def main():
                         "mixed_newton_steps": st["newton_steps"], "mixed_cg_iters": st["cg_iters"],
                         "fp64_newton_steps": fp64["newton_steps"] if fp64 else None,
                         "fp64_cg_iters": fp64["cg_iters"] if fp64 else None},
+        "time_to_1e6_grid28": grid28,
         "sinkhorn_baseline": sink,
         "kernels": kern,
         "round": rnd,
