@@ -23,9 +23,11 @@
  *    marked "host" point to host memory.
  *  - Scratch memory comes from the caller-provided `ws` (device, 256-byte
  *    aligned) of at least the size eot_workspace_size() reports; the library
- *    calls no hipMalloc. The only memory it takes itself is a small pool of
- *    512-byte pinned host buffers that receive the scalars a call reads back
- *    (one per concurrently running call, reused, never freed).
+ *    calls no hipMalloc. The only memory it takes itself is two small pools
+ *    of pinned host buffers, one per concurrently running call each, reused
+ *    and never freed: 512-byte buffers that receive the scalars a call reads
+ *    back, and 64-byte coherent buffers into which the CG kernels store their
+ *    progress (iterations done, done flag) for the host to pace its launches.
  *  - `stream` is a hipStream_t (NULL = the default stream). eot_marginals
  *    and eot_hvp are asynchronous on it; eot_newton_cg and eot_solve make
  *    host-side decisions and return after their work on `stream` finished.
@@ -37,7 +39,7 @@
  *  - Calls on different streams with different workspaces are independent;
  *    the library keeps no global mutable state apart from the opt-in pass
  *    timer (guarded by a mutex), the tile-height override below (an atomic)
- *    and the pinned-buffer pool (guarded by a mutex).
+ *    and the pinned-buffer pools (guarded by mutexes).
  */
 #ifndef EOT_H
 #define EOT_H

@@ -104,21 +104,32 @@ struct HdVecs {
 // reductions, flags): device -> pinned copies skip the runtime's pageable
 // staging. A process-wide pool of small buffers, leased by a call for its
 // lifetime; buffers are reused and never freed (at most one per concurrently
-// running call). Without pinned memory the copies go to pageable memory.
+// running call). Without pinned memory the copies go to pageable memory. A
+// second pool of coherent buffers holds the CG progress words the kernels
+// store into (see device_pcg).
 constexpr int kPinBytes = 512;
-std::mutex g_pin_mu;
-std::vector<void*>* g_pin_free = nullptr;      // never destroyed: safe at process exit
+constexpr int kMirrorBytes = 64;
+
+struct HostPool {
+    std::mutex mu;
+    std::vector<void*>* free = nullptr;         // never destroyed: safe at process exit
+    unsigned flags;
+    size_t bytes;
+};
+HostPool g_pin_pool{{}, nullptr, hipHostMallocDefault, kPinBytes};
+HostPool g_mirror_pool{{}, nullptr, hipHostMallocCoherent, kMirrorBytes};
 
 struct PinLease {
+    HostPool& pool;
     void* p = nullptr;
-    PinLease()
+    explicit PinLease(HostPool& pl) : pool(pl)
     {
-        std::lock_guard<std::mutex> lk(g_pin_mu);
-        if (!g_pin_free) g_pin_free = new std::vector<void*>();
-        if (!g_pin_free->empty()) {
-            p = g_pin_free->back();
-            g_pin_free->pop_back();
-        } else if (hipHostMalloc(&p, kPinBytes, hipHostMallocDefault) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(pool.mu);
+        if (!pool.free) pool.free = new std::vector<void*>();
+        if (!pool.free->empty()) {
+            p = pool.free->back();
+            pool.free->pop_back();
+        } else if (hipHostMalloc(&p, pool.bytes, pool.flags) != hipSuccess) {
             p = nullptr;
             (void)hipGetLastError();            // do not leave the failure for a later check
         }
@@ -126,15 +137,16 @@ struct PinLease {
     ~PinLease()
     {
         if (!p) return;
-        std::lock_guard<std::mutex> lk(g_pin_mu);
-        g_pin_free->push_back(p);
+        std::lock_guard<std::mutex> lk(pool.mu);
+        pool.free->push_back(p);
     }
     PinLease(const PinLease&) = delete;
     PinLease& operator=(const PinLease&) = delete;
 };
 
 struct Ctx {
-    PinLease pin;
+    PinLease pin{g_pin_pool};
+    PinLease mirror{g_mirror_pool};
     eot_cost cost{};
     int64_t n = 0, m = 0;
     int tiles_m = 0, tiles_n = 0;
@@ -460,18 +472,25 @@ struct NewtonResult {
 // F_r(rho) p = r(P) o p - rho P ((P^T p) / c) and Jacobi preconditioner
 // M_i = r(P)_i - rho s_i; r(P) in V.rP, log r(P) in lr (also the row shift).
 // Solution in V.dtry (with P^T d in V.ptd_try and P (P^T d / c) in V.pcptd_try).
-// The iterations are enqueued in chunks without waiting: each kernel of an
-// iteration returns at once when the device flag sc.done is set (by the
-// iteration that met the stop test, broke down or reached max_cg), so the
-// host reads the scalars once per chunk.
+// The iterations are enqueued without waiting: each kernel of an iteration
+// returns at once when the device flag sc.done is set (by the iteration that
+// met the stop test, broke down or reached max_cg). The host paces its launches
+// by progress words the kernels store into pinned host memory and reads the
+// scalars once at the end (without pinned memory: in chunks of 4, 8, 16, 32
+// iterations with a read-back after each).
 eot_status device_pcg(Ctx& x, int prec, const double* u, const double* lr, const double* v,
                       double beta, const double* s, const double* c, double rho, double tol,
                       int max_cg, CgScalars* out)
 {
     NewtonVecs& V = x.nv;
     const int64_t n = x.n, m = x.m;
+    int32_t* mirror = static_cast<int32_t*>(x.mirror.p);
+    if (mirror) {
+        mirror[0] = 0;
+        mirror[1] = 0;
+    }
     HIPCHK(launch_cg_init(V.b, V.rP, s, rho, V.dtry, V.res, V.z, V.p, V.M, V.ptd_try,
-                          V.pcptd_try, n, m, x.sc.red, x.sc.cg, tol, max_cg, x.s));
+                          V.pcptd_try, n, m, x.sc.red, x.sc.cg, tol, max_cg, mirror, x.s));
     PassArgs pa = make_args(x, u, lr, v, beta);        // pass A: column sums of P p
     pa.xw0 = V.p;
     pa.skip = &x.sc.cg->done;
@@ -490,14 +509,15 @@ eot_status device_pcg(Ctx& x, int prec, const double* u, const double* lr, const
         if (small)
             return launch_cg_small(x.sc.row_part, x.rtiles, n, m, lr, V.rP, V.p, rho, V.t, V.q,
                                    V.dtry, V.res, V.z, V.M, V.pcptd_try, V.w, V.ptd_try, x.sc.cg,
-                                   x.s);
+                                   mirror, x.s);
         int nb_pq = 0, nb = 0;
         e = launch_cg_rowstep(x.sc.row_part, x.rtiles, n, lr, V.rP, V.p, rho, V.t, V.q, x.sc.red2,
                               &nb_pq, x.sc.cg, x.s);
         if (e == hipSuccess)
             e = launch_cg_update(x.sc.red2, nb_pq, V.dtry, V.res, V.z, V.p, V.q, V.M, V.t,
                                  V.pcptd_try, V.w, V.ptd_try, n, m, x.sc.red, &nb, x.sc.cg, x.s);
-        if (e == hipSuccess) e = launch_cg_direction(x.sc.red, nb, V.z, V.p, n, x.sc.cg, x.s);
+        if (e == hipSuccess)
+            e = launch_cg_direction(x.sc.red, nb, V.z, V.p, n, x.sc.cg, mirror, x.s);
         return e;
     };
     auto read_scalars = [&]() -> eot_status {
@@ -535,7 +555,45 @@ eot_status device_pcg(Ctx& x, int prec, const double* u, const double* lr, const
         if (graph) (void)hipGraphDestroy(graph);
         EOTCHK(gs);
     }
-    if (!graphed) {
+    if (!graphed && mirror) {
+        // Enqueue while watching the progress words: at most kCgLead iterations
+        // in flight, none once the stop test has passed. At the lead limit the
+        // host spins on the words (no runtime calls, which would contend with
+        // other threads' launches); after kStallUs without progress it asks
+        // the stream, and if that has drained it reads the scalars back
+        // (authoritative) and goes on from there.
+        constexpr int kCgLead = 2;
+        constexpr auto kStall = std::chrono::microseconds(200);
+        const volatile int32_t* hm = mirror;
+        int32_t seen = -1;
+        auto t_seen = std::chrono::steady_clock::now();
+        while (issued < max_cg && !hm[1]) {
+            const int32_t done_it = hm[0];
+            if (issued - done_it >= kCgLead) {
+                const auto now = std::chrono::steady_clock::now();
+                if (done_it != seen) {
+                    seen = done_it;
+                    t_seen = now;
+                    continue;
+                }
+                if (now - t_seen < kStall) {
+                    std::this_thread::yield();
+                    continue;
+                }
+                const hipError_t q = hipStreamQuery(x.s);
+                if (q == hipErrorNotReady) {
+                    t_seen = now;
+                    continue;
+                }
+                if (q != hipSuccess) return EOT_ERR_HIP;
+                EOTCHK(read_scalars());
+                if (h.done) break;
+            }
+            HIPCHK(iteration());
+            ++issued;
+        }
+        EOTCHK(read_scalars());
+    } else if (!graphed) {
         int chunk = 4;
         for (;;) {
             for (int it = 0; it < chunk && issued < max_cg; ++it, ++issued) HIPCHK(iteration());

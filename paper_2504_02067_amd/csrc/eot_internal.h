@@ -223,10 +223,13 @@ struct CgScalars {
     int32_t broke;     // <p, F p> <= 0 or a non-finite step
     int32_t max_iter;
 };
+// `mirror` (nullable, pinned coherent host memory, two int32): the kernels
+// that run the stop test also store {iterations done, done flag} there, so the
+// host can watch the loop's progress without synchronising the stream.
 hipError_t launch_cg_init(const double* b, const double* rP, const double* s, double rho,
                           double* d, double* res, double* z, double* p, double* M, double* ptd,
                           double* pcptd, int64_t n, int64_t m, double* red, CgScalars* sc,
-                          double tol, int32_t max_iter, hipStream_t st);
+                          double tol, int32_t max_iter, int32_t* mirror, hipStream_t st);
 // after pass A (column sums of P p): w = raw column sums, wc = w / c
 hipError_t launch_cg_colstep(const double* part, int tiles, int64_t m, const double* c,
                              double* w, double* wc, const CgScalars* sc, hipStream_t st);
@@ -240,14 +243,15 @@ hipError_t launch_cg_update(const double* red_pq, int nb_pq, double* d, double* 
                             double* pcptd, const double* w, double* ptd, int64_t n, int64_t m,
                             double* red, int* nb, CgScalars* sc, hipStream_t st);
 hipError_t launch_cg_direction(const double* red, int nb, const double* z, double* p,
-                               int64_t n, CgScalars* sc, hipStream_t st);
+                               int64_t n, CgScalars* sc, int32_t* mirror, hipStream_t st);
 // Small problems (n, m <= kCgSmallMax): row step, update, direction and stop
 // test of one CG iteration in a single workgroup launch.
 constexpr int64_t kCgSmallMax = 8192;
 hipError_t launch_cg_small(const double* part, int tiles, int64_t n, int64_t m, const double* a,
                            const double* rP, double* p, double rho, double* t, double* q,
                            double* d, double* res, double* z, const double* M, double* pcptd,
-                           const double* w, double* ptd, CgScalars* sc, hipStream_t s);
+                           const double* w, double* ptd, CgScalars* sc, int32_t* mirror,
+                           hipStream_t s);
 
 
 }  // namespace eot

@@ -903,8 +903,21 @@ __global__ void k_cg_init(const double* b, const double* rP, const double* s, do
 // The CG iteration kernels below all return at once when sc->done is set
 // (converged, broke down or out of iterations), so the host can enqueue a
 // chunk of iterations without waiting for each convergence test.
+
+// Progress of the CG loop for a host that watches it without synchronising:
+// mirror[0] = iterations done, mirror[1] = the done flag, stored into pinned
+// coherent host memory (nullable). Relaxed: the host uses them only to pace
+// its launches and reads the scalars back after the stream has finished, so
+// no ordering is needed (a release at system scope would write back the whole
+// L2 after every iteration).
+__device__ __forceinline__ void cg_publish(int32_t* mirror, int32_t iters, int32_t done)
+{
+    if (!mirror) return;
+    __hip_atomic_store(mirror, iters, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(mirror + 1, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 __global__ void k_cg_init_finish(const double* red, int nb, CgScalars* sc, double tol,
-                                 int32_t max_iter)
+                                 int32_t max_iter, int32_t* mirror)
 {
     __shared__ double s_w[kVecThreads / 64];
     const double rz = sum_partials(red, nb, s_w);
@@ -921,6 +934,7 @@ __global__ void k_cg_init_finish(const double* red, int nb, CgScalars* sc, doubl
         sc->broke = 0;
         sc->max_iter = max_iter;
         sc->done = (l1 <= tol || max_iter <= 0) ? 1 : 0;
+        cg_publish(mirror, 0, sc->done);
     }
 }
 
@@ -1011,7 +1025,7 @@ __global__ void k_cg_direction(const double* red, int nb, const double* z, doubl
 }
 
 // End of one CG iteration: ||res||_1, the iteration count and the stop test.
-__global__ void k_cg_tail(const double* red, int nb, CgScalars* sc)
+__global__ void k_cg_tail(const double* red, int nb, CgScalars* sc, int32_t* mirror)
 {
     if (sc->done) return;
     __shared__ double s_w[kVecThreads / 64];
@@ -1026,6 +1040,7 @@ __global__ void k_cg_tail(const double* red, int nb, CgScalars* sc)
         } else if (l1 <= sc->tol || sc->iters >= sc->max_iter) {
             sc->done = 1;
         }
+        cg_publish(mirror, sc->iters, sc->done);
     }
 }
 
@@ -1052,7 +1067,7 @@ __device__ __forceinline__ double block_sum_small(double v, double* s_w)
 __global__ __launch_bounds__(kCgSmallThreads) void k_cg_small(
     const double* part, int tiles, int64_t n, int64_t m, const double* a, const double* rP,
     double* p, double rho, double* t, double* q, double* d, double* res, double* z,
-    const double* M, double* pcptd, const double* w, double* ptd, CgScalars* sc)
+    const double* M, double* pcptd, const double* w, double* ptd, CgScalars* sc, int32_t* mirror)
 {
     if (sc->done) return;
     __shared__ double s_w[kCgSmallThreads / 64];
@@ -1101,6 +1116,7 @@ __global__ __launch_bounds__(kCgSmallThreads) void k_cg_small(
         } else if (l1 <= sc->tol || sc->iters >= sc->max_iter) {
             sc->done = 1;
         }
+        cg_publish(mirror, sc->iters, sc->done);
     }
 }
 
@@ -1640,13 +1656,13 @@ hipError_t launch_div(const double* x, const double* y, double* out, double sign
 hipError_t launch_cg_init(const double* b, const double* rP, const double* s_, double rho, double* d,
                           double* res, double* z, double* p, double* M, double* ptd, double* pcptd,
                           int64_t n, int64_t m, double* red, CgScalars* sc, double tol,
-                          int32_t max_iter, hipStream_t s)
+                          int32_t max_iter, int32_t* mirror, hipStream_t s)
 {
     const int nb = vec_blocks(n > m ? n : m);
     hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(kVecThreads), 0, s, b, rP, s_, rho, d, res, z, p,
                        M, ptd, pcptd, n, m, red);
     hipLaunchKernelGGL(k_cg_init_finish, dim3(1), dim3(kVecThreads), 0, s, red, nb, sc, tol,
-                       max_iter);
+                       max_iter, mirror);
     return hipGetLastError();
 }
 
@@ -1680,21 +1696,22 @@ hipError_t launch_cg_update(const double* red_pq, int nb_pq, double* d, double* 
 }
 
 hipError_t launch_cg_direction(const double* red, int nb, const double* z, double* p, int64_t n,
-                               CgScalars* sc, hipStream_t s)
+                               CgScalars* sc, int32_t* mirror, hipStream_t s)
 {
     hipLaunchKernelGGL(k_cg_direction, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, red, nb, z, p,
                        n, sc);
-    hipLaunchKernelGGL(k_cg_tail, dim3(1), dim3(kVecThreads), 0, s, red, nb, sc);
+    hipLaunchKernelGGL(k_cg_tail, dim3(1), dim3(kVecThreads), 0, s, red, nb, sc, mirror);
     return hipGetLastError();
 }
 
 hipError_t launch_cg_small(const double* part, int tiles, int64_t n, int64_t m, const double* a,
                            const double* rP, double* p, double rho, double* t, double* q,
                            double* d, double* res, double* z, const double* M, double* pcptd,
-                           const double* w, double* ptd, CgScalars* sc, hipStream_t s)
+                           const double* w, double* ptd, CgScalars* sc, int32_t* mirror,
+                           hipStream_t s)
 {
     hipLaunchKernelGGL(k_cg_small, dim3(1), dim3(kCgSmallThreads), 0, s, part, tiles, n, m, a, rP,
-                       p, rho, t, q, d, res, z, M, pcptd, w, ptd, sc);
+                       p, rho, t, q, d, res, z, M, pcptd, w, ptd, sc, mirror);
     return hipGetLastError();
 }
 
