@@ -264,6 +264,44 @@ def test_full_size_sampled_marginals():
     torch.cuda.empty_cache()
 
 
+def test_full_size_sampled_hvp():
+    """The benchmark's roofline kernel in its launch configuration: the fused HVP
+    on the 16384 x 16384 FP32 cost with the row shift from the marginals and
+    rho = 1, both precisions; Hx on 40 sampled rows and Hy on 40 sampled columns
+    (plus the first and last) recomputed by the oracle from those rows and
+    columns of the cost."""
+    side = 128
+    n = side * side
+    p = W.large_grid_problem(3000)
+    gamma, rho = 1e-3, 1.0
+    beta = 1.0 / gamma
+    rng = np.random.default_rng(4)
+    u = np.log(p.r) + 0.5 * rng.standard_normal(n)
+    v = np.log(p.c) + 0.5 * rng.standard_normal(n)
+    x = rng.standard_normal(n); y = rng.standard_normal(n)
+    say("full-size hvp: cost build")
+    C = W.grid_cost_device(side, "sqeuclid", DEV)
+    rows = np.concatenate([[0, n - 1], np.sort(rng.choice(n, 40, replace=False))])
+    cols = np.concatenate([[0, n - 1], np.sort(rng.choice(n, 40, replace=False))])
+    Crows = W.grid_cost_rows(side, rows)
+    Ccols = W.grid_cost_rows(side, cols).T.copy()        # symmetric grid cost
+    hx_ref, _ = O.hvp(Crows, beta, u[rows], v, rho, x[rows], y)
+    ax, _ = O.hvp(Crows, beta, u[rows], v, rho, np.abs(x[rows]), np.abs(y))
+    _, hy_ref = O.hvp(Ccols, beta, u, v[cols], rho, x, y[cols])
+    _, ay = O.hvp(Ccols, beta, u, v[cols], rho, np.abs(x), np.abs(y[cols]))
+    f, g = dvec(u * gamma), dvec(v * gamma)
+    for prec, tol in (("mixed", 4e-6), ("fp64", 1e-12)):
+        say(f"full-size hvp {prec}")
+        shift = eot.eot_marginals(C, gamma, f, g, want=("log_rP",), precision=prec)["log_rP"]
+        Hx, Hy = eot.eot_hvp(C, gamma, f, g, rho, dvec(x), dvec(y), row_shift=shift,
+                             precision=prec)
+        torch.cuda.synchronize()
+        assert np.all(np.abs(host(Hx)[rows] - hx_ref) <= tol * ax + 1e-300)
+        assert np.all(np.abs(host(Hy)[cols] - hy_ref) <= tol * ay + 1e-300)
+    del C
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("seed", [1000, 1001])
 def test_sinkhorn_projection_parity_fp64(seed):
     """MDOT with the Sinkhorn projection (the paper's baseline) on the same

@@ -195,3 +195,37 @@ def test_points_full_size_sampled_marginals():
         np.testing.assert_allclose(lc[cols], lc_ref, atol=tol, rtol=0)
         m1 = np.exp(lr).sum(); m2 = np.exp(lc).sum()
         assert abs(m1 - m2) <= 10 * tol * m1
+
+
+def test_points_full_size_sampled_hvp():
+    """The point-cloud HVP the benchmark times (n = m = 2^20 in R^3, row shift
+    from the marginals, rho = 1, mixed): Hx on 24 sampled rows and Hy on 24
+    sampled columns recomputed by the oracle from the points."""
+    p = W.point_cloud_problem()
+    n = p.n
+    gamma, rho = 1e-2, 1.0
+    beta = 1.0 / gamma
+    rng = np.random.default_rng(2)
+    pc = eot.PointCloud(torch.from_numpy(p.X).to(DEV), torch.from_numpy(p.Y).to(DEV), p.scale)
+    u = np.log(p.r) + 0.5 * rng.standard_normal(n)
+    v = np.log(p.c) + 0.5 * rng.standard_normal(n)
+    f, g = u * gamma, v * gamma
+    u, v = O.to_log_units(f, g, gamma)
+    x = rng.standard_normal(n); y = rng.standard_normal(n)
+    rows = np.sort(rng.choice(n, 24, replace=False))
+    cols = np.sort(rng.choice(n, 24, replace=False))
+    Crows = O.sqeuclid_points_cost(p.X[rows], p.Y, p.scale)
+    Ccols = O.sqeuclid_points_cost(p.X, p.Y[cols], p.scale)
+    hx_ref, _ = O.hvp(Crows, beta, u[rows], v, rho, x[rows], y)
+    ax, _ = O.hvp(Crows, beta, u[rows], v, rho, np.abs(x[rows]), np.abs(y))
+    _, hy_ref = O.hvp(Ccols, beta, u, v[cols], rho, x, y[cols])
+    _, ay = O.hvp(Ccols, beta, u, v[cols], rho, np.abs(x), np.abs(y[cols]))
+    say("points full-size 2^20 hvp mixed")
+    fd, gd = dvec(f), dvec(g)
+    shift = eot.eot_marginals(pc, gamma, fd, gd, precision="mixed", want=("log_rP",))["log_rP"]
+    Hx, Hy = eot.eot_hvp(pc, gamma, fd, gd, rho, dvec(x), dvec(y), row_shift=shift,
+                         precision="mixed")
+    torch.cuda.synchronize()
+    tol = mixed_tol(beta, max(Crows.max(), Ccols.max()))
+    assert np.all(np.abs(host(Hx)[rows] - hx_ref) <= tol * ax + 1e-300)
+    assert np.all(np.abs(host(Hy)[cols] - hy_ref) <= tol * ay + 1e-300)
