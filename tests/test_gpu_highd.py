@@ -159,6 +159,30 @@ def test_highd_gradient_parity(d):
         assert err <= 1e-8, (key, err)
 
 
+def test_highd_autograd_points():
+    """The torch.autograd wrapper on d = 32 embeddings: dS/dX and dS/dY from
+    backward() against the oracle's formulas at the potentials of the same
+    solve (1e-6 of the largest entry: the gradients come back in FP32)."""
+    from paper_2504_02067_amd import autograd as AG
+    gamma = 0.05
+    p, pc, C = cloud(160, 190, 32, 123)
+    X = torch.from_numpy(p.X).to(DEV).requires_grad_(True)
+    Y = torch.from_numpy(p.Y).to(DEV).requires_grad_(True)
+    say("high-d autograd d=32")
+    Wv, Sv = AG.entropic_ot_points(X, Y, dvec(p.r), dvec(p.c), gamma, p.scale,
+                                   gamma_init=1.0 / 8.0, tol=1e-9)
+    Sv.backward()
+    assert X.grad.shape == X.shape and Y.grad.shape == Y.shape
+    f, g, st = eot.eot_solve(eot.PointCloud(X.detach(), Y.detach(), p.scale), dvec(p.r),
+                             dvec(p.c), gamma_init=1.0 / 8.0, gamma_final=gamma, tol=1e-9)
+    u, v = O.to_log_units(host(f), host(g), gamma)
+    G, *_ = OG.vjp(C, 1.0 / gamma, u, v, 0.0, 1.0)
+    gX, gY = OG.points_grad(p.X, p.Y, p.scale, G)
+    for a, ref in ((host(X.grad), gX), (host(Y.grad), gY)):
+        err = np.abs(a.astype(np.float64) - ref).max() / np.abs(ref).max()
+        assert err <= 1e-6, err
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_highd_solve_parity(prec):
     p, pc, C = cloud(300, 400, 64, 11)
