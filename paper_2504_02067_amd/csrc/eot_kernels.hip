@@ -191,8 +191,10 @@ __device__ __forceinline__ void pass_body(const PassArgs& A)
     __shared__ double s_rr[RB];         // R_i = exp(a_i) 2^Ul (HVP)
     __shared__ double s_wmax[kWaves];
     __shared__ float s_x[DP > 0 ? RB * DP : 1];   // point rows
+    __shared__ __attribute__((aligned(16))) double s_exp[MIXED ? 2 : 128];  // FP64: exp_tab64
 
     const int tid = threadIdx.x;
+    if constexpr (!MIXED) load_exp_table(s_exp);  // read after the prologue's barrier
     const int64_t n = A.n, m = A.m;
     const int rbt = A.rb;                      // rows of this launch's tiles (<= RB, % 8 == 0)
     const int64_t i0 = (int64_t)blockIdx.y * rbt;
@@ -355,7 +357,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& A)
                     cd = (double)c;
                 } else {
                     const double c = getc(rr, q);
-                    e64 = exp(fma(-beta, c, s_A[sb + rr] + vc[ch][q]));
+                    e64 = exp_tab64(fma(-beta, c, s_A[sb + rr] + vc[ch][q]), s_exp);
                     cd = c;
                 }
                 if constexpr (MODE2 == R2_HVP) {

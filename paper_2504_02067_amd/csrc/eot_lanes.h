@@ -156,4 +156,75 @@ __device__ __forceinline__ void lds_dma16(const void* gptr, uint32_t lds_base)
                  : "memory");
 }
 
+// ---- FP64 exp for the streaming passes ---------------------------------------
+// exp(x) by the table-driven method of P. T. P. Tang (ACM TOMS 15(2), 1989):
+// x = (64 q + j) ln2 / 64 + r with |r| <= ln2 / 128, so exp(x) = 2^q 2^(j/64) e^r;
+// 2^(j/64) is a table entry held as a pair T_hi + T_lo (T_hi rounded to double,
+// T_lo the rounded remainder; copied to LDS by the kernel), e^r - 1 = s comes from
+// its Taylor polynomial of degree 5 (truncation below 4e-17 relative), and
+// 2^(j/64) e^r = T_hi + (T_hi s + T_lo) to within 2^-60 relative, leaving one
+// final rounding: the result is within about 0.6 ulp. The reduction uses ln2 / 64
+// split into a rounded part and its remainder. x is clamped to [-1100, 710] by
+// fmin / fmax, so that -inf and very negative x give 0, x above 709.79 (also
+// +inf) gives inf, and NaN (which fmin replaces by 710) gives inf: non-finite
+// either way, as the passes' checks need. |k| = |rint(64 x / ln2)| stays below
+// 2^17, and the table index k & 63 is in range for every input.
+// {T_hi, T_lo} of 2^(j/64), j = 0..63 (from 60-digit decimal arithmetic).
+static __constant__ double kExp2Tab64[128] = {
+    1.0, 0.0, 1.0108892860517005, -1.5234778603368577e-17,
+    1.0218971486541166, 5.109225028973444e-17, 1.0330248790212284, 7.600838874027088e-18,
+    1.0442737824274138, 8.551889705537965e-17, 1.0556451783605572, 1.759325738772092e-18,
+    1.0671404006768237, -7.899853966841582e-17, 1.0787607977571199, -6.656660436056593e-17,
+    1.0905077326652577, -3.046782079812471e-17, 1.102382583307841, 5.2660368715706944e-17,
+    1.1143867425958924, 1.0410278456845571e-16, 1.1265216186082418, 5.165856758795457e-17,
+    1.1387886347566916, 8.912812676025408e-17, 1.1511892299529827, 3.250710218863827e-17,
+    1.1637248587775775, 3.8292048369240935e-17, 1.1763969916502812, 5.554203254218079e-17,
+    1.189207115002721, 3.982015231465646e-17, 1.202156731452703, 6.644981499252301e-17,
+    1.215247359980469, -7.712630692681488e-17, 1.22848053610687, -1.89878163130253e-17,
+    1.241857812073484, 4.658027591836937e-17, 1.255380757024691, -6.7113898212968784e-18,
+    1.2690509571917332, 2.667932131342186e-18, 1.2828700160787783, 1.713594918243561e-17,
+    1.2968395546510096, 2.5382502794888315e-17, 1.3109612115247644, -7.181536135519454e-17,
+    1.3252366431597413, -2.8587312100388614e-17, 1.339667524053303, 8.927282594831732e-17,
+    1.3542555469368927, 7.70094837980299e-17, 1.3690024229745905, 9.593797919118849e-17,
+    1.383909881963832, -6.770511658794786e-17, 1.3989796725383112, -9.614213209051323e-17,
+    1.4142135623730951, -9.667293313452913e-17, 1.42961333839197, -1.2031642489053655e-17,
+    1.4451808069770467, -3.0237581349939873e-17, 1.460917794180647, -5.600377186075216e-17,
+    1.4768261459394993, -3.483994556892796e-17, 1.4929077282912648, 1.4192920154284036e-17,
+    1.5091644275934228, -1.016455327754295e-16, 1.5255981507445384, -1.1024941712342561e-16,
+    1.5422108254079407, 7.949834809697621e-17, 1.559004400237837, 3.7812070533575275e-17,
+    1.5759808451078865, -1.0136916471278304e-17, 1.593142151342267, -1.0094406542311964e-16,
+    1.6104903319492543, 2.4707192569797888e-17, 1.6280274218573478, -6.712955084707084e-17,
+    1.645755478153965, -1.0125679913674773e-16, 1.6636765803267364, 5.8909926967131e-17,
+    1.681792830507429, 8.199010020581497e-17, 1.7001063537185235, -8.0237193703977e-18,
+    1.718619298122478, -1.851380418263111e-17, 1.7373338352737062, 3.164389299292957e-17,
+    1.7562521603732995, 2.960140695448873e-17, 1.7753764925265212, 6.429731796556572e-17,
+    1.7947090750031072, 1.8227458427912087e-17, 1.8142521755003989, -9.969531538920349e-17,
+    1.8340080864093424, 3.283107224245627e-17, 1.8539791250833855, 9.761887490727594e-17,
+    1.8741676341103, -6.122763413004143e-17, 1.8945759815869656, 3.4034035352165297e-17,
+    1.9152065613971474, -1.0619946056195963e-16, 1.9360617934922943, 1.0332385960676326e-16,
+    1.9571441241754002, 8.960767791036668e-17, 1.978456026387951, 4.0388753109278167e-17,
+};
+constexpr double kInvLn2x64 = 92.33248261689366;        // 64 / ln 2
+constexpr double kLn2d64Hi = 0.010830424696249145;       // ln 2 / 64, rounded
+constexpr double kLn2d64Lo = 3.623510646634843e-19;       // ln 2 / 64 - kLn2d64Hi
+
+// s_tab: 128 doubles of LDS, 16-byte aligned.
+__device__ __forceinline__ void load_exp_table(double* s_tab)
+{
+    if (threadIdx.x < 128) s_tab[threadIdx.x] = kExp2Tab64[threadIdx.x];
+}
+
+__device__ __forceinline__ double exp_tab64(double x, const double* s_tab)
+{
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    x = fmax(fmin(x, 710.0), -1100.0);
+    const double kf = __builtin_rint(x * kInvLn2x64);
+    const int k = (int)kf;
+    const double r = fma(-kf, kLn2d64Lo, fma(-kf, kLn2d64Hi, x));
+    const double t = fma(fma(fma(1.0 / 120.0, r, 1.0 / 24.0), r, 1.0 / 6.0), r, 0.5);
+    const double s = fma(r * r, t, r);          // e^r - 1
+    const d2 T = reinterpret_cast<const d2*>(s_tab)[k & 63];
+    return ldexp(T.x + fma(T.x, s, T.y), k >> 6);
+}
+
 }  // namespace eot
