@@ -323,6 +323,25 @@ def batch_measure(args, eot, W, dev):
     return res
 
 
+def highd_only(eot, W, dev, iters=5):
+    """The high-dimensional mixed HVP of highd_measure alone (one warm-up pass,
+    then `iters` passes), for counter runs."""
+    import torch
+    p = W.embedding_problem(1 << 16, d=64)
+    pc = eot.PointCloud(torch.from_numpy(p.X).to(dev), torch.from_numpy(p.Y).to(dev), p.scale)
+    gamma = 1e-2
+    rng = np.random.default_rng(1)
+    f = torch.from_numpy(gamma * (np.log(p.r) + 0.5 * rng.standard_normal(p.n))).to(dev)
+    g = torch.from_numpy(gamma * (np.log(p.c) + 0.5 * rng.standard_normal(p.m))).to(dev)
+    x = torch.from_numpy(rng.standard_normal(p.n)).to(dev)
+    y = torch.from_numpy(rng.standard_normal(p.m)).to(dev)
+    shift = eot.eot_marginals(pc, gamma, f, g, precision="mixed", want=("log_rP",))["log_rP"]
+    for _ in range(1 + iters):
+        eot.eot_hvp(pc, gamma, f, g, 1.0, x, y, row_shift=shift, precision="mixed")
+    torch.cuda.synchronize()
+    log(f"high-d only: {1 + iters} mixed HVP passes at n = m = {p.n}, d = 64")
+
+
 def kernels_only(args, eot, W, p, C, dev):
     """The mixed HVP pass (as in the full run) and a 1 GiB device-to-device copy
     whose fetched / written bytes calibrate the memory counters."""
@@ -364,6 +383,9 @@ def main():
     ap.add_argument("--batch-workers", type=int, default=8)
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the HVP kernel loop and a 1 GiB device copy (for counter runs)")
+    ap.add_argument("--highd-only", action="store_true",
+                    help="only 1 + 5 mixed high-dimensional HVP passes (n = m = 65536, d = 64; "
+                         "for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the library has no "
@@ -374,6 +396,9 @@ def main():
     from paper_2504_02067_amd import eot, workloads as W
 
     dev = torch.device("cuda:0")
+    if args.highd_only:
+        highd_only(eot, W, dev)
+        return
     side = 128
     p = W.large_grid_problem(args.seed)
     n = m = p.n
