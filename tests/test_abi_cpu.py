@@ -170,3 +170,41 @@ def test_rows_per_tile_override_validation(L):
         assert L.eot_workspace_size(eot.EOT_OP_SOLVE, ctypes.byref(c), 0, ctypes.byref(sz)) == 0
         sizes.append(sz.value)
     assert sizes[0] > sizes[1]          # 8-row tiles need more column partials
+
+
+def test_batched_validation(L):
+    """eot_solve_batched / eot_workspace_size_batched reject bad arguments before
+    touching any device memory (the pointers below are never dereferenced)."""
+    from paper_2504_02067_amd import eot
+    p = ctypes.c_void_p(4096)
+    cost = eot.eot_cost(kind=0, d=0, n=16, m=24, ldc=24, C=p, X=None, Y=None, scale=0.0)
+    probs = (eot.eot_batch_problem * 2)()
+    for k in range(2):
+        probs[k] = eot.eot_batch_problem(cost=cost, r=p, c=p, f=p, g=p)
+    o = eot.eot_solve_opts()
+    L.eot_solve_opts_default(ctypes.byref(o))
+    stats = (eot.eot_solve_stats * 2)()
+    status = (ctypes.c_int32 * 2)()
+    sz = ctypes.c_size_t(0)
+    assert L.eot_workspace_size_batched(2, probs, 4, ctypes.byref(sz)) == eot.EOT_OK
+    assert sz.value > 0
+    # more workers never need less workspace
+    sz1 = ctypes.c_size_t(0)
+    assert L.eot_workspace_size_batched(2, probs, 1, ctypes.byref(sz1)) == eot.EOT_OK
+    assert sz.value >= sz1.value
+
+    def solve(nprob=2, pr=probs, workers=4, ws=p, nbytes=1 << 40):
+        return L.eot_solve_batched(nprob, pr, ctypes.byref(o), workers, stats, status, ws,
+                                   nbytes, None)
+
+    assert solve(nprob=0) == eot.EOT_ERR_INVALID_ARG
+    assert solve(workers=0) == eot.EOT_ERR_INVALID_ARG
+    assert solve(pr=None) == eot.EOT_ERR_INVALID_ARG
+    assert solve(ws=None) == eot.EOT_ERR_WORKSPACE
+    assert solve(nbytes=16) == eot.EOT_ERR_WORKSPACE
+    probs[1].r = None
+    assert solve() == eot.EOT_ERR_INVALID_ARG
+    probs[1].r = p
+    probs[1].cost.n = 0
+    assert solve() == eot.EOT_ERR_INVALID_ARG
+    assert L.eot_workspace_size_batched(2, probs, 4, ctypes.byref(sz)) == eot.EOT_ERR_INVALID_ARG
