@@ -87,6 +87,41 @@ def test_highd_hvp_parity(d, n, m, prec):
     assert np.all(np.abs(host(Hy) - Hy_ref) <= tol * ay + 1e-300)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_highd_unaligned_points_parity(prec):
+    """Y as an element-offset view (4 bytes past a 16-byte boundary): the FP64
+    pass and the FP64 row maxima, which read Y in 16-byte vectors, take the
+    per-entry kernel instead; marginals (with the row shift) and the HVP against
+    the oracle."""
+    n, m, d, gamma, rho = 200, 333, 48, 0.05, 0.7
+    beta = 1.0 / gamma
+    p = W.embedding_problem(n, m, d, 55)
+    X = torch.from_numpy(p.X).to(DEV)
+    buf = torch.empty(m * d + 1, dtype=torch.float32, device=DEV)
+    Y = buf[1:].view(m, d)
+    Y.copy_(torch.from_numpy(p.Y))
+    assert Y.data_ptr() % 16 == 4
+    pc = eot.PointCloud(X, Y, p.scale)
+    C = O.sqeuclid_points_cost(p.X, p.Y, p.scale)
+    rng = np.random.default_rng(56)
+    u = np.log(p.r) + 0.5 * rng.standard_normal(n)
+    v = np.log(p.c) + 0.5 * rng.standard_normal(m)
+    f, g = u * gamma, v * gamma
+    u, v = O.to_log_units(f, g, gamma)
+    x = rng.standard_normal(n); y = rng.standard_normal(m)
+    say(f"high-d unaligned Y {prec}")
+    out = eot.eot_marginals(pc, gamma, dvec(f), dvec(g), precision=prec)
+    Hx, Hy = eot.eot_hvp(pc, gamma, dvec(f), dvec(g), rho, dvec(x), dvec(y), precision=prec)
+    torch.cuda.synchronize()
+    tol = 1e-12 if prec == "fp64" else mixed_tol(beta)
+    np.testing.assert_allclose(host(out["log_rP"]), O.log_row_marginal(C, beta, u, v), atol=tol, rtol=0)
+    np.testing.assert_allclose(host(out["log_cP"]), O.log_col_marginal(C, beta, u, v), atol=tol, rtol=0)
+    Hx_ref, Hy_ref = O.hvp(C, beta, u, v, rho, x, y)
+    ax, ay = O.hvp(C, beta, u, v, rho, np.abs(x), np.abs(y))
+    assert np.all(np.abs(host(Hx) - Hx_ref) <= tol * ax + 1e-300)
+    assert np.all(np.abs(host(Hy) - Hy_ref) <= tol * ay + 1e-300)
+
+
 @pytest.mark.parametrize("d", [16, 48])
 def test_highd_newton_cg_parity_fp64(d):
     """NewtonSolve (Alg. 2) on the matrix-core passes: the same rho levels as the
