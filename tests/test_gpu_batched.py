@@ -93,6 +93,29 @@ def test_batched_mixed_kinds_and_failure_isolation():
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batched_high_dimensional_points(prec):
+    """High-dimensional clouds (d = 16 .. 64, matrix-core passes) next to a dense
+    cost in one batch: each problem's potentials are bitwise those of its own
+    solve."""
+    rng = np.random.default_rng(12)
+    items = []
+    for n, m, d, seed in ((150, 180, 32, 1), (200, 170, 64, 2), (90, 300, 16, 3)):
+        p = W.embedding_problem(n, m, d, seed)
+        pc = eot.PointCloud(torch.from_numpy(p.X).to(DEV), torch.from_numpy(p.Y).to(DEV), p.scale)
+        items.append((pc, dvec(p.r), dvec(p.c)))
+    C = torch.from_numpy(rng.uniform(0, 1, (100, 120)).astype(np.float32)).to(DEV)
+    items.insert(1, (C, dvec(rng.dirichlet(np.ones(100))), dvec(rng.dirichlet(np.ones(120)))))
+    opts = dict(gamma_init=1.0 / 8.0, gamma_final=0.02, tol=1e-6, precision=prec)
+    say(f"batch with high-d clouds ({prec})")
+    outs, stats, status = eot.eot_solve_batched(items, workers=3, **opts)
+    assert all(s == 0 for s in status)
+    for k, (Ck, r, c) in enumerate(items):
+        f, g, st = eot.eot_solve(Ck, r, c, **opts)
+        assert torch.equal(outs[k][0], f) and torch.equal(outs[k][1], g), k
+        assert stats[k]["err_r"] + stats[k]["err_c"] <= 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_cg_graph_replay_matches_direct_launches(prec):
     """CG chunks recorded once as a HIP graph and replayed give bitwise the
     potentials of direct launches: in the batch (worker streams) and for a
