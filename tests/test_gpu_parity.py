@@ -66,10 +66,15 @@ SHAPES = [
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("shift", [False, True])
 def test_marginals_parity(n, m, cdt, prec, shift):
-    if prec == "mixed" and cdt == np.float64:
-        pytest.skip("mixed precision needs an FP32 cost")
     gamma = 0.02
     C, f, g, r, c = random_case(n, m, 11 + n + m, gamma, cdt)
+    if prec == "mixed" and cdt == np.float64:
+        # mixed precision reads an FP32 cost: the library rejects an FP64 one
+        with pytest.raises(eot.EotError) as e:
+            eot.eot_marginals(torch.from_numpy(C).to(DEV), gamma, dvec(f), dvec(g),
+                              precision=prec)
+        assert e.value.status == eot.EOT_ERR_UNSUPPORTED
+        return
     u, v = to_log(f, g, gamma)
     beta = 1.0 / gamma
     lr_ref = O.log_row_marginal(C, beta, u, v)
@@ -118,10 +123,15 @@ def test_marginals_padded_leading_dimension():
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("rho", [1.0, 0.5625, 0.0])
 def test_hvp_parity(n, m, cdt, prec, rho):
-    if prec == "mixed" and cdt == np.float64:
-        pytest.skip("mixed precision needs an FP32 cost")
     gamma = 0.05
     C, f, g, r, c = random_case(n, m, 3 * n + m, gamma, cdt, spread=1.0)
+    if prec == "mixed" and cdt == np.float64:
+        # mixed precision reads an FP32 cost: the library rejects an FP64 one
+        with pytest.raises(eot.EotError) as e:
+            eot.eot_hvp(torch.from_numpy(C).to(DEV), gamma, dvec(f), dvec(g), rho,
+                        dvec(np.ones(n)), dvec(np.ones(m)), precision=prec)
+        assert e.value.status == eot.EOT_ERR_UNSUPPORTED
+        return
     u, v = to_log(f, g, gamma)
     rng = np.random.default_rng(7)
     x = rng.standard_normal(n); y = rng.standard_normal(m)
