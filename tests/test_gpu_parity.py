@@ -182,6 +182,25 @@ def test_newton_cg_parity_fp64(n, m, eta, rho0):
     assert np.abs(e).sum() <= eta * np.abs(rP - r).sum() * (1 + 1e-9)
 
 
+@pytest.mark.parametrize("max_cg", [1, 2, 3])
+def test_newton_cg_iteration_cap_fp64(max_cg):
+    """CG capped at a few iterations: the paced launches stop at the cap, and
+    NewtonSolve's levels, final rho, iteration count, forcing miss and direction
+    match the oracle's under the same cap."""
+    gamma = 0.05
+    C, r, c, u, v, beta = _fixed_instance(200, 150, 5, gamma)
+    lr = O.log_row_marginal(C, beta, u, v)
+    R = O.newton_solve(C, beta, u, v, r, c, lr, 0.05, 0.0, max_cg=max_cg)
+    say(f"newton_cg cap max_cg={max_cg}")
+    out = eot.eot_newton_cg(torch.from_numpy(C).to(DEV), gamma, dvec(u * gamma), dvec(v * gamma),
+                            dvec(r), dvec(c), 0.05, 0.0, max_cg=max_cg, precision="fp64")
+    assert (out.levels, out.rho_out, out.forcing_miss) == (R.levels, R.rho, R.forcing_miss)
+    assert out.cg_iters == R.cg_iters
+    scale = np.abs(R.du).max()
+    np.testing.assert_allclose(host(out.dir_f) / gamma, R.du, rtol=0, atol=1e-9 * scale)
+    np.testing.assert_allclose(host(out.dir_g) / gamma, R.dv, rtol=0, atol=1e-9 * scale)
+
+
 def test_newton_cg_mixed_meets_forcing():
     gamma = 0.02
     C, r, c, u, v, beta = _fixed_instance(700, 900, 21, gamma)
