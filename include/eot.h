@@ -187,6 +187,8 @@ typedef struct {
     int32_t cg_graph;       /* 1: each CG solve records one chunk of 8 iterations as a HIP
                                graph and replays it (streams other than the legacy default
                                stream, pass timing off; otherwise direct launches); 0    */
+    int32_t verbose;        /* 1: one line on stderr after each MDOT step (temperature,
+                               Newton steps, CG iterations, passes, seconds so far); 0  */
 } eot_solve_opts;
 
 typedef struct {

@@ -17,6 +17,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <numeric>
@@ -924,6 +925,7 @@ eot_status solve_impl(Ctx& x, const double* r, const double* c, const eot_solve_
                       double* f_out, double* g_out, eot_solve_stats* st)
 {
     x.cg_graph = o->cg_graph != 0;
+    const auto t_start = std::chrono::steady_clock::now();
     SolveVecs& S = x.sv;
     const int64_t n = x.n, m = x.m;
     const int prec = o->precision;
@@ -977,6 +979,16 @@ eot_status solve_impl(Ctx& x, const double* r, const double* c, const eot_solve_
         st->delta_min_last = dmin;
         st->mdot_steps = t;
         st->final_gamma = 1.0 / beta;
+        if (o->verbose) {
+            const double secs =
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+            std::fprintf(stderr,
+                         "[eot] mdot step %d: temperature %.3e, newton %d, cg %d, passes %lld, "
+                         "%.1f s\n",
+                         t, 1.0 / beta, st->newton_steps, st->cg_iters,
+                         (long long)x.passes, secs);
+            std::fflush(stderr);
+        }
         if (status != EOT_OK || done) break;
         if (o->adaptive_q) {                                               // AdjustSchedule (Sec. 3.3)
             if (dmin > 0.95) q = std::min(2.0, q * q);
@@ -1391,6 +1403,7 @@ void eot_solve_opts_default(eot_solve_opts* o)
     o->verify_fp64 = 1;
     o->projection = EOT_PROJ_TNP;
     o->cg_graph = 0;
+    o->verbose = 0;
 }
 
 eot_status eot_solve(const eot_cost* cost, const double* r, const double* c,

@@ -60,7 +60,7 @@ class eot_solve_opts(ctypes.Structure):
                 ("adaptive_rho0", _c_i32), ("max_cg", _c_i32), ("max_levels", _c_i32),
                 ("max_backtrack", _c_i32), ("max_newton", _c_i32), ("max_sinkhorn", _c_i32),
                 ("max_mdot", _c_i32), ("precision", _c_i32), ("verify_fp64", _c_i32),
-                ("projection", _c_i32), ("cg_graph", _c_i32)]
+                ("projection", _c_i32), ("cg_graph", _c_i32), ("verbose", _c_i32)]
 
 
 class eot_solve_stats(ctypes.Structure):

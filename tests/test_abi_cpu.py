@@ -113,6 +113,7 @@ def test_argument_validation_happens_before_any_device_work(L):
     L.eot_solve_opts_default(ctypes.byref(o))
     assert (o.p, o.q1, o.w_r, o.adaptive_q, o.adaptive_rho0) == (1.5, 2.0, 0.45, 1, 1)
     assert o.max_backtrack == 60 and o.verify_fp64 == 1
+    assert o.cg_graph == 0 and o.verbose == 0
     o.w_r = 0.6
     st = eot.eot_solve_stats()
     assert L.eot_solve(ctypes.byref(c), p, p, ctypes.byref(o), p, p, ctypes.byref(st), p,
