@@ -131,12 +131,29 @@ def points_measure(args, eot, W, dev, iters=4):
     lane_rate = 256 * 4 * 16 * 2.4e9          # CUs x SIMDs x lanes x clock
     peak_eps = lane_rate / cyc
     log(f"points HVP {sec * 1e3:.1f} ms per pass, {elems / sec / 1e12:.3f} T elements/s")
+    # a full solve on the same mixtures at n = m = 65536 (temperature 1/32 -> 1e-4, tol 1e-4)
+    q = W.point_cloud_problem(n=1 << 16)
+    qc = eot.PointCloud(torch.from_numpy(q.X).to(dev), torch.from_numpy(q.Y).to(dev), q.scale)
+    qr, qcm = torch.from_numpy(q.r).to(dev), torch.from_numpy(q.c).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, qs = eot.eot_solve(qc, qr, qcm, gamma_init=q.gamma_init, gamma_final=q.gamma_final,
+                             tol=q.tol, precision="mixed")
+    torch.cuda.synchronize()
+    qt = time.perf_counter() - t0
+    qp = sum(v for k, v in qs.items() if k.startswith("passes_"))
+    log(f"points solve n = m = {q.n}: {qt:.2f} s, {qp} passes, error {qs['err_r'] + qs['err_c']:.1e}")
     return {"workload": f"gmm3d n=m={n} d=3 on-the-fly |x-y|^2/s, mixed HVP pass",
             "kernel_ms": sec * 1e3, "elements_per_s": elems / sec,
             "roofline": {"bound": "alu", "achieved": elems / sec / 1e12,
                          "peak": peak_eps / 1e12, "unit": "T elements/s",
                          "frac": elems / sec / peak_eps,
-                         "valu_cycles_per_element": cyc}}
+                         "valu_cycles_per_element": cyc},
+            "solve": {"workload": f"gmm3d n=m={q.n} d=3, temperature {q.gamma_init} -> "
+                                  f"{q.gamma_final}, tol {q.tol}, mixed",
+                      "seconds": qt, "passes": qp, "newton_steps": qs["newton_steps"],
+                      "cg_iters": qs["cg_iters"], "err": qs["err_r"] + qs["err_c"],
+                      "status": qs["status"]}}
 
 
 def highd_measure(args, eot, W, dev, iters=5):
