@@ -52,6 +52,28 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Trace(ctypes.Structure):
+    _fields_ = [("cap_steps", _i32), ("cap_newton", _i32), ("n_steps", _i32),
+                ("n_newton", _i32),
+                ("beta", _dp), ("eps_d", _dp), ("start_err", _dp), ("delta_min", _dp),
+                ("q", _dp), ("newton", _i32p), ("sweeps", _i32p), ("u_proj", _dp),
+                ("v_proj", _dp),
+                ("step_of", _i32p), ("gnorm", _dp), ("eta", _dp), ("cg_tol", _dp),
+                ("rho0", _dp), ("rho_out", _dp), ("cg_iters", _i32p), ("levels", _i32p),
+                ("alpha", _dp), ("gnorm_next", _dp)]
+
+
+STEP_FIELDS = ("beta", "eps_d", "start_err", "delta_min", "q", "newton", "sweeps")
+NEWTON_FIELDS = ("step_of", "gnorm", "eta", "cg_tol", "rho0", "rho_out", "cg_iters",
+                 "levels", "alpha", "gnorm_next")
+INT_FIELDS = ("newton", "sweeps", "step_of", "cg_iters", "levels")
+
+
+class State(ctypes.Structure):
+    _fields_ = [("t", _i32), ("beta", _f64), ("beta_prev", _f64), ("q", _f64),
+                ("rho0", _f64), ("u", _dp), ("v", _dp), ("u_prev", _dp), ("v_prev", _dp)]
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -82,6 +104,13 @@ def lib():
             "orc_solve": (ctypes.c_int, [_i64, _i64, _dp, _dp, _dp, ctypes.POINTER(Opts),
                                          _dp, _dp, ctypes.POINTER(Stats)]),
             "orc_round": (None, [_i64, _i64, _dp, _f64, _dp, _dp, _dp, _dp, _dp]),
+            "orc_solve_ex": (ctypes.c_int, [_i64, _i64, _dp, _dp, _dp, ctypes.POINTER(Opts),
+                                            _i32, ctypes.POINTER(State),
+                                            ctypes.POINTER(State), ctypes.POINTER(Trace),
+                                            _dp, _dp, ctypes.POINTER(Stats)]),
+            "orc_adjust_schedule": (_f64, [_f64, _f64]),
+            "orc_extrapolate": (None, [_i64, _dp, _dp, _f64, _f64, _f64]),
+            "orc_forcing_eta": (_f64, [_f64, _f64]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -289,3 +318,94 @@ def round_plan(C, beta, u, v, r, c):
     P = np.empty(C.shape)
     lib().orc_round(C.shape[0], C.shape[1], _p(C), beta, _p(u), _p(v), _p(r), _p(c), _p(P))
     return P
+
+
+# ---------------------------------------------------------------- traced solves
+
+def _alloc_trace(n, m, cap_steps, cap_newton, potentials):
+    bufs = {}
+    tr = Trace(cap_steps=cap_steps, cap_newton=cap_newton)
+    for k in STEP_FIELDS:
+        a = np.zeros(cap_steps, dtype=np.int32 if k in INT_FIELDS else np.float64)
+        bufs[k] = a
+        setattr(tr, k, a.ctypes.data_as(_i32p if k in INT_FIELDS else _dp))
+    for k in NEWTON_FIELDS:
+        a = np.zeros(cap_newton, dtype=np.int32 if k in INT_FIELDS else np.float64)
+        bufs[k] = a
+        setattr(tr, k, a.ctypes.data_as(_i32p if k in INT_FIELDS else _dp))
+    if potentials:
+        bufs["u_proj"] = np.zeros((cap_steps, n))
+        bufs["v_proj"] = np.zeros((cap_steps, m))
+        tr.u_proj = _p(bufs["u_proj"])
+        tr.v_proj = _p(bufs["v_proj"])
+    return tr, bufs
+
+
+def _trace_dict(tr, bufs):
+    ns = min(tr.n_steps, tr.cap_steps)
+    nk = min(tr.n_newton, tr.cap_newton)
+    out = {"n_steps": tr.n_steps, "n_newton": tr.n_newton}
+    for k in STEP_FIELDS:
+        out[k] = bufs[k][:ns].copy()
+    for k in NEWTON_FIELDS:
+        out[k] = bufs[k][:nk].copy()
+    if "u_proj" in bufs:
+        out["u_proj"] = bufs["u_proj"][:ns].copy()
+        out["v_proj"] = bufs["v_proj"][:ns].copy()
+    return out
+
+
+def _make_state(n, m, src=None):
+    arrs = {k: np.zeros(n if k in ("u", "u_prev") else m) for k in ("u", "v", "u_prev", "v_prev")}
+    st = State()
+    if src is not None:
+        st.t, st.beta, st.beta_prev = src["t"], src["beta"], src["beta_prev"]
+        st.q, st.rho0 = src["q"], src["rho0"]
+        for k in arrs:
+            arrs[k][:] = src[k]
+    for k, a in arrs.items():
+        setattr(st, k, _p(a))
+    return st, arrs
+
+
+def solve_ex(C, r, c, opts=None, warm=None, resume=None, trace=True, potentials=False,
+             cap_steps=512, cap_newton=4096, **kw):
+    """MDOT + TruncatedNewtonProject with the step trace and the carried state.
+
+    warm: (u0, v0) log-unit start at the first temperature; resume: a state
+    dict from an earlier call. Returns (u, v, stats, trace dict or None, state dict)."""
+    C = _C(C); r = _d(r); c = _d(c)
+    o = opts or default_opts(**kw)
+    n, m = C.shape
+    u = np.zeros(n); v = np.zeros(m)
+    if warm is not None:
+        u[:] = warm[0]; v[:] = warm[1]
+    st = Stats()
+    tr, bufs = (_alloc_trace(n, m, cap_steps, cap_newton, potentials) if trace
+                else (None, None))
+    rs, _keep = _make_state(n, m, resume) if resume is not None else (None, None)
+    so, sarr = _make_state(n, m)
+    status = lib().orc_solve_ex(n, m, _p(C), _p(r), _p(c), ctypes.byref(o),
+                                1 if warm is not None else 0,
+                                ctypes.byref(rs) if rs is not None else None,
+                                ctypes.byref(so), ctypes.byref(tr) if tr is not None else None,
+                                _p(u), _p(v), ctypes.byref(st))
+    d = st.as_dict()
+    d["status"] = int(status)
+    state = {"t": so.t, "beta": so.beta, "beta_prev": so.beta_prev, "q": so.q, "rho0": so.rho0,
+             **{k: a.copy() for k, a in sarr.items()}}
+    return u, v, d, (_trace_dict(tr, bufs) if tr is not None else None), state
+
+
+def adjust_schedule(q, delta_min):
+    return float(lib().orc_adjust_schedule(float(q), float(delta_min)))
+
+
+def extrapolate(z, z_prev, beta_prev, beta, beta_next):
+    z = _d(z).copy(); zp = _d(z_prev).copy()
+    lib().orc_extrapolate(z.size, _p(z), _p(zp), float(beta_prev), float(beta), float(beta_next))
+    return z, zp
+
+
+def forcing_eta(gnorm, eps):
+    return float(lib().orc_forcing_eta(float(gnorm), float(eps)))

@@ -465,10 +465,36 @@ int orc_sinkhorn_project(int64_t n, int64_t m, const double* C, double beta, dou
  * delta_k (eq. delta_k-ratio) compares the norm used to set eta_k (after
  * ChiSinkhorn) with the norm after the row refresh that follows the step (reading).
  * Returns delta_min over the Newton steps (+inf when none ran). */
+/* Forcing term of Alg. 4: eta = max(||grad g||_1, 0.8 eps / ||grad g||_1).
+ * Pinned by: hand-worked values of the printed rule (tests/golden). */
+double orc_forcing_eta(double gnorm, double eps)
+{
+    double b = 0.8 * eps / gnorm;
+    return gnorm > b ? gnorm : b;
+}
+
+static int tnp_impl(int64_t n, int64_t m, const double* C, double beta, double* u,
+                    double* v, const double* r, const double* c, double eps,
+                    const orc_opts* o, double* rho0_io, double* delta_min,
+                    orc_stats* st, orc_trace* tr, int32_t step, double* start_err,
+                    int32_t* sweeps_out);
+
 int orc_tnp(int64_t n, int64_t m, const double* C, double beta, double* u,
             double* v, const double* r, const double* c, double eps,
             const orc_opts* o, double* rho0_io, double* delta_min,
             orc_stats* st)
+{
+    double e0 = 0.0;
+    int32_t sw = 0;
+    return tnp_impl(n, m, C, beta, u, v, r, c, eps, o, rho0_io, delta_min, st, NULL, 0,
+                    &e0, &sw);
+}
+
+static int tnp_impl(int64_t n, int64_t m, const double* C, double beta, double* u,
+                    double* v, const double* r, const double* c, double eps,
+                    const orc_opts* o, double* rho0_io, double* delta_min,
+                    orc_stats* st, orc_trace* tr, int32_t step, double* start_err,
+                    int32_t* sweeps_out)
 {
     double* lr = dalloc(n);
     double* lc = dalloc(m);
@@ -486,10 +512,11 @@ int orc_tnp(int64_t n, int64_t m, const double* C, double beta, double* u,
     st->passes_projection += 2;
 
     double dmin = INFINITY;
-    int32_t k = 0;
+    int32_t k = 0, sweeps = 0;
     for (;;) {
         double gn = 0.0;
         for (int64_t i = 0; i < n; ++i) gn += fabs(r[i] - exp(lr[i]));
+        if (k == 0) *start_err = gn;
         if (gn <= eps) break;                                   /* tolerance met */
         if (k >= o->max_newton) { status = ORC_NOT_CONVERGED; break; }
         int32_t sk = 0;                                         /* ChiSinkhorn */
@@ -497,14 +524,16 @@ int orc_tnp(int64_t n, int64_t m, const double* C, double beta, double* u,
                                   o->max_sinkhorn, &sk);
         st->sinkhorn_iters += sk;
         st->passes_sinkhorn += 2 * (int64_t)sk;
+        sweeps += sk;
         if (s1 != ORC_OK) { status = s1; break; }
         double gk = 0.0;
         for (int64_t i = 0; i < n; ++i) {
             grad[i] = exp(lr[i]) - r[i];
             gk += fabs(grad[i]);
         }
-        double eta = gk > 0.8 * eps / gk ? gk : 0.8 * eps / gk;   /* forcing term */
+        double eta = orc_forcing_eta(gk, eps);                  /* forcing term */
         double rho_out = 0.0;                                   /* Alg. 2, d_v */
+        const double rho_in = *rho0_io;
         int32_t cgk = 0, lev = 0, miss = 0;
         int64_t np = 0;
         int s2 = orc_newton_solve(n, m, C, beta, u, v, r, c, lr, eta, *rho0_io,
@@ -534,11 +563,28 @@ int orc_tnp(int64_t n, int64_t m, const double* C, double beta, double* u,
         for (int64_t i = 0; i < n; ++i) gk1 += fabs(r[i] - exp(lr[i]));
         double dk = (gk - gk1) / ((1.0 - eta) * gk);
         if (dk < dmin) dmin = dk;
+        if (tr) {
+            const int32_t e = tr->n_newton;
+            if (e < tr->cap_newton) {
+                if (tr->step_of) tr->step_of[e] = step;
+                if (tr->gnorm) tr->gnorm[e] = gk;
+                if (tr->eta) tr->eta[e] = eta;
+                if (tr->cg_tol) tr->cg_tol[e] = 0.25 * eta * gk;
+                if (tr->rho0) tr->rho0[e] = rho_in;
+                if (tr->rho_out) tr->rho_out[e] = rho_out;
+                if (tr->cg_iters) tr->cg_iters[e] = cgk;
+                if (tr->levels) tr->levels[e] = lev;
+                if (tr->alpha) tr->alpha[e] = alpha;
+                if (tr->gnorm_next) tr->gnorm_next[e] = gk1;
+            }
+            tr->n_newton = e + 1;
+        }
         ++k;
     }
     /* closing row fit: u <- u + log r - log r(P) */
     for (int64_t i = 0; i < n; ++i) u[i] += log(r[i]) - lr[i];
     *delta_min = dmin;
+    *sweeps_out = sweeps;
     free(lr); free(lc); free(grad); free(du); free(dv); free(zero);
     return status;
 }
@@ -551,25 +597,59 @@ static double entropy(int64_t k, const double* x)
     return h;
 }
 
+/* AdjustSchedule (Sec. 3.3): a projection whose Newton steps all achieved
+ * decrease ratios above 0.95 squares the decay factor (capped at 2), one
+ * with a ratio below 0.8 takes its square root, otherwise q is kept.
+ * Pinned by: hand-worked sequences (tests/golden/alg1_rules.json) and the
+ * set {2^(2^-k)} that every reachable q belongs to. */
+double orc_adjust_schedule(double q, double delta_min)
+{
+    if (delta_min > 0.95) return fmin(2.0, q * q);
+    if (delta_min < 0.8) return sqrt(q);
+    return q;
+}
+
+/* Extrapolation of Alg. 1: z^(t+1) = z^(t) + (beta^(t+1) - beta^(t)) /
+ * (beta^(t) - beta^(t-1)) (z^(t) - z^(t-1)); z_prev becomes z^(t).
+ * Pinned by: exactness on potentials that are affine in beta, and a
+ * separable cost with uniform marginals, whose projected potentials are
+ * affine in beta, so every extrapolated start is already projected. */
+void orc_extrapolate(int64_t k, double* z, double* z_prev, double beta_prev,
+                     double beta, double beta_next)
+{
+    const double ratio = (beta_next - beta) / (beta - beta_prev);
+    for (int64_t i = 0; i < k; ++i) {
+        double zn = z[i] + ratio * (z[i] - z_prev[i]);
+        z_prev[i] = z[i];
+        z[i] = zn;
+    }
+}
+
 /* MDOT (Alg. 1) with AdjustSchedule (Sec. 3.3), asymmetric smoothing
  * (Sec. 3.4) and TruncatedNewtonProject as the Bregman projection.
  *   eps_d = min(H(r), H(c)) / beta^p;   r~ = (1 - w_r eps_d) r + w_r eps_d / n,
  *   c~ likewise with w_c = 1/2 - w_r (and 1/m);
  *   z^(t) <- TNP(z^(t), beta^(t), r~, c~, eps_d / 2);
- *   q <- min(2, q^2) if delta_min > 0.95, sqrt(q) if delta_min < 0.8;
- *   beta^(t+1) = min(q beta^(t), beta_f);
- *   z^(t+1) = z^(t) + (beta^(t+1) - beta^(t)) / (beta^(t) - beta^(t-1)) (z^(t) - z^(t-1)).
+ *   q <- AdjustSchedule(q, delta_min);  beta^(t+1) = min(q beta^(t), beta_f);
+ *   z^(t+1) by the extrapolation above.
  * Readings: at the final temperature eps_d <- min(eps_d, tol/2) so that the
  * error against the unsmoothed marginals ends below tol; the output is the
  * last projected z of Alg. 1 in log units at beta_f; rounding (its last step) is a
- * separate routine (orc_round).
+ * separate routine (orc_round). A warm start replaces the initial
+ * (log r~, log c~) by the given potentials; a resumed solve takes every
+ * carried quantity from the saved state.
  * Pinned by: brute-force assignment as the temperature goes to 0, 2x2
- * closed form, separable costs, strong duality, marginal error <= tol. */
-int orc_solve(int64_t n, int64_t m, const double* C, const double* r,
-              const double* c, const orc_opts* o, double* u, double* v,
-              orc_stats* st)
+ * closed form, separable costs, strong duality, marginal error <= tol; the
+ * trace pins of the schedule (fixed q: beta_i q^k capped at beta_f), the
+ * smoothing (projected marginals equal r~ and c~ within eps_d / 2 at
+ * intermediate temperatures), eps_d, and the warm discounts. */
+int orc_solve_ex(int64_t n, int64_t m, const double* C, const double* r,
+                 const double* c, const orc_opts* o, int32_t warm,
+                 const orc_state* resume, orc_state* state_out, orc_trace* tr,
+                 double* u, double* v, orc_stats* st)
 {
     memset(st, 0, sizeof(*st));
+    if (tr) { tr->n_steps = 0; tr->n_newton = 0; }
     const double beta_f = 1.0 / o->gamma_final;
     const double beta_i = 1.0 / o->gamma_init;
     const double w_c = 0.5 - o->w_r;
@@ -584,8 +664,25 @@ int orc_solve(int64_t n, int64_t m, const double* C, const double* r,
     double beta = beta_i < beta_f ? beta_i : beta_f;
     double q = o->q1;
     double rho0 = 0.0;
-    int status = ORC_OK;
     int32_t t = 1;
+    int fresh = 1;                                                 /* z^(1) still to set */
+    if (resume) {
+        t = resume->t;
+        beta = resume->beta;
+        beta_prev = resume->beta_prev;
+        q = resume->q;
+        rho0 = resume->rho0;
+        memcpy(u, resume->u, (size_t)n * sizeof(double));
+        memcpy(v, resume->v, (size_t)m * sizeof(double));
+        memcpy(zu_prev, resume->u_prev, (size_t)n * sizeof(double));
+        memcpy(zv_prev, resume->v_prev, (size_t)m * sizeof(double));
+        fresh = 0;
+    } else if (warm) {
+        memcpy(zu_prev, u, (size_t)n * sizeof(double));
+        memcpy(zv_prev, v, (size_t)m * sizeof(double));
+        fresh = 0;
+    }
+    int status = ORC_OK;
     int done = 0;
     while (!done) {
         if (t > o->max_mdot) { status = ORC_NOT_CONVERGED; break; }
@@ -596,38 +693,58 @@ int orc_solve(int64_t n, int64_t m, const double* C, const double* r,
             rt[i] = (1.0 - o->w_r * eps_d) * r[i] + o->w_r * eps_d / (double)n;
         for (int64_t j = 0; j < m; ++j)
             ct[j] = (1.0 - w_c * eps_d) * c[j] + w_c * eps_d / (double)m;
-        if (t == 1) {                                              /* initial potentials */
+        if (fresh) {                                               /* initial potentials */
             for (int64_t i = 0; i < n; ++i) u[i] = zu_prev[i] = log(rt[i]);
             for (int64_t j = 0; j < m; ++j) v[j] = zv_prev[j] = log(ct[j]);
+            fresh = 0;
         }
         double dmin = INFINITY;                                    /* projection */
+        double e0 = 0.0;
+        int32_t sweeps = 0;
+        const int32_t newton0 = st->newton_steps;
+        const int32_t sk0 = st->sinkhorn_iters;
         int s = o->projection == 1
                     ? orc_sinkhorn_project(n, m, C, beta, u, v, rt, ct, 0.5 * eps_d, o, st)
-                    : orc_tnp(n, m, C, beta, u, v, rt, ct, 0.5 * eps_d, o, &rho0, &dmin, st);
+                    : tnp_impl(n, m, C, beta, u, v, rt, ct, 0.5 * eps_d, o, &rho0, &dmin, st,
+                               tr, t, &e0, &sweeps);
         st->delta_min_last = dmin;
         st->mdot_steps = t;
         st->final_beta = beta;
+        if (s == ORC_OK && !done && o->adaptive_q) q = orc_adjust_schedule(q, dmin);
+        if (tr) {
+            const int32_t e = tr->n_steps;
+            if (e < tr->cap_steps) {
+                if (tr->beta) tr->beta[e] = beta;
+                if (tr->eps_d) tr->eps_d[e] = eps_d;
+                if (tr->start_err) tr->start_err[e] = e0;
+                if (tr->delta_min) tr->delta_min[e] = dmin;
+                if (tr->q) tr->q[e] = q;
+                if (tr->newton) tr->newton[e] = st->newton_steps - newton0;
+                if (tr->sweeps) tr->sweeps[e] = st->sinkhorn_iters - sk0;
+                if (tr->u_proj) memcpy(tr->u_proj + (size_t)e * n, u, (size_t)n * sizeof(double));
+                if (tr->v_proj) memcpy(tr->v_proj + (size_t)e * m, v, (size_t)m * sizeof(double));
+            }
+            tr->n_steps = e + 1;
+        }
         if (s != ORC_OK) { status = s; break; }
         if (done) break;
-        if (o->adaptive_q) {                                       /* AdjustSchedule */
-            if (dmin > 0.95) q = fmin(2.0, q * q);
-            else if (dmin < 0.8) q = sqrt(q);
-        }
         double beta_next = fmin(q * beta, beta_f);                 /* next temperature */
-        double ratio = (beta_next - beta) / (beta - beta_prev);    /* extrapolation */
-        for (int64_t i = 0; i < n; ++i) {
-            double zn = u[i] + ratio * (u[i] - zu_prev[i]);
-            zu_prev[i] = u[i];
-            u[i] = zn;
-        }
-        for (int64_t j = 0; j < m; ++j) {
-            double zn = v[j] + ratio * (v[j] - zv_prev[j]);
-            zv_prev[j] = v[j];
-            v[j] = zn;
-        }
+        orc_extrapolate(n, u, zu_prev, beta_prev, beta, beta_next);
+        orc_extrapolate(m, v, zv_prev, beta_prev, beta, beta_next);
         beta_prev = beta;
         beta = beta_next;
         ++t;
+    }
+    if (state_out) {
+        state_out->t = t;
+        state_out->beta = beta;
+        state_out->beta_prev = beta_prev;
+        state_out->q = q;
+        state_out->rho0 = rho0;
+        if (state_out->u) memcpy(state_out->u, u, (size_t)n * sizeof(double));
+        if (state_out->v) memcpy(state_out->v, v, (size_t)m * sizeof(double));
+        if (state_out->u_prev) memcpy(state_out->u_prev, zu_prev, (size_t)n * sizeof(double));
+        if (state_out->v_prev) memcpy(state_out->v_prev, zv_prev, (size_t)m * sizeof(double));
     }
     /* Report at the output potentials against the unsmoothed marginals. */
     double* lr = dalloc(n);
@@ -643,6 +760,13 @@ int orc_solve(int64_t n, int64_t m, const double* C, const double* r,
     st->status = status;
     free(lr); free(lc); free(rt); free(ct); free(zu_prev); free(zv_prev);
     return status;
+}
+
+int orc_solve(int64_t n, int64_t m, const double* C, const double* r,
+              const double* c, const orc_opts* o, double* u, double* v,
+              orc_stats* st)
+{
+    return orc_solve_ex(n, m, C, r, c, o, 0, NULL, NULL, NULL, u, v, st);
 }
 
 /* Rounding onto U(r, c) (Altschuler, Weed & Rigollet 2017, Alg. 2; the last

@@ -60,6 +60,50 @@ typedef struct {
     double delta_min_last; /* delta_min of the last projection                 */
 } orc_stats;
 
+/* Record of what Alg. 1 (MDOT) and Alg. 4 (TruncatedNewtonProject)
+ * decided, step by step: test instrumentation, so that the schedule, the
+ * tolerances and the forcing terms can be checked against the paper's rules
+ * and compared with another implementation. Arrays are caller-owned with the
+ * given capacities (any may be NULL); n_steps / n_newton count every step,
+ * also those beyond the capacity, which are not stored. */
+typedef struct {
+    int32_t cap_steps, cap_newton;   /* in                                          */
+    int32_t n_steps, n_newton;       /* out                                         */
+    /* per MDOT step t = 1, 2, ... */
+    double* beta;        /* inverse temperature of the projection                  */
+    double* eps_d;       /* eps_d of Alg. 1 (the projection stops at eps_d / 2)    */
+    double* start_err;   /* ||r~ - r(P)||_1 after the projection's first column fix */
+    double* delta_min;   /* delta_min of the projection (+inf: no Newton step)     */
+    double* q;           /* decay factor after AdjustSchedule at the end of step t */
+    int32_t* newton;     /* Newton steps of the projection                         */
+    int32_t* sweeps;     /* ChiSinkhorn sweeps of the projection                   */
+    double* u_proj;      /* [cap_steps][n]: projected u at step t (log units)      */
+    double* v_proj;      /* [cap_steps][m]                                         */
+    /* per Newton step k = 1, 2, ... over the whole solve */
+    int32_t* step_of;    /* MDOT step it belongs to                                */
+    double* gnorm;       /* ||grad g||_1 after ChiSinkhorn                         */
+    double* eta;         /* forcing term                                           */
+    double* cg_tol;      /* L1 residual tolerance of each CG solve                 */
+    double* rho0;        /* discount NewtonSolve starts from                       */
+    double* rho_out;     /* discount NewtonSolve returns                           */
+    int32_t* cg_iters;   /* CG iterations of the NewtonSolve                       */
+    int32_t* levels;     /* discount levels solved                                 */
+    double* alpha;       /* accepted line-search step                              */
+    double* gnorm_next;  /* ||r~ - r(P)||_1 after the row refresh                  */
+} orc_trace;
+
+/* The state Alg. 1 carries from one temperature to the next, so a solve can
+ * stop after some temperatures and be resumed: the potentials z^(t) that
+ * start projection t (after the extrapolation), the last projected z^(t-1),
+ * the inverse temperatures beta^(t), beta^(t-1) (0 before the first
+ * projection), the decay factor q and the warm discount rho0 for the next
+ * NewtonSolve (App. B). u, u_prev: n, v, v_prev: m, log units, caller-owned. */
+typedef struct {
+    int32_t t;
+    double beta, beta_prev, q, rho0;
+    double *u, *v, *u_prev, *v_prev;
+} orc_state;
+
 /* ---- plan-level definitions (Sec. 2, eqs. lagrangian-closed-form .. hessian) */
 void   orc_log_row_marginal(int64_t n, int64_t m, const double* C, double beta,
                             const double* u, const double* v, double* log_rP);
@@ -116,6 +160,27 @@ int  orc_tnp(int64_t n, int64_t m, const double* C, double beta, double* u,
 int  orc_solve(int64_t n, int64_t m, const double* C, const double* r,
                const double* c, const orc_opts* o, double* u, double* v,
                orc_stats* st);
+/* orc_solve with options: `warm` (0 or 1) starts from the given u, v at the
+ * first temperature instead of (log r~, log c~); `resume` (nullable)
+ * continues from a saved state (u, v ignored on input); `state_out`
+ * (nullable) receives the state at exit (a solve stopped by max_mdot can be
+ * resumed from it); `trace` (nullable) records the steps. */
+int  orc_solve_ex(int64_t n, int64_t m, const double* C, const double* r,
+                  const double* c, const orc_opts* o, int32_t warm,
+                  const orc_state* resume, orc_state* state_out, orc_trace* trace,
+                  double* u, double* v, orc_stats* st);
+
+/* ---- Alg. 1's scalar rules, exported so tests can pin them on their own */
+/* AdjustSchedule (Sec. 3.3): the decay factor after a projection whose
+ * smallest Newton decrease ratio was delta_min. */
+double orc_adjust_schedule(double q, double delta_min);
+/* Warm-start extrapolation of Alg. 1, in place over k entries:
+ * z_next = z + (beta_next - beta) / (beta - beta_prev) (z - z_prev),
+ * z_prev <- z. */
+void orc_extrapolate(int64_t k, double* z, double* z_prev, double beta_prev,
+                     double beta, double beta_next);
+/* Forcing term of Alg. 4 at ||grad g||_1 = gnorm and tolerance eps. */
+double orc_forcing_eta(double gnorm, double eps);
 
 /* ---- rounding onto U(r, c) (Altschuler et al. 2017, Alg. 2) ---------------- */
 void orc_round(int64_t n, int64_t m, const double* C, double beta,
