@@ -102,12 +102,15 @@ struct HdVecs {
 };
 
 // Pinned host staging for the scalars the host driver reads back (CG scalars,
-// reductions, flags): device -> pinned copies skip the runtime's pageable
-// staging. A process-wide pool of small buffers, leased by a call for its
-// lifetime; buffers are reused and never freed (at most one per concurrently
-// running call). Without pinned memory the copies go to pageable memory. A
-// second pool of coherent buffers holds the CG progress words the kernels
-// store into (see device_pcg).
+// reductions, flags). A process-wide pool of small buffers, leased by a call
+// that reads back for its lifetime; buffers are reused and never freed (at
+// most one per concurrently running call). Every device -> host copy of the
+// library goes into such a buffer: a call that cannot lease one fails with
+// EOT_ERR_HIP instead of copying into pageable memory (concurrent pageable
+// copies from several host threads go through the runtime's shared staging
+// path; the batched solver once crashed inside it). A second pool of coherent
+// buffers holds the CG progress words the kernels store into (see
+// device_pcg); without one the CG loop reads its scalars back in chunks.
 constexpr int kPinBytes = 512;
 constexpr int kMirrorBytes = 64;
 
@@ -123,8 +126,12 @@ HostPool g_mirror_pool{{}, nullptr, hipHostMallocCoherent, kMirrorBytes};
 struct PinLease {
     HostPool& pool;
     void* p = nullptr;
-    explicit PinLease(HostPool& pl) : pool(pl)
+    explicit PinLease(HostPool& pl) : pool(pl) {}
+    // Takes a buffer from the pool (allocating one if the pool is empty); p
+    // stays null if that fails.
+    void acquire()
     {
+        if (p) return;
         std::lock_guard<std::mutex> lk(pool.mu);
         if (!pool.free) pool.free = new std::vector<void*>();
         if (!pool.free->empty()) {
@@ -135,6 +142,9 @@ struct PinLease {
             (void)hipGetLastError();            // do not leave the failure for a later check
         }
     }
+    // After a failed wait a copy into the buffer may still be in flight: the
+    // buffer is dropped (never returned to the pool) so no later call reuses it.
+    void discard() { p = nullptr; }
     ~PinLease()
     {
         if (!p) return;
@@ -290,6 +300,8 @@ void layout(Ctx& x)
     x.ctiles = x.atomic ? 1 : x.tiles_n;
 }
 
+eot_status clear_flags(Ctx& x);
+
 eot_status setup(Ctx& x, const eot_cost* cost, int op, int prec, void* ws, size_t ws_bytes,
                  void* stream)
 {
@@ -310,7 +322,13 @@ eot_status setup(Ctx& x, const eot_cost* cost, int op, int prec, void* ws, size_
     ar.cap = ws_bytes;
     ar.dry = false;
     carve(ar, x, op);
-    HIPCHK(hipMemsetAsync(x.sc.flags, 0, 16 * sizeof(int32_t), x.s));
+    if (op == EOT_OP_NEWTON_CG || op == EOT_OP_SOLVE || op == EOT_OP_GRADIENT ||
+        op == EOT_OP_ROUND) {                   // host read-backs: pinned buffers
+        x.pin.acquire();
+        if (!x.pin.p) return EOT_ERR_HIP;
+        x.mirror.acquire();
+    }
+    EOTCHK(clear_flags(x));
     if (x.hd.xh) {
         HIPCHK(launch_hd_prep(x.cost.X, x.n, x.cost.d, x.hd.xh, x.hd.xl, x.hd.xx, x.s));
         HIPCHK(launch_hd_prep(x.cost.Y, x.m, x.cost.d, x.hd.yh, x.hd.yl, x.hd.yy, x.s));
@@ -372,19 +390,18 @@ hipError_t run_pass(Ctx& x, const PassArgs& A, int prec, int nr, int nc, int mod
     return launch_pass(A, prec, nr, nc, mode2, x.s);
 }
 
-// Read `k` device doubles back to the host (waits for the stream).
-// Device -> host copy of `bytes` bytes and a wait on the stream (through the
-// call's pinned buffer when it has one and the data fit).
+// Device -> host copy of `bytes` bytes through the call's pinned buffer and a
+// wait on the stream. Every return after a queued copy has waited for it (or
+// dropped the buffer), so no copy lands in memory the caller no longer owns.
 eot_status fetch_bytes(Ctx& x, const void* d, void* h, size_t bytes)
 {
-    if (x.pin.p && bytes <= (size_t)kPinBytes) {
-        HIPCHK(hipMemcpyAsync(x.pin.p, d, bytes, hipMemcpyDeviceToHost, x.s));
-        HIPCHK(hipStreamSynchronize(x.s));
-        std::memcpy(h, x.pin.p, bytes);
-        return EOT_OK;
+    if (!x.pin.p || bytes > (size_t)kPinBytes) return EOT_ERR_HIP;
+    HIPCHK(hipMemcpyAsync(x.pin.p, d, bytes, hipMemcpyDeviceToHost, x.s));
+    if (hipStreamSynchronize(x.s) != hipSuccess) {
+        x.pin.discard();
+        return EOT_ERR_HIP;
     }
-    HIPCHK(hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, x.s));
-    HIPCHK(hipStreamSynchronize(x.s));
+    std::memcpy(h, x.pin.p, bytes);
     return EOT_OK;
 }
 
@@ -398,9 +415,11 @@ eot_status fetch_flags(Ctx& x, int32_t* h)
     return fetch_bytes(x, x.sc.flags, h, sizeof(int32_t) * 2);
 }
 
+// The 16 int32 flags are cleared by a fill kernel (8 doubles of +0.0 are the
+// same 64 zero bytes), not a memset node, so callers may capture the calls.
 eot_status clear_flags(Ctx& x)
 {
-    HIPCHK(hipMemsetAsync(x.sc.flags, 0, 16 * sizeof(int32_t), x.s));
+    HIPCHK(launch_fill(reinterpret_cast<double*>(x.sc.flags), 0.0, 8, x.s));
     return EOT_OK;
 }
 
@@ -711,18 +730,20 @@ eot_status refresh(Ctx& x, int prec, double beta, const double* shift_guess, Sol
     int nb = 0;
     HIPCHK(launch_reduce(RED_L1_DIFF_EXP, S.rt, S.lr, x.n, x.sc.red, &nb, x.s));
     HIPCHK(launch_finish_sum(x.sc.red, nb, x.sc.scal, x.s));
-    if (x.pin.p) {
-        char* pb = static_cast<char*>(x.pin.p);
-        HIPCHK(hipMemcpyAsync(pb, x.sc.flags, sizeof(fl), hipMemcpyDeviceToHost, x.s));
-        HIPCHK(hipMemcpyAsync(pb + 64, x.sc.scal, sizeof(double), hipMemcpyDeviceToHost, x.s));
-        HIPCHK(hipStreamSynchronize(x.s));
-        std::memcpy(fl, pb, sizeof(fl));
-        std::memcpy(gn_out, pb + 64, sizeof(double));
-    } else {
-        HIPCHK(hipMemcpyAsync(fl, x.sc.flags, sizeof(fl), hipMemcpyDeviceToHost, x.s));
-        HIPCHK(hipMemcpyAsync(gn_out, x.sc.scal, sizeof(double), hipMemcpyDeviceToHost, x.s));
-        HIPCHK(hipStreamSynchronize(x.s));
+    if (!x.pin.p) return EOT_ERR_HIP;
+    char* pb = static_cast<char*>(x.pin.p);
+    const hipError_t e1 = hipMemcpyAsync(pb, x.sc.flags, sizeof(fl), hipMemcpyDeviceToHost, x.s);
+    const hipError_t e2 =
+        e1 == hipSuccess ? hipMemcpyAsync(pb + 64, x.sc.scal, sizeof(double),
+                                          hipMemcpyDeviceToHost, x.s)
+                         : e1;
+    if (hipStreamSynchronize(x.s) != hipSuccess) {       // wait even when a copy failed
+        x.pin.discard();
+        return EOT_ERR_HIP;
     }
+    if (e2 != hipSuccess) return EOT_ERR_HIP;
+    std::memcpy(fl, pb, sizeof(fl));
+    std::memcpy(gn_out, pb + 64, sizeof(double));
     if (fl[0] == 0) return EOT_OK;
     ss.st->range_retries += 1;
     EOTCHK(clear_flags(x));
