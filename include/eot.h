@@ -132,6 +132,25 @@ eot_status eot_hvp(const eot_cost* cost, double gamma, const double* f, const do
                    double* Hx, double* Hy, int32_t prec, void* ws, size_t ws_bytes,
                    void* stream);
 
+/* eot_hvp without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc). Same operation, arguments, kernels and results as
+ * eot_hvp; the scratch comes from a library-owned device array of 64 MiB
+ * (one copy per GPU, taken when the library's code object is loaded on that
+ * GPU and held until the process ends; its address is looked up at the first
+ * call on each GPU). The call allocates nothing: no hipMalloc / hipFree, no
+ * pinned host memory. It uses the array of the CURRENT device, so `stream`
+ * must belong to that device. Every call on one GPU shares that array, which
+ * keeps the last call's contents (each call initialises what it reads), so
+ * calls that overlap on one GPU (different streams, or host threads) race
+ * and must be serialised by the caller. Returns EOT_ERR_WORKSPACE when the
+ * problem needs more than 64 MiB of scratch (eot_workspace_size(EOT_OP_HVP)
+ * > 64 MiB: a dense n = m = 16384 cost needs 25 MiB, n = m = 32768 needs
+ * 98 MiB), before any device work. */
+eot_status eot_hvp_noalloc(const eot_cost* cost, double gamma, const double* f, const double* g,
+                           const double* row_shift, double rho, const double* x, const double* y,
+                           double* Hx, double* Hy, int32_t prec, void* stream);
+
 typedef struct {
     double rho_out;     /* discount at exit (after the update following the last solve, Alg. 2)          */
     int32_t cg_iters;   /* CG iterations over all discount levels                     */

@@ -29,6 +29,14 @@
 
 using namespace eot;
 
+// Workspace of eot_hvp_noalloc: device memory owned by the library for
+// callers that cannot allocate. Each GPU the library runs on holds its own
+// copy (from the first call on that GPU until the process ends); in host code
+// the name is only a stand-in, the device address comes from
+// hipGetSymbolAddress (noalloc_scratch below).
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
 namespace {
 
 static_assert(sizeof(CgScalars) % sizeof(double) == 0, "CgScalars is fetched as doubles");
@@ -1035,6 +1043,31 @@ eot_status solve_impl(Ctx& x, const double* r, const double* c, const eot_solve_
 
 bool bad_gamma(double gamma) { return !(gamma > 0.0) || !std::isfinite(gamma); }
 
+// Device address of the current GPU's copy of `scratch`, looked up once per
+// device with that device current and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+eot_status noalloc_scratch(void** out)
+{
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return EOT_ERR_HIP;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return EOT_ERR_HIP;
+        }
+        g_noalloc_ptr[dev] = ptr;
+    }
+    *out = g_noalloc_ptr[dev];
+    return EOT_OK;
+}
+
 bool bad_opts(const eot_solve_opts& o)
 {
     return bad_gamma(o.gamma_init) || bad_gamma(o.gamma_final) || !(o.tol > 0.0) ||
@@ -1358,6 +1391,21 @@ eot_status eot_hvp(const eot_cost* cost, double gamma, const double* f, const do
     HIPCHK(launch_hvp_finish(x.sc.row_part, x.rtiles, x.sc.col_part, x.ctiles, x.n, x.m, a, Hx,
                              Hy, x.s));
     return EOT_OK;
+}
+
+eot_status eot_hvp_noalloc(const eot_cost* cost, double gamma, const double* f, const double* g,
+                           const double* row_shift, double rho, const double* xv,
+                           const double* yv, double* Hx, double* Hy, int32_t prec, void* stream)
+{
+    if (!f || !g || !xv || !yv || !Hx || !Hy || bad_gamma(gamma)) return EOT_ERR_INVALID_ARG;
+    if (!(rho >= 0.0 && rho <= 1.0)) return EOT_ERR_INVALID_ARG;
+    size_t need = 0;
+    EOTCHK(eot_workspace_size(EOT_OP_HVP, cost, prec, &need));
+    if (need > kNoAllocBytes) return EOT_ERR_WORKSPACE;
+    void* ws = nullptr;
+    EOTCHK(noalloc_scratch(&ws));
+    return eot_hvp(cost, gamma, f, g, row_shift, rho, xv, yv, Hx, Hy, prec, ws, kNoAllocBytes,
+                   stream);
 }
 
 eot_status eot_newton_cg(const eot_cost* cost, double gamma, const double* f, const double* g,

@@ -103,6 +103,8 @@ SIGNATURES = {
                                _c_vp]),
     "eot_hvp": (_c_i32, [ctypes.POINTER(eot_cost), _c_f64, _c_vp, _c_vp, _c_vp, _c_f64, _c_vp,
                          _c_vp, _c_vp, _c_vp, _c_i32, _c_vp, ctypes.c_size_t, _c_vp]),
+    "eot_hvp_noalloc": (_c_i32, [ctypes.POINTER(eot_cost), _c_f64, _c_vp, _c_vp, _c_vp, _c_f64,
+                                 _c_vp, _c_vp, _c_vp, _c_vp, _c_i32, _c_vp]),
     "eot_newton_cg": (_c_i32, [ctypes.POINTER(eot_cost), _c_f64, _c_vp, _c_vp, _c_vp, _c_vp,
                                _c_f64, _c_f64, _c_i32, _c_i32, _c_vp, _c_vp,
                                ctypes.POINTER(eot_newton_stats), _c_i32, _c_vp,
@@ -278,6 +280,23 @@ def eot_hvp(C, gamma, f, g, rho, x, y, row_shift=None, precision="fp64"):
                        _vec(y, m, "y"), _vec(Hx, n, "Hx"), _vec(Hy, m, "Hy"), prec,
                        ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev))
     _check(st, "eot_hvp")
+    return Hx, Hy
+
+
+def eot_hvp_noalloc(C, gamma, f, g, rho, x, y, row_shift=None, precision="fp64", Hx=None, Hy=None):
+    """eot_hvp on the library's own per-GPU scratch (no workspace argument; the
+    call allocates nothing). Hx, Hy: optional preallocated outputs."""
+    cost = make_cost(C)
+    n, m = cost.n, cost.m
+    dev = C.device
+    prec = _prec(precision)
+    Hx = torch.empty(n, dtype=torch.float64, device=dev) if Hx is None else Hx
+    Hy = torch.empty(m, dtype=torch.float64, device=dev) if Hy is None else Hy
+    st = lib().eot_hvp_noalloc(ctypes.byref(cost), float(gamma), _vec(f, n, "f"), _vec(g, m, "g"),
+                               _vec(row_shift, n, "row_shift", True), float(rho), _vec(x, n, "x"),
+                               _vec(y, m, "y"), _vec(Hx, n, "Hx"), _vec(Hy, m, "Hy"), prec,
+                               _stream(dev))
+    _check(st, "eot_hvp_noalloc")
     return Hx, Hy
 
 

@@ -209,3 +209,16 @@ def test_batched_validation(L):
     probs[1].cost.n = 0
     assert solve() == eot.EOT_ERR_INVALID_ARG
     assert L.eot_workspace_size_batched(2, probs, 4, ctypes.byref(sz)) == eot.EOT_ERR_INVALID_ARG
+
+
+def test_noalloc_hvp_rejects_oversize_before_device_work(L):
+    """eot_hvp_noalloc checks the scratch it needs against its fixed 64 MiB
+    before any HIP call: a dense 32768^2 cost needs 98 MiB."""
+    from paper_2504_02067_amd import eot
+    big = eot.eot_cost(kind=0, d=0, n=32768, m=32768, ldc=32768, C=ctypes.c_void_p(4096),
+                       X=None, Y=None, scale=0.0)
+    p = ctypes.c_void_p(8)
+    assert L.eot_hvp_noalloc(ctypes.byref(big), 0.1, p, p, None, 0.5, p, p, p, p, 1,
+                             None) == eot.EOT_ERR_WORKSPACE
+    assert L.eot_hvp_noalloc(ctypes.byref(big), 0.1, None, p, None, 0.5, p, p, p, p, 1,
+                             None) == eot.EOT_ERR_INVALID_ARG
