@@ -400,6 +400,8 @@ def main():
     ap.add_argument("--batch-workers", type=int, default=8)
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the HVP kernel loop and a 1 GiB device copy (for counter runs)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the 512-problem batch in both precisions (for trace runs)")
     ap.add_argument("--highd-only", action="store_true",
                     help="only 1 + 5 mixed high-dimensional HVP passes (n = m = 65536, d = 64; "
                          "for counter runs)")
@@ -415,6 +417,10 @@ def main():
     dev = torch.device("cuda:0")
     if args.highd_only:
         highd_only(eot, W, dev)
+        return
+    if args.batch_only:
+        print(json.dumps({"mode": "batch-only", "batch": batch_measure(args, eot, W, dev)}),
+              flush=True)
         return
     side = 128
     p = W.large_grid_problem(args.seed)

@@ -208,6 +208,9 @@ typedef struct {
                                stream, pass timing off; otherwise direct launches); 0    */
     int32_t verbose;        /* 1: one line on stderr after each MDOT step (temperature,
                                Newton steps, CG iterations, passes, seconds so far); 0  */
+    int32_t warm_start;     /* 1: f, g on input are the potentials that start the first
+                               projection (Alg. 1's z^(1), converted to log units at
+                               gamma_init) instead of (log r~, log c~); 0             */
 } eot_solve_opts;
 
 typedef struct {
@@ -232,10 +235,75 @@ void eot_solve_opts_default(eot_solve_opts* opts);
  * returns the potentials at gamma_final in cost units (f: n, g: m). The
  * plan at the output is exp((f_i + g_j - C_ij)/gamma_final); rounding onto
  * U(r, c) (the last step of Alg. 1) is not applied. r: n, c: m on the simplex.
+ * f, g are also inputs when opts->warm_start is set (cost units at
+ * gamma_init). When the solve stops at opts->max_mdot (EOT_ERR_NOT_CONVERGED)
+ * f, g hold the extrapolated potentials of the next temperature, in cost
+ * units of that temperature (stats->final_gamma).
  * opts, stats: host pointers (stats nullable). */
 eot_status eot_solve(const eot_cost* cost, const double* r, const double* c,
                      const eot_solve_opts* opts, double* f, double* g,
                      eot_solve_stats* stats, void* ws, size_t ws_bytes, void* stream);
+
+/* The state Alg. 1 carries from one temperature to the next, so that a solve
+ * stopped after some temperatures (opts.max_mdot) can be resumed exactly:
+ * z^(t) = (u, v), the potentials that start projection t (already
+ * extrapolated), the last projected z^(t-1) = (u_prev, v_prev), the inverse
+ * temperatures beta^(t) and beta^(t-1) (0 before the first projection), the
+ * decay factor q and the warm discount rho0 of the next NewtonSolve (App. B).
+ * Vectors are DEVICE arrays owned by the caller (u, u_prev: n; v, v_prev: m)
+ * in the paper's LOG units (u = f / gamma), so that a resumed solve takes
+ * bitwise the same steps as an uninterrupted one. */
+typedef struct {
+    int32_t t;                /* MDOT step that starts next (1-based)                 */
+    double beta, beta_prev;   /* beta^(t), beta^(t-1)                                 */
+    double q, rho0;
+    double* u;
+    double* v;
+    double* u_prev;
+    double* v_prev;
+} eot_solve_state;
+
+/* Record of what Algs. 1 and 4 decided, step by step (instrumentation for
+ * tests and tuning). Arrays are HOST memory owned by the caller, each nullable,
+ * with the capacities given; n_steps and n_newton count every step, also
+ * those beyond the capacity, which are not stored. */
+typedef struct {
+    int32_t cap_steps, cap_newton;  /* in                                            */
+    int32_t n_steps, n_newton;      /* out                                           */
+    /* per MDOT step t = 1, 2, ... */
+    double* beta;        /* inverse temperature of the projection                       */
+    double* eps_d;       /* eps_d of Alg. 1 (the projection stops at eps_d / 2)         */
+    double* start_err;   /* ||r~ - r(P)||_1 after the projection's first column fix     */
+    double* delta_min;   /* smallest Newton decrease ratio (+inf: no Newton step)       */
+    double* q;           /* decay factor after AdjustSchedule at the end of the step    */
+    int32_t* newton;     /* Newton steps of the step (mixed: with the FP64 finish)      */
+    int32_t* sweeps;     /* ChiSinkhorn sweeps of the step                              */
+    /* per Newton step over the whole solve */
+    int32_t* step_of;    /* MDOT step it belongs to                                     */
+    double* gnorm;       /* ||grad g||_1 after ChiSinkhorn                              */
+    double* eta;         /* forcing term of Alg. 4                                      */
+    double* cg_tol;      /* L1 residual tolerance of its CG solves (eta/4 ||grad g||_1) */
+    double* rho0;        /* discount NewtonSolve starts from                            */
+    double* rho_out;     /* discount NewtonSolve returns                                */
+    int32_t* cg_iters;   /* CG iterations of the NewtonSolve                            */
+    int32_t* levels;     /* discount levels solved                                      */
+    double* alpha;       /* accepted line-search step                                   */
+    double* gnorm_next;  /* ||r~ - r(P)||_1 after the row refresh                       */
+} eot_solve_trace;
+
+/* eot_solve with the carried state and the step trace: `resume` (host struct
+ * with device vectors, nullable) continues a solve from a saved state (f, g
+ * and opts.warm_start are then ignored on input); `state_out` (nullable; its
+ * vectors must be allocated by the caller) receives the state at exit, also
+ * when the solve stopped at opts.max_mdot with EOT_ERR_NOT_CONVERGED;
+ * `trace` (nullable) records the steps. Solving with max_mdot = k and
+ * resuming from the saved state with a larger cap gives bitwise the potentials
+ * of one uninterrupted solve (same kernels, same order). */
+eot_status eot_solve_ex(const eot_cost* cost, const double* r, const double* c,
+                        const eot_solve_opts* opts, const eot_solve_state* resume,
+                        eot_solve_state* state_out, eot_solve_trace* trace, double* f,
+                        double* g, eot_solve_stats* stats, void* ws, size_t ws_bytes,
+                        void* stream);
 
 /* Rounding onto the transport polytope U(r, c) (the last step of Alg. 1; the procedure of
  * Altschuler et al. that the paper cites for it): with P the plan at (f, g),

@@ -697,7 +697,34 @@ eot_status newton_solve(Ctx& x, int prec, const double* u, const double* v, doub
 struct SolveState {
     const eot_solve_opts* o;
     eot_solve_stats* st;
+    eot_solve_trace* tr = nullptr;   // step trace (host, nullable)
+    int32_t step = 0;                // MDOT step being projected
+    double start_err = 0.0;          // first ||r~ - r(P)||_1 of the step's projection
+    int32_t sweeps = 0;              // ChiSinkhorn sweeps of the step
+    bool first_projection = true;    // false for the FP64 finish of a mixed step
 };
+
+// One Newton step of Alg. 4 into the trace.
+void trace_newton(SolveState& ss, double gk, double eta, double rho_in, double rho_out,
+                  int32_t cg, int32_t lev, double alpha, double gk1)
+{
+    eot_solve_trace* tr = ss.tr;
+    if (!tr) return;
+    const int32_t e = tr->n_newton;
+    if (e < tr->cap_newton) {
+        if (tr->step_of) tr->step_of[e] = ss.step;
+        if (tr->gnorm) tr->gnorm[e] = gk;
+        if (tr->eta) tr->eta[e] = eta;
+        if (tr->cg_tol) tr->cg_tol[e] = 0.25 * eta * gk;
+        if (tr->rho0) tr->rho0[e] = rho_in;
+        if (tr->rho_out) tr->rho_out[e] = rho_out;
+        if (tr->cg_iters) tr->cg_iters[e] = cg;
+        if (tr->levels) tr->levels[e] = lev;
+        if (tr->alpha) tr->alpha[e] = alpha;
+        if (tr->gnorm_next) tr->gnorm_next[e] = gk1;
+    }
+    tr->n_newton = e + 1;
+}
 
 // Column fix (v <- v + log c~ - log c(P)) followed by the row refresh
 // (log r(P), s), with a fallback to FP64 passes from exact row maxima when
@@ -792,6 +819,7 @@ eot_status tnp(Ctx& x, int prec, double beta, double eps, double* rho0, double* 
         gn_known = -1.0;
         if (!(gn >= 0.0)) EOTCHK(reduce_host(x, RED_L1_DIFF_EXP, S.rt, S.lr, n, &gn));
         if (!std::isfinite(gn)) return EOT_ERR_NONFINITE;
+        if (k == 0 && ss.first_projection) ss.start_err = gn;
         if (gn <= eps) break;                                              // tolerance met
         if (stall_exit) {
             slow = (gn <= 1e-3 && gn > 0.5 * g_prev) ? slow + 1 : 0;
@@ -812,6 +840,7 @@ eot_status tnp(Ctx& x, int prec, double beta, double eps, double* rho0, double* 
             EOTCHK(fix_and_refresh(x, prec, beta, S.lrt, ss));
             st->passes_sinkhorn += x.passes - p0;
             st->sinkhorn_iters += 1;
+            ss.sweeps += 1;
             ++sweeps;
         }
         HIPCHK(launch_newton_init(S.lr, S.rt, x.nv.rP, x.nv.grad, x.nv.b, x.nv.d, n, x.s));
@@ -820,6 +849,7 @@ eot_status tnp(Ctx& x, int prec, double beta, double eps, double* rho0, double* 
         if (sweeps > 0) EOTCHK(reduce_host(x, RED_L1, x.nv.grad, nullptr, n, &gk));
         const double eta = std::max(gk, 0.8 * eps / gk);                  // forcing term
         NewtonResult nr;                                                   // Alg. 2 and d_v
+        const double rho_in = *rho0;
         p0 = x.passes;
         EOTCHK(newton_solve(x, prec, S.u, S.v, beta, S.lr, S.s, S.rt, S.ct, eta, *rho0,
                             o->max_cg, o->max_levels, S.du, S.dv, &nr, gk));
@@ -864,6 +894,7 @@ eot_status tnp(Ctx& x, int prec, double beta, double eps, double* rho0, double* 
         gn_known = gk1;
         const double dk = (gk - gk1) / ((1.0 - eta) * gk);
         dmin = std::min(dmin, dk);
+        trace_newton(ss, gk, eta, rho_in, nr.rho, nr.cg_iters, nr.levels, alpha, gk1);
         ++k;
     }
     HIPCHK(launch_add_logdiff(S.u, S.lrt, S.lr, n, x.s));                 // closing row fit
@@ -951,7 +982,8 @@ eot_status check_marginal(Ctx& x, const double* p, int64_t k)
 }
 
 eot_status solve_impl(Ctx& x, const double* r, const double* c, const eot_solve_opts* o,
-                      double* f_out, double* g_out, eot_solve_stats* st)
+                      const eot_solve_state* resume, eot_solve_state* state_out,
+                      eot_solve_trace* trace, double* f_out, double* g_out, eot_solve_stats* st)
 {
     x.cg_graph = o->cg_graph != 0;
     const auto t_start = std::chrono::steady_clock::now();
@@ -974,9 +1006,31 @@ eot_status solve_impl(Ctx& x, const double* r, const double* c, const eot_solve_
     double q = o->q1;
     double rho0 = 0.0;
     SolveState ss{o, st};
+    ss.tr = trace;
+    if (trace) trace->n_steps = trace->n_newton = 0;
     eot_status status = EOT_OK;
     bool done = false;
     int32_t t = 1;
+    bool fresh = true;                                                     // z^(1) still to set
+    if (resume) {                                                          // carried state of Alg. 1
+        t = resume->t;
+        beta = resume->beta;
+        beta_prev = resume->beta_prev;
+        q = resume->q;
+        rho0 = resume->rho0;
+        HIPCHK(launch_copy(resume->u, S.u, n, x.s));
+        HIPCHK(launch_copy(resume->v, S.v, m, x.s));
+        HIPCHK(launch_copy(resume->u_prev, S.u_prev, n, x.s));
+        HIPCHK(launch_copy(resume->v_prev, S.v_prev, m, x.s));
+        fresh = false;
+    } else if (o->warm_start) {                                            // given z^(1)
+        const double gamma0 = beta_i <= beta_f ? o->gamma_init : o->gamma_final;
+        HIPCHK(launch_divs(f_out, gamma0, S.u, n, x.s));
+        HIPCHK(launch_divs(g_out, gamma0, S.v, m, x.s));
+        HIPCHK(launch_copy(S.u, S.u_prev, n, x.s));
+        HIPCHK(launch_copy(S.v, S.v_prev, m, x.s));
+        fresh = false;
+    }
     while (!done) {
         if (t > o->max_mdot) { status = EOT_ERR_NOT_CONVERGED; break; }
         done = (beta == beta_f);                                           // last temperature
@@ -985,21 +1039,28 @@ eot_status solve_impl(Ctx& x, const double* r, const double* c, const eot_solve_
         HIPCHK(launch_smooth(r, o->w_r * eps_d, 1.0 / (double)n, S.rt, S.lrt, n, x.s));   // smoothing (Sec. 3.4)
         HIPCHK(launch_smooth(c, w_c * eps_d, 1.0 / (double)m, S.ct, S.lct, m, x.s));
         HIPCHK(launch_recip(S.ct, S.inv_ct, m, x.s));
-        if (t == 1) {                                                      // initial potentials
+        if (fresh) {                                                       // initial potentials
             HIPCHK(launch_copy(S.lrt, S.u, n, x.s));
             HIPCHK(launch_copy(S.lrt, S.u_prev, n, x.s));
             HIPCHK(launch_copy(S.lct, S.v, m, x.s));
             HIPCHK(launch_copy(S.lct, S.v_prev, m, x.s));
+            fresh = false;
         }
         double dmin = INFINITY;                                            // projection
         const bool mixed = prec == EOT_PREC_MIXED;
         bool stalled = false;
         const bool sk = o->projection == EOT_PROJ_SINKHORN;
+        const int32_t newton0 = st->newton_steps;
+        ss.step = t;
+        ss.start_err = 0.0;
+        ss.sweeps = 0;
+        ss.first_projection = true;
         status = sk ? sinkhorn_project(x, prec, beta, 0.5 * eps_d, ss, mixed, &stalled)
                     : tnp(x, prec, beta, 0.5 * eps_d, &rho0, &dmin, ss, mixed, &stalled);
         st->mixed_stalls += stalled ? 1 : 0;
         if (status == EOT_OK && done && mixed && o->verify_fp64) {
             double dmin64 = INFINITY;
+            ss.first_projection = false;
             status = sk ? sinkhorn_project(x, EOT_PREC_FP64, beta, 0.5 * eps_d, ss)
                         : tnp(x, EOT_PREC_FP64, beta, 0.5 * eps_d, &rho0, &dmin64, ss);
         } else if (status == EOT_OK && done && stalled) {
@@ -1008,6 +1069,23 @@ eot_status solve_impl(Ctx& x, const double* r, const double* c, const eot_solve_
         st->delta_min_last = dmin;
         st->mdot_steps = t;
         st->final_gamma = 1.0 / beta;
+        if (status == EOT_OK && !done && o->adaptive_q) {                  // AdjustSchedule (Sec. 3.3)
+            if (dmin > 0.95) q = std::min(2.0, q * q);
+            else if (dmin < 0.8) q = std::sqrt(q);
+        }
+        if (trace) {
+            const int32_t e = trace->n_steps;
+            if (e < trace->cap_steps) {
+                if (trace->beta) trace->beta[e] = beta;
+                if (trace->eps_d) trace->eps_d[e] = eps_d;
+                if (trace->start_err) trace->start_err[e] = ss.start_err;
+                if (trace->delta_min) trace->delta_min[e] = dmin;
+                if (trace->q) trace->q[e] = q;
+                if (trace->newton) trace->newton[e] = st->newton_steps - newton0;
+                if (trace->sweeps) trace->sweeps[e] = ss.sweeps;
+            }
+            trace->n_steps = e + 1;
+        }
         if (o->verbose) {
             const double secs =
                 std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
@@ -1019,10 +1097,6 @@ eot_status solve_impl(Ctx& x, const double* r, const double* c, const eot_solve_
             std::fflush(stderr);
         }
         if (status != EOT_OK || done) break;
-        if (o->adaptive_q) {                                               // AdjustSchedule (Sec. 3.3)
-            if (dmin > 0.95) q = std::min(2.0, q * q);
-            else if (dmin < 0.8) q = std::sqrt(q);
-        }
         const double beta_next = std::min(q * beta, beta_f);               // next temperature
         const double ratio = (beta_next - beta) / (beta - beta_prev);      // extrapolation
         HIPCHK(launch_extrapolate(S.u, S.u_prev, ratio, n, x.s));
@@ -1031,7 +1105,19 @@ eot_status solve_impl(Ctx& x, const double* r, const double* c, const eot_solve_
         beta = beta_next;
         ++t;
     }
+    if (state_out) {
+        state_out->t = t;
+        state_out->beta = beta;
+        state_out->beta_prev = beta_prev;
+        state_out->q = q;
+        state_out->rho0 = rho0;
+        HIPCHK(launch_copy(S.u, state_out->u, n, x.s));
+        HIPCHK(launch_copy(S.v, state_out->v, m, x.s));
+        HIPCHK(launch_copy(S.u_prev, state_out->u_prev, n, x.s));
+        HIPCHK(launch_copy(S.v_prev, state_out->v_prev, m, x.s));
+    }
     if (status == EOT_OK || status == EOT_ERR_NOT_CONVERGED) {
+        st->final_gamma = 1.0 / beta;
         eot_status rs = report(x, beta, r, c, st);
         if (rs != EOT_OK) return rs;
         HIPCHK(launch_scale(S.u, 1.0 / beta, f_out, n, x.s));
@@ -1073,7 +1159,17 @@ bool bad_opts(const eot_solve_opts& o)
     return bad_gamma(o.gamma_init) || bad_gamma(o.gamma_final) || !(o.tol > 0.0) ||
            !(o.p >= 1.0) || !(o.q1 > 1.0) || !(o.w_r > 0.0 && o.w_r < 0.5) || o.max_cg < 1 ||
            o.max_levels < 0 || o.max_backtrack < 0 || o.max_newton < 0 || o.max_sinkhorn < 0 ||
-           o.max_mdot < 1 || (o.projection != EOT_PROJ_TNP && o.projection != EOT_PROJ_SINKHORN);
+           o.max_mdot < 1 || (o.projection != EOT_PROJ_TNP && o.projection != EOT_PROJ_SINKHORN) ||
+           (o.warm_start != 0 && o.warm_start != 1);
+}
+
+bool bad_state(const eot_solve_state* s, bool in)
+{
+    if (!s) return false;
+    if (!s->u || !s->v || !s->u_prev || !s->v_prev) return true;
+    if (!in) return false;
+    return s->t < 1 || !(s->beta > 0.0) || !std::isfinite(s->beta) || !(s->beta_prev >= 0.0) ||
+           !(s->beta_prev < s->beta) || !(s->q > 1.0) || !(s->rho0 >= 0.0 && s->rho0 < 1.0);
 }
 
 size_t align_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
@@ -1081,13 +1177,15 @@ size_t align_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 // One solve on `stream` with workspace ws (options already validated).
 eot_status solve_one(const eot_cost* cost, const double* r, const double* c,
                      const eot_solve_opts* opts, double* f, double* g, eot_solve_stats* stats,
-                     void* ws, size_t ws_bytes, void* stream)
+                     void* ws, size_t ws_bytes, void* stream,
+                     const eot_solve_state* resume = nullptr,
+                     eot_solve_state* state_out = nullptr, eot_solve_trace* trace = nullptr)
 {
     const auto t0 = std::chrono::steady_clock::now();
     Ctx x;
     EOTCHK(setup(x, cost, EOT_OP_SOLVE, opts->precision, ws, ws_bytes, stream));
     eot_solve_stats st{};
-    eot_status status = solve_impl(x, r, c, opts, f, g, &st);
+    eot_status status = solve_impl(x, r, c, opts, resume, state_out, trace, f, g, &st);
     st.passes_other = x.passes - st.passes_newton - st.passes_linesearch - st.passes_sinkhorn -
                       st.passes_projection;
     st.status = status;
@@ -1473,6 +1571,7 @@ void eot_solve_opts_default(eot_solve_opts* o)
     o->projection = EOT_PROJ_TNP;
     o->cg_graph = 0;
     o->verbose = 0;
+    o->warm_start = 0;
 }
 
 eot_status eot_solve(const eot_cost* cost, const double* r, const double* c,
@@ -1482,6 +1581,20 @@ eot_status eot_solve(const eot_cost* cost, const double* r, const double* c,
     if (!r || !c || !opts || !f || !g) return EOT_ERR_INVALID_ARG;
     if (bad_opts(*opts)) return EOT_ERR_INVALID_ARG;
     return solve_one(cost, r, c, opts, f, g, stats, ws, ws_bytes, stream);
+}
+
+eot_status eot_solve_ex(const eot_cost* cost, const double* r, const double* c,
+                        const eot_solve_opts* opts, const eot_solve_state* resume,
+                        eot_solve_state* state_out, eot_solve_trace* trace, double* f,
+                        double* g, eot_solve_stats* stats, void* ws, size_t ws_bytes,
+                        void* stream)
+{
+    if (!r || !c || !opts || !f || !g) return EOT_ERR_INVALID_ARG;
+    if (bad_opts(*opts) || bad_state(resume, true) || bad_state(state_out, false))
+        return EOT_ERR_INVALID_ARG;
+    if (trace && (trace->cap_steps < 0 || trace->cap_newton < 0)) return EOT_ERR_INVALID_ARG;
+    return solve_one(cost, r, c, opts, f, g, stats, ws, ws_bytes, stream, resume, state_out,
+                     trace);
 }
 
 eot_status eot_workspace_size_batched(int32_t nprob, const eot_batch_problem* probs,

@@ -60,7 +60,8 @@ class eot_solve_opts(ctypes.Structure):
                 ("adaptive_rho0", _c_i32), ("max_cg", _c_i32), ("max_levels", _c_i32),
                 ("max_backtrack", _c_i32), ("max_newton", _c_i32), ("max_sinkhorn", _c_i32),
                 ("max_mdot", _c_i32), ("precision", _c_i32), ("verify_fp64", _c_i32),
-                ("projection", _c_i32), ("cg_graph", _c_i32), ("verbose", _c_i32)]
+                ("projection", _c_i32), ("cg_graph", _c_i32), ("verbose", _c_i32),
+                ("warm_start", _c_i32)]
 
 
 class eot_solve_stats(ctypes.Structure):
@@ -75,6 +76,27 @@ class eot_solve_stats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class eot_solve_state(ctypes.Structure):
+    _fields_ = [("t", _c_i32), ("beta", _c_f64), ("beta_prev", _c_f64), ("q", _c_f64),
+                ("rho0", _c_f64), ("u", _c_vp), ("v", _c_vp), ("u_prev", _c_vp),
+                ("v_prev", _c_vp)]
+
+
+_c_dp = ctypes.POINTER(ctypes.c_double)
+_c_ip = ctypes.POINTER(ctypes.c_int32)
+TRACE_STEP_FIELDS = ("beta", "eps_d", "start_err", "delta_min", "q", "newton", "sweeps")
+TRACE_NEWTON_FIELDS = ("step_of", "gnorm", "eta", "cg_tol", "rho0", "rho_out", "cg_iters",
+                       "levels", "alpha", "gnorm_next")
+TRACE_INT_FIELDS = ("newton", "sweeps", "step_of", "cg_iters", "levels")
+
+
+class eot_solve_trace(ctypes.Structure):
+    _fields_ = ([("cap_steps", _c_i32), ("cap_newton", _c_i32), ("n_steps", _c_i32),
+                 ("n_newton", _c_i32)]
+                + [(k, _c_ip if k in TRACE_INT_FIELDS else _c_dp) for k in TRACE_STEP_FIELDS]
+                + [(k, _c_ip if k in TRACE_INT_FIELDS else _c_dp) for k in TRACE_NEWTON_FIELDS])
 
 
 # Every entry point declared in include/eot.h, with its ctypes signature.
@@ -113,6 +135,11 @@ SIGNATURES = {
     "eot_solve": (_c_i32, [ctypes.POINTER(eot_cost), _c_vp, _c_vp,
                            ctypes.POINTER(eot_solve_opts), _c_vp, _c_vp,
                            ctypes.POINTER(eot_solve_stats), _c_vp, ctypes.c_size_t, _c_vp]),
+    "eot_solve_ex": (_c_i32, [ctypes.POINTER(eot_cost), _c_vp, _c_vp,
+                              ctypes.POINTER(eot_solve_opts), ctypes.POINTER(eot_solve_state),
+                              ctypes.POINTER(eot_solve_state), ctypes.POINTER(eot_solve_trace),
+                              _c_vp, _c_vp, ctypes.POINTER(eot_solve_stats), _c_vp,
+                              ctypes.c_size_t, _c_vp]),
     "eot_workspace_size_batched": (_c_i32, [_c_i32, ctypes.POINTER(eot_batch_problem), _c_i32,
                                             ctypes.POINTER(ctypes.c_size_t)]),
     "eot_solve_batched": (_c_i32, [_c_i32, ctypes.POINTER(eot_batch_problem),
@@ -364,6 +391,74 @@ def eot_solve(C, r, c, opts: Optional[eot_solve_opts] = None, allow_not_converge
     allow = (EOT_OK, EOT_ERR_NOT_CONVERGED) if allow_not_converged else (EOT_OK,)
     _check(st, "eot_solve", allow)
     return f, g, stats.as_dict()
+
+
+def eot_solve_ex(C, r, c, opts: Optional[eot_solve_opts] = None, warm=None, resume=None,
+                 want_state=False, trace=False, cap_steps=512, cap_newton=4096,
+                 allow_not_converged=False, **kw):
+    """eot_solve with the carried MDOT state and the step trace.
+
+    warm: (f0, g0) cost-unit potentials that start the first projection
+    (sets opts.warm_start); resume: a state dict returned by an earlier call
+    (device vectors in log units). Returns (f, g, stats dict, trace dict or
+    None, state dict or None)."""
+    import numpy as np
+    cost = make_cost(C)
+    n, m = cost.n, cost.m
+    dev = C.device
+    o = opts if opts is not None else default_solve_opts(**kw)
+    f = torch.empty(n, dtype=torch.float64, device=dev)
+    g = torch.empty(m, dtype=torch.float64, device=dev)
+    if warm is not None:
+        f.copy_(warm[0])
+        g.copy_(warm[1])
+        o.warm_start = 1
+    stats = eot_solve_stats()
+    rs = None
+    if resume is not None:
+        rs = eot_solve_state(t=resume["t"], beta=resume["beta"], beta_prev=resume["beta_prev"],
+                             q=resume["q"], rho0=resume["rho0"],
+                             u=_vec(resume["u"], n, "u"), v=_vec(resume["v"], m, "v"),
+                             u_prev=_vec(resume["u_prev"], n, "u_prev"),
+                             v_prev=_vec(resume["v_prev"], m, "v_prev"))
+    so, sv = None, None
+    if want_state:
+        sv = {k: torch.empty(n if k in ("u", "u_prev") else m, dtype=torch.float64, device=dev)
+              for k in ("u", "v", "u_prev", "v_prev")}
+        so = eot_solve_state(**{k: _vec(t, t.numel(), k) for k, t in sv.items()})
+    tr, bufs = None, None
+    if trace:
+        tr = eot_solve_trace(cap_steps=cap_steps, cap_newton=cap_newton)
+        bufs = {}
+        for k in TRACE_STEP_FIELDS + TRACE_NEWTON_FIELDS:
+            cap = cap_steps if k in TRACE_STEP_FIELDS else cap_newton
+            a = np.zeros(cap, dtype=np.int32 if k in TRACE_INT_FIELDS else np.float64)
+            bufs[k] = a
+            setattr(tr, k, a.ctypes.data_as(_c_ip if k in TRACE_INT_FIELDS else _c_dp))
+    ws = workspace(EOT_OP_SOLVE, cost, o.precision, dev)
+    st = lib().eot_solve_ex(ctypes.byref(cost), _vec(r, n, "r"), _vec(c, m, "c"),
+                            ctypes.byref(o), ctypes.byref(rs) if rs is not None else None,
+                            ctypes.byref(so) if so is not None else None,
+                            ctypes.byref(tr) if tr is not None else None,
+                            _vec(f, n, "f"), _vec(g, m, "g"), ctypes.byref(stats),
+                            ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev))
+    allow = (EOT_OK, EOT_ERR_NOT_CONVERGED) if allow_not_converged else (EOT_OK,)
+    _check(st, "eot_solve_ex", allow)
+    d = stats.as_dict()
+    d["status"] = int(st)
+    tdict = None
+    if tr is not None:
+        ns, nk = min(tr.n_steps, cap_steps), min(tr.n_newton, cap_newton)
+        tdict = {"n_steps": tr.n_steps, "n_newton": tr.n_newton}
+        for k in TRACE_STEP_FIELDS:
+            tdict[k] = bufs[k][:ns].copy()
+        for k in TRACE_NEWTON_FIELDS:
+            tdict[k] = bufs[k][:nk].copy()
+    sdict = None
+    if so is not None:
+        sdict = {"t": so.t, "beta": so.beta, "beta_prev": so.beta_prev, "q": so.q,
+                 "rho0": so.rho0, **sv}
+    return f, g, d, tdict, sdict
 
 
 def eot_solve_batched(problems, opts: Optional[eot_solve_opts] = None, workers=8,
