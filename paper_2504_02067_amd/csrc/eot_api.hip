@@ -352,7 +352,10 @@ PassArgs make_args(const Ctx& x, const double* u, const double* a, const double*
     A.n = x.n;
     A.m = x.m;
     A.ldc = x.cost.ldc;
-    A.vec_ok = (x.cost.ldc % 4 == 0) && (reinterpret_cast<uintptr_t>(x.cost.C) % 16 == 0);
+    // 16-byte loads only where a 4-column group never crosses column m: the
+    // ldc padding of a row is never read (it may hold anything)
+    A.vec_ok = (x.cost.ldc % 4 == 0) && (x.m % 4 == 0) &&
+               (reinterpret_cast<uintptr_t>(x.cost.C) % 16 == 0);
     A.u = u;
     A.a = a;
     A.v = v;

@@ -70,16 +70,19 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 // Loads of 4 consecutive cost entries starting at column jb of one row. They
-// never branch: addresses are clamped into the row's allocation (ldc elements)
-// and entries past column m are replaced by 0 by the caller on edge tiles, so
-// the compiler keeps all loads of a sub-band in flight. Streaming data, so
-// non-temporal (no reuse expected in the caches).
+// never branch: addresses are clamped into the row's first m entries (vector
+// loads are used only when m and ldc are multiples of 4, so a clamped
+// 16-byte group never reaches the ldc padding), so the compiler keeps all
+// loads of a sub-band in flight and whatever the padding holds (NaN, inf) is
+// never read. Lanes past column m get a clamped finite entry whose plan weight
+// the -inf column potential makes 0. Streaming data, so non-temporal (no
+// reuse expected in the caches).
 template <bool VEC>
 __device__ __forceinline__ void load4(const float* __restrict__ row, int64_t jb, int64_t m,
                                       int64_t ldc, float (&out)[kVec])
 {
-    if constexpr (VEC) {   // ldc % 4 == 0 and 16-byte aligned base: row + jl is aligned
-        const int64_t jl = jb < ldc - 3 ? jb : ldc - 4;
+    if constexpr (VEC) {   // m, ldc % 4 == 0 and 16-byte aligned base: row + jl is aligned
+        const int64_t jl = jb < m - 3 ? jb : m - 4;
         const f32x4 x = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(row + jl));
         out[0] = x.x; out[1] = x.y; out[2] = x.z; out[3] = x.w;
     } else {
@@ -106,7 +109,7 @@ __device__ __forceinline__ void load4(const double* __restrict__ row, int64_t jb
                                       int64_t ldc, double (&out)[kVec])
 {
     if constexpr (VEC) {
-        const int64_t jl = jb < ldc - 3 ? jb : ldc - 4;
+        const int64_t jl = jb < m - 3 ? jb : m - 4;
         const f64x2 x0 = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(row + jl));
         const f64x2 x1 = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(row + jl + 2));
         out[0] = x0.x; out[1] = x0.y; out[2] = x1.x; out[3] = x1.y;

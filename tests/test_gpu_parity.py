@@ -118,6 +118,40 @@ def test_marginals_padded_leading_dimension():
         np.testing.assert_allclose(host(out["log_cP"]), O.log_col_marginal(C, beta, u, v), atol=tol, rtol=0)
 
 
+@pytest.mark.parametrize("n,m,ldc", [(257, 1030, 1032), (300, 2052, 2060), (9, 5, 8)])
+@pytest.mark.parametrize("pad", [np.nan, -np.inf])
+@pytest.mark.parametrize("cdt", [np.float32, np.float64])
+def test_padding_is_never_read(n, m, ldc, pad, cdt):
+    """Rows padded to a multiple of 4 elements (16-byte aligned rows) with NaN
+    or -inf in the padding: marginals and HVPs equal those of the unpadded
+    cost (m % 4 != 0 and m % 4 == 0 with ldc > m)."""
+    gamma = 0.05
+    C, f, g, r, c = random_case(n, m, n + ldc, gamma, cdt)
+    buf = np.full((n, ldc), pad, dtype=cdt)
+    buf[:, :m] = C
+    Cd = torch.from_numpy(buf).to(DEV)[:, :m]
+    assert Cd.stride(0) == ldc and Cd.data_ptr() % 16 == 0
+    u, v = to_log(f, g, gamma)
+    beta = 1.0 / gamma
+    rng = np.random.default_rng(n)
+    x, y = rng.standard_normal(n), rng.standard_normal(m)
+    Hx_ref, Hy_ref = O.hvp(C, beta, u, v, 0.5625, x, y)
+    ax, ay = O.hvp(C, beta, u, v, 0.5625, np.abs(x), np.abs(y))
+    for prec, tol in (("fp64", 1e-12), ("mixed", 4e-6)):
+        if prec == "mixed" and cdt == np.float64:
+            continue
+        say(f"padding {pad} ldc={ldc} m={m} {cdt.__name__} {prec}")
+        out = eot.eot_marginals(Cd, gamma, dvec(f), dvec(g), precision=prec)
+        np.testing.assert_allclose(host(out["log_rP"]), O.log_row_marginal(C, beta, u, v),
+                                   atol=tol, rtol=0)
+        np.testing.assert_allclose(host(out["log_cP"]), O.log_col_marginal(C, beta, u, v),
+                                   atol=tol, rtol=0)
+        Hx, Hy = eot.eot_hvp(Cd, gamma, dvec(f), dvec(g), 0.5625, dvec(x), dvec(y),
+                             precision=prec)
+        assert (np.abs(host(Hx) - Hx_ref) <= tol * ax).all()
+        assert (np.abs(host(Hy) - Hy_ref) <= tol * ay).all()
+
+
 @pytest.mark.parametrize("n,m,cdt", [(64, 64, np.float64), (300, 4500, np.float32),
                                      (130, 2049, np.float32), (1, 3, np.float32)])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
