@@ -14,7 +14,9 @@ levels) and the schedule (beta, q, alpha, rho) exactly equal; L1 errors within
 order differs); the forcing term eta = max(g, 0.8 eps / g) and the CG
 tolerance eta g / 4 inherit the relative error of g = ||grad g||_1, so they are
 compared relative to 1e-8 + 1e-12 / g (twice that for the CG tolerance);
-potentials 1e-10 relative to their scale. One exception: a NewtonSolve that
+potentials 1e-10 relative to their scale. The line search's step length is
+compared exactly while ||grad g||_1 >= 1e-7; below that, Armijo's test on the
+FP64 mass is decided by rounding on both sides. One exception: a NewtonSolve that
 ends at the discount cap 1 - 2^-30 (the forcing miss of nearly decomposable
 plans) runs its last CG solves at a condition number up to ~2e9, where the
 iteration count depends on rounding; for those Newton steps the CG count is
@@ -34,7 +36,12 @@ from paper_2504_02067_amd import workloads as W
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
 
-EXACT = ("newton", "sweeps", "step_of", "levels", "beta", "q", "alpha", "rho0", "rho_out")
+EXACT = ("newton", "sweeps", "step_of", "levels", "beta", "q", "rho0", "rho_out")
+# Armijo's test on the mass (mass - 1 <= 0.99 alpha slope) is decided by rounding
+# once |slope| ~ sum grad^2 / r(P) falls below the ~1e-15 rounding of the FP64
+# mass (each side sums the plan with its own exp): below this gradient norm the
+# two sides may accept different step lengths
+ALPHA_DECIDABLE = 1e-7
 CLOSE = ("eps_d", "start_err", "gnorm", "gnorm_next")
 RHO_CAP = 1.0 - 2.0 ** -30
 
@@ -65,6 +72,8 @@ def compare_traces(tg, to, where):
     assert tg["n_newton"] == to["n_newton"], (where, tg["n_newton"], to["n_newton"])
     for k in EXACT:
         np.testing.assert_array_equal(tg[k], to[k], err_msg=f"{where}: {k}")
+    dec = to["gnorm"] >= ALPHA_DECIDABLE
+    np.testing.assert_array_equal(tg["alpha"][dec], to["alpha"][dec], err_msg=f"{where}: alpha")
     capped = to["rho_out"] > RHO_CAP
     kc = int(np.argmax(capped)) if capped.any() else len(capped)   # first capped Newton step
     tc = int(to["step_of"][kc]) if capped.any() else len(to["beta"]) + 1
