@@ -211,6 +211,10 @@ typedef struct {
     int32_t warm_start;     /* 1: f, g on input are the potentials that start the first
                                projection (Alg. 1's z^(1), converted to log units at
                                gamma_init) instead of (log r~, log c~); 0             */
+    int32_t batch_persistent; /* eot_solve_batched: 1 solves every problem it can (dense or
+                               d = 2, 3 points, n, m <= 16384, TNP projection, no warm
+                               start) in one persistent launch on the device; 0 uses
+                               host worker threads for every problem; 1               */
 } eot_solve_opts;
 
 typedef struct {
@@ -225,7 +229,9 @@ typedef struct {
     double cost;            /* <P, C> at the output potentials, FP64                    */
     double dual_value;      /* W = gamma (<u, r> + <v, c> - sum P + 1), cost units      */
     double rho_last, delta_min_last;
-    double seconds;         /* host wall-clock of the call                              */
+    double seconds;         /* wall-clock of the solve: the host's, or in the persistent
+                               batch the device's from the team's start of the problem
+                               to its end                                              */
 } eot_solve_stats;
 
 void eot_solve_opts_default(eot_solve_opts* opts);
@@ -329,13 +335,23 @@ eot_status eot_round(const eot_cost* cost, double gamma, const double* f, const 
                      size_t ws_bytes, void* stream);
 
 /* Batched solves: many independent problems (any mix of sizes and cost kinds)
- * solved with one shared option set. A native scheduler runs `workers` host
- * threads, each with its own non-blocking HIP stream (default priority) and
- * its own slice of the workspace; problems are dealt largest n m first to
- * whichever worker is free, so small problems fill in behind large ones and
- * the GPU runs up to `workers` solves at once. Each problem's arithmetic is
- * exactly that of eot_solve on it (same kernels, same order): results are
- * bitwise identical to solving the problems one by one.
+ * solved with one shared option set.
+ * Persistent path (opts->batch_persistent, default): every problem with a dense
+ * cost or d = 2, 3 points and n, m <= 16384 is solved by ONE cooperative kernel
+ * launch per cost kind. The grid (the co-resident capacity, at most 1024
+ * workgroups) is split into teams of K workgroups (K from the largest n m);
+ * each team takes problems from a device queue, largest n m first, and runs
+ * the whole solve (Algs. 1-4, the CG iterations, the line search and the FP64
+ * report) on the device with team barriers, without host round trips. Same
+ * algorithm, decisions and tolerances as eot_solve; the passes are the
+ * persistent kernel's own (fixed summation order, reproducible run to run, not
+ * bitwise those of eot_solve). Wait bound: a team barrier that waits longer
+ * than ~16 s aborts the launch and the affected problems report EOT_ERR_HIP.
+ * Host-worker path (the other problems, or all with batch_persistent = 0): a
+ * native scheduler runs `workers` host threads, each with its own non-blocking
+ * HIP stream (default priority) and its own slice of the workspace; problems
+ * are dealt largest n m first to whichever worker is free. Each problem's
+ * arithmetic is exactly that of eot_solve on it: bitwise identical results.
  * probs: host array of nprob entries (device pointers inside); stats and
  * status: host arrays of nprob entries (nullable). Work on the caller's stream
  * that precedes the call is waited for; the call returns when every problem

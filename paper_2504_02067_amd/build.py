@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libeot.so")
-SOURCES = ["eot_kernels.hip", "eot_highd.hip", "eot_api.hip"]
+SOURCES = ["eot_kernels.hip", "eot_highd.hip", "eot_team.hip", "eot_api.hip"]
 # Per-source options: the matrix-core pass keeps its MFMA accumulators in
 # ordinary VGPRs (no accumulator-register copies before the epilogue reads them).
 EXTRA = {"eot_highd.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}

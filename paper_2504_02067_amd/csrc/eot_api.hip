@@ -1163,7 +1163,8 @@ bool bad_opts(const eot_solve_opts& o)
            !(o.p >= 1.0) || !(o.q1 > 1.0) || !(o.w_r > 0.0 && o.w_r < 0.5) || o.max_cg < 1 ||
            o.max_levels < 0 || o.max_backtrack < 0 || o.max_newton < 0 || o.max_sinkhorn < 0 ||
            o.max_mdot < 1 || (o.projection != EOT_PROJ_TNP && o.projection != EOT_PROJ_SINKHORN) ||
-           (o.warm_start != 0 && o.warm_start != 1);
+           (o.warm_start != 0 && o.warm_start != 1) ||
+           (o.batch_persistent != 0 && o.batch_persistent != 1);
 }
 
 bool bad_state(const eot_solve_state* s, bool in)
@@ -1401,6 +1402,171 @@ eot_status round_impl(Ctx& x, double gamma, const double* f, const double* g, co
 
 }  // namespace
 
+namespace {
+
+// ---------------------------------------------------------------- persistent batch
+// Problems the persistent team solver takes (eot_team.hip): dense costs and 2-D /
+// 3-D points with n, m <= kTeamMaxDim. Team kind: 0 dense FP32, 1 dense FP64,
+// 2 / 3 points.
+int team_kind(const eot_cost& c)
+{
+    if (c.n > kTeamMaxDim || c.m > kTeamMaxDim) return -1;
+    if (c.kind == EOT_COST_DENSE_F32) return 0;
+    if (c.kind == EOT_COST_DENSE_F64) return 1;
+    if (c.kind == EOT_COST_SQEUCLID_POINTS && (c.d == 2 || c.d == 3)) return c.d;
+    return -1;
+}
+
+// Workgroups per team from the largest problem: a team of K workgroups runs at
+// about K / 4 compute units (4 workgroups of 256 threads per unit), so the
+// largest problems get more of them; small ones still share the chip through
+// many teams.
+int team_size_for(int64_t max_nm)
+{
+    if (max_nm >= (int64_t)4 << 20) return 16;
+    if (max_nm >= (int64_t)1 << 20) return 8;
+    if (max_nm >= (int64_t)1 << 18) return 4;
+    if (max_nm >= (int64_t)1 << 16) return 2;
+    return 1;
+}
+
+struct TeamPlan {
+    int count = 0;                 // problems the team solver can take
+    int K = 1;
+    int64_t vstride = 0;
+    size_t off_table = 0, off_order = 0, off_out = 0, off_vec = 0, off_priv = 0, off_sync = 0;
+    size_t bytes = 0;
+};
+
+// Workspace layout of the persistent path (sized for the largest grid).
+TeamPlan team_plan(int32_t nprob, const eot_batch_problem* probs)
+{
+    TeamPlan t;
+    int64_t dim = 0, max_nm = 0;
+    for (int32_t k = 0; k < nprob; ++k) {
+        const eot_cost& c = probs[k].cost;
+        if (team_kind(c) < 0) continue;
+        t.count += 1;
+        dim = std::max(dim, std::max(c.n, c.m));
+        max_nm = std::max(max_nm, c.n * c.m);
+    }
+    if (t.count == 0) return t;
+    t.K = team_size_for(max_nm);
+    t.vstride = (dim + 63) / 64 * 64;
+    const int64_t nteams = kTeamMaxGrid / t.K;
+    size_t off = 0;
+    auto take = [&](size_t b) { const size_t o = off; off += align_up(b); return o; };
+    t.off_table = take(sizeof(TeamProblem) * (size_t)nprob);
+    t.off_order = take(sizeof(int32_t) * (size_t)nprob);
+    t.off_out = take(sizeof(eot_solve_stats) * (size_t)nprob);
+    t.off_vec = take(sizeof(double) * (size_t)nteams * (size_t)team_doubles_of(t.vstride, t.K));
+    t.off_priv = take(sizeof(double) * (size_t)kTeamMaxGrid * kTeamPriv * (size_t)t.vstride);
+    t.off_sync = take(sizeof(uint32_t) * 16 * (size_t)kTeamMaxGrid + 256);
+    t.bytes = off;
+    return t;
+}
+
+// Solves the problems marked in `sel` with the persistent team kernel, one
+// cooperative launch per cost kind, in order on `s`. Fills st_all / stats_all
+// for them.
+eot_status team_batch(int32_t nprob, const eot_batch_problem* probs,
+                      const eot_solve_opts* opts, const std::vector<char>& sel, char* ws,
+                      hipStream_t s, std::vector<eot_status>& st_all,
+                      std::vector<eot_solve_stats>& stats_all)
+{
+    const TeamPlan tp = team_plan(nprob, probs);
+    if (tp.count == 0) return EOT_OK;
+    const size_t host_bytes = sizeof(TeamProblem) * (size_t)nprob +
+                              sizeof(int32_t) * (size_t)nprob +
+                              sizeof(eot_solve_stats) * (size_t)nprob;
+    void* hbuf = nullptr;                          // pinned staging for the table and the stats
+    HIPCHK(hipHostMalloc(&hbuf, host_bytes, hipHostMallocDefault));
+    struct Free { void* p; ~Free() { (void)hipHostFree(p); } } free_guard{hbuf};
+    TeamProblem* htab = static_cast<TeamProblem*>(hbuf);
+    int32_t* hord = reinterpret_cast<int32_t*>(htab + nprob);
+    eot_solve_stats* hout = reinterpret_cast<eot_solve_stats*>(hord + nprob);
+    for (int32_t k = 0; k < nprob; ++k) {
+        const eot_batch_problem& p = probs[k];
+        TeamProblem& q = htab[k];
+        q.kind = p.cost.kind;
+        q.d = p.cost.d;
+        q.n = p.cost.n;
+        q.m = p.cost.m;
+        q.ldc = p.cost.ldc;
+        q.C = p.cost.C;
+        q.X = p.cost.X;
+        q.Y = p.cost.Y;
+        q.scale = p.cost.scale;
+        q.r = p.r;
+        q.c = p.c;
+        q.f = p.f;
+        q.g = p.g;
+    }
+    TeamProblem* dtab = reinterpret_cast<TeamProblem*>(ws + tp.off_table);
+    int32_t* dord = reinterpret_cast<int32_t*>(ws + tp.off_order);
+    eot_solve_stats* dout = reinterpret_cast<eot_solve_stats*>(ws + tp.off_out);
+    HIPCHK(hipMemcpyAsync(dtab, htab, sizeof(TeamProblem) * (size_t)nprob,
+                          hipMemcpyHostToDevice, s));
+    for (int kind = 0; kind < 4; ++kind) {
+        std::vector<int32_t> order;
+        for (int32_t k = 0; k < nprob; ++k)
+            if (sel[(size_t)k] && team_kind(probs[k].cost) == kind) order.push_back(k);
+        if (order.empty()) continue;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+            return probs[a].cost.n * probs[a].cost.m > probs[b].cost.n * probs[b].cost.m;
+        });
+        int bpc = 0, cus = 0;
+        HIPCHK(team_max_grid(kind, &bpc, &cus));
+        int K = tp.K;
+        int grid = std::min(bpc * cus, kTeamMaxGrid);
+        while (K > 1 && grid < 8 * K) K /= 2;
+        // the team vectors were sized for kTeamMaxGrid / tp.K teams of tp.K members
+        const int64_t alloc = (int64_t)(kTeamMaxGrid / tp.K) * team_doubles_of(tp.vstride, tp.K);
+        grid = (int)std::min<int64_t>(grid, alloc / team_doubles_of(tp.vstride, K) * K);
+        grid = grid / (8 * K) * (8 * K);
+        if (grid < 8) return EOT_ERR_HIP;           // no co-resident team fits
+        // wait for the table upload before the order array is overwritten
+        HIPCHK(hipStreamSynchronize(s));
+        std::memcpy(hord, order.data(), sizeof(int32_t) * order.size());
+        HIPCHK(hipMemcpyAsync(dord, hord, sizeof(int32_t) * order.size(),
+                              hipMemcpyHostToDevice, s));
+        uint32_t* sync = reinterpret_cast<uint32_t*>(ws + tp.off_sync);
+        const int nteams = grid / K;
+        const size_t sync_words = 16 * (size_t)nteams + 64;
+        HIPCHK(launch_fill(reinterpret_cast<double*>(sync), 0.0, (int64_t)(sync_words / 2), s));
+        TeamLaunch L{};
+        L.probs = dtab;
+        L.order = dord;
+        L.nprob = (int32_t)order.size();
+        L.K = K;
+        L.nteams = nteams;
+        L.out = dout;
+        L.vec = reinterpret_cast<double*>(ws + tp.off_vec);
+        L.vstride = tp.vstride;
+        L.team_doubles = team_doubles_of(tp.vstride, K);
+        L.priv = reinterpret_cast<double*>(ws + tp.off_priv);
+        L.sync = sync;
+        L.queue = reinterpret_cast<int32_t*>(sync + 16 * (size_t)nteams);
+        L.abort = L.queue + 16;
+        L.opts = *opts;
+        HIPCHK(launch_team_solve(kind, L, grid, s));
+        HIPCHK(hipMemcpyAsync(hout, dout, sizeof(eot_solve_stats) * (size_t)nprob,
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        int dev = 0, khz = 0;
+        HIPCHK(hipGetDevice(&dev));
+        HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        for (int32_t k : order) {
+            stats_all[(size_t)k] = hout[k];
+            stats_all[(size_t)k].seconds = khz > 0 ? hout[k].seconds / (1e3 * khz) : 0.0;
+            st_all[(size_t)k] = (eot_status)hout[k].status;
+        }
+    }
+    return EOT_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 eot_status eot_workspace_size(int32_t op, const eot_cost* cost, int32_t prec, size_t* bytes)
@@ -1575,6 +1741,7 @@ void eot_solve_opts_default(eot_solve_opts* o)
     o->cg_graph = 0;
     o->verbose = 0;
     o->warm_start = 0;
+    o->batch_persistent = 1;
 }
 
 eot_status eot_solve(const eot_cost* cost, const double* r, const double* c,
@@ -1610,7 +1777,8 @@ eot_status eot_workspace_size_batched(int32_t nprob, const eot_batch_problem* pr
         EOTCHK(eot_workspace_size(EOT_OP_SOLVE, &probs[k].cost, 0, &b));
         slice = std::max(slice, align_up(b));
     }
-    *bytes = slice * (size_t)std::min(workers, nprob) + kAlign;
+    const TeamPlan tp = team_plan(nprob, probs);
+    *bytes = tp.bytes + slice * (size_t)std::min(workers, nprob) + kAlign;
     return EOT_OK;
 }
 
@@ -1630,17 +1798,51 @@ eot_status eot_solve_batched(int32_t nprob, const eot_batch_problem* probs,
     EOTCHK(eot_workspace_size_batched(nprob, probs, workers, &need));
     if (!ws || ws_bytes < need - kAlign || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0)
         return EOT_ERR_WORKSPACE;
-    const int nw = std::min(workers, nprob);
-    const size_t slice = (need - kAlign) / (size_t)nw;
+    hipStream_t caller = static_cast<hipStream_t>(stream);
+    // a problem no worker reached (a worker that could not select the device) reports EOT_ERR_HIP
+    std::vector<eot_status> st_all((size_t)nprob, EOT_ERR_HIP);
+    std::vector<eot_solve_stats> stats_all((size_t)nprob);
+    // Persistent path: the problems the team kernel takes.
+    const TeamPlan tp = team_plan(nprob, probs);
+    std::vector<char> on_team((size_t)nprob, 0);
+    const bool persistent = opts->batch_persistent != 0 && opts->projection == EOT_PROJ_TNP &&
+                            opts->warm_start == 0;
+    int32_t n_team = 0;
+    if (persistent)
+        for (int32_t k = 0; k < nprob; ++k)
+            if (team_kind(probs[k].cost) >= 0 &&
+                !(probs[k].cost.kind == EOT_COST_DENSE_F64 && opts->precision == EOT_PREC_MIXED)) {
+                on_team[(size_t)k] = 1;
+                ++n_team;
+            }
+    if (n_team > 0) {
+        const eot_status ts = team_batch(nprob, probs, opts, on_team, static_cast<char*>(ws),
+                                         caller, st_all, stats_all);
+        if (ts != EOT_OK) return ts;
+    }
+    // Host workers for the rest.
+    std::vector<int32_t> order;
+    for (int32_t k = 0; k < nprob; ++k)
+        if (!on_team[(size_t)k]) order.push_back(k);
+    const int nw = std::min<int>(workers, std::max<int>(1, (int)order.size()));
+    char* wbase = static_cast<char*>(ws) + tp.bytes;
+    const size_t slice = (need - kAlign - tp.bytes) / (size_t)std::min(workers, nprob);
     // Longest first: problems in decreasing n m, dealt to whichever worker is free.
-    std::vector<int32_t> order((size_t)nprob);
-    std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
         return probs[a].cost.n * probs[a].cost.m > probs[b].cost.n * probs[b].cost.m;
     });
+    const int32_t n_work = (int32_t)order.size();
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
-    hipStream_t caller = static_cast<hipStream_t>(stream);
+    if (n_work == 0) {
+        for (int32_t i = 0; i < nprob; ++i) {
+            if (status) status[i] = st_all[(size_t)i];
+            if (stats) stats[i] = stats_all[(size_t)i];
+        }
+        for (int32_t i = 0; i < nprob; ++i)
+            if (st_all[(size_t)i] != EOT_OK) return st_all[(size_t)i];
+        return EOT_OK;
+    }
     hipEvent_t start;
     HIPCHK(hipEventCreateWithFlags(&start, hipEventDisableTiming));
     HIPCHK(hipEventRecord(start, caller));
@@ -1653,16 +1855,13 @@ eot_status eot_solve_batched(int32_t nprob, const eot_batch_problem* probs,
             hipStreamWaitEvent(streams[w], start, 0) != hipSuccess)
             setup_err = EOT_ERR_HIP;
     }
-    // a problem no worker reached (a worker that could not select the device) reports EOT_ERR_HIP
-    std::vector<eot_status> st_all((size_t)nprob, EOT_ERR_HIP);
-    std::vector<eot_solve_stats> stats_all((size_t)nprob);
     std::atomic<int32_t> next{0};
     auto work = [&](int w) {
         if (hipSetDevice(dev) != hipSuccess) return;
-        char* base = static_cast<char*>(ws) + (size_t)w * slice;
+        char* base = wbase + (size_t)w * slice;
         for (;;) {
             const int32_t k = next.fetch_add(1);
-            if (k >= nprob) break;
+            if (k >= n_work) break;
             const int32_t i = order[(size_t)k];
             const eot_batch_problem& p = probs[i];
             st_all[(size_t)i] = solve_one(&p.cost, p.r, p.c, opts, p.f, p.g, &stats_all[(size_t)i],

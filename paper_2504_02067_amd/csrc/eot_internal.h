@@ -253,5 +253,47 @@ hipError_t launch_cg_small(const double* part, int tiles, int64_t n, int64_t m, 
                            const double* w, double* ptd, CgScalars* sc, int32_t* mirror,
                            hipStream_t s);
 
+// ---- batched solves in one persistent launch (eot_team.hip)
+constexpr int kTeamThreads = 256;        // threads per workgroup
+constexpr int kTeamVecs = 40;            // FP64 vectors per team
+constexpr int kTeamPriv = 3;             // FP64 scratch vectors per workgroup
+constexpr int kTeamMaxGrid = 1024;       // workgroups per launch at most
+constexpr int64_t kTeamMaxDim = 16384;   // n, m of a problem the team solver takes
+struct TeamProblem {
+    int32_t kind, d;
+    int64_t n, m, ldc;
+    const void* C;
+    const float* X;
+    const float* Y;
+    double scale;
+    const double* r;
+    const double* c;
+    double* f;
+    double* g;
+};
+struct TeamLaunch {
+    const TeamProblem* probs;   // device table
+    const int32_t* order;       // problem indices, largest first (device)
+    int32_t nprob;              // entries of order
+    int32_t K;                  // workgroups per team
+    int32_t nteams;
+    eot_solve_stats* out;       // device, indexed like probs
+    double* vec;                // [nteams][team_doubles]
+    int64_t vstride;            // doubles per vector (>= every n, m; multiple of 64)
+    int64_t team_doubles;       // kTeamVecs * vstride + K * vstride + 2 * K * 8, rounded up
+    double* priv;               // [grid][kTeamPriv][vstride]
+    uint32_t* sync;             // [nteams][16], zeroed before the launch
+    int32_t* queue;             // next entry of order (zeroed)
+    int32_t* abort;             // set when a team wait timed out (zeroed)
+    eot_solve_opts opts;
+};
+inline int64_t team_doubles_of(int64_t vstride, int K)
+{
+    return ((int64_t)kTeamVecs * vstride + (int64_t)K * vstride + 2 * (int64_t)K * 8 + 63) / 64 * 64;
+}
+// kind: 0 dense FP32, 1 dense FP64, 2 / 3 points in R^2 / R^3; grid a multiple of 8 K,
+// at most the co-resident capacity (team_max_grid). Cooperative launch.
+hipError_t launch_team_solve(int kind, const TeamLaunch& L, int grid, hipStream_t s);
+hipError_t team_max_grid(int kind, int* blocks_per_cu, int* cus);
 
 }  // namespace eot

@@ -1,0 +1,1164 @@
+// Batched solves in one persistent launch.
+//
+// The grid is split into teams of K workgroups. A team takes whole problems from
+// a shared queue (largest first) and solves each of them entirely on the device:
+// MDOT (Alg. 1) with the smoothing of Sec. 3.4 and AdjustSchedule (Sec. 3.3),
+// TruncatedNewtonProject (Alg. 4) with ChiSinkhorn (Alg. 3), NewtonSolve (Alg. 2)
+// with the warm discount of App. B and its preconditioned CG, the FP64 line
+// search, and the FP64 report at the output potentials. The control decisions
+// are the host driver's (eot_api.hip), taken here by every workgroup of the team
+// from team-wide sums, which all members add up in the same fixed order, so the
+// whole team follows one control flow without exchanging decisions.
+//
+// Work split inside a team: workgroup k owns rows [k n / K, (k + 1) n / K) and
+// columns [k m / K, (k + 1) m / K) of every vector. A row-sum pass covers the
+// owned rows against all columns; a column-sum pass covers the owned rows
+// against all columns too and writes per-member column partials that the column
+// owners add in member order. Every pass starts with a team barrier (its inputs
+// may have been written by other members), every team sum ends with one.
+//
+// Team barriers: one counter and one generation word per team in device memory,
+// agent-scope atomics with release / acquire fences around them; every wait is
+// bounded (about 16 s of polling), after which the workgroup raises the launch's
+// abort flag and every member leaves its problem loop, so the kernel always
+// ends. The grid is sized to the co-resident capacity and launched
+// cooperatively, so all members of a team are resident together.
+//
+// Plan entries (log units, shifted by the row value a_i):
+//   FP64:  e_ij = exp(u_i - a_i + v_j - beta C_ij)                (table exp, FP64)
+//   mixed: e_ij = 2^float(U_i + V_j - B C_ij),  U = log2(e)(u - a), V = log2(e) v,
+//          B = log2(e) beta: the exponent is formed in FP64 from the FP64
+//          potentials and rounded once to FP32 (relative error of e_ij about
+//          4.1e-8 |log2 e_ij| + the 1-ulp exp2), the cost itself is FP32
+//          (points: |x - y|^2 in FP32), every sum is FP64.
+// Range guards as in the streaming passes: a shifted row sum outside
+// (2^-64, 2^64) or a column sum that is 0 / not finite makes the step redo its
+// passes in FP64 from exact row maxima.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <type_traits>
+
+#include "eot_internal.h"
+#include "eot_lanes.h"
+
+namespace eot {
+namespace {
+
+constexpr int TT = kTeamThreads;          // threads per workgroup
+constexpr int TW = TT / 64;               // waves per workgroup
+constexpr double kL2E = 1.4426950408889634074;
+constexpr double kRhoCap = 1.0 - 9.313225746154785e-10;   // 1 - 2^-30, as NewtonSolve's host driver
+constexpr uint32_t kSpinLimit = 1u << 24;
+constexpr int kRedSlots = 8;
+
+// Team vectors (n-side first, then m-side), each kTeamVecStride-aligned.
+enum TeamVec : int {
+    V_U, V_LR, V_S, V_RT, V_LRT, V_DU, V_UPREV, V_UA, V_SH, V_SH2, V_RP, V_GRAD, V_B, V_D, V_E1,
+    V_DTRY, V_RES, V_Z, V_P, V_Q, V_T, V_M, V_PCPTD, V_PCPTDT, V_ROWA, V_ROWB,
+    V_V, V_CT, V_LCT, V_INVCT, V_DV, V_VPREV, V_VA, V_COLSUM, V_W, V_WC, V_PTD, V_PTDT, V_COLT,
+    kTeamVecCount
+};
+static_assert(kTeamVecCount <= kTeamVecs, "team vector budget");
+
+struct Team {
+    int K, k;
+    int64_t n, m, r0, r1, c0, c1;
+    double* vec;
+    int64_t vs;
+    double* cpart;          // [K][vs] column partials
+    double* red;            // [2][K][kRedSlots]
+    uint32_t* sync;         // [0] count, [1] generation, [2] problem index
+    int32_t* abort;
+    double* priv;           // this workgroup's scratch [kTeamPriv][vs]
+    double* s_red;          // LDS, TW doubles
+    double* s_exp;          // LDS, FP64 exp table
+    int* s_flag;            // LDS, 1 int: a pass's range flag
+    int* s_ab;              // LDS, 1 int: the abort flag as seen at the last barrier
+    int rc;                 // reduction parity
+    bool ab;                // this workgroup saw the abort flag
+    __device__ double* V(int id) const { return vec + (int64_t)id * vs; }
+    __device__ double* W(int id) const { return priv + (int64_t)id * vs; }
+};
+
+__device__ __forceinline__ double wsum(double x)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+__device__ __forceinline__ double wmax(double x)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
+    return x;
+}
+
+// Workgroup sum in a fixed order (wave butterflies, then waves in order).
+__device__ __forceinline__ double wg_sum(double x, double* s_red)
+{
+    x = wsum(x);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    double r = 0.0;
+#pragma unroll
+    for (int w = 0; w < TW; ++w) r += s_red[w];
+    __syncthreads();
+    return r;
+}
+
+__device__ void team_barrier(Team& T)
+{
+    __syncthreads();
+    if (T.K > 1) {
+        if (threadIdx.x == 0) {
+            uint32_t* cnt = T.sync;
+            uint32_t* gen = T.sync + 1;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const uint32_t g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t a =
+                __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            int ab = 0;
+            if (a == (uint32_t)T.K - 1) {
+                __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                uint32_t spins = 0;
+                while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                    __builtin_amdgcn_s_sleep(2);
+                    if (__hip_atomic_load(T.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+                    if (++spins > kSpinLimit) {
+                        __hip_atomic_store(T.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            ab = __hip_atomic_load(T.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            *T.s_ab = ab;
+        }
+        __syncthreads();
+        T.ab = *T.s_ab != 0;
+        __syncthreads();
+    }
+}
+
+// Team-wide sums of N per-thread partials: workgroup sums, one slot per member,
+// a barrier, then every member adds the K slots in member order.
+template <int N>
+__device__ void team_sums(Team& T, double (&x)[N])
+{
+    static_assert(N <= kRedSlots, "slots");
+    double* slot = T.red + ((int64_t)(T.rc & 1) * T.K) * kRedSlots;
+    T.rc += 1;
+#pragma unroll
+    for (int s = 0; s < N; ++s) {
+        const double w = wg_sum(x[s], T.s_red);
+        if (threadIdx.x == 0) slot[(int64_t)T.k * kRedSlots + s] = w;
+    }
+    team_barrier(T);
+#pragma unroll
+    for (int s = 0; s < N; ++s) {
+        double r = 0.0;
+        for (int q = 0; q < T.K; ++q) r += slot[(int64_t)q * kRedSlots + s];
+        x[s] = r;
+    }
+}
+
+__device__ __forceinline__ double team_sum(Team& T, double x)
+{
+    double a[1] = {x};
+    team_sums<1>(T, a);
+    return a[0];
+}
+
+#define OWN_ROWS(i) for (int64_t i = T.r0 + threadIdx.x; i < T.r1; i += TT)
+#define OWN_COLS(j) for (int64_t j = T.c0 + threadIdx.x; j < T.c1; j += TT)
+
+// ---------------------------------------------------------------- cost access
+// KIND: 0 dense FP32, 1 dense FP64, 2 / 3 points in R^2 / R^3.
+template <int KIND>
+struct Pts {
+    static constexpr int D = KIND >= 2 ? KIND : 1;
+};
+
+template <int KIND, bool MIXED>
+__device__ __forceinline__ auto cost_at(const TeamProblem& P, int64_t i, int64_t j,
+                                        const float (&x)[Pts<KIND>::D],
+                                        const float (&y)[Pts<KIND>::D])
+{
+    using R = typename std::conditional<MIXED, float, double>::type;
+    if constexpr (KIND == 0) {
+        return (R) static_cast<const float*>(P.C)[i * P.ldc + j];
+    } else if constexpr (KIND == 1) {
+        return (R) static_cast<const double*>(P.C)[i * P.ldc + j];
+    } else {
+        R c = 0;
+#pragma unroll
+        for (int q = 0; q < KIND; ++q) {
+            const R t = (R)x[q] - (R)y[q];
+            c = q == 0 ? t * t : (R)fma(t, t, c);
+        }
+        return c;
+    }
+}
+
+template <int KIND>
+__device__ __forceinline__ void load_pt(const float* Z, int64_t i, float (&z)[Pts<KIND>::D])
+{
+    if constexpr (KIND >= 2) {
+#pragma unroll
+        for (int q = 0; q < KIND; ++q) z[q] = Z[i * KIND + q];
+    } else {
+        z[0] = 0.0f;
+        (void)Z;
+        (void)i;
+    }
+}
+
+// The FP64 exp table in LDS, at namespace scope so that the passes (separate
+// functions) address it as LDS.
+__shared__ __attribute__((aligned(16))) double t_exp[128];
+
+// Plan entry from the FP64 exponent base (row part + column part) and the cost.
+template <bool MIXED, typename R>
+__device__ __forceinline__ double entry(double base, double bb, R c, const double*)
+{
+    if constexpr (MIXED)
+        return (double)__builtin_amdgcn_exp2f((float)fma(-bb, (double)c, base));
+    else
+        return exp_tab64(fma(-bb, (double)c, base), t_exp);
+}
+
+// Inverse temperature the entries see (points: C = |x - y|^2 / scale), times
+// log2(e) in mixed mode.
+template <int KIND, bool MIXED>
+__device__ __forceinline__ double beta_eff(const TeamProblem& P, double beta)
+{
+    const double b = KIND >= 2 ? beta / P.scale : beta;
+    return MIXED ? kL2E * b : b;
+}
+
+enum : int { RS_WEIGHT = 0, RS_SQUARE = 1, RS_COST = 2 };
+
+// Row sums over the owned rows, all columns:
+//   s0_i = sum_j e_ij w0_j,  s1_i = sum_j e_ij^2 w1_j (SQUARE) or e_ij C_ij (COST)
+// with e_ij shifted by a_i. epi(i, s0, s1) runs on one lane per row.
+template <int KIND, bool MIXED, int NS, int MODE, class Epi>
+__device__ void row_pass(Team& T, const TeamProblem& P, double beta, const double* u,
+                         const double* a, const double* v, const double* w0, const double* w1,
+                         Epi&& epi)
+{
+    team_barrier(T);
+    const int64_t m = T.m;
+    double* colv = T.W(0);
+    double* cw0 = T.W(1);
+    double* cw1 = T.W(2);
+    for (int64_t j = threadIdx.x; j < m; j += TT) {
+        colv[j] = MIXED ? kL2E * v[j] : v[j];
+        cw0[j] = w0 ? w0[j] : 1.0;
+        if constexpr (NS > 1 && MODE == RS_SQUARE) cw1[j] = w1 ? w1[j] : 1.0;
+    }
+    __syncthreads();
+    const double bb = beta_eff<KIND, MIXED>(P, beta);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t H = T.r1 - T.r0;
+    const int64_t nq = (H + 3) / 4;
+    for (int64_t qd = wave; qd < nq; qd += TW) {
+        int64_t ir[4];
+        double rb[4];
+        float x[4][Pts<KIND>::D];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t i = T.r0 + 4 * qd + r;
+            ir[r] = i < T.r1 ? i : T.r1 - 1;                 // clamped: in bounds
+            const double base = u[ir[r]] - a[ir[r]];
+            rb[r] = MIXED ? kL2E * base : base;
+            load_pt<KIND>(P.X, ir[r], x[r]);
+        }
+        double acc0[4] = {0.0, 0.0, 0.0, 0.0}, acc1[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+        for (int64_t j = lane; j < m; j += 64) {
+            float y[Pts<KIND>::D];
+            load_pt<KIND>(P.Y, j, y);
+            const double cv = colv[j], ww0 = cw0[j];
+            double ww1 = 0.0;
+            if constexpr (NS > 1 && MODE == RS_SQUARE) ww1 = cw1[j];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const auto c = cost_at<KIND, MIXED>(P, ir[r], j, x[r], y);
+                const double e = entry<MIXED>(rb[r] + cv, bb, c, T.s_exp);
+                acc0[r] = fma(e, ww0, acc0[r]);
+                if constexpr (NS > 1) {
+                    if constexpr (MODE == RS_SQUARE) acc1[r] = fma(e * e, ww1, acc1[r]);
+                    else acc1[r] = fma(e, (double)c, acc1[r]);
+                }
+            }
+        }
+        if constexpr (NS == 1) {
+            const double s = wave_transpose_sum<4>(acc0, lane);
+            const int r = lane >> 4;
+            const int64_t i = T.r0 + 4 * qd + r;
+            if ((lane & 15) == 0 && i < T.r1) epi(i, s, 0.0);
+        } else {
+            double g[8];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                g[r] = acc0[r];
+                g[4 + r] = acc1[r];
+            }
+            const double s = wave_transpose_sum<8>(g, lane);
+            // lane l holds value (l >> 3): rows 0..3 of s0 in lanes 0..31, of s1 in 32..63
+            const double s1 = __shfl(s, (lane + 32) & 63, 64);
+            const int r = lane >> 3;
+            const int64_t i = T.r0 + 4 * qd + r;
+            if (lane < 32 && (lane & 7) == 0 && i < T.r1) epi(i, s, s1);
+        }
+    }
+    __syncthreads();                    // outputs visible to every thread of the workgroup
+}
+
+// Column sums over all rows: colsum_j = sum_i exp(a_i) xw_i e_ij (xw nullable =
+// 1). Each member sums its own rows for all columns into its partial row; after a
+// barrier the column owners add the K partials in member order: epi(j, sum).
+template <int KIND, bool MIXED, class Epi>
+__device__ void col_pass(Team& T, const TeamProblem& P, double beta, const double* u,
+                         const double* a, const double* v, const double* xw, Epi&& epi)
+{
+    team_barrier(T);
+    const int64_t m = T.m;
+    double* rowb = T.W(0);      // exponent base of the owned rows
+    double* roww = T.W(1);      // exp(a_i) xw_i
+    double* colv = T.W(2);
+    OWN_ROWS(i) {
+        const double base = u[i] - a[i];
+        rowb[i] = MIXED ? kL2E * base : base;
+        roww[i] = exp(a[i]) * (xw ? xw[i] : 1.0);
+    }
+    for (int64_t j = threadIdx.x; j < m; j += TT) colv[j] = MIXED ? kL2E * v[j] : v[j];
+    __syncthreads();
+    const double bb = beta_eff<KIND, MIXED>(P, beta);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t H = T.r1 - T.r0;
+    // wave w takes rows r0 + w, r0 + w + TW, ...; a chunk is 256 columns (4 per lane)
+    double* out = T.K > 1 ? T.cpart + (int64_t)T.k * T.vs : nullptr;
+    __shared__ double s_cp[TW][256];
+    for (int64_t jc = 0; jc < m; jc += 256) {
+        int64_t jj[4];
+        float y[4][Pts<KIND>::D];
+        double cv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t j = jc + lane + 64 * q;
+            jj[q] = j < m ? j : m - 1;
+            load_pt<KIND>(P.Y, jj[q], y[q]);
+            cv[q] = j < m ? colv[jj[q]] : -INFINITY;
+        }
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+        for (int64_t ii = wave; ii < H; ii += TW) {
+            const int64_t i = T.r0 + ii;
+            float x[Pts<KIND>::D];
+            load_pt<KIND>(P.X, i, x);
+            const double rbv = rowb[i], rw = roww[i];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const auto c = cost_at<KIND, MIXED>(P, i, jj[q], x, y[q]);
+                const double e = entry<MIXED>(rbv + cv[q], bb, c, T.s_exp);
+                acc[q] = fma(e, rw, acc[q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s_cp[wave][lane + 64 * q] = acc[q];
+        __syncthreads();
+        {
+            const int64_t j = jc + threadIdx.x;
+            double s = 0.0;
+#pragma unroll
+            for (int w = 0; w < TW; ++w) s += s_cp[w][threadIdx.x];
+            if (j < m) {
+                if (out) out[j] = s;
+                else epi(j, s);
+            }
+        }
+        __syncthreads();
+    }
+    if (T.K > 1) {
+        team_barrier(T);
+        OWN_COLS(j) {
+            double s = 0.0;
+            for (int q = 0; q < T.K; ++q) s += T.cpart[(int64_t)q * T.vs + j];
+            epi(j, s);
+        }
+    }
+    __syncthreads();                    // outputs visible to every thread of the workgroup
+}
+
+// Exact row maxima max_j (u_i + v_j - beta C_ij) over the owned rows (FP64).
+template <int KIND>
+__device__ __noinline__ void row_max(Team& T, const TeamProblem& P, double beta, const double* u,
+                        const double* v, double* out)
+{
+    team_barrier(T);
+    const double bb = beta_eff<KIND, false>(P, beta);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int64_t i = T.r0 + wave; i < T.r1; i += TW) {
+        float x[Pts<KIND>::D];
+        load_pt<KIND>(P.X, i, x);
+        double mx = -INFINITY;
+#pragma unroll 1
+        for (int64_t j = lane; j < T.m; j += 64) {
+            float y[Pts<KIND>::D];
+            load_pt<KIND>(P.Y, j, y);
+            const double c = cost_at<KIND, false>(P, i, j, x, y);
+            mx = fmax(mx, fma(-bb, c, v[j]));
+        }
+        mx = wmax(mx);
+        if (lane == 0) out[i] = u[i] + mx;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- solver state
+struct Opt {
+    double tol, p, q1, w_r, gamma_init, gamma_final;
+    int adaptive_q, adaptive_rho0, max_cg, max_levels, max_backtrack, max_newton, max_sinkhorn,
+        max_mdot, precision, verify_fp64;
+};
+
+struct Ctl {
+    eot_solve_stats st;
+    int64_t passes;
+};
+
+constexpr double kRowLo = 5.421010862427522e-20;    // 2^-64
+constexpr double kRowHi = 1.8446744073709552e19;    // 2^64
+
+// log r(P) (and s_i = sum_j P_ij^2 / c_j when inv_c) at (u, v) with shift a.
+// Returns this workgroup's range flag count (not yet team-reduced).
+template <int KIND, bool MIXED>
+__device__ __noinline__ int row_marg(Team& T, const TeamProblem& P, Ctl& X, double beta, const double* u,
+                        const double* a, const double* v, const double* inv_c, double* lr,
+                        double* s)
+{
+    int* s_flag = T.s_flag;
+    __syncthreads();
+    if (threadIdx.x == 0) *s_flag = 0;
+    __syncthreads();
+    auto epi = [&](int64_t i, double s0, double s1) {
+        if (!(s0 > kRowLo && s0 < kRowHi)) atomicOr(s_flag, 1);
+        lr[i] = a[i] + log(s0);
+        if (inv_c) s[i] = exp(2.0 * a[i]) * s1;
+    };
+    if (inv_c)
+        row_pass<KIND, MIXED, 2, RS_SQUARE>(T, P, beta, u, a, v, nullptr, inv_c, epi);
+    else
+        row_pass<KIND, MIXED, 1, RS_WEIGHT>(T, P, beta, u, a, v, nullptr, nullptr, epi);
+    X.passes += 1;
+    __syncthreads();
+    const int f = *s_flag;
+    __syncthreads();
+    return f;
+}
+
+// Column sums of P xw (xw nullable = 1) into out (owned columns).
+template <int KIND, bool MIXED>
+__device__ __noinline__ void col_sums(Team& T, const TeamProblem& P, Ctl& X, double beta, const double* u,
+                         const double* a, const double* v, const double* xw, double* out)
+{
+    col_pass<KIND, MIXED>(T, P, beta, u, a, v, xw, [&](int64_t j, double s) { out[j] = s; });
+    X.passes += 1;
+}
+
+// Row sums exp(a_i) sum_j P_ij yw_j into out (owned rows).
+template <int KIND, bool MIXED>
+__device__ __noinline__ void row_sums(Team& T, const TeamProblem& P, Ctl& X, double beta, const double* u,
+                         const double* a, const double* v, const double* yw, double* out)
+{
+    row_pass<KIND, MIXED, 1, RS_WEIGHT>(T, P, beta, u, a, v, yw, nullptr,
+                                        [&](int64_t i, double s0, double) {
+                                            out[i] = exp(a[i]) * s0;
+                                        });
+    X.passes += 1;
+}
+
+template <int KIND>
+__device__ int row_marg_p(Team& T, const TeamProblem& P, Ctl& X, int prec, double beta,
+                          const double* u, const double* a, const double* v, const double* inv_c,
+                          double* lr, double* s)
+{
+    if constexpr (KIND == 1) {
+        return row_marg<KIND, false>(T, P, X, beta, u, a, v, inv_c, lr, s);
+    } else {
+        return prec == EOT_PREC_MIXED ? row_marg<KIND, true>(T, P, X, beta, u, a, v, inv_c, lr, s)
+                                      : row_marg<KIND, false>(T, P, X, beta, u, a, v, inv_c, lr, s);
+    }
+}
+
+template <int KIND>
+__device__ void col_sums_p(Team& T, const TeamProblem& P, Ctl& X, int prec, double beta,
+                           const double* u, const double* a, const double* v, const double* xw,
+                           double* out)
+{
+    if constexpr (KIND == 1) {
+        col_sums<KIND, false>(T, P, X, beta, u, a, v, xw, out);
+    } else {
+        if (prec == EOT_PREC_MIXED) col_sums<KIND, true>(T, P, X, beta, u, a, v, xw, out);
+        else col_sums<KIND, false>(T, P, X, beta, u, a, v, xw, out);
+    }
+}
+
+template <int KIND>
+__device__ void row_sums_p(Team& T, const TeamProblem& P, Ctl& X, int prec, double beta,
+                           const double* u, const double* a, const double* v, const double* yw,
+                           double* out)
+{
+    if constexpr (KIND == 1) {
+        row_sums<KIND, false>(T, P, X, beta, u, a, v, yw, out);
+    } else {
+        if (prec == EOT_PREC_MIXED) row_sums<KIND, true>(T, P, X, beta, u, a, v, yw, out);
+        else row_sums<KIND, false>(T, P, X, beta, u, a, v, yw, out);
+    }
+}
+
+// v_j += log c~_j - log colsum_j on the owned columns; returns the number of
+// columns whose sum was 0 or not finite (this workgroup's).
+__device__ int fix_cols(Team& T, double* v, const double* lct, const double* colsum)
+{
+    int bad = 0;
+    OWN_COLS(j) {
+        const double s = colsum[j];
+        if (s > 0.0 && s < INFINITY) v[j] += lct[j] - log(s);
+        else bad += 1;
+    }
+    return bad;
+}
+
+// Column fix followed by the row refresh (log r(P), s), with the FP64 redo from
+// exact row maxima when a range guard fired.
+template <int KIND>
+__device__ __noinline__ int fix_and_refresh(Team& T, const TeamProblem& P, Ctl& X, int prec, double beta,
+                               const double* shift)
+{
+    double *u = T.V(V_U), *v = T.V(V_V), *lr = T.V(V_LR), *s = T.V(V_S);
+    double *colsum = T.V(V_COLSUM), *lct = T.V(V_LCT), *inv_ct = T.V(V_INVCT);
+    double* sh2 = T.V(V_SH2);
+    col_sums_p<KIND>(T, P, X, prec, beta, u, shift, v, nullptr, colsum);
+    int bad = fix_cols(T, v, lct, colsum);
+    const int rflag = row_marg_p<KIND>(T, P, X, prec, beta, u, shift, v, inv_ct, lr, s);
+    bad += threadIdx.x == 0 ? rflag : 0;                // the row flag is per workgroup
+    if (team_sum(T, (double)bad) == 0.0) return EOT_OK;
+    X.st.range_retries += 1;
+    row_max<KIND>(T, P, beta, u, v, sh2);
+    X.passes += 1;
+    col_sums_p<KIND>(T, P, X, EOT_PREC_FP64, beta, u, sh2, v, nullptr, colsum);
+    bad = fix_cols(T, v, lct, colsum);
+    row_max<KIND>(T, P, beta, u, v, sh2);
+    X.passes += 1;
+    const int rflag2 = row_marg_p<KIND>(T, P, X, EOT_PREC_FP64, beta, u, sh2, v, inv_ct, lr, s);
+    bad += threadIdx.x == 0 ? rflag2 : 0;
+    if (team_sum(T, (double)bad) != 0.0) return EOT_ERR_NONFINITE;
+    return EOT_OK;
+}
+
+// Row refresh after a Newton step, with the same fallback; returns
+// ||r~ - r(P)||_1 of the refreshed plan in *gn.
+template <int KIND>
+__device__ __noinline__ int refresh(Team& T, const TeamProblem& P, Ctl& X, int prec, double beta,
+                       const double* shift, double* gn)
+{
+    double *u = T.V(V_U), *v = T.V(V_V), *lr = T.V(V_LR), *s = T.V(V_S), *rt = T.V(V_RT);
+    double *inv_ct = T.V(V_INVCT), *sh2 = T.V(V_SH2);
+    const int bad = row_marg_p<KIND>(T, P, X, prec, beta, u, shift, v, inv_ct, lr, s);
+    double acc = 0.0;
+    OWN_ROWS(i) acc += fabs(rt[i] - exp(lr[i]));
+    double r2[2] = {threadIdx.x == 0 ? (double)bad : 0.0, acc};
+    team_sums<2>(T, r2);
+    if (r2[0] == 0.0) {
+        *gn = r2[1];
+        return EOT_OK;
+    }
+    X.st.range_retries += 1;
+    row_max<KIND>(T, P, beta, u, v, sh2);
+    X.passes += 1;
+    const int bad2 = row_marg_p<KIND>(T, P, X, EOT_PREC_FP64, beta, u, sh2, v, inv_ct, lr, s);
+    acc = 0.0;
+    OWN_ROWS(i) acc += fabs(rt[i] - exp(lr[i]));
+    double q2[2] = {threadIdx.x == 0 ? (double)bad2 : 0.0, acc};
+    team_sums<2>(T, q2);
+    if (q2[0] != 0.0) return EOT_ERR_NONFINITE;
+    *gn = q2[1];
+    return EOT_OK;
+}
+
+// CG pass A: w = P^T p (column sums), wc = w / c on the owned columns.
+template <int KIND, bool MIXED>
+__device__ __noinline__ void cg_pass_a(Team& T, const TeamProblem& P, double beta,
+                                       const double* u, const double* a, const double* v,
+                                       const double* p, const double* ct, double* w, double* wc)
+{
+    col_pass<KIND, MIXED>(T, P, beta, u, a, v, p, [&](int64_t j, double sj) {
+        w[j] = sj;
+        wc[j] = sj / ct[j];
+    });
+}
+
+struct CgOut {
+    double res_l1;
+    int iters, broke;
+};
+
+// Preconditioned CG on F_r(rho) d = b from d = 0 (Alg. 2's inner loop), with
+// F_r(rho) p = r(P) p - rho P ((P^T p) / c) and M_i = r(P)_i - rho s_i clamped
+// below at max(1 - rho, 2^-40) r(P)_i. Solution in V_DTRY, P^T d in V_PTDT,
+// P (P^T d / c) in V_PCPTDT. Stops at ||res||_1 <= tol, on breakdown or at max_cg.
+template <int KIND>
+__device__ __noinline__ CgOut team_pcg(Team& T, const TeamProblem& P, Ctl& X, int prec, double beta,
+                          double rho, double tol, int max_cg)
+{
+    double *u = T.V(V_U), *v = T.V(V_V), *lr = T.V(V_LR), *s = T.V(V_S);
+    double *b = T.V(V_B), *rP = T.V(V_RP), *d = T.V(V_DTRY), *res = T.V(V_RES), *z = T.V(V_Z);
+    double *p = T.V(V_P), *q = T.V(V_Q), *t = T.V(V_T), *M = T.V(V_M), *pc = T.V(V_PCPTDT);
+    double *ptd = T.V(V_PTDT), *w = T.V(V_W), *wc = T.V(V_WC), *ct = T.V(V_CT);
+    double acc[2] = {0.0, 0.0};
+    OWN_ROWS(i) {
+        const double lo = fmax(1.0 - rho, 9.094947017729282e-13) * rP[i];
+        double mi = rP[i] - rho * s[i];
+        mi = mi > lo ? mi : lo;
+        const double bi = b[i];
+        const double zi = bi / mi;
+        M[i] = mi;
+        d[i] = 0.0;
+        res[i] = bi;
+        z[i] = zi;
+        p[i] = zi;
+        pc[i] = 0.0;
+        acc[0] += bi * zi;
+        acc[1] += fabs(bi);
+    }
+    OWN_COLS(j) ptd[j] = 0.0;
+    team_sums<2>(T, acc);
+    double rz = acc[0];
+    CgOut o{acc[1], 0, 0};
+    bool done = o.res_l1 <= tol || max_cg <= 0;
+    while (!done && !T.ab) {
+        // pass A: w = P^T p (raw column sums), wc = w / c
+        if (KIND != 1 && prec == EOT_PREC_MIXED)
+            cg_pass_a<KIND, KIND != 1>(T, P, beta, u, lr, v, p, ct, w, wc);
+        else
+            cg_pass_a<KIND, false>(T, P, beta, u, lr, v, p, ct, w, wc);
+        // pass B: t = P wc, q = r(P) p - rho t, <p, q>
+        row_sums_p<KIND>(T, P, X, prec, beta, u, lr, v, wc, t);
+        X.passes += 1;                                  // pass A
+        __syncthreads();
+        double pq = 0.0;
+        OWN_ROWS(i) {
+            const double qi = rP[i] * p[i] - rho * t[i];
+            q[i] = qi;
+            pq += p[i] * qi;
+        }
+        pq = team_sum(T, pq);
+        const double alpha = rz / pq;
+        double a2[2] = {0.0, 0.0};
+        OWN_ROWS(i) {
+            d[i] += alpha * p[i];
+            const double ri = res[i] - alpha * q[i];
+            res[i] = ri;
+            const double zi = ri / M[i];
+            z[i] = zi;
+            pc[i] += alpha * t[i];
+            a2[0] += ri * zi;
+            a2[1] += fabs(ri);
+        }
+        OWN_COLS(j) ptd[j] += alpha * w[j];
+        team_sums<2>(T, a2);
+        const double rz_new = a2[0];
+        const double bcg = rz_new / rz;
+        OWN_ROWS(i) p[i] = z[i] + bcg * p[i];
+        rz = rz_new;
+        o.res_l1 = a2[1];
+        o.iters += 1;
+        if (!(fabs(alpha) < INFINITY) || !(pq > 0.0)) {
+            o.broke = 1;
+            done = true;
+        } else if (o.res_l1 <= tol || o.iters >= max_cg) {
+            done = true;
+        }
+    }
+    return o;
+}
+
+struct NewtonOut {
+    double rho;
+    int cg_iters, levels, miss;
+};
+
+// NewtonSolve (Alg. 2) with c(P) = c: log r(P) in V_LR (also the row shift),
+// s in V_S, grad / b / d / rP set by newton_init. Writes d_u to V_DU and
+// d_v = -(P^T d_u) / c to V_DV.
+template <int KIND>
+__device__ __noinline__ NewtonOut team_newton(Team& T, const TeamProblem& P, Ctl& X, int prec, double beta,
+                                 double eta, double rho0, int max_cg, int max_levels,
+                                 double gnorm)
+{
+    double *u = T.V(V_U), *v = T.V(V_V), *lr = T.V(V_LR), *ct = T.V(V_CT);
+    double *rP = T.V(V_RP), *grad = T.V(V_GRAD), *e1 = T.V(V_E1);
+    double *dcur = T.V(V_D), *ptd = T.V(V_PTD), *pcptd = T.V(V_PCPTD), *wc = T.V(V_WC);
+    double *dtry = T.V(V_DTRY), *ptdt = T.V(V_PTDT), *pct = T.V(V_PCPTDT);
+    double *du = T.V(V_DU), *dv = T.V(V_DV);
+    // F_r(1) d for the rho = 0 direction: two explicit passes
+    col_sums_p<KIND>(T, P, X, prec, beta, u, lr, v, dcur, ptd);
+    OWN_COLS(j) wc[j] = ptd[j] / ct[j];
+    row_sums_p<KIND>(T, P, X, prec, beta, u, lr, v, wc, pcptd);
+    double acc = 0.0;
+    OWN_ROWS(i) {
+        const double ei = rP[i] * dcur[i] - pcptd[i] + grad[i];
+        e1[i] = ei;
+        acc += fabs(ei);
+    }
+    double e1n = team_sum(T, acc);
+    double rho = rho0;
+    int lev = 0, cgk = 0, miss = 0;
+    for (;;) {
+        if (T.ab) break;
+        if (e1n <= eta * gnorm) break;
+        if (lev >= max_levels || rho > kRhoCap) { miss = 1; break; }
+        if (rho == 0.0) {
+            cgk += 1;
+            rho = 0.75;
+            ++lev;
+            continue;
+        }
+        const double tol = 0.25 * eta * gnorm;
+        const CgOut h = team_pcg<KIND>(T, P, X, prec, beta, rho, tol, max_cg);
+        cgk += h.iters;
+        const bool conv = !h.broke && h.res_l1 <= tol;
+        if (!conv) { miss = 1; break; }
+        // accept: d <- dtry (and its recurrences); forcing residual
+        acc = 0.0;
+        OWN_ROWS(i) {
+            dcur[i] = dtry[i];
+            pcptd[i] = pct[i];
+            const double ei = rP[i] * dcur[i] - pcptd[i] + grad[i];
+            e1[i] = ei;
+            acc += fabs(ei);
+        }
+        OWN_COLS(j) ptd[j] = ptdt[j];
+        e1n = team_sum(T, acc);
+        rho = 1.0 - (1.0 - rho) / 4.0;
+        ++lev;
+    }
+    OWN_ROWS(i) du[i] = dcur[i];
+    OWN_COLS(j) dv[j] = -1.0 * ptd[j] / ct[j];
+    return NewtonOut{rho, cgk, lev, miss};
+}
+
+// TruncatedNewtonProject (Alg. 4) on the smoothed marginals in V_RT / V_CT.
+template <int KIND>
+__device__ __noinline__ int team_tnp(Team& T, const TeamProblem& P, Ctl& X, const Opt& o, int prec,
+                        double beta, double eps, double* rho0, double* dmin_out, bool stall_exit,
+                        bool* stalled)
+{
+    eot_solve_stats& st = X.st;
+    double *u = T.V(V_U), *v = T.V(V_V), *lr = T.V(V_LR), *s = T.V(V_S), *rt = T.V(V_RT);
+    double *lrt = T.V(V_LRT), *lct = T.V(V_LCT), *sh = T.V(V_SH), *ua = T.V(V_UA);
+    double *va = T.V(V_VA), *du = T.V(V_DU), *dv = T.V(V_DV), *colsum = T.V(V_COLSUM);
+    double *rP = T.V(V_RP), *grad = T.V(V_GRAD), *b = T.V(V_B), *dcur = T.V(V_D);
+    const int64_t n = T.n;
+    (void)n;
+    int64_t p0 = X.passes;
+    row_max<KIND>(T, P, beta, u, v, sh);
+    X.passes += 1;
+    int status = fix_and_refresh<KIND>(T, P, X, prec, beta, sh);
+    if (status != EOT_OK) return status;
+    st.passes_projection += X.passes - p0;
+    double dmin = INFINITY;
+    int k = 0;
+    double g_prev = INFINITY;
+    int slow = 0;
+    if (stalled) *stalled = false;
+    double gn_known = -1.0;
+    for (;;) {
+        if (T.ab) return EOT_ERR_HIP;
+        double gn = gn_known;
+        gn_known = -1.0;
+        if (!(gn >= 0.0)) {
+            double acc = 0.0;
+            OWN_ROWS(i) acc += fabs(rt[i] - exp(lr[i]));
+            gn = team_sum(T, acc);
+        }
+        if (!(fabs(gn) < INFINITY)) return EOT_ERR_NONFINITE;
+        if (gn <= eps) break;
+        if (stall_exit) {
+            slow = (gn <= 1e-3 && gn > 0.5 * g_prev) ? slow + 1 : 0;
+            if (slow >= 2 || k >= o.max_newton) { *stalled = true; break; }
+        }
+        g_prev = gn;
+        if (k >= o.max_newton) { status = EOT_ERR_NOT_CONVERGED; break; }
+        // ChiSinkhorn (Alg. 3) to eps^(2/5)
+        const double eps_chi = pow(eps, 0.4);
+        int sweeps = 0;
+        for (int it = 0;; ++it) {
+            double acc = 0.0;
+            OWN_ROWS(i) {
+                const double e = exp(lr[i]);
+                const double dd = rt[i] - e;
+                acc += dd * dd / e;
+            }
+            const double chi2 = team_sum(T, acc);
+            if (!(chi2 > eps_chi)) break;
+            if (it >= o.max_sinkhorn) return EOT_ERR_NOT_CONVERGED;
+            p0 = X.passes;
+            OWN_ROWS(i) u[i] += lrt[i] - lr[i];
+            status = fix_and_refresh<KIND>(T, P, X, prec, beta, lrt);
+            if (status != EOT_OK) return status;
+            st.passes_sinkhorn += X.passes - p0;
+            st.sinkhorn_iters += 1;
+            ++sweeps;
+            if (T.ab) return EOT_ERR_HIP;
+        }
+        double gk = gn;
+        {
+            double acc = 0.0;
+            OWN_ROWS(i) {
+                const double e = exp(lr[i]);
+                const double gr = e - rt[i];
+                rP[i] = e;
+                grad[i] = gr;
+                b[i] = -gr;
+                dcur[i] = -gr / e;
+                acc += fabs(gr);
+            }
+            if (sweeps > 0) gk = team_sum(T, acc);
+        }
+        const double eta = fmax(gk, 0.8 * eps / gk);
+        p0 = X.passes;
+        const NewtonOut nr = team_newton<KIND>(T, P, X, prec, beta, eta, *rho0, o.max_cg,
+                                               o.max_levels, gk);
+        st.passes_newton += X.passes - p0;
+        st.cg_iters += nr.cg_iters;
+        st.levels += nr.levels;
+        st.forcing_misses += nr.miss;
+        st.rho_last = nr.rho;
+        *rho0 = o.adaptive_rho0 ? fmax(0.0, 1.0 - 4.0 * (1.0 - nr.rho)) : 0.0;
+        // backtracking line search on the mass, FP64 column passes
+        double acc = 0.0;
+        OWN_ROWS(i) acc += grad[i] * du[i];
+        const double slope = -team_sum(T, acc);
+        double alpha = 1.0;
+        int bt = 0;
+        p0 = X.passes;
+        for (;;) {
+            OWN_ROWS(i) {
+                ua[i] = u[i] + alpha * du[i];
+                sh[i] = lr[i] + alpha * du[i];
+            }
+            OWN_COLS(j) va[j] = v[j] + alpha * dv[j];
+            col_sums_p<KIND>(T, P, X, EOT_PREC_FP64, beta, ua, sh, va, nullptr, colsum);
+            double ms = 0.0;
+            OWN_COLS(j) ms += colsum[j];
+            const double mass = team_sum(T, ms);
+            if (fabs(mass) < INFINITY && mass - 1.0 <= 0.99 * alpha * slope) break;
+            if (bt >= o.max_backtrack) { status = EOT_ERR_NOT_CONVERGED; break; }
+            if (T.ab) return EOT_ERR_HIP;
+            alpha *= 0.5;
+            ++bt;
+        }
+        st.passes_linesearch += X.passes - p0;
+        st.backtracks += bt;
+        if (status != EOT_OK) break;
+        // step: u <- ua; v <- va + log c~ - log c(P(alpha))
+        OWN_ROWS(i) u[i] = ua[i];
+        int badc = 0;
+        OWN_COLS(j) {
+            const double sj = colsum[j];
+            if (sj > 0.0 && sj < INFINITY) v[j] = va[j] + lct[j] - log(sj);
+            else { v[j] = va[j]; badc += 1; }
+        }
+        (void)badc;                                  // the refresh's guard catches what follows
+        p0 = X.passes;
+        double gk1 = 0.0;
+        status = refresh<KIND>(T, P, X, prec, beta, sh, &gk1);
+        if (status != EOT_OK) return status;
+        st.passes_projection += X.passes - p0;
+        st.newton_steps += 1;
+        gn_known = gk1;
+        const double dk = (gk - gk1) / ((1.0 - eta) * gk);
+        dmin = fmin(dmin, dk);
+        ++k;
+    }
+    // closing row fit
+    OWN_ROWS(i) u[i] += lrt[i] - lr[i];
+    (void)s;
+    *dmin_out = dmin;
+    return status;
+}
+
+// FP64 report at the output potentials against the unsmoothed marginals.
+template <int KIND>
+__device__ __noinline__ void team_report(Team& T, const TeamProblem& P, Ctl& X, double beta)
+{
+    double *u = T.V(V_U), *v = T.V(V_V), *sh = T.V(V_SH), *ra = T.V(V_ROWA), *rb = T.V(V_ROWB);
+    double* colsum = T.V(V_COLSUM);
+    row_max<KIND>(T, P, beta, u, v, sh);
+    row_pass<KIND, false, 2, RS_COST>(T, P, beta, u, sh, v, nullptr, nullptr,
+                                      [&](int64_t i, double s0, double s1) {
+                                          const double e = exp(sh[i]);
+                                          ra[i] = e * s0;        // r(P)_i
+                                          rb[i] = e * s1;        // sum_j P_ij C_ij
+                                      });
+    col_pass<KIND, false>(T, P, beta, u, sh, v, nullptr,
+                          [&](int64_t j, double s) { colsum[j] = s; });
+    X.passes += 3;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    OWN_ROWS(i) {
+        acc[0] += fabs(P.r[i] - exp(log(ra[i])));
+        acc[2] += rb[i];
+        acc[3] += exp(log(ra[i]));
+        acc[4] += u[i] * P.r[i];
+    }
+    OWN_COLS(j) {
+        acc[1] += fabs(P.c[j] - exp(log(colsum[j])));
+        acc[5] += v[j] * P.c[j];
+    }
+    team_sums<6>(T, acc);
+    X.st.err_r = acc[0];
+    X.st.err_c = acc[1];
+    X.st.cost = KIND >= 2 ? acc[2] / P.scale : acc[2];
+    X.st.dual_value = (acc[4] + acc[5] - acc[3] + 1.0) / beta;
+}
+
+// MDOT (Alg. 1) for one problem.
+template <int KIND>
+__device__ __noinline__ int team_solve(Team& T, const TeamProblem& P, const Opt& o, Ctl& X)
+{
+    eot_solve_stats& st = X.st;
+    const int prec = o.precision;
+    double *rt = T.V(V_RT), *lrt = T.V(V_LRT), *ct = T.V(V_CT), *lct = T.V(V_LCT);
+    double *inv_ct = T.V(V_INVCT), *u = T.V(V_U), *v = T.V(V_V), *up = T.V(V_UPREV);
+    double* vp = T.V(V_VPREV);
+    const int64_t n = T.n, m = T.m;
+    // marginals on the simplex; min(H(r), H(c)) floored at tol (a point mass has
+    // entropy 0, which would ask for an exact projection)
+    double hmin = 0.0;
+    {
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+        OWN_ROWS(i) {
+            const double x = P.r[i];
+            acc[0] += (x > 0.0 && x < INFINITY) ? 0.0 : 1.0;
+            acc[1] += x;
+            acc[4] += x > 0.0 ? -x * log(x) : 0.0;
+        }
+        OWN_COLS(j) {
+            const double x = P.c[j];
+            acc[2] += (x > 0.0 && x < INFINITY) ? 0.0 : 1.0;
+            acc[3] += x;
+            acc[5] += x > 0.0 ? -x * log(x) : 0.0;
+        }
+        team_sums<6>(T, acc);
+        if (acc[0] != 0.0 || !(fabs(acc[1] - 1.0) <= 1e-9) || acc[2] != 0.0 ||
+            !(fabs(acc[3] - 1.0) <= 1e-9))
+            return EOT_ERR_BAD_MARGINALS;
+        hmin = fmax(fmin(acc[4], acc[5]), o.tol);
+    }
+    const double beta_f = 1.0 / o.gamma_final;
+    const double beta_i = 1.0 / o.gamma_init;
+    const double w_c = 0.5 - o.w_r;
+    double beta_prev = 0.0;
+    double beta = fmin(beta_i, beta_f);
+    double q = o.q1;
+    double rho0 = 0.0;
+    int status = EOT_OK;
+    bool done = false;
+    int t = 1;
+    while (!done) {
+        if (T.ab) { status = EOT_ERR_HIP; break; }
+        if (t > o.max_mdot) { status = EOT_ERR_NOT_CONVERGED; break; }
+        done = (beta == beta_f);
+        double eps_d = hmin / pow(beta, o.p);
+        if (done && eps_d > 0.5 * o.tol) eps_d = 0.5 * o.tol;
+        const double wr = o.w_r * eps_d, wc = w_c * eps_d;
+        OWN_ROWS(i) {
+            const double y = (1.0 - wr) * P.r[i] + wr * (1.0 / (double)n);
+            rt[i] = y;
+            lrt[i] = log(y);
+        }
+        OWN_COLS(j) {
+            const double y = (1.0 - wc) * P.c[j] + wc * (1.0 / (double)m);
+            ct[j] = y;
+            lct[j] = log(y);
+            inv_ct[j] = 1.0 / y;
+        }
+        if (t == 1) {
+            OWN_ROWS(i) u[i] = up[i] = lrt[i];
+            OWN_COLS(j) v[j] = vp[j] = lct[j];
+        }
+        double dmin = INFINITY;
+        const bool mixed = prec == EOT_PREC_MIXED;
+        bool stalled = false;
+        status = team_tnp<KIND>(T, P, X, o, prec, beta, 0.5 * eps_d, &rho0, &dmin, mixed, &stalled);
+        st.mixed_stalls += stalled ? 1 : 0;
+        if (status == EOT_OK && done && mixed && o.verify_fp64) {
+            double dmin64 = INFINITY;
+            status = team_tnp<KIND>(T, P, X, o, EOT_PREC_FP64, beta, 0.5 * eps_d, &rho0, &dmin64,
+                                    false, nullptr);
+        } else if (status == EOT_OK && done && stalled) {
+            status = EOT_ERR_NOT_CONVERGED;
+        }
+        st.delta_min_last = dmin;
+        st.mdot_steps = t;
+        st.final_gamma = 1.0 / beta;
+        if (status != EOT_OK || done) break;
+        if (o.adaptive_q) {
+            if (dmin > 0.95) q = fmin(2.0, q * q);
+            else if (dmin < 0.8) q = sqrt(q);
+        }
+        const double beta_next = fmin(q * beta, beta_f);
+        const double ratio = (beta_next - beta) / (beta - beta_prev);
+        OWN_ROWS(i) {
+            const double zn = u[i] + ratio * (u[i] - up[i]);
+            up[i] = u[i];
+            u[i] = zn;
+        }
+        OWN_COLS(j) {
+            const double zn = v[j] + ratio * (v[j] - vp[j]);
+            vp[j] = v[j];
+            v[j] = zn;
+        }
+        beta_prev = beta;
+        beta = beta_next;
+        ++t;
+    }
+    st.final_gamma = 1.0 / beta;
+    if ((status == EOT_OK || status == EOT_ERR_NOT_CONVERGED) && !T.ab) {
+        team_report<KIND>(T, P, X, beta);
+        const double sc = 1.0 / beta;
+        OWN_ROWS(i) P.f[i] = sc * u[i];
+        OWN_COLS(j) P.g[j] = sc * v[j];
+    }
+    if (T.ab) status = EOT_ERR_HIP;
+    return status;
+}
+
+template <int KIND>
+__global__ __launch_bounds__(TT, 4) void k_team_solve(TeamLaunch L)
+{
+    __shared__ double s_red[TW];
+    __shared__ int s_flag;
+    __shared__ int s_ab;
+    __shared__ int s_prob;
+    load_exp_table(t_exp);
+    // team of this workgroup: members share (id mod 8), i.e. one XCD when
+    // workgroups are dealt to the 8 XCDs round-robin (a placement hint only)
+    const int wg = blockIdx.x;
+    const int per_xcd = (int)gridDim.x / 8;
+    const int xcd = wg % 8, slot = wg / 8;
+    const int teams_per_xcd = per_xcd / L.K;
+    const int team = xcd * teams_per_xcd + slot / L.K;
+    Team T;
+    T.K = L.K;
+    T.k = slot % L.K;
+    T.vs = L.vstride;
+    T.vec = L.vec + (int64_t)team * L.team_doubles;
+    T.cpart = T.vec + (int64_t)kTeamVecs * T.vs;
+    T.red = T.cpart + (int64_t)L.K * T.vs;
+    T.sync = L.sync + (int64_t)team * 16;
+    T.abort = L.abort;
+    T.priv = L.priv + (int64_t)wg * kTeamPriv * T.vs;
+    T.s_red = s_red;
+    T.s_exp = t_exp;
+    T.s_flag = &s_flag;
+    T.s_ab = &s_ab;
+    T.rc = 0;
+    T.ab = false;
+    Opt o;
+    o.tol = L.opts.tol;
+    o.p = L.opts.p;
+    o.q1 = L.opts.q1;
+    o.w_r = L.opts.w_r;
+    o.gamma_init = L.opts.gamma_init;
+    o.gamma_final = L.opts.gamma_final;
+    o.adaptive_q = L.opts.adaptive_q;
+    o.adaptive_rho0 = L.opts.adaptive_rho0;
+    o.max_cg = L.opts.max_cg;
+    o.max_levels = L.opts.max_levels;
+    o.max_backtrack = L.opts.max_backtrack;
+    o.max_newton = L.opts.max_newton;
+    o.max_sinkhorn = L.opts.max_sinkhorn;
+    o.max_mdot = L.opts.max_mdot;
+    o.precision = L.opts.precision;
+    o.verify_fp64 = L.opts.verify_fp64;
+    __syncthreads();
+    if (team >= L.nteams) return;                       // grid rounding: not a team member
+    for (;;) {
+        if (T.k == 0 && threadIdx.x == 0) {
+            const int idx = atomicAdd(L.queue, 1);
+            __hip_atomic_store(reinterpret_cast<int*>(T.sync + 2), idx, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        team_barrier(T);
+        if (threadIdx.x == 0)
+            s_prob = __hip_atomic_load(reinterpret_cast<int*>(T.sync + 2), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int idx = s_prob;
+        __syncthreads();
+        if (idx >= L.nprob || T.ab) break;
+        const int pid = L.order[idx];
+        const TeamProblem P = L.probs[pid];
+        T.n = P.n;
+        T.m = P.m;
+        T.r0 = (int64_t)T.k * P.n / T.K;
+        T.r1 = (int64_t)(T.k + 1) * P.n / T.K;
+        T.c0 = (int64_t)T.k * P.m / T.K;
+        T.c1 = (int64_t)(T.k + 1) * P.m / T.K;
+        Ctl X{};
+        X.passes = 0;
+        const uint64_t t_start = wall_clock64();
+        const int status = team_solve<KIND>(T, P, o, X);
+        X.st.seconds = (double)(wall_clock64() - t_start);   // ticks; the host scales them
+        X.st.status = status;
+        X.st.passes_other = X.passes - X.st.passes_newton - X.st.passes_linesearch -
+                            X.st.passes_sinkhorn - X.st.passes_projection;
+        if (T.k == 0 && threadIdx.x == 0) L.out[pid] = X.st;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_team_solve(int kind, const TeamLaunch& L, int grid, hipStream_t s)
+{
+    void* args[] = {const_cast<TeamLaunch*>(&L)};
+    const void* fn = nullptr;
+    switch (kind) {
+    case 0: fn = reinterpret_cast<const void*>(&k_team_solve<0>); break;
+    case 1: fn = reinterpret_cast<const void*>(&k_team_solve<1>); break;
+    case 2: fn = reinterpret_cast<const void*>(&k_team_solve<2>); break;
+    case 3: fn = reinterpret_cast<const void*>(&k_team_solve<3>); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(TT), args, 0, s);
+}
+
+hipError_t team_max_grid(int kind, int* blocks_per_cu, int* cus)
+{
+    const void* fn = nullptr;
+    switch (kind) {
+    case 0: fn = reinterpret_cast<const void*>(&k_team_solve<0>); break;
+    case 1: fn = reinterpret_cast<const void*>(&k_team_solve<1>); break;
+    case 2: fn = reinterpret_cast<const void*>(&k_team_solve<2>); break;
+    case 3: fn = reinterpret_cast<const void*>(&k_team_solve<3>); break;
+    default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, TT, 0);
+    if (e != hipSuccess) return e;
+    int dev = 0;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    return hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev);
+}
+
+}  // namespace eot

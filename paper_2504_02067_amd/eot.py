@@ -61,7 +61,7 @@ class eot_solve_opts(ctypes.Structure):
                 ("max_backtrack", _c_i32), ("max_newton", _c_i32), ("max_sinkhorn", _c_i32),
                 ("max_mdot", _c_i32), ("precision", _c_i32), ("verify_fp64", _c_i32),
                 ("projection", _c_i32), ("cg_graph", _c_i32), ("verbose", _c_i32),
-                ("warm_start", _c_i32)]
+                ("warm_start", _c_i32), ("batch_persistent", _c_i32)]
 
 
 class eot_solve_stats(ctypes.Structure):

@@ -1,8 +1,9 @@
-"""GPU tests of eot_solve_batched: the ragged grid batch (integer grid
-positions as 2-D points, cost recomputed on the fly) solved concurrently must
-give bitwise the potentials of solving each problem alone; mixed cost kinds
-share one batch; a failing problem does not stop the others; and sampled
-problems match the oracle."""
+"""GPU tests of eot_solve_batched on its host-worker path (batch_persistent =
+0): the ragged grid batch (integer grid positions as 2-D points, cost
+recomputed on the fly) solved concurrently must give bitwise the potentials of
+solving each problem alone; mixed cost kinds share one batch; a failing
+problem does not stop the others; and sampled problems match the oracle. The
+persistent single-launch path is tested in test_gpu_persistent.py."""
 import numpy as np
 import pytest
 import torch
@@ -42,7 +43,8 @@ def batch(count, lo=16, hi=40, seed=4000):
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_batched_equals_one_by_one(prec):
     probs, items = batch(24)
-    opts = dict(gamma_init=1.0 / 32.0, gamma_final=1e-3, tol=1e-6, precision=prec)
+    opts = dict(gamma_init=1.0 / 32.0, gamma_final=1e-3, tol=1e-6, precision=prec,
+                batch_persistent=0)
     say(f"batch of 24 ({prec}), 4 workers")
     outs, stats, status = eot.eot_solve_batched(items, workers=4, **opts)
     assert all(s == 0 for s in status)
@@ -58,7 +60,7 @@ def test_batched_matches_oracle_on_samples():
     probs, items = batch(6, lo=16, hi=24, seed=4100)
     say("batch of 6 vs oracle")
     outs, stats, status = eot.eot_solve_batched(items, workers=3, gamma_init=1.0 / 32.0,
-                                                gamma_final=1e-3, tol=1e-6)
+                                                gamma_final=1e-3, tol=1e-6, batch_persistent=0)
     for k in (0, 3, 5):
         p = probs[k]
         C = O.sqeuclid_points_cost(p.X, p.Y, p.scale)
@@ -79,10 +81,12 @@ def test_batched_mixed_kinds_and_failure_isolation():
     items.insert(2, (items[1][0], bad_r, items[1][2]))
     say("mixed kinds with one invalid problem")
     with pytest.raises(eot.EotError) as e:
-        eot.eot_solve_batched(items, workers=4, gamma_init=0.1, gamma_final=1e-2, tol=1e-6)
+        eot.eot_solve_batched(items, workers=4, gamma_init=0.1, gamma_final=1e-2, tol=1e-6,
+                              batch_persistent=0)
     assert e.value.status == eot.EOT_ERR_BAD_MARGINALS
     outs, stats, status = eot.eot_solve_batched(items, workers=4, gamma_init=0.1,
-                                                gamma_final=1e-2, tol=1e-6, check=False)
+                                                gamma_final=1e-2, tol=1e-6, check=False,
+                                                batch_persistent=0)
     assert status[2] == eot.EOT_ERR_BAD_MARGINALS
     assert [s for k, s in enumerate(status) if k != 2] == [0] * (len(items) - 1)
     for k, (C, r, c) in enumerate(items):
@@ -105,7 +109,8 @@ def test_batched_high_dimensional_points(prec):
         items.append((pc, dvec(p.r), dvec(p.c)))
     C = torch.from_numpy(rng.uniform(0, 1, (100, 120)).astype(np.float32)).to(DEV)
     items.insert(1, (C, dvec(rng.dirichlet(np.ones(100))), dvec(rng.dirichlet(np.ones(120)))))
-    opts = dict(gamma_init=1.0 / 8.0, gamma_final=0.02, tol=1e-6, precision=prec)
+    opts = dict(gamma_init=1.0 / 8.0, gamma_final=0.02, tol=1e-6, precision=prec,
+                batch_persistent=0)
     say(f"batch with high-d clouds ({prec})")
     outs, stats, status = eot.eot_solve_batched(items, workers=3, **opts)
     assert all(s == 0 for s in status)
@@ -121,7 +126,8 @@ def test_cg_graph_replay_matches_direct_launches(prec):
     potentials of direct launches: in the batch (worker streams) and for a
     single solve on a non-default stream."""
     probs, items = batch(10, seed=4300)
-    kw = dict(gamma_init=1.0 / 32.0, gamma_final=1e-3, tol=1e-6, precision=prec)
+    kw = dict(gamma_init=1.0 / 32.0, gamma_final=1e-3, tol=1e-6, precision=prec,
+              batch_persistent=0)
     say(f"cg graph batch ({prec})")
     outs0, stats0, _ = eot.eot_solve_batched(items, workers=3, **kw)
     outs1, stats1, st1 = eot.eot_solve_batched(items, workers=3, cg_graph=1, **kw)

@@ -74,9 +74,12 @@ def compare_traces(tg, to, where):
         np.testing.assert_array_equal(tg[k], to[k], err_msg=f"{where}: {k}")
     dec = to["gnorm"] >= ALPHA_DECIDABLE
     np.testing.assert_array_equal(tg["alpha"][dec], to["alpha"][dec], err_msg=f"{where}: alpha")
+    # the trajectories part where a capped NewtonSolve ran or an undecidable
+    # line search went different ways; from there on only the loose checks apply
     capped = to["rho_out"] > RHO_CAP
-    kc = int(np.argmax(capped)) if capped.any() else len(capped)   # first capped Newton step
-    tc = int(to["step_of"][kc]) if capped.any() else len(to["beta"]) + 1
+    parted = capped | (tg["alpha"] != to["alpha"])
+    kc = int(np.argmax(parted)) if parted.any() else len(parted)
+    tc = int(to["step_of"][kc]) if parted.any() else len(to["beta"]) + 1
     tight = np.arange(len(capped)) <= kc                            # its own gnorm still tight
     steps_tight = np.arange(1, len(to["beta"]) + 1) <= tc
     _close(tg["eps_d"], to["eps_d"], 1e-12, 0.0, f"{where}: eps_d")
@@ -84,7 +87,14 @@ def compare_traces(tg, to, where):
                           ("gnorm_next", np.arange(len(capped)) < kc,
                            np.arange(len(capped)) >= kc)):
         _close(tg[k][idx], to[k][idx], 1e-8, 1e-11, f"{where}: {k}")
-        _close(tg[k][loose], to[k][loose], 1e-2, 1e-11, f"{where}: {k} (after a capped step)")
+        if k == "gnorm_next":
+            # after the parting: close, or both already below the projection's tolerance
+            eps_t = 0.5 * to["eps_d"][to["step_of"] - 1]
+            a, b = tg[k][loose], to[k][loose]
+            ok = (np.abs(a - b) <= 1e-2 * np.abs(b) + 1e-11) | ((a <= eps_t[loose]) & (b <= eps_t[loose]))
+            assert ok.all(), (where, k, np.nonzero(loose)[0][~ok], a[~ok], b[~ok])
+        else:
+            _close(tg[k][loose], to[k][loose], 1e-2, 1e-11, f"{where}: {k} (after the parting)")
     g = to["gnorm"]
     for k, mult in (("eta", 1.0), ("cg_tol", 2.0)):
         rel = np.abs(tg[k] - to[k]) / to[k]
