@@ -1460,8 +1460,9 @@ TeamPlan team_plan(int32_t nprob, const eot_batch_problem* probs)
     t.off_order = take(sizeof(int32_t) * (size_t)nprob);
     t.off_out = take(sizeof(eot_solve_stats) * (size_t)nprob);
     t.off_vec = take(sizeof(double) * (size_t)nteams * (size_t)team_doubles_of(t.vstride, t.K));
-    t.off_priv = take(sizeof(double) * (size_t)kTeamMaxGrid * kTeamPriv * (size_t)t.vstride);
-    t.off_sync = take(sizeof(uint32_t) * 16 * (size_t)kTeamMaxGrid + 256);
+    t.off_priv = take(sizeof(double) * (size_t)kTeamMaxGrid * (kTeamPriv + kTeamColVecs) *
+                      (size_t)t.vstride);
+    t.off_sync = take(sizeof(uint32_t) * kTeamSyncWords * (size_t)kTeamMaxGrid + 256);
     t.bytes = off;
     return t;
 }
@@ -1532,7 +1533,7 @@ eot_status team_batch(int32_t nprob, const eot_batch_problem* probs,
                               hipMemcpyHostToDevice, s));
         uint32_t* sync = reinterpret_cast<uint32_t*>(ws + tp.off_sync);
         const int nteams = grid / K;
-        const size_t sync_words = 16 * (size_t)nteams + 64;
+        const size_t sync_words = kTeamSyncWords * (size_t)nteams + 64;
         HIPCHK(launch_fill(reinterpret_cast<double*>(sync), 0.0, (int64_t)(sync_words / 2), s));
         TeamLaunch L{};
         L.probs = dtab;
@@ -1546,7 +1547,7 @@ eot_status team_batch(int32_t nprob, const eot_batch_problem* probs,
         L.team_doubles = team_doubles_of(tp.vstride, K);
         L.priv = reinterpret_cast<double*>(ws + tp.off_priv);
         L.sync = sync;
-        L.queue = reinterpret_cast<int32_t*>(sync + 16 * (size_t)nteams);
+        L.queue = reinterpret_cast<int32_t*>(sync + kTeamSyncWords * (size_t)nteams);
         L.abort = L.queue + 16;
         L.opts = *opts;
         HIPCHK(launch_team_solve(kind, L, grid, s));

@@ -255,10 +255,14 @@ hipError_t launch_cg_small(const double* part, int tiles, int64_t n, int64_t m, 
 
 // ---- batched solves in one persistent launch (eot_team.hip)
 constexpr int kTeamThreads = 256;        // threads per workgroup
-constexpr int kTeamVecs = 40;            // FP64 vectors per team
+constexpr int kTeamVecs = 26;            // FP64 row vectors per team (members own row blocks)
+constexpr int kTeamColVecs = 12;         // FP64 column vectors, private to each workgroup
 constexpr int kTeamPriv = 3;             // FP64 scratch vectors per workgroup
 constexpr int kTeamMaxGrid = 1024;       // workgroups per launch at most
 constexpr int64_t kTeamMaxDim = 16384;   // n, m of a problem the team solver takes
+constexpr int kTeamSyncWords = 64;       // barrier / queue words per team
+constexpr int64_t kTeamEntriesPerWg = int64_t(1) << 18;   // plan entries per workgroup and pass
+                                                         // below which a team splits
 struct TeamProblem {
     int32_t kind, d;
     int64_t n, m, ldc;
@@ -281,8 +285,8 @@ struct TeamLaunch {
     double* vec;                // [nteams][team_doubles]
     int64_t vstride;            // doubles per vector (>= every n, m; multiple of 64)
     int64_t team_doubles;       // kTeamVecs * vstride + K * vstride + 2 * K * 8, rounded up
-    double* priv;               // [grid][kTeamPriv][vstride]
-    uint32_t* sync;             // [nteams][16], zeroed before the launch
+    double* priv;               // [grid][kTeamPriv + kTeamColVecs][vstride]
+    uint32_t* sync;             // [nteams][kTeamSyncWords], zeroed before the launch
     int32_t* queue;             // next entry of order (zeroed)
     int32_t* abort;             // set when a team wait timed out (zeroed)
     eot_solve_opts opts;

@@ -58,10 +58,11 @@ constexpr int kRedSlots = 8;
 enum TeamVec : int {
     V_U, V_LR, V_S, V_RT, V_LRT, V_DU, V_UPREV, V_UA, V_SH, V_SH2, V_RP, V_GRAD, V_B, V_D, V_E1,
     V_DTRY, V_RES, V_Z, V_P, V_Q, V_T, V_M, V_PCPTD, V_PCPTDT, V_ROWA, V_ROWB,
-    V_V, V_CT, V_LCT, V_INVCT, V_DV, V_VPREV, V_VA, V_COLSUM, V_W, V_WC, V_PTD, V_PTDT, V_COLT,
+    V_V, V_CT, V_LCT, V_INVCT, V_DV, V_VPREV, V_VA, V_COLSUM, V_W, V_WC, V_PTD, V_PTDT,
     kTeamVecCount
 };
-static_assert(kTeamVecCount <= kTeamVecs, "team vector budget");
+static_assert(V_V <= kTeamVecs, "team row-vector budget");
+static_assert(kTeamVecCount - V_V <= kTeamColVecs, "private column-vector budget");
 
 struct Team {
     int K, k;
@@ -69,7 +70,8 @@ struct Team {
     double* vec;
     int64_t vs;
     double* cpart;          // [K][vs] column partials
-    double* red;            // [2][K][kRedSlots]
+    double* red;            // [2][team K][kRedSlots], this (sub-)team's members from slot 0
+    int64_t red_par;        // doubles between the two parity halves of red
     uint32_t* sync;         // [0] count, [1] generation, [2] problem index
     int32_t* abort;
     double* priv;           // this workgroup's scratch [kTeamPriv][vs]
@@ -79,9 +81,29 @@ struct Team {
     int* s_ab;              // LDS, 1 int: the abort flag as seen at the last barrier
     int rc;                 // reduction parity
     bool ab;                // this workgroup saw the abort flag
-    __device__ double* V(int id) const { return vec + (int64_t)id * vs; }
-    __device__ double* W(int id) const { return priv + (int64_t)id * vs; }
+    double* cvec;           // this workgroup's private copies of the column vectors
+    int64_t pvs;            // stride of the private vectors (the launch's full stride)
+    // Row vectors live in the team block (each member touches only its own rows);
+    // column vectors are private to each workgroup, which keeps all m columns.
+    __device__ double* V(int id) const
+    {
+        return id >= V_V ? cvec + (int64_t)(id - V_V) * pvs : vec + (int64_t)id * vs;
+    }
+    __device__ double* W(int id) const { return priv + (int64_t)id * pvs; }
 };
+
+// Cross-workgroup data (column partials, team sums) go through device-scope
+// accesses: the stores write through to the device's coherence point and the
+// loads read from it, so no L2 write-back / invalidate of the whole cache is
+// needed around a team barrier.
+__device__ __forceinline__ void st_dev(double* p, double x)
+{
+    __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_dev(const double* p)
+{
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __device__ __forceinline__ double wsum(double x)
 {
@@ -110,21 +132,29 @@ __device__ __forceinline__ double wg_sum(double x, double* s_red)
     return r;
 }
 
+// Team barrier. The data members exchange (column partials, team-sum slots,
+// the queue words) is written and read with device-scope accesses only; every
+// wave first waits for its own memory operations to complete (s_waitcnt 0),
+// the workgroup barrier follows, and then one thread per workgroup arrives on
+// the team counter and waits for the generation word to move. No cache-wide
+// write-back or invalidate is issued.
 __device__ void team_barrier(Team& T)
 {
+    if (T.K > 1) __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (T.K > 1) {
         if (threadIdx.x == 0) {
             uint32_t* cnt = T.sync;
             uint32_t* gen = T.sync + 1;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            const uint32_t g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_s_waitcnt(0);
             const uint32_t a =
-                __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             int ab = 0;
             if (a == (uint32_t)T.K - 1) {
                 __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_s_waitcnt(0);
+                __hip_atomic_store(gen, g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             } else {
                 uint32_t spins = 0;
                 while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
@@ -136,7 +166,7 @@ __device__ void team_barrier(Team& T)
                     }
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __builtin_amdgcn_s_waitcnt(0);
             ab = __hip_atomic_load(T.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             *T.s_ab = ab;
         }
@@ -152,18 +182,18 @@ template <int N>
 __device__ void team_sums(Team& T, double (&x)[N])
 {
     static_assert(N <= kRedSlots, "slots");
-    double* slot = T.red + ((int64_t)(T.rc & 1) * T.K) * kRedSlots;
+    double* slot = T.red + (int64_t)(T.rc & 1) * T.red_par;
     T.rc += 1;
 #pragma unroll
     for (int s = 0; s < N; ++s) {
         const double w = wg_sum(x[s], T.s_red);
-        if (threadIdx.x == 0) slot[(int64_t)T.k * kRedSlots + s] = w;
+        if (threadIdx.x == 0) st_dev(slot + (int64_t)T.k * kRedSlots + s, w);
     }
     team_barrier(T);
 #pragma unroll
     for (int s = 0; s < N; ++s) {
         double r = 0.0;
-        for (int q = 0; q < T.K; ++q) r += slot[(int64_t)q * kRedSlots + s];
+        for (int q = 0; q < T.K; ++q) r += ld_dev(slot + (int64_t)q * kRedSlots + s);
         x[s] = r;
     }
 }
@@ -177,6 +207,8 @@ __device__ __forceinline__ double team_sum(Team& T, double x)
 
 #define OWN_ROWS(i) for (int64_t i = T.r0 + threadIdx.x; i < T.r1; i += TT)
 #define OWN_COLS(j) for (int64_t j = T.c0 + threadIdx.x; j < T.c1; j += TT)
+#define ALL_COLS(j) for (int64_t j = threadIdx.x; j < T.m; j += TT)
+
 
 // ---------------------------------------------------------------- cost access
 // KIND: 0 dense FP32, 1 dense FP64, 2 / 3 points in R^2 / R^3.
@@ -222,6 +254,9 @@ __device__ __forceinline__ void load_pt(const float* Z, int64_t i, float (&z)[Pt
 // The FP64 exp table in LDS, at namespace scope so that the passes (separate
 // functions) address it as LDS.
 __shared__ __attribute__((aligned(16))) double t_exp[128];
+
+// Per-wave column partials of a column-sum pass chunk (one pass runs at a time).
+__shared__ double s_cp[TW][256];
 
 // Plan entry from the FP64 exponent base (row part + column part) and the cost.
 template <bool MIXED, typename R>
@@ -280,20 +315,41 @@ __device__ void row_pass(Team& T, const TeamProblem& P, double beta, const doubl
             load_pt<KIND>(P.X, ir[r], x[r]);
         }
         double acc0[4] = {0.0, 0.0, 0.0, 0.0}, acc1[4] = {0.0, 0.0, 0.0, 0.0};
+        // One column per step and lane; the next step's column data (and dense
+        // cost entries) are loaded while the current step computes. Indices
+        // past m are clamped to m - 1 (in bounds, never used).
+        using R = typename std::conditional<MIXED, float, double>::type;
+        struct ColD {
+            float y[Pts<KIND>::D];
+            R c[4];
+            double cv, w0, w1;
+        };
+        auto fetch = [&](int64_t j, ColD& d) {
+            const int64_t jc = j < m ? j : m - 1;
+            load_pt<KIND>(P.Y, jc, d.y);
+            if constexpr (KIND < 2) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) d.c[r] = cost_at<KIND, MIXED>(P, ir[r], jc, x[r], d.y);
+            }
+            d.cv = colv[jc];
+            d.w0 = cw0[jc];
+            d.w1 = (NS > 1 && MODE == RS_SQUARE) ? cw1[jc] : 0.0;
+        };
+        ColD nxt;
+        fetch(lane, nxt);
 #pragma unroll 1
         for (int64_t j = lane; j < m; j += 64) {
-            float y[Pts<KIND>::D];
-            load_pt<KIND>(P.Y, j, y);
-            const double cv = colv[j], ww0 = cw0[j];
-            double ww1 = 0.0;
-            if constexpr (NS > 1 && MODE == RS_SQUARE) ww1 = cw1[j];
+            const ColD cur = nxt;
+            fetch(j + 64, nxt);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const auto c = cost_at<KIND, MIXED>(P, ir[r], j, x[r], y);
-                const double e = entry<MIXED>(rb[r] + cv, bb, c, T.s_exp);
-                acc0[r] = fma(e, ww0, acc0[r]);
+                R c;
+                if constexpr (KIND < 2) c = cur.c[r];
+                else c = cost_at<KIND, MIXED>(P, ir[r], j, x[r], cur.y);
+                const double e = entry<MIXED>(rb[r] + cur.cv, bb, c, T.s_exp);
+                acc0[r] = fma(e, cur.w0, acc0[r]);
                 if constexpr (NS > 1) {
-                    if constexpr (MODE == RS_SQUARE) acc1[r] = fma(e * e, ww1, acc1[r]);
+                    if constexpr (MODE == RS_SQUARE) acc1[r] = fma(e * e, cur.w1, acc1[r]);
                     else acc1[r] = fma(e, (double)c, acc1[r]);
                 }
             }
@@ -345,7 +401,6 @@ __device__ void col_pass(Team& T, const TeamProblem& P, double beta, const doubl
     const int64_t H = T.r1 - T.r0;
     // wave w takes rows r0 + w, r0 + w + TW, ...; a chunk is 256 columns (4 per lane)
     double* out = T.K > 1 ? T.cpart + (int64_t)T.k * T.vs : nullptr;
-    __shared__ double s_cp[TW][256];
     for (int64_t jc = 0; jc < m; jc += 256) {
         int64_t jj[4];
         float y[4][Pts<KIND>::D];
@@ -358,18 +413,46 @@ __device__ void col_pass(Team& T, const TeamProblem& P, double beta, const doubl
             cv[q] = j < m ? colv[jj[q]] : -INFINITY;
         }
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 1
-        for (int64_t ii = wave; ii < H; ii += TW) {
-            const int64_t i = T.r0 + ii;
-            float x[Pts<KIND>::D];
-            load_pt<KIND>(P.X, i, x);
-            const double rbv = rowb[i], rw = roww[i];
+        // Two rows per step (rows ii and ii + TW of the wave's stride), the next
+        // step's row data (and dense cost entries) loaded while the current one
+        // computes; a row past the block is clamped to the last owned row and
+        // weighted 0.
+        using R = typename std::conditional<MIXED, float, double>::type;
+        struct RowD {
+            float x[2][Pts<KIND>::D];
+            R c[2][4];
+            double rb[2], rw[2];
+        };
+        auto fetch = [&](int64_t ii, RowD& d) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const auto c = cost_at<KIND, MIXED>(P, i, jj[q], x, y[q]);
-                const double e = entry<MIXED>(rbv + cv[q], bb, c, T.s_exp);
-                acc[q] = fma(e, rw, acc[q]);
+            for (int h = 0; h < 2; ++h) {
+                const int64_t iv = ii + (int64_t)h * TW;
+                const int64_t i = T.r0 + (iv < H ? iv : H - 1);
+                load_pt<KIND>(P.X, i, d.x[h]);
+                if constexpr (KIND < 2) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) d.c[h][q] = cost_at<KIND, MIXED>(P, i, jj[q], d.x[h], y[q]);
+                }
+                d.rb[h] = rowb[i];
+                d.rw[h] = iv < H ? roww[i] : 0.0;
             }
+        };
+        RowD nxt;
+        if (H > 0) fetch(wave, nxt);
+#pragma unroll 1
+        for (int64_t ii = wave; ii < H; ii += 2 * TW) {
+            const RowD cur = nxt;
+            fetch(ii + 2 * TW, nxt);
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    R c;
+                    if constexpr (KIND < 2) c = cur.c[h][q];
+                    else c = cost_at<KIND, MIXED>(P, 0, jj[q], cur.x[h], y[q]);
+                    const double e = entry<MIXED>(cur.rb[h] + cv[q], bb, c, T.s_exp);
+                    acc[q] = fma(e, cur.rw[h], acc[q]);
+                }
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) s_cp[wave][lane + 64 * q] = acc[q];
@@ -380,7 +463,7 @@ __device__ void col_pass(Team& T, const TeamProblem& P, double beta, const doubl
 #pragma unroll
             for (int w = 0; w < TW; ++w) s += s_cp[w][threadIdx.x];
             if (j < m) {
-                if (out) out[j] = s;
+                if (out) st_dev(out + j, s);
                 else epi(j, s);
             }
         }
@@ -388,9 +471,9 @@ __device__ void col_pass(Team& T, const TeamProblem& P, double beta, const doubl
     }
     if (T.K > 1) {
         team_barrier(T);
-        OWN_COLS(j) {
+        ALL_COLS(j) {                   // every member keeps all columns
             double s = 0.0;
-            for (int q = 0; q < T.K; ++q) s += T.cpart[(int64_t)q * T.vs + j];
+            for (int q = 0; q < T.K; ++q) s += ld_dev(T.cpart + (int64_t)q * T.vs + j);
             epi(j, s);
         }
     }
@@ -420,6 +503,18 @@ __device__ __noinline__ void row_max(Team& T, const TeamProblem& P, double beta,
         if (lane == 0) out[i] = u[i] + mx;
     }
     __syncthreads();
+}
+
+// Vector stride of one of G sub-teams sharing a team's vector block.
+__device__ __forceinline__ int64_t sub_stride(int64_t vs, int G) { return vs / G / 64 * 64; }
+
+// Workgroups per sub-team for an n x m problem in a team of K (see the kernel).
+__device__ __forceinline__ int sub_team_size(int64_t n, int64_t m, int K, int64_t vs)
+{
+    const int64_t nm = n * m, dim = n > m ? n : m;
+    int S = 1;
+    while (S < K && (nm > (int64_t)S * kTeamEntriesPerWg || dim > sub_stride(vs, K / S))) S *= 2;
+    return S;
 }
 
 // ---------------------------------------------------------------- solver state
@@ -529,7 +624,7 @@ __device__ void row_sums_p(Team& T, const TeamProblem& P, Ctl& X, int prec, doub
 __device__ int fix_cols(Team& T, double* v, const double* lct, const double* colsum)
 {
     int bad = 0;
-    OWN_COLS(j) {
+    ALL_COLS(j) {
         const double s = colsum[j];
         if (s > 0.0 && s < INFINITY) v[j] += lct[j] - log(s);
         else bad += 1;
@@ -639,7 +734,7 @@ __device__ __noinline__ CgOut team_pcg(Team& T, const TeamProblem& P, Ctl& X, in
         acc[0] += bi * zi;
         acc[1] += fabs(bi);
     }
-    OWN_COLS(j) ptd[j] = 0.0;
+    ALL_COLS(j) ptd[j] = 0.0;
     team_sums<2>(T, acc);
     double rz = acc[0];
     CgOut o{acc[1], 0, 0};
@@ -673,7 +768,7 @@ __device__ __noinline__ CgOut team_pcg(Team& T, const TeamProblem& P, Ctl& X, in
             a2[0] += ri * zi;
             a2[1] += fabs(ri);
         }
-        OWN_COLS(j) ptd[j] += alpha * w[j];
+        ALL_COLS(j) ptd[j] += alpha * w[j];
         team_sums<2>(T, a2);
         const double rz_new = a2[0];
         const double bcg = rz_new / rz;
@@ -711,7 +806,7 @@ __device__ __noinline__ NewtonOut team_newton(Team& T, const TeamProblem& P, Ctl
     double *du = T.V(V_DU), *dv = T.V(V_DV);
     // F_r(1) d for the rho = 0 direction: two explicit passes
     col_sums_p<KIND>(T, P, X, prec, beta, u, lr, v, dcur, ptd);
-    OWN_COLS(j) wc[j] = ptd[j] / ct[j];
+    ALL_COLS(j) wc[j] = ptd[j] / ct[j];
     row_sums_p<KIND>(T, P, X, prec, beta, u, lr, v, wc, pcptd);
     double acc = 0.0;
     OWN_ROWS(i) {
@@ -746,13 +841,13 @@ __device__ __noinline__ NewtonOut team_newton(Team& T, const TeamProblem& P, Ctl
             e1[i] = ei;
             acc += fabs(ei);
         }
-        OWN_COLS(j) ptd[j] = ptdt[j];
+        ALL_COLS(j) ptd[j] = ptdt[j];
         e1n = team_sum(T, acc);
         rho = 1.0 - (1.0 - rho) / 4.0;
         ++lev;
     }
     OWN_ROWS(i) du[i] = dcur[i];
-    OWN_COLS(j) dv[j] = -1.0 * ptd[j] / ct[j];
+    ALL_COLS(j) dv[j] = -1.0 * ptd[j] / ct[j];
     return NewtonOut{rho, cgk, lev, miss};
 }
 
@@ -856,11 +951,11 @@ __device__ __noinline__ int team_tnp(Team& T, const TeamProblem& P, Ctl& X, cons
                 ua[i] = u[i] + alpha * du[i];
                 sh[i] = lr[i] + alpha * du[i];
             }
-            OWN_COLS(j) va[j] = v[j] + alpha * dv[j];
+            ALL_COLS(j) va[j] = v[j] + alpha * dv[j];
             col_sums_p<KIND>(T, P, X, EOT_PREC_FP64, beta, ua, sh, va, nullptr, colsum);
             double ms = 0.0;
-            OWN_COLS(j) ms += colsum[j];
-            const double mass = team_sum(T, ms);
+            ALL_COLS(j) ms += colsum[j];
+            const double mass = wg_sum(ms, T.s_red);        // every member holds all columns
             if (fabs(mass) < INFINITY && mass - 1.0 <= 0.99 * alpha * slope) break;
             if (bt >= o.max_backtrack) { status = EOT_ERR_NOT_CONVERGED; break; }
             if (T.ab) return EOT_ERR_HIP;
@@ -873,7 +968,7 @@ __device__ __noinline__ int team_tnp(Team& T, const TeamProblem& P, Ctl& X, cons
         // step: u <- ua; v <- va + log c~ - log c(P(alpha))
         OWN_ROWS(i) u[i] = ua[i];
         int badc = 0;
-        OWN_COLS(j) {
+        ALL_COLS(j) {
             const double sj = colsum[j];
             if (sj > 0.0 && sj < INFINITY) v[j] = va[j] + lct[j] - log(sj);
             else { v[j] = va[j]; badc += 1; }
@@ -913,22 +1008,25 @@ __device__ __noinline__ void team_report(Team& T, const TeamProblem& P, Ctl& X, 
     col_pass<KIND, false>(T, P, beta, u, sh, v, nullptr,
                           [&](int64_t j, double s) { colsum[j] = s; });
     X.passes += 3;
-    double acc[6] = {0, 0, 0, 0, 0, 0};
+    double rs[4] = {0, 0, 0, 0};                   // row sums: the team adds its members'
     OWN_ROWS(i) {
-        acc[0] += fabs(P.r[i] - exp(log(ra[i])));
-        acc[2] += rb[i];
-        acc[3] += exp(log(ra[i]));
-        acc[4] += u[i] * P.r[i];
+        rs[0] += fabs(P.r[i] - exp(log(ra[i])));
+        rs[1] += rb[i];
+        rs[2] += exp(log(ra[i]));
+        rs[3] += u[i] * P.r[i];
     }
-    OWN_COLS(j) {
-        acc[1] += fabs(P.c[j] - exp(log(colsum[j])));
-        acc[5] += v[j] * P.c[j];
+    double c1 = 0.0, c5 = 0.0;                     // column sums: every member has all columns
+    ALL_COLS(j) {
+        c1 += fabs(P.c[j] - exp(log(colsum[j])));
+        c5 += v[j] * P.c[j];
     }
-    team_sums<6>(T, acc);
-    X.st.err_r = acc[0];
-    X.st.err_c = acc[1];
-    X.st.cost = KIND >= 2 ? acc[2] / P.scale : acc[2];
-    X.st.dual_value = (acc[4] + acc[5] - acc[3] + 1.0) / beta;
+    c1 = wg_sum(c1, T.s_red);
+    c5 = wg_sum(c5, T.s_red);
+    team_sums<4>(T, rs);
+    X.st.err_r = rs[0];
+    X.st.err_c = c1;
+    X.st.cost = KIND >= 2 ? rs[1] / P.scale : rs[1];
+    X.st.dual_value = (rs[3] + c5 - rs[2] + 1.0) / beta;
 }
 
 // MDOT (Alg. 1) for one problem.
@@ -945,24 +1043,26 @@ __device__ __noinline__ int team_solve(Team& T, const TeamProblem& P, const Opt&
     // entropy 0, which would ask for an exact projection)
     double hmin = 0.0;
     {
-        double acc[6] = {0, 0, 0, 0, 0, 0};
+        double ra[3] = {0, 0, 0};                // rows: team sums
         OWN_ROWS(i) {
             const double x = P.r[i];
-            acc[0] += (x > 0.0 && x < INFINITY) ? 0.0 : 1.0;
-            acc[1] += x;
-            acc[4] += x > 0.0 ? -x * log(x) : 0.0;
+            ra[0] += (x > 0.0 && x < INFINITY) ? 0.0 : 1.0;
+            ra[1] += x;
+            ra[2] += x > 0.0 ? -x * log(x) : 0.0;
         }
-        OWN_COLS(j) {
+        double ca[3] = {0, 0, 0};                // columns: every member has all of them
+        ALL_COLS(j) {
             const double x = P.c[j];
-            acc[2] += (x > 0.0 && x < INFINITY) ? 0.0 : 1.0;
-            acc[3] += x;
-            acc[5] += x > 0.0 ? -x * log(x) : 0.0;
+            ca[0] += (x > 0.0 && x < INFINITY) ? 0.0 : 1.0;
+            ca[1] += x;
+            ca[2] += x > 0.0 ? -x * log(x) : 0.0;
         }
-        team_sums<6>(T, acc);
-        if (acc[0] != 0.0 || !(fabs(acc[1] - 1.0) <= 1e-9) || acc[2] != 0.0 ||
-            !(fabs(acc[3] - 1.0) <= 1e-9))
+        for (int q = 0; q < 3; ++q) ca[q] = wg_sum(ca[q], T.s_red);
+        team_sums<3>(T, ra);
+        if (ra[0] != 0.0 || !(fabs(ra[1] - 1.0) <= 1e-9) || ca[0] != 0.0 ||
+            !(fabs(ca[1] - 1.0) <= 1e-9))
             return EOT_ERR_BAD_MARGINALS;
-        hmin = fmax(fmin(acc[4], acc[5]), o.tol);
+        hmin = fmax(fmin(ra[2], ca[2]), o.tol);
     }
     const double beta_f = 1.0 / o.gamma_final;
     const double beta_i = 1.0 / o.gamma_init;
@@ -986,7 +1086,7 @@ __device__ __noinline__ int team_solve(Team& T, const TeamProblem& P, const Opt&
             rt[i] = y;
             lrt[i] = log(y);
         }
-        OWN_COLS(j) {
+        ALL_COLS(j) {
             const double y = (1.0 - wc) * P.c[j] + wc * (1.0 / (double)m);
             ct[j] = y;
             lct[j] = log(y);
@@ -994,7 +1094,7 @@ __device__ __noinline__ int team_solve(Team& T, const TeamProblem& P, const Opt&
         }
         if (t == 1) {
             OWN_ROWS(i) u[i] = up[i] = lrt[i];
-            OWN_COLS(j) v[j] = vp[j] = lct[j];
+            ALL_COLS(j) v[j] = vp[j] = lct[j];
         }
         double dmin = INFINITY;
         const bool mixed = prec == EOT_PREC_MIXED;
@@ -1023,7 +1123,7 @@ __device__ __noinline__ int team_solve(Team& T, const TeamProblem& P, const Opt&
             up[i] = u[i];
             u[i] = zn;
         }
-        OWN_COLS(j) {
+        ALL_COLS(j) {
             const double zn = v[j] + ratio * (v[j] - vp[j]);
             vp[j] = v[j];
             v[j] = zn;
@@ -1065,9 +1165,12 @@ __global__ __launch_bounds__(TT, 4) void k_team_solve(TeamLaunch L)
     T.vec = L.vec + (int64_t)team * L.team_doubles;
     T.cpart = T.vec + (int64_t)kTeamVecs * T.vs;
     T.red = T.cpart + (int64_t)L.K * T.vs;
-    T.sync = L.sync + (int64_t)team * 16;
+    T.red_par = (int64_t)L.K * kRedSlots;
+    T.sync = L.sync + (int64_t)team * kTeamSyncWords;
     T.abort = L.abort;
-    T.priv = L.priv + (int64_t)wg * kTeamPriv * T.vs;
+    T.priv = L.priv + (int64_t)wg * (kTeamPriv + kTeamColVecs) * T.vs;
+    T.cvec = T.priv + (int64_t)kTeamPriv * T.vs;
+    T.pvs = T.vs;
     T.s_red = s_red;
     T.s_exp = t_exp;
     T.s_flag = &s_flag;
@@ -1093,37 +1196,67 @@ __global__ __launch_bounds__(TT, 4) void k_team_solve(TeamLaunch L)
     o.verify_fp64 = L.opts.verify_fp64;
     __syncthreads();
     if (team >= L.nteams) return;                       // grid rounding: not a team member
+    __shared__ int s_take[3];
+    int* const words = reinterpret_cast<int*>(T.sync);
     for (;;) {
+        // The leader takes the next problem and sizes the sub-teams for it: the
+        // team splits into G = K / S sub-teams of S workgroups, S the smallest
+        // power of two that gives each workgroup at most kTeamEntriesPerWg
+        // plan entries and whose share of the team vectors holds the problem;
+        // sub-team 0 solves that problem, the others the next G - 1 of the
+        // queue (no larger: the queue is in decreasing n m).
         if (T.k == 0 && threadIdx.x == 0) {
             const int idx = atomicAdd(L.queue, 1);
-            __hip_atomic_store(reinterpret_cast<int*>(T.sync + 2), idx, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            int S = L.K, idx2 = 0;
+            if (idx < L.nprob) {
+                const TeamProblem& P0 = L.probs[L.order[idx]];
+                S = sub_team_size(P0.n, P0.m, L.K, T.vs);
+                if (S < L.K) idx2 = atomicAdd(L.queue, L.K / S - 1);
+            }
+            __hip_atomic_store(words + 2, idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(words + 3, idx2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(words + 4, S, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         team_barrier(T);
-        if (threadIdx.x == 0)
-            s_prob = __hip_atomic_load(reinterpret_cast<int*>(T.sync + 2), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x < 3)
+            s_take[threadIdx.x] = __hip_atomic_load(words + 2 + threadIdx.x, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
-        const int idx = s_prob;
+        const int idx = s_take[0], idx2 = s_take[1], S = s_take[2];
         __syncthreads();
         if (idx >= L.nprob || T.ab) break;
-        const int pid = L.order[idx];
-        const TeamProblem P = L.probs[pid];
-        T.n = P.n;
-        T.m = P.m;
-        T.r0 = (int64_t)T.k * P.n / T.K;
-        T.r1 = (int64_t)(T.k + 1) * P.n / T.K;
-        T.c0 = (int64_t)T.k * P.m / T.K;
-        T.c1 = (int64_t)(T.k + 1) * P.m / T.K;
-        Ctl X{};
-        X.passes = 0;
-        const uint64_t t_start = wall_clock64();
-        const int status = team_solve<KIND>(T, P, o, X);
-        X.st.seconds = (double)(wall_clock64() - t_start);   // ticks; the host scales them
-        X.st.status = status;
-        X.st.passes_other = X.passes - X.st.passes_newton - X.st.passes_linesearch -
-                            X.st.passes_sinkhorn - X.st.passes_projection;
-        if (T.k == 0 && threadIdx.x == 0) L.out[pid] = X.st;
+        const int G = L.K / S, j = T.k / S;
+        const int my = j == 0 ? idx : idx2 + j - 1;
+        if (my < L.nprob) {
+            const int pid = L.order[my];
+            const TeamProblem P = L.probs[pid];
+            Team U = T;                              // this workgroup's sub-team
+            U.K = S;
+            U.k = T.k % S;
+            U.vs = G == 1 ? T.vs : sub_stride(T.vs, G);
+            U.vec = T.vec + (int64_t)j * kTeamVecs * U.vs;
+            U.cpart = T.cpart + (int64_t)j * S * T.vs;
+            U.red = T.red + (int64_t)j * S * kRedSlots;
+            U.red_par = T.red_par;
+            U.sync = G == 1 ? T.sync : T.sync + 8 + 2 * j;
+            U.rc = 0;
+            U.n = P.n;
+            U.m = P.m;
+            U.r0 = (int64_t)U.k * P.n / U.K;
+            U.r1 = (int64_t)(U.k + 1) * P.n / U.K;
+            U.c0 = (int64_t)U.k * P.m / U.K;
+            U.c1 = (int64_t)(U.k + 1) * P.m / U.K;
+            Ctl X{};
+            X.passes = 0;
+            const uint64_t t_start = wall_clock64();
+            const int status = team_solve<KIND>(U, P, o, X);
+            X.st.seconds = (double)(wall_clock64() - t_start);   // ticks; the host scales them
+            X.st.status = status;
+            X.st.passes_other = X.passes - X.st.passes_newton - X.st.passes_linesearch -
+                                X.st.passes_sinkhorn - X.st.passes_projection;
+            if (U.k == 0 && threadIdx.x == 0) L.out[pid] = X.st;
+            T.ab = T.ab || U.ab;
+        }
     }
 }
 
