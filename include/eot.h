@@ -423,6 +423,14 @@ eot_status eot_gradient(const eot_cost* cost, double gamma, const double* f, con
  * workspaces after changing it. */
 eot_status eot_set_rows_per_tile(int32_t rows);
 
+/* Workgroups per team of the persistent batched solver (a power of two up to
+ * 64) used by every later call in this process, or 0 to restore the default
+ * choice from the largest problem (16 from n m >= 4M, 8 from 1M, 4 from 256k,
+ * 2 from 64k, else 1); and the plan entries per workgroup and pass below
+ * which a team splits into sub-teams for a problem (0: the default 2^18).
+ * For tuning and tests; size workspaces after changing it. */
+eot_status eot_set_team_size(int32_t k, int64_t entries_per_wg);
+
 /* Opt-in timing of the streaming passes (for benchmarks and profiling). While
  * enabled, every streaming-pass kernel the library launches is bracketed by two
  * HIP events recorded on the stream it is launched on. eot_pass_timing(1)

@@ -1421,8 +1421,13 @@ int team_kind(const eot_cost& c)
 // about K / 4 compute units (4 workgroups of 256 threads per unit), so the
 // largest problems get more of them; small ones still share the chip through
 // many teams.
+std::atomic<int> g_team_override{0};
+std::atomic<int64_t> g_team_entries{0};
+
 int team_size_for(int64_t max_nm)
 {
+    const int ov = g_team_override.load();
+    if (ov > 0) return ov;
     if (max_nm >= (int64_t)4 << 20) return 16;
     if (max_nm >= (int64_t)1 << 20) return 8;
     if (max_nm >= (int64_t)1 << 18) return 4;
@@ -1550,6 +1555,8 @@ eot_status team_batch(int32_t nprob, const eot_batch_problem* probs,
         L.queue = reinterpret_cast<int32_t*>(sync + kTeamSyncWords * (size_t)nteams);
         L.abort = L.queue + 16;
         L.opts = *opts;
+        const int64_t epw = g_team_entries.load();
+        L.entries_per_wg = epw > 0 ? epw : kTeamEntriesPerWg;
         HIPCHK(launch_team_solve(kind, L, grid, s));
         HIPCHK(hipMemcpyAsync(hout, dout, sizeof(eot_solve_stats) * (size_t)nprob,
                               hipMemcpyDeviceToHost, s));
@@ -1933,6 +1940,15 @@ eot_status eot_set_rows_per_tile(int32_t rows)
     if (rows != 0 && (rows < 8 || rows > kTileRows || (rows & (rows - 1)) != 0))
         return EOT_ERR_INVALID_ARG;
     g_rows_override.store(rows);
+    return EOT_OK;
+}
+
+eot_status eot_set_team_size(int32_t k, int64_t entries_per_wg)
+{
+    if (k < 0 || k > kTeamMaxK || (k & (k - 1)) != 0 || entries_per_wg < 0)
+        return EOT_ERR_INVALID_ARG;
+    g_team_override.store(k);
+    g_team_entries.store(entries_per_wg);
     return EOT_OK;
 }
 

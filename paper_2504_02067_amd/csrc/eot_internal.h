@@ -260,7 +260,8 @@ constexpr int kTeamColVecs = 12;         // FP64 column vectors, private to each
 constexpr int kTeamPriv = 3;             // FP64 scratch vectors per workgroup
 constexpr int kTeamMaxGrid = 1024;       // workgroups per launch at most
 constexpr int64_t kTeamMaxDim = 16384;   // n, m of a problem the team solver takes
-constexpr int kTeamSyncWords = 64;       // barrier / queue words per team
+constexpr int kTeamSyncWords = 160;      // barrier / queue words per team (8 + 2 per sub-team)
+constexpr int kTeamMaxK = 64;            // workgroups per team at most
 constexpr int64_t kTeamEntriesPerWg = int64_t(1) << 18;   // plan entries per workgroup and pass
                                                          // below which a team splits
 struct TeamProblem {
@@ -284,16 +285,18 @@ struct TeamLaunch {
     eot_solve_stats* out;       // device, indexed like probs
     double* vec;                // [nteams][team_doubles]
     int64_t vstride;            // doubles per vector (>= every n, m; multiple of 64)
-    int64_t team_doubles;       // kTeamVecs * vstride + K * vstride + 2 * K * 8, rounded up
+    int64_t team_doubles;       // kTeamVecs * vstride + K vstride + 2 K 8, rounded up
     double* priv;               // [grid][kTeamPriv + kTeamColVecs][vstride]
     uint32_t* sync;             // [nteams][kTeamSyncWords], zeroed before the launch
     int32_t* queue;             // next entry of order (zeroed)
     int32_t* abort;             // set when a team wait timed out (zeroed)
+    int64_t entries_per_wg;     // sub-team sizing: plan entries per workgroup and pass
     eot_solve_opts opts;
 };
 inline int64_t team_doubles_of(int64_t vstride, int K)
 {
-    return ((int64_t)kTeamVecs * vstride + (int64_t)K * vstride + 2 * (int64_t)K * 8 + 63) / 64 * 64;
+    return ((int64_t)kTeamVecs * vstride + (int64_t)K * vstride + 2 * (int64_t)K * 8 + 63) / 64 *
+           64;
 }
 // kind: 0 dense FP32, 1 dense FP64, 2 / 3 points in R^2 / R^3; grid a multiple of 8 K,
 // at most the co-resident capacity (team_max_grid). Cooperative launch.

@@ -176,8 +176,10 @@ __device__ void team_barrier(Team& T)
     }
 }
 
+__shared__ double s_tsum[8];
+
 // Team-wide sums of N per-thread partials: workgroup sums, one slot per member,
-// a barrier, then every member adds the K slots in member order.
+// a barrier, then every member adds the K slots in one fixed order.
 template <int N>
 __device__ void team_sums(Team& T, double (&x)[N])
 {
@@ -190,12 +192,26 @@ __device__ void team_sums(Team& T, double (&x)[N])
         if (threadIdx.x == 0) st_dev(slot + (int64_t)T.k * kRedSlots + s, w);
     }
     team_barrier(T);
+    if (T.K == 1) {
 #pragma unroll
-    for (int s = 0; s < N; ++s) {
-        double r = 0.0;
-        for (int q = 0; q < T.K; ++q) r += ld_dev(slot + (int64_t)q * kRedSlots + s);
-        x[s] = r;
+        for (int s = 0; s < N; ++s) x[s] = ld_dev(slot + s);
+        return;
     }
+    // lane q of wave 0 reads member q's slots (one load per sum for the whole
+    // team), then a fixed butterfly adds them: the same order in every member
+    if (threadIdx.x < 64) {
+        const int q = threadIdx.x;
+#pragma unroll
+        for (int s = 0; s < N; ++s) {
+            const double v = q < T.K ? ld_dev(slot + (int64_t)q * kRedSlots + s) : 0.0;
+            const double r = wsum(v);
+            if (q == 0) s_tsum[s] = r;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < N; ++s) x[s] = s_tsum[s];
+    __syncthreads();
 }
 
 __device__ __forceinline__ double team_sum(Team& T, double x)
@@ -472,8 +488,17 @@ __device__ void col_pass(Team& T, const TeamProblem& P, double beta, const doubl
     if (T.K > 1) {
         team_barrier(T);
         ALL_COLS(j) {                   // every member keeps all columns
+            // member order; the loads of 8 members are issued together
             double s = 0.0;
-            for (int q = 0; q < T.K; ++q) s += ld_dev(T.cpart + (int64_t)q * T.vs + j);
+            int q = 0;
+            for (; q + 8 <= T.K; q += 8) {
+                double t[8];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) t[r] = ld_dev(T.cpart + (int64_t)(q + r) * T.vs + j);
+#pragma unroll
+                for (int r = 0; r < 8; ++r) s += t[r];
+            }
+            for (; q < T.K; ++q) s += ld_dev(T.cpart + (int64_t)q * T.vs + j);
             epi(j, s);
         }
     }
@@ -509,11 +534,12 @@ __device__ __noinline__ void row_max(Team& T, const TeamProblem& P, double beta,
 __device__ __forceinline__ int64_t sub_stride(int64_t vs, int G) { return vs / G / 64 * 64; }
 
 // Workgroups per sub-team for an n x m problem in a team of K (see the kernel).
-__device__ __forceinline__ int sub_team_size(int64_t n, int64_t m, int K, int64_t vs)
+__device__ __forceinline__ int sub_team_size(int64_t n, int64_t m, int K, int64_t vs,
+                                             int64_t per_wg)
 {
     const int64_t nm = n * m, dim = n > m ? n : m;
     int S = 1;
-    while (S < K && (nm > (int64_t)S * kTeamEntriesPerWg || dim > sub_stride(vs, K / S))) S *= 2;
+    while (S < K && (nm > (int64_t)S * per_wg || dim > sub_stride(vs, K / S))) S *= 2;
     return S;
 }
 
@@ -1210,7 +1236,7 @@ __global__ __launch_bounds__(TT, 4) void k_team_solve(TeamLaunch L)
             int S = L.K, idx2 = 0;
             if (idx < L.nprob) {
                 const TeamProblem& P0 = L.probs[L.order[idx]];
-                S = sub_team_size(P0.n, P0.m, L.K, T.vs);
+                S = sub_team_size(P0.n, P0.m, L.K, T.vs, L.entries_per_wg);
                 if (S < L.K) idx2 = atomicAdd(L.queue, L.K / S - 1);
             }
             __hip_atomic_store(words + 2, idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -154,6 +154,7 @@ SIGNATURES = {
                               ctypes.POINTER(eot_grad_info), _c_i32, _c_vp, ctypes.c_size_t,
                               _c_vp]),
     "eot_set_rows_per_tile": (_c_i32, [_c_i32]),
+    "eot_set_team_size": (_c_i32, [_c_i32, _c_i64]),
     "eot_pass_timing": (_c_i32, [_c_i32]),
     "eot_pass_timing_read": (_c_i32, [_c_i32, _c_i32, _c_i32, _c_i32, ctypes.POINTER(_c_i64),
                                       ctypes.POINTER(_c_f64)]),
@@ -565,6 +566,10 @@ def eot_set_rows_per_tile(rows: int) -> None:
     """Force the tile height of the passes (power of two in [8, 256]); 0 restores
     the library's choice."""
     _check(lib().eot_set_rows_per_tile(int(rows)), "eot_set_rows_per_tile")
+
+
+def eot_set_team_size(k: int, entries_per_wg: int = 0) -> None:
+    _check(lib().eot_set_team_size(int(k), int(entries_per_wg)), "eot_set_team_size")
 
 
 def eot_pass_timing(enable: bool) -> None:

