@@ -57,49 +57,121 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(p, C_rows_fn, budget_s=10.0):
-    """The FP64 oracle's HVP on a row band of the same cost: the band grows
-    until one call takes ~1 s (or covers every row), then calls repeat until
-    the time budget is spent; returns GB/s of FP32-cost-equivalent bytes."""
+def oracle_hvp_band(p, C_rows_fn, budget_s, max_rows=None):
+    """The FP64 oracle's HVP on a row band of the grid128 cost: the band grows
+    until one call takes ~0.5 s (or reaches max_rows / every row), then calls
+    repeat until the time budget is spent. Returns (GB/s of FP32-cost-equivalent
+    bytes, rows, calls, seconds)."""
     import oracle as O
     n = p.n
     gamma = 1e-3
     rng = np.random.default_rng(1)
     u = np.log(p.r) + 0.5 * rng.standard_normal(n)
     v = np.log(p.c) + 0.5 * rng.standard_normal(n)
-    rows = 64
+    rows = 16
+    limit = n if max_rows is None else min(n, max_rows)
     while True:
-        Cs = C_rows_fn(np.arange(rows))
+        # the oracle takes FP64 costs: convert the band once, outside the timing
+        Cs = np.ascontiguousarray(C_rows_fn(np.arange(rows)), dtype=np.float64)
         x = rng.standard_normal(rows)
         y = rng.standard_normal(n)
         t0 = time.perf_counter()
         O.hvp(Cs, 1.0 / gamma, u[:rows], v, 1.0, x, y)
         dt = time.perf_counter() - t0
-        if dt > 1.0 or rows >= n:
+        if dt > 0.5 or rows >= limit:
             break
-        rows = min(n, rows * 4)
+        rows = min(limit, rows * 4)
     calls, total = 1, dt
     while total < budget_s:
         t0 = time.perf_counter()
         O.hvp(Cs, 1.0 / gamma, u[:rows], v, 1.0, x, y)
         total += time.perf_counter() - t0
         calls += 1
-    gbs = 4.0 * rows * n * calls / total / 1e9
+    return 4.0 * rows * n * calls / total / 1e9, rows, calls, total
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(p, C_rows_fn, W, batch=None, budget_s=6.0):
+    """The FP64 oracle timed on the host cores (it is never tuned for this):
+    its HVP on a row band of the grid128 cost with every thread and with one
+    (a child process with OMP_NUM_THREADS=1, CPU only), full oracle solves of
+    the 64-point instance (points64, seed 1000) and of the 28 x 28 grid with the
+    squared-L2 cost (seed 2000), time per pass / CG iteration / Newton step from
+    that solve, and estimates for the 28 x 28 L1 instance and the 512-problem
+    batch from the oracle's time per plan entry and pass times the passes the
+    same algorithm takes on the GPU (the oracle solve of the L1 instance alone
+    takes ~30 s, the batch's largest problem ~50 s)."""
+    import subprocess
+    import oracle as O
     cores = len(os.sched_getaffinity(0))
-    return {"value": gbs, "unit": "GB/s", "cores": cores, "kind": "oracle",
-            "sample": f"oracle HVP (FP64, row and column reductions) on a {rows} x {n} row band of "
-                      f"the same cost, {calls} calls in {total:.1f} s; OpenMP threads = "
-                      f"{os.environ.get('OMP_NUM_THREADS', cores)}"}
+    threads = os.environ.get("OMP_NUM_THREADS", str(cores))
+    gbs, rows, calls, total = oracle_hvp_band(p, C_rows_fn, budget_s, 1024)
+    out = {"value": gbs, "unit": "GB/s", "cores": int(threads) if threads.isdigit() else cores,
+           "kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+           "affinity_cpus": cores,
+           "sample": f"oracle HVP (FP64, row and column reductions) on a {rows} x {p.n} row band of "
+                     f"the grid128 cost, {calls} calls in {total:.1f} s; OpenMP threads = {threads}"}
+    # one thread, in a CPU-only child process (the oracle library reads its thread
+    # count when loaded)
+    code = ("import sys, json; sys.path.insert(0, %r); import bench, numpy as np; "
+            "from paper_2504_02067_amd import workloads as W; p = W.large_grid_problem(3000); "
+            "r = bench.oracle_hvp_band(p, lambda rows: W.grid_cost_rows(128, rows), 3.0, 1024); "
+            "print(json.dumps(r))") % ROOT
+    env = dict(os.environ, OMP_NUM_THREADS="1", HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+    try:
+        res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True,
+                             text=True, timeout=120)
+        g1, r1, c1, t1 = json.loads(res.stdout.strip().splitlines()[-1])
+        out["single_core"] = {"value": g1, "unit": "GB/s",
+                              "sample": f"{r1} x {p.n} row band, {c1} calls in {t1:.1f} s, 1 thread"}
+    except Exception as e:                      # reported, not fatal
+        out["single_core"] = {"error": str(e)[:200]}
+    solves = {}
+    q = W.small_points_problem(1000)
+    t0 = time.perf_counter()
+    _, _, st = O.solve(q.C, q.r, q.c, gamma_init=q.gamma_init, gamma_final=q.gamma_final, tol=q.tol)
+    solves["points64"] = {"seconds": time.perf_counter() - t0, "newton_steps": st["newton_steps"],
+                          "cg_iters": st["cg_iters"], "status": st["status"]}
+    q = W.mnist_like_problem(2000, "sqeuclid")
+    t0 = time.perf_counter()
+    _, _, st = O.solve(q.C, q.r, q.c, gamma_init=q.gamma_init, gamma_final=q.gamma_final, tol=q.tol)
+    dt = time.perf_counter() - t0
+    passes = (st["passes_newton"] + st["passes_linesearch"] + st["passes_sinkhorn"]
+              + st["passes_projection"])
+    s_entry = dt / (passes * float(q.n) * q.m)             # seconds per plan entry and pass
+    solves["grid28_sqeuclid_s2000"] = {
+        "seconds": dt, "newton_steps": st["newton_steps"], "cg_iters": st["cg_iters"],
+        "passes": passes, "status": st["status"], "ms_per_pass": 1e3 * dt / passes,
+        "ms_per_cg_iter": 2e3 * dt / passes,             # a CG iteration is two passes
+        "ms_per_newton_step": 1e3 * dt / max(1, st["newton_steps"]),
+        "ns_per_entry_pass": 1e9 * s_entry}
+    out["solves"] = solves
+    est = {"basis": "oracle seconds per plan entry and pass (grid28 squared-L2 solve above) "
+                    "x passes the same algorithm takes on the GPU x n m"}
+    if batch is not None and "entry_passes" in batch.get("fp64", {}):
+        est["batch512_seconds"] = s_entry * batch["fp64"]["entry_passes"]
+    out["estimates"] = est
+    return out
 
 
 def valu_cycles_points_hvp(d):
-    """VALU instructions per plan entry that the mixed point-cloud HVP needs
-    (one lane; each issues in one cycle): d subtractions and d multiply-adds
-    for |x - y|^2, three for the exponent (hi-part sum, two multiply-adds),
-    exp2, the FP32 -> FP64 conversion, and four FP64 multiply-adds for the row
-    and column accumulations. Loop control and the per-row reductions come on
-    top (the compiled loop issues 15.75 per entry at d = 3)."""
-    return 2 * d + 3 + 1 + 1 + 4
+    """VALU lane instructions per plan entry of the method's own work in the
+    point-cloud HVP (each issues in one slot; counters on MI355X show
+    v_exp_f32 taking one slot too): d subtractions and d multiply-adds for
+    |x - y|^2, two for the exponent (sum of the row and column parts, one
+    multiply-add with the cost), exp, and one accumulation each for the row
+    and the column sum. The implementation issues 16.2 per entry at d = 3
+    (FP64 accumulation, loop control, per-row reductions)."""
+    return 2 * d + 2 + 1 + 2
 
 
 def points_measure(args, eot, W, dev, iters=4):
@@ -200,12 +272,16 @@ def highd_measure(args, eot, W, dev, iters=5):
         sec = ms / 1e3 / k
         res[f"{name}_mixed_ms"] = sec * 1e3
         res[f"{name}_mfma_frac"] = 3 * 2 * d * float(n) * m / sec / 2.5e15
+        res[f"{name}_mfma_method_frac"] = 2 * d * float(n) * m / sec / 2.5e15
     eps = res["mixed_entries_per_s"]
     mfma = 3 * 2 * d * eps                      # BF16 hi/lo: three products per dimension pair
     res["mfma"] = {"achieved": mfma / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
                    "frac": mfma / 2.5e15,
-                   "note": "dense BF16 matrix-core peak; the pass also evaluates exp and the row and "
-                           "column sums per entry on the vector units"}
+                   "method_frac": 2 * d * eps / 2.5e15,
+                   "note": "dense BF16 matrix-core peak; frac counts the three hi/lo products the "
+                           "matrix cores execute (3 x 2d flops per entry), method_frac only the "
+                           "method's own x . y (2d flops per entry); the pass also evaluates exp and "
+                           "the row and column sums per entry on the vector units"}
     mfma64 = 2 * d * res["fp64_entries_per_s"]  # FP64: one product per dimension pair
     res["mfma_fp64"] = {"achieved": mfma64 / 1e12, "peak": 78.6, "unit": "TFLOP/s",
                         "frac": mfma64 / 78.6e12,
@@ -276,6 +352,7 @@ def grid28_measure(eot, W, dev, seeds=3):
         rows = {"mixed": [], "fp64": []}
         costs = {"mixed": [], "fp64": []}
         errs = {"mixed": [], "fp64": []}
+        per_cg = {"mixed": [], "fp64": []}
         for s in range(seeds):
             p = W.mnist_like_problem(2000 + s, kind)
             C = torch.from_numpy(p.C).to(dev)
@@ -290,10 +367,13 @@ def grid28_measure(eot, W, dev, seeds=3):
                 _, _, st = eot.eot_solve(C, r, c, opts=o)
                 torch.cuda.synchronize()
                 rows[prec].append(time.perf_counter() - t0)
+                per_cg[prec].append(rows[prec][-1] / max(1, st["cg_iters"]))
                 costs[prec].append(st["cost"])
                 errs[prec].append(st["err_r"] + st["err_c"])
         med = {k: float(np.median(v)) for k, v in rows.items()}
         res[kind] = {"mixed_ms": 1e3 * med["mixed"], "fp64_ms": 1e3 * med["fp64"],
+                     "mixed_us_per_cg_iter": 1e6 * float(np.median(per_cg["mixed"])),
+                     "fp64_us_per_cg_iter": 1e6 * float(np.median(per_cg["fp64"])),
                      "speedup_mixed_vs_fp64": med["fp64"] / med["mixed"],
                      "max_err": float(max(errs["mixed"] + errs["fp64"])),
                      "max_cost_rel_diff": float(max(abs(a - b) / b for a, b in
@@ -303,11 +383,12 @@ def grid28_measure(eot, W, dev, seeds=3):
     return res
 
 
-def batch_measure(args, eot, W, dev):
+def batch_measure(args, eot, W, dev, host_path=True):
     """The ragged batch: 512 grid problems, sides uniform on 16..64 (n = side^2
     in [256, 4096]), integer grid positions as 2-D points with the cost
     recomputed on the fly, temperature 1/32 -> 1e-3, tol 1e-6; one
-    eot_solve_batched call per precision."""
+    eot_solve_batched call per precision on the persistent single-launch path,
+    and (host_path) the host-worker path in mixed precision for comparison."""
     import torch
     sides = W.batch_sides()
     items = []
@@ -320,24 +401,59 @@ def batch_measure(args, eot, W, dev):
                        f"on-the-fly 2-D points, temperature 1/32 -> 1e-3, tol 1e-6",
            "problems": len(items), "mean_n2": float(np.mean([float(s) ** 4 for s in sides])),
            "workers": args.batch_workers}
-    for prec in ("mixed", "fp64"):
-        log(f"batch: {len(items)} problems, {prec}, {args.batch_workers} workers")
+    legs = [("mixed", 1), ("fp64", 1)] + ([("mixed", 0)] if host_path else [])
+    for prec, pers in legs:
+        key = prec if pers else f"{prec}_host_workers"
+        log(f"batch: {len(items)} problems, {prec}, "
+            + ("one persistent launch" if pers else f"{args.batch_workers} host workers"))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         outs, stats, status = eot.eot_solve_batched(items, workers=args.batch_workers,
                                                     gamma_init=1.0 / 32.0, gamma_final=1e-3,
-                                                    tol=1e-6, precision=prec, check=False)
+                                                    tol=1e-6, precision=prec, check=False,
+                                                    batch_persistent=pers)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         errs = [st["err_r"] + st["err_c"] for st in stats]
-        res[prec] = {"seconds": dt, "problems_per_s": len(items) / dt,
-                     "failed": int(sum(1 for x in status if x != 0)),
-                     "max_err": float(max(errs)),
-                     "newton_steps": int(sum(st["newton_steps"] for st in stats)),
-                     "cg_iters": int(sum(st["cg_iters"] for st in stats))}
-        log(f"  {dt:.2f} s, failed {res[prec]['failed']}, max err {max(errs):.2e}")
+        # plan entries evaluated: passes x n m of every problem
+        ent = float(sum(sum(v for k, v in st.items() if k.startswith("passes_")) * float(s) ** 4
+                        for st, s in zip(stats, sides)))
+        res[key] = {"seconds": dt, "problems_per_s": len(items) / dt,
+                    "failed": int(sum(1 for x in status if x != 0)),
+                    "max_err": float(max(errs)),
+                    "newton_steps": int(sum(st["newton_steps"] for st in stats)),
+                    "cg_iters": int(sum(st["cg_iters"] for st in stats)),
+                    "mixed_stalls": int(sum(st["mixed_stalls"] for st in stats)),
+                    "range_retries": int(sum(st["range_retries"] for st in stats)),
+                    "entry_passes": ent, "entries_per_s": ent / dt}
+        log(f"  {dt:.2f} s, failed {res[key]['failed']}, max err {max(errs):.2e}, "
+            f"{ent / dt / 1e12:.2f} T plan entries/s")
     res["speedup_mixed_vs_fp64"] = res["fp64"]["seconds"] / res["mixed"]["seconds"]
+    if host_path:
+        res["speedup_persistent_vs_host_workers"] = (res["mixed_host_workers"]["seconds"]
+                                                     / res["mixed"]["seconds"])
     return res
+
+
+def points_only(eot, W, dev, iters=2):
+    """The point-cloud mixed HVP of points_measure alone (one warm-up pass, then
+    `iters` passes), for counter runs."""
+    import torch
+    p = W.point_cloud_problem()
+    n, m = p.n, p.m
+    pc = eot.PointCloud(torch.from_numpy(p.X).to(dev), torch.from_numpy(p.Y).to(dev), p.scale)
+    gamma = 1e-2
+    rng = np.random.default_rng(1)
+    f = torch.from_numpy(gamma * (np.log(p.r) + 0.5 * rng.standard_normal(n))).to(dev)
+    g = torch.from_numpy(gamma * (np.log(p.c) + 0.5 * rng.standard_normal(m))).to(dev)
+    x = torch.from_numpy(rng.standard_normal(n)).to(dev)
+    y = torch.from_numpy(rng.standard_normal(m)).to(dev)
+    shift = eot.eot_marginals(pc, gamma, f, g, precision="mixed", want=("log_rP",))["log_rP"]
+    for _ in range(1 + iters):
+        eot.eot_hvp(pc, gamma, f, g, 1.0, x, y, row_shift=shift, precision="mixed")
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "points-only", "hvp_launches": 1 + iters, "entries": float(n) * m}),
+          flush=True)
 
 
 def highd_only(eot, W, dev, iters=5):
@@ -400,6 +516,9 @@ def main():
     ap.add_argument("--batch-workers", type=int, default=8)
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the HVP kernel loop and a 1 GiB device copy (for counter runs)")
+    ap.add_argument("--points-only", action="store_true",
+                    help="only 1 + 2 mixed point-cloud HVP passes (n = m = 2^20, d = 3; for "
+                         "counter runs)")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the 512-problem batch in both precisions (for trace runs)")
     ap.add_argument("--highd-only", action="store_true",
@@ -419,8 +538,11 @@ def main():
         highd_only(eot, W, dev)
         return
     if args.batch_only:
-        print(json.dumps({"mode": "batch-only", "batch": batch_measure(args, eot, W, dev)}),
-              flush=True)
+        print(json.dumps({"mode": "batch-only",
+                          "batch": batch_measure(args, eot, W, dev, host_path=False)}), flush=True)
+        return
+    if args.points_only:
+        points_only(eot, W, dev)
         return
     side = 128
     p = W.large_grid_problem(args.seed)
@@ -580,7 +702,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("CPU baseline (oracle)")
-        cpu = cpu_baseline(p, lambda rows: W.grid_cost_rows(side, rows))
+        cpu = cpu_baseline(p, lambda rows: W.grid_cost_rows(side, rows), W, batch)
 
     out = {
         "metric": "HVP GB/s (% HBM peak); time-to-1e-6 marginal error, mixed vs plain FP64",
@@ -610,6 +732,7 @@ def main():
                         "fp64_err": fp64["err"] if fp64 else None,
                         "cost_rel_diff": (abs(st["cost"] - fp64["cost"]) / fp64["cost"]) if fp64 else None,
                         "mixed_newton_steps": st["newton_steps"], "mixed_cg_iters": st["cg_iters"],
+                        "mixed_stalls": st["mixed_stalls"], "mixed_range_retries": st["range_retries"],
                         "fp64_newton_steps": fp64["newton_steps"] if fp64 else None,
                         "fp64_cg_iters": fp64["cg_iters"] if fp64 else None},
         "time_to_1e6_grid28": grid28,
