@@ -223,6 +223,11 @@ typedef struct {
     int32_t forcing_misses, range_retries;
     int32_t mixed_stalls;   /* mixed projections ended at the FP32 error floor (the last
                                one is then finished in FP64 when verify_fp64 is set)   */
+    int32_t linesearch_unresolved; /* line searches that took a trial whose Armijo test
+                               failed by less than the FP64 resolution of the mass
+                               (2^-50 mass (max|u| + |du| + max|v| + |dv| + 745)):
+                               the inequality is undecidable there, near the
+                               projection's optimum                                    */
     int64_t passes_newton, passes_linesearch, passes_sinkhorn, passes_projection, passes_other;
     double final_gamma;
     double err_r, err_c;    /* L1 marginal errors vs the unsmoothed r, c, FP64 pass     */

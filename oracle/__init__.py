@@ -41,7 +41,7 @@ class Opts(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("status", _i32), ("mdot_steps", _i32), ("newton_steps", _i32),
                 ("cg_iters", _i32), ("backtracks", _i32), ("sinkhorn_iters", _i32),
-                ("levels", _i32), ("forcing_misses", _i32),
+                ("levels", _i32), ("forcing_misses", _i32), ("linesearch_unresolved", _i32),
                 ("passes_newton", ctypes.c_int64), ("passes_linesearch", ctypes.c_int64),
                 ("passes_sinkhorn", ctypes.c_int64), ("passes_projection", ctypes.c_int64),
                 ("final_beta", _f64), ("err_r", _f64), ("err_c", _f64),
@@ -98,7 +98,7 @@ def lib():
             "orc_chi_sinkhorn": (ctypes.c_int, [_i64, _i64, _dp, _f64, _dp, _dp, _dp, _dp,
                                                 _dp, _f64, _i32, _i32p]),
             "orc_line_search": (ctypes.c_int, [_i64, _i64, _dp, _f64, _dp, _dp, _dp, _dp,
-                                               _dp, _i32, _dp, _dp, _i32p]),
+                                               _dp, _i32, _dp, _dp, _i32p, _i32p]),
             "orc_tnp": (ctypes.c_int, [_i64, _i64, _dp, _f64, _dp, _dp, _dp, _dp, _f64,
                                        ctypes.POINTER(Opts), _dp, _dp, ctypes.POINTER(Stats)]),
             "orc_solve": (ctypes.c_int, [_i64, _i64, _dp, _dp, _dp, ctypes.POINTER(Opts),
@@ -265,14 +265,17 @@ def chi_sinkhorn(C, beta, u, v, r, c, log_rP, eps_chi, max_iter=10000):
     return u, v, lr, int(it.value), int(st)
 
 
-def line_search(C, beta, u, v, grad_u, du, dv, max_backtrack=60):
+def line_search(C, beta, u, v, grad_u, du, dv, max_backtrack=60, return_unresolved=False):
     C = _C(C); u = _d(u); v = _d(v); g = _d(grad_u); du = _d(du); dv = _d(dv)
     alpha = ctypes.c_double(0.0)
     lc = np.empty(C.shape[1])
     bt = ctypes.c_int32(0)
+    unres = ctypes.c_int32(0)
     st = lib().orc_line_search(C.shape[0], C.shape[1], _p(C), beta, _p(u), _p(v), _p(g),
                                _p(du), _p(dv), int(max_backtrack), ctypes.byref(alpha),
-                               _p(lc), ctypes.byref(bt))
+                               _p(lc), ctypes.byref(bt), ctypes.byref(unres))
+    if return_unresolved:
+        return alpha.value, lc, int(bt.value), int(st), int(unres.value)
     return alpha.value, lc, int(bt.value), int(st)
 
 

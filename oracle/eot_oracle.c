@@ -393,11 +393,21 @@ int orc_chi_sinkhorn(int64_t n, int64_t m, const double* C, double beta,
  * c(P) = c), where log c(P(alpha)) = v + alpha d_v
  * + LSE_c((u + alpha d_u) 1^T - beta C). Returns the accepted trial's
  * log c(P(alpha)). Pinned by: direct evaluation of the Armijo inequality
- * on g. */
+ * on g.
+ * Resolution (a reading; the paper is silent): the mass is a sum of
+ * exponentials whose arguments u_i + v_j - beta C_ij carry rounding errors of
+ * a few units in the last place of the potentials' magnitudes (for every
+ * entry that is not negligible, |beta C_ij| <= |u_i| + |v_j| + 745), so in
+ * FP64 mass - 1 is only known to within
+ *   tau = 2^-50 mass (max_i(|u_i| + |du_i|) + max_j(|v_j| + |dv_j|) + 745).
+ * When the test fails by at most tau (mass - 1 - 0.99 alpha slope <= tau),
+ * the inequality cannot be decided and that trial is accepted; *unresolved
+ * (nullable) is set to 1. */
 int orc_line_search(int64_t n, int64_t m, const double* C, double beta,
                     const double* u, const double* v, const double* grad_u,
                     const double* du, const double* dv, int32_t max_backtrack,
-                    double* alpha, double* log_cP_alpha, int32_t* backtracks)
+                    double* alpha, double* log_cP_alpha, int32_t* backtracks,
+                    int32_t* unresolved)
 {
     double slope = 0.0;                      /* <-grad_u g, d_u> */
     for (int64_t i = 0; i < n; ++i) slope -= grad_u[i] * du[i];
@@ -406,6 +416,8 @@ int orc_line_search(int64_t n, int64_t m, const double* C, double beta,
     double a = 1.0;
     int32_t k = 0;
     int status = ORC_OK;
+    double span = -1.0;                      /* max|u| + max|v| bound, when needed */
+    if (unresolved) *unresolved = 0;
     for (;;) {
         for (int64_t i = 0; i < n; ++i) ua[i] = u[i] + a * du[i];
         for (int64_t j = 0; j < m; ++j) va[j] = v[j] + a * dv[j];
@@ -413,6 +425,18 @@ int orc_line_search(int64_t n, int64_t m, const double* C, double beta,
         double mass = 0.0;
         for (int64_t j = 0; j < m; ++j) mass += exp(log_cP_alpha[j]);
         if (mass - 1.0 <= 0.99 * a * slope) break;
+        if (isfinite(mass)) {
+            if (span < 0.0) {
+                double mu = 0.0, mv = 0.0;
+                for (int64_t i = 0; i < n; ++i) mu = fmax(mu, fabs(u[i]) + fabs(du[i]));
+                for (int64_t j = 0; j < m; ++j) mv = fmax(mv, fabs(v[j]) + fabs(dv[j]));
+                span = mu + mv + 745.0;
+            }
+            if (mass - 1.0 - 0.99 * a * slope <= ldexp(mass * span, -50)) {
+                if (unresolved) *unresolved = 1;
+                break;
+            }
+        }
         if (k >= max_backtrack) { status = ORC_NOT_CONVERGED; break; }
         a *= 0.5;
         ++k;
@@ -547,10 +571,11 @@ static int tnp_impl(int64_t n, int64_t m, const double* C, double beta, double* 
         *rho0_io = o->adaptive_rho0 ? fmax(0.0, 1.0 - 4.0 * (1.0 - rho_out)) : 0.0;
         if (s2 != ORC_OK) { status = s2; break; }
         double alpha = 1.0;                                     /* line search */
-        int32_t bt = 0;
+        int32_t bt = 0, unres = 0;
         int s3 = orc_line_search(n, m, C, beta, u, v, grad, du, dv,
-                                 o->max_backtrack, &alpha, lc, &bt);
+                                 o->max_backtrack, &alpha, lc, &bt, &unres);
         st->backtracks += bt;
+        st->linesearch_unresolved += unres;
         st->passes_linesearch += 1 + bt;
         if (s3 != ORC_OK) { status = s3; break; }
         for (int64_t i = 0; i < n; ++i) u[i] += alpha * du[i];  /* step */

@@ -51,6 +51,8 @@ typedef struct {
     int32_t status;
     int32_t mdot_steps, newton_steps, cg_iters, backtracks, sinkhorn_iters, levels;
     int32_t forcing_misses; /* NewtonSolve exits with the forcing test unmet  */
+    int32_t linesearch_unresolved; /* line searches ended at a trial whose Armijo
+                              test was below the FP64 resolution of the mass  */
     int64_t passes_newton, passes_linesearch, passes_sinkhorn, passes_projection;
     double final_beta;
     double err_r, err_c;   /* L1 errors vs the unsmoothed marginals at output  */
@@ -146,7 +148,8 @@ int  orc_chi_sinkhorn(int64_t n, int64_t m, const double* C, double beta,
 int  orc_line_search(int64_t n, int64_t m, const double* C, double beta,
                      const double* u, const double* v, const double* grad_u,
                      const double* du, const double* dv, int32_t max_backtrack,
-                     double* alpha, double* log_cP_alpha, int32_t* backtracks);
+                     double* alpha, double* log_cP_alpha, int32_t* backtracks,
+                     int32_t* unresolved);
 /* Sinkhorn as the projection: alternate row and column fits until the row
  * marginal is within eps in L1 (the column marginal is exact after each
  * sweep), then the closing row fit of Alg. 4. */

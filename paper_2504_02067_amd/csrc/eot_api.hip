@@ -439,7 +439,8 @@ eot_status reduce_host(Ctx& x, int op, const double* a, const double* b, int64_t
 {
     int nb = 0;
     HIPCHK(launch_reduce(op, a, b, k, x.sc.red, &nb, x.s));
-    HIPCHK(launch_finish_sum(x.sc.red, nb, x.sc.scal, x.s));
+    if (op == RED_MAXABS2) HIPCHK(launch_finish_max(x.sc.red, nb, x.sc.scal, x.s));
+    else HIPCHK(launch_finish_sum(x.sc.red, nb, x.sc.scal, x.s));
     return fetch(x, x.sc.scal, out, 1);
 }
 
@@ -862,11 +863,13 @@ eot_status tnp(Ctx& x, int prec, double beta, double eps, double* rho0, double* 
         st->forcing_misses += nr.miss;
         st->rho_last = nr.rho;
         *rho0 = o->adaptive_rho0 ? std::max(0.0, 1.0 - 4.0 * (1.0 - nr.rho)) : 0.0;
-        // Backtracking line search on the mass, FP64 passes.
+        // Backtracking line search on the mass, FP64 passes. A trial whose
+        // Armijo test fails by less than the FP64 resolution of the mass is
+        // taken (armijo_resolution).
         double slope = 0.0;
         EOTCHK(reduce_host(x, RED_DOT, x.nv.grad, S.du, n, &slope));
         slope = -slope;
-        double alpha = 1.0;
+        double alpha = 1.0, span = -1.0;
         int32_t bt = 0;
         p0 = x.passes;
         for (;;) {
@@ -877,6 +880,18 @@ eot_status tnp(Ctx& x, int prec, double beta, double eps, double* rho0, double* 
             double mass = 0.0;
             EOTCHK(reduce_host(x, RED_SUM, S.colsum, nullptr, m, &mass));
             if (std::isfinite(mass) && mass - 1.0 <= 0.99 * alpha * slope) break;
+            if (std::isfinite(mass)) {
+                if (span < 0.0) {
+                    double mu = 0.0, mv = 0.0;
+                    EOTCHK(reduce_host(x, RED_MAXABS2, S.u, S.du, n, &mu));
+                    EOTCHK(reduce_host(x, RED_MAXABS2, S.v, S.dv, m, &mv));
+                    span = mu + mv;
+                }
+                if (mass - 1.0 - 0.99 * alpha * slope <= armijo_resolution(mass, span)) {
+                    st->linesearch_unresolved += 1;
+                    break;
+                }
+            }
             if (bt >= o->max_backtrack) { status = EOT_ERR_NOT_CONVERGED; break; }
             alpha *= 0.5;
             ++bt;

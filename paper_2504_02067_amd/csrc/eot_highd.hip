@@ -731,7 +731,7 @@ __global__ __launch_bounds__(256) void k_pass_hd_f64(PassArgs A, float* out32)
     __shared__ double s_w0[kHdRows], s_w1[kHdRows];    // column weights (R_i included)
     __shared__ double s_hx[kHdRows];                   // HVP: x_i
     __shared__ double s_cp[2][NCA][kWaves][kF64Blk];
-    __shared__ __attribute__((aligned(16))) double s_exp[MAXOP ? 2 : 128];  // exp_tab64
+    __shared__ __attribute__((aligned(16))) double s_exp[MAXOP ? 2 : kExpTabDoubles];  // exp_tab256
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int jl = lane & 15, g = lane >> 4;
@@ -859,7 +859,7 @@ __global__ __launch_bounds__(256) void k_pass_hd_f64(PassArgs A, float* out32)
                         racc[0][b][r] = fmax(racc[0][b][r], fma(2.0 * beta, xy, s_E[row] + F));
                         continue;
                     }
-                    const double e = exp_tab64(fma(2.0 * beta, xy, s_E[row] + F), s_exp);
+                    const double e = exp_tab256(fma(2.0 * beta, xy, s_E[row] + F), s_exp);
                     if constexpr (HVP) {
                         racc[0][b][r] = fma(e, fma(srho, yw0, s_hx[row]), racc[0][b][r]);
                         cacc[0] = fma(e, fma(s_w1[row], yw0, s_w0[row]), cacc[0]);

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <cmath>
 
 #include "eot.h"
 
@@ -150,12 +151,28 @@ enum VecRed : int {
     RED_SUM = 4,           // x_i
     RED_ENTROPY = 5,       // -x_i log x_i
     RED_L1 = 6,            // |x_i|
-    RED_BAD = 7            // 1 if x_i is not finite and positive
+    RED_BAD = 7,           // 1 if x_i is not finite and positive
+    RED_MAXABS2 = 8        // max_i |x_i| + |y_i| (a maximum, not a sum)
 };
 hipError_t launch_reduce(int op, const double* x, const double* y, int64_t k, double* red,
                          int* nb_out, hipStream_t s);
+// FP64 resolution of the line search's mass (Alg. 4's Armijo test on
+// ||c(P(alpha))||_1 - 1): the mass sums exponentials whose arguments
+// u_i + v_j - beta C_ij carry rounding errors of a few units in the last place
+// of the potentials (for every entry that is not negligible,
+// |beta C_ij| <= |u_i| + |v_j| + 745), so it is known only to within
+// 2^-50 mass (max_i(|u_i| + |du_i|) + max_j(|v_j| + |dv_j|) + 745); span is
+// the sum of the two maxima. A test that fails by less cannot be decided in
+// FP64, and the trial is taken.
+__host__ __device__ inline double armijo_resolution(double mass, double span)
+{
+    return ldexp(mass * (span + 745.0), -50);
+}
+
 // Host-visible scalar: sum of nb partials written to dst[0] (device).
 hipError_t launch_finish_sum(const double* red, int nb, double* dst, hipStream_t s);
+// The same for RED_MAXABS2: the largest of nb partials.
+hipError_t launch_finish_max(const double* red, int nb, double* dst, hipStream_t s);
 
 // Elementwise updates used by the drivers.
 hipError_t launch_axpy(double alpha, const double* x, double* y, int64_t k, hipStream_t s);

@@ -194,7 +194,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& A)
     __shared__ double s_rr[RB];         // R_i = exp(a_i) 2^Ul (HVP)
     __shared__ double s_wmax[kWaves];
     __shared__ float s_x[DP > 0 ? RB * DP : 1];   // point rows
-    __shared__ __attribute__((aligned(16))) double s_exp[MIXED ? 2 : 128];  // FP64: exp_tab64
+    __shared__ __attribute__((aligned(16))) double s_exp[MIXED ? 2 : kExpTabDoubles];  // FP64: exp_tab256
 
     const int tid = threadIdx.x;
     if constexpr (!MIXED) load_exp_table(s_exp);  // read after the prologue's barrier
@@ -360,7 +360,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& A)
                     cd = (double)c;
                 } else {
                     const double c = getc(rr, q);
-                    e64 = exp_tab64(fma(-beta, c, s_A[sb + rr] + vc[ch][q]), s_exp);
+                    e64 = exp_tab256(fma(-beta, c, s_A[sb + rr] + vc[ch][q]), s_exp);
                     cd = c;
                 }
                 if constexpr (MODE2 == R2_HVP) {
@@ -734,6 +734,7 @@ __device__ __forceinline__ double red_term(const double* x, const double* y, int
     if (OP == RED_SUM) return x[i];
     if (OP == RED_ENTROPY) return x[i] > 0.0 ? -x[i] * log(x[i]) : 0.0;
     if (OP == RED_BAD) return (x[i] > 0.0 && x[i] < INFINITY) ? 0.0 : 1.0;
+    if (OP == RED_MAXABS2) return fabs(x[i]) + fabs(y[i]);
     return fabs(x[i]);
 }
 
@@ -749,15 +750,29 @@ __device__ __forceinline__ double block_sum(double v, double* s_w)
     return r;
 }
 
+__device__ __forceinline__ double block_max(double v, double* s_w)
+{
+    v = wave_max(v);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) s_w[w] = v;
+    __syncthreads();
+    double r = s_w[0];
+    for (int k = 1; k < nw; ++k) r = fmax(r, s_w[k]);
+    __syncthreads();
+    return r;
+}
+
 template <int OP>
 __global__ void k_reduce(const double* x, const double* y, int64_t k, double* red)
 {
     __shared__ double s_w[kVecThreads / 64];
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
-         i += (int64_t)gridDim.x * blockDim.x)
-        acc += red_term<OP>(x, y, i);
-    acc = block_sum(acc, s_w);
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if constexpr (OP == RED_MAXABS2) acc = fmax(acc, red_term<OP>(x, y, i));
+        else acc += red_term<OP>(x, y, i);
+    }
+    acc = OP == RED_MAXABS2 ? block_max(acc, s_w) : block_sum(acc, s_w);
     if (threadIdx.x == 0) red[blockIdx.x] = acc;
 }
 
@@ -773,6 +788,15 @@ __global__ void k_finish_sum(const double* red, int nb, double* dst)
     __shared__ double s_w[kVecThreads / 64];
     const double s = sum_partials(red, nb, s_w);
     if (threadIdx.x == 0) dst[0] = s;
+}
+
+__global__ void k_finish_max(const double* red, int nb, double* dst)
+{
+    __shared__ double s_w[kVecThreads / 64];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) acc = fmax(acc, red[b]);
+    acc = block_max(acc, s_w);
+    if (threadIdx.x == 0) dst[0] = acc;
 }
 
 // ---------------------------------------------------------------- elementwise
@@ -1616,6 +1640,7 @@ hipError_t launch_reduce(int op, const double* x, const double* y, int64_t k, do
         case RED_ENTROPY: hipLaunchKernelGGL(k_reduce<RED_ENTROPY>, g, b, 0, s, x, y, k, red); break;
         case RED_L1: hipLaunchKernelGGL(k_reduce<RED_L1>, g, b, 0, s, x, y, k, red); break;
         case RED_BAD: hipLaunchKernelGGL(k_reduce<RED_BAD>, g, b, 0, s, x, y, k, red); break;
+        case RED_MAXABS2: hipLaunchKernelGGL(k_reduce<RED_MAXABS2>, g, b, 0, s, x, y, k, red); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1624,6 +1649,12 @@ hipError_t launch_reduce(int op, const double* x, const double* y, int64_t k, do
 hipError_t launch_finish_sum(const double* red, int nb, double* dst, hipStream_t s)
 {
     hipLaunchKernelGGL(k_finish_sum, dim3(1), dim3(kVecThreads), 0, s, red, nb, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_max(const double* red, int nb, double* dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finish_max, dim3(1), dim3(kVecThreads), 0, s, red, nb, dst);
     return hipGetLastError();
 }
 

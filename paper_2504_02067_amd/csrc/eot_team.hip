@@ -225,6 +225,34 @@ __device__ __forceinline__ double team_sum(Team& T, double x)
 #define OWN_COLS(j) for (int64_t j = T.c0 + threadIdx.x; j < T.c1; j += TT)
 #define ALL_COLS(j) for (int64_t j = threadIdx.x; j < T.m; j += TT)
 
+// Workgroup maximum (every thread gets it).
+__device__ __forceinline__ double wg_max(double x, double* s_red)
+{
+    x = wmax(x);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    double r = s_red[0];
+#pragma unroll
+    for (int w = 1; w < TW; ++w) r = fmax(r, s_red[w]);
+    __syncthreads();
+    return r;
+}
+
+// The span of the line search's resolution (armijo_resolution): a bound on
+// max_i(|u_i| + |du_i|) + max_j(|v_j| + |dv_j|). Every member holds all
+// columns; the row part sums the members' own maxima (at most K times the
+// team's maximum). Every member must call it.
+__device__ double team_span(Team& T, const double* u, const double* du, const double* v,
+                            const double* dv)
+{
+    double mu = 0.0, mv = 0.0;
+    OWN_ROWS(i) mu = fmax(mu, fabs(u[i]) + fabs(du[i]));
+    ALL_COLS(j) mv = fmax(mv, fabs(v[j]) + fabs(dv[j]));
+    mu = wg_max(mu, T.s_red);
+    mv = wg_max(mv, T.s_red);
+    return team_sum(T, threadIdx.x == 0 ? mu : 0.0) + mv;
+}
+
 
 // ---------------------------------------------------------------- cost access
 // KIND: 0 dense FP32, 1 dense FP64, 2 / 3 points in R^2 / R^3.
@@ -269,7 +297,7 @@ __device__ __forceinline__ void load_pt(const float* Z, int64_t i, float (&z)[Pt
 
 // The FP64 exp table in LDS, at namespace scope so that the passes (separate
 // functions) address it as LDS.
-__shared__ __attribute__((aligned(16))) double t_exp[128];
+__shared__ __attribute__((aligned(16))) double t_exp[kExpTabDoubles];
 
 // Per-wave column partials of a column-sum pass chunk (one pass runs at a time).
 __shared__ double s_cp[TW][256];
@@ -281,7 +309,7 @@ __device__ __forceinline__ double entry(double base, double bb, R c, const doubl
     if constexpr (MIXED)
         return (double)__builtin_amdgcn_exp2f((float)fma(-bb, (double)c, base));
     else
-        return exp_tab64(fma(-bb, (double)c, base), t_exp);
+        return exp_tab256(fma(-bb, (double)c, base), t_exp);
 }
 
 // Inverse temperature the entries see (points: C = |x - y|^2 / scale), times
@@ -969,7 +997,7 @@ __device__ __noinline__ int team_tnp(Team& T, const TeamProblem& P, Ctl& X, cons
         double acc = 0.0;
         OWN_ROWS(i) acc += grad[i] * du[i];
         const double slope = -team_sum(T, acc);
-        double alpha = 1.0;
+        double alpha = 1.0, span = -1.0;
         int bt = 0;
         p0 = X.passes;
         for (;;) {
@@ -983,6 +1011,13 @@ __device__ __noinline__ int team_tnp(Team& T, const TeamProblem& P, Ctl& X, cons
             ALL_COLS(j) ms += colsum[j];
             const double mass = wg_sum(ms, T.s_red);        // every member holds all columns
             if (fabs(mass) < INFINITY && mass - 1.0 <= 0.99 * alpha * slope) break;
+            if (fabs(mass) < INFINITY) {                    // the same in every member
+                if (span < 0.0) span = team_span(T, u, du, v, dv);
+                if (mass - 1.0 - 0.99 * alpha * slope <= armijo_resolution(mass, span)) {
+                    st.linesearch_unresolved += 1;
+                    break;
+                }
+            }
             if (bt >= o.max_backtrack) { status = EOT_ERR_NOT_CONVERGED; break; }
             if (T.ab) return EOT_ERR_HIP;
             alpha *= 0.5;
@@ -1175,7 +1210,6 @@ __global__ __launch_bounds__(TT, 4) void k_team_solve(TeamLaunch L)
     __shared__ double s_red[TW];
     __shared__ int s_flag;
     __shared__ int s_ab;
-    __shared__ int s_prob;
     load_exp_table(t_exp);
     // team of this workgroup: members share (id mod 8), i.e. one XCD when
     // workgroups are dealt to the 8 XCDs round-robin (a placement hint only)

@@ -68,7 +68,8 @@ class eot_solve_stats(ctypes.Structure):
     _fields_ = [("status", _c_i32), ("mdot_steps", _c_i32), ("newton_steps", _c_i32),
                 ("cg_iters", _c_i32), ("backtracks", _c_i32), ("sinkhorn_iters", _c_i32),
                 ("levels", _c_i32), ("forcing_misses", _c_i32), ("range_retries", _c_i32),
-                ("mixed_stalls", _c_i32), ("passes_newton", _c_i64), ("passes_linesearch", _c_i64),
+                ("mixed_stalls", _c_i32), ("linesearch_unresolved", _c_i32),
+                ("passes_newton", _c_i64), ("passes_linesearch", _c_i64),
                 ("passes_sinkhorn", _c_i64), ("passes_projection", _c_i64),
                 ("passes_other", _c_i64), ("final_gamma", _c_f64), ("err_r", _c_f64),
                 ("err_c", _c_f64), ("cost", _c_f64), ("dual_value", _c_f64),

@@ -298,8 +298,9 @@ def test_line_search_is_armijo_on_the_dual():
     slope = grad @ R.du                       # <grad g, d>, the v-part vanishes
     for scale in (1.0, 40.0):
         du, dv = scale * R.du, scale * R.dv
-        alpha, lca, bt, st = O.line_search(C, beta, u, v, grad, du, dv)
-        assert st == 0
+        alpha, lca, bt, st, unres = O.line_search(C, beta, u, v, grad, du, dv,
+                                                  return_unresolved=True)
+        assert st == 0 and unres == 0              # decided by the inequality itself
         g1 = O.dual(C, beta, u + alpha * du, v + alpha * dv, r, c)
         assert g1 <= g0 + 0.01 * alpha * scale * slope + 1e-15
         np.testing.assert_allclose(lca, O.log_col_marginal(C, beta, u + alpha * du, v + alpha * dv),
@@ -309,6 +310,65 @@ def test_line_search_is_armijo_on_the_dual():
             g2 = O.dual(C, beta, u + a2 * du, v + a2 * dv, r, c)
             assert g2 > g0 + 0.01 * a2 * scale * slope
     assert scale == 40.0 and bt > 0
+
+
+def _mass_exact(C, beta, u, v):
+    """sum_ij exp(u_i + v_j - beta C_ij) in extended precision (x87 long double,
+    11 more mantissa bits than FP64), the reference for the resolution bound."""
+    L = np.longdouble
+    t = (u.astype(L)[:, None] + v.astype(L)[None, :]) - L(beta) * C.astype(L)
+    return np.exp(t).sum()
+
+
+def test_line_search_resolution_bounds_the_mass_error():
+    # The line search treats its Armijo test as undecidable when it fails by at
+    # most tau = 2^-50 mass (max(|u| + |du|) + max(|v| + |dv|) + 745): tau must
+    # bound the FP64 mass error, here against an extended-precision evaluation
+    # at large potentials (beta up to 1000).
+    assert np.finfo(np.longdouble).nmant >= 63
+    worst = 0.0
+    for seed, beta in ((1, 10.0), (2, 200.0), (3, 1000.0), (4, 1000.0)):
+        C, r, c, u, v, _ = instance(24, 31, 50 + seed, spread=3.0)
+        u = u + beta * 0.3                      # potentials of size ~beta, as at a cold temperature
+        v = fixed_cols(C, beta, u, c)
+        mass = np.exp(O.log_col_marginal(C, beta, u, v)).sum()
+        exact = _mass_exact(C, beta, u, v)
+        span = np.abs(u).max() + np.abs(v).max() + 745.0
+        tau = 2.0 ** -50 * mass * span
+        err = float(abs(L_(mass) - exact))
+        assert err <= tau, (seed, err, tau)
+        worst = max(worst, err / tau)
+    assert worst > 1e-4                          # the bound is not vacuous either
+
+
+def L_(x):
+    return np.longdouble(x)
+
+
+def test_line_search_undecidable_trial_is_taken():
+    # At the projection's optimum (grad ~ 0) any direction's Armijo test is
+    # decided by rounding alone; the line search then takes alpha = 1 and says
+    # so, instead of halving to its cap. Far from it the test stays decisive.
+    C, r, c, u, v, beta = instance(9, 11, 21, beta=20.0, spread=1.0)
+    u = u + 300.0                                # large potentials: v comes out near -300
+    v = fixed_cols(C, beta, u, c)
+    for _ in range(300):                         # converge the row marginals (Sinkhorn)
+        u = u + np.log(r) - O.log_row_marginal(C, beta, u, v)
+        v = fixed_cols(C, beta, u, c)
+    lr = O.log_row_marginal(C, beta, u, v)
+    grad = np.exp(lr) - r
+    assert np.abs(grad).sum() < 1e-13
+    rng = np.random.default_rng(5)
+    du, dv = 1e-9 * rng.standard_normal(9), 1e-9 * rng.standard_normal(11)
+    undecided = 0
+    for k in range(8):
+        alpha, lca, bt, st, unres = O.line_search(C, beta, u, v, grad, du * (k + 1), dv,
+                                                  max_backtrack=60, return_unresolved=True)
+        assert st == 0 and bt < 60
+        undecided += unres
+        if unres:
+            assert alpha == 0.5 ** bt
+    assert undecided > 0
 
 
 # ------------------------------------------------------------ ChiSinkhorn / TNP
