@@ -209,23 +209,92 @@ def points_measure(args, eot, W, dev, iters=4):
     qr, qcm = torch.from_numpy(q.r).to(dev), torch.from_numpy(q.c).to(dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, _, qs = eot.eot_solve(qc, qr, qcm, gamma_init=q.gamma_init, gamma_final=q.gamma_final,
-                             tol=q.tol, precision="mixed")
+    qf, qg, qs = eot.eot_solve(qc, qr, qcm, gamma_init=q.gamma_init, gamma_final=q.gamma_final,
+                               tol=q.tol, precision="mixed")
     torch.cuda.synchronize()
     qt = time.perf_counter() - t0
     qp = sum(v for k, v in qs.items() if k.startswith("passes_"))
     log(f"points solve n = m = {q.n}: {qt:.2f} s, {qp} passes, error {qs['err_r'] + qs['err_c']:.1e}")
+    mf = points_mfma_form(eot, pc, p, f, g, x, y, shift, gamma, iters, sec,
+                          cold=(qc, q, qf, qg))
     return {"workload": f"gmm3d n=m={n} d=3 on-the-fly |x-y|^2/s, mixed HVP pass",
             "kernel_ms": sec * 1e3, "elements_per_s": elems / sec,
             "roofline": {"bound": "alu", "achieved": elems / sec / 1e12,
                          "peak": peak_eps / 1e12, "unit": "T elements/s",
                          "frac": elems / sec / peak_eps,
                          "valu_cycles_per_element": cyc},
+            "mfma_form": mf,
             "solve": {"workload": f"gmm3d n=m={q.n} d=3, temperature {q.gamma_init} -> "
                                   f"{q.gamma_final}, tol {q.tol}, mixed",
                       "seconds": qt, "passes": qp, "newton_steps": qs["newton_steps"],
                       "cg_iters": qs["cg_iters"], "err": qs["err_r"] + qs["err_c"],
                       "status": qs["status"]}}
+
+
+def _pad16(cloud, eot):
+    """The same points with coordinates zero-padded to d = 16 (the padding adds
+    nothing to any distance)."""
+    import torch
+    X16 = torch.zeros(cloud.X.shape[0], 16, dtype=torch.float32, device=cloud.X.device)
+    Y16 = torch.zeros(cloud.Y.shape[0], 16, dtype=torch.float32, device=cloud.X.device)
+    X16[:, :cloud.X.shape[1]] = cloud.X
+    Y16[:, :cloud.Y.shape[1]] = cloud.Y
+    return eot.PointCloud(X16, Y16, cloud.scale)
+
+
+def _marginal_errors(eot, clouds, gam, f, g):
+    """Max |log r(P) - ref| and |log c(P) - ref| of each mixed form, the
+    reference being the FP64 difference form (its log r(P) is the row shift)."""
+    want = ("log_rP", "log_cP")
+    ref = eot.eot_marginals(clouds["difference"], gam, f, g, precision="fp64", want=want)
+    out = {}
+    for name, cloud in clouds.items():
+        o = eot.eot_marginals(cloud, gam, f, g, row_shift=ref["log_rP"], precision="mixed",
+                              want=want)
+        out[name] = max(float((o[w] - ref[w]).abs().max()) for w in want)
+    return out
+
+
+def points_mfma_form(eot, pc, p, f, g, x, y, shift, gamma, iters, diff_sec, cold):
+    """The d = 3 pass with |x - y|^2 = |x|^2 + |y|^2 - 2 x . y and x . y on the
+    matrix cores (the high-dimensional kernel on the coordinates zero-padded to
+    16) against the difference form on the vector units: time per HVP pass on
+    the 2^20-point clouds, and the error of each form's log marginals against
+    the FP64 difference form, at the benchmark temperature and at the final
+    temperature of the 65536-point solve (its converged potentials)."""
+    import torch
+    n, m = p.n, p.m
+    pc16 = _pad16(pc, eot)
+    eot.eot_hvp(pc16, gamma, f, g, 1.0, x, y, row_shift=shift, precision="mixed")
+    torch.cuda.synchronize()
+    eot.eot_pass_timing(True)
+    for _ in range(iters):
+        eot.eot_hvp(pc16, gamma, f, g, 1.0, x, y, row_shift=shift, precision="mixed")
+    torch.cuda.synchronize()
+    k, ms = eot.eot_pass_timing_read(fused_hvp=1, precision="mixed")
+    eot.eot_pass_timing(False)
+    sec = ms / 1e3 / k
+    res = {"note": "x . y on the matrix cores (BF16 hi/lo, coordinates zero-padded to d = 16) "
+                   "against the difference form on the vector units; errors: max |log r(P) - ref| "
+                   "over rows and |log c(P) - ref| over columns, ref = FP64 difference form",
+           "mfma_hvp_ms": sec * 1e3, "difference_hvp_ms": diff_sec * 1e3,
+           "mfma_elements_per_s": float(n) * m / sec, "speedup_vs_difference": diff_sec / sec}
+    e1 = _marginal_errors(eot, {"difference": pc, "mfma": pc16}, gamma, f, g)
+    del pc16
+    qc, q, qf, qg = cold
+    qc16 = _pad16(qc, eot)
+    e2 = _marginal_errors(eot, {"difference": qc, "mfma": qc16}, q.gamma_final, qf, qg)
+    del qc16
+    torch.cuda.synchronize()
+    for name in ("difference", "mfma"):
+        res[f"{name}_err_n2^20_gamma_{gamma:g}"] = e1[name]
+        res[f"{name}_err_n65536_solution_gamma_{q.gamma_final:g}"] = e2[name]
+    log(f"points MFMA form (d padded to 16): {sec * 1e3:.1f} ms per HVP pass "
+        f"({diff_sec / sec:.2f}x the difference form); log-marginal error vs FP64: "
+        f"gamma {gamma:g}: difference {e1['difference']:.1e}, MFMA {e1['mfma']:.1e}; "
+        f"solution at gamma {q.gamma_final:g}: difference {e2['difference']:.1e}, "
+        f"MFMA {e2['mfma']:.1e}")
+    return res
 
 
 def highd_measure(args, eot, W, dev, iters=5):
@@ -476,8 +545,9 @@ def highd_only(eot, W, dev, iters=5):
 
 
 def kernels_only(args, eot, W, p, C, dev):
-    """The mixed HVP pass (as in the full run) and a 1 GiB device-to-device copy
-    whose fetched / written bytes calibrate the memory counters."""
+    """The HVP pass (as in the full run, in --kernels-prec) and a 1 GiB
+    device-to-device copy whose fetched / written bytes calibrate the memory
+    counters."""
     import torch
     n, m = p.n, p.m
     gamma = p.gamma_final
@@ -488,14 +558,16 @@ def kernels_only(args, eot, W, p, C, dev):
     y = torch.from_numpy(rng.standard_normal(m)).to(dev)
     shift = eot.eot_marginals(C, gamma, f, g, precision="mixed", want=("log_rP",))["log_rP"]
     for _ in range(args.hvp_iters):
-        eot.eot_hvp(C, gamma, f, g, 1.0, x, y, row_shift=shift, precision="mixed")
+        eot.eot_hvp(C, gamma, f, g, 1.0, x, y, row_shift=shift, precision=args.kernels_prec)
     src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
     dst = torch.empty_like(src)
     for _ in range(args.hvp_iters):
         dst.copy_(src)
     torch.cuda.synchronize()
-    print(json.dumps({"mode": "kernels-only", "hvp_launches": args.hvp_iters,
-                      "copy_bytes": 4 * src.numel(), "copy_launches": args.hvp_iters}), flush=True)
+    print(json.dumps({"mode": "kernels-only", "precision": args.kernels_prec,
+                      "hvp_launches": args.hvp_iters,
+                      "copy_bytes": 4 * src.numel(), "copy_launches": args.hvp_iters}),
+          flush=True)
 
 
 def main():
@@ -516,6 +588,8 @@ def main():
     ap.add_argument("--batch-workers", type=int, default=8)
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the HVP kernel loop and a 1 GiB device copy (for counter runs)")
+    ap.add_argument("--kernels-prec", choices=("mixed", "fp64"), default="mixed",
+                    help="precision of the --kernels-only HVP passes")
     ap.add_argument("--points-only", action="store_true",
                     help="only 1 + 2 mixed point-cloud HVP passes (n = m = 2^20, d = 3; for "
                          "counter runs)")
