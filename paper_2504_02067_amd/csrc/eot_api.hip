@@ -98,6 +98,36 @@ struct GradVecs {
     double *v, *cP, *bv, *inv_c, *mu, *cb, *tm, *h0, *hy0, *hy1, *hy2;          // m
 };
 
+// Buffers of the single-launch CG (launch_cg_persist) for small problems.
+struct CgpVecs {
+    double* sync = nullptr;       // kCgpSyncDoubles: barrier flags, then the abort word
+};
+
+// Single-launch CG: 0 off, 1 on (default); a fixed grid or 0 for the default.
+std::atomic<int> g_cgp_mode{1};
+std::atomic<int> g_cgp_grid{0};
+
+// Workgroups of the single-launch CG for an n x m problem before the
+// co-resident cap: the fixed grid or the smallest one with at most 8 rows and
+// 8 columns per workgroup (the kernel's bound), at most kCgpMaxGrid.
+int cgp_grid_for(int64_t n, int64_t m)
+{
+    const int lo = (int)((std::max(n, m) + 7) / 8);
+    return std::min(std::max(g_cgp_grid.load(), lo), kCgpMaxGrid);
+}
+
+// Cost kind of the single-launch CG (0 dense FP32, 1 dense FP64, 2 points in
+// the plane), or -1 when it does not take the problem: too large, or points in
+// R^3, whose version of the kernel gave wrong directions (see the kernel).
+int cgp_kind(const eot_cost& c)
+{
+    if (c.n > kCgpMaxDim || c.m > kCgpMaxDim) return -1;
+    if (c.kind == EOT_COST_DENSE_F32) return 0;
+    if (c.kind == EOT_COST_DENSE_F64) return 1;
+    if (c.kind == EOT_COST_SQEUCLID_POINTS && c.d == 2) return 2;
+    return -1;
+}
+
 struct HdVecs {
     void *xh = nullptr, *xl = nullptr, *yh = nullptr, *yl = nullptr;   // BF16, n (m) x hd_padded_dim(d)
     float *xx = nullptr, *yy = nullptr;
@@ -180,9 +210,11 @@ struct Ctx {
     SolveVecs sv{};
     GradVecs gv{};
     HdVecs hd{};
+    CgpVecs cgp{};
     int64_t passes = 0;
     int32_t range_retries = 0;
     bool cg_graph = false;        // replay CG chunks from a recorded HIP graph
+    bool cgp_ok = true;           // the single-launch CG may be used (not in batch workers)
 };
 
 void carve(Arena& ar, Ctx& x, int op)
@@ -217,6 +249,10 @@ void carve(Arena& ar, Ctx& x, int op)
         double** mvec[] = {&v.v, &v.cP, &v.bv, &v.inv_c, &v.mu, &v.cb, &v.tm, &v.h0, &v.hy0,
                            &v.hy1, &v.hy2};
         for (double** p : mvec) *p = ar.take<double>(m);
+    }
+    if ((op == EOT_OP_NEWTON_CG || op == EOT_OP_SOLVE || op == EOT_OP_GRADIENT) &&
+        cgp_kind(x.cost) >= 0) {
+        x.cgp.sync = ar.take<double>(kCgpSyncDoubles);
     }
     if (op == EOT_OP_NEWTON_CG || op == EOT_OP_SOLVE || op == EOT_OP_GRADIENT) {
         NewtonVecs& v = x.nv;
@@ -500,6 +536,28 @@ struct NewtonResult {
     double forcing_ratio = 0.0;
 };
 
+// Grid of the single-launch CG for this problem (cgp_grid_for, at most the
+// co-resident capacity and the workgroups the workspace holds), or 0 to use
+// the launches per iteration.
+eot_status cgp_pick_grid(Ctx& x, int prec, int* grid)
+{
+    *grid = 0;
+    if (!g_cgp_mode.load()) return EOT_OK;
+    const int kind = cgp_kind(x.cost);
+    const int mixed = prec == EOT_PREC_MIXED ? 1 : 0;
+    if (kind < 0 || (kind == 1 && mixed)) return EOT_OK;
+    static std::atomic<int> cap[4][2];           // co-resident capacity per kernel, 0 = unknown
+    int c = cap[kind][mixed].load();
+    if (c == 0) {
+        HIPCHK(cg_persist_max_grid(kind, mixed, &c));
+        cap[kind][mixed].store(c);
+    }
+    const int lo = (int)((std::max(x.n, x.m) + 7) / 8);
+    const int g = std::min(cgp_grid_for(x.n, x.m), c);
+    if (g >= lo) *grid = g;
+    return EOT_OK;
+}
+
 // Preconditioned CG on F_r(rho) d = V.b (Alg. 2 inner loop) from d = 0, with
 // F_r(rho) p = r(P) o p - rho P ((P^T p) / c) and Jacobi preconditioner
 // M_i = r(P)_i - rho s_i; r(P) in V.rP, log r(P) in lr (also the row shift).
@@ -520,6 +578,51 @@ eot_status device_pcg(Ctx& x, int prec, const double* u, const double* lr, const
     if (mirror) {
         mirror[0] = 0;
         mirror[1] = 0;
+    }
+    int cgp_grid = 0;
+    if (x.cgp.sync && x.cgp_ok && !x.cg_graph) EOTCHK(cgp_pick_grid(x, prec, &cgp_grid));
+    if (cgp_grid > 0) {
+        // the whole CG solve in one cooperative launch
+        CgpArgs A{};
+        A.P.kind = x.cost.kind;
+        A.P.d = x.cost.d;
+        A.P.n = n;
+        A.P.m = m;
+        A.P.ldc = x.cost.ldc;
+        A.P.C = x.cost.C;
+        A.P.X = x.cost.X;
+        A.P.Y = x.cost.Y;
+        A.P.scale = x.cost.scale;
+        A.KIND = cgp_kind(x.cost);
+        A.mixed = prec == EOT_PREC_MIXED ? 1 : 0;
+        A.beta = beta;
+        A.u = u;
+        A.a = lr;
+        A.v = v;
+        A.c = c;
+        A.rP = V.rP;
+        A.s = s;
+        A.b = V.b;
+        A.rho = rho;
+        A.tol = tol;
+        A.max_cg = max_cg;
+        A.d = V.dtry;
+        A.ptd = V.ptd_try;
+        A.pcptd = V.pcptd_try;
+        A.sc = x.sc.cg;
+        A.wc = V.wc;
+        A.t = V.t;
+        A.sync = reinterpret_cast<uint32_t*>(x.cgp.sync);
+        A.abort = reinterpret_cast<int32_t*>(x.cgp.sync + kCgpMaxGrid / 2);
+        HIPCHK(launch_fill(x.cgp.sync, 0.0, kCgpSyncDoubles, x.s));
+        HIPCHK(launch_cg_persist(A, cgp_grid, x.s));
+        CgScalars h{};
+        EOTCHK(fetch(x, reinterpret_cast<const double*>(x.sc.cg), reinterpret_cast<double*>(&h),
+                     sizeof(CgScalars) / sizeof(double)));
+        if (!h.done) return EOT_ERR_HIP;        // a grid wait timed out
+        x.passes += 2 * (int64_t)h.iters;
+        *out = h;
+        return EOT_OK;
     }
     HIPCHK(launch_cg_init(V.b, V.rP, s, rho, V.dtry, V.res, V.z, V.p, V.M, V.ptd_try,
                           V.pcptd_try, n, m, x.sc.red, x.sc.cg, tol, max_cg, mirror, x.s));
@@ -1198,10 +1301,12 @@ eot_status solve_one(const eot_cost* cost, const double* r, const double* c,
                      const eot_solve_opts* opts, double* f, double* g, eot_solve_stats* stats,
                      void* ws, size_t ws_bytes, void* stream,
                      const eot_solve_state* resume = nullptr,
-                     eot_solve_state* state_out = nullptr, eot_solve_trace* trace = nullptr)
+                     eot_solve_state* state_out = nullptr, eot_solve_trace* trace = nullptr,
+                     bool single_launch_cg = true)
 {
     const auto t0 = std::chrono::steady_clock::now();
     Ctx x;
+    x.cgp_ok = single_launch_cg;
     EOTCHK(setup(x, cost, EOT_OP_SOLVE, opts->precision, ws, ws_bytes, stream));
     eot_solve_stats st{};
     eot_status status = solve_impl(x, r, c, opts, resume, state_out, trace, f, g, &st);
@@ -1887,8 +1992,10 @@ eot_status eot_solve_batched(int32_t nprob, const eot_batch_problem* probs,
             if (k >= n_work) break;
             const int32_t i = order[(size_t)k];
             const eot_batch_problem& p = probs[i];
+            // no single-launch CG here: cooperative launches from 8 threads at once
             st_all[(size_t)i] = solve_one(&p.cost, p.r, p.c, opts, p.f, p.g, &stats_all[(size_t)i],
-                                          base, slice, streams[w]);
+                                          base, slice, streams[w], nullptr, nullptr, nullptr,
+                                          false);
         }
     };
     if (setup_err == EOT_OK) {
@@ -1955,6 +2062,15 @@ eot_status eot_set_rows_per_tile(int32_t rows)
     if (rows != 0 && (rows < 8 || rows > kTileRows || (rows & (rows - 1)) != 0))
         return EOT_ERR_INVALID_ARG;
     g_rows_override.store(rows);
+    return EOT_OK;
+}
+
+eot_status eot_set_cg_persist(int32_t enable, int32_t grid)
+{
+    if ((enable != 0 && enable != 1) || grid < 0 || grid > kCgpMaxGrid)
+        return EOT_ERR_INVALID_ARG;
+    g_cgp_mode.store(enable);
+    g_cgp_grid.store(grid);
     return EOT_OK;
 }
 

@@ -1320,6 +1320,328 @@ __global__ __launch_bounds__(TT, 4) void k_team_solve(TeamLaunch L)
     }
 }
 
+// ---------------------------------------------------------------- persistent CG
+// One CG solve of NewtonSolve (Alg. 2's inner loop) in a single cooperative
+// launch for small problems, with the host driver's formulas (F_r(rho) p =
+// r(P) p - rho P ((P^T p) / c), M_i = r(P)_i - rho s_i clamped below at
+// max(1 - rho, 2^-40) r(P)_i, the recurrences for P^T d and P (P^T d / c), and
+// its stop and breakdown tests).
+//
+// The potentials do not change during a CG solve, so neither does the plan:
+// each thread evaluates its plan entries P_ij = exp(a_i) e_ij once, keeps them
+// in registers (at most kCgpKMax per pass), and an iteration is two
+// register-times-LDS products and the vector update. Column-sum pass:
+// workgroup g owns a block of at most 8 columns and sums them over all rows
+// (no partial sums to merge), writing (P^T p) / c. Row-sum pass: workgroup g
+// owns a block of at most 8 rows and sums them over all columns, writing
+// t = P ((P^T p) / c). Each is followed by a grid barrier. Every workgroup
+// then reads all of t and updates all n rows of its own copy of the CG vectors
+// (registers) in the same order as every other workgroup: the dot products,
+// the step and the stop test come out bitwise equal everywhere, so all
+// workgroups leave the loop together without exchanging decisions. P^T d is
+// kept by the owners of its columns.
+
+constexpr int kCgpKMax = 32;              // plan entries per thread and pass
+constexpr int kCgpRowsPerThread = (int)(kCgpMaxDim / TT);
+
+// Grid barrier: each workgroup has a flag word holding the number of the last
+// barrier it reached. Arrival: the workgroup's own memory operations complete,
+// then it stores its barrier number into its flag (device scope). Wait: wave 0
+// reads every workgroup's flag (one device-scope load per lane and round) until
+// all have reached this barrier. No counter is shared, so arrivals do not
+// serialise on one address, and numbers only grow, so nothing is reset between
+// barriers. Every wait is bounded and raises the abort flag when it runs out;
+// returns true when the abort flag is set.
+__device__ bool cgp_barrier(uint32_t* flags, int G, uint32_t epoch, int32_t* abort, int* s_ab)
+{
+    __builtin_amdgcn_s_waitcnt(0);
+#ifdef EOT_CGP_FENCE
+    __atomic_thread_fence(__ATOMIC_RELEASE);
+#endif
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int lane = (int)threadIdx.x;
+        if (lane == 0) __hip_atomic_store(flags + blockIdx.x, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t spins = 0;
+        int ab = 0;
+        for (;;) {
+            int ok = 1;
+            for (int q = lane; q < G; q += 64) {
+                const uint32_t f = __hip_atomic_load(flags + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok &= (int32_t)(f - epoch) >= 0 ? 1 : 0;
+            }
+            if (__all(ok)) break;
+            __builtin_amdgcn_s_sleep(1);
+            if ((++spins & 63) == 0) {                    // the abort word every 64 rounds
+                const int a = __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (__builtin_amdgcn_readfirstlane(a)) {
+                    ab = 1;
+                    break;
+                }
+            }
+            if (spins > kSpinLimit) {
+                if (lane == 0) __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ab = 1;
+                break;
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        if (lane == 0) *s_ab = ab;
+    }
+#ifdef EOT_CGP_FENCE
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+#endif
+    __syncthreads();
+    return *s_ab != 0;                  // rewritten only after the next barrier's first sync
+}
+
+// Two workgroup sums in one round (fixed order, every thread gets both).
+__device__ __forceinline__ void wg_sum2(double& x, double& y, double* s_red2)
+{
+    x = wsum(x);
+    y = wsum(y);
+    if ((threadIdx.x & 63) == 0) {
+        s_red2[threadIdx.x >> 6] = x;
+        s_red2[TW + (threadIdx.x >> 6)] = y;
+    }
+    __syncthreads();
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int w = 0; w < TW; ++w) {
+        a += s_red2[w];
+        b += s_red2[TW + w];
+    }
+    __syncthreads();
+    x = a;
+    y = b;
+}
+
+// dst[0..k) = the device-scope values at src[0..k), loads issued in groups of 4
+__device__ __forceinline__ void cgp_gather(double* dst, const double* src, int64_t k)
+{
+    constexpr int B = 4;
+    for (int64_t i0 = threadIdx.x; i0 < k; i0 += (int64_t)TT * B) {
+        double v[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            const int64_t i = i0 + (int64_t)q * TT;
+            v[q] = i < k ? ld_dev(src + i) : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            const int64_t i = i0 + (int64_t)q * TT;
+            if (i < k) dst[i] = v[q];
+        }
+    }
+}
+
+// P_ij = exp(a_i) e_ij; point coordinates from the LDS copies sx, sy.
+template <int KIND, bool MIXED>
+__device__ __forceinline__ double cgp_entry(const CgpArgs& A, double bb, int64_t i, int64_t j,
+                                            const float* sx, const float* sy)
+{
+    const TeamProblem& P = A.P;
+    float x[Pts<KIND>::D], y[Pts<KIND>::D];
+    load_pt<KIND>(sx, i, x);
+    load_pt<KIND>(sy, j, y);
+    const auto c = cost_at<KIND, MIXED>(P, i, j, x, y);
+    const double ai = A.a[i];
+    const double base = A.u[i] - ai;
+    const double e = entry<MIXED>(MIXED ? kL2E * base + kL2E * A.v[j] : base + A.v[j], bb, c,
+                                  t_exp);
+    return exp(ai) * e;
+}
+
+template <int KIND, bool MIXED>
+__global__ __launch_bounds__(TT) void k_cg_persist(CgpArgs A)
+{
+    __shared__ double s_red[2 * TW];
+    __shared__ double s_cp[TT];
+    __shared__ double s_p[kCgpMaxDim];         // the direction p (all rows)
+    __shared__ double s_wc[kCgpMaxDim];        // (P^T p) / c (all columns)
+    __shared__ double s_t[kCgpMaxDim];         // P ((P^T p) / c) (all rows)
+    __shared__ float s_x[KIND >= 2 ? kCgpMaxDim * KIND : 1];   // point coordinates
+    __shared__ float s_y[KIND >= 2 ? kCgpMaxDim * KIND : 1];
+    __shared__ int s_ab;
+    load_exp_table(t_exp);
+    const int G = (int)gridDim.x, g = (int)blockIdx.x, tid = (int)threadIdx.x;
+    const int64_t n = A.P.n, m = A.P.m;
+    if constexpr (KIND >= 2) {
+        for (int64_t e = tid; e < n * KIND; e += TT) s_x[e] = A.P.X[e];
+        for (int64_t e = tid; e < m * KIND; e += TT) s_y[e] = A.P.Y[e];
+    }
+    // blocks of at most 8 columns / rows (the host keeps G >= max(n, m) / 8)
+    const int64_t cb = (m + G - 1) / G, rb = (n + G - 1) / G;
+    const int64_t j0 = g * cb < m ? g * cb : m, j1 = j0 + cb < m ? j0 + cb : m;
+    const int64_t i0 = g * rb < n ? g * rb : n, i1 = i0 + rb < n ? i0 + rb : n;
+    int CBp = 1, RBp = 1;
+    while (CBp < cb) CBp *= 2;
+    while (RBp < rb) RBp *= 2;
+    const int NRG = TT / CBp;                  // row groups of the column-sum pass
+    const int CGp = TT / RBp;                  // column lanes per row of the row-sum pass
+    const int cc = tid & (CBp - 1), rg = tid / CBp;
+    const int rr = tid / CGp, cl = tid - rr * CGp;
+    const int64_t jc = j0 + cc, ir = i0 + rr;
+    const double bb = beta_eff<KIND, MIXED>(A.P, A.beta);
+    const double rho = A.rho, tol = A.tol;
+    __syncthreads();                           // the exp table and the points
+
+    // the plan entries of this thread: column jc at rows rg + k NRG, row ir at
+    // columns cl + k CGp (0 outside the problem)
+    double EC[kCgpKMax], ER[kCgpKMax];
+#pragma unroll
+    for (int k = 0; k < kCgpKMax; ++k) {
+        const int64_t i = rg + (int64_t)k * NRG;
+        EC[k] = (jc < j1 && i < n) ? cgp_entry<KIND, MIXED>(A, bb, i, jc, s_x, s_y) : 0.0;
+        const int64_t j = cl + (int64_t)k * CGp;
+        ER[k] = (ir < i1 && j < m) ? cgp_entry<KIND, MIXED>(A, bb, ir, j, s_x, s_y) : 0.0;
+    }
+    // CG start from d = 0; rows tid + q TT of every vector in registers
+    constexpr int NV = kCgpRowsPerThread;
+    double M[NV], d[NV], res[NV], z[NV], pc[NV], pr[NV], rp[NV];
+    double rz = 0.0, l1 = 0.0;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        const int64_t i = tid + (int64_t)q * TT;
+        M[q] = 1.0, d[q] = 0.0, res[q] = 0.0, z[q] = 0.0, pc[q] = 0.0, pr[q] = 0.0, rp[q] = 0.0;
+        if (i < n) {
+            const double r_i = A.rP[i];
+            const double lo = fmax(1.0 - rho, 9.094947017729282e-13) * r_i;
+            double mi = r_i - rho * A.s[i];
+            mi = mi > lo ? mi : lo;
+            const double bi = A.b[i];
+            const double zi = bi / mi;
+            M[q] = mi;
+            res[q] = bi;
+            z[q] = zi;
+            pr[q] = zi;
+            rp[q] = r_i;
+            s_p[i] = zi;
+            rz += bi * zi;
+            l1 += fabs(bi);
+        }
+    }
+    wg_sum2(rz, l1, s_red);
+    double ptd = 0.0, wcol = 0.0;              // P^T d and P^T p at column jc (tid < CBp)
+    int iters = 0, broke = 0;
+    double pq = 0.0, alpha = 0.0, bcg = 0.0, rz_new = rz;
+    bool ab = false;
+    uint32_t epoch = 0;                        // barriers passed (the flag words start at 0)
+    bool done = l1 <= tol || A.max_cg <= 0;
+    while (!done && !ab) {
+        // column-sum pass over the owned columns
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < kCgpKMax; ++k) {
+            const int64_t i = rg + (int64_t)k * NRG;
+            if (i < n) acc = fma(EC[k], s_p[i], acc);
+        }
+        s_cp[tid] = acc;
+        __syncthreads();
+        if (tid < CBp) {
+            double sw = 0.0;
+            for (int r = 0; r < NRG; ++r) sw += s_cp[r * CBp + tid];
+            wcol = sw;
+            if (jc < j1) st_dev(A.wc + jc, sw / A.c[jc]);
+        }
+        ab = cgp_barrier(A.sync, G, ++epoch, A.abort, &s_ab);
+        if (ab) break;
+        // row-sum pass over the owned rows
+        cgp_gather(s_wc, A.wc, m);
+        __syncthreads();
+        acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < kCgpKMax; ++k) {
+            const int64_t j = cl + (int64_t)k * CGp;
+            if (j < m) acc = fma(ER[k], s_wc[j], acc);
+        }
+        s_cp[tid] = acc;
+        __syncthreads();
+        if (tid < RBp) {
+            double st = 0.0;
+            for (int k = 0; k < CGp; ++k) st += s_cp[tid * CGp + k];
+            if (i0 + tid < i1) st_dev(A.t + i0 + tid, st);
+        }
+        ab = cgp_barrier(A.sync, G, ++epoch, A.abort, &s_ab);
+        if (ab) break;
+        // the vector step over all rows, the same in every workgroup
+        cgp_gather(s_t, A.t, n);
+        __syncthreads();
+        double pqa = 0.0;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            const int64_t i = tid + (int64_t)q * TT;
+            if (i < n) pqa += pr[q] * (rp[q] * pr[q] - rho * s_t[i]);
+        }
+        pq = wg_sum(pqa, s_red);
+        alpha = rz / pq;
+        double rza = 0.0, l1a = 0.0;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            const int64_t i = tid + (int64_t)q * TT;
+            if (i < n) {
+                const double ti = s_t[i];
+                const double qi = rp[q] * pr[q] - rho * ti;
+                d[q] += alpha * pr[q];
+                const double ri = res[q] - alpha * qi;
+                res[q] = ri;
+                const double zi = ri / M[q];
+                z[q] = zi;
+                pc[q] += alpha * ti;
+                rza += ri * zi;
+                l1a += fabs(ri);
+            }
+        }
+        if (tid < CBp) ptd += alpha * wcol;
+        wg_sum2(rza, l1a, s_red);
+        rz_new = rza;
+        l1 = l1a;
+        bcg = rz_new / rz;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            const int64_t i = tid + (int64_t)q * TT;
+            if (i < n) {
+                pr[q] = z[q] + bcg * pr[q];
+                s_p[i] = pr[q];
+            }
+        }
+        rz = rz_new;
+        iters += 1;
+        if (!(fabs(alpha) < INFINITY) || !(pq > 0.0)) {
+            broke = 1;
+            done = true;
+        } else if (l1 <= tol || iters >= A.max_cg) {
+            done = true;
+        }
+        __syncthreads();                        // s_p before the next column-sum pass
+    }
+    if (tid < CBp && jc < j1) A.ptd[jc] = ptd;  // every owner its columns
+    if (g == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            const int64_t i = tid + (int64_t)q * TT;
+            if (i < n) {
+                A.d[i] = d[q];
+                A.pcptd[i] = pc[q];
+            }
+        }
+        if (tid == 0) {
+            CgScalars* sc = A.sc;
+            sc->rz = rz;
+            sc->rz_new = rz_new;
+            sc->pq = pq;
+            sc->alpha = alpha;
+            sc->beta = bcg;
+            sc->res_l1 = l1;
+            sc->tol = tol;
+            sc->iters = iters;
+            sc->broke = broke;
+            sc->max_iter = A.max_cg;
+            sc->done = ab ? 0 : 1;
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_team_solve(int kind, const TeamLaunch& L, int grid, hipStream_t s)
@@ -1352,6 +1674,49 @@ hipError_t team_max_grid(int kind, int* blocks_per_cu, int* cus)
     e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     return hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev);
+}
+
+template <int KIND, bool MIXED>
+const void* cgp_fn()
+{
+    return reinterpret_cast<const void*>(&k_cg_persist<KIND, MIXED>);
+}
+
+// Points in R^3 are not taken: that instantiation returned directions up to
+// 27% off the launches-per-iteration path's (deterministically, on 300 x 517
+// and 320 x 520 clouds, not on 256 x 256 or with 128 workgroups), while dense
+// costs and points in the plane agree to rounding; the cause was not found.
+const void* cgp_select(int kind, int mixed)
+{
+    switch (kind) {
+    case 0: return mixed ? cgp_fn<0, true>() : cgp_fn<0, false>();
+    case 1: return mixed ? nullptr : cgp_fn<1, false>();
+    case 2: return mixed ? cgp_fn<2, true>() : cgp_fn<2, false>();
+    default: return nullptr;
+    }
+}
+
+hipError_t launch_cg_persist(const CgpArgs& A, int grid, hipStream_t s)
+{
+    const void* fn = cgp_select(A.KIND, A.mixed);
+    if (!fn) return hipErrorInvalidValue;
+    void* args[] = {const_cast<CgpArgs*>(&A)};
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(TT), args, 0, s);
+}
+
+hipError_t cg_persist_max_grid(int kind, int mixed, int* grid)
+{
+    const void* fn = cgp_select(kind, mixed);
+    if (!fn) return hipErrorInvalidValue;
+    int per_cu = 0, cus = 0, dev = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, TT, 0);
+    if (e != hipSuccess) return e;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    *grid = per_cu * cus;
+    return hipSuccess;
 }
 
 }  // namespace eot

@@ -156,6 +156,7 @@ SIGNATURES = {
                               _c_vp]),
     "eot_set_rows_per_tile": (_c_i32, [_c_i32]),
     "eot_set_team_size": (_c_i32, [_c_i32, _c_i64]),
+    "eot_set_cg_persist": (_c_i32, [_c_i32, _c_i32]),
     "eot_pass_timing": (_c_i32, [_c_i32]),
     "eot_pass_timing_read": (_c_i32, [_c_i32, _c_i32, _c_i32, _c_i32, ctypes.POINTER(_c_i64),
                                       ctypes.POINTER(_c_f64)]),
@@ -567,6 +568,12 @@ def eot_set_rows_per_tile(rows: int) -> None:
     """Force the tile height of the passes (power of two in [8, 256]); 0 restores
     the library's choice."""
     _check(lib().eot_set_rows_per_tile(int(rows)), "eot_set_rows_per_tile")
+
+
+def eot_set_cg_persist(enable: int, grid: int = 0) -> None:
+    """Single-launch CG of small problems on (1, default) or off (0); grid
+    0 = default workgroup count."""
+    _check(lib().eot_set_cg_persist(int(enable), int(grid)), "eot_set_cg_persist")
 
 
 def eot_set_team_size(k: int, entries_per_wg: int = 0) -> None:

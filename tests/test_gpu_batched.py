@@ -17,6 +17,15 @@ pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
 
 
+@pytest.fixture(autouse=True)
+def _launches_per_iteration():
+    """The batch workers (and the CG graph replay) launch each CG iteration;
+    the single solves they are compared with bitwise do the same here."""
+    eot.eot_set_cg_persist(0, 0)
+    yield
+    eot.eot_set_cg_persist(1, 0)
+
+
 def say(msg):
     print(f"[gpu-batch] {msg}", flush=True)
 
