@@ -100,7 +100,7 @@ struct GradVecs {
 
 // Buffers of the single-launch CG (launch_cg_persist) for small problems.
 struct CgpVecs {
-    double* sync = nullptr;       // kCgpSyncDoubles: barrier flags, then the abort word
+    double* sync = nullptr;       // 8 doubles: the abort word
 };
 
 // Single-launch CG: 0 off, 1 on (default); a fixed grid or 0 for the default.
@@ -252,7 +252,7 @@ void carve(Arena& ar, Ctx& x, int op)
     }
     if ((op == EOT_OP_NEWTON_CG || op == EOT_OP_SOLVE || op == EOT_OP_GRADIENT) &&
         cgp_kind(x.cost) >= 0) {
-        x.cgp.sync = ar.take<double>(kCgpSyncDoubles);
+        x.cgp.sync = ar.take<double>(8);
     }
     if (op == EOT_OP_NEWTON_CG || op == EOT_OP_SOLVE || op == EOT_OP_GRADIENT) {
         NewtonVecs& v = x.nv;
@@ -612,9 +612,10 @@ eot_status device_pcg(Ctx& x, int prec, const double* u, const double* lr, const
         A.sc = x.sc.cg;
         A.wc = V.wc;
         A.t = V.t;
-        A.sync = reinterpret_cast<uint32_t*>(x.cgp.sync);
-        A.abort = reinterpret_cast<int32_t*>(x.cgp.sync + kCgpMaxGrid / 2);
-        HIPCHK(launch_fill(x.cgp.sync, 0.0, kCgpSyncDoubles, x.s));
+        A.abort = reinterpret_cast<int32_t*>(x.cgp.sync);
+        HIPCHK(launch_fill(x.cgp.sync, 0.0, 8, x.s));
+        HIPCHK(launch_fill(V.wc, 0.0, m, x.s));            // tag 0: nothing published yet
+        HIPCHK(launch_fill(V.t, 0.0, n, x.s));
         HIPCHK(launch_cg_persist(A, cgp_grid, x.s));
         CgScalars h{};
         EOTCHK(fetch(x, reinterpret_cast<const double*>(x.sc.cg), reinterpret_cast<double*>(&h),

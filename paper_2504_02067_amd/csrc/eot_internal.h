@@ -319,8 +319,8 @@ inline int64_t team_doubles_of(int64_t vstride, int K)
 // at most the co-resident capacity (team_max_grid). Cooperative launch.
 // One preconditioned CG solve of NewtonSolve (Alg. 2's inner loop) in a single
 // cooperative launch, for small problems (n, m <= kCgpMaxDim): the iterations
-// run on the device with two grid barriers each (after the column-sum pass and
-// after the row-sum pass), instead of four launches per iteration. Workgroup g
+// run on the device, two exchanges each (the column sums, then the row sums)
+// through iteration-tagged values, instead of four launches per iteration. Workgroup g
 // owns a block of at most 8 columns in the column-sum pass and of at most 8
 // rows in the row-sum pass (so the grid has at least max(n, m) / 8
 // workgroups); every workgroup keeps its own copy of the n-side CG vectors and
@@ -338,11 +338,10 @@ struct CgpArgs {
     int32_t max_cg;
     double *d, *ptd, *pcptd;      // outputs: solution, P^T d (m), P (P^T d / c) (n)
     CgScalars* sc;                // output scalars
-    double *wc, *t;               // exchange: (P^T p) / c (m), P ((P^T p) / c) (n)
-    uint32_t* sync;               // [kCgpMaxGrid] barrier flags; zeroed before the launch
+    double *wc, *t;               // exchange: (P^T p) / c (m), P ((P^T p) / c) (n), tagged;
+                                  // zeroed before the launch
     int32_t* abort;               // set when a wait timed out; zeroed before the launch
 };
-constexpr int kCgpSyncDoubles = kCgpMaxGrid / 2 + 8;   // the flags, then the abort word
 hipError_t launch_cg_persist(const CgpArgs& A, int grid, hipStream_t s);
 hipError_t cg_persist_max_grid(int kind, int mixed, int* grid);
 

@@ -1332,68 +1332,17 @@ __global__ __launch_bounds__(TT, 4) void k_team_solve(TeamLaunch L)
 // in registers (at most kCgpKMax per pass), and an iteration is two
 // register-times-LDS products and the vector update. Column-sum pass:
 // workgroup g owns a block of at most 8 columns and sums them over all rows
-// (no partial sums to merge), writing (P^T p) / c. Row-sum pass: workgroup g
-// owns a block of at most 8 rows and sums them over all columns, writing
-// t = P ((P^T p) / c). Each is followed by a grid barrier. Every workgroup
-// then reads all of t and updates all n rows of its own copy of the CG vectors
-// (registers) in the same order as every other workgroup: the dot products,
-// the step and the stop test come out bitwise equal everywhere, so all
-// workgroups leave the loop together without exchanging decisions. P^T d is
-// kept by the owners of its columns.
+// (no partial sums to merge), publishing (P^T p) / c. Row-sum pass: workgroup
+// g reads all of (P^T p) / c, owns a block of at most 8 rows and sums them over
+// all columns, publishing t = P ((P^T p) / c). Every workgroup then reads all
+// of t and updates all n rows of its own copy of the CG vectors (registers) in
+// the same order as every other workgroup: the dot products, the step and the
+// stop test come out bitwise equal everywhere, so all workgroups leave the
+// loop together without exchanging decisions. P^T d is kept by the owners of
+// its columns.
 
 constexpr int kCgpKMax = 32;              // plan entries per thread and pass
 constexpr int kCgpRowsPerThread = (int)(kCgpMaxDim / TT);
-
-// Grid barrier: each workgroup has a flag word holding the number of the last
-// barrier it reached. Arrival: the workgroup's own memory operations complete,
-// then it stores its barrier number into its flag (device scope). Wait: wave 0
-// reads every workgroup's flag (one device-scope load per lane and round) until
-// all have reached this barrier. No counter is shared, so arrivals do not
-// serialise on one address, and numbers only grow, so nothing is reset between
-// barriers. Every wait is bounded and raises the abort flag when it runs out;
-// returns true when the abort flag is set.
-__device__ bool cgp_barrier(uint32_t* flags, int G, uint32_t epoch, int32_t* abort, int* s_ab)
-{
-    __builtin_amdgcn_s_waitcnt(0);
-#ifdef EOT_CGP_FENCE
-    __atomic_thread_fence(__ATOMIC_RELEASE);
-#endif
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        const int lane = (int)threadIdx.x;
-        if (lane == 0) __hip_atomic_store(flags + blockIdx.x, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t spins = 0;
-        int ab = 0;
-        for (;;) {
-            int ok = 1;
-            for (int q = lane; q < G; q += 64) {
-                const uint32_t f = __hip_atomic_load(flags + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok &= (int32_t)(f - epoch) >= 0 ? 1 : 0;
-            }
-            if (__all(ok)) break;
-            __builtin_amdgcn_s_sleep(1);
-            if ((++spins & 63) == 0) {                    // the abort word every 64 rounds
-                const int a = __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (__builtin_amdgcn_readfirstlane(a)) {
-                    ab = 1;
-                    break;
-                }
-            }
-            if (spins > kSpinLimit) {
-                if (lane == 0) __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ab = 1;
-                break;
-            }
-        }
-        __builtin_amdgcn_s_waitcnt(0);
-        if (lane == 0) *s_ab = ab;
-    }
-#ifdef EOT_CGP_FENCE
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
-#endif
-    __syncthreads();
-    return *s_ab != 0;                  // rewritten only after the next barrier's first sync
-}
 
 // Two workgroup sums in one round (fixed order, every thread gets both).
 __device__ __forceinline__ void wg_sum2(double& x, double& y, double* s_red2)
@@ -1416,26 +1365,84 @@ __device__ __forceinline__ void wg_sum2(double& x, double& y, double* s_red2)
     y = b;
 }
 
-// dst[0..k) = the device-scope values at src[0..k), loads issued in groups of 4
-__device__ __forceinline__ void cgp_gather(double* dst, const double* src, int64_t k)
+// The exchange carries its own readiness: a value published in iteration k is
+// stored with the parity of k in its lowest mantissa bit (one 8-byte store,
+// which is single-copy atomic), and a reader polls each value until that bit
+// reads k's parity. A slot holds iteration k - 1's value until it is
+// overwritten (or, for k = 1, the zeros the host writes before the launch), so
+// a stale value is never taken, and iteration k + 1's value cannot appear
+// before every reader has taken iteration k's: a workgroup publishes k + 1
+// only after it has read every workgroup's iteration-k values of the other
+// buffer, which each of them published only after reading iteration k's values
+// of this one. No barrier is needed. The tag bit stays in the value,
+// identically in every workgroup (a change of at most one unit in the last
+// place).
+__device__ __forceinline__ unsigned long long cgp_tagged(double v, uint32_t k)
 {
-    constexpr int B = 4;
-    for (int64_t i0 = threadIdx.x; i0 < k; i0 += (int64_t)TT * B) {
-        double v[B];
-#pragma unroll
-        for (int q = 0; q < B; ++q) {
-            const int64_t i = i0 + (int64_t)q * TT;
-            v[q] = i < k ? ld_dev(src + i) : 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < B; ++q) {
-            const int64_t i = i0 + (int64_t)q * TT;
-            if (i < k) dst[i] = v[q];
-        }
-    }
+    return (__builtin_bit_cast(unsigned long long, v) & ~1ull) | (unsigned long long)(k & 1u);
 }
 
-// P_ij = exp(a_i) e_ij; point coordinates from the LDS copies sx, sy.
+__device__ __forceinline__ void cgp_publish(double* slot, double v, uint32_t k)
+{
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(slot), cgp_tagged(v, k),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// dst[0..cnt) = iteration k's values of src[0..cnt), each polled until its tag
+// reads k's parity (at most kCgpRowsPerThread values per thread). Every wait is
+// bounded and raises the abort flag when it runs out; returns true when the
+// abort flag is set (the same in every thread of the workgroup).
+template <int NQ>
+__device__ bool cgp_gather(double* dst, const double* src, int64_t cnt, uint32_t k,
+                           int32_t* abort, int* s_ab)
+{
+    const unsigned long long* s = reinterpret_cast<const unsigned long long*>(src);
+    const unsigned long long want = k & 1u;
+    unsigned long long v[NQ];
+    int pending = 0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int64_t i = threadIdx.x + (int64_t)q * TT;
+        v[q] = want;
+        if (i < cnt) {
+            v[q] = __hip_atomic_load(s + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            pending |= ((v[q] & 1ull) != want) << q;
+        }
+    }
+    uint32_t spins = 0;
+    int ab = 0;
+    while (pending) {
+        __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            if (pending & (1 << q)) {
+                const int64_t i = threadIdx.x + (int64_t)q * TT;
+                v[q] = __hip_atomic_load(s + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((v[q] & 1ull) == want) pending &= ~(1 << q);
+            }
+        }
+        if ((++spins & 255) == 0 && __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            ab = 1;
+            break;
+        }
+        if (spins > kSpinLimit) {
+            __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ab = 1;
+            break;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int64_t i = threadIdx.x + (int64_t)q * TT;
+        if (i < cnt) dst[i] = __builtin_bit_cast(double, v[q]);
+    }
+    if (threadIdx.x == 0) *s_ab = 0;
+    __syncthreads();
+    if (ab) *s_ab = 1;
+    __syncthreads();
+    return *s_ab != 0;
+}
+
 template <int KIND, bool MIXED>
 __device__ __forceinline__ double cgp_entry(const CgpArgs& A, double bb, int64_t i, int64_t j,
                                             const float* sx, const float* sy)
@@ -1484,6 +1491,7 @@ __global__ __launch_bounds__(TT) void k_cg_persist(CgpArgs A)
     const int64_t jc = j0 + cc, ir = i0 + rr;
     const double bb = beta_eff<KIND, MIXED>(A.P, A.beta);
     const double rho = A.rho, tol = A.tol;
+    const double cj = (tid < CBp && jc < j1) ? A.c[jc] : 1.0;
     __syncthreads();                           // the exp table and the points
 
     // the plan entries of this thread: column jc at rows rg + k NRG, row ir at
@@ -1526,47 +1534,55 @@ __global__ __launch_bounds__(TT) void k_cg_persist(CgpArgs A)
     int iters = 0, broke = 0;
     double pq = 0.0, alpha = 0.0, bcg = 0.0, rz_new = rz;
     bool ab = false;
-    uint32_t epoch = 0;                        // barriers passed (the flag words start at 0)
     bool done = l1 <= tol || A.max_cg <= 0;
     while (!done && !ab) {
-        // column-sum pass over the owned columns
-        double acc = 0.0;
+        // column-sum pass over the owned columns: two chains per thread, the
+        // row groups of a column added across the wave's lanes, then the waves
+        double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-        for (int k = 0; k < kCgpKMax; ++k) {
+        for (int k = 0; k < kCgpKMax; k += 2) {
             const int64_t i = rg + (int64_t)k * NRG;
-            if (i < n) acc = fma(EC[k], s_p[i], acc);
+            if (i < n) a0 = fma(EC[k], s_p[i], a0);
+            if (i + NRG < n) a1 = fma(EC[k + 1], s_p[i + NRG], a1);
         }
-        s_cp[tid] = acc;
+        double acc = a0 + a1;
+        for (int off = CBp; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
+        if ((tid & 63) < CBp) s_cp[(tid >> 6) * CBp + (tid & 63)] = acc;
         __syncthreads();
+        const uint32_t it1 = (uint32_t)iters + 1;
         if (tid < CBp) {
             double sw = 0.0;
-            for (int r = 0; r < NRG; ++r) sw += s_cp[r * CBp + tid];
-            wcol = sw;
-            if (jc < j1) st_dev(A.wc + jc, sw / A.c[jc]);
-        }
-        ab = cgp_barrier(A.sync, G, ++epoch, A.abort, &s_ab);
-        if (ab) break;
-        // row-sum pass over the owned rows
-        cgp_gather(s_wc, A.wc, m);
-        __syncthreads();
-        acc = 0.0;
 #pragma unroll
-        for (int k = 0; k < kCgpKMax; ++k) {
-            const int64_t j = cl + (int64_t)k * CGp;
-            if (j < m) acc = fma(ER[k], s_wc[j], acc);
+            for (int w = 0; w < TW; ++w) sw += s_cp[w * CBp + tid];
+            wcol = sw;
+            if (jc < j1) cgp_publish(A.wc + jc, sw / cj, it1);
         }
-        s_cp[tid] = acc;
+        // row-sum pass over the owned rows
+        ab = cgp_gather<kCgpRowsPerThread>(s_wc, A.wc, m, it1, A.abort, &s_ab);
+        if (ab) break;
+        a0 = 0.0;
+        a1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < kCgpKMax; k += 2) {
+            const int64_t j = cl + (int64_t)k * CGp;
+            if (j < m) a0 = fma(ER[k], s_wc[j], a0);
+            if (j + CGp < m) a1 = fma(ER[k + 1], s_wc[j + CGp], a1);
+        }
+        acc = a0 + a1;
+        // a row's column lanes: within the wave, then its waves (CGp >= 32)
+        const int span = CGp < 64 ? CGp : 64;
+        for (int off = 1; off < span; off <<= 1) acc += __shfl_xor(acc, off, 64);
+        if ((tid & (span - 1)) == 0) s_cp[tid / span] = acc;
         __syncthreads();
         if (tid < RBp) {
+            const int per = CGp / span;
             double st = 0.0;
-            for (int k = 0; k < CGp; ++k) st += s_cp[tid * CGp + k];
-            if (i0 + tid < i1) st_dev(A.t + i0 + tid, st);
+            for (int k = 0; k < per; ++k) st += s_cp[tid * per + k];
+            if (i0 + tid < i1) cgp_publish(A.t + i0 + tid, st, it1);
         }
-        ab = cgp_barrier(A.sync, G, ++epoch, A.abort, &s_ab);
-        if (ab) break;
         // the vector step over all rows, the same in every workgroup
-        cgp_gather(s_t, A.t, n);
-        __syncthreads();
+        ab = cgp_gather<kCgpRowsPerThread>(s_t, A.t, n, it1, A.abort, &s_ab);
+        if (ab) break;
         double pqa = 0.0;
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
