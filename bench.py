@@ -412,8 +412,10 @@ def grid28_measure(eot, W, dev, seeds=3):
     """Time to 1e-6 marginal error on the 28 x 28 grid (n = m = 784, dense FP32
     cost, temperature 1/32 -> 1e-4), L1 and squared-L2 costs, mixed against plain
     FP64; medians over seeds 2000.. (each solve timed after one untimed solve of
-    the same instance). Small problems: the solve is bound by launches and host
-    round trips, not by the passes."""
+    the same instance). Small problems: the solve is bound by latency (each CG
+    solve is one cooperative launch, the rest of Alg. 4 launches per step), not
+    by the passes. For comparison, the FP64 solve of the first seed also with
+    the CG launched per iteration (eot_set_cg_persist(0))."""
     import torch
     res = {"workload": f"grid28 n=m=784 dense FP32 cost, 3-blob marginals seeds 2000..{2000 + seeds - 1}, "
                        "temperature 1/32 -> 1e-4, tol 1e-6"}
@@ -440,14 +442,32 @@ def grid28_measure(eot, W, dev, seeds=3):
                 costs[prec].append(st["cost"])
                 errs[prec].append(st["err_r"] + st["err_c"])
         med = {k: float(np.median(v)) for k, v in rows.items()}
+        p = W.mnist_like_problem(2000, kind)
+        C = torch.from_numpy(p.C).to(dev)
+        r = torch.from_numpy(p.r).to(dev)
+        c = torch.from_numpy(p.c).to(dev)
+        o = eot.default_solve_opts(gamma_init=p.gamma_init, gamma_final=p.gamma_final, tol=p.tol,
+                                   precision="fp64")
+        eot.eot_set_cg_persist(0, 0)
+        try:
+            eot.eot_solve(C, r, c, opts=o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            eot.eot_solve(C, r, c, opts=o)
+            torch.cuda.synchronize()
+            launches_s = time.perf_counter() - t0
+        finally:
+            eot.eot_set_cg_persist(1, 0)
         res[kind] = {"mixed_ms": 1e3 * med["mixed"], "fp64_ms": 1e3 * med["fp64"],
+                     "fp64_cg_launched_per_iteration_ms_seed2000": 1e3 * launches_s,
                      "mixed_us_per_cg_iter": 1e6 * float(np.median(per_cg["mixed"])),
                      "fp64_us_per_cg_iter": 1e6 * float(np.median(per_cg["fp64"])),
                      "speedup_mixed_vs_fp64": med["fp64"] / med["mixed"],
                      "max_err": float(max(errs["mixed"] + errs["fp64"])),
                      "max_cost_rel_diff": float(max(abs(a - b) / b for a, b in
                                                     zip(costs["mixed"], costs["fp64"])))}
-        log(f"grid28 {kind}: mixed {res[kind]['mixed_ms']:.1f} ms, fp64 {res[kind]['fp64_ms']:.1f} ms, "
+        log(f"grid28 {kind}: mixed {res[kind]['mixed_ms']:.1f} ms, fp64 {res[kind]['fp64_ms']:.1f} ms "
+            f"(CG launched per iteration: {1e3 * launches_s:.1f} ms), "
             f"cost rel diff {res[kind]['max_cost_rel_diff']:.1e}")
     return res
 
@@ -595,6 +615,9 @@ def main():
                          "counter runs)")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the 512-problem batch in both precisions (for trace runs)")
+    ap.add_argument("--grid28-only", choices=("l1", "sqeuclid"),
+                    help="only one FP64 solve of the 28 x 28 grid (seed 2000) with that cost, after "
+                         "one untimed solve (for trace runs)")
     ap.add_argument("--highd-only", action="store_true",
                     help="only 1 + 5 mixed high-dimensional HVP passes (n = m = 65536, d = 64; "
                          "for counter runs)")
@@ -608,6 +631,20 @@ def main():
     from paper_2504_02067_amd import eot, workloads as W
 
     dev = torch.device("cuda:0")
+    if args.grid28_only:
+        p = W.mnist_like_problem(2000, args.grid28_only)
+        C = torch.from_numpy(p.C).to(dev)
+        r = torch.from_numpy(p.r).to(dev)
+        c = torch.from_numpy(p.c).to(dev)
+        o = eot.default_solve_opts(gamma_init=p.gamma_init, gamma_final=p.gamma_final, tol=p.tol,
+                                   precision="fp64")
+        eot.eot_solve(C, r, c, opts=o)
+        _, _, st = eot.eot_solve(C, r, c, opts=o)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "grid28-only", "cost": args.grid28_only,
+                          "cg_iters": st["cg_iters"], "newton_steps": st["newton_steps"],
+                          "seconds": st["seconds"]}), flush=True)
+        return
     if args.highd_only:
         highd_only(eot, W, dev)
         return
