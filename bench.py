@@ -342,6 +342,11 @@ def highd_measure(args, eot, W, dev, iters=5):
         res[f"{name}_mixed_ms"] = sec * 1e3
         res[f"{name}_mfma_frac"] = 3 * 2 * d * float(n) * m / sec / 2.5e15
         res[f"{name}_mfma_method_frac"] = 2 * d * float(n) * m / sec / 2.5e15
+    want = ("log_rP", "log_cP")
+    ref = eot.eot_marginals(pc, gamma, f, g, precision="fp64", want=want)
+    mx = eot.eot_marginals(pc, gamma, f, g, row_shift=ref["log_rP"], precision="mixed", want=want)
+    res["mixed_log_marginal_err_vs_fp64"] = max(float((mx[w] - ref[w]).abs().max()) for w in want)
+    res["beta_over_scale"] = 1.0 / gamma / p.scale
     eps = res["mixed_entries_per_s"]
     mfma = 3 * 2 * d * eps                      # BF16 hi/lo: three products per dimension pair
     res["mfma"] = {"achieved": mfma / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
@@ -359,6 +364,8 @@ def highd_measure(args, eot, W, dev, iters=5):
     log(f"high-d HVP mixed {res['mixed_ms']:.2f} ms ({eps / 1e12:.2f} T entries/s, MFMA "
         f"{mfma / 1e12:.0f} TFLOP/s = {100 * mfma / 2.5e15:.1f}% of BF16 peak), FP64 {res['fp64_ms']:.2f} ms "
         f"(FP64 MFMA {mfma64 / 1e12:.1f} TFLOP/s = {100 * mfma64 / 78.6e12:.0f}% of FP64 peak)")
+    log(f"high-d mixed log-marginal error vs FP64 at gamma {gamma:g}: "
+        f"{res['mixed_log_marginal_err_vs_fp64']:.1e}")
     log(f"high-d CG passes mixed: column {res['colpass_mixed_ms']:.2f} ms "
         f"({100 * res['colpass_mfma_frac']:.1f}% of BF16 peak), row {res['rowpass_mixed_ms']:.2f} ms "
         f"({100 * res['rowpass_mfma_frac']:.1f}%)")

@@ -306,3 +306,33 @@ def test_highd_atomic_outputs_sampled(prec):
     _, ay = O.hvp(C_cols, beta, u, v[cols], rho, np.abs(x), np.abs(y[cols]))
     assert np.all(np.abs(host(Hx)[rows] - hx_ref) <= tol * ax + 1e-300)
     assert np.all(np.abs(host(Hy)[cols] - hy_ref) <= tol * ay + 1e-300)
+
+
+def test_highd_mixed_error_at_the_final_temperature():
+    """The embedding workload's own temperatures (1/8 -> 1e-2, beta / scale = 25 at the
+    end) at n = m = 2048, d = 64: a mixed solve, then the mixed log marginals at its
+    output potentials against the oracle's. States the error the matrix-core form makes
+    where the solve ends (the bound of the module docstring, 1.2e-3 at beta = 100), and
+    that the solve still reaches its tolerance: the mixed projections that stall at that
+    floor hand over to FP64 (R18), the last one always finishes in FP64."""
+    p, pc, C = cloud(2048, 2048, 64, 77)
+    gamma = p.gamma_final
+    beta = 1.0 / gamma
+    f, g, st = eot.eot_solve(pc, dvec(p.r), dvec(p.c), gamma_init=p.gamma_init,
+                             gamma_final=gamma, tol=p.tol, precision="mixed")
+    assert st["status"] == 0 and st["err_r"] + st["err_c"] <= p.tol
+    u, v = O.to_log_units(host(f), host(g), gamma)
+    lr_ref = O.log_row_marginal(C, beta, u, v)
+    lc_ref = O.log_col_marginal(C, beta, u, v)
+    res = {}
+    for prec in ("mixed", "fp64"):
+        out = eot.eot_marginals(pc, gamma, f, g, precision=prec, want=("log_rP", "log_cP"))
+        torch.cuda.synchronize()
+        res[prec] = max(np.abs(host(out["log_rP"]) - lr_ref).max(),
+                        np.abs(host(out["log_cP"]) - lc_ref).max())
+    say(f"embeddings 2048 x 2048, d = 64, solve at gamma {gamma:g} (beta {beta:g}): log-marginal "
+        f"error against the oracle mixed {res['mixed']:.2e} (bound {mixed_tol(beta):.1e}), "
+        f"fp64 {res['fp64']:.1e}; solve error {st['err_r'] + st['err_c']:.1e}, mixed stalls "
+        f"{st['mixed_stalls']}, range retries {st['range_retries']}")
+    assert res["mixed"] <= mixed_tol(beta)
+    assert res["fp64"] <= 1e-12 + 2.0 ** -52 * beta * C.max()
