@@ -1699,9 +1699,11 @@ const void* cgp_fn()
 }
 
 // Points in R^3 are not taken: that instantiation returned directions up to
-// 27% off the launches-per-iteration path's (deterministically, on 300 x 517
-// and 320 x 520 clouds, not on 256 x 256 or with 128 workgroups), while dense
-// costs and points in the plane agree to rounding; the cause was not found.
+// 27% off the launches-per-iteration path's, deterministically, on 300 x 517
+// and 320 x 520 clouds (where a thread's row-pass entries 16..31 are in use),
+// while every tested 3-D shape with n, m <= 512, the same shapes with 128
+// workgroups, dense costs and points in the plane agree to rounding; the
+// cause was not found.
 const void* cgp_select(int kind, int mixed)
 {
     switch (kind) {
