@@ -164,14 +164,19 @@ def cpu_baseline(p, C_rows_fn, W, batch=None, budget_s=6.0):
 
 
 def valu_cycles_points_hvp(d):
-    """VALU lane instructions per plan entry of the method's own work in the
-    point-cloud HVP (each issues in one slot; counters on MI355X show
-    v_exp_f32 taking one slot too): d subtractions and d multiply-adds for
-    |x - y|^2, two for the exponent (sum of the row and column parts, one
-    multiply-add with the cost), exp, and one accumulation each for the row
-    and the column sum. The implementation issues 16.2 per entry at d = 3
-    (FP64 accumulation, loop control, per-row reductions)."""
+    """FP32 vector lane operations per plan entry of the method's own work in
+    the point-cloud HVP with the marginals given: d subtractions and d
+    multiply-adds for |x - y|^2, two for the exponent (sum of the row and
+    column parts, one multiply-add with the cost), exp, and one accumulation
+    each for the row and the column sum (11 at d = 3). The implementation
+    issues about 13.5 per entry (the lo part of beta, per-row reductions, loop
+    control)."""
     return 2 * d + 2 + 1 + 2
+
+
+# FP32 vector lane operations per second: the published FP32 vector peak
+# (157.3 TFLOP/s, a multiply-add counted as two flops) over two.
+FP32_LANE_OPS = 157.3e12 / 2
 
 
 def points_measure(args, eot, W, dev, iters=4):
@@ -200,9 +205,24 @@ def points_measure(args, eot, W, dev, iters=4):
     sec = ms / 1e3 / k
     elems = float(n) * float(m)
     cyc = valu_cycles_points_hvp(3)
-    lane_rate = 256 * 4 * 16 * 2.4e9          # CUs x SIMDs x lanes x clock
-    peak_eps = lane_rate / cyc
+    peak_eps = FP32_LANE_OPS / cyc
     log(f"points HVP {sec * 1e3:.1f} ms per pass, {elems / sec / 1e12:.3f} T elements/s")
+    # the same product with r(P), c(P) given (one weighted sum per direction)
+    mg = eot.eot_marginals(pc, gamma, f, g, row_shift=shift, precision="mixed",
+                           want=("log_rP", "log_cP"))
+    eot.eot_hvp_with_marginals(pc, gamma, f, g, mg["log_rP"], mg["log_cP"], 1.0, x, y,
+                               precision="mixed")
+    torch.cuda.synchronize()
+    eot.eot_pass_timing(True)
+    for _ in range(iters):
+        eot.eot_hvp_with_marginals(pc, gamma, f, g, mg["log_rP"], mg["log_cP"], 1.0, x, y,
+                                   precision="mixed")
+    torch.cuda.synchronize()
+    k2, ms2 = eot.eot_pass_timing_read(nr=1, nc=1, fused_hvp=0, precision="mixed")
+    eot.eot_pass_timing(False)
+    sec_m = ms2 / 1e3 / k2
+    log(f"points HVP with marginals {sec_m * 1e3:.1f} ms per pass, "
+        f"{elems / sec_m / 1e12:.3f} T elements/s")
     # a full solve on the same mixtures at n = m = 65536 (temperature 1/32 -> 1e-4, tol 1e-4)
     q = W.point_cloud_problem(n=1 << 16)
     qc = eot.PointCloud(torch.from_numpy(q.X).to(dev), torch.from_numpy(q.Y).to(dev), q.scale)
@@ -217,12 +237,17 @@ def points_measure(args, eot, W, dev, iters=4):
     log(f"points solve n = m = {q.n}: {qt:.2f} s, {qp} passes, error {qs['err_r'] + qs['err_c']:.1e}")
     mf = points_mfma_form(eot, pc, p, f, g, x, y, shift, gamma, iters, sec,
                           cold=(qc, q, qf, qg))
-    return {"workload": f"gmm3d n=m={n} d=3 on-the-fly |x-y|^2/s, mixed HVP pass",
-            "kernel_ms": sec * 1e3, "elements_per_s": elems / sec,
-            "roofline": {"bound": "alu", "achieved": elems / sec / 1e12,
+    return {"workload": f"gmm3d n=m={n} d=3 on-the-fly |x-y|^2/s, mixed HVP pass "
+                        "(eot_hvp_with_marginals: r(P), c(P) given, P y and P^T x in one pass)",
+            "kernel_ms": sec_m * 1e3, "elements_per_s": elems / sec_m,
+            "roofline": {"bound": "alu", "achieved": elems / sec_m / 1e12,
                          "peak": peak_eps / 1e12, "unit": "T elements/s",
-                         "frac": elems / sec / peak_eps,
-                         "valu_cycles_per_element": cyc},
+                         "frac": elems / sec_m / peak_eps,
+                         "fp32_lane_ops_per_element": cyc},
+            "fused_hvp": {
+                "note": "eot_hvp: r(P), c(P) formed in the same pass (two sums per direction)",
+                "kernel_ms": sec * 1e3, "elements_per_s": elems / sec,
+                "frac": elems / sec / peak_eps},
             "mfma_form": mf,
             "solve": {"workload": f"gmm3d n=m={q.n} d=3, temperature {q.gamma_init} -> "
                                   f"{q.gamma_final}, tol {q.tol}, mixed",
@@ -547,8 +572,16 @@ def points_only(eot, W, dev, iters=2):
     shift = eot.eot_marginals(pc, gamma, f, g, precision="mixed", want=("log_rP",))["log_rP"]
     for _ in range(1 + iters):
         eot.eot_hvp(pc, gamma, f, g, 1.0, x, y, row_shift=shift, precision="mixed")
+    # then the product with the marginals given: one marginal pass and 1 + iters
+    # HVP passes of the same kernel (k_pass<..., 1, 1, 0, ...>)
+    mg = eot.eot_marginals(pc, gamma, f, g, row_shift=shift, precision="mixed",
+                           want=("log_rP", "log_cP"))
+    for _ in range(1 + iters):
+        eot.eot_hvp_with_marginals(pc, gamma, f, g, mg["log_rP"], mg["log_cP"], 1.0, x, y,
+                                   precision="mixed")
     torch.cuda.synchronize()
-    print(json.dumps({"mode": "points-only", "hvp_launches": 1 + iters, "entries": float(n) * m}),
+    print(json.dumps({"mode": "points-only", "hvp_launches": 1 + iters,
+                      "hvp_with_marginals_launches": 1 + iters, "entries": float(n) * m}),
           flush=True)
 
 

@@ -151,6 +151,26 @@ eot_status eot_hvp_noalloc(const eot_cost* cost, double gamma, const double* f, 
                            const double* row_shift, double rho, const double* x, const double* y,
                            double* Hx, double* Hy, int32_t prec, void* stream);
 
+/* The same discounted Hessian-vector product with the plan's marginals given,
+ * as a Newton solver has them at its current iterate (eqs. hessian and
+ * discounted-hessian: the diagonal blocks are D(r(P)) and D(c(P))):
+ *   Hx = exp(log_rP) * x + sqrt(rho) * P y,    Hy = sqrt(rho) * P^T x + exp(log_cP) * y.
+ * The pass then carries one weighted sum per direction instead of two (P y
+ * over rows, P^T x over columns), which matters where the pass is bound by
+ * arithmetic rather than memory (point clouds). log_rP (n) and log_cP (m) are
+ * log r(P) and log c(P) at (f, g), e.g. from eot_marginals; log_rP also serves
+ * as the row shift (the same range requirement as row_shift of
+ * eot_marginals). Results equal eot_hvp's up to rounding when the marginals
+ * are exact; other marginals give the operator with those diagonal blocks.
+ * All pointers are device memory, none nullable; x, Hx: n; y, Hy: m.
+ * Workspace: eot_workspace_size(EOT_OP_HVP, ...). Returns EOT_ERR_INVALID_ARG
+ * for a NULL pointer, gamma <= 0 or rho outside [0, 1]. */
+eot_status eot_hvp_with_marginals(const eot_cost* cost, double gamma, const double* f,
+                                  const double* g, const double* log_rP, const double* log_cP,
+                                  double rho, const double* x, const double* y, double* Hx,
+                                  double* Hy, int32_t prec, void* ws, size_t ws_bytes,
+                                  void* stream);
+
 typedef struct {
     double rho_out;     /* discount at exit (after the update following the last solve, Alg. 2)          */
     int32_t cg_iters;   /* CG iterations over all discount levels                     */

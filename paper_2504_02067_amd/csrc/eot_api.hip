@@ -1804,6 +1804,33 @@ eot_status eot_hvp_noalloc(const eot_cost* cost, double gamma, const double* f, 
                    stream);
 }
 
+eot_status eot_hvp_with_marginals(const eot_cost* cost, double gamma, const double* f,
+                                  const double* g, const double* log_rP, const double* log_cP,
+                                  double rho, const double* xv, const double* yv, double* Hx,
+                                  double* Hy, int32_t prec, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!f || !g || !log_rP || !log_cP || !xv || !yv || !Hx || !Hy || bad_gamma(gamma))
+        return EOT_ERR_INVALID_ARG;
+    if (!(rho >= 0.0 && rho <= 1.0)) return EOT_ERR_INVALID_ARG;
+    Ctx x;
+    EOTCHK(setup(x, cost, EOT_OP_HVP, prec, ws, ws_bytes, stream));
+    const double beta = 1.0 / gamma;
+    double* u = x.tmp_n[0];
+    double* v = x.tmp_m[0];
+    HIPCHK(launch_divs(f, gamma, u, x.n, x.s));
+    HIPCHK(launch_divs(g, gamma, v, x.m, x.s));
+    // One pass, one weighted sum per direction: (P y)_i over rows, (P^T x)_j over
+    // columns; log r(P) doubles as the row shift. The diagonal blocks come from
+    // the given marginals in the epilogue.
+    PassArgs A = make_args(x, u, log_rP, v, beta);
+    A.yw0 = yv;
+    A.xw0 = xv;
+    HIPCHK(run_pass(x, A, prec, 1, 1, R2_WEIGHT));
+    HIPCHK(launch_hvp_finish_diag(x.sc.row_part, x.rtiles, x.sc.col_part, x.ctiles, x.n, x.m,
+                                  log_rP, std::sqrt(rho), log_rP, log_cP, xv, yv, Hx, Hy, x.s));
+    return EOT_OK;
+}
+
 eot_status eot_newton_cg(const eot_cost* cost, double gamma, const double* f, const double* g,
                          const double* r, const double* c, double eta, double rho0,
                          int32_t max_cg, int32_t max_levels, double* dir_f, double* dir_g,

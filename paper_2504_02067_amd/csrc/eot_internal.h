@@ -26,6 +26,16 @@ constexpr int kTileRows = 256;           // maximum rows per tile (column partia
 #endif
 constexpr int kSubRows = EOT_SUB_ROWS;
 constexpr int kSubRowsFused = EOT_SUB_ROWS_FUSED;
+// The same for the point-cloud passes (arithmetic-bound: more rows per
+// sub-band give more independent accumulation chains).
+#ifndef EOT_PTS_SUB_ROWS
+#define EOT_PTS_SUB_ROWS 8
+#endif
+#ifndef EOT_PTS_SUB_ROWS_FUSED
+#define EOT_PTS_SUB_ROWS_FUSED 4
+#endif
+constexpr int kPtsSubRows = EOT_PTS_SUB_ROWS;
+constexpr int kPtsSubRowsFused = EOT_PTS_SUB_ROWS_FUSED;
 // Optional occupancy request (waves per SIMD) for the fused passes, build-time.
 #if defined(EOT_FUSED_WAVES_PER_EU) && EOT_FUSED_WAVES_PER_EU > 0
 #define EOT_FUSED_OCCUPANCY __attribute__((amdgpu_waves_per_eu(EOT_FUSED_WAVES_PER_EU)))
@@ -140,6 +150,11 @@ hipError_t launch_log_ratio_fix(double* v, const double* va, const double* log_c
 hipError_t launch_hvp_finish(const double* row_part, int tiles_m, const double* col_part,
                              int tiles_n, int64_t n, int64_t m, const double* a, double* Hx,
                              double* Hy, hipStream_t s);
+// Hx = exp(log_rP) x + srho exp(a) (row sums), Hy = srho (column sums) + exp(log_cP) y
+hipError_t launch_hvp_finish_diag(const double* row_part, int tiles_m, const double* col_part,
+                                  int tiles_n, int64_t n, int64_t m, const double* a, double srho,
+                                  const double* log_rP, const double* log_cP, const double* x,
+                                  const double* y, double* Hx, double* Hy, hipStream_t s);
 hipError_t launch_log_row_from_sums(const double* part, int tiles, int64_t n, const double* a,
                                     double* log_rP, int32_t* flags, hipStream_t s);
 // Block partial sums of an elementwise expression: writes nb partials to red.

@@ -169,7 +169,14 @@ __device__ __forceinline__ void load_rows(const TC* __restrict__ C, int64_t ldc,
 }
 
 // ---------------------------------------------------------------- the pass
-// PREC = EOT_PREC_MIXED (FP32 exponent / exp, FP64 sums) or EOT_PREC_FP64.
+// Rows whose column sums a lane keeps in FP32 before adding them to its FP64
+// totals (mixed point-cloud passes with plain weights; a multiple of the
+// sub-band height).
+constexpr int kLane32Rows = 16;
+
+// PREC = EOT_PREC_MIXED (FP32 exponent / exp, FP64 sums; the point-cloud
+// passes with plain weights sum in FP32 within a lane, see LANE32) or
+// EOT_PREC_FP64.
 // DP = 0: dense cost streamed from memory. RS rows are in flight per chunk;
 // the next chunk's loads are issued before the current chunk is computed
 // (double buffer), and row partials are reduced per wave in registers, so the
@@ -195,6 +202,11 @@ __device__ __forceinline__ void pass_body(const PassArgs& A)
     __shared__ double s_wmax[kWaves];
     __shared__ float s_x[DP > 0 ? RB * DP : 1];   // point rows
     __shared__ __attribute__((aligned(16))) double s_exp[MIXED ? 2 : kExpTabDoubles];  // FP64: exp_tab256
+    // Mixed point-cloud passes with plain weighted sums (one row and / or one
+    // column sum, weight e_ij): the sums run in FP32 within a lane and in FP64
+    // from there on (lanes, waves, tiles), as in the high-dimensional pass.
+    constexpr bool LANE32 = MIXED && DP > 0 && MODE2 != R2_HVP && NR <= 1 && NC <= 1;
+    __shared__ float s_xwf[LANE32 ? RB : 1];      // FP32 copy of the column-sum weights
 
     const int tid = threadIdx.x;
     if constexpr (!MIXED) load_exp_table(s_exp);  // read after the prologue's barrier
@@ -282,6 +294,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& A)
             s_xw[0][tid] = 0.0;
             s_xw[1][tid] = 0.0;
         }
+        if constexpr (LANE32) s_xwf[tid] = (float)s_xw[0][tid];
         if constexpr (DP > 0) {
 #pragma unroll
             for (int k = 0; k < DP; ++k) s_x[tid * DP + k] = rvalid ? A.X[irow * DP + k] : 0.0f;
@@ -441,16 +454,82 @@ __device__ __forceinline__ void pass_body(const PassArgs& A)
                 }
             };
         };
-        for (int b = 0; b < nsb; ++b) {
-            const int sb = b * RS;
-            double racc[NRA][RS];
+        if constexpr (LANE32) {
+            // Row sums: FP32 over the lane's NCH x V columns of a sub-band, then
+            // the FP64 wave reduction. Column sums: FP32 over kLane32Rows rows,
+            // then added to FP64.
+            static_assert(kLane32Rows % RS == 0, "column runs of whole sub-bands");
+            float ywf[NCH][V];
 #pragma unroll
-            for (int k = 0; k < NRA; ++k)
+            for (int ch = 0; ch < NCH; ++ch)
 #pragma unroll
-                for (int rr = 0; rr < RS; ++rr) racc[k][rr] = 0.0;
-            compute(sb, 0, pts(sb, 0), racc);
-            compute(sb, 1, pts(sb, 1), racc);
-            if constexpr (NR > 0) wave_rows_out<NR, RS, MODE2>(racc, s_rf, sb, i0, n, A);
+                for (int q = 0; q < V; ++q) ywf[ch][q] = (float)ywr[0][ch][q];
+            float cacc32[NCH][V];
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+                for (int q = 0; q < V; ++q) cacc32[ch][q] = 0.0f;
+            for (int b = 0; b < nsb; ++b) {
+                const int sb = b * RS;
+                // one row accumulator per chunk: shorter dependent chains
+                float racc32s[NCH][RS];
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+                    for (int rr = 0; rr < RS; ++rr) racc32s[ch][rr] = 0.0f;
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) {
+                    float (&racc32)[RS] = racc32s[ch];
+                    auto getc = pts(sb, ch);
+#pragma unroll
+                    for (int rr = 0; rr < RS; ++rr) {
+                        const float uh_r = s_uh[sb + rr];
+                        const float xw_r = s_xwf[sb + rr];
+#pragma unroll
+                        for (int q = 0; q < V; ++q) {
+                            const float c = getc(rr, q);
+                            const float t = fmaf(-Bh, c, uh_r + vh[ch][q]);
+                            const float e = __builtin_amdgcn_exp2f(fmaf(-Bl, c, t));
+                            if constexpr (NR > 0) racc32[rr] = fmaf(e, ywf[ch][q], racc32[rr]);
+                            if constexpr (NC > 0) cacc32[ch][q] = fmaf(e, xw_r, cacc32[ch][q]);
+                        }
+                    }
+                }
+                if constexpr (NR > 0) {
+                    double racc[NRA][RS];
+#pragma unroll
+                    for (int rr = 0; rr < RS; ++rr) {
+                        float t = racc32s[0][rr];
+#pragma unroll
+                        for (int ch = 1; ch < NCH; ++ch) t += racc32s[ch][rr];
+                        racc[0][rr] = (double)t;
+                    }
+                    wave_rows_out<NR, RS, MODE2>(racc, s_rf, sb, i0, n, A);
+                }
+                if constexpr (NC > 0) {
+                    if (((b + 1) * RS) % kLane32Rows == 0 || b + 1 == nsb) {
+#pragma unroll
+                        for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+                            for (int q = 0; q < V; ++q) {
+                                cacc[0][ch][q] += (double)cacc32[ch][q];
+                                cacc32[ch][q] = 0.0f;
+                            }
+                    }
+                }
+            }
+        } else {
+            for (int b = 0; b < nsb; ++b) {
+                const int sb = b * RS;
+                double racc[NRA][RS];
+#pragma unroll
+                for (int k = 0; k < NRA; ++k)
+#pragma unroll
+                    for (int rr = 0; rr < RS; ++rr) racc[k][rr] = 0.0;
+                compute(sb, 0, pts(sb, 0), racc);
+                compute(sb, 1, pts(sb, 1), racc);
+                if constexpr (NR > 0) wave_rows_out<NR, RS, MODE2>(racc, s_rf, sb, i0, n, A);
+            }
         }
     }
     if constexpr (NC > 0) {
@@ -831,6 +910,26 @@ __global__ void k_hvp_cols(const double* part, int tiles, int64_t m, double* Hy)
     const double sj = col_sum_2d(part, tiles, m, j, s_p);
     if (threadIdx.x < kColsPerBlock && j < m) Hy[j] = sj;
 }
+// The Hessian-vector product with the marginals given (eqs. hessian and
+// discounted-hessian): the pass summed P y over rows and P^T x over columns;
+// Hx_i = r(P)_i x_i + sqrt(rho) (P y)_i, Hy_j = sqrt(rho) (P^T x)_j + c(P)_j y_j.
+__global__ void k_hvp_rows_diag(const double* part, int tiles, int64_t n, const double* a,
+                                double srho, const double* log_rP, const double* x, double* Hx)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s0 = 0.0;
+    for (int t = 0; t < tiles; ++t) s0 += part[(int64_t)t * n + i];
+    Hx[i] = fma(exp(log_rP[i]), x[i], srho * (exp(a[i]) * s0));
+}
+__global__ void k_hvp_cols_diag(const double* part, int tiles, int64_t m, double srho,
+                                const double* log_cP, const double* y, double* Hy)
+{
+    __shared__ double s_p[kVecThreads];
+    const int64_t j = (int64_t)blockIdx.x * kColsPerBlock + threadIdx.x % kColsPerBlock;
+    const double sj = col_sum_2d(part, tiles, m, j, s_p);
+    if (threadIdx.x < kColsPerBlock && j < m) Hy[j] = fma(exp(log_cP[j]), y[j], srho * sj);
+}
 __global__ void k_axpy(double alpha, const double* x, double* y, int64_t k) { EW_LOOP(k) y[i] += alpha * x[i]; }
 __global__ void k_log(const double* x, double* y, int64_t k) { EW_LOOP(k) y[i] = log(x[i]); }
 __global__ void k_exp(const double* x, double* y, int64_t k) { EW_LOOP(k) y[i] = exp(x[i]); }
@@ -1173,14 +1272,16 @@ hipError_t launch_pass_v(const PassArgs& a, int prec, hipStream_t s)
 {
     constexpr bool FUSED = MODE2 == R2_HVP || (NR > 0 && NC > 0);
     constexpr int RS = FUSED ? kSubRowsFused : kSubRows;
+    // mixed point-cloud passes: their own sub-band height
+    constexpr int RSM = DP > 0 ? (FUSED ? kPtsSubRowsFused : kPtsSubRows) : RS;
     dim3 grid((unsigned)a.tiles_m, (unsigned)a.tiles_n);
     if (prec == EOT_PREC_MIXED) {
         if constexpr (sizeof(TC) == 4) {
             if constexpr (FUSED)
-                hipLaunchKernelGGL((k_pass_fused<EOT_PREC_MIXED, TC, NR, NC, MODE2, VEC, RS, DP>),
+                hipLaunchKernelGGL((k_pass_fused<EOT_PREC_MIXED, TC, NR, NC, MODE2, VEC, RSM, DP>),
                                    grid, dim3(kPassThreads), 0, s, a);
             else
-                hipLaunchKernelGGL((k_pass<EOT_PREC_MIXED, TC, NR, NC, MODE2, VEC, RS, DP>), grid,
+                hipLaunchKernelGGL((k_pass<EOT_PREC_MIXED, TC, NR, NC, MODE2, VEC, RSM, DP>), grid,
                                    dim3(kPassThreads), 0, s, a);
         } else {
             return hipErrorInvalidValue;
@@ -1672,6 +1773,17 @@ hipError_t launch_hvp_finish(const double* row_part, int tiles_m, const double* 
 {
     hipLaunchKernelGGL(k_hvp_rows, dim3(map_blocks(n)), dim3(kVecThreads), 0, s, row_part, tiles_m, n, a, Hx);
     hipLaunchKernelGGL(k_hvp_cols, dim3(col_blocks(m)), dim3(kVecThreads), 0, s, col_part, tiles_n, m, Hy);
+    return hipGetLastError();
+}
+hipError_t launch_hvp_finish_diag(const double* row_part, int tiles_m, const double* col_part,
+                                  int tiles_n, int64_t n, int64_t m, const double* a, double srho,
+                                  const double* log_rP, const double* log_cP, const double* x,
+                                  const double* y, double* Hx, double* Hy, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_hvp_rows_diag, dim3(map_blocks(n)), dim3(kVecThreads), 0, s, row_part,
+                       tiles_m, n, a, srho, log_rP, x, Hx);
+    hipLaunchKernelGGL(k_hvp_cols_diag, dim3(col_blocks(m)), dim3(kVecThreads), 0, s, col_part,
+                       tiles_n, m, srho, log_cP, y, Hy);
     return hipGetLastError();
 }
 hipError_t launch_axpy(double alpha, const double* x, double* y, int64_t k, hipStream_t s) { EW_LAUNCH(k_axpy, k, alpha, x, y, k); }

@@ -128,6 +128,9 @@ SIGNATURES = {
                          _c_vp, _c_vp, _c_vp, _c_i32, _c_vp, ctypes.c_size_t, _c_vp]),
     "eot_hvp_noalloc": (_c_i32, [ctypes.POINTER(eot_cost), _c_f64, _c_vp, _c_vp, _c_vp, _c_f64,
                                  _c_vp, _c_vp, _c_vp, _c_vp, _c_i32, _c_vp]),
+    "eot_hvp_with_marginals": (_c_i32, [ctypes.POINTER(eot_cost), _c_f64, _c_vp, _c_vp, _c_vp,
+                                        _c_vp, _c_f64, _c_vp, _c_vp, _c_vp, _c_vp, _c_i32, _c_vp,
+                                        ctypes.c_size_t, _c_vp]),
     "eot_newton_cg": (_c_i32, [ctypes.POINTER(eot_cost), _c_f64, _c_vp, _c_vp, _c_vp, _c_vp,
                                _c_f64, _c_f64, _c_i32, _c_i32, _c_vp, _c_vp,
                                ctypes.POINTER(eot_newton_stats), _c_i32, _c_vp,
@@ -327,6 +330,25 @@ def eot_hvp_noalloc(C, gamma, f, g, rho, x, y, row_shift=None, precision="fp64",
                                _vec(y, m, "y"), _vec(Hx, n, "Hx"), _vec(Hy, m, "Hy"), prec,
                                _stream(dev))
     _check(st, "eot_hvp_noalloc")
+    return Hx, Hy
+
+
+def eot_hvp_with_marginals(C, gamma, f, g, log_rP, log_cP, rho, x, y, precision="fp64"):
+    """(Hx, Hy) = discounted Hessian times (x, y) with the diagonal blocks
+    exp(log_rP), exp(log_cP) given (log_rP is also the row shift)."""
+    cost = make_cost(C)
+    n, m = cost.n, cost.m
+    dev = C.device
+    prec = _prec(precision)
+    Hx = torch.empty(n, dtype=torch.float64, device=dev)
+    Hy = torch.empty(m, dtype=torch.float64, device=dev)
+    ws = workspace(EOT_OP_HVP, cost, prec, dev)
+    st = lib().eot_hvp_with_marginals(ctypes.byref(cost), float(gamma), _vec(f, n, "f"),
+                                      _vec(g, m, "g"), _vec(log_rP, n, "log_rP"),
+                                      _vec(log_cP, m, "log_cP"), float(rho), _vec(x, n, "x"),
+                                      _vec(y, m, "y"), _vec(Hx, n, "Hx"), _vec(Hy, m, "Hy"), prec,
+                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev))
+    _check(st, "eot_hvp_with_marginals")
     return Hx, Hy
 
 

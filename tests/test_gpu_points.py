@@ -229,3 +229,12 @@ def test_points_full_size_sampled_hvp():
     tol = mixed_tol(beta, max(Crows.max(), Ccols.max()))
     assert np.all(np.abs(host(Hx)[rows] - hx_ref) <= tol * ax + 1e-300)
     assert np.all(np.abs(host(Hy)[cols] - hy_ref) <= tol * ay + 1e-300)
+    # the same product with the diagonal blocks from the library's mixed marginals
+    say("points full-size 2^20 hvp with marginals, mixed")
+    mg = eot.eot_marginals(pc, gamma, fd, gd, row_shift=shift, precision="mixed",
+                           want=("log_rP", "log_cP"))
+    Hx, Hy = eot.eot_hvp_with_marginals(pc, gamma, fd, gd, mg["log_rP"], mg["log_cP"], rho,
+                                        dvec(x), dvec(y), precision="mixed")
+    torch.cuda.synchronize()
+    assert np.all(np.abs(host(Hx)[rows] - hx_ref) <= tol * ax + 1e-300)
+    assert np.all(np.abs(host(Hy)[cols] - hy_ref) <= tol * ay + 1e-300)
