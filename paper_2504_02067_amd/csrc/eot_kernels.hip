@@ -170,13 +170,12 @@ __device__ __forceinline__ void load_rows(const TC* __restrict__ C, int64_t ldc,
 
 // ---------------------------------------------------------------- the pass
 // Rows whose column sums a lane keeps in FP32 before adding them to its FP64
-// totals (mixed point-cloud passes with plain weights; a multiple of the
-// sub-band height).
+// totals (LANE32 passes; a multiple of the sub-band height).
 constexpr int kLane32Rows = 16;
 
 // PREC = EOT_PREC_MIXED (FP32 exponent / exp, FP64 sums; the point-cloud
-// passes with plain weights sum in FP32 within a lane, see LANE32) or
-// EOT_PREC_FP64.
+// passes with one plain row and one column sum sum in FP32 within a lane, see
+// LANE32) or EOT_PREC_FP64.
 // DP = 0: dense cost streamed from memory. RS rows are in flight per chunk;
 // the next chunk's loads are issued before the current chunk is computed
 // (double buffer), and row partials are reduced per wave in registers, so the
@@ -202,10 +201,13 @@ __device__ __forceinline__ void pass_body(const PassArgs& A)
     __shared__ double s_wmax[kWaves];
     __shared__ float s_x[DP > 0 ? RB * DP : 1];   // point rows
     __shared__ __attribute__((aligned(16))) double s_exp[MIXED ? 2 : kExpTabDoubles];  // FP64: exp_tab256
-    // Mixed point-cloud passes with plain weighted sums (one row and / or one
-    // column sum, weight e_ij): the sums run in FP32 within a lane and in FP64
-    // from there on (lanes, waves, tiles), as in the high-dimensional pass.
-    constexpr bool LANE32 = MIXED && DP > 0 && MODE2 != R2_HVP && NR <= 1 && NC <= 1;
+    // Mixed point-cloud passes with one plain weighted row sum and one column
+    // sum (the HVP with the marginals given, the marginal pass): the sums run
+    // in FP32 within a lane and in FP64 from there on (lanes, waves, tiles), as
+    // in the high-dimensional pass. The CG's single-sum passes keep FP64 sums:
+    // FP32 ones there slow the tight CG solves of the gradient (61 -> 150
+    // iterations at n = 4096, temperature 1e-3) for no gain in the column pass.
+    constexpr bool LANE32 = MIXED && DP > 0 && MODE2 != R2_HVP && NR == 1 && NC == 1;
     __shared__ float s_xwf[LANE32 ? RB : 1];      // FP32 copy of the column-sum weights
 
     const int tid = threadIdx.x;
