@@ -456,13 +456,15 @@ eot_status eot_set_rows_per_tile(int32_t rows);
  * For tuning and tests; size workspaces after changing it. */
 eot_status eot_set_team_size(int32_t k, int64_t entries_per_wg);
 
-/* The single-launch CG of small problems (n, m <= 1024; dense costs and d = 2
- * points; d = 3 points use the launches per iteration): each CG solve of NewtonSolve (Alg. 2) runs as one cooperative
- * kernel launch with two grid barriers per iteration, instead of four launches
- * per iteration. enable: 1 (the default) or 0 for the launches per iteration;
- * grid: workgroups of that launch (0 ... 128; raised to max(n, m) / 8 when
- * smaller, 0 = that minimum). Applies to every later call in this process;
- * the batched solvers do not use it. For tuning and tests. */
+/* The single-launch CG of small problems (n, m <= 1024 and
+ * min(n, m) >= max(n, m) / 8; dense costs and d = 2 points; d = 3 points use
+ * the launches per iteration): each CG solve of NewtonSolve (Alg. 2) runs as
+ * one cooperative kernel launch whose workgroups exchange parity-tagged
+ * values, instead of four launches per iteration. enable: 1 (the default) or
+ * 0 for the launches per iteration; grid: workgroups of that launch (0 ...
+ * 128; raised to max(n, m) / 8 when smaller and lowered to min(n, m) when
+ * larger, 0 = the minimum). Applies to every later call in this process; the
+ * batched solvers do not use it. For tuning and tests. */
 eot_status eot_set_cg_persist(int32_t enable, int32_t grid);
 
 /* Opt-in timing of the streaming passes (for benchmarks and profiling). While

@@ -109,11 +109,13 @@ std::atomic<int> g_cgp_grid{0};
 
 // Workgroups of the single-launch CG for an n x m problem before the
 // co-resident cap: the fixed grid or the smallest one with at most 8 rows and
-// 8 columns per workgroup (the kernel's bound), at most kCgpMaxGrid.
+// 8 columns per workgroup (the kernel's bound), at most kCgpMaxGrid and at
+// most min(n, m) (every workgroup owns a row and a column).
 int cgp_grid_for(int64_t n, int64_t m)
 {
     const int lo = (int)((std::max(n, m) + 7) / 8);
-    return std::min(std::max(g_cgp_grid.load(), lo), kCgpMaxGrid);
+    const int hi = (int)std::min<int64_t>(std::min(n, m), kCgpMaxGrid);
+    return std::min(std::max(g_cgp_grid.load(), lo), hi);
 }
 
 // Cost kind of the single-launch CG (0 dense FP32, 1 dense FP64, 2 points in
@@ -537,8 +539,9 @@ struct NewtonResult {
 };
 
 // Grid of the single-launch CG for this problem (cgp_grid_for, at most the
-// co-resident capacity and the workgroups the workspace holds), or 0 to use
-// the launches per iteration.
+// co-resident capacity), or 0 to use the launches per iteration (also when no
+// grid has both at most 8 rows and columns per workgroup and at least one of
+// each: min(n, m) < max(n, m) / 8).
 eot_status cgp_pick_grid(Ctx& x, int prec, int* grid)
 {
     *grid = 0;

@@ -1374,7 +1374,9 @@ __device__ __forceinline__ void wg_sum2(double& x, double& y, double* s_red2)
 // before every reader has taken iteration k's: a workgroup publishes k + 1
 // only after it has read every workgroup's iteration-k values of the other
 // buffer, which each of them published only after reading iteration k's values
-// of this one. No barrier is needed. The tag bit stays in the value,
+// of this one. That needs every workgroup to publish into both buffers, i.e. to
+// own at least one column and one row (the host's grid is at most min(n, m)).
+// No barrier is needed. The tag bit stays in the value,
 // identically in every workgroup (a change of at most one unit in the last
 // place).
 __device__ __forceinline__ unsigned long long cgp_tagged(double v, uint32_t k)
@@ -1477,10 +1479,12 @@ __global__ __launch_bounds__(TT) void k_cg_persist(CgpArgs A)
         for (int64_t e = tid; e < n * KIND; e += TT) s_x[e] = A.P.X[e];
         for (int64_t e = tid; e < m * KIND; e += TT) s_y[e] = A.P.Y[e];
     }
-    // blocks of at most 8 columns / rows (the host keeps G >= max(n, m) / 8)
+    // even blocks of at most 8 columns / rows: the host keeps
+    // max(n, m) / 8 <= G <= min(n, m), so every workgroup owns at least one
+    // column and one row (the exchange below relies on it)
     const int64_t cb = (m + G - 1) / G, rb = (n + G - 1) / G;
-    const int64_t j0 = g * cb < m ? g * cb : m, j1 = j0 + cb < m ? j0 + cb : m;
-    const int64_t i0 = g * rb < n ? g * rb : n, i1 = i0 + rb < n ? i0 + rb : n;
+    const int64_t j0 = (int64_t)g * m / G, j1 = (int64_t)(g + 1) * m / G;
+    const int64_t i0 = (int64_t)g * n / G, i1 = (int64_t)(g + 1) * n / G;
     int CBp = 1, RBp = 1;
     while (CBp < cb) CBp *= 2;
     while (RBp < rb) RBp *= 2;

@@ -1,5 +1,6 @@
 """The single-launch CG of small problems (launch_cg_persist: one cooperative
-kernel per CG solve of NewtonSolve, Alg. 2, two grid barriers per iteration)
+kernel per CG solve of NewtonSolve, Alg. 2, parity-tagged exchange between
+its workgroups)
 against the launches-per-iteration path it replaces (eot_set_cg_persist(0)),
 which the other GPU tests pin to the oracle: the same NewtonSolve directions
 (the summation orders differ, so to rounding), the same CG iteration counts,
@@ -97,7 +98,10 @@ def test_newton_direction_dense_grid28(kind, prec):
 
 
 @pytest.mark.parametrize("d", [2, 3])
-@pytest.mark.parametrize("nm", [(300, 517), (1024, 1024), (1025, 700)])
+# (130, 1000): 125 workgroups over 130 rows, one or two each; (100, 900): no
+# grid has both at most 8 columns and at least one row per workgroup, so both
+# modes take the launches per iteration
+@pytest.mark.parametrize("nm", [(300, 517), (1024, 1024), (1025, 700), (130, 1000), (100, 900)])
 def test_newton_direction_points(d, nm):
     n, m = nm
     rng = np.random.default_rng(d * 1000 + n)
