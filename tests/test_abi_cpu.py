@@ -28,7 +28,8 @@ def L():
 
 def test_header_declares_the_boundary():
     names = _declared()
-    for n in ("eot_marginals", "eot_hvp", "eot_newton_cg", "eot_solve", "eot_workspace_size",
+    for n in ("eot_marginals", "eot_hvp", "eot_hvp_with_marginals", "eot_newton_cg", "eot_solve",
+              "eot_workspace_size",
               "eot_status_string", "eot_version", "eot_solve_opts_default"):
         assert n in names
 
@@ -94,9 +95,25 @@ def test_argument_validation_happens_before_any_device_work(L):
     # rho outside [0, 1]
     assert L.eot_hvp(ctypes.byref(c), 1.0, p, p, None, 1.5, p, p, p, p, 0, p, 1 << 20,
                      None) == eot.EOT_ERR_INVALID_ARG
+    # the HVP with the marginals given: both marginals required, rho in [0, 1], gamma > 0
+    hm = L.eot_hvp_with_marginals
+    assert hm(ctypes.byref(c), 1.0, p, p, None, p, 1.0, p, p, p, p, 0, p, 1 << 20,
+              None) == eot.EOT_ERR_INVALID_ARG
+    assert hm(ctypes.byref(c), 1.0, p, p, p, None, 1.0, p, p, p, p, 0, p, 1 << 20,
+              None) == eot.EOT_ERR_INVALID_ARG
+    assert hm(ctypes.byref(c), 1.0, p, p, p, p, -0.5, p, p, p, p, 0, p, 1 << 20,
+              None) == eot.EOT_ERR_INVALID_ARG
+    assert hm(ctypes.byref(c), 0.0, p, p, p, p, 1.0, p, p, p, p, 0, p, 1 << 20,
+              None) == eot.EOT_ERR_INVALID_ARG
+    assert hm(ctypes.byref(c), 1.0, p, p, p, p, 1.0, p, p, None, p, 0, p, 1 << 20,
+              None) == eot.EOT_ERR_INVALID_ARG
+    assert hm(ctypes.byref(c), 1.0, p, p, p, p, 1.0, p, p, p, p, 0, p, 16,
+              None) == eot.EOT_ERR_WORKSPACE
     # mixed precision on an FP64 dense cost is not supported
     c64 = eot.eot_cost(kind=1, d=0, n=8, m=8, ldc=8, C=ctypes.c_void_p(4096), X=None, Y=None,
                        scale=0.0)
+    assert hm(ctypes.byref(c64), 1.0, p, p, p, p, 1.0, p, p, p, p, 1, p, 1 << 20,
+              None) == eot.EOT_ERR_UNSUPPORTED
     assert L.eot_marginals(ctypes.byref(c64), 1.0, p, p, None, p, None, None, None, None, 1,
                            p, 1 << 20, None) == eot.EOT_ERR_UNSUPPORTED
     # workspace too small / misaligned
