@@ -351,6 +351,23 @@ def highd_measure(args, eot, W, dev, iters=5):
         sec = ms / 1e3 / k
         res[f"{prec}_ms"] = sec * 1e3
         res[f"{prec}_entries_per_s"] = float(n) * m / sec
+    # the HVP with the marginals given (one weighted sum per direction), mixed
+    mg = eot.eot_marginals(pc, gamma, f, g, row_shift=shift, precision="mixed",
+                           want=("log_rP", "log_cP"))
+    fn = lambda: eot.eot_hvp_with_marginals(pc, gamma, f, g, mg["log_rP"], mg["log_cP"], 1.0, x,
+                                            y, precision="mixed")
+    fn()
+    torch.cuda.synchronize()
+    eot.eot_pass_timing(True)
+    for _ in range(iters):
+        fn()
+    torch.cuda.synchronize()
+    k, ms = eot.eot_pass_timing_read(precision="mixed", nr=1, nc=1, fused_hvp=0)
+    eot.eot_pass_timing(False)
+    sec = ms / 1e3 / k
+    res["with_marginals_mixed_ms"] = sec * 1e3
+    res["with_marginals_mfma_frac"] = 3 * 2 * d * float(n) * m / sec / 2.5e15
+    res["with_marginals_mfma_method_frac"] = 2 * d * float(n) * m / sec / 2.5e15
     # the CG's single-sum passes (column sums, then row sums), mixed
     for name, want, filt in (("colpass", ("log_cP",), dict(nr=0, nc=1)),
                              ("rowpass", ("log_rP",), dict(nr=1, nc=0))):
@@ -391,6 +408,8 @@ def highd_measure(args, eot, W, dev, iters=5):
         f"(FP64 MFMA {mfma64 / 1e12:.1f} TFLOP/s = {100 * mfma64 / 78.6e12:.0f}% of FP64 peak)")
     log(f"high-d mixed log-marginal error vs FP64 at gamma {gamma:g}: "
         f"{res['mixed_log_marginal_err_vs_fp64']:.1e}")
+    log(f"high-d HVP with marginals mixed {res['with_marginals_mixed_ms']:.2f} ms "
+        f"({100 * res['with_marginals_mfma_frac']:.1f}% of BF16 peak)")
     log(f"high-d CG passes mixed: column {res['colpass_mixed_ms']:.2f} ms "
         f"({100 * res['colpass_mfma_frac']:.1f}% of BF16 peak), row {res['rowpass_mixed_ms']:.2f} ms "
         f"({100 * res['rowpass_mfma_frac']:.1f}%)")
@@ -549,6 +568,28 @@ def batch_measure(args, eot, W, dev, host_path=True):
                     "entry_passes": ent, "entries_per_s": ent / dt}
         log(f"  {dt:.2f} s, failed {res[key]['failed']}, max err {max(errs):.2e}, "
             f"{ent / dt / 1e12:.2f} T plan entries/s")
+        if key == "fp64":
+            sol64 = outs
+    # the backward over the whole batch (eot_gradient_batched) at the FP64
+    # solutions: d(W + S) for X, Y, r, c of every problem
+    gprobs = [(pc, 1e-3, f, g) for (pc, _, _), (f, g) in zip(items, sol64)]
+    res["backward"] = {"workload": f"eot_gradient_batched over the {len(items)} FP64 solutions, "
+                                   f"w_W = w_S = 1, outputs X, Y, r, c",
+                       "workers": args.batch_workers}
+    for prec, tol in (("fp64", 1e-11), ("mixed", 1e-5)):
+        eot.eot_gradient_batched(gprobs[:8], w_W=1.0, w_S=1.0, tol=tol, precision=prec,
+                                 workers=args.batch_workers, check=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gout = eot.eot_gradient_batched(gprobs, w_W=1.0, w_S=1.0, tol=tol, precision=prec,
+                                        workers=args.batch_workers, check=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res["backward"][prec] = {"seconds": dt, "problems_per_s": len(gprobs) / dt, "cg_tol": tol,
+                                 "failed": int(sum(1 for o in gout if o["status"] != 0)),
+                                 "cg_iters": int(sum(o["cg_iters"] for o in gout))}
+        log(f"batch backward {prec}: {dt:.2f} s, {res['backward'][prec]['cg_iters']} CG iterations, "
+            f"failed {res['backward'][prec]['failed']}")
     res["speedup_mixed_vs_fp64"] = res["fp64"]["seconds"] / res["mixed"]["seconds"]
     if host_path:
         res["speedup_persistent_vs_host_workers"] = (res["mixed_host_workers"]["seconds"]

@@ -441,6 +441,41 @@ eot_status eot_gradient(const eot_cost* cost, double gamma, const double* f, con
                         double* grad_Y, double* grad_r, double* grad_c, eot_grad_info* info,
                         int32_t prec, void* ws, size_t ws_bytes, void* stream);
 
+/* eot_gradient over a batch of independent problems (the backward of a batch
+ * of solves), with one pair of weights (w_W, w_S) and one precision. Each
+ * problem's outputs, formulas, validation and info (tol, max_cg in; cg_iters,
+ * cg_residual, S out) are those of eot_gradient on it. A native scheduler runs
+ * `workers` host threads, each with its own non-blocking HIP stream (default
+ * priority) and its own workspace slice, largest n m first; per problem the
+ * arithmetic is that of eot_gradient with the single-launch CG switched off
+ * (eot_set_cg_persist(0)), so results are bitwise equal to such calls on dense
+ * costs and equal to rounding on point clouds (their gradient atomics).
+ * probs, info: host arrays of nprob entries (device pointers inside); status:
+ * host array of nprob entries (nullable). Work on the caller's stream that
+ * precedes the call is waited for; the call returns when every problem is
+ * done, with the caller's stream ordered after them. Returns EOT_OK, the first
+ * argument error before any device work, or the status of the lowest-numbered
+ * problem that failed (the others are still computed). ws:
+ * eot_workspace_size_gradient_batched bytes, 256-byte aligned. */
+typedef struct {
+    eot_cost cost;
+    double gamma;        /* temperature of the problem's potentials            */
+    const double* f;     /* device, n, in (cost units)                          */
+    const double* g;     /* device, m, in                                       */
+    double* grad_C;      /* device, dense costs only, n x ldg (nullable)        */
+    int64_t ldg;
+    double* grad_X;      /* device, point clouds only, n x d (nullable)         */
+    double* grad_Y;      /* device, point clouds only, m x d (nullable)         */
+    double* grad_r;      /* device, n (nullable)                                */
+    double* grad_c;      /* device, m (nullable)                                */
+} eot_grad_problem;
+
+eot_status eot_workspace_size_gradient_batched(int32_t nprob, const eot_grad_problem* probs,
+                                               int32_t workers, size_t* bytes);
+eot_status eot_gradient_batched(int32_t nprob, const eot_grad_problem* probs, double w_W,
+                                double w_S, eot_grad_info* info, int32_t prec, int32_t workers,
+                                int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
 /* Rows per tile of the streaming passes (a power of two in [8, 256]) used by
  * every later call in this process, or 0 to restore the default choice (the
  * measured table compiled into the library, else the smallest halving of 256

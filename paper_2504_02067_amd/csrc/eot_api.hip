@@ -1697,6 +1697,79 @@ eot_status team_batch(int32_t nprob, const eot_batch_problem* probs,
     return EOT_OK;
 }
 
+// Host workers: `nw` threads, each with its own non-blocking stream (default
+// priority) and workspace slice wbase + w * slice, take the problems of
+// `order` (already sorted) one at a time and run job(i, base, slice, stream);
+// st_all[i] receives its status. The caller's stream is ordered before and
+// after all of them. Returns EOT_ERR_HIP when the streams could not be set up
+// (the problems no worker reached keep the status they had).
+template <class Job>
+eot_status run_host_workers(const std::vector<int32_t>& order, int nw, char* wbase, size_t slice,
+                            hipStream_t caller, std::vector<eot_status>& st_all, Job job)
+{
+    const int32_t n_work = (int32_t)order.size();
+    if (n_work == 0) return EOT_OK;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    hipEvent_t start;
+    HIPCHK(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(start, caller));
+    std::vector<hipStream_t> streams((size_t)nw, nullptr);
+    std::vector<hipEvent_t> done((size_t)nw, nullptr);
+    eot_status setup_err = EOT_OK;
+    for (int w = 0; w < nw && setup_err == EOT_OK; ++w) {
+        if (hipStreamCreateWithFlags(&streams[w], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&done[w], hipEventDisableTiming) != hipSuccess ||
+            hipStreamWaitEvent(streams[w], start, 0) != hipSuccess)
+            setup_err = EOT_ERR_HIP;
+    }
+    std::atomic<int32_t> next{0};
+    auto work = [&](int w) {
+        if (hipSetDevice(dev) != hipSuccess) return;
+        char* base = wbase + (size_t)w * slice;
+        for (;;) {
+            const int32_t k = next.fetch_add(1);
+            if (k >= n_work) break;
+            const int32_t i = order[(size_t)k];
+            st_all[(size_t)i] = job(i, base, slice, streams[w]);
+        }
+    };
+    if (setup_err == EOT_OK) {
+        std::vector<std::thread> pool;
+        for (int w = 1; w < nw; ++w) pool.emplace_back(work, w);
+        work(0);
+        for (auto& t : pool) t.join();
+    }
+    for (int w = 0; w < nw; ++w) {
+        if (streams[w]) {
+            if (done[w] && hipEventRecord(done[w], streams[w]) == hipSuccess)
+                (void)hipStreamWaitEvent(caller, done[w], 0);
+        }
+    }
+    for (int w = 0; w < nw; ++w) {
+        if (streams[w]) (void)hipStreamSynchronize(streams[w]);
+        if (done[w]) (void)hipEventDestroy(done[w]);
+        if (streams[w]) (void)hipStreamDestroy(streams[w]);
+    }
+    (void)hipEventDestroy(start);
+    return setup_err;
+}
+
+// Arguments of one gradient (eot_gradient, each problem of eot_gradient_batched).
+eot_status grad_check(const eot_cost* cost, double gamma, const double* f, const double* g,
+                      double w_W, double w_S, const eot_grad_info* info, const double* grad_C,
+                      int64_t ldg, const double* grad_X, const double* grad_Y)
+{
+    if (!f || !g || !info || bad_gamma(gamma)) return EOT_ERR_INVALID_ARG;
+    if (!std::isfinite(w_W) || !std::isfinite(w_S)) return EOT_ERR_INVALID_ARG;
+    if (w_S != 0.0 && (!(info->tol > 0.0) || info->max_cg < 1)) return EOT_ERR_INVALID_ARG;
+    EOTCHK(check_cost(cost));
+    const bool pts = cost->kind == EOT_COST_SQEUCLID_POINTS;
+    if (grad_C && (pts || ldg < cost->m)) return EOT_ERR_INVALID_ARG;
+    if ((grad_X || grad_Y) && !pts) return EOT_ERR_INVALID_ARG;
+    return EOT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1990,70 +2063,22 @@ eot_status eot_solve_batched(int32_t nprob, const eot_batch_problem* probs,
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
         return probs[a].cost.n * probs[a].cost.m > probs[b].cost.n * probs[b].cost.m;
     });
-    const int32_t n_work = (int32_t)order.size();
-    int dev = 0;
-    HIPCHK(hipGetDevice(&dev));
-    if (n_work == 0) {
-        for (int32_t i = 0; i < nprob; ++i) {
-            if (status) status[i] = st_all[(size_t)i];
-            if (stats) stats[i] = stats_all[(size_t)i];
-        }
-        for (int32_t i = 0; i < nprob; ++i)
-            if (st_all[(size_t)i] != EOT_OK) return st_all[(size_t)i];
-        return EOT_OK;
-    }
-    hipEvent_t start;
-    HIPCHK(hipEventCreateWithFlags(&start, hipEventDisableTiming));
-    HIPCHK(hipEventRecord(start, caller));
-    std::vector<hipStream_t> streams((size_t)nw, nullptr);
-    std::vector<hipEvent_t> done((size_t)nw, nullptr);
-    eot_status setup_err = EOT_OK;
-    for (int w = 0; w < nw && setup_err == EOT_OK; ++w) {
-        if (hipStreamCreateWithFlags(&streams[w], hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&done[w], hipEventDisableTiming) != hipSuccess ||
-            hipStreamWaitEvent(streams[w], start, 0) != hipSuccess)
-            setup_err = EOT_ERR_HIP;
-    }
-    std::atomic<int32_t> next{0};
-    auto work = [&](int w) {
-        if (hipSetDevice(dev) != hipSuccess) return;
-        char* base = wbase + (size_t)w * slice;
-        for (;;) {
-            const int32_t k = next.fetch_add(1);
-            if (k >= n_work) break;
-            const int32_t i = order[(size_t)k];
+    const eot_status first = run_host_workers(
+        order, nw, wbase, slice, caller, st_all,
+        [&](int32_t i, char* base, size_t bytes, hipStream_t st) {
             const eot_batch_problem& p = probs[i];
             // no single-launch CG here: cooperative launches from 8 threads at once
-            st_all[(size_t)i] = solve_one(&p.cost, p.r, p.c, opts, p.f, p.g, &stats_all[(size_t)i],
-                                          base, slice, streams[w], nullptr, nullptr, nullptr,
-                                          false);
-        }
-    };
-    if (setup_err == EOT_OK) {
-        std::vector<std::thread> pool;
-        for (int w = 1; w < nw; ++w) pool.emplace_back(work, w);
-        work(0);
-        for (auto& t : pool) t.join();
-    }
-    eot_status first = setup_err;
-    for (int w = 0; w < nw; ++w) {
-        if (streams[w]) {
-            if (done[w] && hipEventRecord(done[w], streams[w]) == hipSuccess)
-                (void)hipStreamWaitEvent(caller, done[w], 0);
-        }
-    }
-    for (int w = 0; w < nw; ++w) {
-        if (streams[w]) (void)hipStreamSynchronize(streams[w]);
-        if (done[w]) (void)hipEventDestroy(done[w]);
-        if (streams[w]) (void)hipStreamDestroy(streams[w]);
-    }
-    (void)hipEventDestroy(start);
+            return solve_one(&p.cost, p.r, p.c, opts, p.f, p.g, &stats_all[(size_t)i], base, bytes,
+                             st, nullptr, nullptr, nullptr, false);
+        });
     for (int32_t i = 0; i < nprob; ++i) {
         if (status) status[i] = st_all[(size_t)i];
         if (stats) stats[i] = stats_all[(size_t)i];
-        if (first == EOT_OK && st_all[(size_t)i] != EOT_OK) first = st_all[(size_t)i];
     }
-    return first;
+    if (first != EOT_OK) return first;
+    for (int32_t i = 0; i < nprob; ++i)
+        if (st_all[(size_t)i] != EOT_OK) return st_all[(size_t)i];
+    return EOT_OK;
 }
 
 eot_status eot_gradient(const eot_cost* cost, double gamma, const double* f, const double* g,
@@ -2061,17 +2086,65 @@ eot_status eot_gradient(const eot_cost* cost, double gamma, const double* f, con
                         double* grad_Y, double* grad_r, double* grad_c, eot_grad_info* info,
                         int32_t prec, void* ws, size_t ws_bytes, void* stream)
 {
-    if (!f || !g || !info || bad_gamma(gamma)) return EOT_ERR_INVALID_ARG;
-    if (!std::isfinite(w_W) || !std::isfinite(w_S)) return EOT_ERR_INVALID_ARG;
-    if (w_S != 0.0 && (!(info->tol > 0.0) || info->max_cg < 1)) return EOT_ERR_INVALID_ARG;
-    EOTCHK(check_cost(cost));
-    const bool pts = cost->kind == EOT_COST_SQEUCLID_POINTS;
-    if (grad_C && (pts || ldg < cost->m)) return EOT_ERR_INVALID_ARG;
-    if ((grad_X || grad_Y) && !pts) return EOT_ERR_INVALID_ARG;
+    EOTCHK(grad_check(cost, gamma, f, g, w_W, w_S, info, grad_C, ldg, grad_X, grad_Y));
     Ctx x;
     EOTCHK(setup(x, cost, EOT_OP_GRADIENT, prec, ws, ws_bytes, stream));
     return gradient_impl(x, gamma, f, g, w_W, w_S, grad_C, ldg, grad_X, grad_Y, grad_r, grad_c,
                          info, prec);
+}
+
+eot_status eot_workspace_size_gradient_batched(int32_t nprob, const eot_grad_problem* probs,
+                                               int32_t workers, size_t* bytes)
+{
+    if (!bytes || nprob < 1 || !probs || workers < 1) return EOT_ERR_INVALID_ARG;
+    size_t slice = 0;
+    for (int32_t k = 0; k < nprob; ++k) {
+        size_t b = 0;
+        EOTCHK(eot_workspace_size(EOT_OP_GRADIENT, &probs[k].cost, 0, &b));
+        slice = std::max(slice, align_up(b));
+    }
+    *bytes = slice * (size_t)std::min(workers, nprob) + kAlign;
+    return EOT_OK;
+}
+
+eot_status eot_gradient_batched(int32_t nprob, const eot_grad_problem* probs, double w_W,
+                                double w_S, eot_grad_info* info, int32_t prec, int32_t workers,
+                                int32_t* status, void* ws, size_t ws_bytes, void* stream)
+{
+    if (nprob < 1 || !probs || !info || workers < 1) return EOT_ERR_INVALID_ARG;
+    for (int32_t k = 0; k < nprob; ++k) {
+        const eot_grad_problem& p = probs[k];
+        EOTCHK(grad_check(&p.cost, p.gamma, p.f, p.g, w_W, w_S, &info[k], p.grad_C, p.ldg,
+                          p.grad_X, p.grad_Y));
+    }
+    size_t need = 0;
+    EOTCHK(eot_workspace_size_gradient_batched(nprob, probs, workers, &need));
+    if (!ws || ws_bytes < need - kAlign || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0)
+        return EOT_ERR_WORKSPACE;
+    std::vector<eot_status> st_all((size_t)nprob, EOT_ERR_HIP);
+    std::vector<int32_t> order((size_t)nprob);
+    for (int32_t k = 0; k < nprob; ++k) order[(size_t)k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return probs[a].cost.n * probs[a].cost.m > probs[b].cost.n * probs[b].cost.m;
+    });
+    const int nw = std::min<int>(workers, nprob);
+    const size_t slice = (need - kAlign) / (size_t)nw;
+    const eot_status first = run_host_workers(
+        order, nw, static_cast<char*>(ws), slice, static_cast<hipStream_t>(stream), st_all,
+        [&](int32_t i, char* base, size_t bytes, hipStream_t st) -> eot_status {
+            const eot_grad_problem& p = probs[i];
+            Ctx x;
+            x.cgp_ok = false;                    // no cooperative launches from several threads
+            EOTCHK(setup(x, &p.cost, EOT_OP_GRADIENT, prec, base, bytes, st));
+            return gradient_impl(x, p.gamma, p.f, p.g, w_W, w_S, p.grad_C, p.ldg, p.grad_X,
+                                 p.grad_Y, p.grad_r, p.grad_c, &info[i], prec);
+        });
+    if (status)
+        for (int32_t i = 0; i < nprob; ++i) status[i] = st_all[(size_t)i];
+    if (first != EOT_OK) return first;
+    for (int32_t i = 0; i < nprob; ++i)
+        if (st_all[(size_t)i] != EOT_OK) return st_all[(size_t)i];
+    return EOT_OK;
 }
 
 eot_status eot_round(const eot_cost* cost, double gamma, const double* f, const double* g,

@@ -118,6 +118,12 @@ class eot_grad_info(ctypes.Structure):
                 ("cg_residual", _c_f64), ("S", _c_f64)]
 
 
+class eot_grad_problem(ctypes.Structure):
+    _fields_ = [("cost", eot_cost), ("gamma", _c_f64), ("f", _c_vp), ("g", _c_vp),
+                ("grad_C", _c_vp), ("ldg", _c_i64), ("grad_X", _c_vp), ("grad_Y", _c_vp),
+                ("grad_r", _c_vp), ("grad_c", _c_vp)]
+
+
 SIGNATURES = {
     "eot_workspace_size": (_c_i32, [_c_i32, ctypes.POINTER(eot_cost), _c_i32,
                                     ctypes.POINTER(ctypes.c_size_t)]),
@@ -157,6 +163,11 @@ SIGNATURES = {
                               _c_vp, _c_i64, _c_vp, _c_vp, _c_vp, _c_vp,
                               ctypes.POINTER(eot_grad_info), _c_i32, _c_vp, ctypes.c_size_t,
                               _c_vp]),
+    "eot_workspace_size_gradient_batched": (_c_i32, [_c_i32, ctypes.POINTER(eot_grad_problem),
+                                                     _c_i32, ctypes.POINTER(ctypes.c_size_t)]),
+    "eot_gradient_batched": (_c_i32, [_c_i32, ctypes.POINTER(eot_grad_problem), _c_f64, _c_f64,
+                                      ctypes.POINTER(eot_grad_info), _c_i32, _c_i32,
+                                      ctypes.POINTER(_c_i32), _c_vp, ctypes.c_size_t, _c_vp]),
     "eot_set_rows_per_tile": (_c_i32, [_c_i32]),
     "eot_set_team_size": (_c_i32, [_c_i32, _c_i64]),
     "eot_set_cg_persist": (_c_i32, [_c_i32, _c_i32]),
@@ -584,6 +595,65 @@ def eot_gradient(C, gamma, f, g, w_W=1.0, w_S=0.0, want=None, tol=1e-11, max_cg=
     _check(st, "eot_gradient", allow)
     out.update(S=info.S, cg_iters=info.cg_iters, cg_residual=info.cg_residual, status=st)
     return out
+
+
+def eot_gradient_batched(problems, w_W=1.0, w_S=0.0, want=None, tol=1e-11, max_cg=5000,
+                         precision="fp64", workers=8, check=True):
+    """eot_gradient over many problems at once. ``problems``: sequence of
+    (C, gamma, f, g) with C a dense GPU tensor or a PointCloud. Returns a list of
+    per-problem dicts as eot_gradient's (tensors named by ``want``, plus "S",
+    "cg_iters", "cg_residual" and "status"); with check=False a failed problem
+    does not raise."""
+    k = len(problems)
+    arr = (eot_grad_problem * k)()
+    info = (eot_grad_info * k)()
+    outs, keep = [], []
+    dev = None
+
+    def ptr(t):
+        return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+    for i, (C, gamma, f, g) in enumerate(problems):
+        cost = make_cost(C)
+        n, m, d = cost.n, cost.m, cost.d
+        dev = C.device
+        pts = cost.kind == EOT_COST_SQEUCLID_POINTS
+        w = want if want is not None else (("X", "Y", "r", "c") if pts else ("C", "r", "c"))
+        o = {"C": torch.empty((n, m), dtype=torch.float64, device=dev) if "C" in w else None,
+             "X": torch.empty((n, d), dtype=torch.float64, device=dev) if "X" in w else None,
+             "Y": torch.empty((m, d), dtype=torch.float64, device=dev) if "Y" in w else None,
+             "r": torch.empty(n, dtype=torch.float64, device=dev) if "r" in w else None,
+             "c": torch.empty(m, dtype=torch.float64, device=dev) if "c" in w else None}
+        arr[i].cost = cost
+        arr[i].gamma = float(gamma)
+        arr[i].f = _vec(f, n, "f")
+        arr[i].g = _vec(g, m, "g")
+        arr[i].grad_C = ptr(o["C"])
+        arr[i].ldg = m
+        arr[i].grad_X = ptr(o["X"])
+        arr[i].grad_Y = ptr(o["Y"])
+        arr[i].grad_r = ptr(o["r"])
+        arr[i].grad_c = ptr(o["c"])
+        info[i].tol = float(tol)
+        info[i].max_cg = int(max_cg)
+        outs.append(o)
+        keep.append((C, f, g))
+    nbytes = ctypes.c_size_t(0)
+    _check(lib().eot_workspace_size_gradient_batched(k, arr, int(workers), ctypes.byref(nbytes)),
+           "eot_workspace_size_gradient_batched")
+    buf = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=dev)
+    off = (-buf.data_ptr()) % 256
+    ws = buf[off:off + int(nbytes.value)]
+    status = (_c_i32 * k)()
+    st = lib().eot_gradient_batched(k, arr, float(w_W), float(w_S), info, _prec(precision),
+                                    int(workers), status, ctypes.c_void_p(ws.data_ptr()),
+                                    ws.numel(), _stream(dev))
+    if check:
+        _check(st, "eot_gradient_batched")
+    for i, o in enumerate(outs):
+        o.update(S=info[i].S, cg_iters=info[i].cg_iters, cg_residual=info[i].cg_residual,
+                 status=int(status[i]))
+    return outs
 
 
 def eot_set_rows_per_tile(rows: int) -> None:

@@ -228,6 +228,48 @@ def test_batched_validation(L):
     assert L.eot_workspace_size_batched(2, probs, 4, ctypes.byref(sz)) == eot.EOT_ERR_INVALID_ARG
 
 
+def test_gradient_batched_validation(L):
+    """eot_gradient_batched checks every problem's arguments (those of
+    eot_gradient) and the workspace before any device work."""
+    from paper_2504_02067_amd import eot
+    p = ctypes.c_void_p(4096)
+    c = eot.eot_cost(kind=0, d=0, n=8, m=8, ldc=8, C=p, X=None, Y=None, scale=0.0)
+    probs = (eot.eot_grad_problem * 2)()
+    for k in range(2):
+        probs[k].cost = c
+        probs[k].gamma = 0.1
+        probs[k].f = p
+        probs[k].g = p
+        probs[k].ldg = 8
+    info = (eot.eot_grad_info * 2)()
+    for k in range(2):
+        info[k].tol = 1e-10
+        info[k].max_cg = 100
+    nbytes = ctypes.c_size_t(0)
+    assert L.eot_workspace_size_gradient_batched(2, probs, 4, ctypes.byref(nbytes)) == eot.EOT_OK
+    one = ctypes.c_size_t(0)
+    assert L.eot_workspace_size(eot.EOT_OP_GRADIENT, ctypes.byref(c), 0, ctypes.byref(one)) == 0
+    assert nbytes.value >= 2 * one.value
+    gb = L.eot_gradient_batched
+    assert gb(0, probs, 1.0, 1.0, info, 0, 4, None, p, 1 << 30, None) == eot.EOT_ERR_INVALID_ARG
+    assert gb(2, probs, 1.0, 1.0, None, 0, 4, None, p, 1 << 30, None) == eot.EOT_ERR_INVALID_ARG
+    assert gb(2, probs, 1.0, 1.0, info, 0, 0, None, p, 1 << 30, None) == eot.EOT_ERR_INVALID_ARG
+    assert gb(2, probs, float("nan"), 1.0, info, 0, 4, None, p, 1 << 30,
+              None) == eot.EOT_ERR_INVALID_ARG
+    probs[1].gamma = 0.0                      # one bad problem fails the call up front
+    assert gb(2, probs, 1.0, 1.0, info, 0, 4, None, p, 1 << 30, None) == eot.EOT_ERR_INVALID_ARG
+    probs[1].gamma = 0.1
+    probs[1].grad_X = p                       # point gradients of a dense cost
+    assert gb(2, probs, 1.0, 1.0, info, 0, 4, None, p, 1 << 30, None) == eot.EOT_ERR_INVALID_ARG
+    probs[1].grad_X = None
+    info[1].max_cg = 0                        # the S part needs a CG budget
+    assert gb(2, probs, 1.0, 1.0, info, 0, 4, None, p, 1 << 30, None) == eot.EOT_ERR_INVALID_ARG
+    info[1].max_cg = 100
+    assert gb(2, probs, 1.0, 1.0, info, 0, 4, None, p, 16, None) == eot.EOT_ERR_WORKSPACE
+    assert gb(2, probs, 1.0, 1.0, info, 0, 4, None, ctypes.c_void_p(4100), 1 << 30,
+              None) == eot.EOT_ERR_WORKSPACE
+
+
 def test_noalloc_hvp_rejects_oversize_before_device_work(L):
     """eot_hvp_noalloc checks the scratch it needs against its fixed 64 MiB
     before any HIP call: a dense 32768^2 cost needs 98 MiB."""
