@@ -570,10 +570,11 @@ eot_status cgp_pick_grid(Ctx& x, int prec, int* grid)
 // met the stop test, broke down or reached max_cg). The host paces its launches
 // by progress words the kernels store into pinned host memory and reads the
 // scalars once at the end (without pinned memory: in chunks of 4, 8, 16, 32
-// iterations with a read-back after each).
+// iterations with a read-back after each). exact_sums: the mixed point-cloud
+// row-sum pass keeps FP64 sums in every lane (for solves to a tight residual).
 eot_status device_pcg(Ctx& x, int prec, const double* u, const double* lr, const double* v,
                       double beta, const double* s, const double* c, double rho, double tol,
-                      int max_cg, CgScalars* out)
+                      int max_cg, CgScalars* out, bool exact_sums = false)
 {
     NewtonVecs& V = x.nv;
     const int64_t n = x.n, m = x.m;
@@ -636,6 +637,7 @@ eot_status device_pcg(Ctx& x, int prec, const double* u, const double* lr, const
     PassArgs pb = make_args(x, u, lr, v, beta);        // pass B: row sums of P (w / c)
     pb.yw0 = V.wc;
     pb.skip = &x.sc.cg->done;
+    pb.exact_sums = exact_sums ? 1 : 0;
     CgScalars h{};
     const bool small = std::max(n, m) <= kCgSmallMax;
     // one CG iteration; every kernel returns at once once sc.done is set
@@ -1372,8 +1374,9 @@ eot_status gradient_impl(Ctx& x, double gamma, const double* f, const double* g,
         EOTCHK(reduce_host(x, RED_L1, V.b, nullptr, n, &bnorm));
         CgScalars h{};
         if (bnorm > 0.0) {
+            // FP64 row sums in every lane: this solve goes to a tight residual
             EOTCHK(device_pcg(x, prec, G.u, G.lr, G.v, beta, G.s, G.cP, 1.0, info->tol * bnorm,
-                              info->max_cg, &h));
+                              info->max_cg, &h, true));
             info->cg_iters = h.iters;
             info->cg_residual = h.res_l1 / bnorm;
             if (h.broke || !(h.res_l1 <= info->tol * bnorm)) status = EOT_ERR_NOT_CONVERGED;
