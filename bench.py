@@ -839,8 +839,13 @@ def main():
                                              precision=prec, want=("log_cP",))
         call_row = lambda: eot.eot_marginals(C, p.gamma_final, f, g, row_shift=shift,
                                              precision=prec, want=("log_rP",))
+        mg = eot.eot_marginals(C, p.gamma_final, f, g, row_shift=shift, precision=prec,
+                               want=("log_rP", "log_cP"))
+        call_hvpm = lambda: eot.eot_hvp_with_marginals(C, p.gamma_final, f, g, mg["log_rP"],
+                                                       mg["log_cP"], 1.0, x, y, precision=prec)
         for name, fn, nbytes, filt in (
                 ("hvp", call_hvp, hvp_bytes, dict(fused_hvp=1)),
+                ("hvp_with_marginals", call_hvpm, hvp_bytes, dict(nr=1, nc=1, fused_hvp=0)),
                 ("colpass", call_col, col_bytes, dict(nr=0, nc=1)),
                 ("rowpass", call_row, row_bytes, dict(nr=1, nc=0))):
             us = kernel_us(fn, args.hvp_iters, precision=prec, **filt)
@@ -848,7 +853,9 @@ def main():
             kern[f"{name}_{prec}"] = {"kernel_us": us, "gbs": nbytes / (us * 1e-6) / 1e9,
                                       "call_us": call, "bytes": nbytes}
         log(f"{prec}: hvp {kern[f'hvp_{prec}']['kernel_us']:.1f} us "
-            f"({kern[f'hvp_{prec}']['gbs']:.0f} GB/s) col {kern[f'colpass_{prec}']['kernel_us']:.1f} us "
+            f"({kern[f'hvp_{prec}']['gbs']:.0f} GB/s; with marginals "
+            f"{kern[f'hvp_with_marginals_{prec}']['kernel_us']:.1f} us) "
+            f"col {kern[f'colpass_{prec}']['kernel_us']:.1f} us "
             f"row {kern[f'rowpass_{prec}']['kernel_us']:.1f} us (kernel only)")
     hvp = kern["hvp_mixed"]
 
