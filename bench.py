@@ -459,6 +459,38 @@ def grad_measure(eot, W, dev):
     return res
 
 
+def c1_measure(eot, W, dev, seeds=range(1000, 1010)):
+    """The 64-point instances (n = m = 64, FP64 cost, temperature 1e-1 -> 1e-3,
+    tol 1e-9), FP64 solves on the GPU: time per solve and per CG iteration
+    (wall clock of the whole solve over its CG iterations), seeds 1000..1009."""
+    import torch
+    rows = []
+    for s in seeds:
+        q = W.small_points_problem(s)
+        C = torch.from_numpy(q.C).to(dev)
+        r, c = torch.from_numpy(q.r).to(dev), torch.from_numpy(q.c).to(dev)
+        eot.eot_solve(C, r, c, gamma_init=q.gamma_init, gamma_final=q.gamma_final, tol=q.tol,
+                      precision="fp64")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, st = eot.eot_solve(C, r, c, gamma_init=q.gamma_init, gamma_final=q.gamma_final,
+                                 tol=q.tol, precision="fp64")
+        torch.cuda.synchronize()
+        rows.append((time.perf_counter() - t0, st["cg_iters"], st["newton_steps"],
+                     st["err_r"] + st["err_c"]))
+    sec = [x[0] for x in rows]
+    res = {"workload": "points64 n=m=64, FP64 cost, temperature 0.1 -> 1e-3, tol 1e-9, FP64, "
+                       f"seeds {seeds[0]}..{seeds[-1]}",
+           "median_ms": float(np.median(sec)) * 1e3,
+           "us_per_cg_iter": float(np.median([x[0] / max(x[1], 1) for x in rows])) * 1e6,
+           "cg_iters_median": float(np.median([x[1] for x in rows])),
+           "newton_steps_median": float(np.median([x[2] for x in rows])),
+           "max_err": float(max(x[3] for x in rows))}
+    log(f"C1 points64: median {res['median_ms']:.1f} ms per FP64 solve, "
+        f"{res['us_per_cg_iter']:.0f} us per CG iteration (whole solve), max error {res['max_err']:.1e}")
+    return res
+
+
 def grid28_measure(eot, W, dev, seeds=3):
     """Time to 1e-6 marginal error on the 28 x 28 grid (n = m = 784, dense FP32
     cost, temperature 1/32 -> 1e-4), L1 and squared-L2 costs, mixed against plain
@@ -891,6 +923,7 @@ def main():
         highd = highd_measure(args, eot, W, dev)
 
     grid28 = None if (args.no_fp64 or args.no_grid28) else grid28_measure(eot, W, dev)
+    c1 = None if (args.no_fp64 or args.no_grid28) else c1_measure(eot, W, dev)
 
     batch = None
     grad = None
@@ -935,6 +968,7 @@ def main():
                         "fp64_newton_steps": fp64["newton_steps"] if fp64 else None,
                         "fp64_cg_iters": fp64["cg_iters"] if fp64 else None},
         "time_to_1e6_grid28": grid28,
+        "points64_fp64": c1,
         "sinkhorn_baseline": sink,
         "kernels": kern,
         "round": rnd,
