@@ -90,8 +90,8 @@ struct PassArgs {
     const void* hd_yl;
     const float* hd_xx;
     const float* hd_yy;
-    int32_t exact_sums;    // 1: the mixed point-cloud row-sum pass keeps FP64 sums in every
-                           //    lane (tight CG solves); 0: FP32 within a lane
+    int32_t exact_sums;    // 1: the mixed point-cloud row-sum pass keeps FP64 sums per entry
+                           //    (tight CG solves); 0: FP32 over runs of 16 columns
     int32_t atomic;        // 1: row_part = [nr][n], col_part = [nc][m], pre-zeroed, atomically
                            //    accumulated (problems whose per-tile partials would not fit)
     // high-dimensional point clouds: columns per tile, and the per-pass tables of

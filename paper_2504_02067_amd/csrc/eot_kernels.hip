@@ -201,15 +201,12 @@ __device__ __forceinline__ void pass_body(const PassArgs& A)
     __shared__ double s_wmax[kWaves];
     __shared__ float s_x[DP > 0 ? RB * DP : 1];   // point rows
     __shared__ __attribute__((aligned(16))) double s_exp[MIXED ? 2 : kExpTabDoubles];  // FP64: exp_tab256
-    // Mixed point-cloud passes with one plain weighted row sum and at most one
-    // column sum (the HVP with the marginals given, the marginal pass, the CG's
-    // row-sum pass): the sums run in FP32 within a lane and in FP64 from there
-    // on (lanes, waves, tiles), as in the high-dimensional pass. A row-sum pass
-    // launched with exact_sums keeps FP64 sums in the lane instead: the tight CG
-    // solve of the gradient needs them (FP32 ones took it from 61 to 115
-    // iterations at n = 4096, temperature 1e-3). The column-sum pass always
-    // keeps FP64 sums (FP32 ones made it slower).
-    constexpr bool LANE32 = MIXED && DP > 0 && MODE2 != R2_HVP && NR == 1 && NC <= 1;
+    // Mixed point-cloud passes with one plain weighted row sum and one column
+    // sum (the HVP with the marginals given, the marginal pass): the sums run in
+    // FP32 within a lane and in FP64 from there on (lanes, waves, tiles), as in
+    // the high-dimensional pass. (The column-sum pass keeps FP64 sums, FP32 ones
+    // made it slower; mixed row-sum passes over points use k_rows_pts.)
+    constexpr bool LANE32 = MIXED && DP > 0 && MODE2 != R2_HVP && NR == 1 && NC == 1;
     __shared__ float s_xwf[LANE32 ? RB : 1];      // FP32 copy of the column-sum weights
 
     const int tid = threadIdx.x;
@@ -473,9 +470,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& A)
             }
         };
         if constexpr (LANE32) {
-            if (NC == 0 && A.exact_sums) {
-                lane64_loop();
-            } else {
+            {
                 // Row sums: FP32 over the lane's NCH x V columns of a sub-band, then
                 // the FP64 wave reduction. Column sums: FP32 over kLane32Rows rows,
                 // then added to FP64.
@@ -578,6 +573,122 @@ __global__ __launch_bounds__(kPassThreads) EOT_FUSED_OCCUPANCY void k_pass_fused
     pass_body<PREC, TC, NR, NC, MODE2, VEC, RS, DP>(A);
 }
 
+
+// Mixed row-sum pass over point clouds (d = 2, 3) with the rows on the lanes:
+// a workgroup takes 256 rows (one per thread) against the 2048 columns of a
+// tile, whose coordinates, hi exponent parts and weights (times 2^Vl) sit in
+// LDS and are read as broadcasts; every lane sums its own row, so no
+// cross-lane reduction is needed (the general pass puts columns on the lanes
+// and reduces each row over the wave). Each 512-column quarter of the tile
+// gives one row partial, written to the slot the general pass gives its wave,
+// so the outputs and their consumers are the same. The exponent is assembled
+// from the same hi / lo parts on the tile's 2^-g grid. EXACT = false: sums in
+// FP32 over runs of 16 columns, then FP64; EXACT = true: the FP64 weight and
+// sum per entry (for CG solves to a tight residual).
+constexpr int kRowsPtsRun = 16;
+constexpr int64_t kRowsPtsMinGroups = 512;    // workgroups below which the general pass is used
+
+template <int DP, bool EXACT>
+__global__ __launch_bounds__(kPassThreads) void k_rows_pts(PassArgs A)
+{
+    static_assert(DP == 2 || DP == 3, "points in the plane or in space");
+    if (A.skip && *A.skip) return;             // uniform: a finished CG chunk
+    constexpr int T = kPassThreads, TC = kTileCols, Q = kTileCols / kWaves, NQ = TC / T;
+    static_assert(Q % kRowsPtsRun == 0 && TC % T == 0, "tile split");
+    __shared__ float4 s_c[TC];                 // y_j (zero-padded to 3) and Vh_j
+    __shared__ float s_w[EXACT ? 1 : TC];      // w_j 2^Vl_j (FP32 sums)
+    __shared__ double s_w64[EXACT ? TC : 1];   // w_j 2^Vl_j (FP64 sums)
+    __shared__ double s_wmax[kWaves];
+    const int tid = threadIdx.x;
+    const int64_t n = A.n, m = A.m;
+    const int64_t i = (int64_t)blockIdx.y * T + tid;
+    const int64_t j0 = (int64_t)blockIdx.x * TC;
+    const bool rvalid = i < n;
+
+    // the tile's exponent grid: largest |U| of these rows, |V| of these columns
+    double Ud = 0.0, mx = 0.0;
+    if (rvalid) {
+        Ud = kLog2e * (A.u[i] - A.a[i]);
+        mx = fabs(Ud);
+    }
+    double Vd[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int64_t j = j0 + (int64_t)q * T + tid;
+        Vd[q] = j < m ? kLog2e * A.v[j] : 0.0;
+        mx = fmax(mx, fabs(Vd[q]));
+    }
+    mx = wave_max(mx);
+    if ((tid & 63) == 0) s_wmax[tid >> 6] = mx;
+    __syncthreads();
+    mx = s_wmax[0];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) mx = fmax(mx, s_wmax[w]);
+    if (!(mx < 4.0e6)) mx = 4.0e6;             // non-finite input: results flagged later
+    int e2;
+    frexp(2.0 * mx + 2.0, &e2);                // 2 mx + 2 < 2^e2
+    const int g = 23 - e2;                     // |Uh + Vh| < 2^(23-g) on a 2^-g grid: exact
+    const double sc = ldexp(1.0, g), isc = ldexp(1.0, -g);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int64_t j = j0 + (int64_t)q * T + tid;
+        const double h = rint(Vd[q] * sc) * isc;
+        float4 rec = make_float4(0.0f, 0.0f, 0.0f, -INFINITY);
+        double w = 0.0;
+        if (j < m) {
+            rec.x = A.Y[j * DP];
+            rec.y = A.Y[j * DP + 1];
+            if constexpr (DP == 3) rec.z = A.Y[j * DP + 2];
+            rec.w = (float)h;
+            w = (A.yw0 ? A.yw0[j] : 1.0) * exp2((double)(float)(Vd[q] - h));
+        }
+        s_c[q * T + tid] = rec;
+        if constexpr (EXACT) s_w64[q * T + tid] = w;
+        else s_w[q * T + tid] = (float)w;
+    }
+    const double uhd = rint(Ud * sc) * isc;
+    const float uh = rvalid ? (float)uhd : -INFINITY;
+    const double rf = rvalid ? exp2(Ud - uhd) : 0.0;
+    float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
+    if (rvalid) {
+        x0 = A.X[i * DP];
+        x1 = A.X[i * DP + 1];
+        if constexpr (DP == 3) x2 = A.X[i * DP + 2];
+    }
+    const double Bd = kLog2e * A.beta;
+    const float Bh = (float)Bd;
+    const float Bl = (float)(Bd - (double)Bh);
+    __syncthreads();
+
+    for (int s = 0; s < kWaves; ++s) {
+        double acc = 0.0;
+        for (int jb = s * Q; jb < (s + 1) * Q; jb += kRowsPtsRun) {
+            float a32 = 0.0f;
+#pragma unroll
+            for (int k = 0; k < kRowsPtsRun; ++k) {
+                const float4 rec = s_c[jb + k];
+                const float d0 = x0 - rec.x, d1 = x1 - rec.y;
+                float d2 = fmaf(d1, d1, d0 * d0);
+                if constexpr (DP == 3) {
+                    const float dz = x2 - rec.z;
+                    d2 = fmaf(dz, dz, d2);
+                }
+                const float t = fmaf(-Bh, d2, uh + rec.w);
+                const float e = __builtin_amdgcn_exp2f(fmaf(-Bl, d2, t));
+                if constexpr (EXACT) acc = fma((double)e, s_w64[jb + k], acc);
+                else a32 = fmaf(e, s_w[jb + k], a32);
+            }
+            if constexpr (!EXACT) acc += (double)a32;
+        }
+        if (rvalid) {
+            const double out = acc * rf;
+            if (A.atomic)
+                atomicAdd(&A.row_part[i], out);
+            else
+                A.row_part[((int64_t)blockIdx.x * kWaves + s) * n + i] = out;
+        }
+    }
+}
 
 // Row shifts a_i ~ max_j (u_i + v_j - beta C_ij). They only keep the shifted
 // row sums of the passes in range (every pass evaluates exp(x_ij - a_i) from the
@@ -1286,9 +1397,23 @@ hipError_t launch_pass_v(const PassArgs& a, int prec, hipStream_t s)
     constexpr int RS = FUSED ? kSubRowsFused : kSubRows;
     // mixed point-cloud passes: their own sub-band height
     constexpr int RSM = DP > 0 ? (FUSED ? kPtsSubRowsFused : kPtsSubRows) : RS;
+    // mixed point-cloud row sums: the rows-on-lanes kernel
+    constexpr bool ROWS_PTS = DP > 0 && NR == 1 && NC == 0 && MODE2 == R2_WEIGHT;
     dim3 grid((unsigned)a.tiles_m, (unsigned)a.tiles_n);
     if (prec == EOT_PREC_MIXED) {
         if constexpr (sizeof(TC) == 4) {
+            if constexpr (ROWS_PTS) {
+                // 256 rows per workgroup: only where that still gives a full grid
+                const int64_t gy = (a.n + kPassThreads - 1) / kPassThreads;
+                if ((int64_t)a.tiles_m * gy >= kRowsPtsMinGroups) {
+                    const dim3 g2((unsigned)a.tiles_m, (unsigned)gy);
+                    if (a.exact_sums)
+                        hipLaunchKernelGGL((k_rows_pts<DP, true>), g2, dim3(kPassThreads), 0, s, a);
+                    else
+                        hipLaunchKernelGGL((k_rows_pts<DP, false>), g2, dim3(kPassThreads), 0, s, a);
+                    return hipGetLastError();
+                }
+            }
             if constexpr (FUSED)
                 hipLaunchKernelGGL((k_pass_fused<EOT_PREC_MIXED, TC, NR, NC, MODE2, VEC, RSM, DP>),
                                    grid, dim3(kPassThreads), 0, s, a);

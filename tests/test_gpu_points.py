@@ -238,3 +238,53 @@ def test_points_full_size_sampled_hvp():
     torch.cuda.synchronize()
     assert np.all(np.abs(host(Hx)[rows] - hx_ref) <= tol * ax + 1e-300)
     assert np.all(np.abs(host(Hy)[cols] - hy_ref) <= tol * ay + 1e-300)
+
+
+@pytest.mark.parametrize("d,n,m", [(3, 20000, 17000), (2, 16384, 16500)])
+def test_points_row_pass_rows_on_lanes(d, n, m):
+    """Mixed row sums of large clouds go through the rows-on-lanes kernel
+    (k_rows_pts: at least 512 workgroups of 256 rows x 2048 columns): log r(P)
+    (rows only) on 48 sampled rows against the oracle and every row against the
+    library's FP64 pass. (Its weighted form carries the CG of the large solves
+    in tests/test_gpu_configs.py.)"""
+    gamma = 0.02
+    beta = 1.0 / gamma
+    X, Y, s, pc, rng = cloud(n, m, d, 500 + d)
+    u = -np.log(n) + rng.standard_normal(n)
+    v = -np.log(m) + rng.standard_normal(m)
+    f, g = u * gamma, v * gamma
+    u, v = O.to_log_units(f, g, gamma)
+    rows = np.sort(rng.choice(n, 48, replace=False))
+    Crows = O.sqeuclid_points_cost(X[rows], Y, s)
+    lr_ref = O.log_row_marginal(Crows, beta, u[rows], v)
+    tol = mixed_tol(beta, Crows.max())
+    say(f"points rows-on-lanes row pass d={d} {n}x{m}")
+    fd, gd = dvec(f), dvec(g)
+    lr64 = host(eot.eot_marginals(pc, gamma, fd, gd, precision="fp64", want=("log_rP",))["log_rP"])
+    lr32 = host(eot.eot_marginals(pc, gamma, fd, gd, precision="mixed", want=("log_rP",))["log_rP"])
+    torch.cuda.synchronize()
+    assert np.abs(lr64[rows] - lr_ref).max() <= 1e-12
+    assert np.abs(lr32[rows] - lr_ref).max() <= tol
+    assert np.abs(lr32 - lr64).max() <= tol
+
+
+def test_points_gradient_mixed_large_keeps_exact_row_sums():
+    """The gradient's CG on a large cloud (n = m = 16384, d = 2: the row pass is
+    the rows-on-lanes kernel) runs its row sums in FP64 per entry: the mixed CG
+    takes about as many iterations as the FP64 one and reaches the same
+    gradient to the mixed tolerance."""
+    n = 16384
+    p = W.point_cloud_problem(n=n, m=n, d=2, seed=71)
+    pc = eot.PointCloud(torch.from_numpy(p.X).to(DEV), torch.from_numpy(p.Y).to(DEV), p.scale)
+    gamma = 0.01
+    f, g, st = eot.eot_solve(pc, dvec(p.r), dvec(p.c), gamma_init=1.0 / 8.0, gamma_final=gamma,
+                             tol=1e-7, precision="mixed")
+    say("points 16384 gradient, FP64 and mixed CG")
+    a = eot.eot_gradient(pc, gamma, f, g, w_W=0.5, w_S=1.0, tol=1e-8)
+    b = eot.eot_gradient(pc, gamma, f, g, w_W=0.5, w_S=1.0, tol=1e-8, precision="mixed")
+    torch.cuda.synchronize()
+    say(f"  CG iterations fp64 {a['cg_iters']}, mixed {b['cg_iters']}")
+    assert b["cg_iters"] <= 1.5 * a["cg_iters"] + 10
+    for name in ("X", "Y", "r"):
+        x, y = host(a[name]), host(b[name])
+        assert np.abs(x - y).max() <= 1e-4 * np.abs(x).max(), name
