@@ -223,6 +223,23 @@ def points_measure(args, eot, W, dev, iters=4):
     sec_m = ms2 / 1e3 / k2
     log(f"points HVP with marginals {sec_m * 1e3:.1f} ms per pass, "
         f"{elems / sec_m / 1e12:.3f} T elements/s")
+    # the CG's two single-sum passes on the same clouds (row sums: rows on the lanes)
+    cgp = {}
+    for name, want, filt in (("row", ("log_rP",), dict(nr=1, nc=0)),
+                             ("col", ("log_cP",), dict(nr=0, nc=1))):
+        fn = lambda: eot.eot_marginals(pc, gamma, f, g, row_shift=shift, precision="mixed",
+                                       want=want)
+        fn()
+        torch.cuda.synchronize()
+        eot.eot_pass_timing(True)
+        for _ in range(iters):
+            fn()
+        torch.cuda.synchronize()
+        k3, ms3 = eot.eot_pass_timing_read(precision="mixed", **filt)
+        eot.eot_pass_timing(False)
+        cgp[f"{name}_ms"] = ms3 / k3
+        cgp[f"{name}_entries_per_s"] = elems / (ms3 / k3 / 1e3)
+    log(f"points CG passes: row {cgp['row_ms']:.1f} ms, column {cgp['col_ms']:.1f} ms")
     # a full solve on the same mixtures at n = m = 65536 (temperature 1/32 -> 1e-4, tol 1e-4)
     q = W.point_cloud_problem(n=1 << 16)
     qc = eot.PointCloud(torch.from_numpy(q.X).to(dev), torch.from_numpy(q.Y).to(dev), q.scale)
@@ -244,6 +261,7 @@ def points_measure(args, eot, W, dev, iters=4):
                          "peak": peak_eps / 1e12, "unit": "T elements/s",
                          "frac": elems / sec_m / peak_eps,
                          "fp32_lane_ops_per_element": cyc},
+            "cg_passes": cgp,
             "fused_hvp": {
                 "note": "eot_hvp: r(P), c(P) formed in the same pass (two sums per direction)",
                 "kernel_ms": sec * 1e3, "elements_per_s": elems / sec,
