@@ -455,8 +455,71 @@ __device__ __forceinline__ void pass_body(const PassArgs& A)
                 }
             };
         };
-        // FP64 sums in every lane (the general path)
-        auto lane64_loop = [&]() {
+        if constexpr (LANE32) {
+            // Row sums: FP32 over the lane's NCH x V columns of a sub-band, then
+            // the FP64 wave reduction. Column sums: FP32 over kLane32Rows rows,
+            // then added to FP64.
+            static_assert(kLane32Rows % RS == 0, "column runs of whole sub-bands");
+            float ywf[NCH][V];
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+                for (int q = 0; q < V; ++q) ywf[ch][q] = (float)ywr[0][ch][q];
+            float cacc32[NCH][V];
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+                for (int q = 0; q < V; ++q) cacc32[ch][q] = 0.0f;
+            for (int b = 0; b < nsb; ++b) {
+                const int sb = b * RS;
+                // one row accumulator per chunk: shorter dependent chains
+                float racc32s[NCH][RS];
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+                    for (int rr = 0; rr < RS; ++rr) racc32s[ch][rr] = 0.0f;
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) {
+                    float (&racc32)[RS] = racc32s[ch];
+                    auto getc = pts(sb, ch);
+#pragma unroll
+                    for (int rr = 0; rr < RS; ++rr) {
+                        const float uh_r = s_uh[sb + rr];
+                        const float xw_r = s_xwf[sb + rr];
+#pragma unroll
+                        for (int q = 0; q < V; ++q) {
+                            const float c = getc(rr, q);
+                            const float t = fmaf(-Bh, c, uh_r + vh[ch][q]);
+                            const float e = __builtin_amdgcn_exp2f(fmaf(-Bl, c, t));
+                            if constexpr (NR > 0) racc32[rr] = fmaf(e, ywf[ch][q], racc32[rr]);
+                            if constexpr (NC > 0) cacc32[ch][q] = fmaf(e, xw_r, cacc32[ch][q]);
+                        }
+                    }
+                }
+                if constexpr (NR > 0) {
+                    double racc[NRA][RS];
+#pragma unroll
+                    for (int rr = 0; rr < RS; ++rr) {
+                        float t = racc32s[0][rr];
+#pragma unroll
+                        for (int ch = 1; ch < NCH; ++ch) t += racc32s[ch][rr];
+                        racc[0][rr] = (double)t;
+                    }
+                    wave_rows_out<NR, RS, MODE2>(racc, s_rf, sb, i0, n, A);
+                }
+                if constexpr (NC > 0) {
+                    if (((b + 1) * RS) % kLane32Rows == 0 || b + 1 == nsb) {
+#pragma unroll
+                        for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+                            for (int q = 0; q < V; ++q) {
+                                cacc[0][ch][q] += (double)cacc32[ch][q];
+                                cacc32[ch][q] = 0.0f;
+                            }
+                    }
+                }
+            }
+        } else {
             for (int b = 0; b < nsb; ++b) {
                 const int sb = b * RS;
                 double racc[NRA][RS];
@@ -468,75 +531,6 @@ __device__ __forceinline__ void pass_body(const PassArgs& A)
                 compute(sb, 1, pts(sb, 1), racc);
                 if constexpr (NR > 0) wave_rows_out<NR, RS, MODE2>(racc, s_rf, sb, i0, n, A);
             }
-        };
-        if constexpr (LANE32) {
-            {
-                // Row sums: FP32 over the lane's NCH x V columns of a sub-band, then
-                // the FP64 wave reduction. Column sums: FP32 over kLane32Rows rows,
-                // then added to FP64.
-                static_assert(kLane32Rows % RS == 0, "column runs of whole sub-bands");
-                float ywf[NCH][V];
-#pragma unroll
-                for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-                    for (int q = 0; q < V; ++q) ywf[ch][q] = (float)ywr[0][ch][q];
-                float cacc32[NCH][V];
-#pragma unroll
-                for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-                    for (int q = 0; q < V; ++q) cacc32[ch][q] = 0.0f;
-                for (int b = 0; b < nsb; ++b) {
-                    const int sb = b * RS;
-                    // one row accumulator per chunk: shorter dependent chains
-                    float racc32s[NCH][RS];
-#pragma unroll
-                    for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-                        for (int rr = 0; rr < RS; ++rr) racc32s[ch][rr] = 0.0f;
-#pragma unroll
-                    for (int ch = 0; ch < NCH; ++ch) {
-                        float (&racc32)[RS] = racc32s[ch];
-                        auto getc = pts(sb, ch);
-#pragma unroll
-                        for (int rr = 0; rr < RS; ++rr) {
-                            const float uh_r = s_uh[sb + rr];
-                            const float xw_r = s_xwf[sb + rr];
-#pragma unroll
-                            for (int q = 0; q < V; ++q) {
-                                const float c = getc(rr, q);
-                                const float t = fmaf(-Bh, c, uh_r + vh[ch][q]);
-                                const float e = __builtin_amdgcn_exp2f(fmaf(-Bl, c, t));
-                                if constexpr (NR > 0) racc32[rr] = fmaf(e, ywf[ch][q], racc32[rr]);
-                                if constexpr (NC > 0) cacc32[ch][q] = fmaf(e, xw_r, cacc32[ch][q]);
-                            }
-                        }
-                    }
-                    if constexpr (NR > 0) {
-                        double racc[NRA][RS];
-#pragma unroll
-                        for (int rr = 0; rr < RS; ++rr) {
-                            float t = racc32s[0][rr];
-#pragma unroll
-                            for (int ch = 1; ch < NCH; ++ch) t += racc32s[ch][rr];
-                            racc[0][rr] = (double)t;
-                        }
-                        wave_rows_out<NR, RS, MODE2>(racc, s_rf, sb, i0, n, A);
-                    }
-                    if constexpr (NC > 0) {
-                        if (((b + 1) * RS) % kLane32Rows == 0 || b + 1 == nsb) {
-#pragma unroll
-                            for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-                                for (int q = 0; q < V; ++q) {
-                                    cacc[0][ch][q] += (double)cacc32[ch][q];
-                                    cacc32[ch][q] = 0.0f;
-                                }
-                        }
-                    }
-                }
-            }
-        } else {
-            lane64_loop();
         }
     }
     if constexpr (NC > 0) {
