@@ -749,6 +749,9 @@ def main():
     ap.add_argument("--grid28-only", choices=("l1", "sqeuclid"),
                     help="only one FP64 solve of the 28 x 28 grid (seed 2000) with that cost, after "
                          "one untimed solve (for trace runs)")
+    ap.add_argument("--points-solve-only", action="store_true",
+                    help="only the mixed solve of the n = m = 65536 Gaussian-mixture clouds in R^3 "
+                         "(temperature 1/32 -> 1e-4, tol 1e-4; for trace runs)")
     ap.add_argument("--highd-only", action="store_true",
                     help="only 1 + 5 mixed high-dimensional HVP passes (n = m = 65536, d = 64; "
                          "for counter runs)")
@@ -778,6 +781,19 @@ def main():
         return
     if args.highd_only:
         highd_only(eot, W, dev)
+        return
+    if args.points_solve_only:
+        q = W.point_cloud_problem(n=1 << 16)
+        qc = eot.PointCloud(torch.from_numpy(q.X).to(dev), torch.from_numpy(q.Y).to(dev), q.scale)
+        t0 = time.perf_counter()
+        _, _, st = eot.eot_solve(qc, torch.from_numpy(q.r).to(dev), torch.from_numpy(q.c).to(dev),
+                                 gamma_init=q.gamma_init, gamma_final=q.gamma_final, tol=q.tol,
+                                 precision="mixed")
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "points-solve-only", "n": q.n, "seconds": time.perf_counter() - t0,
+                          "passes": sum(v for k, v in st.items() if k.startswith("passes_")),
+                          "cg_iters": st["cg_iters"], "newton_steps": st["newton_steps"],
+                          "err": st["err_r"] + st["err_c"]}), flush=True)
         return
     if args.batch_only:
         print(json.dumps({"mode": "batch-only",
