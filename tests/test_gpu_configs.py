@@ -135,8 +135,8 @@ def test_gmm3d_65536_final_temperature_sampled():
     """The n = m = 65536 twin solved in mixed precision to 1e-4; at its output
     potentials (inverse temperature 1e4 / scale), 32 sampled rows and columns
     of the marginals in both precisions against the oracle on the dense rows
-    and columns of the cost. Mixed bound: 4e-6 from the FP32 exponent plus
-    3e-7 beta max C from the FP32 |x - y|^2."""
+    and columns of the cost (rows also from a rows-only pass). Mixed bound: 4e-6
+    from the FP32 exponent plus 3e-7 beta max C from the FP32 |x - y|^2."""
     p, pc = _cloud(65536)
     say("gmm3d 65536 mixed solve to 1e-4")
     f, g, st = eot.eot_solve(pc, dvec(p.r), dvec(p.c), gamma_init=p.gamma_init,
@@ -161,6 +161,10 @@ def test_gmm3d_65536_final_temperature_sampled():
         say(f"gmm3d 65536 at beta {beta:.0e}, {prec}: log r(P) {er:.2e}, log c(P) {ec:.2e} "
             f"(bound {tol:.1e})")
         assert max(er, ec) <= tol
+        # rows alone: in mixed precision the rows-on-lanes kernel (k_rows_pts)
+        lr = host(eot.eot_marginals(pc, gamma, f, g, precision=prec, want=("log_rP",))["log_rP"])
+        torch.cuda.synchronize()
+        assert np.abs(lr[rows] - lr_ref).max() <= tol
 
 
 SWITCHES = [dict(adaptive_q=0, q1=2.0), dict(adaptive_q=0, q1=4.0), dict(adaptive_rho0=0),
